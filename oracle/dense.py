@@ -1,0 +1,158 @@
+"""Brute-force dense reference for tiny grids (up to about 8^3 cells).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+The operators are built here from scratch, independently of ``orc.c``: as
+products of 1-D staggered difference matrices combined by Kronecker
+products, following the definitions of Section 2.1 (second-order central
+differences on a staggered grid) and Appendix B (wall rows):
+
+* the pressure Laplacian is literally L_p = D G, with D the divergence
+  (cells <- faces of all three components) and G the gradient
+  (faces <- cells, zero on the wall faces: homogeneous Neumann);
+* the operator for u and w (stored at cell-centre height) uses, at a wall,
+  the flux of a mirror ghost value (Dirichlet u = 0 half a cell away);
+* the operator for v (interior y faces) is G_y D_y with wall values v = 0.
+
+The dense solve uses ``numpy.linalg.solve``.  For the singular Neumann
+pressure problem it solves the bordered system
+    [[L_p, 1], [w^T, 0]] [x; mu] = [b; 0],
+whose solution satisfies L_p x = b - mu 1 (the compatible projection of b,
+mu = w^T b / w^T 1) and w^T x = 0 (zero volume-weighted mean).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import Grid, OP_P, OP_U, OP_V, OP_W
+
+
+def _circ_diff_fwd(n: int, h: float) -> np.ndarray:
+    """(f_{i+1} - f_i)/h, periodic (cells <- faces in x or z)."""
+    m = np.zeros((n, n))
+    for i in range(n):
+        m[i, (i + 1) % n] += 1.0 / h
+        m[i, i] -= 1.0 / h
+    return m
+
+
+def _circ_diff_bwd(n: int, h: float) -> np.ndarray:
+    """(f_i - f_{i-1})/h, periodic (faces <- cells in x or z)."""
+    m = np.zeros((n, n))
+    for i in range(n):
+        m[i, i] += 1.0 / h
+        m[i, (i - 1) % n] -= 1.0 / h
+    return m
+
+
+def dy_faces_to_cells(g: Grid) -> np.ndarray:
+    """(ny x ny+1): (F_{j+1} - F_j)/Delta_j."""
+    ny = g.ny
+    m = np.zeros((ny, ny + 1))
+    for j in range(ny):
+        m[j, j + 1] = 1.0 / g.dyc[j]
+        m[j, j] = -1.0 / g.dyc[j]
+    return m
+
+
+def gy_cells_to_faces_neumann(g: Grid) -> np.ndarray:
+    """(ny+1 x ny): (f_j - f_{j-1})/delta_j on interior faces, 0 on walls."""
+    ny = g.ny
+    m = np.zeros((ny + 1, ny))
+    for j in range(1, ny):
+        m[j, j] = 1.0 / g.dyf[j]
+        m[j, j - 1] = -1.0 / g.dyf[j]
+    return m
+
+
+def gy_cells_to_faces_dirichlet_mirror(g: Grid) -> np.ndarray:
+    """(ny+1 x ny): interior as Neumann; at the walls the gradient between the
+    first (last) value and its mirror ghost, which has the opposite sign and
+    sits one cell height away: 2 f_0/Delta_0 and -2 f_{ny-1}/Delta_{ny-1}."""
+    m = gy_cells_to_faces_neumann(g)
+    m[0, 0] = 2.0 / g.dyc[0]
+    m[g.ny, g.ny - 1] = -2.0 / g.dyc[g.ny - 1]
+    return m
+
+
+def _k3(az, ay, ax):
+    return np.kron(az, np.kron(ay, ax))
+
+
+def divergence_matrix(g: Grid) -> np.ndarray:
+    """D: cells <- (u faces, v faces incl. walls, w faces)."""
+    Ix, Iy, Iz = np.eye(g.nx), np.eye(g.ny), np.eye(g.nz)
+    Du = _k3(Iz, Iy, _circ_diff_fwd(g.nx, g.hx))
+    Dv = _k3(Iz, dy_faces_to_cells(g), Ix)
+    Dw = _k3(_circ_diff_fwd(g.nz, g.hz), Iy, Ix)
+    return np.hstack([Du, Dv, Dw])
+
+
+def gradient_matrix(g: Grid) -> np.ndarray:
+    """G: (u faces, v faces incl. walls, w faces) <- cells."""
+    Ix, Iy, Iz = np.eye(g.nx), np.eye(g.ny), np.eye(g.nz)
+    Gu = _k3(Iz, Iy, _circ_diff_bwd(g.nx, g.hx))
+    Gv = _k3(Iz, gy_cells_to_faces_neumann(g), Ix)
+    Gw = _k3(_circ_diff_bwd(g.nz, g.hz), Iy, Ix)
+    return np.vstack([Gu, Gv, Gw])
+
+
+def laplacian(g: Grid, op: int) -> np.ndarray:
+    """Unweighted Laplacian over the unknowns of ``op`` (v: interior faces)."""
+    Ix, Iz = np.eye(g.nx), np.eye(g.nz)
+    if op == OP_P:
+        return divergence_matrix(g) @ gradient_matrix(g)
+    Lx = _circ_diff_bwd(g.nx, g.hx) @ _circ_diff_fwd(g.nx, g.hx)
+    Lz = _circ_diff_bwd(g.nz, g.hz) @ _circ_diff_fwd(g.nz, g.hz)
+    if op in (OP_U, OP_W):
+        Ly = dy_faces_to_cells(g) @ gy_cells_to_faces_dirichlet_mirror(g)
+        Iy = np.eye(g.ny)
+    elif op == OP_V:
+        full = gy_cells_to_faces_neumann(g) @ dy_faces_to_cells(g)
+        Ly = full[1:g.ny, 1:g.ny]
+        Iy = np.eye(g.ny - 1)
+    else:
+        raise ValueError(op)
+    return _k3(Iz, Iy, Lx) + _k3(Iz, Ly, Ix) + _k3(Lz, Iy, Ix)
+
+
+def weights(g: Grid, op: int) -> np.ndarray:
+    if op == OP_V:
+        wy = g.dyf[1:g.ny]
+        nyu = g.ny - 1
+    else:
+        wy = g.dyc
+        nyu = g.ny
+    return np.broadcast_to((g.hx * g.hz * wy)[None, :, None], (g.nz, nyu, g.nx)).reshape(-1).copy()
+
+
+def operator(g: Grid, op: int, c: float = 0.0) -> np.ndarray:
+    L = laplacian(g, op)
+    if op == OP_P:
+        return L
+    return np.eye(L.shape[0]) - c * L
+
+
+def solve(g: Grid, op: int, b: np.ndarray, c: float = 0.0) -> np.ndarray:
+    """Dense solve; b and the result in the full array layout."""
+    if op == OP_V:
+        rhs = np.ascontiguousarray(b[:, 1:g.ny, :]).reshape(-1)
+    else:
+        rhs = np.ascontiguousarray(b).reshape(-1)
+    A = operator(g, op, c)
+    if op == OP_P:
+        n = A.shape[0]
+        w = weights(g, op)
+        B = np.zeros((n + 1, n + 1))
+        B[:n, :n] = A
+        B[:n, n] = 1.0
+        B[n, :n] = w
+        sol = np.linalg.solve(B, np.concatenate([rhs, [0.0]]))[:n]
+    else:
+        sol = np.linalg.solve(A, rhs)
+    out = np.zeros(g.shape(op))
+    if op == OP_V:
+        out[:, 1:g.ny, :] = sol.reshape(g.nz, g.ny - 1, g.nx)
+    else:
+        out[...] = sol.reshape(g.shape(op))
+    return out

@@ -1,0 +1,572 @@
+/*
+ * Reference (oracle) solver for the staggered-grid Poisson and Helmholtz
+ * problems of the fractional-step method (paper eqs. e and f of the
+ * Runge-Kutta sub-step, Section 2.1; linear systems, Section 2.3.3).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously
+ * correct CPU definition that the GPU library is checked against.  It is
+ * used by tests/, by the smoke check and by the benchmark's CPU-baseline
+ * leg; the GPU library never links, loads or calls it, and it shares no
+ * code with the GPU library.
+ *
+ * What it does, in FP64 (long double only where stated):
+ *   - builds the (optionally tanh-stretched) staggered grid in y;
+ *   - applies the staggered divergence D and gradient G (second-order
+ *     central differences on a staggered grid, Section 2.1), periodic in
+ *     x and z, walls in y;
+ *   - assembles the 7-point operators L_p = D G (pressure), L_c (velocity
+ *     components stored at cell-centre height, Dirichlet wall by a mirror
+ *     ghost: Appendix B, alpha = 2) and L_f (wall-normal velocity on the
+ *     y faces, Dirichlet wall value: Appendix B, alpha = 1) as CSR, in the
+ *     symmetric weighted form S = W(-L_p) or S = W(I - cL);
+ *   - solves S x = f by Jacobi-preconditioned conjugate gradients to a
+ *     true relative residual of 1e-14, then polishes with a few steps of
+ *     iterative refinement whose residual b - A x is evaluated from the
+ *     flux form of the stencil in long double;
+ *   - for the pressure problem, projects the right-hand side onto the
+ *     compatible subspace (Neumann compatibility: weighted mean of b is
+ *     zero) and returns the solution with zero volume-weighted mean (the
+ *     null mode is fixed; the paper fixes it by a zero mean in the triply
+ *     periodic solver, Section 2.3.3, item S2).
+ *
+ * Array layout: C order [z][y][x] (x fastest).  Cell fields and the x- and
+ * z-face velocities are [nz][ny][nx]; the y-face velocity v is
+ * [nz][ny+1][nx], faces j = 0 and j = ny being the walls (ignored on input,
+ * written as zero on output).
+ *
+ * Operator codes: 0 = pressure Poisson (A = L_p), 1 = u Helmholtz,
+ * 2 = v Helmholtz, 3 = w Helmholtz (A = I - c L).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int nx, ny, nz;
+    double hx, hz;
+    const double *dyc; /* [ny]    cell heights Delta_j                  */
+    const double *dyf; /* [ny+1]  centre-to-centre distances delta_j,   */
+                       /*         valid for j = 1..ny-1                 */
+} orc_geom;
+
+typedef struct {
+    int iters;          /* CG iterations of the main solve            */
+    int polish_steps;   /* refinement steps after the main solve      */
+    int polish_iters;   /* CG iterations spent in refinement          */
+    int stagnated;      /* 1 if the main CG stalled above tolerance   */
+    double rel_residual;    /* ||b - A x|| / ||b|| (long double, final) */
+    double removed_mean;    /* weighted mean removed from b (Poisson)  */
+} orc_info;
+
+/* ------------------------------------------------------------------ */
+/* Grid (uniform x, z; tanh-stretched y).                              */
+/* ------------------------------------------------------------------ */
+
+/* Face positions y_f[j] = (ly/2) (1 + tanh(beta (2j/ny - 1)) / tanh(beta)),
+ * j = 0..ny; beta = 0 gives the uniform grid of Section 2.1.  If yf_in is
+ * non-NULL it is copied instead.  Outputs: centres yc[ny], heights
+ * dyc[ny] = yf[j+1]-yf[j], distances dyf[ny+1] with dyf[j] = yc[j]-yc[j-1]
+ * for j = 1..ny-1 and dyf[0] = dyf[ny] = 0. */
+int orc_grid(int ny, double ly, double beta, const double *yf_in, double *yf,
+             double *yc, double *dyc, double *dyf)
+{
+    if (ny < 1) return -1;
+    for (int j = 0; j <= ny; ++j) {
+        if (yf_in) {
+            yf[j] = yf_in[j];
+        } else if (beta == 0.0) {
+            yf[j] = ly * (double)j / (double)ny;
+        } else {
+            double t = tanh(beta * (2.0 * (double)j / (double)ny - 1.0));
+            yf[j] = 0.5 * ly * (1.0 + t / tanh(beta));
+        }
+    }
+    for (int j = 0; j < ny; ++j) {
+        yc[j] = 0.5 * (yf[j] + yf[j + 1]);
+        dyc[j] = yf[j + 1] - yf[j];
+        if (!(dyc[j] > 0.0)) return -2;
+    }
+    dyf[0] = 0.0;
+    dyf[ny] = 0.0;
+    for (int j = 1; j < ny; ++j) dyf[j] = yc[j] - yc[j - 1];
+    return 0;
+}
+
+static inline int64_t cidx(const orc_geom *g, int i, int j, int k)
+{
+    return ((int64_t)k * g->ny + j) * g->nx + i;
+}
+static inline int64_t vidx(const orc_geom *g, int i, int j, int k)
+{
+    return ((int64_t)k * (g->ny + 1) + j) * g->nx + i;
+}
+static inline int wrap(int i, int n) { return (i % n + n) % n; }
+
+/* ------------------------------------------------------------------ */
+/* Divergence and gradient (Section 2.1; kernels E2 and E3).           */
+/* ------------------------------------------------------------------ */
+
+/* b = scale * D(u,v,w) on cells:
+ * (u_{i+1}-u_i)/hx + (v_{j+1}-v_j)/Delta_j + (w_{k+1}-w_k)/hz. */
+void orc_divergence(const orc_geom *g, const double *u, const double *v,
+                    const double *w, double scale, double *b)
+{
+#pragma omp parallel for collapse(2)
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                double du = (u[cidx(g, wrap(i + 1, g->nx), j, k)] - u[cidx(g, i, j, k)]) / g->hx;
+                double dv = (v[vidx(g, i, j + 1, k)] - v[vidx(g, i, j, k)]) / g->dyc[j];
+                double dw = (w[cidx(g, i, j, wrap(k + 1, g->nz))] - w[cidx(g, i, j, k)]) / g->hz;
+                b[cidx(g, i, j, k)] = scale * (du + dv + dw);
+            }
+}
+
+/* Components of G(phi): (phi_i - phi_{i-1})/hx on x-faces,
+ * (phi_j - phi_{j-1})/delta_j on interior y-faces (zero on the wall faces:
+ * homogeneous Neumann), (phi_k - phi_{k-1})/hz on z-faces. */
+void orc_gradient(const orc_geom *g, const double *phi, double *gu, double *gv,
+                  double *gw)
+{
+#pragma omp parallel for collapse(2)
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j <= g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                if (j < g->ny) {
+                    gu[cidx(g, i, j, k)] =
+                        (phi[cidx(g, i, j, k)] - phi[cidx(g, wrap(i - 1, g->nx), j, k)]) / g->hx;
+                    gw[cidx(g, i, j, k)] =
+                        (phi[cidx(g, i, j, k)] - phi[cidx(g, i, j, wrap(k - 1, g->nz))]) / g->hz;
+                }
+                if (j == 0 || j == g->ny)
+                    gv[vidx(g, i, j, k)] = 0.0;
+                else
+                    gv[vidx(g, i, j, k)] =
+                        (phi[cidx(g, i, j, k)] - phi[cidx(g, i, j - 1, k)]) / g->dyf[j];
+            }
+}
+
+/* ------------------------------------------------------------------ */
+/* Unknown numbering.                                                  */
+/* ------------------------------------------------------------------ */
+
+static int64_t n_unknowns(const orc_geom *g, int op)
+{
+    int nyu = (op == 2) ? g->ny - 1 : g->ny;
+    return (int64_t)g->nx * nyu * g->nz;
+}
+/* (i, j, k) of unknown number r; for op 2, j is the face index 1..ny-1 */
+static void unknown_ijk(const orc_geom *g, int op, int64_t r, int *i, int *j,
+                        int *k)
+{
+    int nyu = (op == 2) ? g->ny - 1 : g->ny;
+    *i = (int)(r % g->nx);
+    int64_t t = r / g->nx;
+    *j = (int)(t % nyu) + (op == 2 ? 1 : 0);
+    *k = (int)(t / nyu);
+}
+static int64_t unknown_id(const orc_geom *g, int op, int i, int j, int k)
+{
+    int nyu = (op == 2) ? g->ny - 1 : g->ny;
+    int jj = (op == 2) ? j - 1 : j;
+    return ((int64_t)k * nyu + jj) * g->nx + i;
+}
+/* position of unknown r in the caller's full array layout */
+static int64_t unknown_to_array(const orc_geom *g, int op, int64_t r)
+{
+    int i, j, k;
+    unknown_ijk(g, op, r, &i, &j, &k);
+    return (op == 2) ? vidx(g, i, j, k) : cidx(g, i, j, k);
+}
+/* weight W of unknown r: hx hz Delta_j (cells and cell-height faces),
+ * hx hz delta_j (y faces) */
+static double unknown_weight(const orc_geom *g, int op, int64_t r)
+{
+    int i, j, k;
+    unknown_ijk(g, op, r, &i, &j, &k);
+    return g->hx * g->hz * ((op == 2) ? g->dyf[j] : g->dyc[j]);
+}
+
+/* ------------------------------------------------------------------ */
+/* Stencil of the unweighted Laplacian L for unknown (i,j,k).          */
+/* Up to 7 (column, value) pairs, duplicates merged.                   */
+/* ------------------------------------------------------------------ */
+static int add_entry(int64_t *cols, double *vals, int n, int64_t c, double v)
+{
+    for (int q = 0; q < n; ++q)
+        if (cols[q] == c) { vals[q] += v; return n; }
+    cols[n] = c;
+    vals[n] = v;
+    return n + 1;
+}
+
+static int laplacian_row(const orc_geom *g, int op, int i, int j, int k,
+                         int64_t *cols, double *vals)
+{
+    int n = 0;
+    const double ax = 1.0 / (g->hx * g->hx), az = 1.0 / (g->hz * g->hz);
+    int64_t me = unknown_id(g, op, i, j, k);
+    /* periodic x and z: (f_{i+1} - 2 f_i + f_{i-1}) / h^2 */
+    n = add_entry(cols, vals, n, me, -2.0 * ax - 2.0 * az);
+    n = add_entry(cols, vals, n, unknown_id(g, op, wrap(i - 1, g->nx), j, k), ax);
+    n = add_entry(cols, vals, n, unknown_id(g, op, wrap(i + 1, g->nx), j, k), ax);
+    n = add_entry(cols, vals, n, unknown_id(g, op, i, j, wrap(k - 1, g->nz)), az);
+    n = add_entry(cols, vals, n, unknown_id(g, op, i, j, wrap(k + 1, g->nz)), az);
+    const int ny = g->ny;
+    if (op == 0 || op == 1 || op == 3) {
+        /* cell-centre height: (F_{j+1/2} - F_{j-1/2}) / Delta_j */
+        double D = g->dyc[j];
+        if (j + 1 < ny) { /* interior upper flux (f_{j+1}-f_j)/delta_{j+1} */
+            double a = 1.0 / (g->dyf[j + 1] * D);
+            n = add_entry(cols, vals, n, unknown_id(g, op, i, j + 1, k), a);
+            n = add_entry(cols, vals, n, me, -a);
+        } else if (op != 0) { /* wall above: mirror ghost, flux -2 f/Delta */
+            n = add_entry(cols, vals, n, me, -2.0 / (D * D));
+        } /* Poisson: homogeneous Neumann, zero flux */
+        if (j > 0) {
+            double a = 1.0 / (g->dyf[j] * D);
+            n = add_entry(cols, vals, n, unknown_id(g, op, i, j - 1, k), a);
+            n = add_entry(cols, vals, n, me, -a);
+        } else if (op != 0) {
+            n = add_entry(cols, vals, n, me, -2.0 / (D * D));
+        }
+    } else {
+        /* y faces j = 1..ny-1: ((v_{j+1}-v_j)/Delta_j - (v_j-v_{j-1})/Delta_{j-1}) / delta_j,
+         * wall values v_0 = v_ny = 0 */
+        double d = g->dyf[j];
+        double au = 1.0 / (g->dyc[j] * d), al = 1.0 / (g->dyc[j - 1] * d);
+        n = add_entry(cols, vals, n, me, -au - al);
+        if (j + 1 <= ny - 1) n = add_entry(cols, vals, n, unknown_id(g, op, i, j + 1, k), au);
+        if (j - 1 >= 1) n = add_entry(cols, vals, n, unknown_id(g, op, i, j - 1, k), al);
+    }
+    return n;
+}
+
+/* Assemble the unweighted operator A (op 0: L_p; else I - cL) as CSR over
+ * the unknowns.  rowptr has n+1 entries, col/val up to 7n.  Returns n. */
+int64_t orc_assemble(const orc_geom *g, int op, double c, int64_t *rowptr,
+                     int64_t *col, double *val)
+{
+    int64_t n = n_unknowns(g, op);
+    rowptr[0] = 0;
+    for (int64_t r = 0; r < n; ++r) {
+        int i, j, k;
+        int64_t cols[8];
+        double vals[8];
+        unknown_ijk(g, op, r, &i, &j, &k);
+        int m = laplacian_row(g, op, i, j, k, cols, vals);
+        if (op != 0) {
+            for (int q = 0; q < m; ++q) vals[q] = -c * vals[q];
+            m = add_entry(cols, vals, m, r, 1.0);
+        }
+        /* sort columns (insertion sort, m <= 7) */
+        for (int a = 1; a < m; ++a)
+            for (int b = a; b > 0 && cols[b - 1] > cols[b]; --b) {
+                int64_t tc = cols[b]; cols[b] = cols[b - 1]; cols[b - 1] = tc;
+                double tv = vals[b]; vals[b] = vals[b - 1]; vals[b - 1] = tv;
+            }
+        for (int q = 0; q < m; ++q) {
+            col[rowptr[r] + q] = cols[q];
+            val[rowptr[r] + q] = vals[q];
+        }
+        rowptr[r + 1] = rowptr[r] + m;
+    }
+    return n;
+}
+
+int64_t orc_num_unknowns(const orc_geom *g, int op) { return n_unknowns(g, op); }
+
+/* weights W of all unknowns, in unknown order */
+void orc_weights(const orc_geom *g, int op, double *w)
+{
+    int64_t n = n_unknowns(g, op);
+    for (int64_t r = 0; r < n; ++r) w[r] = unknown_weight(g, op, r);
+}
+
+/* ------------------------------------------------------------------ */
+/* Residual r = b - A x in long double, straight from the flux form.   */
+/* x, b, r in the caller's full array layout.  Returns ||r||_2 and     */
+/* ||b||_2 (over the unknowns) through norms[0], norms[1].             */
+/* ------------------------------------------------------------------ */
+static long double flux_apply_ld(const orc_geom *g, int op, int i, int j, int k,
+                                 const double *x)
+{
+    const int nx = g->nx, ny = g->ny, nz = g->nz;
+    long double hx = g->hx, hz = g->hz;
+    int64_t (*at)(const orc_geom *, int, int, int) = (op == 2) ? vidx : cidx;
+    long double xc = x[at(g, i, j, k)];
+    long double xe = x[at(g, wrap(i + 1, nx), j, k)], xw = x[at(g, wrap(i - 1, nx), j, k)];
+    long double xt = x[at(g, i, j, wrap(k + 1, nz))], xb = x[at(g, i, j, wrap(k - 1, nz))];
+    long double lap = ((xe - xc) / hx - (xc - xw) / hx) / hx + ((xt - xc) / hz - (xc - xb) / hz) / hz;
+    if (op != 2) {
+        long double D = g->dyc[j];
+        long double fu, fl;
+        if (j + 1 < ny) fu = ((long double)x[at(g, i, j + 1, k)] - xc) / (long double)g->dyf[j + 1];
+        else fu = (op == 0) ? 0.0L : (0.0L - xc) / (D / 2.0L);
+        if (j > 0) fl = (xc - (long double)x[at(g, i, j - 1, k)]) / (long double)g->dyf[j];
+        else fl = (op == 0) ? 0.0L : (xc - 0.0L) / (D / 2.0L);
+        lap += (fu - fl) / D;
+    } else {
+        long double vu = (j + 1 <= ny - 1) ? (long double)x[vidx(g, i, j + 1, k)] : 0.0L;
+        long double vl = (j - 1 >= 1) ? (long double)x[vidx(g, i, j - 1, k)] : 0.0L;
+        long double fu = (vu - xc) / (long double)g->dyc[j];
+        long double fl = (xc - vl) / (long double)g->dyc[j - 1];
+        lap += (fu - fl) / (long double)g->dyf[j];
+    }
+    return lap;
+}
+
+void orc_residual_ld(const orc_geom *g, int op, double c, const double *x,
+                     const double *b, double *r, double *norms)
+{
+    int64_t n = n_unknowns(g, op);
+    long double rr = 0.0L, bb = 0.0L;
+#pragma omp parallel for reduction(+ : rr, bb)
+    for (int64_t q = 0; q < n; ++q) {
+        int i, j, k;
+        unknown_ijk(g, op, q, &i, &j, &k);
+        int64_t a = unknown_to_array(g, op, q);
+        long double lap = flux_apply_ld(g, op, i, j, k, x);
+        long double ax = (op == 0) ? lap : (long double)x[a] - (long double)c * lap;
+        long double res = (long double)b[a] - ax;
+        r[a] = (double)res;
+        rr += res * res;
+        bb += (long double)b[a] * (long double)b[a];
+    }
+    if (op == 2) {
+        for (int k = 0; k < g->nz; ++k)
+            for (int i = 0; i < g->nx; ++i) {
+                r[vidx(g, i, 0, k)] = 0.0;
+                r[vidx(g, i, g->ny, k)] = 0.0;
+            }
+    }
+    if (norms) {
+        norms[0] = sqrt((double)rr);
+        norms[1] = sqrt((double)bb);
+    }
+}
+
+/* y = A x (unweighted, CSR), unknown ordering */
+static void csr_mv(int64_t n, const int64_t *rp, const int64_t *ci, const double *v,
+                   const double *x, double *y)
+{
+#pragma omp parallel for
+    for (int64_t r = 0; r < n; ++r) {
+        double s = 0.0;
+        for (int64_t q = rp[r]; q < rp[r + 1]; ++q) s += v[q] * x[ci[q]];
+        y[r] = s;
+    }
+}
+
+static double dot(int64_t n, const double *a, const double *b)
+{
+    double s = 0.0;
+#pragma omp parallel for reduction(+ : s)
+    for (int64_t q = 0; q < n; ++q) s += a[q] * b[q];
+    return s;
+}
+
+/* weighted mean sum(w x)/sum(w) */
+static double wmean(int64_t n, const double *w, const double *x)
+{
+    long double s = 0.0L, t = 0.0L;
+    for (int64_t q = 0; q < n; ++q) {
+        s += (long double)w[q] * x[q];
+        t += w[q];
+    }
+    return (double)(s / t);
+}
+
+/* Jacobi-preconditioned CG on the symmetric weighted system S x = f,
+ * S = sgn * diag(w) * A (sgn = -1 for the pressure operator so that S is
+ * positive semidefinite).  The true residual f - S x is recomputed every
+ * 50 iterations and at the stop; stop when ||f - S x|| <= tol ||f||.
+ * For the pressure problem the residual and the iterate are projected
+ * onto the zero-weighted-mean subspace at each recomputation. */
+static int pcg(int64_t n, const int64_t *rp, const int64_t *ci, const double *av,
+               const double *w, double sgn, int proj, const double *f, double *x,
+               double tol, int maxit, int *stagnated)
+{
+    double *r = malloc(n * sizeof(double)), *z = malloc(n * sizeof(double));
+    double *p = malloc(n * sizeof(double)), *q = malloc(n * sizeof(double));
+    double *dinv = malloc(n * sizeof(double));
+    for (int64_t i = 0; i < n; ++i) {
+        double dii = 0.0;
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+            if (ci[e] == i) dii = av[e];
+        dinv[i] = 1.0 / (sgn * w[i] * dii);
+    }
+    double fn = sqrt(dot(n, f, f));
+    if (fn == 0.0) {
+        memset(x, 0, n * sizeof(double));
+        free(r); free(z); free(p); free(q); free(dinv);
+        return 0;
+    }
+    /* r = f - S x */
+    csr_mv(n, rp, ci, av, x, q);
+    for (int64_t i = 0; i < n; ++i) r[i] = f[i] - sgn * w[i] * q[i];
+    for (int64_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
+    memcpy(p, z, n * sizeof(double));
+    double rz = dot(n, r, z);
+    int it = 0;
+    double best = INFINITY;
+    int since_best = 0;
+    *stagnated = 0;
+    for (it = 1; it <= maxit; ++it) {
+        csr_mv(n, rp, ci, av, p, q);
+#pragma omp parallel for
+        for (int64_t i = 0; i < n; ++i) q[i] *= sgn * w[i];
+        double pq = dot(n, p, q);
+        if (!(pq > 0.0)) break;
+        double alpha = rz / pq;
+#pragma omp parallel for
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] += alpha * p[i];
+            r[i] -= alpha * q[i];
+        }
+        if (it % 50 == 0) {
+            if (proj) {
+                double m = wmean(n, w, x);
+                for (int64_t i = 0; i < n; ++i) x[i] -= m;
+            }
+            csr_mv(n, rp, ci, av, x, q);
+#pragma omp parallel for
+            for (int64_t i = 0; i < n; ++i) r[i] = f[i] - sgn * w[i] * q[i];
+            double rn = sqrt(dot(n, r, r));
+            if (rn <= tol * fn) break;
+            if (rn < 0.999 * best) { best = rn; since_best = 0; }
+            else if (++since_best >= 20) { *stagnated = 1; break; }
+        }
+#pragma omp parallel for
+        for (int64_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
+        double rz1 = dot(n, r, z);
+        double beta = rz1 / rz;
+        rz = rz1;
+#pragma omp parallel for
+        for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+        if (it % 50 != 0 && sqrt(dot(n, r, r)) <= tol * fn) {
+            /* confirm on the true residual */
+            csr_mv(n, rp, ci, av, x, q);
+            for (int64_t i = 0; i < n; ++i) r[i] = f[i] - sgn * w[i] * q[i];
+            if (sqrt(dot(n, r, r)) <= tol * fn) break;
+        }
+    }
+    free(r); free(z); free(p); free(q); free(dinv);
+    return it;
+}
+
+/* Solve A x = b for operator op (Helmholtz coefficient c ignored for
+ * op 0).  b and x in the caller's full layout.  Returns 0 on success. */
+int orc_solve(const orc_geom *g, int op, double c, const double *b_in, double *x_out,
+              double tol, int maxit, orc_info *info)
+{
+    if (op < 0 || op > 3) return -1;
+    if (op == 2 && g->ny < 2) return -1;
+    int64_t n = n_unknowns(g, op);
+    int64_t *rp = malloc((n + 1) * sizeof(int64_t));
+    int64_t *ci = malloc(7 * n * sizeof(int64_t));
+    double *av = malloc(7 * n * sizeof(double));
+    double *w = malloc(n * sizeof(double));
+    double *b = malloc(n * sizeof(double)), *f = malloc(n * sizeof(double));
+    double *x = calloc(n, sizeof(double)), *d = malloc(n * sizeof(double));
+    double *full_r = NULL;
+    orc_assemble(g, op, c, rp, ci, av);
+    orc_weights(g, op, w);
+    for (int64_t q = 0; q < n; ++q) b[q] = b_in[unknown_to_array(g, op, q)];
+    double sgn = (op == 0) ? -1.0 : 1.0;
+    int proj = (op == 0);
+    double removed = 0.0;
+    if (proj) { /* Neumann compatibility: remove the weighted mean of b */
+        removed = wmean(n, w, b);
+        for (int64_t q = 0; q < n; ++q) b[q] -= removed;
+    }
+    for (int64_t q = 0; q < n; ++q) f[q] = sgn * w[q] * b[q];
+    int stag = 0;
+    int iters = pcg(n, rp, ci, av, w, sgn, proj, f, x, tol, maxit, &stag);
+    if (proj) {
+        double m = wmean(n, w, x);
+        for (int64_t q = 0; q < n; ++q) x[q] -= m;
+    }
+    /* write out, evaluate the long double residual of the projected b */
+    int64_t nfull = (op == 2) ? (int64_t)g->nx * (g->ny + 1) * g->nz
+                              : (int64_t)g->nx * g->ny * g->nz;
+    double *full_b = calloc(nfull, sizeof(double));
+    full_r = calloc(nfull, sizeof(double));
+    memset(x_out, 0, nfull * sizeof(double));
+    for (int64_t q = 0; q < n; ++q) {
+        x_out[unknown_to_array(g, op, q)] = x[q];
+        full_b[unknown_to_array(g, op, q)] = b[q];
+    }
+    double norms[2];
+    orc_residual_ld(g, op, c, x_out, full_b, full_r, norms);
+    /* polish: x += A^{-1} r with r from the long double flux residual */
+    int psteps = 0, piters = 0;
+    double prev = norms[0];
+    for (int s = 0; s < 6 && norms[0] > 0.0; ++s) {
+        for (int64_t q = 0; q < n; ++q) d[q] = full_r[unknown_to_array(g, op, q)];
+        if (proj) {
+            double m = wmean(n, w, d);
+            for (int64_t q = 0; q < n; ++q) d[q] -= m;
+        }
+        for (int64_t q = 0; q < n; ++q) f[q] = sgn * w[q] * d[q];
+        memset(d, 0, n * sizeof(double));
+        int st2 = 0;
+        piters += pcg(n, rp, ci, av, w, sgn, proj, f, d, 1e-12, maxit, &st2);
+        for (int64_t q = 0; q < n; ++q) x[q] += d[q];
+        if (proj) {
+            double m = wmean(n, w, x);
+            for (int64_t q = 0; q < n; ++q) x[q] -= m;
+        }
+        for (int64_t q = 0; q < n; ++q) x_out[unknown_to_array(g, op, q)] = x[q];
+        orc_residual_ld(g, op, c, x_out, full_b, full_r, norms);
+        ++psteps;
+        if (!(norms[0] < 0.5 * prev)) break;
+        prev = norms[0];
+    }
+    if (info) {
+        info->iters = iters;
+        info->polish_steps = psteps;
+        info->polish_iters = piters;
+        info->stagnated = stag;
+        info->rel_residual = norms[1] > 0.0 ? norms[0] / norms[1] : 0.0;
+        info->removed_mean = removed;
+    }
+    free(rp); free(ci); free(av); free(w); free(b); free(f); free(x); free(d);
+    free(full_b); free(full_r);
+    return 0;
+}
+
+/* Weighted mean sum(W x)/sum(W) of a field in full layout (x over the
+ * unknowns of op). */
+double orc_weighted_mean(const orc_geom *g, int op, const double *x)
+{
+    int64_t n = n_unknowns(g, op);
+    long double s = 0.0L, t = 0.0L;
+    for (int64_t q = 0; q < n; ++q) {
+        double wq = unknown_weight(g, op, q);
+        s += (long double)wq * x[unknown_to_array(g, op, q)];
+        t += wq;
+    }
+    return (double)(s / t);
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

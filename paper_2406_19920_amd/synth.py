@@ -1,0 +1,123 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
+
+This module holds no arithmetic of the solver: it only draws random fields
+(numpy PCG64 ``default_rng``), low-pass filters them in index space and
+synthesises an immersed-boundary-like forcing shell.  Discrete operators
+(divergence, Laplacians) are applied by each side on its own.
+
+Layout: C order [z][y][x]; u, w are [nz][ny][nx]; v is [nz][ny+1][nx] with
+the wall faces j = 0 and j = ny included.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.fft as sfft
+
+
+def velocity(nx: int, ny: int, nz: int, seed: int):
+    """i.i.d. N(0,1) face velocities, drawn in the order u, v, w, each in
+    C order; v includes its wall faces."""
+    rng = np.random.default_rng(seed)
+    u = rng.standard_normal((nz, ny, nx))
+    v = rng.standard_normal((nz, ny + 1, nx))
+    w = rng.standard_normal((nz, ny, nx))
+    return u, v, w
+
+
+def scalar(nx: int, ny: int, nz: int, seed: int, rows: int | None = None):
+    """One i.i.d. N(0,1) field of shape [nz][rows or ny][nx]."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((nz, ny if rows is None else rows, nx))
+
+
+def lowpass(f: np.ndarray, kmax: float = 16.0) -> np.ndarray:
+    """Keep modes with sqrt(kx^2 + ky^2 + kz^2) <= kmax in index space:
+    kx, kz are the (signed) periodic DFT indices, ky the DCT-II index along
+    y.  Used to make smooth, channel-like synthetic fields."""
+    nz, ny, nx = f.shape
+    F = sfft.rfft(f, axis=2)
+    F = sfft.fft(F, axis=0)
+    F = sfft.dct(F.real, type=2, axis=1, norm="ortho") + 1j * sfft.dct(F.imag, type=2, axis=1, norm="ortho")
+    kx = np.arange(F.shape[2])
+    kz = np.fft.fftfreq(nz, d=1.0 / nz)
+    ky = np.arange(ny)
+    K2 = kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2
+    F = np.where(K2 <= kmax * kmax, F, 0.0)
+    F = sfft.idct(F.real, type=2, axis=1, norm="ortho") + 1j * sfft.idct(F.imag, type=2, axis=1, norm="ortho")
+    F = sfft.ifft(F, axis=0)
+    return np.ascontiguousarray(sfft.irfft(F, n=nx, axis=2))
+
+
+def filtered_velocity(nx: int, ny: int, nz: int, seed: int, kmax: float = 16.0,
+                      zero_wall_v: bool = True):
+    """N(0,1) face velocities low-pass filtered to index radius kmax; the
+    wall faces of v are set to zero after filtering when requested."""
+    u, v, w = velocity(nx, ny, nz, seed)
+    u, v, w = lowpass(u, kmax), lowpass(v, kmax), lowpass(w, kmax)
+    if zero_wall_v:
+        v[:, 0, :] = 0.0
+        v[:, ny, :] = 0.0
+    return u, v, w
+
+
+def _roma3(r: np.ndarray) -> np.ndarray:
+    """Three-point regularised delta kernel of Roma, Peskin and Berger
+    (1999), in index units; it sums to one over any unit-spaced lattice."""
+    a = np.abs(r)
+    out = np.zeros_like(a)
+    m1 = a <= 0.5
+    out[m1] = (1.0 + np.sqrt(1.0 - 3.0 * a[m1] ** 2)) / 3.0
+    m2 = (a > 0.5) & (a <= 1.5)
+    out[m2] = (5.0 - 3.0 * a[m2] - np.sqrt(np.maximum(0.0, 1.0 - 3.0 * (1.0 - a[m2]) ** 2))) / 6.0
+    return out
+
+
+def forcing_shell(nx: int, ny: int, nz: int, seed: int, radius_frac: float = 0.1):
+    """Immersed-boundary-like source: markers on a sphere (Fibonacci
+    lattice) of radius radius_frac * nx index units, centre uniform in
+    [0.3, 0.7] of each index extent, marker forces N(0,1)^3, spread to the
+    three staggered face grids with the Roma kernel in index space.  The
+    geometry lives in index space (stretching is ignored): it is a synthetic
+    source, not a physical body.  Returns (fu, fv, fw)."""
+    rng = np.random.default_rng(seed)
+    centre = rng.uniform(0.3, 0.7, size=3) * np.array([nx, ny, nz], dtype=np.float64)
+    R = radius_frac * nx
+    nmark = max(8, int(round(4.0 * np.pi * R * R)))
+    q = np.arange(nmark) + 0.5
+    zc = 1.0 - 2.0 * q / nmark
+    th = np.pi * (1.0 + 5.0 ** 0.5) * q
+    rr = np.sqrt(np.maximum(0.0, 1.0 - zc * zc))
+    X = centre[0] + R * rr * np.cos(th)
+    Y = centre[1] + R * rr * np.sin(th)
+    Z = centre[2] + R * zc
+    F = rng.standard_normal((nmark, 3))
+    fu = np.zeros((nz, ny, nx))
+    fv = np.zeros((nz, ny + 1, nx))
+    fw = np.zeros((nz, ny, nx))
+    # staggered positions in index units: u (i, j+.5, k+.5), v (i+.5, j, k+.5),
+    # w (i+.5, j+.5, k)
+    for comp, (arr, off) in enumerate(((fu, (0.0, 0.5, 0.5)), (fv, (0.5, 0.0, 0.5)),
+                                       (fw, (0.5, 0.5, 0.0)))):
+        nyr = arr.shape[1]
+        for m in range(nmark):
+            px, py, pz = X[m] - off[0], Y[m] - off[1], Z[m] - off[2]
+            ix0, iy0, iz0 = int(np.floor(px)) - 1, int(np.floor(py)) - 1, int(np.floor(pz)) - 1
+            ii = np.arange(ix0, ix0 + 4)
+            jj = np.arange(iy0, iy0 + 4)
+            kk = np.arange(iz0, iz0 + 4)
+            wx, wy, wz = _roma3(ii - px), _roma3(jj - py), _roma3(kk - pz)
+            ok = (jj >= 0) & (jj < nyr)
+            wgt = wz[:, None, None] * wy[None, :, None] * wx[None, None, :] * F[m, comp]
+            wgt = wgt[:, ok, :]
+            arr[np.ix_(kk % nz, jj[ok], ii % nx)] += wgt
+    return fu, fv, fw
+
+
+def manufactured(nx: int, ny: int, nz: int, seed: int, rows: int | None = None,
+                 kmax: float | None = 8.0, noise: float = 1e-3):
+    """A smooth seeded field plus a small white-noise part: used as a known
+    exact solution x_true (the right-hand side A x_true is then formed by
+    whichever side is being checked)."""
+    f = scalar(nx, ny, nz, seed, rows)
+    g = lowpass(f, kmax) if kmax is not None else np.zeros_like(f)
+    return g + noise * scalar(nx, ny, nz, seed + 7919, rows)
