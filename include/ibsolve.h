@@ -1,0 +1,220 @@
+/*
+ * ibsolve: direct solver for the linear systems of one fractional step of
+ * an incompressible staggered-grid flow solver, on AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The systems are those of the Runge-Kutta sub-step (Section 2.1):
+ *   - the Helmholtz problem for each intermediate velocity component,
+ *     eq. (e), written here as (I - c L) x = r with c = beta_n dt / Re
+ *     (or 0.5 nu dt for Crank-Nicolson);
+ *   - the pseudo-pressure Poisson problem, eq. (f), L_p phi = b, with the
+ *     null mode fixed (Section 2.3.3, items S2 and S2.1);
+ *   - the projection u = u* - g grad(phi), eq. (g), and the pressure
+ *     update p += phi - c_p lap(phi), eq. (h).
+ * Second-order central differences on a staggered Cartesian grid
+ * (Section 2.1): periodic in x and z, walls in y (homogeneous Dirichlet
+ * velocity, homogeneous Neumann pressure, Appendix B), y faces optionally
+ * stretched by tanh.
+ *
+ * Method: x and z are diagonalised by precomputed 1-D orthonormal
+ * eigenvector matrices applied as dense contractions (the paper's 2-D FFT
+ * of the two periodic directions, Section 2.3.3, items S1.1/S2.1, with the
+ * modified wavenumbers of Appendix A as eigenvalues); every (x-mode,
+ * z-mode) pencil is then a tridiagonal system along y (Appendix B), solved
+ * directly.
+ *
+ * Conventions for every entry point:
+ *   - Arrays are C-contiguous [z][y][x] (x fastest), FP64, in device memory
+ *     owned by the caller.  Cell fields (p, phi, b) and the x- and z-face
+ *     velocities (u, w) are [nz][ny][nx].  The y-face velocity v is
+ *     [nz][ny+1][nx]; its wall faces j = 0 and j = ny are ignored on input
+ *     and written as 0 on output.
+ *   - u[k][j][i] sits on the x-face at x = i*hx (between cells i-1 and i),
+ *     w[k][j][i] on the z-face at z = k*hz, v[k][j][i] on the y-face y_f[j].
+ *   - The library never allocates device memory: constants and workspace are
+ *     caller-owned buffers sized by solver_plan_bytes().
+ *   - Every call is asynchronous on the given stream (a hipStream_t passed
+ *     as void*; NULL = the default stream) and returns an ibs_status.
+ *     Argument errors are detected on the host before anything is enqueued.
+ *     Errors raised asynchronously by the device surface in info->status or
+ *     at the next call.  No call throws across this interface.
+ *   - ibs_last_error() returns a thread-local message for the last failure.
+ */
+#ifndef IBSOLVE_H
+#define IBSOLVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ibs_plan_s *ibs_plan;
+
+typedef enum {
+    IBS_OK = 0,
+    IBS_ERR_INVALID_ARG = 1,         /* bad pointer, size, shape or value       */
+    IBS_ERR_UNSUPPORTED = 2,         /* valid request this build does not serve */
+    IBS_ERR_WORKSPACE_TOO_SMALL = 3, /* work_bytes below solver_plan_bytes()    */
+    IBS_ERR_HIP = 4,                 /* a HIP runtime call failed               */
+    IBS_ERR_NOT_CONVERGED = 5,       /* refined path missed tol within max_iter */
+    IBS_ERR_INCOMPATIBLE_RHS = 6,    /* strict_compat and b has a weighted mean */
+    IBS_ERR_NOT_UPLOADED = 7         /* solver_plan_upload() not called yet     */
+} ibs_status;
+
+typedef enum {
+    IBS_FP64 = 0,           /* every stage in FP64                              */
+    IBS_REFINED_FP16X2 = 1, /* split-FP16 transforms, FP32 accumulation,
+                               refined against an FP64 residual                */
+    IBS_REFINED_BF16X3 = 2, /* split-BF16 (3 terms) transforms, FP32 accum.     */
+    IBS_REFINED_AUTO = 3    /* library picks the split scheme                   */
+} ibs_precision;
+
+typedef enum { IBS_PERIODIC = 0, IBS_DIRICHLET = 1, IBS_NEUMANN = 2 } ibs_bc;
+
+/* Problem description.  Grid: nx*ny*nz cells on [0,lx]x[0,ly]x[0,lz];
+ * hx = lx/nx, hz = lz/nz; y faces y_f[j] = (ly/2)(1 + tanh(beta(2j/ny-1))/
+ * tanh(beta)), j = 0..ny (beta = 0: uniform), unless y_faces is given.
+ * Supported: nx, nz multiples of 16 in [16, 1024]; ny in [2, 768];
+ * bc_x = bc_z = IBS_PERIODIC; bc_y_vel = IBS_DIRICHLET; bc_y_p = IBS_NEUMANN. */
+typedef struct {
+    int32_t nx, ny, nz;
+    double lx, ly, lz;        /* <= 0 means 1                                */
+    double beta;              /* tanh stretching of y; 0 = uniform           */
+    const double *y_faces;    /* optional host array [ny+1], strictly
+                                 increasing; overrides beta/ly; copied        */
+    int32_t bc_x, bc_z;       /* ibs_bc                                      */
+    int32_t bc_y_vel, bc_y_p; /* ibs_bc                                      */
+    int32_t precision;        /* ibs_precision                               */
+    double tol;               /* refined path: target ||delta||/||x|| (1e-10 if <= 0) */
+    int32_t max_iter;         /* refined path: refinement steps (0: default) */
+    int32_t strict_compat;    /* 1: Poisson rhs with nonzero weighted mean
+                                 reports IBS_ERR_INCOMPATIBLE_RHS in info    */
+} ibs_grid_desc;
+
+/* Per-solve report, written by the device at the end of the solve.  Must
+ * point to memory the device can write (device memory or pinned host
+ * memory); may be NULL. */
+typedef struct {
+    int32_t iters;          /* transform passes (1 for FP64)                   */
+    int32_t status;         /* ibs_status of the device part of the solve      */
+    double rel_residual;    /* refined: ||b - A x|| / ||b|| at the last check   */
+    double rel_correction;  /* refined: ||delta|| / ||x|| of the last step      */
+    double removed_mean;    /* Poisson: volume-weighted mean removed from b    */
+} ibs_solve_info;
+
+/* Operation codes for solver_plan_bytes() and residual(). */
+#define IBS_OP_POISSON 0
+#define IBS_OP_HELMHOLTZ_U 1
+#define IBS_OP_HELMHOLTZ_V 2
+#define IBS_OP_HELMHOLTZ_W 3
+
+/* Build a plan on the host: the y grid, the tridiagonal coefficients of the
+ * y operators (Appendix B, generalised to stretched y), the x and z
+ * eigenvector matrices and eigenvalues (Appendix A: lambda = -kappa'^2),
+ * kernel tile choices.  *out owns host memory only; free it with
+ * solver_plan_destroy().  Errors: IBS_ERR_INVALID_ARG, IBS_ERR_UNSUPPORTED. */
+ibs_status solver_plan(const ibs_grid_desc *desc, ibs_plan *out);
+
+/* Byte counts for the caller's buffers.  op: IBS_OP_POISSON, or
+ * IBS_OP_HELMHOLTZ_U for a Helmholtz batch of ncomp (1..3) components (the
+ * count covers any mix of u, v, w); ncomp is ignored for Poisson.
+ * const_bytes: size of the device constant buffer for solver_plan_upload();
+ * work_bytes: minimum workspace for one solve call.  Either output pointer
+ * may be NULL. */
+ibs_status solver_plan_bytes(ibs_plan plan, int32_t op, int32_t ncomp,
+                             size_t *const_bytes, size_t *work_bytes);
+
+/* Copy the plan's constants into dev_const (device memory, >= const_bytes,
+ * 256-byte aligned) on stream.  The plan remembers dev_const; it must stay
+ * allocated while the plan is used.  The copy reads host memory owned by
+ * the plan, so the plan must outlive the copy. */
+ibs_status solver_plan_upload(ibs_plan plan, void *dev_const, size_t bytes,
+                              void *stream);
+
+ibs_status solver_plan_destroy(ibs_plan plan);
+
+/* Pressure Poisson problem, eq. (f): L_p phi = b with homogeneous Neumann
+ * walls.  The volume-weighted mean of b is removed first (Neumann
+ * compatibility; reported in info->removed_mean) and phi is returned with
+ * zero volume-weighted mean (the null mode; internally the singular
+ * (0,0) pencil is pinned at its first point as in Section 2.3.3, item
+ * S2.1, then shifted).  b: [nz][ny][nx] device, read only; phi: same shape,
+ * may alias b.  work: device buffer of >= work_bytes (solver_plan_bytes
+ * with IBS_OP_POISSON).  Errors: IBS_ERR_INVALID_ARG, IBS_ERR_NOT_UPLOADED,
+ * IBS_ERR_WORKSPACE_TOO_SMALL, IBS_ERR_HIP. */
+ibs_status solve_poisson(ibs_plan plan, const double *b, double *phi, void *work,
+                         size_t work_bytes, ibs_solve_info *info, void *stream);
+
+/* Helmholtz problems, eq. (e): (I - c[q] L) x[q] = r[q] for ncomp (1..3)
+ * components solved together (one launch per stage).  comp[q] in {0 = u,
+ * 1 = v, 2 = w} selects the grid of component q (u, w: Dirichlet wall by a
+ * mirror ghost, Appendix B alpha = 2; v: wall-face values, alpha = 1).
+ * comp, c, r, x are HOST arrays of ncomp entries; r[q], x[q] are device
+ * fields of the component's shape; x[q] may alias r[q]; c[q] >= 0.
+ * info: NULL or ncomp records.  Errors as solve_poisson. */
+ibs_status solve_helmholtz_batch(ibs_plan plan, int32_t ncomp, const int32_t *comp,
+                                 const double *c, const double *const *r,
+                                 double *const *x, void *work, size_t work_bytes,
+                                 ibs_solve_info *info, void *stream);
+
+/* Residual r = b - A x in FP64 for op IBS_OP_POISSON (A = L_p) or
+ * IBS_OP_HELMHOLTZ_{U,V,W} (A = I - c L), with the 7-point stencil.  x, b, r
+ * device fields of the op's shape (r may not alias x).  norms2: NULL or a
+ * device double[2] receiving ||r||_2^2 and ||b||_2^2 over the unknowns
+ * (deterministic fixed-order reduction).  Uses no workspace beyond an
+ * internal region of the plan's constant buffer; calls on one plan must not
+ * overlap in time.  Errors: IBS_ERR_INVALID_ARG, IBS_ERR_NOT_UPLOADED. */
+ibs_status residual(ibs_plan plan, int32_t op, double c, const double *x,
+                    const double *b, double *r, double *norms2, void *stream);
+
+/* RHS of the Poisson problem (kernel E2 of Section 2.3.2):
+ * b = scale * D(u, v, w), D the staggered divergence.  v's wall faces are
+ * read (a nonzero wall flux makes b incompatible).  b: [nz][ny][nx]. */
+ibs_status ibs_divergence(ibs_plan plan, const double *u, const double *v,
+                          const double *w, double *b, double scale, void *stream);
+
+/* Projection, eq. (g), and pressure update, eq. (h) (kernel E3):
+ * u -= g dphi/dx, v -= g dphi/dy (interior faces; walls set to 0),
+ * w -= g dphi/dz; if p != NULL: p += phi - cp * lap_phi, where lap_phi is the
+ * already-known Laplacian of phi (the Poisson right-hand side b; may be
+ * NULL when cp == 0).  In place on u, v, w, p. */
+ibs_status ibs_correct(ibs_plan plan, const double *phi, double *u, double *v,
+                       double *w, double g, double *p, const double *lap_phi,
+                       double cp, void *stream);
+
+/* Host copies of the plan's tables, for inspection and host-side checks.
+ * table: 0 y faces [ny+1]; 1 Q_x [nx*nx] (row-major, Q[i*nx+a] = mode a at
+ * grid index i); 2 Q_z [nz*nz]; 3 lambda_x [nx]; 4 lambda_z [nz];
+ * 5+3*kind+{0,1,2}: lower, diagonal, upper coefficients [ny+1] of the y
+ * operator of kind 0 (pressure), 1 (u, w), 2 (v, rows = faces 0..ny).
+ * out: host array of n doubles; n must equal the table length (queried by
+ * passing out = NULL, which returns the length through *n). */
+ibs_status ibs_plan_export(ibs_plan plan, int32_t table, double *out, size_t *n);
+
+/* Live per-kernel profile of one plan's launches, for benchmarking.
+ * ibs_profile(plan, 1) clears the record and brackets every later launch of
+ * the plan with HIP events on the launch stream; ibs_profile(plan, 0) stops.
+ * ibs_profile_read() synchronises on the recorded events and returns, for
+ * kernel class `kernel`, the summed device time (ms), the launch count and
+ * the summed algorithmic flops and HBM bytes of those launches (the work
+ * the method needs, not counter readings).  Kernel classes: 0 x transform
+ * (FP64 matrix cores), 1 z transform (FP64), 2 y tridiagonal (FP64),
+ * 3 divergence, 4 correction, 5 residual, 6 x transform (split),
+ * 7 z transform (split), 8 y tridiagonal (FP32 data), 9 refinement update.
+ * Any output pointer may be NULL. */
+ibs_status ibs_profile(ibs_plan plan, int32_t enable);
+ibs_status ibs_profile_read(ibs_plan plan, int32_t kernel, double *ms, int64_t *launches,
+                            double *flops, double *bytes);
+
+/* Thread-local text of the last error (never NULL). */
+const char *ibs_last_error(void);
+
+/* Library version string. */
+const char *ibs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IBSOLVE_H */

@@ -1,0 +1,345 @@
+// C ABI of the solver library: validation, error layer, stage sequencing.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "ibs_internal.h"
+
+namespace ibs {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+ibs_status build_plan(const ibs_grid_desc &d, Plan *&out);
+
+static size_t field_doubles(const Plan &p, int rows) { return (size_t)p.nz * rows * p.nx; }
+
+static ibs_status hip_fail(hipError_t e, const char *where)
+{
+    set_error(std::string(where) + ": " + hipGetErrorString(e));
+    return IBS_ERR_HIP;
+}
+
+static bool aligned32(const void *ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 31u) == 0; }
+
+static ibs_status check_plan(ibs_plan plan)
+{
+    if (!plan) { set_error("plan is NULL"); return IBS_ERR_INVALID_ARG; }
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (!p->dev_const) { set_error("solver_plan_upload() has not been called"); return IBS_ERR_NOT_UPLOADED; }
+    return IBS_OK;
+}
+
+// ---- optional live profile ------------------------------------------------
+static hipEvent_t pool_get(Profile &pr)
+{
+    if (!pr.pool.empty()) {
+        hipEvent_t e = pr.pool.back();
+        pr.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+static void prof_collect(Profile &pr)
+{
+    for (auto &r : pr.recs) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.stop) == hipSuccess &&
+            hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
+            pr.ms[r.kid] += ms;
+            pr.flops[r.kid] += r.flops;
+            pr.bytes[r.kid] += r.bytes;
+            pr.launches[r.kid] += 1;
+        }
+        pr.pool.push_back(r.start);
+        pr.pool.push_back(r.stop);
+    }
+    pr.recs.clear();
+}
+
+// Launch through f(); when profiling, bracket it with events on stream s and
+// book the algorithmic flops and bytes of the launch to kernel class kid.
+template <typename F>
+static hipError_t timed(Plan &p, int kid, double flops, double bytes, hipStream_t s, F f)
+{
+    if (!p.prof.on) return f();
+    if (p.prof.recs.size() > 4096) prof_collect(p.prof);
+    ProfRec r{kid, pool_get(p.prof), pool_get(p.prof), flops, bytes};
+    if (!r.start || !r.stop) return f();
+    hipEventRecord(r.start, s);
+    hipError_t e = f();
+    hipEventRecord(r.stop, s);
+    p.prof.recs.push_back(r);
+    return e;
+}
+
+size_t work_bytes_for(const Plan &p, int op, int ncomp)
+{
+    if (op == IBS_OP_POISSON) return field_doubles(p, p.ny) * sizeof(double);
+    return (size_t)ncomp * field_doubles(p, p.ny + 1) * sizeof(double);
+}
+
+static double total_cells(const JobSet &js, const Plan &p)
+{
+    double n = 0;
+    for (int q = 0; q < js.n; ++q) n += (double)p.nz * js.j[q].rows * p.nx;
+    return n;
+}
+
+// The five FP64 stages.  js.j[q].in holds the right-hand side; W[q] is the
+// job's scratch field and X[q] its output.
+static ibs_status run_fp64_pipeline_multi(Plan &p, JobSet js, double *const *W, double *const *X,
+                                          bool poisson, hipStream_t s)
+{
+    hipError_t e;
+    const double cells = total_cells(js, p);
+    const double xflop = 2.0 * p.nx * cells, zflop = 2.0 * p.nz * cells, rw = 16.0 * cells;
+    const double *xb_f = blob_ptr(p, p.lay.bx_fwd), *xb_i = blob_ptr(p, p.lay.bx_inv);
+    const double *za_f = blob_ptr(p, p.lay.az_fwd), *za_i = blob_ptr(p, p.lay.az_inv);
+    for (int q = 0; q < js.n; ++q) js.j[q].out = W[q];
+    e = timed(p, PK_XGEMM, xflop, rw, s, [&] { return launch_xgemm_f64(js, p.nz, p.nx, p.nx, xb_f, s); });
+    if (e != hipSuccess) return hip_fail(e, "x forward");
+    for (int q = 0; q < js.n; ++q) { js.j[q].in = W[q]; js.j[q].out = X[q]; }
+    e = timed(p, PK_ZGEMM, zflop, rw, s, [&] { return launch_zgemm_f64(js, p.nz, p.nz, p.nx, za_f, s); });
+    if (e != hipSuccess) return hip_fail(e, "z forward");
+    for (int q = 0; q < js.n; ++q) js.j[q].in = X[q];
+    e = timed(p, PK_TRIDIAG, 20.0 * cells, rw, s, [&] { return launch_tridiag_f64(js, p, poisson, s); });
+    if (e != hipSuccess) return hip_fail(e, "tridiagonal");
+    for (int q = 0; q < js.n; ++q) { js.j[q].in = X[q]; js.j[q].out = W[q]; }
+    e = timed(p, PK_ZGEMM, zflop, rw, s, [&] { return launch_zgemm_f64(js, p.nz, p.nz, p.nx, za_i, s); });
+    if (e != hipSuccess) return hip_fail(e, "z inverse");
+    for (int q = 0; q < js.n; ++q) { js.j[q].in = W[q]; js.j[q].out = X[q]; }
+    e = timed(p, PK_XGEMM, xflop, rw, s, [&] { return launch_xgemm_f64(js, p.nz, p.nx, p.nx, xb_i, s); });
+    if (e != hipSuccess) return hip_fail(e, "x inverse");
+    return IBS_OK;
+}
+
+static ibs_status run_fp64_pipeline(Plan &p, JobSet js, double *W, double *X, bool poisson,
+                                    hipStream_t s)
+{
+    return run_fp64_pipeline_multi(p, js, &W, &X, poisson, s);
+}
+
+}  // namespace ibs
+
+using namespace ibs;
+
+extern "C" {
+
+const char *ibs_last_error(void) { return g_err.c_str(); }
+
+const char *ibs_version(void) { return "ibsolve 0.1 (gfx950)"; }
+
+ibs_status solver_plan(const ibs_grid_desc *desc, ibs_plan *out)
+{
+    try {
+        if (!desc || !out) { set_error("desc and out must be non-NULL"); return IBS_ERR_INVALID_ARG; }
+        *out = nullptr;
+        if (desc->ny > 768) { set_error("ny must be <= 768"); return IBS_ERR_UNSUPPORTED; }
+        Plan *p = nullptr;
+        ibs_status st = build_plan(*desc, p);
+        if (st != IBS_OK) return st;
+        *out = reinterpret_cast<ibs_plan>(p);
+        return IBS_OK;
+    } catch (...) {
+        set_error("host exception while building the plan");
+        return IBS_ERR_INVALID_ARG;
+    }
+}
+
+ibs_status solver_plan_bytes(ibs_plan plan, int32_t op, int32_t ncomp, size_t *const_bytes,
+                             size_t *work_bytes)
+{
+    if (!plan) { set_error("plan is NULL"); return IBS_ERR_INVALID_ARG; }
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (op < IBS_OP_POISSON || op > IBS_OP_HELMHOLTZ_W) { set_error("bad op"); return IBS_ERR_INVALID_ARG; }
+    if (op != IBS_OP_POISSON && (ncomp < 1 || ncomp > 3)) { set_error("ncomp must be 1..3"); return IBS_ERR_INVALID_ARG; }
+    if (const_bytes) *const_bytes = p->lay.total;
+    if (work_bytes) *work_bytes = work_bytes_for(*p, op, ncomp);
+    return IBS_OK;
+}
+
+ibs_status solver_plan_upload(ibs_plan plan, void *dev_const, size_t bytes, void *stream)
+{
+    if (!plan || !dev_const) { set_error("plan and dev_const must be non-NULL"); return IBS_ERR_INVALID_ARG; }
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (bytes < p->lay.total) { set_error("constant buffer smaller than const_bytes"); return IBS_ERR_WORKSPACE_TOO_SMALL; }
+    if ((reinterpret_cast<uintptr_t>(dev_const) & 255u) != 0) { set_error("dev_const must be 256-byte aligned"); return IBS_ERR_INVALID_ARG; }
+    hipError_t e = hipMemcpyAsync(dev_const, p->blob.data(), p->lay.total, hipMemcpyHostToDevice,
+                                  static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "solver_plan_upload");
+    p->dev_const = dev_const;
+    return IBS_OK;
+}
+
+ibs_status solver_plan_destroy(ibs_plan plan)
+{
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (p) {
+        prof_collect(p->prof);
+        for (hipEvent_t e : p->prof.pool) hipEventDestroy(e);
+    }
+    delete p;
+    return IBS_OK;
+}
+
+ibs_status solve_poisson(ibs_plan plan, const double *b, double *phi, void *work, size_t work_bytes,
+                         ibs_solve_info *info, void *stream)
+{
+    ibs_status st = check_plan(plan);
+    if (st != IBS_OK) return st;
+    Plan &p = *reinterpret_cast<Plan *>(plan);
+    if (!b || !phi || !work) { set_error("b, phi and work must be non-NULL"); return IBS_ERR_INVALID_ARG; }
+    if (!aligned32(b) || !aligned32(phi) || !aligned32(work)) { set_error("device arrays must be 32-byte aligned"); return IBS_ERR_INVALID_ARG; }
+    if (work_bytes < work_bytes_for(p, IBS_OP_POISSON, 1)) { set_error("workspace too small"); return IBS_ERR_WORKSPACE_TOO_SMALL; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double *W = static_cast<double *>(work);
+    JobSet js{};
+    js.n = 1;
+    js.j[0].rows = p.ny;
+    js.j[0].kind = KIND_P;
+    js.j[0].c = 0.0;
+    js.j[0].info = info;
+    // x forward: b -> W; z forward: W -> phi; pencils in place on phi;
+    // z inverse: phi -> W; x inverse: W -> phi
+    js.j[0].in = b; js.j[0].out = W;
+    ibs_status r = run_fp64_pipeline(p, js, W, phi, true, s);
+    return r;
+}
+
+ibs_status solve_helmholtz_batch(ibs_plan plan, int32_t ncomp, const int32_t *comp, const double *c,
+                                 const double *const *r, double *const *x, void *work,
+                                 size_t work_bytes, ibs_solve_info *info, void *stream)
+{
+    ibs_status st = check_plan(plan);
+    if (st != IBS_OK) return st;
+    Plan &p = *reinterpret_cast<Plan *>(plan);
+    if (ncomp < 1 || ncomp > 3) { set_error("ncomp must be 1..3"); return IBS_ERR_INVALID_ARG; }
+    if (!comp || !c || !r || !x || !work) { set_error("comp, c, r, x and work must be non-NULL"); return IBS_ERR_INVALID_ARG; }
+    if (work_bytes < work_bytes_for(p, IBS_OP_HELMHOLTZ_U, ncomp)) { set_error("workspace too small"); return IBS_ERR_WORKSPACE_TOO_SMALL; }
+    if (!aligned32(work)) { set_error("work must be 32-byte aligned"); return IBS_ERR_INVALID_ARG; }
+    JobSet js{};
+    js.n = ncomp;
+    const size_t stride = field_doubles(p, p.ny + 1);
+    double *W = static_cast<double *>(work);
+    for (int q = 0; q < ncomp; ++q) {
+        if (comp[q] < 0 || comp[q] > 2) { set_error("comp must be 0 (u), 1 (v) or 2 (w)"); return IBS_ERR_INVALID_ARG; }
+        if (!(c[q] >= 0.0) || !std::isfinite(c[q])) { set_error("c must be finite and >= 0"); return IBS_ERR_INVALID_ARG; }
+        if (!r[q] || !x[q] || !aligned32(r[q]) || !aligned32(x[q])) { set_error("r[q], x[q] must be non-NULL and 32-byte aligned"); return IBS_ERR_INVALID_ARG; }
+        js.j[q].rows = comp[q] == 1 ? p.ny + 1 : p.ny;
+        js.j[q].kind = comp[q] == 1 ? KIND_F : KIND_C;
+        js.j[q].c = c[q];
+        js.j[q].info = info ? info + q : nullptr;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int q = 0; q < ncomp; ++q) { js.j[q].in = r[q]; js.j[q].out = W + q * stride; }
+    double *Ws[4], *Xs[4];
+    for (int q = 0; q < ncomp; ++q) { Ws[q] = W + q * stride; Xs[q] = x[q]; }
+    return run_fp64_pipeline_multi(p, js, Ws, Xs, false, s);
+}
+
+ibs_status residual(ibs_plan plan, int32_t op, double c, const double *x, const double *b, double *r,
+                    double *norms2, void *stream)
+{
+    ibs_status st = check_plan(plan);
+    if (st != IBS_OK) return st;
+    Plan &p = *reinterpret_cast<Plan *>(plan);
+    if (op < IBS_OP_POISSON || op > IBS_OP_HELMHOLTZ_W) { set_error("bad op"); return IBS_ERR_INVALID_ARG; }
+    if (!x || !b || !r) { set_error("x, b, r must be non-NULL"); return IBS_ERR_INVALID_ARG; }
+    if (r == x) { set_error("r may not alias x"); return IBS_ERR_INVALID_ARG; }
+    if (!std::isfinite(c)) { set_error("c must be finite"); return IBS_ERR_INVALID_ARG; }
+    const double cells = (double)p.nz * (op == IBS_OP_HELMHOLTZ_V ? p.ny + 1 : p.ny) * p.nx;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = timed(p, PK_RESIDUAL, 10.0 * cells, 24.0 * cells, s,
+                         [&] { return launch_residual(p, op, c, x, b, r, norms2, s); });
+    if (e != hipSuccess) return hip_fail(e, "residual");
+    return IBS_OK;
+}
+
+ibs_status ibs_divergence(ibs_plan plan, const double *u, const double *v, const double *w, double *b,
+                          double scale, void *stream)
+{
+    ibs_status st = check_plan(plan);
+    if (st != IBS_OK) return st;
+    Plan &p = *reinterpret_cast<Plan *>(plan);
+    if (!u || !v || !w || !b) { set_error("u, v, w, b must be non-NULL"); return IBS_ERR_INVALID_ARG; }
+    const double cells = (double)p.nz * p.ny * p.nx;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = timed(p, PK_DIVERGENCE, 7.0 * cells, 8.0 * (4.0 * cells + (double)p.nz * p.nx), s,
+                         [&] { return launch_divergence(p, u, v, w, b, scale, s); });
+    if (e != hipSuccess) return hip_fail(e, "divergence");
+    return IBS_OK;
+}
+
+ibs_status ibs_correct(ibs_plan plan, const double *phi, double *u, double *v, double *w, double g,
+                       double *pres, const double *lap_phi, double cp, void *stream)
+{
+    ibs_status st = check_plan(plan);
+    if (st != IBS_OK) return st;
+    Plan &p = *reinterpret_cast<Plan *>(plan);
+    if (!phi || !u || !v || !w) { set_error("phi, u, v, w must be non-NULL"); return IBS_ERR_INVALID_ARG; }
+    if (pres && cp != 0.0 && !lap_phi) { set_error("lap_phi is required when p != NULL and cp != 0"); return IBS_ERR_INVALID_ARG; }
+    const double cells = (double)p.nz * p.ny * p.nx;
+    const double extra = pres ? (lap_phi && cp != 0.0 ? 24.0 : 16.0) * cells : 0.0;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = timed(p, PK_CORRECT, 9.0 * cells, 56.0 * cells + 16.0 * p.nz * p.nx + extra, s,
+                         [&] { return launch_correct(p, phi, u, v, w, g, pres, lap_phi, cp, s); });
+    if (e != hipSuccess) return hip_fail(e, "correct");
+    return IBS_OK;
+}
+
+ibs_status ibs_profile(ibs_plan plan, int32_t enable)
+{
+    if (!plan) { set_error("plan is NULL"); return IBS_ERR_INVALID_ARG; }
+    Plan &p = *reinterpret_cast<Plan *>(plan);
+    prof_collect(p.prof);
+    for (int k = 0; k < NUM_PK; ++k) {
+        p.prof.ms[k] = 0; p.prof.flops[k] = 0; p.prof.bytes[k] = 0; p.prof.launches[k] = 0;
+    }
+    p.prof.on = enable != 0;
+    return IBS_OK;
+}
+
+ibs_status ibs_profile_read(ibs_plan plan, int32_t kernel, double *ms, int64_t *launches,
+                            double *flops, double *bytes)
+{
+    if (!plan || kernel < 0 || kernel >= NUM_PK) { set_error("bad plan or kernel class"); return IBS_ERR_INVALID_ARG; }
+    Plan &p = *reinterpret_cast<Plan *>(plan);
+    prof_collect(p.prof);
+    if (ms) *ms = p.prof.ms[kernel];
+    if (launches) *launches = p.prof.launches[kernel];
+    if (flops) *flops = p.prof.flops[kernel];
+    if (bytes) *bytes = p.prof.bytes[kernel];
+    return IBS_OK;
+}
+
+ibs_status ibs_plan_export(ibs_plan plan, int32_t table, double *out, size_t *n)
+{
+    if (!plan || !n) { set_error("plan and n must be non-NULL"); return IBS_ERR_INVALID_ARG; }
+    Plan &p = *reinterpret_cast<Plan *>(plan);
+    const std::vector<double> *v = nullptr;
+    switch (table) {
+    case 0: v = &p.yf; break;
+    case 1: v = &p.qx; break;
+    case 2: v = &p.qz; break;
+    case 3: v = &p.lam_x; break;
+    case 4: v = &p.lam_z; break;
+    default:
+        if (table >= 5 && table < 5 + 3 * NUM_KINDS) {
+            const int kd = (table - 5) / 3, which = (table - 5) % 3;
+            v = which == 0 ? &p.lo[kd] : (which == 1 ? &p.di[kd] : &p.up[kd]);
+        }
+    }
+    if (!v) { set_error("unknown table"); return IBS_ERR_INVALID_ARG; }
+    if (!out) { *n = v->size(); return IBS_OK; }
+    if (*n != v->size()) { set_error("n does not match the table length"); return IBS_ERR_INVALID_ARG; }
+    std::memcpy(out, v->data(), v->size() * sizeof(double));
+    return IBS_OK;
+}
+
+}  // extern "C"

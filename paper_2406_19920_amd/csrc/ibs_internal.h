@@ -1,0 +1,115 @@
+// Internal declarations shared by the host runtime and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ibsolve.h"
+
+namespace ibs {
+
+// Kinds of y operator (rows of the tridiagonal systems, Appendix B):
+//   KIND_P: pressure, cell centres, homogeneous Neumann walls (n = ny rows)
+//   KIND_C: u and w, cell-centre height, Dirichlet wall by mirror ghost
+//   KIND_F: v, y faces incl. the two wall faces as identity rows (n = ny+1)
+enum { KIND_P = 0, KIND_C = 1, KIND_F = 2, NUM_KINDS = 3 };
+
+// Byte offsets of the tables inside the device constant blob.
+struct BlobLayout {
+    size_t bx_fwd, bx_inv;   // x transform as B operand of C = A B, swizzled
+    size_t az_fwd, az_inv;   // z transform as A operand of C = A B, swizzled
+    size_t lam_x, lam_z;     // eigenvalues (double)
+    size_t lo[NUM_KINDS], di[NUM_KINDS], up[NUM_KINDS];  // y operator rows
+    size_t wy;               // Delta_j (pressure weights), ny doubles
+    size_t dyc, dyf;         // cell heights [ny], centre distances [ny+1]
+    size_t red;              // reduction scratch (doubles)
+    size_t red_count;        // number of doubles in the reduction scratch
+    size_t total;
+};
+
+// Kernel classes for the optional live profile (HIP events around launches).
+enum {
+    PK_XGEMM = 0, PK_ZGEMM, PK_TRIDIAG, PK_DIVERGENCE, PK_CORRECT, PK_RESIDUAL,
+    PK_XGEMM_SPLIT, PK_ZGEMM_SPLIT, PK_TRIDIAG_F32, PK_UPDATE, NUM_PK
+};
+
+struct ProfRec {
+    int kid;
+    hipEvent_t start, stop;
+    double flops, bytes;
+};
+
+struct Profile {
+    bool on = false;
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> pool;
+    double ms[NUM_PK] = {};
+    double flops[NUM_PK] = {};
+    double bytes[NUM_PK] = {};
+    long long launches[NUM_PK] = {};
+};
+
+struct Plan {
+    ibs_grid_desc desc;
+    int nx, ny, nz;
+    double hx, hz;
+    std::vector<double> yf, yc, dyc, dyf;          // grid
+    std::vector<double> qx, qz;                    // Q[i][a], row-major n x n
+    std::vector<double> lam_x, lam_z;
+    std::vector<double> lo[NUM_KINDS], di[NUM_KINDS], up[NUM_KINDS];
+    int rows[NUM_KINDS];
+    BlobLayout lay;
+    std::vector<unsigned char> blob;               // host image of the blob
+    void *dev_const = nullptr;
+    Profile prof;
+};
+
+// Per-component record for batched launches (passed by value).
+struct FieldJob {
+    const double *in;   // input field
+    double *out;        // output field
+    int rows;           // rows per z-plane (ny or ny+1)
+    int kind;           // KIND_*
+    double c;           // Helmholtz coefficient (Poisson: unused)
+    void *info;         // ibs_solve_info* or null
+};
+struct JobSet {
+    FieldJob j[4];
+    int n;
+};
+
+// Error reporting
+void set_error(const std::string &msg);
+
+// ---- kernel launchers (return hipError_t of the launch) --------------------
+// C[M x N] = A[M x K] * Bs, A row-major (lda), Bs the swizzled K x N matrix;
+// batched over the jobs of js (A = js.j[q].in, C = js.j[q].out, M = nz*rows).
+hipError_t launch_xgemm_f64(const JobSet &js, int nz, int K, int N,
+                            const double *bs, hipStream_t s);
+// C[M x Ncol] = As * B, As the swizzled M x K matrix, B row-major (K x Ncol),
+// Ncol = rows * nx per job.
+hipError_t launch_zgemm_f64(const JobSet &js, int M, int K, int nx,
+                            const double *as, hipStream_t s);
+// Tridiagonal pencils along y, in place on js.j[q].out ([nz][rows][nx]).
+// poisson: pressure operator (pin + weighted-mean handling of pencil 0,0).
+hipError_t launch_tridiag_f64(const JobSet &js, const Plan &p, bool poisson,
+                              hipStream_t s);
+hipError_t launch_divergence(const Plan &p, const double *u, const double *v,
+                             const double *w, double *b, double scale, hipStream_t s);
+hipError_t launch_correct(const Plan &p, const double *phi, double *u, double *v,
+                          double *w, double g, double *pr, const double *lap,
+                          double cp, hipStream_t s);
+hipError_t launch_residual(const Plan &p, int op, double c, const double *x,
+                           const double *b, double *r, double *norms2, hipStream_t s);
+
+inline const double *blob_ptr(const Plan &p, size_t off) {
+    return reinterpret_cast<const double *>(static_cast<const unsigned char *>(p.dev_const) + off);
+}
+inline double *blob_mut(const Plan &p, size_t off) {
+    return reinterpret_cast<double *>(static_cast<unsigned char *>(p.dev_const) + off);
+}
+
+}  // namespace ibs

@@ -1,0 +1,271 @@
+// Tridiagonal solves along y, one system per (x-mode a, z-mode c) pencil.
+//
+// After the x and z transforms every pencil is decoupled (Section 2.3.3,
+// items S1.1 and S2.1; Appendix B gives the matrices on a uniform grid).
+// Row j of pencil (a, c), with T the y part of the Laplacian (lo, di, up)
+// and s = lambda_x[a] + lambda_z[c] (minus the transverse modified
+// wavenumber squared, Appendix A):
+//   Poisson   : lo_j x_{j-1} + (di_j + s) x_j + up_j x_{j+1} = b_j
+//   Helmholtz : -c lo_j x_{j-1} + (1 - c s - c di_j) x_j - c up_j x_{j+1} = r_j
+// The Neumann (0,0) pressure pencil is singular: its right-hand side is
+// first made compatible (its volume-weighted mean removed), its first point
+// is pinned to zero (as in Section 2.3.3, item S2.1), and after the solve
+// the weighted mean is removed, which fixes the null mode at zero mean.
+//
+// Layout and parallel scheme (an MI355X design, not the paper's
+// thread-per-pencil Thomas sweep): a workgroup owns 16 consecutive x-modes
+// of one z-plane and all rows.  The tile is read row by row (128-byte
+// coalesced segments) into LDS.  Each pencil is split into P (16 or 32)
+// chunks of M consecutive rows, one lane per chunk.  Every lane eliminates its chunk
+// with two local sweeps (down and up), leaving one equation per lane that
+// couples the last unknowns of neighbouring chunks; that reduced tridiagonal
+// system of P equations is solved by parallel cyclic reduction with
+// wavefront shuffles; the lanes then back-substitute their interiors.  Rows
+// beyond the system size are identity rows.  All arithmetic is FP64.
+#include "ibs_internal.h"
+
+namespace ibs {
+
+struct TriParams {
+    const double *lam_x, *lam_z;
+    const double *lo[NUM_KINDS], *di[NUM_KINDS], *up[NUM_KINDS];
+    const double *wy;   // Delta_j: weights of the pressure unknowns
+    int nx, nz;
+    int poisson;
+    int strict;
+    double inv_sqrt_nxnz;
+};
+
+template <int P, int M>
+__global__ __launch_bounds__(16 * P) void tridiag_f64_kernel(JobSet js, TriParams tp)
+{
+    constexpr int TA = 16;                 // pencils per workgroup
+    constexpr int NT = TA * P;             // threads
+    constexpr int NR = P * M;              // padded rows
+    constexpr int NPAD = NR + ((16 - NR % 32) + 32) % 32;  // pencil stride = 16 mod 32
+    __shared__ double sx[TA * NPAD];
+    __shared__ double slo[NR], sdi[NR], sup[NR], sw[NR];
+
+    const FieldJob &jb = js.j[blockIdx.z];
+    const int n = jb.rows, kind = jb.kind;
+    const int c = blockIdx.y;
+    const int a0 = blockIdx.x * TA;
+    const int nx = tp.nx;
+    double *__restrict__ base = jb.out + (size_t)c * n * nx;
+    const int tid = threadIdx.x;
+
+    for (int j = tid; j < NR; j += NT) {
+        const bool real = j < n;
+        slo[j] = real ? tp.lo[kind][j] : 0.0;
+        sdi[j] = real ? tp.di[kind][j] : 0.0;
+        sup[j] = real ? tp.up[kind][j] : 0.0;
+        sw[j] = (real && tp.poisson) ? tp.wy[j] : 0.0;
+    }
+    for (int e = tid; e < NR * TA; e += NT) {
+        const int j = e / TA, p = e % TA;
+        double v = 0.0;
+        if (j < n && !(kind == KIND_F && (j == 0 || j == n - 1)))
+            v = base[(size_t)j * nx + a0 + p];
+        sx[p * NPAD + j] = v;
+    }
+    __syncthreads();
+
+    const int p = tid / P, k = tid % P;
+    const int a = a0 + p;
+    const double sh = tp.lam_x[a] + tp.lam_z[c];
+    const double cc = jb.c;
+    const bool pois = tp.poisson != 0;
+    const bool pinned = pois && a == 0 && c == 0;
+    const int s = k * M;
+    double *col = sx + p * NPAD;
+
+    double r[M];
+#pragma unroll
+    for (int t = 0; t < M; ++t) r[t] = col[s + t];
+
+    double removed = 0.0, rms = 0.0;
+    if (pinned) {
+        // compatibility: remove the volume-weighted mean of this pencil's rhs
+        double swr = 0.0, sww = 0.0, swrr = 0.0;
+#pragma unroll
+        for (int t = 0; t < M; ++t) {
+            swr += sw[s + t] * r[t];
+            sww += sw[s + t];
+            swrr += sw[s + t] * r[t] * r[t];
+        }
+#pragma unroll
+        for (int d = 1; d < P; d <<= 1) {
+            swr += __shfl_xor(swr, d, P);
+            sww += __shfl_xor(sww, d, P);
+            swrr += __shfl_xor(swrr, d, P);
+        }
+        const double mean = swr / sww;
+        rms = sqrt(fmax(swrr / sww, 0.0));
+        removed = mean;
+#pragma unroll
+        for (int t = 0; t < M; ++t)
+            if (s + t < n) r[t] -= mean;
+        if (k == 0) r[0] = 0.0;  // pin the first point
+    }
+
+    auto coef = [&](int j, double &A, double &B, double &C) {
+        const double lo = slo[j], di = sdi[j], up = sup[j];
+        if (j >= n) { A = 0.0; B = 1.0; C = 0.0; return; }
+        if (pois) {
+            A = lo; B = di + sh; C = up;
+            if (pinned && j == 0) { A = 0.0; B = 1.0; C = 0.0; }
+        } else {
+            A = -cc * lo; B = 1.0 - cc * sh - cc * di; C = -cc * up;
+        }
+    };
+
+    // up-sweep: rows s+M-2 .. s in the form lam x_{j-1} + x_j + mu x_e = sig
+    double lam_u, mu_u, sig_u;
+    {
+        double A, B, C;
+        coef(s + M - 2, A, B, C);
+        double inv = 1.0 / B;
+        lam_u = A * inv; mu_u = C * inv; sig_u = r[M - 2] * inv;
+#pragma unroll
+        for (int t = M - 3; t >= 0; --t) {
+            coef(s + t, A, B, C);
+            inv = 1.0 / (B - C * lam_u);
+            const double nmu = -C * mu_u * inv;
+            sig_u = (r[t] - C * sig_u) * inv;
+            lam_u = A * inv;
+            mu_u = nmu;
+        }
+    }
+    // down-sweep: rows s+1 .. s+M-1 in the form al x_s + x_j + ga x_{j+1} = rho
+    double al[M], ga[M];
+    {
+        double A, B, C;
+        coef(s + 1, A, B, C);
+        double inv = 1.0 / B;
+        al[1] = A * inv; ga[1] = C * inv; r[1] = r[1] * inv;
+#pragma unroll
+        for (int t = 2; t < M; ++t) {
+            coef(s + t, A, B, C);
+            inv = 1.0 / (B - A * ga[t - 1]);
+            al[t] = -A * al[t - 1] * inv;
+            ga[t] = C * inv;
+            r[t] = (r[t] - A * r[t - 1]) * inv;
+        }
+    }
+    al[0] = 0.0; ga[0] = 0.0;
+
+    // reduced system in z_k = x_{last row of chunk k}
+    double lam1 = __shfl_down(lam_u, 1, P), mu1 = __shfl_down(mu_u, 1, P),
+           sig1 = __shfl_down(sig_u, 1, P);
+    if (k == P - 1) { lam1 = 0.0; mu1 = 0.0; sig1 = 0.0; }
+    const double ae = al[M - 1], ge = ga[M - 1], re = r[M - 1];
+    double EA = -ae * lam_u;
+    double EB = 1.0 - ae * mu_u - ge * lam1;
+    double EC = -ge * mu1;
+    double ED = re - ae * sig_u - ge * sig1;
+#pragma unroll
+    for (int d = 1; d < P; d <<= 1) {
+        double am = __shfl_up(EA, d, P), bm = __shfl_up(EB, d, P);
+        double cm = __shfl_up(EC, d, P), dm = __shfl_up(ED, d, P);
+        double ap = __shfl_down(EA, d, P), bp = __shfl_down(EB, d, P);
+        double cp = __shfl_down(EC, d, P), dp = __shfl_down(ED, d, P);
+        if (k < d) { am = 0.0; bm = 1.0; cm = 0.0; dm = 0.0; }
+        if (k + d >= P) { ap = 0.0; bp = 1.0; cp = 0.0; dp = 0.0; }
+        const double k1 = EA / bm, k2 = EC / bp;
+        const double nA = -k1 * am, nC = -k2 * cp;
+        const double nB = EB - k1 * cm - k2 * ap;
+        const double nD = ED - k1 * dm - k2 * dp;
+        EA = nA; EB = nB; EC = nC; ED = nD;
+    }
+    const double z = ED / EB;
+    double zm = __shfl_up(z, 1, P);
+    if (k == 0) zm = 0.0;
+    const double xs = sig_u - lam_u * zm - mu_u * z;
+
+    double x[M];
+    x[M - 1] = z;
+    x[0] = xs;
+#pragma unroll
+    for (int t = M - 2; t >= 1; --t) x[t] = r[t] - al[t] * xs - ga[t] * x[t + 1];
+
+    if (pinned) {
+        // null mode: zero volume-weighted mean
+        double swx = 0.0, sww = 0.0;
+#pragma unroll
+        for (int t = 0; t < M; ++t) {
+            swx += sw[s + t] * x[t];
+            sww += sw[s + t];
+        }
+#pragma unroll
+        for (int d = 1; d < P; d <<= 1) {
+            swx += __shfl_xor(swx, d, P);
+            sww += __shfl_xor(sww, d, P);
+        }
+        const double mx = swx / sww;
+#pragma unroll
+        for (int t = 0; t < M; ++t)
+            if (s + t < n) x[t] -= mx;
+    }
+#pragma unroll
+    for (int t = 0; t < M; ++t) col[s + t] = x[t];
+
+    if (blockIdx.x == 0 && c == 0 && tid == 0 && jb.info) {
+        ibs_solve_info *inf = static_cast<ibs_solve_info *>(jb.info);
+        const double rm = removed * tp.inv_sqrt_nxnz;
+        const bool bad = pois && tp.strict && fabs(removed) > 1e-10 * rms;
+        inf->iters = 1;
+        inf->status = bad ? IBS_ERR_INCOMPATIBLE_RHS : IBS_OK;
+        inf->rel_residual = 0.0;
+        inf->rel_correction = 0.0;
+        inf->removed_mean = pois ? rm : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < n * TA; e += NT) {
+        const int j = e / TA, q = e % TA;
+        base[(size_t)j * nx + a0 + q] = sx[q * NPAD + j];
+    }
+}
+
+template <int P, int M>
+static hipError_t launch_pm(const JobSet &js, const TriParams &tp, hipStream_t s)
+{
+    dim3 grid(tp.nx / 16, tp.nz, js.n);
+    hipLaunchKernelGGL((tridiag_f64_kernel<P, M>), grid, dim3(16 * P), 0, s, js, tp);
+    return hipGetLastError();
+}
+
+hipError_t launch_tridiag_f64(const JobSet &js, const Plan &p, bool poisson, hipStream_t s)
+{
+    TriParams tp;
+    tp.lam_x = blob_ptr(p, p.lay.lam_x);
+    tp.lam_z = blob_ptr(p, p.lay.lam_z);
+    for (int kd = 0; kd < NUM_KINDS; ++kd) {
+        tp.lo[kd] = blob_ptr(p, p.lay.lo[kd]);
+        tp.di[kd] = blob_ptr(p, p.lay.di[kd]);
+        tp.up[kd] = blob_ptr(p, p.lay.up[kd]);
+    }
+    tp.wy = blob_ptr(p, p.lay.wy);
+    tp.nx = p.nx;
+    tp.nz = p.nz;
+    tp.poisson = poisson ? 1 : 0;
+    tp.strict = p.desc.strict_compat ? 1 : 0;
+    tp.inv_sqrt_nxnz = 1.0 / std::sqrt((double)p.nx * (double)p.nz);
+    int n = 0;
+    for (int q = 0; q < js.n; ++q) n = js.j[q].rows > n ? js.j[q].rows : n;
+    // 16 lanes per pencil up to 144 rows, then 32 (keeps the per-lane chunk
+    // short, so the chunk arrays stay in registers at useful occupancy)
+    if (n <= 48) return launch_pm<16, 3>(js, tp, s);
+    if (n <= 80) return launch_pm<16, 5>(js, tp, s);
+    if (n <= 112) return launch_pm<16, 7>(js, tp, s);
+    if (n <= 144) return launch_pm<16, 9>(js, tp, s);
+    if (n <= 224) return launch_pm<32, 7>(js, tp, s);
+    if (n <= 288) return launch_pm<32, 9>(js, tp, s);
+    if (n <= 352) return launch_pm<32, 11>(js, tp, s);
+    if (n <= 416) return launch_pm<32, 13>(js, tp, s);
+    if (n <= 544) return launch_pm<32, 17>(js, tp, s);
+    if (n <= 672) return launch_pm<32, 21>(js, tp, s);
+    if (n <= 800) return launch_pm<32, 25>(js, tp, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace ibs

@@ -1,0 +1,227 @@
+// Host plan builder: grid, y operators, x/z eigenbases, device blob image.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "ibs_internal.h"
+
+namespace ibs {
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Real orthonormal Fourier basis of the periodic 3-point second difference
+// (its eigenvectors; eigenvalues are minus the modified wavenumber squared,
+// -(2/h^2)(1 - cos(kappa h)) = -(4/h^2) sin^2(pi k / N), Appendix A).
+// Column order: a = 0 constant; a = 1..N/2-1 cosines of wavenumber a;
+// a = N/2 the alternating mode; a = N/2+1..N-1 sines of wavenumber a - N/2.
+// Angles are reduced exactly, 2 pi ((k i) mod N) / N, and evaluated in long
+// double.  Q is row-major: Q[i*N + a] = mode a at grid index i.
+static void fourier_basis(int N, double h, std::vector<double> &Q, std::vector<double> &lam)
+{
+    Q.assign(size_t(N) * N, 0.0);
+    lam.assign(N, 0.0);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const long double s0 = 1.0L / std::sqrt((long double)N);
+    const long double s1 = std::sqrt(2.0L / (long double)N);
+    const int half = N / 2;
+    for (int a = 0; a < N; ++a) {
+        int k = (a <= half) ? a : a - half;
+        long double sk = std::sin(pi * (long double)k / (long double)N);
+        lam[a] = (double)(-(4.0L / ((long double)h * h)) * sk * sk);
+        for (int i = 0; i < N; ++i) {
+            long double v;
+            long long ki = ((long long)k * i) % N;
+            long double th = 2.0L * pi * (long double)ki / (long double)N;
+            if (a == 0) v = s0;
+            else if (a < half) v = s1 * std::cos(th);
+            else if (a == half) v = (i % 2 == 0) ? s0 : -s0;
+            else v = s1 * std::sin(th);
+            Q[size_t(i) * N + a] = (double)v;
+        }
+    }
+}
+
+// Swizzle a K x N row-major matrix B into the per-lane fragment order of
+// the 16x16x4 FP64 matrix-core instruction: for every 16-deep K chunk kc and
+// 16-wide column block bj, lane l (0..63) holds four consecutive values
+// B[16 kc + 4 (l/16) + t][16 bj + l%16], t = 0..3.
+static void swizzle_b(const double *B, int K, int N, double *out)
+{
+    size_t o = 0;
+    for (int kc = 0; kc < K / 16; ++kc)
+        for (int bj = 0; bj < N / 16; ++bj)
+            for (int l = 0; l < 64; ++l)
+                for (int t = 0; t < 4; ++t)
+                    out[o++] = B[size_t(16 * kc + 4 * (l / 16) + t) * N + 16 * bj + (l % 16)];
+}
+// Same for an M x K row-major A operand: lane l holds
+// A[16 bi + l%16][16 kc + 4 (l/16) + t].
+static void swizzle_a(const double *A, int M, int K, double *out)
+{
+    size_t o = 0;
+    for (int kc = 0; kc < K / 16; ++kc)
+        for (int bi = 0; bi < M / 16; ++bi)
+            for (int l = 0; l < 64; ++l)
+                for (int t = 0; t < 4; ++t)
+                    out[o++] = A[size_t(16 * bi + (l % 16)) * K + 16 * kc + 4 * (l / 16) + t];
+}
+
+ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
+{
+    if (d.nx < 16 || d.nz < 16 || d.nx > 1024 || d.nz > 1024 || d.nx % 16 || d.nz % 16) {
+        set_error("nx and nz must be multiples of 16 in [16, 1024]");
+        return IBS_ERR_UNSUPPORTED;
+    }
+    if (d.ny < 2 || d.ny > 1024) {
+        set_error("ny must be in [2, 1024]");
+        return IBS_ERR_UNSUPPORTED;
+    }
+    if (d.bc_x != IBS_PERIODIC || d.bc_z != IBS_PERIODIC || d.bc_y_vel != IBS_DIRICHLET ||
+        d.bc_y_p != IBS_NEUMANN) {
+        set_error("only periodic x/z with Dirichlet velocity / Neumann pressure walls in y are supported");
+        return IBS_ERR_UNSUPPORTED;
+    }
+    if (d.precision < IBS_FP64 || d.precision > IBS_REFINED_AUTO) {
+        set_error("unknown precision");
+        return IBS_ERR_INVALID_ARG;
+    }
+    if (!(std::isfinite(d.beta)) || d.beta < 0.0 || d.beta > 10.0) {
+        set_error("beta must be in [0, 10]");
+        return IBS_ERR_INVALID_ARG;
+    }
+    Plan *p = new (std::nothrow) Plan();
+    if (!p) { set_error("out of host memory"); return IBS_ERR_INVALID_ARG; }
+    p->desc = d;
+    p->desc.y_faces = nullptr;
+    const double lx = d.lx > 0 ? d.lx : 1.0, ly = d.ly > 0 ? d.ly : 1.0, lz = d.lz > 0 ? d.lz : 1.0;
+    p->desc.lx = lx; p->desc.ly = ly; p->desc.lz = lz;
+    if (p->desc.tol <= 0) p->desc.tol = 1e-10;
+    const int nx = d.nx, ny = d.ny, nz = d.nz;
+    p->nx = nx; p->ny = ny; p->nz = nz;
+    p->hx = lx / nx;
+    p->hz = lz / nz;
+
+    // y grid: tanh-stretched faces (uniform for beta = 0), centres midway
+    p->yf.resize(ny + 1);
+    for (int j = 0; j <= ny; ++j) {
+        if (d.y_faces) {
+            p->yf[j] = d.y_faces[j];
+        } else if (d.beta == 0.0) {
+            p->yf[j] = ly * (double)j / (double)ny;
+        } else {
+            double t = std::tanh(d.beta * (2.0 * (double)j / (double)ny - 1.0));
+            p->yf[j] = 0.5 * ly * (1.0 + t / std::tanh(d.beta));
+        }
+    }
+    p->yc.resize(ny);
+    p->dyc.resize(ny);
+    p->dyf.assign(ny + 1, 0.0);
+    for (int j = 0; j < ny; ++j) {
+        p->yc[j] = 0.5 * (p->yf[j] + p->yf[j + 1]);
+        p->dyc[j] = p->yf[j + 1] - p->yf[j];
+        if (!(p->dyc[j] > 0.0) || !std::isfinite(p->dyc[j])) {
+            set_error("y faces must be finite and strictly increasing");
+            delete p;
+            return IBS_ERR_INVALID_ARG;
+        }
+    }
+    for (int j = 1; j < ny; ++j) p->dyf[j] = p->yc[j] - p->yc[j - 1];
+
+    // y operators, one tridiagonal row per unknown (unweighted Laplacian in y)
+    p->rows[KIND_P] = ny;
+    p->rows[KIND_C] = ny;
+    p->rows[KIND_F] = ny + 1;
+    for (int kd = 0; kd < NUM_KINDS; ++kd) {
+        p->lo[kd].assign(ny + 1, 0.0);
+        p->di[kd].assign(ny + 1, 0.0);
+        p->up[kd].assign(ny + 1, 0.0);
+    }
+    for (int j = 0; j < ny; ++j) {
+        // cell-centre rows: (F_{j+1/2} - F_{j-1/2}) / Delta_j
+        double lo = (j > 0) ? 1.0 / (p->dyf[j] * p->dyc[j]) : 0.0;
+        double up = (j + 1 < ny) ? 1.0 / (p->dyf[j + 1] * p->dyc[j]) : 0.0;
+        p->lo[KIND_P][j] = lo;
+        p->up[KIND_P][j] = up;
+        p->di[KIND_P][j] = -(lo + up);  // Neumann: no wall flux
+        double wall = 0.0;              // Dirichlet: mirror ghost, flux 2 f / Delta
+        if (j == 0) wall += 2.0 / (p->dyc[0] * p->dyc[0]);
+        if (j == ny - 1) wall += 2.0 / (p->dyc[ny - 1] * p->dyc[ny - 1]);
+        p->lo[KIND_C][j] = lo;
+        p->up[KIND_C][j] = up;
+        p->di[KIND_C][j] = -(lo + up) - wall;
+    }
+    for (int j = 1; j < ny; ++j) {
+        // face rows: ((v_{j+1}-v_j)/Delta_j - (v_j-v_{j-1})/Delta_{j-1}) / delta_j;
+        // the wall rows 0 and ny stay zero (their unknowns are pinned to 0)
+        double lo = 1.0 / (p->dyf[j] * p->dyc[j - 1]);
+        double up = 1.0 / (p->dyf[j] * p->dyc[j]);
+        p->lo[KIND_F][j] = lo;
+        p->up[KIND_F][j] = up;
+        p->di[KIND_F][j] = -(lo + up);
+    }
+
+    fourier_basis(nx, p->hx, p->qx, p->lam_x);
+    fourier_basis(nz, p->hz, p->qz, p->lam_z);
+
+    // blob layout
+    BlobLayout &L = p->lay;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+    L.bx_fwd = take(sizeof(double) * nx * nx);
+    L.bx_inv = take(sizeof(double) * nx * nx);
+    L.az_fwd = take(sizeof(double) * nz * nz);
+    L.az_inv = take(sizeof(double) * nz * nz);
+    L.lam_x = take(sizeof(double) * nx);
+    L.lam_z = take(sizeof(double) * nz);
+    for (int kd = 0; kd < NUM_KINDS; ++kd) {
+        L.lo[kd] = take(sizeof(double) * (ny + 1));
+        L.di[kd] = take(sizeof(double) * (ny + 1));
+        L.up[kd] = take(sizeof(double) * (ny + 1));
+    }
+    L.wy = take(sizeof(double) * ny);
+    L.dyc = take(sizeof(double) * ny);
+    L.dyf = take(sizeof(double) * (ny + 1));
+    L.red_count = 8192;
+    L.red = take(sizeof(double) * L.red_count);
+    L.total = o;
+    p->blob.assign(L.total, 0);
+    auto put = [&](size_t off, const double *src, size_t n) {
+        std::memcpy(p->blob.data() + off, src, n * sizeof(double));
+    };
+    {
+        std::vector<double> tmp(size_t(nx) * nx), tr(size_t(nx) * nx);
+        // x forward: C = X Q (contract over grid index i)
+        swizzle_b(p->qx.data(), nx, nx, tmp.data());
+        put(L.bx_fwd, tmp.data(), tmp.size());
+        // x inverse: C = Xhat Q^T
+        for (int i = 0; i < nx; ++i)
+            for (int a = 0; a < nx; ++a) tr[size_t(a) * nx + i] = p->qx[size_t(i) * nx + a];
+        swizzle_b(tr.data(), nx, nx, tmp.data());
+        put(L.bx_inv, tmp.data(), tmp.size());
+    }
+    {
+        std::vector<double> tmp(size_t(nz) * nz), tr(size_t(nz) * nz);
+        // z forward: Xhat[c] = sum_k Q[k][c] X[k]  -> A = Q^T
+        for (int k = 0; k < nz; ++k)
+            for (int c = 0; c < nz; ++c) tr[size_t(c) * nz + k] = p->qz[size_t(k) * nz + c];
+        swizzle_a(tr.data(), nz, nz, tmp.data());
+        put(L.az_fwd, tmp.data(), tmp.size());
+        // z inverse: X[k] = sum_c Q[k][c] Xhat[c] -> A = Q
+        swizzle_a(p->qz.data(), nz, nz, tmp.data());
+        put(L.az_inv, tmp.data(), tmp.size());
+    }
+    put(L.lam_x, p->lam_x.data(), nx);
+    put(L.lam_z, p->lam_z.data(), nz);
+    for (int kd = 0; kd < NUM_KINDS; ++kd) {
+        put(L.lo[kd], p->lo[kd].data(), ny + 1);
+        put(L.di[kd], p->di[kd].data(), ny + 1);
+        put(L.up[kd], p->up[kd].data(), ny + 1);
+    }
+    put(L.wy, p->dyc.data(), ny);
+    put(L.dyc, p->dyc.data(), ny);
+    put(L.dyf, p->dyf.data(), ny + 1);
+    out = p;
+    return IBS_OK;
+}
+
+}  // namespace ibs

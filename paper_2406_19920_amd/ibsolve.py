@@ -1,0 +1,282 @@
+"""ctypes binding of libibsolve.so (declared in include/ibsolve.h).
+
+Argument marshalling only: every step of a solve runs in the library's HIP
+kernels.  The functions keep the C names; ``Solver`` is a small convenience
+that owns torch device buffers (constants, workspace) for one plan.  Torch is
+used for device memory and streams only.
+
+Importing this module loads the library; if it has not been built, the
+import fails loudly (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libibsolve.so")
+
+IBS_OK = 0
+IBS_ERR_INVALID_ARG = 1
+IBS_ERR_UNSUPPORTED = 2
+IBS_ERR_WORKSPACE_TOO_SMALL = 3
+IBS_ERR_HIP = 4
+IBS_ERR_NOT_CONVERGED = 5
+IBS_ERR_INCOMPATIBLE_RHS = 6
+IBS_ERR_NOT_UPLOADED = 7
+
+IBS_FP64, IBS_REFINED_FP16X2, IBS_REFINED_BF16X3, IBS_REFINED_AUTO = 0, 1, 2, 3
+IBS_PERIODIC, IBS_DIRICHLET, IBS_NEUMANN = 0, 1, 2
+IBS_OP_POISSON, IBS_OP_HELMHOLTZ_U, IBS_OP_HELMHOLTZ_V, IBS_OP_HELMHOLTZ_W = 0, 1, 2, 3
+
+# every exported entry point of include/ibsolve.h
+EXPORTS = ("solver_plan", "solver_plan_bytes", "solver_plan_upload", "solver_plan_destroy",
+           "solve_poisson", "solve_helmholtz_batch", "residual", "ibs_divergence",
+           "ibs_correct", "ibs_plan_export", "ibs_profile", "ibs_profile_read",
+           "ibs_last_error", "ibs_version")
+
+PROFILE_KERNELS = ("xgemm_f64", "zgemm_f64", "tridiag_f64", "divergence", "correct", "residual",
+                   "xgemm_split", "zgemm_split", "tridiag_f32", "update")
+
+
+class ibs_grid_desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
+                ("beta", ctypes.c_double), ("y_faces", ctypes.POINTER(ctypes.c_double)),
+                ("bc_x", ctypes.c_int32), ("bc_z", ctypes.c_int32),
+                ("bc_y_vel", ctypes.c_int32), ("bc_y_p", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("strict_compat", ctypes.c_int32)]
+
+
+class ibs_solve_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("rel_correction", ctypes.c_double),
+                ("removed_mean", ctypes.c_double)]
+
+
+INFO_BYTES = ctypes.sizeof(ibs_solve_info)
+
+
+class IbsError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: status {status}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2406_19920_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, i32, dbl = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_double
+    L.solver_plan.argtypes = [ctypes.POINTER(ibs_grid_desc), ctypes.POINTER(vp)]
+    L.solver_plan_bytes.argtypes = [vp, i32, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    L.solver_plan_upload.argtypes = [vp, vp, sz, vp]
+    L.solver_plan_destroy.argtypes = [vp]
+    L.solve_poisson.argtypes = [vp, vp, vp, vp, sz, vp, vp]
+    L.solve_helmholtz_batch.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl),
+                                        ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz, vp, vp]
+    L.residual.argtypes = [vp, i32, dbl, vp, vp, vp, vp, vp]
+    L.ibs_divergence.argtypes = [vp, vp, vp, vp, vp, dbl, vp]
+    L.ibs_correct.argtypes = [vp, vp, vp, vp, vp, dbl, vp, vp, dbl, vp]
+    L.ibs_plan_export.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(sz)]
+    L.ibs_profile.argtypes = [vp, i32]
+    L.ibs_profile_read.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64),
+                                   ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+    for name in EXPORTS:
+        if name in ("ibs_last_error", "ibs_version"):
+            getattr(L, name).restype = ctypes.c_char_p
+        else:
+            getattr(L, name).restype = ctypes.c_int
+    return L
+
+
+lib = _load()
+
+
+def ibs_last_error() -> str:
+    return lib.ibs_last_error().decode()
+
+
+def ibs_version() -> str:
+    return lib.ibs_version().decode()
+
+
+def _check(st: int, where: str):
+    if st != IBS_OK:
+        raise IbsError(st, where, ibs_last_error())
+
+
+def make_desc(nx, ny, nz, lx=1.0, ly=1.0, lz=1.0, beta=0.0, y_faces=None,
+              precision=IBS_FP64, tol=1e-10, max_iter=0, strict_compat=0,
+              bc_x=IBS_PERIODIC, bc_z=IBS_PERIODIC, bc_y_vel=IBS_DIRICHLET,
+              bc_y_p=IBS_NEUMANN):
+    d = ibs_grid_desc()
+    d.nx, d.ny, d.nz = nx, ny, nz
+    d.lx, d.ly, d.lz = lx, ly, lz
+    d.beta = beta
+    d._yf_keep = None
+    if y_faces is not None:
+        arr = (ctypes.c_double * len(y_faces))(*[float(t) for t in y_faces])
+        d._yf_keep = arr
+        d.y_faces = ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))
+    d.bc_x, d.bc_z, d.bc_y_vel, d.bc_y_p = bc_x, bc_z, bc_y_vel, bc_y_p
+    d.precision, d.tol, d.max_iter, d.strict_compat = precision, tol, max_iter, strict_compat
+    return d
+
+
+def solver_plan(desc: ibs_grid_desc) -> int:
+    h = ctypes.c_void_p()
+    _check(lib.solver_plan(ctypes.byref(desc), ctypes.byref(h)), "solver_plan")
+    return h.value
+
+
+def solver_plan_bytes(plan: int, op: int, ncomp: int = 1):
+    cb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib.solver_plan_bytes(plan, op, ncomp, ctypes.byref(cb), ctypes.byref(wb)),
+           "solver_plan_bytes")
+    return cb.value, wb.value
+
+
+def solver_plan_upload(plan: int, dev_const: int, nbytes: int, stream: int):
+    _check(lib.solver_plan_upload(plan, dev_const, nbytes, stream), "solver_plan_upload")
+
+
+def solver_plan_destroy(plan: int):
+    _check(lib.solver_plan_destroy(plan), "solver_plan_destroy")
+
+
+def solve_poisson(plan, b, phi, work, work_bytes, info, stream):
+    _check(lib.solve_poisson(plan, b, phi, work, work_bytes, info, stream), "solve_poisson")
+
+
+def solve_helmholtz_batch(plan, comps, cs, rs, xs, work, work_bytes, info, stream):
+    n = len(comps)
+    ca = (ctypes.c_int32 * n)(*comps)
+    da = (ctypes.c_double * n)(*cs)
+    ra = (ctypes.c_void_p * n)(*rs)
+    xa = (ctypes.c_void_p * n)(*xs)
+    _check(lib.solve_helmholtz_batch(plan, n, ca, da, ra, xa, work, work_bytes, info, stream),
+           "solve_helmholtz_batch")
+
+
+def residual(plan, op, c, x, b, r, norms2, stream):
+    _check(lib.residual(plan, op, c, x, b, r, norms2, stream), "residual")
+
+
+def ibs_divergence(plan, u, v, w, b, scale, stream):
+    _check(lib.ibs_divergence(plan, u, v, w, b, scale, stream), "ibs_divergence")
+
+
+def ibs_correct(plan, phi, u, v, w, g, p, lap_phi, cp, stream):
+    _check(lib.ibs_correct(plan, phi, u, v, w, g, p, lap_phi, cp, stream), "ibs_correct")
+
+
+def ibs_plan_export(plan, table: int):
+    import numpy as np
+    n = ctypes.c_size_t()
+    _check(lib.ibs_plan_export(plan, table, None, ctypes.byref(n)), "ibs_plan_export")
+    out = np.zeros(n.value)
+    _check(lib.ibs_plan_export(plan, table, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               ctypes.byref(n)), "ibs_plan_export")
+    return out
+
+
+def ibs_profile(plan, enable: bool):
+    _check(lib.ibs_profile(plan, 1 if enable else 0), "ibs_profile")
+
+
+def ibs_profile_read(plan, kernel: int):
+    ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib.ibs_profile_read(plan, kernel, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl),
+                                ctypes.byref(by)), "ibs_profile_read")
+    return dict(ms=ms.value, launches=n.value, flops=fl.value, bytes=by.value)
+
+
+# ---------------------------------------------------------------------------
+# torch-owned buffers around one plan
+# ---------------------------------------------------------------------------
+class Solver:
+    """One plan plus the device buffers it needs (torch allocations)."""
+
+    def __init__(self, nx, ny, nz, device="cuda", **kw):
+        import torch
+        self.torch = torch
+        self.desc = make_desc(nx, ny, nz, **kw)
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.plan = solver_plan(self.desc)
+        self.device = torch.device(device)
+        cb, self.work_p = solver_plan_bytes(self.plan, IBS_OP_POISSON)
+        _, self.work_h = solver_plan_bytes(self.plan, IBS_OP_HELMHOLTZ_U, 3)
+        self.const = torch.empty(cb, dtype=torch.uint8, device=self.device)
+        self.work = torch.empty(max(self.work_p, self.work_h), dtype=torch.uint8, device=self.device)
+        self.info = torch.zeros((4, INFO_BYTES // 8), dtype=torch.float64, device=self.device)
+        solver_plan_upload(self.plan, self.const.data_ptr(), cb, self.stream())
+        self.work_bytes = self.work.numel()
+
+    def stream(self) -> int:
+        return self.torch.cuda.current_stream(self.device).cuda_stream
+
+    def shape(self, op=IBS_OP_POISSON):
+        return (self.nz, self.ny + 1 if op == IBS_OP_HELMHOLTZ_V else self.ny, self.nx)
+
+    def empty(self, op=IBS_OP_POISSON):
+        return self.torch.empty(self.shape(op), dtype=self.torch.float64, device=self.device)
+
+    def _chk(self, t, op):
+        assert t.dtype == self.torch.float64 and t.is_contiguous() and t.device == self.device
+        assert tuple(t.shape) == self.shape(op), (tuple(t.shape), self.shape(op))
+
+    def poisson(self, b, phi=None):
+        self._chk(b, IBS_OP_POISSON)
+        phi = self.empty() if phi is None else phi
+        self._chk(phi, IBS_OP_POISSON)
+        solve_poisson(self.plan, b.data_ptr(), phi.data_ptr(), self.work.data_ptr(),
+                      self.work_bytes, self.info.data_ptr(), self.stream())
+        return phi
+
+    def helmholtz(self, comps, cs, rs, xs=None):
+        ops = [c + 1 for c in comps]
+        if xs is None:
+            xs = [self.empty(op) for op in ops]
+        for r, x, op in zip(rs, xs, ops):
+            self._chk(r, op)
+            self._chk(x, op)
+        solve_helmholtz_batch(self.plan, list(comps), list(cs), [r.data_ptr() for r in rs],
+                              [x.data_ptr() for x in xs], self.work.data_ptr(), self.work_bytes,
+                              self.info.data_ptr(), self.stream())
+        return xs
+
+    def residual(self, op, c, x, b, r=None, norms=False):
+        r = self.empty(op) if r is None else r
+        n2 = self.torch.zeros(2, dtype=self.torch.float64, device=self.device) if norms else None
+        residual(self.plan, op, c, x.data_ptr(), b.data_ptr(), r.data_ptr(),
+                 n2.data_ptr() if n2 is not None else None, self.stream())
+        return (r, n2) if norms else r
+
+    def divergence(self, u, v, w, scale=1.0, b=None):
+        b = self.empty() if b is None else b
+        ibs_divergence(self.plan, u.data_ptr(), v.data_ptr(), w.data_ptr(), b.data_ptr(), scale,
+                       self.stream())
+        return b
+
+    def correct(self, phi, u, v, w, g, p=None, lap_phi=None, cp=0.0):
+        ibs_correct(self.plan, phi.data_ptr(), u.data_ptr(), v.data_ptr(), w.data_ptr(), g,
+                    p.data_ptr() if p is not None else None,
+                    lap_phi.data_ptr() if lap_phi is not None else None, cp, self.stream())
+
+    def read_info(self, q=0):
+        raw = self.info[q].cpu().numpy().tobytes()[:INFO_BYTES]
+        return ibs_solve_info.from_buffer_copy(raw)
+
+    def close(self):
+        if self.plan:
+            solver_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
