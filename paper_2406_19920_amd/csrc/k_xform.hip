@@ -9,8 +9,8 @@
 // S1.2, S2.1, S2.2).
 //
 // Instruction: V_MFMA_F64_16X16X4_F64.  Per lane l of the 64-wide wave: A
-// element (row l%16, k l/16), B element (k l/16, col l%16); result rows
-// 4*(l/16)+q, q = 0..3, column l%16.  The K index inside a 16-deep chunk is
+// element (row l%16, k l/16), B element (k l/16, col l%16); result element q
+// (q = 0..3) is row l/16 + 4q, column l%16 (checked on gfx950).  The K index inside a 16-deep chunk is
 // permuted so that lane l feeds k = 4*(l/16) + t at step t = 0..3: then each
 // lane reads four consecutive K values of its row (a 32-byte load).  The
 // transform matrices are pre-swizzled on the host into exactly that order.
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void xgemm_f64_kernel(JobSet js, int nz, int K
             if (j >= ncb) break;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                C[(size_t)(row0 + 16 * i + 4 * lg + q) * N + col0 + 16 * j + li] = acc[i][j][q];
+                C[(size_t)(row0 + 16 * i + lg + 4 * q) * N + col0 + 16 * j + li] = acc[i][j][q];
         }
     }
 }
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(JobSet js, int M, int K,
             if (j >= ncb) break;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                C[(size_t)(row0 + 16 * i + 4 * lg + q) * Ncol + col0 + 16 * j + li] = acc[i][j][q];
+                C[(size_t)(row0 + 16 * i + lg + 4 * q) * Ncol + col0 + 16 * j + li] = acc[i][j][q];
         }
     }
 }

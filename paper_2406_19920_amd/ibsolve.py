@@ -206,7 +206,10 @@ class Solver:
         self.desc = make_desc(nx, ny, nz, **kw)
         self.nx, self.ny, self.nz = nx, ny, nz
         self.plan = solver_plan(self.desc)
-        self.device = torch.device(device)
+        dv = torch.device(device)
+        if dv.type == "cuda" and dv.index is None:
+            dv = torch.device("cuda", torch.cuda.current_device())
+        self.device = dv
         cb, self.work_p = solver_plan_bytes(self.plan, IBS_OP_POISSON)
         _, self.work_h = solver_plan_bytes(self.plan, IBS_OP_HELMHOLTZ_U, 3)
         self.const = torch.empty(cb, dtype=torch.uint8, device=self.device)
