@@ -13,9 +13,10 @@
 // the weighted mean is removed, which fixes the null mode at zero mean.
 //
 // Layout and parallel scheme (an MI355X design, not the paper's
-// thread-per-pencil Thomas sweep): a workgroup owns 16 consecutive x-modes
-// of one z-plane and all rows.  The tile is read row by row (128-byte
-// coalesced segments) into LDS.  Each pencil is split into P (16 or 32)
+// thread-per-pencil Thomas sweep): a tile is 16 consecutive x-modes of one
+// z-plane, all rows.  Persistent workgroups walk the tiles; each tile is
+// read row by row (128-byte coalesced segments) into registers while the
+// previous tile is being solved, then staged through LDS.  Each pencil is split into P (16 or 32)
 // chunks of M consecutive rows, one lane per chunk.  Every lane eliminates its chunk
 // with two local sweeps (down and up), leaving one equation per lane that
 // couples the last unknowns of neighbouring chunks; that reduced tridiagonal
@@ -37,200 +38,229 @@ struct TriParams {
 };
 
 template <int P, int M>
-__global__ __launch_bounds__(16 * P) void tridiag_f64_kernel(JobSet js, TriParams tp)
+__global__ __launch_bounds__(16 * P) void tridiag_f64_kernel(JobSet js, TriParams tp, int ntx,
+                                                             int ntiles)
 {
-    constexpr int TA = 16;                 // pencils per workgroup
+    constexpr int TA = 16;                 // pencils per tile
     constexpr int NT = TA * P;             // threads
     constexpr int NR = P * M;              // padded rows
-    constexpr int NPAD = NR + ((16 - NR % 32) + 32) % 32;  // pencil stride = 16 mod 32
-    __shared__ double sx[TA * NPAD];
+    constexpr int LDR = TA + 1;            // LDS row stride (doubles)
+    __shared__ double sx[NR * LDR];
     __shared__ double slo[NR], sdi[NR], sup[NR], sw[NR];
 
-    const FieldJob &jb = js.j[blockIdx.z];
-    const int n = jb.rows, kind = jb.kind;
-    const int c = blockIdx.y;
-    const int a0 = blockIdx.x * TA;
-    const int nx = tp.nx;
-    double *__restrict__ base = jb.out + (size_t)c * n * nx;
     const int tid = threadIdx.x;
-
-    for (int j = tid; j < NR; j += NT) {
-        const bool real = j < n;
-        slo[j] = real ? tp.lo[kind][j] : 0.0;
-        sdi[j] = real ? tp.di[kind][j] : 0.0;
-        sup[j] = real ? tp.up[kind][j] : 0.0;
-        sw[j] = (real && tp.poisson) ? tp.wy[j] : 0.0;
-    }
-    for (int e = tid; e < NR * TA; e += NT) {
-        const int j = e / TA, p = e % TA;
-        double v = 0.0;
-        if (j < n && !(kind == KIND_F && (j == 0 || j == n - 1)))
-            v = base[(size_t)j * nx + a0 + p];
-        sx[p * NPAD + j] = v;
-    }
-    __syncthreads();
-
+    const int nx = tp.nx;
+    // staging role: thread loads rows lrow + P*r (r < M) of column lcol
+    const int lcol = tid % TA, lrow = tid / TA;
+    // solving role: pencil p (column), chunk k of M rows
     const int p = tid / P, k = tid % P;
-    const int a = a0 + p;
-    const double sh = tp.lam_x[a] + tp.lam_z[c];
-    const double cc = jb.c;
-    const bool pois = tp.poisson != 0;
-    const bool pinned = pois && a == 0 && c == 0;
     const int s = k * M;
-    double *col = sx + p * NPAD;
+    const bool pois = tp.poisson != 0;
 
-    double r[M];
+    double pf[M];
+    auto fetch = [&](int tile) {
+        const int job = tile / (tp.nz * ntx);
+        const int rem = tile - job * tp.nz * ntx;
+        const int c = rem / ntx, a0 = (rem - c * ntx) * TA;
+        const FieldJob &jb = js.j[job];
+        const int n = jb.rows;
+        const double *__restrict__ base = jb.out + (size_t)c * n * nx + a0 + lcol;
+        const bool walls = jb.kind == KIND_F;
 #pragma unroll
-    for (int t = 0; t < M; ++t) r[t] = col[s + t];
-
-    double removed = 0.0, rms = 0.0;
-    if (pinned) {
-        // compatibility: remove the volume-weighted mean of this pencil's rhs
-        double swr = 0.0, sww = 0.0, swrr = 0.0;
-#pragma unroll
-        for (int t = 0; t < M; ++t) {
-            swr += sw[s + t] * r[t];
-            sww += sw[s + t];
-            swrr += sw[s + t] * r[t] * r[t];
-        }
-#pragma unroll
-        for (int d = 1; d < P; d <<= 1) {
-            swr += __shfl_xor(swr, d, P);
-            sww += __shfl_xor(sww, d, P);
-            swrr += __shfl_xor(swrr, d, P);
-        }
-        const double mean = swr / sww;
-        rms = sqrt(fmax(swrr / sww, 0.0));
-        removed = mean;
-#pragma unroll
-        for (int t = 0; t < M; ++t)
-            if (s + t < n) r[t] -= mean;
-        if (k == 0) r[0] = 0.0;  // pin the first point
-    }
-
-    auto coef = [&](int j, double &A, double &B, double &C) {
-        const double lo = slo[j], di = sdi[j], up = sup[j];
-        if (j >= n) { A = 0.0; B = 1.0; C = 0.0; return; }
-        if (pois) {
-            A = lo; B = di + sh; C = up;
-            if (pinned && j == 0) { A = 0.0; B = 1.0; C = 0.0; }
-        } else {
-            A = -cc * lo; B = 1.0 - cc * sh - cc * di; C = -cc * up;
+        for (int r = 0; r < M; ++r) {
+            const int j = lrow + P * r;
+            pf[r] = (j < n && !(walls && (j == 0 || j == n - 1))) ? base[(size_t)j * nx] : 0.0;
         }
     };
 
-    // up-sweep: rows s+M-2 .. s in the form lam x_{j-1} + x_j + mu x_e = sig
-    double lam_u, mu_u, sig_u;
-    {
-        double A, B, C;
-        coef(s + M - 2, A, B, C);
-        double inv = 1.0 / B;
-        lam_u = A * inv; mu_u = C * inv; sig_u = r[M - 2] * inv;
-#pragma unroll
-        for (int t = M - 3; t >= 0; --t) {
-            coef(s + t, A, B, C);
-            inv = 1.0 / (B - C * lam_u);
-            const double nmu = -C * mu_u * inv;
-            sig_u = (r[t] - C * sig_u) * inv;
-            lam_u = A * inv;
-            mu_u = nmu;
+    int tile = blockIdx.x;
+    if (tile < ntiles) fetch(tile);
+    int cur_job = -1;
+    for (; tile < ntiles; tile += gridDim.x) {
+        const int job = tile / (tp.nz * ntx);
+        const int rem = tile - job * tp.nz * ntx;
+        const int c = rem / ntx, a0 = (rem - c * ntx) * TA;
+        const FieldJob &jb = js.j[job];
+        const int n = jb.rows, kind = jb.kind;
+        __syncthreads();  // the previous tile's LDS is no longer read
+        if (job != cur_job) {
+            for (int j = tid; j < NR; j += NT) {
+                const bool real = j < n;
+                slo[j] = real ? tp.lo[kind][j] : 0.0;
+                sdi[j] = real ? tp.di[kind][j] : 0.0;
+                sup[j] = real ? tp.up[kind][j] : 0.0;
+                sw[j] = (real && pois) ? tp.wy[j] : 0.0;
+            }
+            cur_job = job;
         }
-    }
-    // down-sweep: rows s+1 .. s+M-1 in the form al x_s + x_j + ga x_{j+1} = rho
-    double al[M], ga[M];
-    {
-        double A, B, C;
-        coef(s + 1, A, B, C);
-        double inv = 1.0 / B;
-        al[1] = A * inv; ga[1] = C * inv; r[1] = r[1] * inv;
 #pragma unroll
-        for (int t = 2; t < M; ++t) {
-            coef(s + t, A, B, C);
-            inv = 1.0 / (B - A * ga[t - 1]);
-            al[t] = -A * al[t - 1] * inv;
-            ga[t] = C * inv;
-            r[t] = (r[t] - A * r[t - 1]) * inv;
+        for (int r = 0; r < M; ++r) sx[(lrow + P * r) * LDR + lcol] = pf[r];
+        __syncthreads();
+        if (tile + (int)gridDim.x < ntiles) fetch(tile + gridDim.x);  // overlaps the solve
+
+        const int a = a0 + p;
+        const double sh = tp.lam_x[a] + tp.lam_z[c];
+        const double cc = jb.c;
+        const bool pinned = pois && a == 0 && c == 0;
+
+        double r[M];
+#pragma unroll
+        for (int t = 0; t < M; ++t) r[t] = sx[(s + t) * LDR + p];
+
+        double removed = 0.0, rms = 0.0;
+        if (pinned) {
+            // compatibility: remove the volume-weighted mean of this pencil's rhs
+            double swr = 0.0, sww = 0.0, swrr = 0.0;
+#pragma unroll
+            for (int t = 0; t < M; ++t) {
+                swr += sw[s + t] * r[t];
+                sww += sw[s + t];
+                swrr += sw[s + t] * r[t] * r[t];
+            }
+#pragma unroll
+            for (int d = 1; d < P; d <<= 1) {
+                swr += __shfl_xor(swr, d, P);
+                sww += __shfl_xor(sww, d, P);
+                swrr += __shfl_xor(swrr, d, P);
+            }
+            const double mean = swr / sww;
+            rms = sqrt(fmax(swrr / sww, 0.0));
+            removed = mean;
+#pragma unroll
+            for (int t = 0; t < M; ++t)
+                if (s + t < n) r[t] -= mean;
+            if (k == 0) r[0] = 0.0;  // pin the first point
         }
-    }
-    al[0] = 0.0; ga[0] = 0.0;
 
-    // reduced system in z_k = x_{last row of chunk k}
-    double lam1 = __shfl_down(lam_u, 1, P), mu1 = __shfl_down(mu_u, 1, P),
-           sig1 = __shfl_down(sig_u, 1, P);
-    if (k == P - 1) { lam1 = 0.0; mu1 = 0.0; sig1 = 0.0; }
-    const double ae = al[M - 1], ge = ga[M - 1], re = r[M - 1];
-    double EA = -ae * lam_u;
-    double EB = 1.0 - ae * mu_u - ge * lam1;
-    double EC = -ge * mu1;
-    double ED = re - ae * sig_u - ge * sig1;
-#pragma unroll
-    for (int d = 1; d < P; d <<= 1) {
-        double am = __shfl_up(EA, d, P), bm = __shfl_up(EB, d, P);
-        double cm = __shfl_up(EC, d, P), dm = __shfl_up(ED, d, P);
-        double ap = __shfl_down(EA, d, P), bp = __shfl_down(EB, d, P);
-        double cp = __shfl_down(EC, d, P), dp = __shfl_down(ED, d, P);
-        if (k < d) { am = 0.0; bm = 1.0; cm = 0.0; dm = 0.0; }
-        if (k + d >= P) { ap = 0.0; bp = 1.0; cp = 0.0; dp = 0.0; }
-        const double k1 = EA / bm, k2 = EC / bp;
-        const double nA = -k1 * am, nC = -k2 * cp;
-        const double nB = EB - k1 * cm - k2 * ap;
-        const double nD = ED - k1 * dm - k2 * dp;
-        EA = nA; EB = nB; EC = nC; ED = nD;
-    }
-    const double z = ED / EB;
-    double zm = __shfl_up(z, 1, P);
-    if (k == 0) zm = 0.0;
-    const double xs = sig_u - lam_u * zm - mu_u * z;
+        auto coef = [&](int j, double &A, double &B, double &C) {
+            const double lo = slo[j], di = sdi[j], up = sup[j];
+            if (j >= n) { A = 0.0; B = 1.0; C = 0.0; return; }
+            if (pois) {
+                A = lo; B = di + sh; C = up;
+                if (pinned && j == 0) { A = 0.0; B = 1.0; C = 0.0; }
+            } else {
+                A = -cc * lo; B = 1.0 - cc * sh - cc * di; C = -cc * up;
+            }
+        };
 
-    double x[M];
-    x[M - 1] = z;
-    x[0] = xs;
+        // up-sweep: rows s+M-2 .. s in the form lam x_{j-1} + x_j + mu x_e = sig
+        double lam_u, mu_u, sig_u;
+        {
+            double A, B, C;
+            coef(s + M - 2, A, B, C);
+            double inv = 1.0 / B;
+            lam_u = A * inv; mu_u = C * inv; sig_u = r[M - 2] * inv;
 #pragma unroll
-    for (int t = M - 2; t >= 1; --t) x[t] = r[t] - al[t] * xs - ga[t] * x[t + 1];
-
-    if (pinned) {
-        // null mode: zero volume-weighted mean
-        double swx = 0.0, sww = 0.0;
-#pragma unroll
-        for (int t = 0; t < M; ++t) {
-            swx += sw[s + t] * x[t];
-            sww += sw[s + t];
+            for (int t = M - 3; t >= 0; --t) {
+                coef(s + t, A, B, C);
+                inv = 1.0 / (B - C * lam_u);
+                const double nmu = -C * mu_u * inv;
+                sig_u = (r[t] - C * sig_u) * inv;
+                lam_u = A * inv;
+                mu_u = nmu;
+            }
         }
+        // down-sweep: rows s+1 .. s+M-1 in the form al x_s + x_j + ga x_{j+1} = rho
+        double al[M], ga[M];
+        {
+            double A, B, C;
+            coef(s + 1, A, B, C);
+            double inv = 1.0 / B;
+            al[1] = A * inv; ga[1] = C * inv; r[1] = r[1] * inv;
+#pragma unroll
+            for (int t = 2; t < M; ++t) {
+                coef(s + t, A, B, C);
+                inv = 1.0 / (B - A * ga[t - 1]);
+                al[t] = -A * al[t - 1] * inv;
+                ga[t] = C * inv;
+                r[t] = (r[t] - A * r[t - 1]) * inv;
+            }
+        }
+
+        // reduced system in z_k = x_{last row of chunk k}
+        double lam1 = __shfl_down(lam_u, 1, P), mu1 = __shfl_down(mu_u, 1, P),
+               sig1 = __shfl_down(sig_u, 1, P);
+        if (k == P - 1) { lam1 = 0.0; mu1 = 0.0; sig1 = 0.0; }
+        const double ae = al[M - 1], ge = ga[M - 1], re = r[M - 1];
+        double EA = -ae * lam_u;
+        double EB = 1.0 - ae * mu_u - ge * lam1;
+        double EC = -ge * mu1;
+        double ED = re - ae * sig_u - ge * sig1;
 #pragma unroll
         for (int d = 1; d < P; d <<= 1) {
-            swx += __shfl_xor(swx, d, P);
-            sww += __shfl_xor(sww, d, P);
+            double am = __shfl_up(EA, d, P), bm = __shfl_up(EB, d, P);
+            double cm = __shfl_up(EC, d, P), dm = __shfl_up(ED, d, P);
+            double ap = __shfl_down(EA, d, P), bp = __shfl_down(EB, d, P);
+            double cp = __shfl_down(EC, d, P), dp = __shfl_down(ED, d, P);
+            if (k < d) { am = 0.0; bm = 1.0; cm = 0.0; dm = 0.0; }
+            if (k + d >= P) { ap = 0.0; bp = 1.0; cp = 0.0; dp = 0.0; }
+            const double k1 = EA / bm, k2 = EC / bp;
+            const double nA = -k1 * am, nC = -k2 * cp;
+            const double nB = EB - k1 * cm - k2 * ap;
+            const double nD = ED - k1 * dm - k2 * dp;
+            EA = nA; EB = nB; EC = nC; ED = nD;
         }
-        const double mx = swx / sww;
-#pragma unroll
-        for (int t = 0; t < M; ++t)
-            if (s + t < n) x[t] -= mx;
-    }
-#pragma unroll
-    for (int t = 0; t < M; ++t) col[s + t] = x[t];
+        const double z = ED / EB;
+        double zm = __shfl_up(z, 1, P);
+        if (k == 0) zm = 0.0;
+        const double xs = sig_u - lam_u * zm - mu_u * z;
 
-    if (blockIdx.x == 0 && c == 0 && tid == 0 && jb.info) {
-        ibs_solve_info *inf = static_cast<ibs_solve_info *>(jb.info);
-        const double rm = removed * tp.inv_sqrt_nxnz;
-        const bool bad = pois && tp.strict && fabs(removed) > 1e-10 * rms;
-        inf->iters = 1;
-        inf->status = bad ? IBS_ERR_INCOMPATIBLE_RHS : IBS_OK;
-        inf->rel_residual = 0.0;
-        inf->rel_correction = 0.0;
-        inf->removed_mean = pois ? rm : 0.0;
-    }
-    __syncthreads();
-    for (int e = tid; e < n * TA; e += NT) {
-        const int j = e / TA, q = e % TA;
-        base[(size_t)j * nx + a0 + q] = sx[q * NPAD + j];
+        // interior back-substitution, in place: r[t] becomes x[t]
+        r[M - 1] = z;
+#pragma unroll
+        for (int t = M - 2; t >= 1; --t) r[t] = r[t] - al[t] * xs - ga[t] * r[t + 1];
+        r[0] = xs;
+
+        if (pinned) {
+            // null mode: zero volume-weighted mean
+            double swx = 0.0, sww = 0.0;
+#pragma unroll
+            for (int t = 0; t < M; ++t) {
+                swx += sw[s + t] * r[t];
+                sww += sw[s + t];
+            }
+#pragma unroll
+            for (int d = 1; d < P; d <<= 1) {
+                swx += __shfl_xor(swx, d, P);
+                sww += __shfl_xor(sww, d, P);
+            }
+            const double mx = swx / sww;
+#pragma unroll
+            for (int t = 0; t < M; ++t)
+                if (s + t < n) r[t] -= mx;
+        }
+#pragma unroll
+        for (int t = 0; t < M; ++t) sx[(s + t) * LDR + p] = r[t];
+
+        if (a0 == 0 && c == 0 && tid == 0 && jb.info) {
+            ibs_solve_info *inf = static_cast<ibs_solve_info *>(jb.info);
+            const double rm = removed * tp.inv_sqrt_nxnz;
+            const bool bad = pois && tp.strict && fabs(removed) > 1e-10 * rms;
+            inf->iters = 1;
+            inf->status = bad ? IBS_ERR_INCOMPATIBLE_RHS : IBS_OK;
+            inf->rel_residual = 0.0;
+            inf->rel_correction = 0.0;
+            inf->removed_mean = pois ? rm : 0.0;
+        }
+        __syncthreads();
+        double *__restrict__ base = jb.out + (size_t)c * n * nx + a0 + lcol;
+#pragma unroll
+        for (int r2 = 0; r2 < M; ++r2) {
+            const int j = lrow + P * r2;
+            if (j < n) base[(size_t)j * nx] = sx[j * LDR + lcol];
+        }
     }
 }
 
 template <int P, int M>
 static hipError_t launch_pm(const JobSet &js, const TriParams &tp, hipStream_t s)
 {
-    dim3 grid(tp.nx / 16, tp.nz, js.n);
-    hipLaunchKernelGGL((tridiag_f64_kernel<P, M>), grid, dim3(16 * P), 0, s, js, tp);
+    // persistent blocks walk the tiles (job, z-mode, 16 x-modes) in order
+    const int ntx = tp.nx / 16;
+    const int ntiles = ntx * tp.nz * js.n;
+    const int grid = ntiles < 1024 ? ntiles : 1024;
+    hipLaunchKernelGGL((tridiag_f64_kernel<P, M>), dim3(grid), dim3(16 * P), 0, s, js, tp, ntx,
+                       ntiles);
     return hipGetLastError();
 }
 
