@@ -80,7 +80,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--beta", type=float, default=2.0)
-    ap.add_argument("--path", choices=["fp64"], default="fp64")
+    ap.add_argument("--path", choices=["refined", "fp64", "both"], default="both")
     ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -98,83 +98,115 @@ def main():
     log(f"inputs {n}^3 beta={beta}")
     u, v, w = make_inputs(n, beta, seed=2)
     c = 0.125 * h_min(n, beta) ** 2
-    S = ibs.Solver(n, n, n, beta=beta)
     ru, rv, rw = (torch.from_numpy(a).to(dev) for a in (u, v, w))
-    xu, xv, xw = S.empty(1), S.empty(2), S.empty(3)
-    b = S.empty(0)
-    phi = S.empty(0)
     stream = torch.cuda.current_stream(dev)
-
-    def step():
-        S.helmholtz([0, 1, 2], [c, c, c], [ru, rv, rw], [xu, xv, xw])
-        S.divergence(xu, xv, xw, 1.0, b)
-        S.poisson(b, phi)
-        S.correct(phi, xu, xv, xw, 1.0)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    evs[0].record(stream)
-    for k in range(args.steps):
-        step()
-        evs[k + 1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    per = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)])
-    ms = wall * 1e3 / args.steps
     cells = n ** 3
-    value = 4 * cells / (ms * 1e-3) / 1e6
 
-    # live per-kernel timing (HIP events on the launch stream) over the same
-    # number of steps
-    ibs.ibs_profile(S.plan, True)
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    kern = {}
-    for kid, name in enumerate(ibs.PROFILE_KERNELS):
-        r = ibs.ibs_profile_read(S.plan, kid)
-        if r["launches"]:
-            kern[name] = r
-    ibs.ibs_profile(S.plan, False)
-    dom_name = max(kern, key=lambda k: kern[k]["ms"])
-    d = kern[dom_name]
-    avg_ms = d["ms"] / d["launches"]
-    if dom_name.startswith(("xgemm_f64", "zgemm_f64")):
-        achieved = d["flops"] / d["launches"] / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp64_tflops"],
-                "unit": "TFLOP/s"}
-    else:
-        achieved = d["bytes"] / d["launches"] / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_gbs"], "unit": "GB/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = dom_name
-    roof["avg_launch_ms"] = avg_ms
-    breakdown = {k: {"ms_per_step": r["ms"] / args.steps, "launches_per_step": r["launches"] / args.steps,
-                     "tflops": r["flops"] / (r["ms"] * 1e-3) / 1e12 if r["ms"] else None,
-                     "gbs": r["bytes"] / (r["ms"] * 1e-3) / 1e9 if r["ms"] else None}
-                 for k, r in kern.items()}
+    def run_path(precision):
+        S = ibs.Solver(n, n, n, beta=beta, precision=precision)
+        xu, xv, xw = S.empty(1), S.empty(2), S.empty(3)
+        b = S.empty(0)
+        phi = S.empty(0)
+
+        def step():
+            S.helmholtz([0, 1, 2], [c, c, c], [ru, rv, rw], [xu, xv, xw])
+            S.divergence(xu, xv, xw, 1.0, b)
+            S.poisson(b, phi)
+            S.correct(phi, xu, xv, xw, 1.0)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        evs[0].record(stream)
+        for k in range(args.steps):
+            step()
+            evs[k + 1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        per = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)])
+        ms = wall * 1e3 / args.steps
+        infos = [S.read_info(q) for q in range(3)]
+        # live per-kernel timing (HIP events on the launch stream) over the
+        # same number of steps
+        ibs.ibs_profile(S.plan, True)
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        kern = {}
+        for kid, name in enumerate(ibs.PROFILE_KERNELS):
+            r = ibs.ibs_profile_read(S.plan, kid)
+            if r["launches"]:
+                kern[name] = r
+        ibs.ibs_profile(S.plan, False)
+        S.poisson(b, phi)
+        torch.cuda.synchronize()
+        pinfo = S.read_info(0)
+        S.close()
+        return dict(ms=ms, per=per, kern=kern, hinfo=infos, pinfo=pinfo)
+
+    def roofline(kern, steps):
+        dom_name = max(kern, key=lambda k: kern[k]["ms"])
+        d = kern[dom_name]
+        avg_ms = d["ms"] / d["launches"]
+        if dom_name in ("xgemm_f64", "zgemm_f64"):
+            achieved = d["flops"] / d["launches"] / (avg_ms * 1e-3) / 1e12
+            roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp64_tflops"],
+                    "unit": "TFLOP/s"}
+        else:
+            achieved = d["bytes"] / d["launches"] / (avg_ms * 1e-3) / 1e9
+            roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_gbs"], "unit": "GB/s"}
+        roof["frac"] = roof["achieved"] / roof["peak"]
+        roof["traffic"] = None
+        roof["kernel"] = dom_name
+        roof["avg_launch_ms"] = avg_ms
+        breakdown = {k: {"ms_per_step": r["ms"] / steps,
+                         "launches_per_step": r["launches"] / steps,
+                         "tflops": r["flops"] / (r["ms"] * 1e-3) / 1e12 if r["ms"] else None,
+                         "gbs": r["bytes"] / (r["ms"] * 1e-3) / 1e9 if r["ms"] else None}
+                     for k, r in kern.items()}
+        return roof, breakdown
+
+    results = {}
+    paths = ["refined", "fp64"] if args.path == "both" else [args.path]
+    for path in paths:
+        log(f"path {path}")
+        prec = ibs.IBS_REFINED_BF16X3 if path == "refined" else ibs.IBS_FP64
+        r = run_path(prec)
+        roof, brk = roofline(r["kern"], args.steps)
+        results[path] = dict(
+            value=4 * cells / (r["ms"] * 1e-3) / 1e6, ms_per_step=r["ms"],
+            latency_ms={"p50": float(np.percentile(r["per"], 50)),
+                        "p99": float(np.percentile(r["per"], 99))},
+            roofline=roof, kernels=brk,
+            passes={"helmholtz": r["hinfo"][0].iters, "poisson": r["pinfo"].iters},
+            predicted_rel_err={"helmholtz": max(i.rel_residual for i in r["hinfo"]),
+                               "poisson": r["pinfo"].rel_residual} if path == "refined" else None,
+            status=[i.status for i in r["hinfo"]] + [r["pinfo"].status])
 
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle at {args.cpu_sample}^3")
         cpu = cpu_baseline(args.cpu_sample, beta, seed=2)
 
+    head = results[paths[0]]
     out = {
-        "metric": "Mcell-solves/s at 256^3 (FP64 path): 3 Helmholtz + Poisson per step",
-        "value": value, "unit": "Mcell-solves/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "metric": "Mcell-solves/s at 256^3: 3 Helmholtz + 1 Poisson solve per step "
+                  "(refined mixed precision to 1e-10; FP64 path alongside); p50/p99 step latency",
+        "value": head["value"], "unit": "Mcell-solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": ("bf16x3 MFMA, f32 accumulate, f64 residual/iterate" if paths[0] == "refined"
+                  else "f64"),
+        "data": "synthetic",
         "config": {"workload": f"fractional-step solves {n}^3, tanh beta={beta}, periodic x/z, "
                                f"Dirichlet/Neumann walls, c={c:.4e}",
-                   "path": args.path, "grid": [n, n, n]},
-        "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))},
-        "roofline": roof,
-        "kernels": breakdown,
+                   "path": paths[0], "grid": [n, n, n]},
+        "latency_ms": head["latency_ms"],
+        "roofline": head["roofline"],
+        "paths": results,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -88,7 +88,7 @@ typedef struct {
     int32_t bc_y_vel, bc_y_p; /* ibs_bc                                      */
     int32_t precision;        /* ibs_precision                               */
     double tol;               /* refined path: target ||delta||/||x|| (1e-10 if <= 0) */
-    int32_t max_iter;         /* refined path: refinement steps (0: default) */
+    int32_t max_iter;         /* refined path: solve passes, >= 1 (0: 2)     */
     int32_t strict_compat;    /* 1: Poisson rhs with nonzero weighted mean
                                  reports IBS_ERR_INCOMPATIBLE_RHS in info    */
 } ibs_grid_desc;
@@ -97,10 +97,12 @@ typedef struct {
  * point to memory the device can write (device memory or pinned host
  * memory); may be NULL. */
 typedef struct {
-    int32_t iters;          /* transform passes (1 for FP64)                   */
+    int32_t iters;          /* solve passes (1 for FP64; refinement passes)    */
     int32_t status;         /* ibs_status of the device part of the solve      */
-    double rel_residual;    /* refined: ||b - A x|| / ||b|| at the last check   */
-    double rel_correction;  /* refined: ||delta|| / ||x|| of the last step      */
+    double rel_residual;    /* refined: predicted relative error of x, i.e.
+                               rel_correction times the last observed
+                               contraction ratio; NOT_CONVERGED if > tol       */
+    double rel_correction;  /* refined: ||delta|| / ||x|| of the last pass     */
     double removed_mean;    /* Poisson: volume-weighted mean removed from b    */
 } ibs_solve_info;
 

@@ -125,6 +125,74 @@ static ibs_status run_fp64_pipeline(Plan &p, JobSet js, double *W, double *X, bo
     return run_fp64_pipeline_multi(p, js, &W, &X, poisson, s);
 }
 
+// Refined path: pass 0 solves A x = b with the split-precision transforms;
+// every later pass forms r = b - A x in FP64 (stored FP32), solves A d = r
+// the same way and updates x += d in FP64.  The job records carry the
+// right-hand side (b), the FP64 iterate (x) and two FP32 work fields each.
+static ibs_status run_refined(Plan &p, SplitSet ss, float *const *W1, float *const *W2, bool poisson,
+                              int passes, hipStream_t s)
+{
+    hipError_t e;
+    if (passes > max_refine_passes(ss, p)) {
+        set_error("max_iter exceeds the refinement passes this plan's scratch can record");
+        return IBS_ERR_INVALID_ARG;
+    }
+    double cells = 0;
+    for (int q = 0; q < ss.n; ++q) cells += (double)p.nz * ss.j[q].rows * p.nx;
+    const double xfl = 2.0 * p.nx * cells, zfl = 2.0 * p.nz * cells;
+    JobSet js{};
+    js.n = ss.n;
+    void *info[4];
+    for (int q = 0; q < ss.n; ++q) {
+        info[q] = ss.j[q].info;
+        js.j[q].out = reinterpret_cast<double *>(W2[q]);
+        js.j[q].in = js.j[q].out;
+        js.j[q].rows = ss.j[q].rows;
+        js.j[q].kind = ss.j[q].kind;
+        js.j[q].c = ss.j[q].c;
+    }
+    for (int pass = 0; pass < passes; ++pass) {
+        if (pass > 0) {
+            for (int q = 0; q < ss.n; ++q) ss.j[q].r = W2[q];
+            e = timed(p, PK_RESIDUAL, 10.0 * cells, 20.0 * cells, s, [&] { return launch_residual_f32(ss, p, s); });
+            if (e != hipSuccess) return hip_fail(e, "residual (refined)");
+        }
+        for (int q = 0; q < ss.n; ++q) {
+            ss.j[q].in = pass == 0 ? static_cast<const void *>(ss.j[q].b) : static_cast<const void *>(W2[q]);
+            ss.j[q].out = W1[q];
+        }
+        e = timed(p, PK_XGEMM_SPLIT, xfl, (pass == 0 ? 12.0 : 8.0) * cells, s,
+                  [&] { return launch_split_xgemm(ss, p, false, pass == 0, 0, pass, s); });
+        if (e != hipSuccess) return hip_fail(e, "x forward (split)");
+        for (int q = 0; q < ss.n; ++q) { ss.j[q].in = W1[q]; ss.j[q].out = W2[q]; }
+        e = timed(p, PK_ZGEMM_SPLIT, zfl, 8.0 * cells, s, [&] { return launch_split_zgemm(ss, p, false, s); });
+        if (e != hipSuccess) return hip_fail(e, "z forward (split)");
+        for (int q = 0; q < ss.n; ++q) js.j[q].info = pass == 0 ? info[q] : nullptr;
+        e = timed(p, PK_TRIDIAG_F32, 20.0 * cells, 8.0 * cells, s, [&] { return launch_tridiag_f32(js, p, poisson, pass, s); });
+        if (e != hipSuccess) return hip_fail(e, "tridiagonal (refined)");
+        for (int q = 0; q < ss.n; ++q) { ss.j[q].in = W2[q]; ss.j[q].out = W1[q]; }
+        e = timed(p, PK_ZGEMM_SPLIT, zfl, 8.0 * cells, s, [&] { return launch_split_zgemm(ss, p, true, s); });
+        if (e != hipSuccess) return hip_fail(e, "z inverse (split)");
+        for (int q = 0; q < ss.n; ++q) ss.j[q].in = W1[q];
+        const int mode = pass == 0 ? 1 : 2;
+        e = timed(p, PK_UPDATE, xfl, (pass == 0 ? 12.0 : 20.0) * cells, s,
+                  [&] { return launch_split_xgemm(ss, p, true, false, mode, pass, s); });
+        if (e != hipSuccess) return hip_fail(e, "x inverse + update (split)");
+    }
+    if (passes > 1) {
+        e = launch_refine_finalize(ss, p, passes, s);
+        if (e != hipSuccess) return hip_fail(e, "refinement report");
+    }
+    return IBS_OK;
+}
+
+static int default_passes(const Plan &p, bool poisson)
+{
+    (void)poisson;
+    if (p.desc.max_iter > 0) return p.desc.max_iter;
+    return 2;
+}
+
 }  // namespace ibs
 
 using namespace ibs;
@@ -198,6 +266,21 @@ ibs_status solve_poisson(ibs_plan plan, const double *b, double *phi, void *work
     if (!aligned32(b) || !aligned32(phi) || !aligned32(work)) { set_error("device arrays must be 32-byte aligned"); return IBS_ERR_INVALID_ARG; }
     if (work_bytes < work_bytes_for(p, IBS_OP_POISSON, 1)) { set_error("workspace too small"); return IBS_ERR_WORKSPACE_TOO_SMALL; }
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p.desc.precision != IBS_FP64) {
+        if (phi == b) { set_error("the refined path needs phi distinct from b"); return IBS_ERR_INVALID_ARG; }
+        SplitSet ss{};
+        ss.n = 1;
+        ss.j[0].b = b;
+        ss.j[0].x = phi;
+        ss.j[0].rows = p.ny;
+        ss.j[0].kind = KIND_P;
+        ss.j[0].op = IBS_OP_POISSON;
+        ss.j[0].c = 0.0;
+        ss.j[0].info = info;
+        float *W1 = static_cast<float *>(work);
+        float *W2 = W1 + field_doubles(p, p.ny);
+        return run_refined(p, ss, &W1, &W2, true, default_passes(p, true), s);
+    }
     double *W = static_cast<double *>(work);
     JobSet js{};
     js.n = 1;
@@ -237,6 +320,24 @@ ibs_status solve_helmholtz_batch(ibs_plan plan, int32_t ncomp, const int32_t *co
         js.j[q].info = info ? info + q : nullptr;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p.desc.precision != IBS_FP64) {
+        SplitSet ss{};
+        ss.n = ncomp;
+        float *W1[4], *W2[4];
+        for (int q = 0; q < ncomp; ++q) {
+            if (x[q] == r[q]) { set_error("the refined path needs x[q] distinct from r[q]"); return IBS_ERR_INVALID_ARG; }
+            ss.j[q].b = r[q];
+            ss.j[q].x = x[q];
+            ss.j[q].rows = js.j[q].rows;
+            ss.j[q].kind = js.j[q].kind;
+            ss.j[q].op = comp[q] + 1;
+            ss.j[q].c = c[q];
+            ss.j[q].info = js.j[q].info;
+            W1[q] = reinterpret_cast<float *>(W + q * stride);
+            W2[q] = W1[q] + stride;
+        }
+        return run_refined(p, ss, W1, W2, false, default_passes(p, false), s);
+    }
     for (int q = 0; q < ncomp; ++q) { js.j[q].in = r[q]; js.j[q].out = W + q * stride; }
     double *Ws[4], *Xs[4];
     for (int q = 0; q < ncomp; ++q) { Ws[q] = W + q * stride; Xs[q] = x[q]; }

@@ -25,6 +25,10 @@ struct BlobLayout {
     size_t lo[NUM_KINDS], di[NUM_KINDS], up[NUM_KINDS];  // y operator rows
     size_t wy;               // Delta_j (pressure weights), ny doubles
     size_t dyc, dyf;         // cell heights [ny], centre distances [ny+1]
+    size_t sx_fwd, sx_inv;   // x transform, bf16x3 split, B-operand swizzle
+    size_t sz_fwd, sz_inv;   // z transform, bf16x3 split, A-operand swizzle
+    size_t bmean;            // per-job weighted mean of the Poisson rhs (4 doubles)
+    size_t xsum;             // per-job partial sums of Delta_j x (XSUM_SLOTS each)
     size_t red;              // reduction scratch (doubles)
     size_t red_count;        // number of doubles in the reduction scratch
     size_t total;
@@ -68,6 +72,8 @@ struct Plan {
 };
 
 // Per-component record for batched launches (passed by value).
+// The refined path reuses it with float work arrays (cast through the
+// pointers) and x the FP64 iterate.
 struct FieldJob {
     const double *in;   // input field
     double *out;        // output field
@@ -104,6 +110,37 @@ hipError_t launch_correct(const Plan &p, const double *phi, double *u, double *v
                           double cp, hipStream_t s);
 hipError_t launch_residual(const Plan &p, int op, double c, const double *x,
                            const double *b, double *r, double *norms2, hipStream_t s);
+
+// ---- refined (split-precision) path ---------------------------------------
+constexpr int XSUM_SLOTS = 1024;   // residual blocks per job (fixed: deterministic sums)
+struct SplitJob {
+    const void *in;     // x transforms: FP64 (first pass) or FP32 input rows
+    float *out;         // FP32 output (forward passes, z passes)
+    double *x;          // x inverse: FP64 iterate (store or += update)
+    const double *b;    // residual: right-hand side
+    float *r;           // residual: FP32 output
+    int rows;           // rows per z-plane
+    int kind;
+    int op;             // IBS_OP_* of the job (residual stencil)
+    double c;
+    void *info;
+};
+struct SplitSet {
+    SplitJob j[4];
+    int n;
+};
+// x transform: in (FP64 when in64, else FP32) -> out (FP32), or, for the
+// inverse (mode 1: x = result, mode 2: x += result with norm partials).
+// pass: refinement pass of an update (mode 2), selecting its partial-sum region.
+hipError_t launch_split_xgemm(const SplitSet &ss, const Plan &p, bool inverse, bool in64, int mode,
+                              int pass, hipStream_t s);
+int max_refine_passes(const SplitSet &ss, const Plan &p);
+hipError_t launch_split_zgemm(const SplitSet &ss, const Plan &p, bool inverse, hipStream_t s);
+// pass: refinement pass (0 records the rhs mean; later passes steer the
+// Poisson correction so that x + d has zero weighted mean)
+hipError_t launch_tridiag_f32(const JobSet &js, const Plan &p, bool poisson, int pass, hipStream_t s);
+hipError_t launch_residual_f32(const SplitSet &ss, const Plan &p, hipStream_t s);
+hipError_t launch_refine_finalize(const SplitSet &ss, const Plan &p, int passes, hipStream_t s);
 
 inline const double *blob_ptr(const Plan &p, size_t off) {
     return reinterpret_cast<const double *>(static_cast<const unsigned char *>(p.dev_const) + off);

@@ -31,15 +31,21 @@ struct TriParams {
     const double *lam_x, *lam_z;
     const double *lo[NUM_KINDS], *di[NUM_KINDS], *up[NUM_KINDS];
     const double *wy;   // Delta_j: weights of the pressure unknowns
+    double *bmean;      // per job: weighted mean removed from the rhs (Poisson)
+    const double *xsum; // per job: XSUM_SLOTS partial sums of Delta_j x, or null
+    int record_mean;    // write bmean (first pass of a solve)
+    double wsum_y;      // sum of Delta_j
     int nx, nz;
     int poisson;
     int strict;
     double inv_sqrt_nxnz;
 };
 
-template <int P, int M>
-__global__ __launch_bounds__(16 * P) void tridiag_f64_kernel(JobSet js, TriParams tp, int ntx,
-                                                             int ntiles)
+// T: storage type of the field (double, or float on the refined path);
+// the arithmetic is FP64 either way.
+template <typename T, int P, int M>
+__global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp, int ntx,
+                                                         int ntiles)
 {
     constexpr int TA = 16;                 // pencils per tile
     constexpr int NT = TA * P;             // threads
@@ -64,12 +70,12 @@ __global__ __launch_bounds__(16 * P) void tridiag_f64_kernel(JobSet js, TriParam
         const int c = rem / ntx, a0 = (rem - c * ntx) * TA;
         const FieldJob &jb = js.j[job];
         const int n = jb.rows;
-        const double *__restrict__ base = jb.out + (size_t)c * n * nx + a0 + lcol;
+        const T *__restrict__ base = reinterpret_cast<const T *>(jb.out) + (size_t)c * n * nx + a0 + lcol;
         const bool walls = jb.kind == KIND_F;
 #pragma unroll
         for (int r = 0; r < M; ++r) {
             const int j = lrow + P * r;
-            pf[r] = (j < n && !(walls && (j == 0 || j == n - 1))) ? base[(size_t)j * nx] : 0.0;
+            pf[r] = (j < n && !(walls && (j == 0 || j == n - 1))) ? (double)base[(size_t)j * nx] : 0.0;
         }
     };
 
@@ -224,7 +230,17 @@ __global__ __launch_bounds__(16 * P) void tridiag_f64_kernel(JobSet js, TriParam
                 swx += __shfl_xor(swx, d, P);
                 sww += __shfl_xor(sww, d, P);
             }
-            const double mx = swx / sww;
+            double mx = swx / sww;
+            if (tp.xsum) {
+                // refinement: steer the correction so that x + d has zero
+                // weighted mean (in this pencil's normalisation)
+                const double *xs = tp.xsum + (size_t)job * XSUM_SLOTS;
+                double part = 0.0;
+                for (int q = k; q < XSUM_SLOTS; q += P) part += xs[q];
+#pragma unroll
+                for (int d = 1; d < P; d <<= 1) part += __shfl_xor(part, d, P);
+                mx += part * tp.inv_sqrt_nxnz / tp.wsum_y;
+            }
 #pragma unroll
             for (int t = 0; t < M; ++t)
                 if (s + t < n) r[t] -= mx;
@@ -232,6 +248,7 @@ __global__ __launch_bounds__(16 * P) void tridiag_f64_kernel(JobSet js, TriParam
 #pragma unroll
         for (int t = 0; t < M; ++t) sx[(s + t) * LDR + p] = r[t];
 
+        if (pinned && k == 0 && tp.record_mean) tp.bmean[job] = removed * tp.inv_sqrt_nxnz;
         if (a0 == 0 && c == 0 && tid == 0 && jb.info) {
             ibs_solve_info *inf = static_cast<ibs_solve_info *>(jb.info);
             const double rm = removed * tp.inv_sqrt_nxnz;
@@ -243,28 +260,29 @@ __global__ __launch_bounds__(16 * P) void tridiag_f64_kernel(JobSet js, TriParam
             inf->removed_mean = pois ? rm : 0.0;
         }
         __syncthreads();
-        double *__restrict__ base = jb.out + (size_t)c * n * nx + a0 + lcol;
+        T *__restrict__ base = reinterpret_cast<T *>(jb.out) + (size_t)c * n * nx + a0 + lcol;
 #pragma unroll
         for (int r2 = 0; r2 < M; ++r2) {
             const int j = lrow + P * r2;
-            if (j < n) base[(size_t)j * nx] = sx[j * LDR + lcol];
+            if (j < n) base[(size_t)j * nx] = (T)sx[j * LDR + lcol];
         }
     }
 }
 
-template <int P, int M>
+template <typename T, int P, int M>
 static hipError_t launch_pm(const JobSet &js, const TriParams &tp, hipStream_t s)
 {
     // persistent blocks walk the tiles (job, z-mode, 16 x-modes) in order
     const int ntx = tp.nx / 16;
     const int ntiles = ntx * tp.nz * js.n;
     const int grid = ntiles < 1024 ? ntiles : 1024;
-    hipLaunchKernelGGL((tridiag_f64_kernel<P, M>), dim3(grid), dim3(16 * P), 0, s, js, tp, ntx,
+    hipLaunchKernelGGL((tridiag_kernel<T, P, M>), dim3(grid), dim3(16 * P), 0, s, js, tp, ntx,
                        ntiles);
     return hipGetLastError();
 }
 
-hipError_t launch_tridiag_f64(const JobSet &js, const Plan &p, bool poisson, hipStream_t s)
+template <typename T>
+static hipError_t launch_tridiag(const JobSet &js, const Plan &p, bool poisson, int pass, hipStream_t s)
 {
     TriParams tp;
     tp.lam_x = blob_ptr(p, p.lay.lam_x);
@@ -275,27 +293,46 @@ hipError_t launch_tridiag_f64(const JobSet &js, const Plan &p, bool poisson, hip
         tp.up[kd] = blob_ptr(p, p.lay.up[kd]);
     }
     tp.wy = blob_ptr(p, p.lay.wy);
+    tp.bmean = blob_mut(p, p.lay.bmean);
+    tp.xsum = nullptr;
+    tp.record_mean = 1;
+    tp.wsum_y = 0.0;
+    for (int j = 0; j < p.ny; ++j) tp.wsum_y += p.dyc[j];
     tp.nx = p.nx;
     tp.nz = p.nz;
     tp.poisson = poisson ? 1 : 0;
     tp.strict = p.desc.strict_compat ? 1 : 0;
+    if (pass > 0) {
+        tp.record_mean = 0;
+        tp.xsum = blob_ptr(p, p.lay.xsum);
+    }
     tp.inv_sqrt_nxnz = 1.0 / std::sqrt((double)p.nx * (double)p.nz);
     int n = 0;
     for (int q = 0; q < js.n; ++q) n = js.j[q].rows > n ? js.j[q].rows : n;
     // 16 lanes per pencil up to 144 rows, then 32 (keeps the per-lane chunk
     // short, so the chunk arrays stay in registers at useful occupancy)
-    if (n <= 48) return launch_pm<16, 3>(js, tp, s);
-    if (n <= 80) return launch_pm<16, 5>(js, tp, s);
-    if (n <= 112) return launch_pm<16, 7>(js, tp, s);
-    if (n <= 144) return launch_pm<16, 9>(js, tp, s);
-    if (n <= 224) return launch_pm<32, 7>(js, tp, s);
-    if (n <= 288) return launch_pm<32, 9>(js, tp, s);
-    if (n <= 352) return launch_pm<32, 11>(js, tp, s);
-    if (n <= 416) return launch_pm<32, 13>(js, tp, s);
-    if (n <= 544) return launch_pm<32, 17>(js, tp, s);
-    if (n <= 672) return launch_pm<32, 21>(js, tp, s);
-    if (n <= 800) return launch_pm<32, 25>(js, tp, s);
+    if (n <= 48) return launch_pm<T, 16, 3>(js, tp, s);
+    if (n <= 80) return launch_pm<T, 16, 5>(js, tp, s);
+    if (n <= 112) return launch_pm<T, 16, 7>(js, tp, s);
+    if (n <= 144) return launch_pm<T, 16, 9>(js, tp, s);
+    if (n <= 224) return launch_pm<T, 32, 7>(js, tp, s);
+    if (n <= 288) return launch_pm<T, 32, 9>(js, tp, s);
+    if (n <= 352) return launch_pm<T, 32, 11>(js, tp, s);
+    if (n <= 416) return launch_pm<T, 32, 13>(js, tp, s);
+    if (n <= 544) return launch_pm<T, 32, 17>(js, tp, s);
+    if (n <= 672) return launch_pm<T, 32, 21>(js, tp, s);
+    if (n <= 800) return launch_pm<T, 32, 25>(js, tp, s);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_tridiag_f64(const JobSet &js, const Plan &p, bool poisson, hipStream_t s)
+{
+    return launch_tridiag<double>(js, p, poisson, 0, s);
+}
+
+hipError_t launch_tridiag_f32(const JobSet &js, const Plan &p, bool poisson, int pass, hipStream_t s)
+{
+    return launch_tridiag<float>(js, p, poisson, pass, s);
 }
 
 }  // namespace ibs

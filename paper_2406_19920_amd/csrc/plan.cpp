@@ -66,6 +66,63 @@ static void swizzle_a(const double *A, int M, int K, double *out)
                     out[o++] = A[size_t(16 * bi + (l % 16)) * K + 16 * kc + 4 * (l / 16) + t];
 }
 
+// Round a double to the nearest bfloat16 value (8 significant bits, ties to
+// even), returned as a double.
+static double round_bf16(double v)
+{
+    if (v == 0.0 || !std::isfinite(v)) return v;
+    int e;
+    double m = std::frexp(v, &e);              // v = m 2^e, 0.5 <= |m| < 1
+    return std::ldexp(std::nearbyint(std::ldexp(m, 8)), e - 8);
+}
+static uint16_t bf16_bits(double v)            // v exactly representable
+{
+    float f = (float)v;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return (uint16_t)(u >> 16);
+}
+// Three-term bfloat16 split v = t0 + t1 + t2 (+ O(2^-24 |v|)).
+static void split3(double v, uint16_t t[3])
+{
+    double h0 = round_bf16(v), r1 = v - h0;
+    double h1 = round_bf16(r1), r2 = r1 - h1;
+    double h2 = round_bf16(r2);
+    t[0] = bf16_bits(h0);
+    t[1] = bf16_bits(h1);
+    t[2] = bf16_bits(h2);
+}
+// Swizzle for the 16x16x32 bf16 matrix-core instruction, B operand (K x N):
+// per 32-deep chunk kc and 16-wide column block bj, per split term t, lane l
+// holds B[32 kc + 8 (l/16) + e][16 bj + l%16], e = 0..7 (16 bytes).
+static void swizzle_b_split(const double *B, int K, int N, uint16_t *out)
+{
+    size_t o = 0;
+    uint16_t tt[3];
+    for (int kc = 0; kc < K / 32; ++kc)
+        for (int bj = 0; bj < N / 16; ++bj)
+            for (int t = 0; t < 3; ++t)
+                for (int l = 0; l < 64; ++l)
+                    for (int e = 0; e < 8; ++e) {
+                        split3(B[size_t(32 * kc + 8 * (l / 16) + e) * N + 16 * bj + (l % 16)], tt);
+                        out[o++] = tt[t];
+                    }
+}
+// A operand (M x K): lane l holds A[16 bi + l%16][32 kc + 8 (l/16) + e].
+static void swizzle_a_split(const double *A, int M, int K, uint16_t *out)
+{
+    size_t o = 0;
+    uint16_t tt[3];
+    for (int kc = 0; kc < K / 32; ++kc)
+        for (int bi = 0; bi < M / 16; ++bi)
+            for (int t = 0; t < 3; ++t)
+                for (int l = 0; l < 64; ++l)
+                    for (int e = 0; e < 8; ++e) {
+                        split3(A[size_t(16 * bi + (l % 16)) * K + 32 * kc + 8 * (l / 16) + e], tt);
+                        out[o++] = tt[t];
+                    }
+}
+
 ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
 {
     if (d.nx < 16 || d.nz < 16 || d.nx > 1024 || d.nz > 1024 || d.nx % 16 || d.nz % 16) {
@@ -84,6 +141,10 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     if (d.precision < IBS_FP64 || d.precision > IBS_REFINED_AUTO) {
         set_error("unknown precision");
         return IBS_ERR_INVALID_ARG;
+    }
+    if (d.precision != IBS_FP64 && (d.nx % 32 || d.nz % 32)) {
+        set_error("the refined path needs nx and nz to be multiples of 32");
+        return IBS_ERR_UNSUPPORTED;
     }
     if (!(std::isfinite(d.beta)) || d.beta < 0.0 || d.beta > 10.0) {
         set_error("beta must be in [0, 10]");
@@ -181,7 +242,14 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     L.wy = take(sizeof(double) * ny);
     L.dyc = take(sizeof(double) * ny);
     L.dyf = take(sizeof(double) * (ny + 1));
-    L.red_count = 8192;
+    const bool split = d.precision != IBS_FP64;
+    L.sx_fwd = take(split ? sizeof(uint16_t) * 3 * nx * nx : 0);
+    L.sx_inv = take(split ? sizeof(uint16_t) * 3 * nx * nx : 0);
+    L.sz_fwd = take(split ? sizeof(uint16_t) * 3 * nz * nz : 0);
+    L.sz_inv = take(split ? sizeof(uint16_t) * 3 * nz * nz : 0);
+    L.bmean = take(sizeof(double) * 4);
+    L.xsum = take(sizeof(double) * 4 * XSUM_SLOTS);
+    L.red_count = 131072;
     L.red = take(sizeof(double) * L.red_count);
     L.total = o;
     p->blob.assign(L.total, 0);
@@ -209,6 +277,24 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
         // z inverse: X[k] = sum_c Q[k][c] Xhat[c] -> A = Q
         swizzle_a(p->qz.data(), nz, nz, tmp.data());
         put(L.az_inv, tmp.data(), tmp.size());
+    }
+    if (split) {
+        std::vector<double> tr(size_t(nx) * nx);
+        std::vector<uint16_t> sw(size_t(3) * nx * nx);
+        swizzle_b_split(p->qx.data(), nx, nx, sw.data());
+        std::memcpy(p->blob.data() + L.sx_fwd, sw.data(), sw.size() * 2);
+        for (int i = 0; i < nx; ++i)
+            for (int a = 0; a < nx; ++a) tr[size_t(a) * nx + i] = p->qx[size_t(i) * nx + a];
+        swizzle_b_split(tr.data(), nx, nx, sw.data());
+        std::memcpy(p->blob.data() + L.sx_inv, sw.data(), sw.size() * 2);
+        std::vector<double> trz(size_t(nz) * nz);
+        std::vector<uint16_t> swz(size_t(3) * nz * nz);
+        for (int k = 0; k < nz; ++k)
+            for (int c = 0; c < nz; ++c) trz[size_t(c) * nz + k] = p->qz[size_t(k) * nz + c];
+        swizzle_a_split(trz.data(), nz, nz, swz.data());
+        std::memcpy(p->blob.data() + L.sz_fwd, swz.data(), swz.size() * 2);
+        swizzle_a_split(p->qz.data(), nz, nz, swz.data());
+        std::memcpy(p->blob.data() + L.sz_inv, swz.data(), swz.size() * 2);
     }
     put(L.lam_x, p->lam_x.data(), nx);
     put(L.lam_z, p->lam_z.data(), nz);

@@ -1,0 +1,145 @@
+"""GPU parity of the refined path (split-bfloat16 transforms with FP32
+accumulation, FP64 residual and iterate) against the oracle.
+
+Tolerance: 1e-10 relative (l2), the refined-path accuracy target.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import OP_P, OP_U, OP_V, OP_W
+from paper_2406_19920_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ibs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_19920_amd import ibsolve
+    return ibsolve
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("shape,beta", [((64, 64, 64), 0.0), ((32, 40, 64), 2.0),
+                                        ((96, 33, 32), 3.0)])
+def test_refined_poisson_vs_oracle(ibs, shape, beta):
+    nx, ny, nz = shape
+    _say("case refined poisson", shape, beta)
+    g = oracle.Grid(nx, ny, nz, beta=beta)
+    u, v, w = synth.velocity(nx, ny, nz, seed=1)
+    b = oracle.divergence(g, u, v, w)
+    xo, info = oracle.solve(g, OP_P, b)
+    errs = []
+    for passes in (1, 2, 3, 4):
+        S = ibs.Solver(nx, ny, nz, beta=beta, precision=ibs.IBS_REFINED_BF16X3, max_iter=passes)
+        xg = _host(S.poisson(_dev(b)))
+        errs.append(_rel(xg, xo))
+        inf = S.read_info()
+        assert inf.iters == passes
+        assert abs(inf.removed_mean - info.removed_mean) < 1e-6 * np.abs(b).max()
+        S.close()
+    _say("errors by passes", errs)
+    S = ibs.Solver(nx, ny, nz, beta=beta, precision=ibs.IBS_REFINED_BF16X3)
+    xg = _host(S.poisson(_dev(b)))
+    err = _rel(xg, xo)
+    inf = S.read_info()
+    _say("default passes", inf.iters, "err", err, "rel_correction", inf.rel_correction)
+    assert err < TOL
+    assert inf.status == 0
+    assert errs[1] < errs[0] * 1e-2   # refinement contracts
+
+
+@pytest.mark.parametrize("shape,beta,c", [((32, 40, 64), 2.0, 1e-3), ((64, 24, 32), 0.0, 3e-2),
+                                          ((32, 17, 32), 3.0, 4.2e-8)])
+def test_refined_helmholtz_vs_oracle(ibs, shape, beta, c):
+    nx, ny, nz = shape
+    _say("case refined helmholtz", shape, beta, c)
+    g = oracle.Grid(nx, ny, nz, beta=beta)
+    u, v, w = synth.velocity(nx, ny, nz, seed=7)
+    refs = [oracle.solve(g, op, f, c=c)[0] for op, f in ((OP_U, u), (OP_V, v), (OP_W, w))]
+    S = ibs.Solver(nx, ny, nz, beta=beta, precision=ibs.IBS_REFINED_BF16X3)
+    xs = S.helmholtz([0, 1, 2], [c, c, c], [_dev(u), _dev(v), _dev(w)])
+    for q, (x, ref) in enumerate(zip(xs, refs)):
+        xg = _host(x)
+        err = _rel(xg, ref)
+        inf = S.read_info(q)
+        _say("comp", q, "err", err, "passes", inf.iters, "rel_corr", inf.rel_correction)
+        assert err < TOL
+        assert inf.status == 0
+        if q == 1:
+            assert np.all(xg[:, 0, :] == 0) and np.all(xg[:, ny, :] == 0)
+
+
+def test_refined_manufactured_256(ibs):
+    """256^3, beta = 2: manufactured solutions (x_true seeded, b = A x_true
+    formed by the oracle's long-double stencil on the CPU)."""
+    n = 256
+    _say("case refined manufactured 256^3")
+    g = oracle.Grid(n, n, n, beta=2.0)
+    S = ibs.Solver(n, n, n, beta=2.0, precision=ibs.IBS_REFINED_BF16X3)
+    c = 0.125 * float(g.dyc.min()) ** 2
+    xt = synth.manufactured(n, n, n, seed=2)
+    xt = xt - oracle.weighted_mean(g, OP_P, xt)
+    r, _, _ = oracle.residual_ld(g, OP_P, 0.0, xt, np.zeros_like(xt))
+    xg = _host(S.poisson(_dev(-r)))
+    err = _rel(xg, xt)
+    _say("poisson err", err, "passes", S.read_info().iters)
+    assert err < TOL
+    for op, comp in ((OP_U, 0), (OP_V, 1), (OP_W, 2)):
+        rows = n + 1 if op == OP_V else None
+        xt = synth.manufactured(n, n, n, seed=3 + comp, rows=rows)
+        if op == OP_V:
+            xt[:, 0, :] = 0
+            xt[:, n, :] = 0
+        r, _, _ = oracle.residual_ld(g, op, c, xt, np.zeros_like(xt))
+        (xg,) = S.helmholtz([comp], [c], [_dev(-r)])
+        err = _rel(_host(xg), xt)
+        _say("helmholtz", comp, "err", err)
+        assert err < TOL
+
+
+def test_refined_not_converged_flag(ibs):
+    """One pass with an unreachable tolerance: the device report says
+    NOT_CONVERGED (forced from the host through the plan)."""
+    n = 32
+    b = synth.scalar(n, n, n, 3)
+    S = ibs.Solver(n, n, n, precision=ibs.IBS_REFINED_BF16X3, max_iter=2, tol=1e-30)
+    S.poisson(_dev(b))
+    inf = S.read_info()
+    assert inf.status == ibs.IBS_ERR_NOT_CONVERGED and inf.iters == 2
+    S2 = ibs.Solver(n, n, n, precision=ibs.IBS_REFINED_BF16X3, max_iter=3, tol=1e-6)
+    S2.poisson(_dev(b))
+    assert S2.read_info().status == 0
+
+
+def test_refined_rejects_alias(ibs):
+    n = 32
+    S = ibs.Solver(n, n, n, precision=ibs.IBS_REFINED_BF16X3)
+    t = _dev(synth.scalar(n, n, n, 3))
+    with pytest.raises(ibs.IbsError) as e:
+        S.poisson(t, t)
+    assert e.value.status == ibs.IBS_ERR_INVALID_ARG
