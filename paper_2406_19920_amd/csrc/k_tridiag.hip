@@ -27,6 +27,17 @@
 
 namespace ibs {
 
+// 1/d from the hardware reciprocal estimate refined by two Newton steps
+// (d is a normal, finite FP64 number here: diagonally dominant pivots).
+static __device__ __forceinline__ double rcp64(double d)
+{
+    double x = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, x, 1.0);
+    x = fma(x, e, x);
+    e = fma(-d, x, 1.0);
+    return fma(x, e, x);
+}
+
 struct TriParams {
     const double *lam_x, *lam_z;
     const double *lo[NUM_KINDS], *di[NUM_KINDS], *up[NUM_KINDS];
@@ -90,11 +101,17 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
         const int n = jb.rows, kind = jb.kind;
         __syncthreads();  // the previous tile's LDS is no longer read
         if (job != cur_job) {
+            // rows of the job's operator without the pencil shift:
+            // Poisson (lo, di, up); Helmholtz (-c lo, 1 - c di, -c up)
+            const double cj = jb.c;
             for (int j = tid; j < NR; j += NT) {
                 const bool real = j < n;
-                slo[j] = real ? tp.lo[kind][j] : 0.0;
-                sdi[j] = real ? tp.di[kind][j] : 0.0;
-                sup[j] = real ? tp.up[kind][j] : 0.0;
+                const double lo = real ? tp.lo[kind][j] : 0.0;
+                const double di = real ? tp.di[kind][j] : 0.0;
+                const double up = real ? tp.up[kind][j] : 0.0;
+                slo[j] = pois ? lo : -cj * lo;
+                sdi[j] = pois ? di : 1.0 - cj * di;
+                sup[j] = pois ? up : -cj * up;
                 sw[j] = (real && pois) ? tp.wy[j] : 0.0;
             }
             cur_job = job;
@@ -106,7 +123,7 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
 
         const int a = a0 + p;
         const double sh = tp.lam_x[a] + tp.lam_z[c];
-        const double cc = jb.c;
+        const double sadd = pois ? sh : -jb.c * sh;   // pencil shift of the diagonal
         const bool pinned = pois && a == 0 && c == 0;
 
         double r[M];
@@ -139,48 +156,46 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
         }
 
         auto coef = [&](int j, double &A, double &B, double &C) {
-            const double lo = slo[j], di = sdi[j], up = sup[j];
-            if (j >= n) { A = 0.0; B = 1.0; C = 0.0; return; }
-            if (pois) {
-                A = lo; B = di + sh; C = up;
-                if (pinned && j == 0) { A = 0.0; B = 1.0; C = 0.0; }
-            } else {
-                A = -cc * lo; B = 1.0 - cc * sh - cc * di; C = -cc * up;
-            }
+            const bool real = j < n && !(pinned && j == 0);
+            A = real ? slo[j] : 0.0;
+            B = real ? sdi[j] + sadd : 1.0;
+            C = real ? sup[j] : 0.0;
         };
 
-        // up-sweep: rows s+M-2 .. s in the form lam x_{j-1} + x_j + mu x_e = sig
-        double lam_u, mu_u, sig_u;
-        {
-            double A, B, C;
-            coef(s + M - 2, A, B, C);
-            double inv = 1.0 / B;
-            lam_u = A * inv; mu_u = C * inv; sig_u = r[M - 2] * inv;
-#pragma unroll
-            for (int t = M - 3; t >= 0; --t) {
-                coef(s + t, A, B, C);
-                inv = 1.0 / (B - C * lam_u);
-                const double nmu = -C * mu_u * inv;
-                sig_u = (r[t] - C * sig_u) * inv;
-                lam_u = A * inv;
-                mu_u = nmu;
-            }
-        }
         // down-sweep: rows s+1 .. s+M-1 in the form al x_s + x_j + ga x_{j+1} = rho
         double al[M], ga[M];
         {
             double A, B, C;
             coef(s + 1, A, B, C);
-            double inv = 1.0 / B;
+            double inv = rcp64(B);
             al[1] = A * inv; ga[1] = C * inv; r[1] = r[1] * inv;
 #pragma unroll
             for (int t = 2; t < M; ++t) {
                 coef(s + t, A, B, C);
-                inv = 1.0 / (B - A * ga[t - 1]);
+                inv = rcp64(B - A * ga[t - 1]);
                 al[t] = -A * al[t - 1] * inv;
                 ga[t] = C * inv;
                 r[t] = (r[t] - A * r[t - 1]) * inv;
             }
+        }
+        // interior rows in terms of the chunk ends, x_j = bp + bq x_s + br x_e,
+        // by back-substitution (no divisions), then the top row
+        //   lam x_{s-1} + x_s + mu x_e = sig
+        double lam_u, mu_u, sig_u;
+        {
+            double bp = r[M - 2], bq = -al[M - 2], br = -ga[M - 2];
+#pragma unroll
+            for (int t = M - 3; t >= 1; --t) {
+                bp = r[t] - ga[t] * bp;
+                bq = -al[t] - ga[t] * bq;
+                br = -ga[t] * br;
+            }
+            double A, B, C;
+            coef(s, A, B, C);
+            const double inv = rcp64(B + C * bq);
+            lam_u = A * inv;
+            mu_u = C * br * inv;
+            sig_u = (r[0] - C * bp) * inv;
         }
 
         // reduced system in z_k = x_{last row of chunk k}
@@ -200,13 +215,13 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
             double cp = __shfl_down(EC, d, P), dp = __shfl_down(ED, d, P);
             if (k < d) { am = 0.0; bm = 1.0; cm = 0.0; dm = 0.0; }
             if (k + d >= P) { ap = 0.0; bp = 1.0; cp = 0.0; dp = 0.0; }
-            const double k1 = EA / bm, k2 = EC / bp;
+            const double k1 = EA * rcp64(bm), k2 = EC * rcp64(bp);
             const double nA = -k1 * am, nC = -k2 * cp;
             const double nB = EB - k1 * cm - k2 * ap;
             const double nD = ED - k1 * dm - k2 * dp;
             EA = nA; EB = nB; EC = nC; ED = nD;
         }
-        const double z = ED / EB;
+        const double z = ED * rcp64(EB);
         double zm = __shfl_up(z, 1, P);
         if (k == 0) zm = 0.0;
         const double xs = sig_u - lam_u * zm - mu_u * z;
