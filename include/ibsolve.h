@@ -186,6 +186,41 @@ ibs_status ibs_correct(ibs_plan plan, const double *phi, double *u, double *v,
                        double *w, double g, double *p, const double *lap_phi,
                        double cp, void *stream);
 
+/* ---- Batched execution (many independent grids, one graph launch) ----- */
+
+typedef struct ibs_batch_s *ibs_batch;
+
+/* One solve of a batch.  op: IBS_OP_POISSON (rhs[0] -> x[0]) or
+ * IBS_OP_HELMHOLTZ_U for a Helmholtz batch of ncomp components (comp, c,
+ * rhs, x as in solve_helmholtz_batch).  Every pointer is captured as is:
+ * the buffers must stay allocated, and at the same addresses, for the
+ * lifetime of the batch.  Solves of one plan must share their plan's
+ * scratch serially, so the batch never overlaps two jobs of one plan. */
+typedef struct {
+    ibs_plan plan;
+    int32_t op;
+    int32_t ncomp;
+    int32_t comp[3];
+    double c[3];
+    const double *rhs[3];
+    double *x[3];
+    void *work;
+    size_t work_bytes;
+    ibs_solve_info *info;   /* NULL or ncomp (Poisson: 1) device records */
+} ibs_batch_job;
+
+/* Record njobs solves (the batching of the multi-grid configuration) into
+ * one HIP graph by stream capture.  Jobs are spread over up to nlanes
+ * independent graph branches (jobs of one plan stay on one branch, lanes
+ * balanced by work) so that small grids overlap on the device.  Nothing is
+ * executed.  Errors: IBS_ERR_INVALID_ARG (bad job; ibs_last_error() names
+ * it), IBS_ERR_HIP, and any error a job's solve call would return. */
+ibs_status ibs_batch_build(const ibs_batch_job *jobs, int32_t njobs, int32_t nlanes,
+                           ibs_batch *out);
+/* Replay the whole batch on stream with one graph launch (asynchronous). */
+ibs_status ibs_batch_launch(ibs_batch batch, void *stream);
+ibs_status ibs_batch_destroy(ibs_batch batch);
+
 /* Host copies of the plan's tables, for inspection and host-side checks.
  * table: 0 y faces [ny+1]; 1 Q_x [nx*nx] (row-major, Q[i*nx+a] = mode a at
  * grid index i); 2 Q_z [nz*nz]; 3 lambda_x [nx]; 4 lambda_z [nz];

@@ -78,6 +78,17 @@ static hipError_t timed(Plan &p, int kid, double flops, double bytes, hipStream_
     return e;
 }
 
+// Profiling records events around launches, which must not happen while a
+// batch is being captured into a graph.
+ibs_status profile_suspend(ibs_plan plan, bool *was_on)
+{
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    *was_on = p->prof.on;
+    p->prof.on = false;
+    return IBS_OK;
+}
+void profile_resume(ibs_plan plan, bool was_on) { reinterpret_cast<Plan *>(plan)->prof.on = was_on; }
+
 size_t work_bytes_for(const Plan &p, int op, int ncomp)
 {
     if (op == IBS_OP_POISSON) return field_doubles(p, p.ny) * sizeof(double);

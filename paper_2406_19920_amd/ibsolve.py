@@ -33,6 +33,7 @@ IBS_OP_POISSON, IBS_OP_HELMHOLTZ_U, IBS_OP_HELMHOLTZ_V, IBS_OP_HELMHOLTZ_W = 0, 
 EXPORTS = ("solver_plan", "solver_plan_bytes", "solver_plan_upload", "solver_plan_destroy",
            "solve_poisson", "solve_helmholtz_batch", "residual", "ibs_divergence",
            "ibs_correct", "ibs_plan_export", "ibs_profile", "ibs_profile_read",
+           "ibs_batch_build", "ibs_batch_launch", "ibs_batch_destroy",
            "ibs_last_error", "ibs_version")
 
 PROFILE_KERNELS = ("xgemm_f64", "zgemm_f64", "tridiag_f64", "divergence", "correct", "residual",
@@ -58,6 +59,14 @@ class ibs_solve_info(ctypes.Structure):
 INFO_BYTES = ctypes.sizeof(ibs_solve_info)
 
 
+class ibs_batch_job(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("op", ctypes.c_int32), ("ncomp", ctypes.c_int32),
+                ("comp", ctypes.c_int32 * 3), ("c", ctypes.c_double * 3),
+                ("rhs", ctypes.c_void_p * 3), ("x", ctypes.c_void_p * 3),
+                ("work", ctypes.c_void_p), ("work_bytes", ctypes.c_size_t),
+                ("info", ctypes.c_void_p)]
+
+
 class IbsError(RuntimeError):
     def __init__(self, status: int, where: str, msg: str):
         super().__init__(f"{where}: status {status}: {msg}")
@@ -81,6 +90,9 @@ def _load():
     L.ibs_correct.argtypes = [vp, vp, vp, vp, vp, dbl, vp, vp, dbl, vp]
     L.ibs_plan_export.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(sz)]
     L.ibs_profile.argtypes = [vp, i32]
+    L.ibs_batch_build.argtypes = [ctypes.POINTER(ibs_batch_job), i32, i32, ctypes.POINTER(vp)]
+    L.ibs_batch_launch.argtypes = [vp, vp]
+    L.ibs_batch_destroy.argtypes = [vp]
     L.ibs_profile_read.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64),
                                    ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     for name in EXPORTS:
@@ -194,6 +206,21 @@ def ibs_profile_read(plan, kernel: int):
     return dict(ms=ms.value, launches=n.value, flops=fl.value, bytes=by.value)
 
 
+def ibs_batch_build(jobs, nlanes: int) -> int:
+    arr = (ibs_batch_job * len(jobs))(*jobs)
+    h = ctypes.c_void_p()
+    _check(lib.ibs_batch_build(arr, len(jobs), nlanes, ctypes.byref(h)), "ibs_batch_build")
+    return h.value
+
+
+def ibs_batch_launch(batch: int, stream: int):
+    _check(lib.ibs_batch_launch(batch, stream), "ibs_batch_launch")
+
+
+def ibs_batch_destroy(batch: int):
+    _check(lib.ibs_batch_destroy(batch), "ibs_batch_destroy")
+
+
 # ---------------------------------------------------------------------------
 # torch-owned buffers around one plan
 # ---------------------------------------------------------------------------
@@ -214,7 +241,7 @@ class Solver:
         _, self.work_h = solver_plan_bytes(self.plan, IBS_OP_HELMHOLTZ_U, 3)
         self.const = torch.empty(cb, dtype=torch.uint8, device=self.device)
         self.work = torch.empty(max(self.work_p, self.work_h), dtype=torch.uint8, device=self.device)
-        self.info = torch.zeros((4, INFO_BYTES // 8), dtype=torch.float64, device=self.device)
+        self.info = torch.zeros((8, INFO_BYTES // 8), dtype=torch.float64, device=self.device)
         solver_plan_upload(self.plan, self.const.data_ptr(), cb, self.stream())
         self.work_bytes = self.work.numel()
 
@@ -239,7 +266,7 @@ class Solver:
                       self.work_bytes, self.info.data_ptr(), self.stream())
         return phi
 
-    def helmholtz(self, comps, cs, rs, xs=None):
+    def helmholtz(self, comps, cs, rs, xs=None, info_slot=0):
         ops = [c + 1 for c in comps]
         if xs is None:
             xs = [self.empty(op) for op in ops]
@@ -248,7 +275,7 @@ class Solver:
             self._chk(x, op)
         solve_helmholtz_batch(self.plan, list(comps), list(cs), [r.data_ptr() for r in rs],
                               [x.data_ptr() for x in xs], self.work.data_ptr(), self.work_bytes,
-                              self.info.data_ptr(), self.stream())
+                              self.info[info_slot].data_ptr(), self.stream())
         return xs
 
     def residual(self, op, c, x, b, r=None, norms=False):
@@ -268,6 +295,29 @@ class Solver:
         ibs_correct(self.plan, phi.data_ptr(), u.data_ptr(), v.data_ptr(), w.data_ptr(), g,
                     p.data_ptr() if p is not None else None,
                     lap_phi.data_ptr() if lap_phi is not None else None, cp, self.stream())
+
+    def poisson_job(self, b, phi, info_slot=0):
+        """An ibs_batch_job record for a Poisson solve (buffers must outlive the batch)."""
+        self._chk(b, IBS_OP_POISSON)
+        self._chk(phi, IBS_OP_POISSON)
+        j = ibs_batch_job()
+        j.plan, j.op, j.ncomp = self.plan, IBS_OP_POISSON, 1
+        j.rhs[0], j.x[0] = b.data_ptr(), phi.data_ptr()
+        j.work, j.work_bytes = self.work.data_ptr(), self.work_bytes
+        j.info = self.info[info_slot].data_ptr()
+        return j
+
+    def helmholtz_job(self, comps, cs, rs, xs, info_slot=0):
+        """An ibs_batch_job record for a Helmholtz batch (info slots info_slot..)."""
+        j = ibs_batch_job()
+        j.plan, j.op, j.ncomp = self.plan, IBS_OP_HELMHOLTZ_U, len(comps)
+        for q, (cp, cv, r, x) in enumerate(zip(comps, cs, rs, xs)):
+            self._chk(r, cp + 1)
+            self._chk(x, cp + 1)
+            j.comp[q], j.c[q], j.rhs[q], j.x[q] = cp, cv, r.data_ptr(), x.data_ptr()
+        j.work, j.work_bytes = self.work.data_ptr(), self.work_bytes
+        j.info = self.info[info_slot].data_ptr()
+        return j
 
     def read_info(self, q=0):
         raw = self.info[q].cpu().numpy().tobytes()[:INFO_BYTES]

@@ -121,3 +121,28 @@ def manufactured(nx: int, ny: int, nz: int, seed: int, rows: int | None = None,
     f = scalar(nx, ny, nz, seed, rows)
     g = lowpass(f, kmax) if kmax is not None else np.zeros_like(f)
     return g + noise * scalar(nx, ny, nz, seed + 7919, rows)
+
+
+# Grid sizes (nx, ny, nz) of the mixed-size batch workload.
+BATCH_SIZES = ((64, 64, 64), (96, 128, 96), (128, 128, 128), (192, 256, 192))
+
+
+def batch_specs(njobs: int = 64, seed: int = 4, sizes=BATCH_SIZES, beta_max: float = 3.0):
+    """Job list of the mixed-size batch: sizes uniform over ``sizes``,
+    tanh stretching beta ~ U[0, beta_max], per-job seeds 1000 + i."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(njobs):
+        nx, ny, nz = sizes[int(rng.integers(0, len(sizes)))]
+        out.append(dict(nx=nx, ny=ny, nz=nz, beta=float(rng.uniform(0.0, beta_max)),
+                        seed=1000 + i))
+    return out
+
+
+def device_normal(shape, seed: int, device):
+    """Seeded N(0,1) FP64 field generated on the device (torch's Philox
+    generator); used where host generation of large batches would dominate."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    return torch.randn(shape, generator=g, dtype=torch.float64, device=device)
