@@ -1,0 +1,294 @@
+"""Continuous-batching request loop for the solver library.
+
+Requests (one pressure Poisson solve, or the three Helmholtz components of
+one fractional step) arrive over time.  The loop admits a waiting request as
+soon as a slot is free and the device memory it needs fits the HBM budget,
+so requests that arrive while others are on the GPU start immediately and
+overlap with them (one HIP stream per slot).  Plans (eigenvector tables and
+workspace) stay resident in an LRU cache keyed by (grid, stretching,
+precision) and count against the budget; fields are allocated per request
+and released on completion.  Completion is detected by polling per-request
+events; latency runs from arrival to completion.
+
+The scheduler talks to an executor.  GpuExecutor drives the C ABI (every
+solve step runs in the library's HIP kernels); tests substitute a fake
+executor to check admission and ordering on the CPU.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import synth
+
+
+def field_bytes(n: int, kind: str) -> int:
+    """Device bytes of a request's fields (right-hand sides and solutions)."""
+    cells = n * n * n
+    if kind == "poisson":
+        return 2 * 8 * cells
+    return 2 * 8 * (2 * cells + n * (n + 1) * n)
+
+
+def plan_key(req):
+    return (req["n"], round(req["beta"], 12), req["refined"])
+
+
+class GpuExecutor:
+    """Runs requests through the C ABI on per-slot HIP streams."""
+
+    def __init__(self, slots: int, device="cuda"):
+        import torch
+        from . import ibsolve
+        self.torch, self.ibs = torch, ibsolve
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
+
+    def plan_bytes(self, req) -> int:
+        ibs = self.ibs
+        n = req["n"]
+        prec = ibs.IBS_REFINED_BF16X3 if req["refined"] else ibs.IBS_FP64
+        plan = ibs.solver_plan(ibs.make_desc(n, n, n, beta=req["beta"], precision=prec))
+        try:
+            cb, wp = ibs.solver_plan_bytes(plan, ibs.IBS_OP_POISSON)
+            _, wh = ibs.solver_plan_bytes(plan, ibs.IBS_OP_HELMHOLTZ_U, 3)
+        finally:
+            ibs.solver_plan_destroy(plan)
+        return cb + max(wp, wh)
+
+    def make_solver(self, req):
+        ibs = self.ibs
+        n = req["n"]
+        prec = ibs.IBS_REFINED_BF16X3 if req["refined"] else ibs.IBS_FP64
+        S = ibs.Solver(n, n, n, beta=req["beta"], precision=prec, device=self.device)
+        # the constants were copied on the current stream; make them visible
+        # to the slot streams before first use
+        self.torch.cuda.current_stream(self.device).synchronize()
+        return S
+
+    @staticmethod
+    def solver_bytes(S) -> int:
+        return S.const.numel() + S.work.numel()
+
+    @staticmethod
+    def close_solver(S):
+        S.close()
+
+    def launch(self, slot, req, S):
+        """Enqueue the request; returns (event, fields, outputs, cell_solves)."""
+        from .batch import cn_coefficient
+        torch = self.torch
+        stream = self.streams[slot]
+        n = req["n"]
+        with torch.cuda.stream(stream):
+            if req["kind"] == "poisson":
+                b = synth.device_normal(S.shape(0), req["seed"], self.device)
+                phi = S.empty(0)
+                S.poisson(b, phi)
+                fields, outs, cells = [b, phi], [phi], n ** 3
+            else:
+                rs = [synth.device_normal(S.shape(op), req["seed"] * 4 + op, self.device)
+                      for op in (1, 2, 3)]
+                rs[1][:, 0, :] = 0
+                rs[1][:, n, :] = 0
+                xs = [S.empty(op) for op in (1, 2, 3)]
+                c = cn_coefficient(S)
+                S.helmholtz([0, 1, 2], [c, c, c], rs, xs)
+                fields, outs, cells = rs + xs, xs, 3 * n ** 3
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        return ev, fields, outs, cells
+
+    @staticmethod
+    def fetch(outs):
+        return [o.cpu() for o in outs]
+
+    def synchronize(self):
+        self.torch.cuda.synchronize(self.device)
+
+
+class PlanCache:
+    """LRU cache of resident plans.  A cached plan is lent to one request at
+    a time (its workspace and scratch are single-use)."""
+
+    def __init__(self, executor, capacity_bytes: int):
+        self.ex = executor
+        self.capacity = capacity_bytes
+        self.items = collections.OrderedDict()   # key -> solver
+        self.busy = set()
+        self.bytes = 0
+        self.hits = 0
+        self.misses = 0
+
+    def acquire(self, req, budget_left: int):
+        """(solver, bytes newly resident) or (None, 0) when it cannot be placed now."""
+        k = plan_key(req)
+        S = self.items.get(k)
+        if S is not None:
+            if k in self.busy:
+                return None, 0
+            self.items.move_to_end(k)
+            self.busy.add(k)
+            self.hits += 1
+            return S, 0
+        need = self.ex.plan_bytes(req)
+        while self.bytes + need > self.capacity or need > budget_left:
+            victim = next((kk for kk in self.items if kk not in self.busy), None)
+            if victim is None:
+                return None, 0
+            old = self.items.pop(victim)
+            nb = self.ex.solver_bytes(old)
+            self.bytes -= nb
+            budget_left += nb
+            self.ex.close_solver(old)
+        S = self.ex.make_solver(req)
+        self.items[k] = S
+        self.busy.add(k)
+        nb = self.ex.solver_bytes(S)
+        self.bytes += nb
+        self.misses += 1
+        return S, nb
+
+    def release(self, req):
+        self.busy.discard(plan_key(req))
+
+    def close(self):
+        for S in self.items.values():
+            self.ex.close_solver(S)
+        self.items.clear()
+        self.bytes = 0
+
+
+@dataclass
+class InFlight:
+    req: dict
+    event: object
+    fields: list
+    outputs: list
+    bytes: int
+    admitted: float
+
+
+@dataclass
+class ServeResult:
+    latencies: np.ndarray
+    makespan: float
+    cell_solves: int
+    completed: int
+    outputs: dict = field(default_factory=dict)
+    max_inflight: int = 0
+    admit_order: list = field(default_factory=list)
+    peak_bytes: int = 0
+    plan_hits: int = 0
+    plan_misses: int = 0
+
+    def summary(self) -> dict:
+        lat = self.latencies * 1e3
+        return {"completed": self.completed, "makespan_s": self.makespan,
+                "req_per_s": self.completed / self.makespan if self.makespan else 0.0,
+                "mcell_solves_per_s": self.cell_solves / self.makespan / 1e6 if self.makespan else 0.0,
+                "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
+                "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
+                "max_inflight": self.max_inflight, "peak_bytes": self.peak_bytes,
+                "plan_hits": self.plan_hits, "plan_misses": self.plan_misses}
+
+
+class Server:
+    def __init__(self, executor, hbm_budget_bytes: int, slots: int = 8, keep_outputs: bool = False,
+                 clock=time.perf_counter, idle=lambda: time.sleep(20e-6)):
+        self.ex = executor
+        self.budget = int(hbm_budget_bytes)
+        self.slots = slots
+        self.cache = PlanCache(executor, self.budget // 2)
+        self.keep = keep_outputs
+        self.clock = clock
+        self.idle = idle
+
+    def run(self, requests) -> ServeResult:
+        """Serve requests (dicts with rid, arrival, kind, refined, n, beta, seed;
+        sorted by arrival).  A request that can never fit is rejected up front."""
+        for r in requests:
+            if field_bytes(r["n"], r["kind"]) > self.budget:
+                raise ValueError(f"request {r['rid']} needs more than the HBM budget")
+        pending = collections.deque()
+        inflight = [None] * self.slots
+        used = self.cache.bytes
+        lat, cell_solves, outputs, order = [], 0, {}, []
+        nreq, nxt, done = len(requests), 0, 0
+        max_inflight, peak = 0, used
+        self.ex.synchronize()
+        t0 = self.clock()
+        while done < nreq:
+            now = self.clock() - t0
+            while nxt < nreq and requests[nxt]["arrival"] <= now:
+                pending.append(requests[nxt])
+                nxt += 1
+            progressed = False
+            for s, f in enumerate(inflight):
+                if f is not None and f.event.query():
+                    lat.append(self.clock() - t0 - f.req["arrival"])
+                    if self.keep:
+                        outputs[f.req["rid"]] = self.ex.fetch(f.outputs)
+                    used -= f.bytes
+                    self.cache.release(f.req)
+                    inflight[s] = None
+                    done += 1
+                    progressed = True
+            while pending:
+                s = next((i for i, f in enumerate(inflight) if f is None), None)
+                if s is None:
+                    break
+                req = pending[0]
+                fb = field_bytes(req["n"], req["kind"])
+                if used + fb > self.budget:
+                    break
+                S, nb = self.cache.acquire(req, self.budget - used - fb)
+                if S is None:
+                    break
+                used += nb
+                pending.popleft()
+                ev, fields, outs, cells = self.ex.launch(s, req, S)
+                cell_solves += cells
+                inflight[s] = InFlight(req, ev, fields, outs, fb, self.clock() - t0)
+                used += fb
+                order.append(req["rid"])
+                progressed = True
+                max_inflight = max(max_inflight, sum(f is not None for f in inflight))
+                peak = max(peak, used)
+            if not progressed:
+                self.idle()
+        makespan = self.clock() - t0
+        return ServeResult(np.array(lat), makespan, cell_solves, done, outputs, max_inflight, order,
+                           peak, self.cache.hits, self.cache.misses)
+
+    def run_alone(self, req):
+        """Run one request by itself (for the alone-versus-mixed check)."""
+        S, _ = self.cache.acquire(req, self.budget)
+        ev, fields, outs, _ = self.ex.launch(0, req, S)
+        self.ex.synchronize()
+        self.cache.release(req)
+        return self.ex.fetch(outs)
+
+    def close(self):
+        self.cache.close()
+
+
+def sweep(rates, count: int, seed: int = 5, hbm_budget_gb: float = 96.0, slots: int = 8,
+          nmin: int = 32, nmax: int = 384):
+    """Serve `count` requests at each arrival rate; one summary per rate."""
+    ex = GpuExecutor(slots)
+    out = []
+    for i, rate in enumerate(rates):
+        reqs = synth.serving_requests(rate, count, seed + i, nmin=nmin, nmax=nmax)
+        srv = Server(ex, int(hbm_budget_gb * (1 << 30)), slots)
+        res = srv.run(reqs)
+        d = res.summary()
+        d["rate"] = rate
+        out.append(d)
+        srv.close()
+    return out

@@ -1,0 +1,134 @@
+"""Serving loop scheduling on the CPU with a fake executor and a simulated
+clock: admission by HBM footprint, FIFO order, overlap, plan reuse, and
+host-forced failures."""
+import numpy as np
+import pytest
+
+from paper_2406_19920_amd import serve, synth
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def tick(self):
+        self.t += 1e-4
+
+
+class FakeEvent:
+    def __init__(self, clock, t_done):
+        self.clock, self.t_done = clock, t_done
+
+    def query(self):
+        return self.clock() >= self.t_done
+
+
+class FakeExecutor:
+    """Duration proportional to the cells solved; bytes proportional to n^3."""
+
+    def __init__(self, clock, rate_cells_per_s=1e9, fail_rid=None):
+        self.clock = clock
+        self.rate = rate_cells_per_s
+        self.fail_rid = fail_rid
+        self.running = []
+        self.max_same_plan = 0
+
+    def plan_bytes(self, req):
+        return 8 * req["n"] ** 2 * 4
+
+    def make_solver(self, req):
+        return {"key": serve.plan_key(req), "bytes": self.plan_bytes(req)}
+
+    @staticmethod
+    def solver_bytes(S):
+        return S["bytes"]
+
+    @staticmethod
+    def close_solver(S):
+        S["closed"] = True
+
+    def launch(self, slot, req, S):
+        if req["rid"] == self.fail_rid:
+            raise RuntimeError("injected executor failure")
+        cells = req["n"] ** 3 * (1 if req["kind"] == "poisson" else 3)
+        ev = FakeEvent(self.clock, self.clock() + cells / self.rate)
+        live = [e for e in self.running if not e[0].query()]
+        same = sum(1 for e in live if e[1] == S["key"]) + 1
+        self.max_same_plan = max(self.max_same_plan, same)
+        self.running = live + [(ev, S["key"])]
+        return ev, [], [req["rid"]], cells
+
+    @staticmethod
+    def fetch(outs):
+        return list(outs)
+
+    def synchronize(self):
+        pass
+
+
+def _server(budget=1 << 34, slots=4, **kw):
+    clock = FakeClock()
+    ex = FakeExecutor(clock, **kw)
+    return serve.Server(ex, budget, slots, keep_outputs=True, clock=clock, idle=clock.tick), ex, clock
+
+
+def test_all_complete_fifo_and_overlap():
+    reqs = synth.serving_requests(rate=5000, count=60, seed=3, nmin=32, nmax=128)
+    srv, ex, _ = _server()
+    res = srv.run(reqs)
+    assert res.completed == 60 and len(res.outputs) == 60
+    assert res.admit_order == sorted(res.admit_order)      # FIFO admission
+    assert res.max_inflight > 1                            # continuous batching overlaps
+    assert np.all(res.latencies > 0)
+    s = res.summary()
+    assert s["p99_ms"] >= s["p50_ms"] > 0
+    assert ex.max_same_plan == 1                           # a plan never runs twice at once
+
+
+def test_budget_limits_concurrency():
+    reqs = [dict(rid=i, arrival=0.0, kind="helmholtz", refined=False, n=64, beta=0.1 * i, seed=i)
+            for i in range(6)]
+    one = serve.field_bytes(64, "helmholtz")
+    budget = int(2.5 * one) + 2 * (8 * 64 ** 2 * 4) + (1 << 20)
+    srv, _, _ = _server(budget=budget, slots=6)
+    res = srv.run(reqs)
+    assert res.completed == 6
+    assert res.max_inflight == 2
+    assert res.peak_bytes <= budget
+
+
+def test_plan_reuse_and_lru():
+    reqs = [dict(rid=i, arrival=0.001 * i, kind="poisson", refined=True, n=32, beta=1.0, seed=i)
+            for i in range(5)]
+    srv, _, _ = _server(slots=2)
+    res = srv.run(reqs)
+    assert res.completed == 5
+    assert res.plan_misses == 1 and res.plan_hits == 4
+
+
+def test_over_budget_request_rejected():
+    reqs = [dict(rid=0, arrival=0.0, kind="poisson", refined=False, n=256, beta=0.0, seed=0)]
+    srv, _, _ = _server(budget=1 << 20)
+    with pytest.raises(ValueError):
+        srv.run(reqs)
+
+
+def test_injected_executor_failure_propagates():
+    reqs = synth.serving_requests(rate=1000, count=8, seed=1, nmin=32, nmax=64)
+    srv, _, _ = _server(fail_rid=3)
+    with pytest.raises(RuntimeError, match="injected"):
+        srv.run(reqs)
+
+
+def test_request_generator_recipe():
+    reqs = synth.serving_requests(rate=1000, count=4000, seed=9)
+    arr = np.array([r["arrival"] for r in reqs])
+    assert np.all(np.diff(arr) >= 0)
+    assert abs(len(reqs) / arr[-1] - 1000) < 100            # Poisson rate
+    ns = np.array([r["n"] for r in reqs])
+    assert ns.min() >= 32 and ns.max() <= 384 and np.all(ns % 32 == 0)
+    assert 0.45 < np.mean([r["kind"] == "poisson" for r in reqs]) < 0.55
+    assert 0.45 < np.mean([r["refined"] for r in reqs]) < 0.55
