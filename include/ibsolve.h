@@ -88,7 +88,9 @@ typedef struct {
     int32_t bc_y_vel, bc_y_p; /* ibs_bc                                      */
     int32_t precision;        /* ibs_precision                               */
     double tol;               /* refined path: target ||delta||/||x|| (1e-10 if <= 0) */
-    int32_t max_iter;         /* refined path: solve passes, >= 1 (0: 2)     */
+    int32_t max_iter;         /* refined path: most solve passes, >= 1 (0:
+                                 3 for Poisson, 2 for Helmholtz); passes stop
+                                 early once the predicted error meets tol    */
     int32_t strict_compat;    /* 1: Poisson rhs with nonzero weighted mean
                                  reports IBS_ERR_INCOMPATIBLE_RHS in info    */
 } ibs_grid_desc;

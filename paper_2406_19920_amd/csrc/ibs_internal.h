@@ -29,6 +29,7 @@ struct BlobLayout {
     size_t sz_fwd, sz_inv;   // z transform, bf16x3 split, A-operand swizzle
     size_t bmean;            // per-job weighted mean of the Poisson rhs (4 doubles)
     size_t xsum;             // per-job partial sums of Delta_j x (XSUM_SLOTS each)
+    size_t done;             // per-job refinement stop flags (4 ints)
     size_t red;              // reduction scratch (doubles)
     size_t red_count;        // number of doubles in the reduction scratch
     size_t total;
@@ -132,15 +133,17 @@ struct SplitSet {
 // x transform: in (FP64 when in64, else FP32) -> out (FP32), or, for the
 // inverse (mode 1: x = result, mode 2: x += result with norm partials).
 // pass: refinement pass of an update (mode 2), selecting its partial-sum region.
+// Kernels of pass >= 2 return at once for jobs whose stop flag is set.
 hipError_t launch_split_xgemm(const SplitSet &ss, const Plan &p, bool inverse, bool in64, int mode,
                               int pass, hipStream_t s);
 int max_refine_passes(const SplitSet &ss, const Plan &p);
-hipError_t launch_split_zgemm(const SplitSet &ss, const Plan &p, bool inverse, hipStream_t s);
+hipError_t launch_split_zgemm(const SplitSet &ss, const Plan &p, bool inverse, int pass, hipStream_t s);
 // pass: refinement pass (0 records the rhs mean; later passes steer the
 // Poisson correction so that x + d has zero weighted mean)
 hipError_t launch_tridiag_f32(const JobSet &js, const Plan &p, bool poisson, int pass, hipStream_t s);
-hipError_t launch_residual_f32(const SplitSet &ss, const Plan &p, hipStream_t s);
-hipError_t launch_refine_finalize(const SplitSet &ss, const Plan &p, int passes, hipStream_t s);
+hipError_t launch_residual_f32(const SplitSet &ss, const Plan &p, int pass, hipStream_t s);
+// After pass >= 1: predict the error, write the report, set the stop flag.
+hipError_t launch_refine_check(const SplitSet &ss, const Plan &p, int pass, hipStream_t s);
 
 inline const double *blob_ptr(const Plan &p, size_t off) {
     return reinterpret_cast<const double *>(static_cast<const unsigned char *>(p.dev_const) + off);

@@ -89,8 +89,10 @@ static __device__ __forceinline__ double wave_sum(double v)
 template <int WM, int WN, typename Tin, int MODE>
 __global__ __launch_bounds__(512) void split_xgemm_kernel(SplitSet ss, int nz, int K, int N,
                                                           const b8 *__restrict__ qs, int wgn,
-                                                          double *__restrict__ red)
+                                                          double *__restrict__ red,
+                                                          const int *__restrict__ skip)
 {
+    if (skip && skip[blockIdx.z]) return;   // this job has already converged
     const SplitJob &jb = ss.j[blockIdx.z];
     const int M = nz * jb.rows;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -179,8 +181,10 @@ __global__ __launch_bounds__(512) void split_xgemm_kernel(SplitSet ss, int nz, i
 // nz) and B the field viewed as K x (rows*nx), FP32 in and out.
 template <int WM, int WN>
 __global__ __launch_bounds__(512) void split_zgemm_kernel(SplitSet ss, int M, int K, int nx,
-                                                          const b8 *__restrict__ qs, int wgn)
+                                                          const b8 *__restrict__ qs, int wgn,
+                                                          const int *__restrict__ skip)
 {
+    if (skip && skip[blockIdx.z]) return;
     const SplitJob &jb = ss.j[blockIdx.z];
     const int Ncol = jb.rows * nx;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -246,9 +250,11 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
                                                            const double *__restrict__ dyc,
                                                            const double *__restrict__ dyf,
                                                            const double *__restrict__ bmean,
-                                                           double *__restrict__ xsum)
+                                                           double *__restrict__ xsum,
+                                                           const int *__restrict__ skip)
 {
     const int job = blockIdx.y;
+    if (skip && skip[job]) return;
     const SplitJob &jb = ss.j[job];
     const int op = jb.op, rows = jb.rows;
     const size_t plane = (size_t)rows * nx;
@@ -295,12 +301,15 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
         xsum[(size_t)job * XSUM_SLOTS + blockIdx.x] = sm[0] + sm[1] + sm[2] + sm[3];
 }
 
-// One block per job: sum the update partials of the last pass (and of the
-// pass before, when there was one) in a fixed order and write the report.
-// rel_correction = ||d_last|| / ||x||.  The error of the returned iterate is
-// predicted as rel_correction times the last observed contraction
-// ||d_last|| / ||d_prev|| (d_prev = the first-pass solution when only two
-// passes ran); the status is NOT_CONVERGED when that prediction exceeds tol.
+// After refinement pass p >= 1, one block per job sums the update partials of
+// pass p (and of pass p-1 when p >= 2) in a fixed order.  rel_correction =
+// ||d_p|| / ||x||; the error of the iterate is predicted as rel_correction
+// times the last observed contraction ||d_p|| / ||d_{p-1}|| (d_0 = the
+// first-pass solution, so the ratio is 1 at p = 1).  The report is written
+// and the job's stop flag set when the prediction meets tol; the kernels of
+// later passes then return at once, so the sequence of launches is fixed
+// (graph-capturable) while the work adapts.  Without convergence by the last
+// pass the status stays NOT_CONVERGED.
 static __device__ double2 sum_pairs(const double *r, int n)
 {
     __shared__ double sm[2][4];
@@ -320,27 +329,35 @@ static __device__ double2 sum_pairs(const double *r, int n)
     return t;
 }
 
-__global__ __launch_bounds__(256) void refine_finalize_kernel(SplitSet ss, const double *__restrict__ red_last,
-                                                              const double *__restrict__ red_prev,
-                                                              int slots_per_job, int passes, double tol)
+__global__ __launch_bounds__(256) void refine_check_kernel(SplitSet ss, const double *__restrict__ red_last,
+                                                           const double *__restrict__ red_prev,
+                                                           int slots_per_job, int pass, double tol,
+                                                           int *__restrict__ done)
 {
-    const SplitJob &jb = ss.j[blockIdx.x];
-    const size_t off = (size_t)blockIdx.x * slots_per_job * 2;
+    const int job = blockIdx.x;
+    if (pass >= 2 && done[job]) return;     // stopped earlier: report stands
+    const SplitJob &jb = ss.j[job];
+    const size_t off = (size_t)job * slots_per_job * 2;
     const double2 last = sum_pairs(red_last + off, slots_per_job);
     double rprev = 1.0;
     if (red_prev) {
         const double2 prev = sum_pairs(red_prev + off, slots_per_job);
         rprev = prev.y > 0.0 ? sqrt(prev.x / prev.y) : 0.0;
     }
-    if (threadIdx.x == 0 && jb.info) {
+    if (threadIdx.x == 0) {
         const double rc = last.y > 0.0 ? sqrt(last.x / last.y) : 0.0;
         const double ratio = rprev > 0.0 ? fmin(1.0, rc / rprev) : 1.0;
         const double predicted = rc * ratio;
-        ibs_solve_info *inf = static_cast<ibs_solve_info *>(jb.info);
-        inf->iters = passes;
-        inf->rel_correction = rc;
-        inf->rel_residual = predicted;
-        if (inf->status == IBS_OK && !(predicted <= tol)) inf->status = IBS_ERR_NOT_CONVERGED;
+        const bool ok = predicted <= tol;
+        done[job] = ok ? 1 : 0;
+        if (jb.info) {
+            ibs_solve_info *inf = static_cast<ibs_solve_info *>(jb.info);
+            const int base = inf->status == IBS_ERR_NOT_CONVERGED ? IBS_OK : inf->status;
+            inf->iters = pass + 1;
+            inf->rel_correction = rc;
+            inf->rel_residual = predicted;
+            inf->status = (base == IBS_OK && !ok) ? IBS_ERR_NOT_CONVERGED : base;
+        }
     }
 }
 
@@ -366,6 +383,7 @@ static size_t update_slots(const SplitSet &ss, const Plan &p);
 hipError_t launch_split_xgemm(const SplitSet &ss, const Plan &p, bool inverse, bool in64, int mode,
                               int pass, hipStream_t s)
 {
+    const int *skip = pass >= 2 ? reinterpret_cast<const int *>(blob_ptr(p, p.lay.done)) : nullptr;
     constexpr int WM = 4, WN = 4;
     int wgn;
     dim3 grid;
@@ -379,22 +397,23 @@ hipError_t launch_split_xgemm(const SplitSet &ss, const Plan &p, bool inverse, b
     if (in64) {
         if (mode != 0) return hipErrorInvalidValue;
         hipLaunchKernelGGL((split_xgemm_kernel<WM, WN, double, 0>), grid, dim3(512), 0, s, ss, p.nz,
-                           p.nx, p.nx, qs, wgn, red);
+                           p.nx, p.nx, qs, wgn, red, skip);
     } else if (mode == 0) {
         hipLaunchKernelGGL((split_xgemm_kernel<WM, WN, float, 0>), grid, dim3(512), 0, s, ss, p.nz,
-                           p.nx, p.nx, qs, wgn, red);
+                           p.nx, p.nx, qs, wgn, red, skip);
     } else if (mode == 1) {
         hipLaunchKernelGGL((split_xgemm_kernel<WM, WN, float, 1>), grid, dim3(512), 0, s, ss, p.nz,
-                           p.nx, p.nx, qs, wgn, red);
+                           p.nx, p.nx, qs, wgn, red, skip);
     } else {
         hipLaunchKernelGGL((split_xgemm_kernel<WM, WN, float, 2>), grid, dim3(512), 0, s, ss, p.nz,
-                           p.nx, p.nx, qs, wgn, red);
+                           p.nx, p.nx, qs, wgn, red, skip);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_split_zgemm(const SplitSet &ss, const Plan &p, bool inverse, hipStream_t s)
+hipError_t launch_split_zgemm(const SplitSet &ss, const Plan &p, bool inverse, int pass, hipStream_t s)
 {
+    const int *skip = pass >= 2 ? reinterpret_cast<const int *>(blob_ptr(p, p.lay.done)) : nullptr;
     constexpr int WM = 4, WN = 4;
     const int M = p.nz;
     const int Ncol = max_rows(ss) * p.nx;
@@ -404,16 +423,18 @@ hipError_t launch_split_zgemm(const SplitSet &ss, const Plan &p, bool inverse, h
     dim3 grid((Ncol + 16 * WN * wgn - 1) / (16 * WN * wgn), (M + 16 * WM * wgm - 1) / (16 * WM * wgm),
               ss.n);
     const b8 *qs = reinterpret_cast<const b8 *>(blob_ptr(p, inverse ? p.lay.sz_inv : p.lay.sz_fwd));
-    hipLaunchKernelGGL((split_zgemm_kernel<WM, WN>), grid, dim3(512), 0, s, ss, M, M, p.nx, qs, wgn);
+    hipLaunchKernelGGL((split_zgemm_kernel<WM, WN>), grid, dim3(512), 0, s, ss, M, M, p.nx, qs, wgn, skip);
     return hipGetLastError();
 }
 
-hipError_t launch_residual_f32(const SplitSet &ss, const Plan &p, hipStream_t s)
+hipError_t launch_residual_f32(const SplitSet &ss, const Plan &p, int pass, hipStream_t s)
 {
+    const int *skip = pass >= 2 ? reinterpret_cast<const int *>(blob_ptr(p, p.lay.done)) : nullptr;
     dim3 grid(XSUM_SLOTS, ss.n);
     hipLaunchKernelGGL(residual_f32_kernel, grid, dim3(256), 0, s, ss, p.nx, p.ny, p.nz,
                        1.0 / (p.hx * p.hx), 1.0 / (p.hz * p.hz), blob_ptr(p, p.lay.dyc),
-                       blob_ptr(p, p.lay.dyf), blob_ptr(p, p.lay.bmean), blob_mut(p, p.lay.xsum));
+                       blob_ptr(p, p.lay.dyf), blob_ptr(p, p.lay.bmean), blob_mut(p, p.lay.xsum),
+                       skip);
     return hipGetLastError();
 }
 
@@ -430,7 +451,7 @@ int max_refine_passes(const SplitSet &ss, const Plan &p)
     return (int)(p.lay.red_count / (2 * update_slots(ss, p))) + 1;
 }
 
-hipError_t launch_refine_finalize(const SplitSet &ss, const Plan &p, int passes, hipStream_t s)
+hipError_t launch_refine_check(const SplitSet &ss, const Plan &p, int pass, hipStream_t s)
 {
     int wgn;
     dim3 grid;
@@ -438,10 +459,10 @@ hipError_t launch_refine_finalize(const SplitSet &ss, const Plan &p, int passes,
     const int per_job = (int)(grid.x * grid.y);
     const size_t region = 2 * (size_t)grid.x * grid.y * grid.z;
     const double *red = blob_ptr(p, p.lay.red);
-    const double *last = red + (size_t)(passes - 2) * region;
-    const double *prev = passes >= 3 ? red + (size_t)(passes - 3) * region : nullptr;
-    hipLaunchKernelGGL(refine_finalize_kernel, dim3(ss.n), dim3(256), 0, s, ss, last, prev, per_job,
-                       passes, p.desc.tol);
+    const double *last = red + (size_t)(pass - 1) * region;
+    const double *prev = pass >= 2 ? red + (size_t)(pass - 2) * region : nullptr;
+    hipLaunchKernelGGL(refine_check_kernel, dim3(ss.n), dim3(256), 0, s, ss, last, prev, per_job,
+                       pass, p.desc.tol, reinterpret_cast<int *>(blob_mut(p, p.lay.done)));
     return hipGetLastError();
 }
 

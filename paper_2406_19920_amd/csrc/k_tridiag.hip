@@ -45,6 +45,7 @@ struct TriParams {
     double *bmean;      // per job: weighted mean removed from the rhs (Poisson)
     const double *xsum; // per job: XSUM_SLOTS partial sums of Delta_j x, or null
     int record_mean;    // write bmean (first pass of a solve)
+    const int *skip;    // per job: refinement already stopped (later passes), or null
     double wsum_y;      // sum of Delta_j
     int nx, nz;
     int poisson;
@@ -99,6 +100,7 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
         const int c = rem / ntx, a0 = (rem - c * ntx) * TA;
         const FieldJob &jb = js.j[job];
         const int n = jb.rows, kind = jb.kind;
+        if (tp.skip && tp.skip[job]) continue;   // block-uniform: the whole tile is skipped
         __syncthreads();  // the previous tile's LDS is no longer read
         if (job != cur_job) {
             // rows of the job's operator without the pencil shift:
@@ -311,6 +313,7 @@ static hipError_t launch_tridiag(const JobSet &js, const Plan &p, bool poisson, 
     tp.bmean = blob_mut(p, p.lay.bmean);
     tp.xsum = nullptr;
     tp.record_mean = 1;
+    tp.skip = nullptr;
     tp.wsum_y = 0.0;
     for (int j = 0; j < p.ny; ++j) tp.wsum_y += p.dyc[j];
     tp.nx = p.nx;
@@ -321,6 +324,7 @@ static hipError_t launch_tridiag(const JobSet &js, const Plan &p, bool poisson, 
         tp.record_mean = 0;
         tp.xsum = blob_ptr(p, p.lay.xsum);
     }
+    if (pass >= 2) tp.skip = reinterpret_cast<const int *>(blob_ptr(p, p.lay.done));
     tp.inv_sqrt_nxnz = 1.0 / std::sqrt((double)p.nx * (double)p.nz);
     int n = 0;
     for (int q = 0; q < js.n; ++q) n = js.j[q].rows > n ? js.j[q].rows : n;

@@ -249,6 +249,7 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     L.sz_inv = take(split ? sizeof(uint16_t) * 3 * nz * nz : 0);
     L.bmean = take(sizeof(double) * 4);
     L.xsum = take(sizeof(double) * 4 * XSUM_SLOTS);
+    L.done = take(sizeof(int) * 4);
     L.red_count = 131072;
     L.red = take(sizeof(double) * L.red_count);
     L.total = o;
