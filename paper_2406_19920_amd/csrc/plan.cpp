@@ -24,18 +24,24 @@ static void fourier_basis(int N, double h, std::vector<double> &Q, std::vector<d
     const long double s0 = 1.0L / std::sqrt((long double)N);
     const long double s1 = std::sqrt(2.0L / (long double)N);
     const int half = N / 2;
+    // only N distinct angles 2 pi m / N occur (m = k i mod N)
+    std::vector<long double> ct(N), st(N);
+    for (int m = 0; m < N; ++m) {
+        const long double th = 2.0L * pi * (long double)m / (long double)N;
+        ct[m] = std::cos(th);
+        st[m] = std::sin(th);
+    }
     for (int a = 0; a < N; ++a) {
         int k = (a <= half) ? a : a - half;
         long double sk = std::sin(pi * (long double)k / (long double)N);
         lam[a] = (double)(-(4.0L / ((long double)h * h)) * sk * sk);
         for (int i = 0; i < N; ++i) {
+            const int m = (int)(((long long)k * i) % N);
             long double v;
-            long long ki = ((long long)k * i) % N;
-            long double th = 2.0L * pi * (long double)ki / (long double)N;
             if (a == 0) v = s0;
-            else if (a < half) v = s1 * std::cos(th);
+            else if (a < half) v = s1 * ct[m];
             else if (a == half) v = (i % 2 == 0) ? s0 : -s0;
-            else v = s1 * std::sin(th);
+            else v = s1 * st[m];
             Q[size_t(i) * N + a] = (double)v;
         }
     }
@@ -66,61 +72,62 @@ static void swizzle_a(const double *A, int M, int K, double *out)
                     out[o++] = A[size_t(16 * bi + (l % 16)) * K + 16 * kc + 4 * (l / 16) + t];
 }
 
-// Round a double to the nearest bfloat16 value (8 significant bits, ties to
-// even), returned as a double.
-static double round_bf16(double v)
+// bfloat16 bits of a float, rounded to nearest even (finite inputs).
+static uint16_t bf16_rne(float f)
 {
-    if (v == 0.0 || !std::isfinite(v)) return v;
-    int e;
-    double m = std::frexp(v, &e);              // v = m 2^e, 0.5 <= |m| < 1
-    return std::ldexp(std::nearbyint(std::ldexp(m, 8)), e - 8);
-}
-static uint16_t bf16_bits(double v)            // v exactly representable
-{
-    float f = (float)v;
     uint32_t u;
     std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
 }
-// Three-term bfloat16 split v = t0 + t1 + t2 (+ O(2^-24 |v|)).
+static double bf16_value(uint16_t b)
+{
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return (double)f;
+}
+// Three-term bfloat16 split v = t0 + t1 + t2 (+ O(2^-24 |v|)); every
+// remainder is formed exactly in double.
 static void split3(double v, uint16_t t[3])
 {
-    double h0 = round_bf16(v), r1 = v - h0;
-    double h1 = round_bf16(r1), r2 = r1 - h1;
-    double h2 = round_bf16(r2);
-    t[0] = bf16_bits(h0);
-    t[1] = bf16_bits(h1);
-    t[2] = bf16_bits(h2);
+    double r = v;
+    for (int q = 0; q < 3; ++q) {
+        t[q] = bf16_rne((float)r);
+        r -= bf16_value(t[q]);
+    }
+}
+static std::vector<uint16_t> split_all(const double *M, size_t n)
+{
+    std::vector<uint16_t> out(3 * n);
+    for (size_t i = 0; i < n; ++i) split3(M[i], &out[3 * i]);
+    return out;
 }
 // Swizzle for the 16x16x32 bf16 matrix-core instruction, B operand (K x N):
 // per 32-deep chunk kc and 16-wide column block bj, per split term t, lane l
 // holds B[32 kc + 8 (l/16) + e][16 bj + l%16], e = 0..7 (16 bytes).
 static void swizzle_b_split(const double *B, int K, int N, uint16_t *out)
 {
+    const std::vector<uint16_t> sp = split_all(B, size_t(K) * N);
     size_t o = 0;
-    uint16_t tt[3];
     for (int kc = 0; kc < K / 32; ++kc)
         for (int bj = 0; bj < N / 16; ++bj)
             for (int t = 0; t < 3; ++t)
                 for (int l = 0; l < 64; ++l)
-                    for (int e = 0; e < 8; ++e) {
-                        split3(B[size_t(32 * kc + 8 * (l / 16) + e) * N + 16 * bj + (l % 16)], tt);
-                        out[o++] = tt[t];
-                    }
+                    for (int e = 0; e < 8; ++e)
+                        out[o++] = sp[3 * (size_t(32 * kc + 8 * (l / 16) + e) * N + 16 * bj + (l % 16)) + t];
 }
 // A operand (M x K): lane l holds A[16 bi + l%16][32 kc + 8 (l/16) + e].
 static void swizzle_a_split(const double *A, int M, int K, uint16_t *out)
 {
+    const std::vector<uint16_t> sp = split_all(A, size_t(M) * K);
     size_t o = 0;
-    uint16_t tt[3];
     for (int kc = 0; kc < K / 32; ++kc)
         for (int bi = 0; bi < M / 16; ++bi)
             for (int t = 0; t < 3; ++t)
                 for (int l = 0; l < 64; ++l)
-                    for (int e = 0; e < 8; ++e) {
-                        split3(A[size_t(16 * bi + (l % 16)) * K + 32 * kc + 8 * (l / 16) + e], tt);
-                        out[o++] = tt[t];
-                    }
+                    for (int e = 0; e < 8; ++e)
+                        out[o++] = sp[3 * (size_t(16 * bi + (l % 16)) * K + 32 * kc + 8 * (l / 16) + e) + t];
 }
 
 ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)

@@ -227,12 +227,15 @@ def ibs_batch_destroy(batch: int):
 class Solver:
     """One plan plus the device buffers it needs (torch allocations)."""
 
-    def __init__(self, nx, ny, nz, device="cuda", **kw):
+    def __init__(self, nx, ny, nz, device="cuda", plan=None, alloc_work=True, **kw):
+        """plan: an already built handle for the same description (ownership
+        passes to the Solver); built here when None.  alloc_work=False leaves
+        the workspace to the caller (set .work and .work_bytes before use)."""
         import torch
         self.torch = torch
         self.desc = make_desc(nx, ny, nz, **kw)
         self.nx, self.ny, self.nz = nx, ny, nz
-        self.plan = solver_plan(self.desc)
+        self.plan = plan if plan is not None else solver_plan(self.desc)
         dv = torch.device(device)
         if dv.type == "cuda" and dv.index is None:
             dv = torch.device("cuda", torch.cuda.current_device())
@@ -240,10 +243,11 @@ class Solver:
         cb, self.work_p = solver_plan_bytes(self.plan, IBS_OP_POISSON)
         _, self.work_h = solver_plan_bytes(self.plan, IBS_OP_HELMHOLTZ_U, 3)
         self.const = torch.empty(cb, dtype=torch.uint8, device=self.device)
-        self.work = torch.empty(max(self.work_p, self.work_h), dtype=torch.uint8, device=self.device)
+        self.work = (torch.empty(max(self.work_p, self.work_h), dtype=torch.uint8, device=self.device)
+                     if alloc_work else None)
         self.info = torch.zeros((8, INFO_BYTES // 8), dtype=torch.float64, device=self.device)
         solver_plan_upload(self.plan, self.const.data_ptr(), cb, self.stream())
-        self.work_bytes = self.work.numel()
+        self.work_bytes = self.work.numel() if self.work is not None else 0
 
     def stream(self) -> int:
         return self.torch.cuda.current_stream(self.device).cuda_stream

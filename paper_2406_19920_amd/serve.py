@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import collections
 import time
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -40,7 +41,7 @@ def plan_key(req):
 class GpuExecutor:
     """Runs requests through the C ABI on per-slot HIP streams."""
 
-    def __init__(self, slots: int, device="cuda"):
+    def __init__(self, slots: int, device="cuda", nmax: int = 384):
         import torch
         from . import ibsolve
         self.torch, self.ibs = torch, ibsolve
@@ -48,24 +49,36 @@ class GpuExecutor:
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
+        # one workspace per slot, sized for the largest request (a plan then
+        # holds only its constants; the workspace is needed only while a
+        # request runs, and a slot runs one request at a time)
+        self.work_bytes = 3 * 8 * nmax * (nmax + 1) * nmax
+        self.slot_work = [torch.empty(self.work_bytes, dtype=torch.uint8, device=self.device)
+                          for _ in range(slots)]
 
-    def plan_bytes(self, req) -> int:
+    def prepare(self, req):
+        """Host-only plan build (thread-safe; the C call releases the GIL).
+        Returns (plan handle, device bytes the plan will need)."""
         ibs = self.ibs
         n = req["n"]
         prec = ibs.IBS_REFINED_BF16X3 if req["refined"] else ibs.IBS_FP64
         plan = ibs.solver_plan(ibs.make_desc(n, n, n, beta=req["beta"], precision=prec))
-        try:
-            cb, wp = ibs.solver_plan_bytes(plan, ibs.IBS_OP_POISSON)
-            _, wh = ibs.solver_plan_bytes(plan, ibs.IBS_OP_HELMHOLTZ_U, 3)
-        finally:
+        cb, wp = ibs.solver_plan_bytes(plan, ibs.IBS_OP_POISSON)
+        _, wh = ibs.solver_plan_bytes(plan, ibs.IBS_OP_HELMHOLTZ_U, 3)
+        if max(wp, wh) > self.work_bytes:
             ibs.solver_plan_destroy(plan)
-        return cb + max(wp, wh)
+            raise ValueError(f"request n={n} exceeds the slot workspace")
+        return plan, cb
 
-    def make_solver(self, req):
+    def discard(self, prepared):
+        self.ibs.solver_plan_destroy(prepared[0])
+
+    def make_solver(self, req, prepared):
         ibs = self.ibs
         n = req["n"]
         prec = ibs.IBS_REFINED_BF16X3 if req["refined"] else ibs.IBS_FP64
-        S = ibs.Solver(n, n, n, beta=req["beta"], precision=prec, device=self.device)
+        S = ibs.Solver(n, n, n, beta=req["beta"], precision=prec, device=self.device,
+                       plan=prepared[0], alloc_work=False)
         # the constants were copied on the current stream; make them visible
         # to the slot streams before first use
         self.torch.cuda.current_stream(self.device).synchronize()
@@ -73,7 +86,7 @@ class GpuExecutor:
 
     @staticmethod
     def solver_bytes(S) -> int:
-        return S.const.numel() + S.work.numel()
+        return S.const.numel()
 
     @staticmethod
     def close_solver(S):
@@ -85,6 +98,7 @@ class GpuExecutor:
         torch = self.torch
         stream = self.streams[slot]
         n = req["n"]
+        S.work, S.work_bytes = self.slot_work[slot], self.work_bytes
         with torch.cuda.stream(stream):
             if req["kind"] == "poisson":
                 b = synth.device_normal(S.shape(0), req["seed"], self.device)
@@ -114,9 +128,10 @@ class GpuExecutor:
 
 class PlanCache:
     """LRU cache of resident plans.  A cached plan is lent to one request at
-    a time (its workspace and scratch are single-use)."""
+    a time (its workspace and scratch are single-use).  Host-side plan
+    builds for waiting requests run ahead on a worker pool."""
 
-    def __init__(self, executor, capacity_bytes: int):
+    def __init__(self, executor, capacity_bytes: int, workers: int = 4):
         self.ex = executor
         self.capacity = capacity_bytes
         self.items = collections.OrderedDict()   # key -> solver
@@ -124,6 +139,20 @@ class PlanCache:
         self.bytes = 0
         self.hits = 0
         self.misses = 0
+        self.pool = ThreadPoolExecutor(workers) if workers > 0 else None
+        self.futures = {}                         # key -> future of a prepared plan
+
+    def prefetch(self, req):
+        k = plan_key(req)
+        if k in self.items or k in self.futures:
+            return
+        if self.pool is not None:
+            self.futures[k] = self.pool.submit(self.ex.prepare, req)
+
+    def _prepared(self, req):
+        k = plan_key(req)
+        fut = self.futures.pop(k, None)
+        return fut.result() if fut is not None else self.ex.prepare(req)
 
     def acquire(self, req, budget_left: int):
         """(solver, bytes newly resident) or (None, 0) when it cannot be placed now."""
@@ -136,17 +165,19 @@ class PlanCache:
             self.busy.add(k)
             self.hits += 1
             return S, 0
-        need = self.ex.plan_bytes(req)
+        prepared = self._prepared(req)
+        need = prepared[1]
         while self.bytes + need > self.capacity or need > budget_left:
             victim = next((kk for kk in self.items if kk not in self.busy), None)
             if victim is None:
+                self.futures[k] = _Done(prepared)     # keep it for the next attempt
                 return None, 0
             old = self.items.pop(victim)
             nb = self.ex.solver_bytes(old)
             self.bytes -= nb
             budget_left += nb
             self.ex.close_solver(old)
-        S = self.ex.make_solver(req)
+        S = self.ex.make_solver(req, prepared)
         self.items[k] = S
         self.busy.add(k)
         nb = self.ex.solver_bytes(S)
@@ -162,6 +193,21 @@ class PlanCache:
             self.ex.close_solver(S)
         self.items.clear()
         self.bytes = 0
+        for fut in self.futures.values():
+            self.ex.discard(fut.result())
+        self.futures.clear()
+        if self.pool is not None:
+            self.pool.shutdown(wait=True)
+
+
+class _Done:
+    """An already available result with the future interface."""
+
+    def __init__(self, v):
+        self.v = v
+
+    def result(self):
+        return self.v
 
 
 @dataclass
@@ -200,11 +246,11 @@ class ServeResult:
 
 class Server:
     def __init__(self, executor, hbm_budget_bytes: int, slots: int = 8, keep_outputs: bool = False,
-                 clock=time.perf_counter, idle=lambda: time.sleep(20e-6)):
+                 clock=time.perf_counter, idle=lambda: time.sleep(20e-6), plan_workers: int = 4):
         self.ex = executor
         self.budget = int(hbm_budget_bytes)
         self.slots = slots
-        self.cache = PlanCache(executor, self.budget // 2)
+        self.cache = PlanCache(executor, self.budget // 2, plan_workers)
         self.keep = keep_outputs
         self.clock = clock
         self.idle = idle
@@ -227,6 +273,7 @@ class Server:
             now = self.clock() - t0
             while nxt < nreq and requests[nxt]["arrival"] <= now:
                 pending.append(requests[nxt])
+                self.cache.prefetch(requests[nxt])
                 nxt += 1
             progressed = False
             for s, f in enumerate(inflight):

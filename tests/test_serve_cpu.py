@@ -36,11 +36,14 @@ class FakeExecutor:
         self.running = []
         self.max_same_plan = 0
 
-    def plan_bytes(self, req):
-        return 8 * req["n"] ** 2 * 4
+    def prepare(self, req):
+        return ("plan", 8 * req["n"] ** 2 * 4)
 
-    def make_solver(self, req):
-        return {"key": serve.plan_key(req), "bytes": self.plan_bytes(req)}
+    def discard(self, prepared):
+        pass
+
+    def make_solver(self, req, prepared):
+        return {"key": serve.plan_key(req), "bytes": prepared[1]}
 
     @staticmethod
     def solver_bytes(S):
@@ -72,7 +75,8 @@ class FakeExecutor:
 def _server(budget=1 << 34, slots=4, **kw):
     clock = FakeClock()
     ex = FakeExecutor(clock, **kw)
-    return serve.Server(ex, budget, slots, keep_outputs=True, clock=clock, idle=clock.tick), ex, clock
+    return serve.Server(ex, budget, slots, keep_outputs=True, clock=clock, idle=clock.tick,
+                        plan_workers=0), ex, clock
 
 
 def test_all_complete_fifo_and_overlap():
