@@ -81,7 +81,7 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--beta", type=float, default=2.0)
     ap.add_argument("--path", choices=["refined", "fp64", "both"], default="both")
-    ap.add_argument("--cpu-sample", type=int, default=128)
+    ap.add_argument("--cpu-sample", type=int, default=160)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--config", choices=["c2", "c3", "batch", "serve"], default="c2",
                     help="c2: 256^3 step (default); c3: 512x384x384 refined step with a forcing "
