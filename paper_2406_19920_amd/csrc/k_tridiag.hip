@@ -75,9 +75,9 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
     const int s = k * M;
     const bool pois = tp.poisson != 0;
 
-    double pf[M];
-    auto fetch = [&](int tile) {
+    auto fetch = [&](int tile, double (&pf)[M]) {
         const int job = tile / (tp.nz * ntx);
+        if (tp.skip && tp.skip[job]) return;   // converged job: nothing to load
         const int rem = tile - job * tp.nz * ntx;
         const int c = rem / ntx, a0 = (rem - c * ntx) * TA;
         const FieldJob &jb = js.j[job];
@@ -91,16 +91,20 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
         }
     };
 
-    int tile = blockIdx.x;
-    if (tile < ntiles) fetch(tile);
+    // two register buffers: the tile two steps ahead is in flight while the
+    // current one is solved (HBM latency is long next to one tile's work)
+    double pfa[M], pfb[M];
     int cur_job = -1;
-    for (; tile < ntiles; tile += gridDim.x) {
+    auto process = [&](const int tile, double (&pf)[M]) {
         const int job = tile / (tp.nz * ntx);
         const int rem = tile - job * tp.nz * ntx;
         const int c = rem / ntx, a0 = (rem - c * ntx) * TA;
         const FieldJob &jb = js.j[job];
         const int n = jb.rows, kind = jb.kind;
-        if (tp.skip && tp.skip[job]) continue;   // block-uniform: the whole tile is skipped
+        if (tp.skip && tp.skip[job]) {   // block-uniform: the whole tile is skipped
+            if (tile + 2 * (int)gridDim.x < ntiles) fetch(tile + 2 * gridDim.x, pf);
+            return;
+        }
         __syncthreads();  // the previous tile's LDS is no longer read
         if (job != cur_job) {
             // rows of the job's operator without the pencil shift:
@@ -121,17 +125,17 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
 #pragma unroll
         for (int r = 0; r < M; ++r) sx[(lrow + P * r) * LDR + lcol] = pf[r];
         __syncthreads();
-        if (tile + (int)gridDim.x < ntiles) fetch(tile + gridDim.x);  // overlaps the solve
-
+        if (tile + 2 * (int)gridDim.x < ntiles) fetch(tile + 2 * gridDim.x, pf);  // two tiles ahead
+    
         const int a = a0 + p;
         const double sh = tp.lam_x[a] + tp.lam_z[c];
         const double sadd = pois ? sh : -jb.c * sh;   // pencil shift of the diagonal
         const bool pinned = pois && a == 0 && c == 0;
-
+    
         double r[M];
 #pragma unroll
         for (int t = 0; t < M; ++t) r[t] = sx[(s + t) * LDR + p];
-
+    
         double removed = 0.0, rms = 0.0;
         if (pinned) {
             // compatibility: remove the volume-weighted mean of this pencil's rhs
@@ -156,14 +160,14 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
                 if (s + t < n) r[t] -= mean;
             if (k == 0) r[0] = 0.0;  // pin the first point
         }
-
+    
         auto coef = [&](int j, double &A, double &B, double &C) {
             const bool real = j < n && !(pinned && j == 0);
             A = real ? slo[j] : 0.0;
             B = real ? sdi[j] + sadd : 1.0;
             C = real ? sup[j] : 0.0;
         };
-
+    
         // down-sweep: rows s+1 .. s+M-1 in the form al x_s + x_j + ga x_{j+1} = rho
         double al[M], ga[M];
         {
@@ -199,7 +203,7 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
             mu_u = C * br * inv;
             sig_u = (r[0] - C * bp) * inv;
         }
-
+    
         // reduced system in z_k = x_{last row of chunk k}
         double lam1 = __shfl_down(lam_u, 1, P), mu1 = __shfl_down(mu_u, 1, P),
                sig1 = __shfl_down(sig_u, 1, P);
@@ -227,13 +231,13 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
         double zm = __shfl_up(z, 1, P);
         if (k == 0) zm = 0.0;
         const double xs = sig_u - lam_u * zm - mu_u * z;
-
+    
         // interior back-substitution, in place: r[t] becomes x[t]
         r[M - 1] = z;
 #pragma unroll
         for (int t = M - 2; t >= 1; --t) r[t] = r[t] - al[t] * xs - ga[t] * r[t + 1];
         r[0] = xs;
-
+    
         if (pinned) {
             // null mode: zero volume-weighted mean
             double swx = 0.0, sww = 0.0;
@@ -264,7 +268,7 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
         }
 #pragma unroll
         for (int t = 0; t < M; ++t) sx[(s + t) * LDR + p] = r[t];
-
+    
         if (pinned && k == 0 && tp.record_mean) tp.bmean[job] = removed * tp.inv_sqrt_nxnz;
         if (a0 == 0 && c == 0 && tid == 0 && jb.info) {
             ibs_solve_info *inf = static_cast<ibs_solve_info *>(jb.info);
@@ -283,6 +287,13 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
             const int j = lrow + P * r2;
             if (j < n) base[(size_t)j * nx] = (T)sx[j * LDR + lcol];
         }
+    };
+    const int G = gridDim.x;
+    if ((int)blockIdx.x < ntiles) fetch(blockIdx.x, pfa);
+    if ((int)blockIdx.x + G < ntiles) fetch(blockIdx.x + G, pfb);
+    for (int tile = blockIdx.x; tile < ntiles; tile += 2 * G) {
+        process(tile, pfa);
+        if (tile + G < ntiles) process(tile + G, pfb);
     }
 }
 
@@ -328,8 +339,8 @@ static hipError_t launch_tridiag(const JobSet &js, const Plan &p, bool poisson, 
     tp.inv_sqrt_nxnz = 1.0 / std::sqrt((double)p.nx * (double)p.nz);
     int n = 0;
     for (int q = 0; q < js.n; ++q) n = js.j[q].rows > n ? js.j[q].rows : n;
-    // 16 lanes per pencil up to 144 rows, then 32 (keeps the per-lane chunk
-    // short, so the chunk arrays stay in registers at useful occupancy)
+    // lanes per pencil and rows per lane: short chunks keep the per-lane
+    // arrays in registers
     if (n <= 48) return launch_pm<T, 16, 3>(js, tp, s);
     if (n <= 80) return launch_pm<T, 16, 5>(js, tp, s);
     if (n <= 112) return launch_pm<T, 16, 7>(js, tp, s);
