@@ -76,7 +76,8 @@ typedef enum { IBS_PERIODIC = 0, IBS_DIRICHLET = 1, IBS_NEUMANN = 2 } ibs_bc;
 /* Problem description.  Grid: nx*ny*nz cells on [0,lx]x[0,ly]x[0,lz];
  * hx = lx/nx, hz = lz/nz; y faces y_f[j] = (ly/2)(1 + tanh(beta(2j/ny-1))/
  * tanh(beta)), j = 0..ny (beta = 0: uniform), unless y_faces is given.
- * Supported: nx, nz multiples of 16 in [16, 1024]; ny in [2, 768];
+ * Supported: nx, nz multiples of 16 in [16, 1024] (refined path: multiples
+ * of 32, at most 512); ny in [2, 768];
  * bc_x = bc_z = IBS_PERIODIC; bc_y_vel = IBS_DIRICHLET; bc_y_p = IBS_NEUMANN. */
 typedef struct {
     int32_t nx, ny, nz;

@@ -113,7 +113,7 @@ hipError_t launch_residual(const Plan &p, int op, double c, const double *x,
                            const double *b, double *r, double *norms2, hipStream_t s);
 
 // ---- refined (split-precision) path ---------------------------------------
-constexpr int XSUM_SLOTS = 1024;   // residual blocks per job (fixed: deterministic sums)
+constexpr int XSUM_SLOTS = 4096;   // max residual blocks per job (fixed order: deterministic sums)
 struct SplitJob {
     const void *in;     // x transforms: FP64 (first pass) or FP32 input rows
     float *out;         // FP32 output (forward passes, z passes)
@@ -142,6 +142,7 @@ hipError_t launch_split_zgemm(const SplitSet &ss, const Plan &p, bool inverse, i
 // Poisson correction so that x + d has zero weighted mean)
 hipError_t launch_tridiag_f32(const JobSet &js, const Plan &p, bool poisson, int pass, hipStream_t s);
 hipError_t launch_residual_f32(const SplitSet &ss, const Plan &p, int pass, hipStream_t s);
+int residual_tiles(const Plan &p);   // residual blocks (x-sum partials) per job
 // After pass >= 1: predict the error, write the report, set the stop flag.
 hipError_t launch_refine_check(const SplitSet &ss, const Plan &p, int pass, hipStream_t s);
 

@@ -16,6 +16,8 @@
 // the host in exactly that order.
 #include "ibs_internal.h"
 
+#include <algorithm>
+
 namespace ibs {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -39,6 +41,10 @@ static __device__ __forceinline__ f4 mma3(const b8 *a, const b8 *b, f4 c)
     c = mma(a[0], b[0], c);
     return c;
 }
+
+// The six partial products of a three-term split, small ones first.
+static constexpr int TA_[6] = {2, 0, 1, 1, 0, 0};
+static constexpr int TB_[6] = {0, 2, 1, 0, 1, 0};
 
 static __device__ __forceinline__ void split8(const float *v, b8 *t)
 {
@@ -82,80 +88,146 @@ static __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// x transform, C = A B with A = rows of the field (M = nz*rows, K = nx),
-// B the split swizzled transform (K x N).  MODE 0: FP32 out; MODE 1: FP64
-// x = C; MODE 2: FP64 x += C and per-block sums of C^2 and x^2 into red.
-// Workgroup: 8 waves laid out wgm x wgn, each owning (16 WM) x (16 WN).
-template <int WM, int WN, typename Tin, int MODE>
+// ---------------------------------------------------------------------------
+// Transform kernels.  Both keep the streamed field in registers: every data
+// element is loaded from HBM and split by exactly one wave.  The transform
+// matrix is shared: per 32-deep K chunk, the workgroup copies the chunk of
+// the pre-split, pre-swizzled matrix (NBT 16-blocks x 3 terms x 64 lanes x
+// 16 bytes) into LDS (double-buffered when it fits), and every wave reads
+// its fragments from there.  The next chunk's matrix and data are loaded
+// while the current chunk is multiplied.
+// ---------------------------------------------------------------------------
+
+// Copy `cnt` 16-byte fragments (global, contiguous) into registers / LDS.
+template <int PER>
+static __device__ __forceinline__ void q_load(const b8 *__restrict__ src, int cnt, b8 (&r)[PER])
+{
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = threadIdx.x + u * 512;
+        if (idx < cnt) r[u] = src[idx];
+    }
+}
+template <int PER>
+static __device__ __forceinline__ void q_store(b8 *__restrict__ dst, int cnt, const b8 (&r)[PER])
+{
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = threadIdx.x + u * 512;
+        if (idx < cnt) dst[idx] = r[u];
+    }
+}
+
+// x transform: C = A B, A = the field's rows (M = nz*rows, K = nx), B the
+// split swizzled nx x nx matrix.  A wave owns WM row blocks (16 rows each)
+// and all N = 16 NB columns (NB <= NBT).  MODE 0: FP32 out; MODE 1: FP64
+// x = C; MODE 2: FP64 x += C with per-block sums of C^2 and x^2 into red.
+template <int NBT, int WM, typename Tin, int MODE>
 __global__ __launch_bounds__(512) void split_xgemm_kernel(SplitSet ss, int nz, int K, int N,
-                                                          const b8 *__restrict__ qs, int wgn,
+                                                          const b8 *__restrict__ qs,
                                                           double *__restrict__ red,
                                                           const int *__restrict__ skip)
 {
+    constexpr int QCNT = NBT * 3 * 64;                // fragments per chunk
+    constexpr bool DB = 2 * QCNT * 16 <= 144 * 1024;  // double buffer if it fits
+    constexpr int QPER = (QCNT + 511) / 512;
+    __shared__ b8 sq[(DB ? 2 : 1) * QCNT];
     if (skip && skip[blockIdx.z]) return;   // this job has already converged
     const SplitJob &jb = ss.j[blockIdx.z];
     const int M = nz * jb.rows;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wgm = 8 / wgn;
-    const int wm = wave / wgn, wn = wave % wgn;
-    const int row0 = (blockIdx.x * wgm + wm) * (16 * WM);
-    const int col0 = (blockIdx.y * wgn + wn) * (16 * WN);
-    const bool active = row0 < M && col0 < N;
-    const int nrb = active ? min(WM, (M - row0) >> 4) : 0;
-    const int ncb = active ? min(WN, (N - col0) >> 4) : 0;
     const int li = lane & 15, lg = lane >> 4;
     const int NB = N >> 4;
-    f4 acc[WM][WN];
+    const int qcnt = NB * 3 * 64;
+    const int row0 = (blockIdx.x * 8 + wave) * (16 * WM);
+    const int nrb = row0 < M ? min(WM, (M - row0) >> 4) : 0;
+    const Tin *__restrict__ A = static_cast<const Tin *>(jb.in);
+    const int KC = K >> 5;
+
+    f4 acc[WM][NBT];
 #pragma unroll
     for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int j = 0; j < WN; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
-    if (active) {
-        const Tin *__restrict__ A = static_cast<const Tin *>(jb.in);
-        for (int kc = 0; kc < (K >> 5); ++kc) {
-            b8 a[WM][3], b[WN][3];
+        for (int j = 0; j < NBT; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
+
+    float dcur[WM][8], dnext[WM][8];
+    auto load_data = [&](int kc, float (&d)[WM][8]) {
 #pragma unroll
-            for (int i = 0; i < WM; ++i) {
-                float v[8];
-                if (i < nrb) {
-                    load8<Tin>(A + (size_t)(row0 + 16 * i + li) * K + 32 * kc + 8 * lg, v);
-                } else {
+        for (int i = 0; i < WM; ++i) {
+            if (i < nrb) {
+                load8<Tin>(A + (size_t)(row0 + 16 * i + li) * K + 32 * kc + 8 * lg, d[i]);
+            } else {
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) v[e] = 0.f;
-                }
-                split8(v, a[i]);
+                for (int e = 0; e < 8; ++e) d[i][e] = 0.f;
             }
+        }
+    };
+    b8 qreg[QPER];
+    q_load<QPER>(qs, qcnt, qreg);
+    q_store<QPER>(sq, qcnt, qreg);
+    load_data(0, dcur);
+    for (int kc = 0; kc < KC; ++kc) {
+        __syncthreads();
+        const b8 *cur = sq + (DB ? (kc & 1) * QCNT : 0);
+        const bool more = kc + 1 < KC;
+        if (more) {
+            q_load<QPER>(qs + (size_t)(kc + 1) * qcnt, qcnt, qreg);
+            load_data(kc + 1, dnext);
+        }
+        b8 a[WM][3];
 #pragma unroll
-            for (int j = 0; j < WN; ++j) {
-                const b8 *q = qs + ((size_t)(kc * NB + (col0 >> 4) + (j < ncb ? j : 0)) * 3) * 64 + lane;
+        for (int i = 0; i < WM; ++i) split8(dcur[i], a[i]);
+        if (nrb > 0) {
+            // groups of G column blocks: the six term products are the outer
+            // loop, so consecutive MFMAs update G*WM independent accumulators
+            // (blocks beyond NB read unused LDS and are never stored)
+            constexpr int G = (NBT >= 4 && WM == 1) ? 4 : 2;
 #pragma unroll
-                for (int t = 0; t < 3; ++t) b[j][t] = q[t * 64];
+            for (int jg = 0; jg < NBT; jg += G) {
+                b8 b[G][3];
+#pragma unroll
+                for (int jj = 0; jj < G; ++jj)
+#pragma unroll
+                    for (int t = 0; t < 3; ++t) b[jj][t] = cur[((jg + jj) * 3 + t) * 64 + lane];
+#pragma unroll
+                for (int pr = 0; pr < 6; ++pr)
+#pragma unroll
+                    for (int jj = 0; jj < G; ++jj)
+#pragma unroll
+                        for (int i = 0; i < WM; ++i)
+                            acc[i][jg + jj] = mma(a[i][TA_[pr]], b[jj][TB_[pr]], acc[i][jg + jj]);
             }
+        }
+        if (more) {
+            if (!DB) __syncthreads();
+            q_store<QPER>(sq + (DB ? ((kc + 1) & 1) * QCNT : 0), qcnt, qreg);
 #pragma unroll
             for (int i = 0; i < WM; ++i)
 #pragma unroll
-                for (int j = 0; j < WN; ++j) acc[i][j] = mma3(a[i], b[j], acc[i][j]);
+                for (int e = 0; e < 8; ++e) dcur[i][e] = dnext[i][e];
         }
     }
     double sd = 0.0, sx = 0.0;
 #pragma unroll
     for (int i = 0; i < WM; ++i) {
+        if (i < nrb) {
 #pragma unroll
-        for (int j = 0; j < WN; ++j) {
-            if (i < nrb && j < ncb) {
+            for (int j = 0; j < NBT; ++j) {
+                if (j < NB) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const size_t o = (size_t)(row0 + 16 * i + 4 * lg + q) * N + col0 + 16 * j + li;
-                    if (MODE == 0) {
-                        jb.out[o] = acc[i][j][q];
-                    } else if (MODE == 1) {
-                        jb.x[o] = (double)acc[i][j][q];
-                    } else {
-                        const double d = (double)acc[i][j][q];
-                        const double xn = jb.x[o] + d;
-                        jb.x[o] = xn;
-                        sd += d * d;
-                        sx += xn * xn;
+                    for (int q = 0; q < 4; ++q) {
+                        const size_t o = (size_t)(row0 + 16 * i + 4 * lg + q) * N + 16 * j + li;
+                        if (MODE == 0) {
+                            jb.out[o] = acc[i][j][q];
+                        } else if (MODE == 1) {
+                            jb.x[o] = (double)acc[i][j][q];
+                        } else {
+                            const double d = (double)acc[i][j][q];
+                            const double xn = jb.x[o] + d;
+                            jb.x[o] = xn;
+                            sd += d * d;
+                            sx += xn * xn;
+                        }
                     }
                 }
             }
@@ -170,69 +242,104 @@ __global__ __launch_bounds__(512) void split_xgemm_kernel(SplitSet ss, int nz, i
         if (threadIdx.x == 0) {
             double a = 0.0, b = 0.0;
             for (int w = 0; w < 8; ++w) { a += sm[0][w]; b += sm[1][w]; }
-            const size_t slot = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+            const size_t slot = (size_t)blockIdx.z * gridDim.x + blockIdx.x;
             red[2 * slot] = a;
             red[2 * slot + 1] = b;
         }
     }
 }
 
-// z transform, C = A B with A the split swizzled transform (M x K, M = K =
-// nz) and B the field viewed as K x (rows*nx), FP32 in and out.
-template <int WM, int WN>
+// z transform: C = A B, A the split swizzled nz x nz matrix (M = K = nz =
+// 16 MB, MB <= MBT), B the field viewed as nz x (rows*nx), FP32 in and out.
+// A wave owns all M rows and WN column blocks (16 columns each).
+template <int MBT, int WN>
 __global__ __launch_bounds__(512) void split_zgemm_kernel(SplitSet ss, int M, int K, int nx,
-                                                          const b8 *__restrict__ qs, int wgn,
+                                                          const b8 *__restrict__ qs,
                                                           const int *__restrict__ skip)
 {
+    constexpr int QCNT = MBT * 3 * 64;
+    constexpr bool DB = 2 * QCNT * 16 <= 144 * 1024;
+    constexpr int QPER = (QCNT + 511) / 512;
+    __shared__ b8 sq[(DB ? 2 : 1) * QCNT];
     if (skip && skip[blockIdx.z]) return;
     const SplitJob &jb = ss.j[blockIdx.z];
     const int Ncol = jb.rows * nx;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wgm = 8 / wgn;
-    const int wm = wave / wgn, wn = wave % wgn;
-    const int row0 = (blockIdx.y * wgm + wm) * (16 * WM);
-    const int col0 = (blockIdx.x * wgn + wn) * (16 * WN);
-    if (row0 >= M || col0 >= Ncol) return;
-    const int nrb = min(WM, (M - row0) >> 4);
-    const int ncb = min(WN, (Ncol - col0) >> 4);
     const int li = lane & 15, lg = lane >> 4;
     const int MB = M >> 4;
+    const int qcnt = MB * 3 * 64;
+    const int col0 = (blockIdx.x * 8 + wave) * (16 * WN);
+    const int ncb = col0 < Ncol ? min(WN, (Ncol - col0) >> 4) : 0;
     const float *__restrict__ B = static_cast<const float *>(jb.in);
-    f4 acc[WM][WN];
+    const int KC = K >> 5;
+
+    f4 acc[MBT][WN];
 #pragma unroll
-    for (int i = 0; i < WM; ++i)
+    for (int i = 0; i < MBT; ++i)
 #pragma unroll
         for (int j = 0; j < WN; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
-    for (int kc = 0; kc < (K >> 5); ++kc) {
-        b8 a[WM][3], b[WN][3];
-#pragma unroll
-        for (int i = 0; i < WM; ++i) {
-            const b8 *q = qs + ((size_t)(kc * MB + (row0 >> 4) + (i < nrb ? i : 0)) * 3) * 64 + lane;
-#pragma unroll
-            for (int t = 0; t < 3; ++t) a[i][t] = q[t * 64];
-        }
+
+    float dcur[WN][8], dnext[WN][8];
+    auto load_data = [&](int kc, float (&d)[WN][8]) {
         const float *brow = B + (size_t)(32 * kc + 8 * lg) * Ncol + col0 + li;
 #pragma unroll
-        for (int j = 0; j < WN; ++j) {
-            float v[8];
+        for (int j = 0; j < WN; ++j)
 #pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = (j < ncb) ? brow[(size_t)e * Ncol + 16 * j] : 0.f;
-            split8(v, b[j]);
+            for (int e = 0; e < 8; ++e) d[j][e] = (j < ncb) ? brow[(size_t)e * Ncol + 16 * j] : 0.f;
+    };
+    b8 qreg[QPER];
+    q_load<QPER>(qs, qcnt, qreg);
+    q_store<QPER>(sq, qcnt, qreg);
+    load_data(0, dcur);
+    for (int kc = 0; kc < KC; ++kc) {
+        __syncthreads();
+        const b8 *cur = sq + (DB ? (kc & 1) * QCNT : 0);
+        const bool more = kc + 1 < KC;
+        if (more) {
+            q_load<QPER>(qs + (size_t)(kc + 1) * qcnt, qcnt, qreg);
+            load_data(kc + 1, dnext);
         }
+        b8 b[WN][3];
 #pragma unroll
-        for (int i = 0; i < WM; ++i)
+        for (int j = 0; j < WN; ++j) split8(dcur[j], b[j]);
+        if (ncb > 0) {
+            constexpr int G = (MBT >= 4 && WN == 1) ? 4 : 2;
 #pragma unroll
-            for (int j = 0; j < WN; ++j) acc[i][j] = mma3(a[i], b[j], acc[i][j]);
+            for (int ig = 0; ig < MBT; ig += G) {
+                b8 a[G][3];
+#pragma unroll
+                for (int ii = 0; ii < G; ++ii)
+#pragma unroll
+                    for (int t = 0; t < 3; ++t) a[ii][t] = cur[((ig + ii) * 3 + t) * 64 + lane];
+#pragma unroll
+                for (int pr = 0; pr < 6; ++pr)
+#pragma unroll
+                    for (int ii = 0; ii < G; ++ii)
+#pragma unroll
+                        for (int j = 0; j < WN; ++j)
+                            acc[ig + ii][j] = mma(a[ii][TA_[pr]], b[j][TB_[pr]], acc[ig + ii][j]);
+            }
+        }
+        if (more) {
+            if (!DB) __syncthreads();
+            q_store<QPER>(sq + (DB ? ((kc + 1) & 1) * QCNT : 0), qcnt, qreg);
+#pragma unroll
+            for (int j = 0; j < WN; ++j)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) dcur[j][e] = dnext[j][e];
+        }
     }
 #pragma unroll
-    for (int i = 0; i < WM; ++i) {
-        if (i >= nrb) break;
+    for (int i = 0; i < MBT; ++i) {
+        if (i < MB) {
 #pragma unroll
-        for (int j = 0; j < WN; ++j) {
-            if (j >= ncb) break;
+            for (int j = 0; j < WN; ++j) {
+                if (j < ncb) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                jb.out[(size_t)(row0 + 16 * i + 4 * lg + q) * Ncol + col0 + 16 * j + li] = acc[i][j][q];
+                    for (int q = 0; q < 4; ++q)
+                        jb.out[(size_t)(16 * i + 4 * lg + q) * Ncol + col0 + 16 * j + li] = acc[i][j][q];
+                }
+            }
         }
     }
 }
@@ -242,16 +349,20 @@ __global__ __launch_bounds__(512) void split_zgemm_kernel(SplitSet ss, int M, in
 // by the first pass) is subtracted first: that constant lies in the null
 // space of every correction, and left in r its FP32 rounding would swamp the
 // shrinking residual.  The same pass sums Delta_j x per block (fixed block
-// count and order), so the next correction can also remove the weighted
+// layout and order), so the next correction can also remove the weighted
 // mean that x has picked up from the FP32 transforms.
-// grid: (XSUM_SLOTS blocks, jobs); each block walks grid rows (j, k).
+// A block owns 4 rows x 64 columns of rz consecutive z planes and marches
+// along z, keeping x at k-1, k, k+1 in registers (each x value is read from
+// HBM about once; x and y neighbours come from the same or adjacent blocks'
+// lines).  grid: (tiles per job, jobs), the same tile count for all jobs.
 __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, int ny, int nz,
                                                            double ihx2, double ihz2,
                                                            const double *__restrict__ dyc,
                                                            const double *__restrict__ dyf,
                                                            const double *__restrict__ bmean,
                                                            double *__restrict__ xsum,
-                                                           const int *__restrict__ skip)
+                                                           const int *__restrict__ skip, int tiles_x,
+                                                           int tiles_xy, int rz)
 {
     const int job = blockIdx.y;
     if (skip && skip[job]) return;
@@ -260,37 +371,54 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
     const size_t plane = (size_t)rows * nx;
     const double *__restrict__ x = jb.x;
     const double bm = (op == IBS_OP_POISSON) ? bmean[job] : 0.0;
+    const int kz = blockIdx.x / tiles_xy, txy = blockIdx.x - kz * tiles_xy;
+    const int tj = txy / tiles_x, ti = txy - tj * tiles_x;
+    const int k0 = kz * rz, k1 = min(nz, k0 + rz);
+    const int j = tj * 4 + (threadIdx.x >> 6), i = ti * 64 + (threadIdx.x & 63);
     double wx = 0.0;
-    for (int rw = blockIdx.x; rw < rows * nz; rw += gridDim.x) {
-        const int j = rw % rows, k = rw / rows;
-        const size_t kp = (k + 1 == nz) ? 0 : (size_t)(k + 1);
-        const size_t km = (k == 0) ? (size_t)(nz - 1) : (size_t)(k - 1);
-        for (int i = threadIdx.x; i < nx; i += blockDim.x) {
-            const size_t c = (size_t)k * plane + (size_t)j * nx + i;
-            if (op == IBS_OP_HELMHOLTZ_V && (j == 0 || j == ny)) {
+    if (j < rows && i < nx) {
+        const bool wall = op == IBS_OP_HELMHOLTZ_V && (j == 0 || j == ny);
+        const int ip = (i + 1 == nx) ? 0 : i + 1, im = (i == 0) ? nx - 1 : i - 1;
+        const size_t o = (size_t)j * nx + i;
+        // y part in difference form, cu (x_up - x) - cl (x - x_lo); a missing
+        // neighbour is the boundary ghost g x (g = 1 Neumann, -1 mirror, 0 wall)
+        double D = 0.0, cu = 0.0, cl = 0.0, gu = 0.0, gl = 0.0;
+        bool ru = false, rl = false;
+        if (op != IBS_OP_HELMHOLTZ_V) {
+            D = dyc[j];
+            const double gb = (op == IBS_OP_POISSON) ? 1.0 : -1.0;
+            ru = j + 1 < ny;
+            cu = ru ? 1.0 / (dyf[j + 1] * D) : 1.0 / (D * D);
+            gu = gb;
+            rl = j > 0;
+            cl = rl ? 1.0 / (dyf[j] * D) : 1.0 / (D * D);
+            gl = gb;
+        } else if (!wall) {
+            cu = 1.0 / (dyc[j] * dyf[j]);
+            cl = 1.0 / (dyc[j - 1] * dyf[j]);
+            ru = j + 1 <= ny - 1;
+            rl = j - 1 >= 1;
+        }
+        double xm = x[(size_t)(k0 == 0 ? nz - 1 : k0 - 1) * plane + o];
+        double xc = x[(size_t)k0 * plane + o];
+#pragma unroll 4
+        for (int k = k0; k < k1; ++k) {
+            const size_t c = (size_t)k * plane + o;
+            const double xp = x[(size_t)(k + 1 == nz ? 0 : k + 1) * plane + o];
+            if (wall) {
                 jb.r[c] = 0.f;
-                continue;
-            }
-            const int ip = (i + 1 == nx) ? 0 : i + 1, im = (i == 0) ? nx - 1 : i - 1;
-            const double xc = x[c];
-            double lap = ((x[c - i + ip] - xc) - (xc - x[c - i + im])) * ihx2 +
-                         ((x[kp * plane + (size_t)j * nx + i] - xc) - (xc - x[km * plane + (size_t)j * nx + i])) * ihz2;
-            if (op != IBS_OP_HELMHOLTZ_V) {
-                const double D = dyc[j];
-                double fu, fl;
-                if (j + 1 < ny) fu = (x[c + nx] - xc) / dyf[j + 1];
-                else fu = (op == IBS_OP_POISSON) ? 0.0 : -2.0 * xc / D;
-                if (j > 0) fl = (xc - x[c - nx]) / dyf[j];
-                else fl = (op == IBS_OP_POISSON) ? 0.0 : 2.0 * xc / D;
-                lap += (fu - fl) / D;
-                wx += D * xc;
             } else {
-                const double vu = (j + 1 <= ny - 1) ? x[c + nx] : 0.0;
-                const double vl = (j - 1 >= 1) ? x[c - nx] : 0.0;
-                lap += ((vu - xc) / dyc[j] - (xc - vl) / dyc[j - 1]) / dyf[j];
+                const double xe = x[c - i + ip], xw = x[c - i + im];
+                const double xu = ru ? x[c + nx] : gu * xc;
+                const double xl = rl ? x[c - nx] : gl * xc;
+                double lap = ((xe - xc) - (xc - xw)) * ihx2 + ((xp - xc) - (xc - xm)) * ihz2;
+                lap += cu * (xu - xc) - cl * (xc - xl);
+                const double ax = (op == IBS_OP_POISSON) ? lap : xc - jb.c * lap;
+                jb.r[c] = (float)((jb.b[c] - bm) - ax);
+                if (op != IBS_OP_HELMHOLTZ_V) wx += D * xc;
             }
-            const double ax = (op == IBS_OP_POISSON) ? lap : xc - jb.c * lap;
-            jb.r[c] = (float)((jb.b[c] - bm) - ax);
+            xm = xc;
+            xc = xp;
         }
     }
     __shared__ double sm[4];
@@ -368,14 +496,37 @@ static int max_rows(const SplitSet &ss)
     return r;
 }
 
-static void xgemm_grid(const SplitSet &ss, const Plan &p, int &wgn, dim3 &grid)
+// x transform tiling: a wave owns WM row blocks and all columns (NB <= NBT
+// column blocks); at most 128 accumulator registers, and the data of the
+// current and next chunk must stay in registers too.
+static int x_nbt(int N) { return N <= 64 ? 4 : (N <= 128 ? 8 : (N <= 256 ? 16 : 32)); }
+static constexpr int x_wm(int nbt) { return nbt == 4 ? 4 : (nbt == 32 ? 1 : 2); }
+
+static void xgemm_grid(const SplitSet &ss, const Plan &p, dim3 &grid)
 {
-    constexpr int WM = 4, WN = 4;
-    const int N = p.nx, M = p.nz * max_rows(ss);
-    const int ncolw = N / (16 * WN);
-    wgn = ncolw >= 4 ? 4 : (ncolw >= 2 ? 2 : 1);
-    const int wgm = 8 / wgn;
-    grid = dim3((M + 16 * WM * wgm - 1) / (16 * WM * wgm), (N + 16 * WN * wgn - 1) / (16 * WN * wgn), ss.n);
+    const int wm = x_wm(x_nbt(p.nx));
+    const int M = p.nz * max_rows(ss);
+    grid = dim3((M + 8 * 16 * wm - 1) / (8 * 16 * wm), 1, ss.n);
+}
+
+template <int NBT, typename Tin, int MODE>
+static void launch_x(const SplitSet &ss, const Plan &p, const b8 *qs, double *red, const int *skip,
+                     dim3 grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((split_xgemm_kernel<NBT, x_wm(NBT), Tin, MODE>), grid, dim3(512), 0, s, ss,
+                       p.nz, p.nx, p.nx, qs, red, skip);
+}
+
+template <typename Tin, int MODE>
+static void launch_x_nb(const SplitSet &ss, const Plan &p, const b8 *qs, double *red, const int *skip,
+                        dim3 grid, hipStream_t s)
+{
+    switch (x_nbt(p.nx)) {
+    case 4: launch_x<4, Tin, MODE>(ss, p, qs, red, skip, grid, s); break;
+    case 8: launch_x<8, Tin, MODE>(ss, p, qs, red, skip, grid, s); break;
+    case 16: launch_x<16, Tin, MODE>(ss, p, qs, red, skip, grid, s); break;
+    default: launch_x<32, Tin, MODE>(ss, p, qs, red, skip, grid, s); break;
+    }
 }
 
 static size_t update_slots(const SplitSet &ss, const Plan &p);
@@ -384,10 +535,8 @@ hipError_t launch_split_xgemm(const SplitSet &ss, const Plan &p, bool inverse, b
                               int pass, hipStream_t s)
 {
     const int *skip = pass >= 2 ? reinterpret_cast<const int *>(blob_ptr(p, p.lay.done)) : nullptr;
-    constexpr int WM = 4, WN = 4;
-    int wgn;
     dim3 grid;
-    xgemm_grid(ss, p, wgn, grid);
+    xgemm_grid(ss, p, grid);
     const b8 *qs = reinterpret_cast<const b8 *>(blob_ptr(p, inverse ? p.lay.sx_inv : p.lay.sx_fwd));
     // each refinement pass keeps its update partials in a region of its own
     const size_t slots = (size_t)grid.x * grid.y * grid.z;
@@ -396,53 +545,74 @@ hipError_t launch_split_xgemm(const SplitSet &ss, const Plan &p, bool inverse, b
     double *red = blob_mut(p, p.lay.red) + (mode == 2 ? (size_t)(pass - 1) * region : 0);
     if (in64) {
         if (mode != 0) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((split_xgemm_kernel<WM, WN, double, 0>), grid, dim3(512), 0, s, ss, p.nz,
-                           p.nx, p.nx, qs, wgn, red, skip);
+        launch_x_nb<double, 0>(ss, p, qs, red, skip, grid, s);
     } else if (mode == 0) {
-        hipLaunchKernelGGL((split_xgemm_kernel<WM, WN, float, 0>), grid, dim3(512), 0, s, ss, p.nz,
-                           p.nx, p.nx, qs, wgn, red, skip);
+        launch_x_nb<float, 0>(ss, p, qs, red, skip, grid, s);
     } else if (mode == 1) {
-        hipLaunchKernelGGL((split_xgemm_kernel<WM, WN, float, 1>), grid, dim3(512), 0, s, ss, p.nz,
-                           p.nx, p.nx, qs, wgn, red, skip);
+        launch_x_nb<float, 1>(ss, p, qs, red, skip, grid, s);
     } else {
-        hipLaunchKernelGGL((split_xgemm_kernel<WM, WN, float, 2>), grid, dim3(512), 0, s, ss, p.nz,
-                           p.nx, p.nx, qs, wgn, red, skip);
+        launch_x_nb<float, 2>(ss, p, qs, red, skip, grid, s);
     }
     return hipGetLastError();
 }
 
+// z transform tiling: a wave owns all M = nz rows (MB <= MBT row blocks)
+// and WN column blocks.
 hipError_t launch_split_zgemm(const SplitSet &ss, const Plan &p, bool inverse, int pass, hipStream_t s)
 {
     const int *skip = pass >= 2 ? reinterpret_cast<const int *>(blob_ptr(p, p.lay.done)) : nullptr;
-    constexpr int WM = 4, WN = 4;
     const int M = p.nz;
     const int Ncol = max_rows(ss) * p.nx;
-    const int nroww = M / (16 * WM);
-    const int wgm = nroww >= 8 ? 8 : (nroww >= 4 ? 4 : (nroww >= 2 ? 2 : 1));
-    const int wgn = 8 / wgm;
-    dim3 grid((Ncol + 16 * WN * wgn - 1) / (16 * WN * wgn), (M + 16 * WM * wgm - 1) / (16 * WM * wgm),
-              ss.n);
     const b8 *qs = reinterpret_cast<const b8 *>(blob_ptr(p, inverse ? p.lay.sz_inv : p.lay.sz_fwd));
-    hipLaunchKernelGGL((split_zgemm_kernel<WM, WN>), grid, dim3(512), 0, s, ss, M, M, p.nx, qs, wgn, skip);
+    const int mbt = M <= 64 ? 4 : (M <= 128 ? 8 : (M <= 256 ? 16 : (M <= 384 ? 24 : 32)));
+    const int wn = mbt == 4 ? 4 : (mbt <= 16 ? 2 : 1);
+    dim3 grid((Ncol + 8 * 16 * wn - 1) / (8 * 16 * wn), 1, ss.n);
+    switch (mbt) {
+    case 4: hipLaunchKernelGGL((split_zgemm_kernel<4, 4>), grid, dim3(512), 0, s, ss, M, M, p.nx, qs, skip); break;
+    case 8: hipLaunchKernelGGL((split_zgemm_kernel<8, 2>), grid, dim3(512), 0, s, ss, M, M, p.nx, qs, skip); break;
+    case 16: hipLaunchKernelGGL((split_zgemm_kernel<16, 2>), grid, dim3(512), 0, s, ss, M, M, p.nx, qs, skip); break;
+    case 24: hipLaunchKernelGGL((split_zgemm_kernel<24, 1>), grid, dim3(512), 0, s, ss, M, M, p.nx, qs, skip); break;
+    default: hipLaunchKernelGGL((split_zgemm_kernel<32, 1>), grid, dim3(512), 0, s, ss, M, M, p.nx, qs, skip); break;
+    }
     return hipGetLastError();
+}
+
+// Residual tiling: 4 x 64 (y, x) tiles times z chunks of rz planes, with at
+// most XSUM_SLOTS blocks per job (one x-sum partial each).
+static void residual_tiling(const Plan &p, int &tiles_x, int &tiles_xy, int &rz, int &tiles)
+{
+    tiles_x = (p.nx + 63) / 64;
+    tiles_xy = ((p.ny + 1 + 3) / 4) * tiles_x;
+    const int chunks = std::max(1, std::min((p.nz + 7) / 8, XSUM_SLOTS / tiles_xy));
+    rz = (p.nz + chunks - 1) / chunks;
+    tiles = tiles_xy * ((p.nz + rz - 1) / rz);
+}
+
+int residual_tiles(const Plan &p)
+{
+    int tx, txy, rz, t;
+    residual_tiling(p, tx, txy, rz, t);
+    return t;
 }
 
 hipError_t launch_residual_f32(const SplitSet &ss, const Plan &p, int pass, hipStream_t s)
 {
     const int *skip = pass >= 2 ? reinterpret_cast<const int *>(blob_ptr(p, p.lay.done)) : nullptr;
-    dim3 grid(XSUM_SLOTS, ss.n);
+    int tiles_x, tiles_xy, rz, tiles;
+    residual_tiling(p, tiles_x, tiles_xy, rz, tiles);
+    if (tiles > XSUM_SLOTS) return hipErrorInvalidValue;
+    dim3 grid(tiles, ss.n);
     hipLaunchKernelGGL(residual_f32_kernel, grid, dim3(256), 0, s, ss, p.nx, p.ny, p.nz,
                        1.0 / (p.hx * p.hx), 1.0 / (p.hz * p.hz), blob_ptr(p, p.lay.dyc),
                        blob_ptr(p, p.lay.dyf), blob_ptr(p, p.lay.bmean), blob_mut(p, p.lay.xsum),
-                       skip);
+                       skip, tiles_x, tiles_xy, rz);
     return hipGetLastError();
 }
 
 static size_t update_slots(const SplitSet &ss, const Plan &p)
 {
-    int wgn;
     dim3 grid;
-    xgemm_grid(ss, p, wgn, grid);
+    xgemm_grid(ss, p, grid);
     return (size_t)grid.x * grid.y * grid.z;
 }
 
@@ -453,9 +623,8 @@ int max_refine_passes(const SplitSet &ss, const Plan &p)
 
 hipError_t launch_refine_check(const SplitSet &ss, const Plan &p, int pass, hipStream_t s)
 {
-    int wgn;
     dim3 grid;
-    xgemm_grid(ss, p, wgn, grid);
+    xgemm_grid(ss, p, grid);
     const int per_job = (int)(grid.x * grid.y);
     const size_t region = 2 * (size_t)grid.x * grid.y * grid.z;
     const double *red = blob_ptr(p, p.lay.red);

@@ -43,7 +43,8 @@ struct TriParams {
     const double *lo[NUM_KINDS], *di[NUM_KINDS], *up[NUM_KINDS];
     const double *wy;   // Delta_j: weights of the pressure unknowns
     double *bmean;      // per job: weighted mean removed from the rhs (Poisson)
-    const double *xsum; // per job: XSUM_SLOTS partial sums of Delta_j x, or null
+    const double *xsum; // per job: nxsum partial sums of Delta_j x (stride XSUM_SLOTS), or null
+    int nxsum;
     int record_mean;    // write bmean (first pass of a solve)
     const int *skip;    // per job: refinement already stopped (later passes), or null
     double wsum_y;      // sum of Delta_j
@@ -257,7 +258,7 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
                 // weighted mean (in this pencil's normalisation)
                 const double *xs = tp.xsum + (size_t)job * XSUM_SLOTS;
                 double part = 0.0;
-                for (int q = k; q < XSUM_SLOTS; q += P) part += xs[q];
+                for (int q = k; q < tp.nxsum; q += P) part += xs[q];
 #pragma unroll
                 for (int d = 1; d < P; d <<= 1) part += __shfl_xor(part, d, P);
                 mx += part * tp.inv_sqrt_nxnz / tp.wsum_y;
@@ -331,6 +332,7 @@ static hipError_t launch_tridiag(const JobSet &js, const Plan &p, bool poisson, 
     tp.nz = p.nz;
     tp.poisson = poisson ? 1 : 0;
     tp.strict = p.desc.strict_compat ? 1 : 0;
+    tp.nxsum = residual_tiles(p);
     if (pass > 0) {
         tp.record_mean = 0;
         tp.xsum = blob_ptr(p, p.lay.xsum);

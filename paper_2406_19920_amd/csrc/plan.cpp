@@ -149,8 +149,8 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
         set_error("unknown precision");
         return IBS_ERR_INVALID_ARG;
     }
-    if (d.precision != IBS_FP64 && (d.nx % 32 || d.nz % 32)) {
-        set_error("the refined path needs nx and nz to be multiples of 32");
+    if (d.precision != IBS_FP64 && (d.nx % 32 || d.nz % 32 || d.nx > 512 || d.nz > 512)) {
+        set_error("the refined path needs nx and nz to be multiples of 32, at most 512");
         return IBS_ERR_UNSUPPORTED;
     }
     if (!(std::isfinite(d.beta)) || d.beta < 0.0 || d.beta > 10.0) {

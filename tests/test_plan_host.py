@@ -76,6 +76,12 @@ def test_plan_bytes_and_errors():
         with pytest.raises(ibs.IbsError) as e:
             _plan(**kw)
         assert e.value.status == ibs.IBS_ERR_UNSUPPORTED
+    for bad in (dict(nx=48), dict(nz=544)):
+        kw = dict(nx=64, ny=16, nz=64, precision=ibs.IBS_REFINED_BF16X3)
+        kw.update(bad)
+        with pytest.raises(ibs.IbsError) as e:
+            _plan(**kw)
+        assert e.value.status == ibs.IBS_ERR_UNSUPPORTED
     with pytest.raises(ibs.IbsError) as e:
         _plan(32, 16, 32, bc_x=ibs.IBS_DIRICHLET)
     assert e.value.status == ibs.IBS_ERR_UNSUPPORTED
