@@ -38,6 +38,36 @@ static __device__ __forceinline__ double rcp64(double d)
     return fma(x, e, x);
 }
 
+// Raw buffer access with the hardware range check: offsets at or beyond the
+// resource's byte count load 0 and drop stores.  The whole offset goes in
+// the vector operand (the scalar offset is outside the range check).
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+template <typename T>
+static __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
+}
+static __device__ __forceinline__ void buf_store_raw(double v, __amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, voff, soff, 0);
+}
+static __device__ __forceinline__ void buf_store_raw(float v, __amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), rs, voff, soff, 0);
+}
+template <typename T>
+static __device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff)
+{
+    buf_store_raw(v, rs, voff, soff);
+}
+
 struct TriParams {
     const double *lam_x, *lam_z;
     const double *lo[NUM_KINDS], *di[NUM_KINDS], *up[NUM_KINDS];
@@ -75,39 +105,58 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
     const int p = tid / P, k = tid % P;
     const int s = k * M;
     const bool pois = tp.poisson != 0;
+    const uint32_t row_bytes = (uint32_t)nx * sizeof(T);
 
-    auto fetch = [&](int tile, double (&pf)[M]) {
-        const int job = tile / (tp.nz * ntx);
-        if (tp.skip && tp.skip[job]) return;   // converged job: nothing to load
-        const int rem = tile - job * tp.nz * ntx;
-        const int c = rem / ntx, a0 = (rem - c * ntx) * TA;
+    // converged jobs (later refinement passes): read once, block-uniform
+    int skipmask = 0;
+    if (tp.skip)
+        for (int q = 0; q < js.n; ++q) skipmask |= tp.skip[q] ? (1 << q) : 0;
+
+    // Every fetch issues the same M + 2 loads and every write-back the same
+    // M stores, whatever the tile: rows beyond the system, tiles beyond the
+    // last and tiles of converged jobs are handled by the buffer range check
+    // (loads return 0, stores are dropped).  With no loads or stores under
+    // branches, the wait before a tile is used covers only that tile's data
+    // and leaves the next tile's loads in flight.
+    auto plane_rsrc = [&](int job, int c, bool live) {
         const FieldJob &jb = js.j[job];
-        const int n = jb.rows;
-        const T *__restrict__ base = reinterpret_cast<const T *>(jb.out) + (size_t)c * n * nx + a0 + lcol;
-        const bool walls = jb.kind == KIND_F;
+        const T *base = reinterpret_cast<const T *>(jb.out) + (size_t)c * jb.rows * nx;
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(base), (short)0,
+                                                 live ? (int)(jb.rows * row_bytes) : 0, 0x00020000);
+    };
+    auto decode = [&](int tile, int &job, int &c, int &a0) {
+        job = tile / (tp.nz * ntx);
+        const int rem = tile - job * tp.nz * ntx;
+        c = rem / ntx;
+        a0 = (rem - c * ntx) * TA;
+    };
+    // raw values only: conversion and wall rows are applied when the tile is
+    // staged, so that nothing here waits for the loads
+    auto fetch = [&](int tile, T (&pf)[M], double &plx, double &plz) {
+        int job, c, a0;
+        decode(tile < ntiles ? tile : ntiles - 1, job, c, a0);
+        const bool live = tile < ntiles && !((skipmask >> job) & 1);
+        plx = tp.lam_x[a0 + p];
+        plz = tp.lam_z[c];
+        const auto rs = plane_rsrc(job, c, live);
+        const uint32_t voff = (uint32_t)(a0 + lcol) * sizeof(T) + (uint32_t)lrow * row_bytes;
 #pragma unroll
-        for (int r = 0; r < M; ++r) {
-            const int j = lrow + P * r;
-            pf[r] = (j < n && !(walls && (j == 0 || j == n - 1))) ? (double)base[(size_t)j * nx] : 0.0;
-        }
+        for (int r = 0; r < M; ++r) pf[r] = buf_load<T>(rs, voff + r * P * row_bytes, 0);
     };
 
     // two register buffers: the tile two steps ahead is in flight while the
     // current one is solved (HBM latency is long next to one tile's work)
-    double pfa[M], pfb[M];
+    T pfa[M], pfb[M];
+    double lxa, lza, lxb, lzb;
     int cur_job = -1;
-    auto process = [&](const int tile, double (&pf)[M]) {
-        const int job = tile / (tp.nz * ntx);
-        const int rem = tile - job * tp.nz * ntx;
-        const int c = rem / ntx, a0 = (rem - c * ntx) * TA;
+    auto process = [&](const int tile, T (&pf)[M], double &plx, double &plz) {
+        int job, c, a0;
+        decode(tile, job, c, a0);
         const FieldJob &jb = js.j[job];
         const int n = jb.rows, kind = jb.kind;
-        if (tp.skip && tp.skip[job]) {   // block-uniform: the whole tile is skipped
-            if (tile + 2 * (int)gridDim.x < ntiles) fetch(tile + 2 * gridDim.x, pf);
-            return;
-        }
+        const bool live = !((skipmask >> job) & 1);   // block-uniform
         __syncthreads();  // the previous tile's LDS is no longer read
-        if (job != cur_job) {
+        if (live && job != cur_job) {
             // rows of the job's operator without the pencil shift:
             // Poisson (lo, di, up); Helmholtz (-c lo, 1 - c di, -c up)
             const double cj = jb.c;
@@ -123,188 +172,203 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
             }
             cur_job = job;
         }
+        const bool walls = kind == KIND_F;
 #pragma unroll
-        for (int r = 0; r < M; ++r) sx[(lrow + P * r) * LDR + lcol] = pf[r];
+        for (int r = 0; r < M; ++r) {
+            const int j = lrow + P * r;
+            sx[j * LDR + lcol] = (walls && (j == 0 || j == n - 1)) ? 0.0 : (double)pf[r];
+        }
+        const double sh = plx + plz;
         __syncthreads();
-        if (tile + 2 * (int)gridDim.x < ntiles) fetch(tile + 2 * gridDim.x, pf);  // two tiles ahead
-    
-        const int a = a0 + p;
-        const double sh = tp.lam_x[a] + tp.lam_z[c];
-        const double sadd = pois ? sh : -jb.c * sh;   // pencil shift of the diagonal
-        const bool pinned = pois && a == 0 && c == 0;
-    
-        double r[M];
+        fetch(tile + 2 * (int)gridDim.x, pf, plx, plz);  // two tiles ahead
+        if (live) {
+            const int a = a0 + p;
+            const double sadd = pois ? sh : -jb.c * sh;   // pencil shift of the diagonal
+            const bool pinned = pois && a == 0 && c == 0;
+
+            double r[M];
 #pragma unroll
-        for (int t = 0; t < M; ++t) r[t] = sx[(s + t) * LDR + p];
-    
-        double removed = 0.0, rms = 0.0;
-        if (pinned) {
-            // compatibility: remove the volume-weighted mean of this pencil's rhs
-            double swr = 0.0, sww = 0.0, swrr = 0.0;
+            for (int t = 0; t < M; ++t) r[t] = sx[(s + t) * LDR + p];
+
+            double removed = 0.0, rms = 0.0;
+            if (pinned) {
+                // compatibility: remove the volume-weighted mean of this pencil's rhs
+                double swr = 0.0, sww = 0.0, swrr = 0.0;
 #pragma unroll
-            for (int t = 0; t < M; ++t) {
-                swr += sw[s + t] * r[t];
-                sww += sw[s + t];
-                swrr += sw[s + t] * r[t] * r[t];
+                for (int t = 0; t < M; ++t) {
+                    swr += sw[s + t] * r[t];
+                    sww += sw[s + t];
+                    swrr += sw[s + t] * r[t] * r[t];
+                }
+#pragma unroll
+                for (int d = 1; d < P; d <<= 1) {
+                    swr += __shfl_xor(swr, d, P);
+                    sww += __shfl_xor(sww, d, P);
+                    swrr += __shfl_xor(swrr, d, P);
+                }
+                const double mean = swr / sww;
+                rms = sqrt(fmax(swrr / sww, 0.0));
+                removed = mean;
+#pragma unroll
+                for (int t = 0; t < M; ++t)
+                    if (s + t < n) r[t] -= mean;
+                if (k == 0) r[0] = 0.0;  // pin the first point
             }
+
+            auto coef = [&](int j, double &A, double &B, double &C) {
+                const bool real = j < n && !(pinned && j == 0);
+                A = real ? slo[j] : 0.0;
+                B = real ? sdi[j] + sadd : 1.0;
+                C = real ? sup[j] : 0.0;
+            };
+
+            // down-sweep: rows s+1 .. s+M-1 in the form al x_s + x_j + ga x_{j+1} = rho
+            double al[M], ga[M];
+            {
+                double A, B, C;
+                coef(s + 1, A, B, C);
+                double inv = rcp64(B);
+                al[1] = A * inv; ga[1] = C * inv; r[1] = r[1] * inv;
+#pragma unroll
+                for (int t = 2; t < M; ++t) {
+                    coef(s + t, A, B, C);
+                    inv = rcp64(B - A * ga[t - 1]);
+                    al[t] = -A * al[t - 1] * inv;
+                    ga[t] = C * inv;
+                    r[t] = (r[t] - A * r[t - 1]) * inv;
+                }
+            }
+            // interior rows in terms of the chunk ends, x_j = bp + bq x_s + br x_e,
+            // by back-substitution (no divisions), then the top row
+            //   lam x_{s-1} + x_s + mu x_e = sig
+            double lam_u, mu_u, sig_u;
+            {
+                double bp = r[M - 2], bq = -al[M - 2], br = -ga[M - 2];
+#pragma unroll
+                for (int t = M - 3; t >= 1; --t) {
+                    bp = r[t] - ga[t] * bp;
+                    bq = -al[t] - ga[t] * bq;
+                    br = -ga[t] * br;
+                }
+                double A, B, C;
+                coef(s, A, B, C);
+                const double inv = rcp64(B + C * bq);
+                lam_u = A * inv;
+                mu_u = C * br * inv;
+                sig_u = (r[0] - C * bp) * inv;
+            }
+
+            // reduced system in z_k = x_{last row of chunk k}
+            double lam1 = __shfl_down(lam_u, 1, P), mu1 = __shfl_down(mu_u, 1, P),
+                   sig1 = __shfl_down(sig_u, 1, P);
+            if (k == P - 1) { lam1 = 0.0; mu1 = 0.0; sig1 = 0.0; }
+            const double ae = al[M - 1], ge = ga[M - 1], re = r[M - 1];
+            double EA = -ae * lam_u;
+            double EB = 1.0 - ae * mu_u - ge * lam1;
+            double EC = -ge * mu1;
+            double ED = re - ae * sig_u - ge * sig1;
 #pragma unroll
             for (int d = 1; d < P; d <<= 1) {
-                swr += __shfl_xor(swr, d, P);
-                sww += __shfl_xor(sww, d, P);
-                swrr += __shfl_xor(swrr, d, P);
+                double am = __shfl_up(EA, d, P), bm = __shfl_up(EB, d, P);
+                double cm = __shfl_up(EC, d, P), dm = __shfl_up(ED, d, P);
+                double ap = __shfl_down(EA, d, P), bp = __shfl_down(EB, d, P);
+                double cp = __shfl_down(EC, d, P), dp = __shfl_down(ED, d, P);
+                if (k < d) { am = 0.0; bm = 1.0; cm = 0.0; dm = 0.0; }
+                if (k + d >= P) { ap = 0.0; bp = 1.0; cp = 0.0; dp = 0.0; }
+                const double k1 = EA * rcp64(bm), k2 = EC * rcp64(bp);
+                const double nA = -k1 * am, nC = -k2 * cp;
+                const double nB = EB - k1 * cm - k2 * ap;
+                const double nD = ED - k1 * dm - k2 * dp;
+                EA = nA; EB = nB; EC = nC; ED = nD;
             }
-            const double mean = swr / sww;
-            rms = sqrt(fmax(swrr / sww, 0.0));
-            removed = mean;
+            const double z = ED * rcp64(EB);
+            double zm = __shfl_up(z, 1, P);
+            if (k == 0) zm = 0.0;
+            const double xs = sig_u - lam_u * zm - mu_u * z;
+
+            // interior back-substitution, in place: r[t] becomes x[t]
+            r[M - 1] = z;
 #pragma unroll
-            for (int t = 0; t < M; ++t)
-                if (s + t < n) r[t] -= mean;
-            if (k == 0) r[0] = 0.0;  // pin the first point
-        }
-    
-        auto coef = [&](int j, double &A, double &B, double &C) {
-            const bool real = j < n && !(pinned && j == 0);
-            A = real ? slo[j] : 0.0;
-            B = real ? sdi[j] + sadd : 1.0;
-            C = real ? sup[j] : 0.0;
-        };
-    
-        // down-sweep: rows s+1 .. s+M-1 in the form al x_s + x_j + ga x_{j+1} = rho
-        double al[M], ga[M];
-        {
-            double A, B, C;
-            coef(s + 1, A, B, C);
-            double inv = rcp64(B);
-            al[1] = A * inv; ga[1] = C * inv; r[1] = r[1] * inv;
+            for (int t = M - 2; t >= 1; --t) r[t] = r[t] - al[t] * xs - ga[t] * r[t + 1];
+            r[0] = xs;
+
+            if (pinned) {
+                // null mode: zero volume-weighted mean
+                double swx = 0.0, sww = 0.0;
 #pragma unroll
-            for (int t = 2; t < M; ++t) {
-                coef(s + t, A, B, C);
-                inv = rcp64(B - A * ga[t - 1]);
-                al[t] = -A * al[t - 1] * inv;
-                ga[t] = C * inv;
-                r[t] = (r[t] - A * r[t - 1]) * inv;
-            }
-        }
-        // interior rows in terms of the chunk ends, x_j = bp + bq x_s + br x_e,
-        // by back-substitution (no divisions), then the top row
-        //   lam x_{s-1} + x_s + mu x_e = sig
-        double lam_u, mu_u, sig_u;
-        {
-            double bp = r[M - 2], bq = -al[M - 2], br = -ga[M - 2];
+                for (int t = 0; t < M; ++t) {
+                    swx += sw[s + t] * r[t];
+                    sww += sw[s + t];
+                }
 #pragma unroll
-            for (int t = M - 3; t >= 1; --t) {
-                bp = r[t] - ga[t] * bp;
-                bq = -al[t] - ga[t] * bq;
-                br = -ga[t] * br;
-            }
-            double A, B, C;
-            coef(s, A, B, C);
-            const double inv = rcp64(B + C * bq);
-            lam_u = A * inv;
-            mu_u = C * br * inv;
-            sig_u = (r[0] - C * bp) * inv;
-        }
-    
-        // reduced system in z_k = x_{last row of chunk k}
-        double lam1 = __shfl_down(lam_u, 1, P), mu1 = __shfl_down(mu_u, 1, P),
-               sig1 = __shfl_down(sig_u, 1, P);
-        if (k == P - 1) { lam1 = 0.0; mu1 = 0.0; sig1 = 0.0; }
-        const double ae = al[M - 1], ge = ga[M - 1], re = r[M - 1];
-        double EA = -ae * lam_u;
-        double EB = 1.0 - ae * mu_u - ge * lam1;
-        double EC = -ge * mu1;
-        double ED = re - ae * sig_u - ge * sig1;
+                for (int d = 1; d < P; d <<= 1) {
+                    swx += __shfl_xor(swx, d, P);
+                    sww += __shfl_xor(sww, d, P);
+                }
+                double mx = swx / sww;
+                if (tp.xsum) {
+                    // refinement: steer the correction so that x + d has zero
+                    // weighted mean (in this pencil's normalisation)
+                    const double *xs = tp.xsum + (size_t)job * XSUM_SLOTS;
+                    double part = 0.0;
+                    for (int q = k; q < tp.nxsum; q += P) part += xs[q];
 #pragma unroll
-        for (int d = 1; d < P; d <<= 1) {
-            double am = __shfl_up(EA, d, P), bm = __shfl_up(EB, d, P);
-            double cm = __shfl_up(EC, d, P), dm = __shfl_up(ED, d, P);
-            double ap = __shfl_down(EA, d, P), bp = __shfl_down(EB, d, P);
-            double cp = __shfl_down(EC, d, P), dp = __shfl_down(ED, d, P);
-            if (k < d) { am = 0.0; bm = 1.0; cm = 0.0; dm = 0.0; }
-            if (k + d >= P) { ap = 0.0; bp = 1.0; cp = 0.0; dp = 0.0; }
-            const double k1 = EA * rcp64(bm), k2 = EC * rcp64(bp);
-            const double nA = -k1 * am, nC = -k2 * cp;
-            const double nB = EB - k1 * cm - k2 * ap;
-            const double nD = ED - k1 * dm - k2 * dp;
-            EA = nA; EB = nB; EC = nC; ED = nD;
-        }
-        const double z = ED * rcp64(EB);
-        double zm = __shfl_up(z, 1, P);
-        if (k == 0) zm = 0.0;
-        const double xs = sig_u - lam_u * zm - mu_u * z;
-    
-        // interior back-substitution, in place: r[t] becomes x[t]
-        r[M - 1] = z;
+                    for (int d = 1; d < P; d <<= 1) part += __shfl_xor(part, d, P);
+                    mx += part * tp.inv_sqrt_nxnz / tp.wsum_y;
+                }
 #pragma unroll
-        for (int t = M - 2; t >= 1; --t) r[t] = r[t] - al[t] * xs - ga[t] * r[t + 1];
-        r[0] = xs;
-    
-        if (pinned) {
-            // null mode: zero volume-weighted mean
-            double swx = 0.0, sww = 0.0;
-#pragma unroll
-            for (int t = 0; t < M; ++t) {
-                swx += sw[s + t] * r[t];
-                sww += sw[s + t];
+                for (int t = 0; t < M; ++t)
+                    if (s + t < n) r[t] -= mx;
             }
 #pragma unroll
-            for (int d = 1; d < P; d <<= 1) {
-                swx += __shfl_xor(swx, d, P);
-                sww += __shfl_xor(sww, d, P);
+            for (int t = 0; t < M; ++t) sx[(s + t) * LDR + p] = r[t];
+
+            if (pinned && k == 0 && tp.record_mean) tp.bmean[job] = removed * tp.inv_sqrt_nxnz;
+            if (a0 == 0 && c == 0 && tid == 0 && jb.info) {
+                ibs_solve_info *inf = static_cast<ibs_solve_info *>(jb.info);
+                const double rm = removed * tp.inv_sqrt_nxnz;
+                const bool bad = pois && tp.strict && fabs(removed) > 1e-10 * rms;
+                inf->iters = 1;
+                inf->status = bad ? IBS_ERR_INCOMPATIBLE_RHS : IBS_OK;
+                inf->rel_residual = 0.0;
+                inf->rel_correction = 0.0;
+                inf->removed_mean = pois ? rm : 0.0;
             }
-            double mx = swx / sww;
-            if (tp.xsum) {
-                // refinement: steer the correction so that x + d has zero
-                // weighted mean (in this pencil's normalisation)
-                const double *xs = tp.xsum + (size_t)job * XSUM_SLOTS;
-                double part = 0.0;
-                for (int q = k; q < tp.nxsum; q += P) part += xs[q];
-#pragma unroll
-                for (int d = 1; d < P; d <<= 1) part += __shfl_xor(part, d, P);
-                mx += part * tp.inv_sqrt_nxnz / tp.wsum_y;
-            }
-#pragma unroll
-            for (int t = 0; t < M; ++t)
-                if (s + t < n) r[t] -= mx;
-        }
-#pragma unroll
-        for (int t = 0; t < M; ++t) sx[(s + t) * LDR + p] = r[t];
-    
-        if (pinned && k == 0 && tp.record_mean) tp.bmean[job] = removed * tp.inv_sqrt_nxnz;
-        if (a0 == 0 && c == 0 && tid == 0 && jb.info) {
-            ibs_solve_info *inf = static_cast<ibs_solve_info *>(jb.info);
-            const double rm = removed * tp.inv_sqrt_nxnz;
-            const bool bad = pois && tp.strict && fabs(removed) > 1e-10 * rms;
-            inf->iters = 1;
-            inf->status = bad ? IBS_ERR_INCOMPATIBLE_RHS : IBS_OK;
-            inf->rel_residual = 0.0;
-            inf->rel_correction = 0.0;
-            inf->removed_mean = pois ? rm : 0.0;
-        }
+        }  // live
         __syncthreads();
-        T *__restrict__ base = reinterpret_cast<T *>(jb.out) + (size_t)c * n * nx + a0 + lcol;
+        const auto rs = plane_rsrc(job, c, live);
+        const uint32_t voff = (uint32_t)(a0 + lcol) * sizeof(T) + (uint32_t)lrow * row_bytes;
 #pragma unroll
-        for (int r2 = 0; r2 < M; ++r2) {
-            const int j = lrow + P * r2;
-            if (j < n) base[(size_t)j * nx] = (T)sx[j * LDR + lcol];
-        }
+        for (int r2 = 0; r2 < M; ++r2)
+            buf_store<T>((T)sx[(lrow + P * r2) * LDR + lcol], rs, voff + r2 * P * row_bytes, 0);
     };
     const int G = gridDim.x;
-    if ((int)blockIdx.x < ntiles) fetch(blockIdx.x, pfa);
-    if ((int)blockIdx.x + G < ntiles) fetch(blockIdx.x + G, pfb);
+    fetch(blockIdx.x, pfa, lxa, lza);
+    fetch(blockIdx.x + G, pfb, lxb, lzb);
     for (int tile = blockIdx.x; tile < ntiles; tile += 2 * G) {
-        process(tile, pfa);
-        if (tile + G < ntiles) process(tile + G, pfb);
+        process(tile, pfa, lxa, lza);
+        if (tile + G < ntiles) process(tile + G, pfb, lxb, lzb);
     }
 }
 
 template <typename T, int P, int M>
 static hipError_t launch_pm(const JobSet &js, const TriParams &tp, hipStream_t s)
 {
-    // persistent blocks walk the tiles (job, z-mode, 16 x-modes) in order
+    // persistent blocks walk the tiles (job, z-mode, 16 x-modes) in order;
+    // as many blocks as are resident at once, so that every block's tiles
+    // run back to back
+    static const int resident = [] {
+        int per_cu = 0, dev = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tridiag_kernel<T, P, M>, 16 * P, 0) !=
+                hipSuccess ||
+            hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 1024;
+        return per_cu * cus > 0 ? per_cu * cus : 1024;
+    }();
     const int ntx = tp.nx / 16;
     const int ntiles = ntx * tp.nz * js.n;
-    const int grid = ntiles < 1024 ? ntiles : 1024;
+    const int grid = ntiles < resident ? ntiles : resident;
     hipLaunchKernelGGL((tridiag_kernel<T, P, M>), dim3(grid), dim3(16 * P), 0, s, js, tp, ntx,
                        ntiles);
     return hipGetLastError();
