@@ -116,6 +116,8 @@ def main():
 
     def run_path(precision):
         S = ibs.Solver(n, n, n, beta=beta, precision=precision)
+        # measured tile shapes for this grid (set-up, outside the timed region)
+        tiles = S.autotune() if precision == ibs.IBS_FP64 else None
         xu, xv, xw = S.empty(1), S.empty(2), S.empty(3)
         b = S.empty(0)
         phi = S.empty(0)
@@ -157,7 +159,7 @@ def main():
         torch.cuda.synchronize()
         pinfo = S.read_info(0)
         S.close()
-        return dict(ms=ms, per=per, kern=kern, hinfo=infos, pinfo=pinfo)
+        return dict(ms=ms, per=per, kern=kern, hinfo=infos, pinfo=pinfo, tiles=tiles)
 
     def roofline(kern, steps):
         dom_name = max(kern, key=lambda k: kern[k]["ms"])
@@ -192,7 +194,7 @@ def main():
             value=4 * cells / (r["ms"] * 1e-3) / 1e6, ms_per_step=r["ms"],
             latency_ms={"p50": float(np.percentile(r["per"], 50)),
                         "p99": float(np.percentile(r["per"], 99))},
-            roofline=roof, kernels=brk,
+            roofline=roof, kernels=brk, tiles=r["tiles"],
             passes={"helmholtz": r["hinfo"][0].iters, "poisson": r["pinfo"].iters},
             predicted_rel_err={"helmholtz": max(i.rel_residual for i in r["hinfo"]),
                                "poisson": r["pinfo"].rel_residual} if path == "refined" else None,

@@ -248,6 +248,24 @@ ibs_status ibs_profile(ibs_plan plan, int32_t enable);
 ibs_status ibs_profile_read(ibs_plan plan, int32_t kernel, double *ms, int64_t *launches,
                             double *flops, double *bytes);
 
+/* Measured choice of launch shapes.  Some kernels come in several tile
+ * shapes that compute every output element with the same operations in the
+ * same order (so results are bitwise identical whichever is used) but run
+ * at different speeds on a given grid.  ibs_autotune() times each candidate
+ * of each such knob on the plan's own grid, using `scratch` (device memory
+ * of at least ibs_autotune_bytes() bytes, contents overwritten), keeps the
+ * fastest in the plan, and writes the chosen indices to `choices`
+ * (IBS_NUM_TUNE entries; may be NULL; -1 for a knob that does not apply to
+ * this grid).  It synchronises `stream`, so it belongs to set-up, not to a
+ * captured or timed sequence.  The plan must have been uploaded.
+ * ibs_plan_set_tiles() restores choices saved earlier for the same grid
+ * (entries < 0 keep the default; out-of-range entries are rejected). */
+#define IBS_NUM_TUNE 2   /* 0: folded FP64 x transform, 1: folded FP64 z transform */
+ibs_status ibs_autotune_bytes(ibs_plan plan, size_t *bytes);
+ibs_status ibs_autotune(ibs_plan plan, void *scratch, size_t scratch_bytes, int32_t *choices,
+                        hipStream_t stream);
+ibs_status ibs_plan_set_tiles(ibs_plan plan, const int32_t *choices, int32_t n);
+
 /* Thread-local text of the last error (never NULL). */
 const char *ibs_last_error(void);
 

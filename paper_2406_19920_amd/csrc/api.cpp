@@ -109,23 +109,34 @@ static ibs_status run_fp64_pipeline_multi(Plan &p, JobSet js, double *const *W, 
 {
     hipError_t e;
     const double cells = total_cells(js, p);
-    const double xflop = 2.0 * p.nx * cells, zflop = 2.0 * p.nz * cells, rw = 16.0 * cells;
+    // matrix-core flops per cell: 2n for the plain transform, n folded
+    const bool fx = can_fold(p.nx), fz = can_fold(p.nz);
+    const double xflop = (fx ? 1.0 : 2.0) * p.nx * cells, zflop = (fz ? 1.0 : 2.0) * p.nz * cells;
+    const double rw = 16.0 * cells;
     const double *xb_f = blob_ptr(p, p.lay.bx_fwd), *xb_i = blob_ptr(p, p.lay.bx_inv);
     const double *za_f = blob_ptr(p, p.lay.az_fwd), *za_i = blob_ptr(p, p.lay.az_inv);
+    auto xform = [&](bool inverse) {
+        return fx ? launch_xfold_f64(js, p, inverse, s)
+                  : launch_xgemm_f64(js, p.nz, p.nx, p.nx, inverse ? xb_i : xb_f, s);
+    };
+    auto zform = [&](bool inverse) {
+        return fz ? launch_zfold_f64(js, p, inverse, s)
+                  : launch_zgemm_f64(js, p.nz, p.nz, p.nx, inverse ? za_i : za_f, s);
+    };
     for (int q = 0; q < js.n; ++q) js.j[q].out = W[q];
-    e = timed(p, PK_XGEMM, xflop, rw, s, [&] { return launch_xgemm_f64(js, p.nz, p.nx, p.nx, xb_f, s); });
+    e = timed(p, PK_XGEMM, xflop, rw, s, [&] { return xform(false); });
     if (e != hipSuccess) return hip_fail(e, "x forward");
     for (int q = 0; q < js.n; ++q) { js.j[q].in = W[q]; js.j[q].out = X[q]; }
-    e = timed(p, PK_ZGEMM, zflop, rw, s, [&] { return launch_zgemm_f64(js, p.nz, p.nz, p.nx, za_f, s); });
+    e = timed(p, PK_ZGEMM, zflop, rw, s, [&] { return zform(false); });
     if (e != hipSuccess) return hip_fail(e, "z forward");
     for (int q = 0; q < js.n; ++q) js.j[q].in = X[q];
     e = timed(p, PK_TRIDIAG, 20.0 * cells, rw, s, [&] { return launch_tridiag_f64(js, p, poisson, s); });
     if (e != hipSuccess) return hip_fail(e, "tridiagonal");
     for (int q = 0; q < js.n; ++q) { js.j[q].in = X[q]; js.j[q].out = W[q]; }
-    e = timed(p, PK_ZGEMM, zflop, rw, s, [&] { return launch_zgemm_f64(js, p.nz, p.nz, p.nx, za_i, s); });
+    e = timed(p, PK_ZGEMM, zflop, rw, s, [&] { return zform(true); });
     if (e != hipSuccess) return hip_fail(e, "z inverse");
     for (int q = 0; q < js.n; ++q) { js.j[q].in = W[q]; js.j[q].out = X[q]; }
-    e = timed(p, PK_XGEMM, xflop, rw, s, [&] { return launch_xgemm_f64(js, p.nz, p.nx, p.nx, xb_i, s); });
+    e = timed(p, PK_XGEMM, xflop, rw, s, [&] { return xform(true); });
     if (e != hipSuccess) return hip_fail(e, "x inverse");
     return IBS_OK;
 }
@@ -430,6 +441,91 @@ ibs_status ibs_profile_read(ibs_plan plan, int32_t kernel, double *ms, int64_t *
     if (launches) *launches = p.prof.launches[kernel];
     if (flops) *flops = p.prof.flops[kernel];
     if (bytes) *bytes = p.prof.bytes[kernel];
+    return IBS_OK;
+}
+
+static size_t autotune_doubles(const Plan &p) { return 2 * (size_t)p.nz * (p.ny + 1) * p.nx; }
+
+ibs_status ibs_autotune_bytes(ibs_plan plan, size_t *bytes)
+{
+    if (!plan || !bytes) { set_error("plan and bytes must be non-NULL"); return IBS_ERR_INVALID_ARG; }
+    *bytes = autotune_doubles(*reinterpret_cast<Plan *>(plan)) * sizeof(double);
+    return IBS_OK;
+}
+
+ibs_status ibs_autotune(ibs_plan plan, void *scratch, size_t scratch_bytes, int32_t *choices,
+                        hipStream_t stream)
+{
+    if (!plan || !scratch) { set_error("plan and scratch must be non-NULL"); return IBS_ERR_INVALID_ARG; }
+    Plan &p = *reinterpret_cast<Plan *>(plan);
+    if (!p.dev_const) { set_error("solver_plan_upload() has not been called"); return IBS_ERR_NOT_UPLOADED; }
+    const size_t nd = autotune_doubles(p);
+    if (scratch_bytes < nd * sizeof(double)) {
+        set_error("scratch smaller than ibs_autotune_bytes()");
+        return IBS_ERR_WORKSPACE_TOO_SMALL;
+    }
+    double *A = static_cast<double *>(scratch), *B = A + nd / 2;
+    hipError_t e = hipMemsetAsync(scratch, 0, nd * sizeof(double), stream);
+    if (e != hipSuccess) return hip_fail(e, "autotune scratch clear");
+    // one pressure-sized field, forward then inverse transform per trial
+    JobSet js{};
+    js.n = 1;
+    js.j[0].rows = p.ny;
+    js.j[0].kind = KIND_P;
+    hipEvent_t ev[2];
+    if ((e = hipEventCreate(&ev[0])) != hipSuccess) return hip_fail(e, "autotune event");
+    if ((e = hipEventCreate(&ev[1])) != hipSuccess) {
+        hipEventDestroy(ev[0]);
+        return hip_fail(e, "autotune event");
+    }
+    struct Knob { int id; bool applies; hipError_t (*launch)(const JobSet &, const Plan &, bool, hipStream_t); };
+    const Knob knobs[NUM_TUNE] = {{TUNE_XFOLD, can_fold(p.nx), launch_xfold_f64},
+                                  {TUNE_ZFOLD, can_fold(p.nz), launch_zfold_f64}};
+    ibs_status st = IBS_OK;
+    for (const Knob &k : knobs) {
+        if (!k.applies) { p.tune[k.id] = -1; continue; }
+        int best = 0;
+        float best_ms = 0.f;
+        for (int cand = 0; cand < fold_candidates() && st == IBS_OK; ++cand) {
+            p.tune[k.id] = cand;
+            auto trial = [&](int reps) {
+                hipError_t r = hipSuccess;
+                for (int i = 0; i < reps && r == hipSuccess; ++i) {
+                    js.j[0].in = A; js.j[0].out = B;
+                    r = k.launch(js, p, false, stream);
+                    if (r != hipSuccess) break;
+                    js.j[0].in = B; js.j[0].out = A;
+                    r = k.launch(js, p, true, stream);
+                }
+                return r;
+            };
+            float ms = 0.f;
+            if ((e = trial(1)) != hipSuccess || (e = hipEventRecord(ev[0], stream)) != hipSuccess ||
+                (e = trial(3)) != hipSuccess || (e = hipEventRecord(ev[1], stream)) != hipSuccess ||
+                (e = hipEventSynchronize(ev[1])) != hipSuccess ||
+                (e = hipEventElapsedTime(&ms, ev[0], ev[1])) != hipSuccess) {
+                st = hip_fail(e, "autotune trial");
+                break;
+            }
+            if (cand == 0 || ms < best_ms) { best = cand; best_ms = ms; }
+        }
+        p.tune[k.id] = best;
+    }
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+    if (st != IBS_OK) return st;
+    if (choices)
+        for (int i = 0; i < NUM_TUNE; ++i) choices[i] = p.tune[i];
+    return IBS_OK;
+}
+
+ibs_status ibs_plan_set_tiles(ibs_plan plan, const int32_t *choices, int32_t n)
+{
+    if (!plan || !choices || n < 0 || n > NUM_TUNE) { set_error("bad plan, choices or count"); return IBS_ERR_INVALID_ARG; }
+    Plan &p = *reinterpret_cast<Plan *>(plan);
+    for (int i = 0; i < n; ++i)
+        if (choices[i] >= fold_candidates()) { set_error("tile choice out of range"); return IBS_ERR_INVALID_ARG; }
+    for (int i = 0; i < n; ++i) p.tune[i] = choices[i] < 0 ? -1 : choices[i];
     return IBS_OK;
 }
 

@@ -19,8 +19,11 @@ enum { KIND_P = 0, KIND_C = 1, KIND_F = 2, NUM_KINDS = 3 };
 
 // Byte offsets of the tables inside the device constant blob.
 struct BlobLayout {
-    size_t bx_fwd, bx_inv;   // x transform as B operand of C = A B, swizzled
-    size_t az_fwd, az_inv;   // z transform as A operand of C = A B, swizzled
+    size_t bx_fwd, bx_inv;   // x transform as B operand of C = A B, swizzled (nx % 32 != 0)
+    size_t az_fwd, az_inv;   // z transform as A operand of C = A B, swizzled (nz % 32 != 0)
+    // folded transforms (n % 32 == 0): the two H x H factors (H = n/2)
+    size_t fx_fwd_c, fx_fwd_s, fx_inv_c, fx_inv_s;   // B-operand swizzle
+    size_t fz_fwd_c, fz_fwd_s, fz_inv_c, fz_inv_s;   // A-operand swizzle
     size_t lam_x, lam_z;     // eigenvalues (double)
     size_t lo[NUM_KINDS], di[NUM_KINDS], up[NUM_KINDS];  // y operator rows
     size_t wy;               // Delta_j (pressure weights), ny doubles
@@ -57,8 +60,13 @@ struct Profile {
     long long launches[NUM_PK] = {};
 };
 
+// Tunable launch shapes (results do not depend on the choice).
+enum { TUNE_XFOLD = 0, TUNE_ZFOLD, NUM_TUNE };
+static_assert(NUM_TUNE == IBS_NUM_TUNE, "tuning knobs and the ABI disagree");
+
 struct Plan {
     ibs_grid_desc desc;
+    int tune[NUM_TUNE] = {-1, -1};   // candidate index per knob; -1 = default
     int nx, ny, nz;
     double hx, hz;
     std::vector<double> yf, yc, dyc, dyf;          // grid
@@ -98,6 +106,11 @@ hipError_t launch_xgemm_f64(const JobSet &js, int nz, int K, int N,
                             const double *bs, hipStream_t s);
 // C[M x Ncol] = As * B, As the swizzled M x K matrix, B row-major (K x Ncol),
 // Ncol = rows * nx per job.
+// Folded FP64 transforms (valid when can_fold(n)).
+bool can_fold(int n);
+int fold_candidates();
+hipError_t launch_xfold_f64(const JobSet &js, const Plan &p, bool inverse, hipStream_t s);
+hipError_t launch_zfold_f64(const JobSet &js, const Plan &p, bool inverse, hipStream_t s);
 hipError_t launch_zgemm_f64(const JobSet &js, int M, int K, int nx,
                             const double *as, hipStream_t s);
 // Tridiagonal pencils along y, in place on js.j[q].out ([nz][rows][nx]).

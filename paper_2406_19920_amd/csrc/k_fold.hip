@@ -1,0 +1,390 @@
+// Folded eigen-transforms of the periodic directions (FP64 matrix cores).
+//
+// The real Fourier basis Q (Appendix A: cos and sin modes, plus the mean
+// and the alternating Nyquist mode) has a mirror symmetry in the grid
+// index: with H = N/2, Q[N-i][a] = Q[i][a] for the cos, mean and Nyquist
+// columns and Q[N-i][a] = -Q[i][a] for the sin columns.  So, per row,
+//   forward:  E[i] = X[i] + X[N-i],  O[i] = X[i] - X[N-i]   (1 <= i < H)
+//             cos outputs  = E Qc (+ the X[H] term),
+//             sin outputs  = O Qs,
+//   inverse:  U = Xc Qc^T (+ the Nyquist term),  V = Xs Qs^T,
+//             X[i] = U[i] + V[i],  X[N-i] = U[i] - V[i],
+// which are two H x H products instead of one N x N product: half the
+// matrix-core work of the plain transform.  The odd cases are the four
+// self-mirrored points: X[0] (the E slot 0), X[H] (carried in the unused
+// O slot 0), the Nyquist output of the forward transform and the X[H]
+// output of the inverse (both alternating sums, done on the vector units
+// while the K loop runs).
+//
+// Spectral layout (as for the plain transform): index a < H is cos mode a
+// (a = 0 the mean), a = H the Nyquist mode, H + k (1 <= k < H) sin mode k.
+// Instruction layout as in the plain kernels: lane l feeds A(row l%16,
+// k 4(l/16)+t) and B(k 4(l/16)+t, col l%16), t = 0..3; result element q
+// is row l/16 + 4q, column l%16.  Requires H a multiple of 16.
+#include "ibs_internal.h"
+
+// No implicit multiply-add fusion in this file: every rounding is written
+// out (fma() where wanted), so that all tile shapes give the same bits.
+#pragma clang fp contract(off)
+
+namespace ibs {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+static __device__ __forceinline__ d4 mfma(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// x transform of every row of a [nz][rows][N] field.  Forward: the
+// physical row -> spectral row; inverse: spectral -> physical.  bc, bs:
+// the two H x H factors, swizzled as B operands.  A wave owns WM row
+// blocks and WN column blocks of both factors.
+template <int WM, int WN, bool INV>
+__global__ __launch_bounds__(256) void xfold_f64_kernel(JobSet js, int nz, int N,
+                                                        const double *__restrict__ bc,
+                                                        const double *__restrict__ bs, int wgn,
+                                                        double s0, double s1)
+{
+    const FieldJob &jb = js.j[blockIdx.z];
+    const int M = nz * jb.rows;
+    const int H = N >> 1, HB = H >> 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wgm = 4 / wgn;
+    const int wm = wave / wgn, wn = wave % wgn;
+    const int row0 = (blockIdx.x * wgm + wm) * (16 * WM);
+    const int cb0 = (blockIdx.y * wgn + wn) * WN;
+    if (row0 >= M || cb0 >= HB) return;
+    const int nrb = min(WM, (M - row0) >> 4);
+    const int ncb = min(WN, HB - cb0);
+    const int li = lane & 15, lg = lane >> 4;
+    const double *__restrict__ A = jb.in;
+    double *__restrict__ C = jb.out;
+
+    d4 acc_c[WM][WN], acc_s[WM][WN];
+    double nyq[WM];
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+        nyq[i] = 0.0;
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+            acc_c[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
+            acc_s[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
+        }
+    }
+    const double *arow[WM];
+#pragma unroll
+    for (int i = 0; i < WM; ++i) arow[i] = A + (size_t)(row0 + 16 * i + (i < nrb ? li : 0)) * N;
+
+    for (int kc = 0; kc < HB; ++kc) {
+        const int k0 = 16 * kc + 4 * lg;
+        d4 xc[WM], xs[WM];   // forward: E, O; inverse: cos and sin inputs
+#pragma unroll
+        for (int i = 0; i < WM; ++i) {
+            if (i < nrb) {
+                if (!INV) {
+                    const d4 pv = *reinterpret_cast<const d4 *>(arow[i] + k0);
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int kk = k0 + t;
+                        const double mv = arow[i][kk == 0 ? H : N - kk];
+                        xc[i][t] = kk == 0 ? pv[t] : pv[t] + mv;
+                        xs[i][t] = kk == 0 ? mv : pv[t] - mv;
+                    }
+                    // Nyquist output: sum of (-1)^i E[i]
+                    nyq[i] += (xc[i][0] - xc[i][1]) + (xc[i][2] - xc[i][3]);
+                } else {
+                    xc[i] = *reinterpret_cast<const d4 *>(arow[i] + k0);
+                    xs[i] = *reinterpret_cast<const d4 *>(arow[i] + H + k0);
+                    // physical point H: sum of Q[H][a] Xc[a], Q[H][a] = w_a (-1)^a
+                    nyq[i] = fma(k0 == 0 ? s0 : s1, xc[i][0], nyq[i]);
+                    nyq[i] = fma(-s1, xc[i][1], nyq[i]);
+                    nyq[i] = fma(s1, xc[i][2], nyq[i]);
+                    nyq[i] = fma(-s1, xc[i][3], nyq[i]);
+                }
+            } else {
+                xc[i] = (d4){0, 0, 0, 0};
+                xs[i] = (d4){0, 0, 0, 0};
+            }
+        }
+        d4 b_c[WN], b_s[WN];
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+            if (j < ncb) {
+                const size_t o = (((size_t)kc * HB + cb0 + j) * 64 + lane) * 4;
+                b_c[j] = *reinterpret_cast<const d4 *>(bc + o);
+                b_s[j] = *reinterpret_cast<const d4 *>(bs + o);
+            } else {
+                b_c[j] = (d4){0, 0, 0, 0};
+                b_s[j] = (d4){0, 0, 0, 0};
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WN; ++j) {
+                    acc_c[i][j] = mfma(xc[i][t], b_c[j][t], acc_c[i][j]);
+                    acc_s[i][j] = mfma(xs[i][t], b_s[j][t], acc_s[i][j]);
+                }
+    }
+
+    const double sH = (H & 1) ? -s0 : s0;   // Q[H][H]
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+        if (i >= nrb) break;
+        double ny = nyq[i];
+        ny += __shfl_xor(ny, 16, 64);
+        ny += __shfl_xor(ny, 32, 64);   // every lane of row li holds its sum
+        const size_t rb = (size_t)(row0 + 16 * i);
+        double ah[4];                   // A[row][H] of the lane's output rows
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ah[q] = A[(rb + lg + 4 * q) * N + H];
+        if (!INV) {
+            double nyr[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) nyr[q] = __shfl(ny, lg + 4 * q, 64);
+#pragma unroll
+            for (int j = 0; j < WN; ++j) {
+                if (j >= ncb) break;
+                const int a = 16 * (cb0 + j) + li;
+                const double wa = (a == 0 ? s0 : s1) * ((a & 1) ? -1.0 : 1.0);   // Q[H][a]
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const size_t o = (rb + lg + 4 * q) * N;
+                    C[o + a] = fma(ah[q], wa, acc_c[i][j][q]);
+                    double sv = acc_s[i][j][q];
+                    if (a == 0) sv = fma(s0, nyr[q], sv);   // spectral index H: Nyquist
+                    C[o + H + a] = sv;
+                }
+            }
+        } else {
+            if (cb0 == 0 && lg == 0) {   // physical point H of row li
+                const size_t r = rb + li;
+                C[r * N + H] = fma(A[r * N + H], sH, ny);
+            }
+#pragma unroll
+            for (int j = 0; j < WN; ++j) {
+                if (j >= ncb) break;
+                const int ii = 16 * (cb0 + j) + li;
+                const double sg = (ii & 1) ? -s0 : s0;   // Q[ii][H]
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const size_t o = (rb + lg + 4 * q) * N;
+                    const double u = fma(ah[q], sg, acc_c[i][j][q]), v = acc_s[i][j][q];
+                    C[o + ii] = u + v;
+                    if (ii != 0) C[o + N - ii] = u - v;
+                }
+            }
+        }
+    }
+}
+
+// z transform: the field viewed as N x Ncol (N = nz planes, Ncol =
+// rows*nx), multiplied from the left.  ac, as: the two H x H factors,
+// swizzled as A operands.  A wave owns WM row blocks (of both factors) and
+// WN column blocks.
+template <int WM, int WN, bool INV>
+__global__ __launch_bounds__(256) void zfold_f64_kernel(JobSet js, int N, int nx,
+                                                        const double *__restrict__ ac,
+                                                        const double *__restrict__ as, int wgn,
+                                                        double s0, double s1)
+{
+    const FieldJob &jb = js.j[blockIdx.z];
+    const int Ncol = jb.rows * nx;
+    const int H = N >> 1, HB = H >> 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wgm = 4 / wgn;
+    const int wm = wave / wgn, wn = wave % wgn;
+    const int rb0 = (blockIdx.y * wgm + wm) * WM;
+    const int col0 = (blockIdx.x * wgn + wn) * (16 * WN);
+    if (rb0 >= HB || col0 >= Ncol) return;
+    const int nrb = min(WM, HB - rb0);
+    const int ncb = min(WN, (Ncol - col0) >> 4);
+    const int li = lane & 15, lg = lane >> 4;
+    const double *__restrict__ B = jb.in;
+    double *__restrict__ C = jb.out;
+
+    d4 acc_c[WM][WN], acc_s[WM][WN];
+    double nyq[WN];
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+        nyq[j] = 0.0;
+#pragma unroll
+        for (int i = 0; i < WM; ++i) {
+            acc_c[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
+            acc_s[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
+        }
+    }
+    for (int kc = 0; kc < HB; ++kc) {
+        const int k0 = 16 * kc + 4 * lg;
+        d4 a_c[WM], a_s[WM];
+#pragma unroll
+        for (int i = 0; i < WM; ++i) {
+            if (i < nrb) {
+                const size_t o = (((size_t)kc * HB + rb0 + i) * 64 + lane) * 4;
+                a_c[i] = *reinterpret_cast<const d4 *>(ac + o);
+                a_s[i] = *reinterpret_cast<const d4 *>(as + o);
+            } else {
+                a_c[i] = (d4){0, 0, 0, 0};
+                a_s[i] = (d4){0, 0, 0, 0};
+            }
+        }
+        d4 xc[WN], xs[WN];
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+            if (j < ncb) {
+                const double *col = B + col0 + 16 * j + li;
+                if (!INV) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int kk = k0 + t;
+                        const double pv = col[(size_t)kk * Ncol];
+                        const double mv = col[(size_t)(kk == 0 ? H : N - kk) * Ncol];
+                        xc[j][t] = kk == 0 ? pv : pv + mv;
+                        xs[j][t] = kk == 0 ? mv : pv - mv;
+                    }
+                    nyq[j] += (xc[j][0] - xc[j][1]) + (xc[j][2] - xc[j][3]);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        xc[j][t] = col[(size_t)(k0 + t) * Ncol];
+                        xs[j][t] = col[(size_t)(H + k0 + t) * Ncol];
+                    }
+                    nyq[j] = fma(k0 == 0 ? s0 : s1, xc[j][0], nyq[j]);
+                    nyq[j] = fma(-s1, xc[j][1], nyq[j]);
+                    nyq[j] = fma(s1, xc[j][2], nyq[j]);
+                    nyq[j] = fma(-s1, xc[j][3], nyq[j]);
+                }
+            } else {
+                xc[j] = (d4){0, 0, 0, 0};
+                xs[j] = (d4){0, 0, 0, 0};
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WN; ++j) {
+                    acc_c[i][j] = mfma(a_c[i][t], xc[j][t], acc_c[i][j]);
+                    acc_s[i][j] = mfma(a_s[i][t], xs[j][t], acc_s[i][j]);
+                }
+    }
+
+    const double sH = (H & 1) ? -s0 : s0;
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+        if (j >= ncb) break;
+        const size_t cc = (size_t)(col0 + 16 * j + li);
+        double ny = nyq[j];
+        ny += __shfl_xor(ny, 16, 64);
+        ny += __shfl_xor(ny, 32, 64);   // every lane of column li holds its sum
+        const double bh = B[(size_t)H * Ncol + cc];
+        if (INV && rb0 == 0 && lg == 0) C[(size_t)H * Ncol + cc] = fma(bh, sH, ny);
+#pragma unroll
+        for (int i = 0; i < WM; ++i) {
+            if (i >= nrb) break;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = 16 * (rb0 + i) + lg + 4 * q;   // 0 <= r < H
+                if (!INV) {
+                    const double wr = (r == 0 ? s0 : s1) * ((r & 1) ? -1.0 : 1.0);   // Q[H][r]
+                    C[(size_t)r * Ncol + cc] = fma(bh, wr, acc_c[i][j][q]);
+                    double sv = acc_s[i][j][q];
+                    if (r == 0) sv = fma(s0, ny, sv);   // plane H: Nyquist
+                    C[(size_t)(H + r) * Ncol + cc] = sv;
+                } else {
+                    const double u = fma(bh, (r & 1) ? -s0 : s0, acc_c[i][j][q]), v = acc_s[i][j][q];
+                    C[(size_t)r * Ncol + cc] = u + v;
+                    if (r != 0) C[(size_t)(N - r) * Ncol + cc] = u - v;
+                }
+            }
+        }
+    }
+}
+
+static int max_rows(const JobSet &js)
+{
+    int r = 0;
+    for (int q = 0; q < js.n; ++q) r = js.j[q].rows > r ? js.j[q].rows : r;
+    return r;
+}
+
+bool can_fold(int n) { return n % 32 == 0; }
+
+// Tile candidates (row blocks x column blocks per wave).  Every candidate
+// sums each output element in the same order, so the choice changes only
+// the speed, never the result.
+static constexpr int XF_WM[] = {2, 4, 4, 1};
+static constexpr int XF_WN[] = {2, 1, 2, 4};
+static constexpr int ZF_WM[] = {2, 1, 2, 4};
+static constexpr int ZF_WN[] = {2, 4, 4, 1};
+int fold_candidates() { return 4; }
+
+template <int WM, int WN>
+static hipError_t xfold_launch(const JobSet &js, const Plan &p, bool inverse, hipStream_t s)
+{
+    const int N = p.nx, HB = N / 32;
+    const int M = p.nz * max_rows(js);
+    const int nwave_cols = (HB + WN - 1) / WN;
+    const int wgn = nwave_cols >= 4 ? 4 : (nwave_cols >= 2 ? 2 : 1);
+    const int wgm = 4 / wgn;
+    dim3 grid((M + 16 * WM * wgm - 1) / (16 * WM * wgm), (nwave_cols + wgn - 1) / wgn, js.n);
+    const double *bc = blob_ptr(p, inverse ? p.lay.fx_inv_c : p.lay.fx_fwd_c);
+    const double *bs = blob_ptr(p, inverse ? p.lay.fx_inv_s : p.lay.fx_fwd_s);
+    const double s0 = 1.0 / std::sqrt((double)N), s1 = std::sqrt(2.0 / (double)N);
+    if (inverse)
+        hipLaunchKernelGGL((xfold_f64_kernel<WM, WN, true>), grid, dim3(256), 0, s, js, p.nz, N, bc, bs,
+                           wgn, s0, s1);
+    else
+        hipLaunchKernelGGL((xfold_f64_kernel<WM, WN, false>), grid, dim3(256), 0, s, js, p.nz, N, bc,
+                           bs, wgn, s0, s1);
+    return hipGetLastError();
+}
+
+template <int WM, int WN>
+static hipError_t zfold_launch(const JobSet &js, const Plan &p, bool inverse, hipStream_t s)
+{
+    const int N = p.nz, HB = N / 32;
+    const int Ncol = max_rows(js) * p.nx;
+    const int nwave_rows = (HB + WM - 1) / WM;
+    const int wgm = nwave_rows >= 4 ? 4 : (nwave_rows >= 2 ? 2 : 1);
+    const int wgn = 4 / wgm;
+    dim3 grid((Ncol + 16 * WN * wgn - 1) / (16 * WN * wgn), (nwave_rows + wgm - 1) / wgm, js.n);
+    const double *ac = blob_ptr(p, inverse ? p.lay.fz_inv_c : p.lay.fz_fwd_c);
+    const double *as = blob_ptr(p, inverse ? p.lay.fz_inv_s : p.lay.fz_fwd_s);
+    const double s0 = 1.0 / std::sqrt((double)N), s1 = std::sqrt(2.0 / (double)N);
+    if (inverse)
+        hipLaunchKernelGGL((zfold_f64_kernel<WM, WN, true>), grid, dim3(256), 0, s, js, N, p.nx, ac, as,
+                           wgn, s0, s1);
+    else
+        hipLaunchKernelGGL((zfold_f64_kernel<WM, WN, false>), grid, dim3(256), 0, s, js, N, p.nx, ac,
+                           as, wgn, s0, s1);
+    return hipGetLastError();
+}
+
+hipError_t launch_xfold_f64(const JobSet &js, const Plan &p, bool inverse, hipStream_t s)
+{
+    switch (p.tune[TUNE_XFOLD] < 0 ? 0 : p.tune[TUNE_XFOLD]) {
+    case 0: return xfold_launch<XF_WM[0], XF_WN[0]>(js, p, inverse, s);
+    case 1: return xfold_launch<XF_WM[1], XF_WN[1]>(js, p, inverse, s);
+    case 2: return xfold_launch<XF_WM[2], XF_WN[2]>(js, p, inverse, s);
+    case 3: return xfold_launch<XF_WM[3], XF_WN[3]>(js, p, inverse, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_zfold_f64(const JobSet &js, const Plan &p, bool inverse, hipStream_t s)
+{
+    switch (p.tune[TUNE_ZFOLD] < 0 ? 0 : p.tune[TUNE_ZFOLD]) {
+    case 0: return zfold_launch<ZF_WM[0], ZF_WN[0]>(js, p, inverse, s);
+    case 1: return zfold_launch<ZF_WM[1], ZF_WN[1]>(js, p, inverse, s);
+    case 2: return zfold_launch<ZF_WM[2], ZF_WN[2]>(js, p, inverse, s);
+    case 3: return zfold_launch<ZF_WM[3], ZF_WN[3]>(js, p, inverse, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace ibs

@@ -72,6 +72,43 @@ static void swizzle_a(const double *A, int M, int K, double *out)
                     out[o++] = A[size_t(16 * bi + (l % 16)) * K + 16 * kc + 4 * (l / 16) + t];
 }
 
+// The two H x H factors of the folded transform (H = N/2), from the basis
+// Q[i][a] (grid index i, spectral index a; a < H cos and mean, a = H
+// Nyquist, H + k sin mode k).  Row index i < H is the grid point paired
+// with N - i; column index of s_* is k (k = 0 stands for the Nyquist mode).
+//   c[i][a]     = Q[i][a]                         (a < H)
+//   s_fwd[i][k] = Q[i][H+k] for i, k >= 1; s_fwd[0][0] = Q[H][H] (the O
+//                 slot 0 carries X[H], whose only odd-side weight is the
+//                 Nyquist one); other entries of row 0 / column 0 zero
+//   s_inv[i][k] = Q[i][H+k] for k >= 1, 0 for k = 0 (the Nyquist input is
+//                 even in i and is added outside the product)
+struct FoldFactors {
+    int h;
+    std::vector<double> c, s_fwd, s_inv;
+    FoldFactors(const std::vector<double> &Q, int N) : h(N / 2)
+    {
+        c.assign(size_t(h) * h, 0.0);
+        s_fwd.assign(size_t(h) * h, 0.0);
+        s_inv.assign(size_t(h) * h, 0.0);
+        for (int i = 0; i < h; ++i)
+            for (int a = 0; a < h; ++a) {
+                c[size_t(i) * h + a] = Q[size_t(i) * N + a];
+                if (a >= 1) {
+                    s_inv[size_t(i) * h + a] = Q[size_t(i) * N + h + a];
+                    if (i >= 1) s_fwd[size_t(i) * h + a] = Q[size_t(i) * N + h + a];
+                }
+            }
+        s_fwd[0] = Q[size_t(h) * N + h];
+    }
+    std::vector<double> transposed(const std::vector<double> &m) const
+    {
+        std::vector<double> t(m.size());
+        for (int i = 0; i < h; ++i)
+            for (int j = 0; j < h; ++j) t[size_t(j) * h + i] = m[size_t(i) * h + j];
+        return t;
+    }
+};
+
 // bfloat16 bits of a float, rounded to nearest even (finite inputs).
 static uint16_t bf16_rne(float f)
 {
@@ -235,10 +272,20 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     BlobLayout &L = p->lay;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
-    L.bx_fwd = take(sizeof(double) * nx * nx);
-    L.bx_inv = take(sizeof(double) * nx * nx);
-    L.az_fwd = take(sizeof(double) * nz * nz);
-    L.az_inv = take(sizeof(double) * nz * nz);
+    const bool fold_x = can_fold(nx), fold_z = can_fold(nz);
+    const size_t hx2 = size_t(nx / 2) * (nx / 2), hz2 = size_t(nz / 2) * (nz / 2);
+    L.bx_fwd = take(fold_x ? 0 : sizeof(double) * nx * nx);
+    L.bx_inv = take(fold_x ? 0 : sizeof(double) * nx * nx);
+    L.az_fwd = take(fold_z ? 0 : sizeof(double) * nz * nz);
+    L.az_inv = take(fold_z ? 0 : sizeof(double) * nz * nz);
+    L.fx_fwd_c = take(fold_x ? sizeof(double) * hx2 : 0);
+    L.fx_fwd_s = take(fold_x ? sizeof(double) * hx2 : 0);
+    L.fx_inv_c = take(fold_x ? sizeof(double) * hx2 : 0);
+    L.fx_inv_s = take(fold_x ? sizeof(double) * hx2 : 0);
+    L.fz_fwd_c = take(fold_z ? sizeof(double) * hz2 : 0);
+    L.fz_fwd_s = take(fold_z ? sizeof(double) * hz2 : 0);
+    L.fz_inv_c = take(fold_z ? sizeof(double) * hz2 : 0);
+    L.fz_inv_s = take(fold_z ? sizeof(double) * hz2 : 0);
     L.lam_x = take(sizeof(double) * nx);
     L.lam_z = take(sizeof(double) * nz);
     for (int kd = 0; kd < NUM_KINDS; ++kd) {
@@ -264,7 +311,18 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     auto put = [&](size_t off, const double *src, size_t n) {
         std::memcpy(p->blob.data() + off, src, n * sizeof(double));
     };
-    {
+    if (fold_x) {
+        FoldFactors f(p->qx, nx);
+        std::vector<double> tmp(hx2);
+        swizzle_b(f.c.data(), nx / 2, nx / 2, tmp.data());   // forward: E Qc
+        put(L.fx_fwd_c, tmp.data(), tmp.size());
+        swizzle_b(f.s_fwd.data(), nx / 2, nx / 2, tmp.data());   // forward: O Qs
+        put(L.fx_fwd_s, tmp.data(), tmp.size());
+        swizzle_b(f.transposed(f.c).data(), nx / 2, nx / 2, tmp.data());   // inverse: Xc Qc^T
+        put(L.fx_inv_c, tmp.data(), tmp.size());
+        swizzle_b(f.transposed(f.s_inv).data(), nx / 2, nx / 2, tmp.data());   // inverse: Xs Qs^T
+        put(L.fx_inv_s, tmp.data(), tmp.size());
+    } else {
         std::vector<double> tmp(size_t(nx) * nx), tr(size_t(nx) * nx);
         // x forward: C = X Q (contract over grid index i)
         swizzle_b(p->qx.data(), nx, nx, tmp.data());
@@ -275,7 +333,18 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
         swizzle_b(tr.data(), nx, nx, tmp.data());
         put(L.bx_inv, tmp.data(), tmp.size());
     }
-    {
+    if (fold_z) {
+        FoldFactors f(p->qz, nz);
+        std::vector<double> tmp(hz2);
+        swizzle_a(f.transposed(f.c).data(), nz / 2, nz / 2, tmp.data());   // forward: Qc^T E
+        put(L.fz_fwd_c, tmp.data(), tmp.size());
+        swizzle_a(f.transposed(f.s_fwd).data(), nz / 2, nz / 2, tmp.data());   // forward: Qs^T O
+        put(L.fz_fwd_s, tmp.data(), tmp.size());
+        swizzle_a(f.c.data(), nz / 2, nz / 2, tmp.data());   // inverse: Qc Xc
+        put(L.fz_inv_c, tmp.data(), tmp.size());
+        swizzle_a(f.s_inv.data(), nz / 2, nz / 2, tmp.data());   // inverse: Qs Xs
+        put(L.fz_inv_s, tmp.data(), tmp.size());
+    } else {
         std::vector<double> tmp(size_t(nz) * nz), tr(size_t(nz) * nz);
         // z forward: Xhat[c] = sum_k Q[k][c] X[k]  -> A = Q^T
         for (int k = 0; k < nz; ++k)

@@ -34,7 +34,10 @@ EXPORTS = ("solver_plan", "solver_plan_bytes", "solver_plan_upload", "solver_pla
            "solve_poisson", "solve_helmholtz_batch", "residual", "ibs_divergence",
            "ibs_correct", "ibs_plan_export", "ibs_profile", "ibs_profile_read",
            "ibs_batch_build", "ibs_batch_launch", "ibs_batch_destroy",
+           "ibs_autotune_bytes", "ibs_autotune", "ibs_plan_set_tiles",
            "ibs_last_error", "ibs_version")
+
+IBS_NUM_TUNE = 2
 
 PROFILE_KERNELS = ("xgemm_f64", "zgemm_f64", "tridiag_f64", "divergence", "correct", "residual",
                    "xgemm_split", "zgemm_split", "tridiag_f32", "update")
@@ -90,6 +93,9 @@ def _load():
     L.ibs_correct.argtypes = [vp, vp, vp, vp, vp, dbl, vp, vp, dbl, vp]
     L.ibs_plan_export.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(sz)]
     L.ibs_profile.argtypes = [vp, i32]
+    L.ibs_autotune_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    L.ibs_autotune.argtypes = [vp, vp, sz, ctypes.POINTER(i32), vp]
+    L.ibs_plan_set_tiles.argtypes = [vp, ctypes.POINTER(i32), i32]
     L.ibs_batch_build.argtypes = [ctypes.POINTER(ibs_batch_job), i32, i32, ctypes.POINTER(vp)]
     L.ibs_batch_launch.argtypes = [vp, vp]
     L.ibs_batch_destroy.argtypes = [vp]
@@ -206,6 +212,24 @@ def ibs_profile_read(plan, kernel: int):
     return dict(ms=ms.value, launches=n.value, flops=fl.value, bytes=by.value)
 
 
+def ibs_autotune_bytes(plan) -> int:
+    n = ctypes.c_size_t()
+    _check(lib.ibs_autotune_bytes(plan, ctypes.byref(n)), "ibs_autotune_bytes")
+    return n.value
+
+
+def ibs_autotune(plan, scratch_ptr: int, scratch_bytes: int, stream: int = 0):
+    """Time the tile candidates on device; returns the chosen indices."""
+    ch = (ctypes.c_int32 * IBS_NUM_TUNE)()
+    _check(lib.ibs_autotune(plan, scratch_ptr, scratch_bytes, ch, stream), "ibs_autotune")
+    return list(ch)
+
+
+def ibs_plan_set_tiles(plan, choices):
+    arr = (ctypes.c_int32 * len(choices))(*choices)
+    _check(lib.ibs_plan_set_tiles(plan, arr, len(choices)), "ibs_plan_set_tiles")
+
+
 def ibs_batch_build(jobs, nlanes: int) -> int:
     arr = (ibs_batch_job * len(jobs))(*jobs)
     h = ctypes.c_void_p()
@@ -248,6 +272,15 @@ class Solver:
         self.info = torch.zeros((8, INFO_BYTES // 8), dtype=torch.float64, device=self.device)
         solver_plan_upload(self.plan, self.const.data_ptr(), cb, self.stream())
         self.work_bytes = self.work.numel() if self.work is not None else 0
+
+    def autotune(self):
+        """Pick the fastest tile shapes for this grid (bitwise-identical
+        results whatever the choice); returns the chosen indices."""
+        n = ibs_autotune_bytes(self.plan)
+        scratch = self.torch.empty(n, dtype=self.torch.uint8, device=self.device)
+        ch = ibs_autotune(self.plan, scratch.data_ptr(), n, self.stream())
+        del scratch
+        return ch
 
     def stream(self) -> int:
         return self.torch.cuda.current_stream(self.device).cuda_stream

@@ -215,3 +215,57 @@ def test_c2_size_manufactured_256(ibs):
         err = _rel(_host(xg), xt)
         _say("helmholtz", comp, "rel err", err)
         assert err < TOL
+
+
+@pytest.mark.parametrize("shape", [(256, 96, 256), (128, 33, 96), (80, 20, 160)])
+def test_fp64_manufactured_large(ibs, shape):
+    """Manufactured solutions (x_true seeded, b = A x_true formed by the
+    oracle's long-double stencil on the CPU) at sizes spanning many tiles of
+    the folded transforms (half-lengths 128, 64, 48 and 80, the last an odd
+    number of 16-blocks) and of the plain one (nx = 80)."""
+    nx, ny, nz = shape
+    _say("case fp64 manufactured", shape)
+    g = oracle.Grid(nx, ny, nz, beta=2.0)
+    S = ibs.Solver(nx, ny, nz, beta=2.0)
+    c = 0.125 * min(float(g.dyc.min()), 1.0 / nx) ** 2
+    xt = synth.manufactured(nx, ny, nz, seed=4)
+    xt = xt - oracle.weighted_mean(g, OP_P, xt)
+    r, _, _ = oracle.residual_ld(g, OP_P, 0.0, xt, np.zeros_like(xt))
+    err = _rel(_host(S.poisson(_dev(-r))), xt)
+    _say("poisson err", err)
+    assert err < TOL
+    for op, comp in ((OP_U, 0), (OP_V, 1), (OP_W, 2)):
+        rows = ny + 1 if op == OP_V else None
+        xt = synth.manufactured(nx, ny, nz, seed=5 + comp, rows=rows)
+        if op == OP_V:
+            xt[:, 0, :] = 0
+            xt[:, ny, :] = 0
+        r, _, _ = oracle.residual_ld(g, op, c, xt, np.zeros_like(xt))
+        (x,) = S.helmholtz([comp], [c], [_dev(-r)])
+        err = _rel(_host(x), xt)
+        _say("helmholtz", comp, "err", err)
+        assert err < TOL
+
+
+def test_tile_candidates_bitwise_equal(ibs):
+    """Every tile candidate of the folded transforms gives the same bits;
+    ibs_autotune() returns valid choices and keeps them in the plan."""
+    nx, ny, nz = 96, 33, 64
+    _say("case tile candidates", (nx, ny, nz))
+    b = synth.scalar(nx, ny, nz, seed=9)
+    u, v, w = synth.velocity(nx, ny, nz, seed=10)
+    S = ibs.Solver(nx, ny, nz, beta=1.5)
+    ref = None
+    for cand in range(4):
+        ibs.ibs_plan_set_tiles(S.plan, [cand, cand])
+        out = [_host(S.poisson(_dev(b)))]
+        out += [_host(x) for x in S.helmholtz([0, 1, 2], [1e-3] * 3, [_dev(u), _dev(v), _dev(w)])]
+        if ref is None:
+            ref = out
+        else:
+            for o, r in zip(out, ref):
+                np.testing.assert_array_equal(o, r, err_msg=f"candidate {cand}")
+    ch = S.autotune()
+    _say("autotune choices", ch)
+    assert len(ch) == 2 and all(0 <= c < 4 for c in ch)
+    np.testing.assert_array_equal(_host(S.poisson(_dev(b))), ref[0])

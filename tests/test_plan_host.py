@@ -82,6 +82,18 @@ def test_plan_bytes_and_errors():
         with pytest.raises(ibs.IbsError) as e:
             _plan(**kw)
         assert e.value.status == ibs.IBS_ERR_UNSUPPORTED
+    p = _plan(64, 16, 64)
+    try:
+        assert ibs.ibs_autotune_bytes(p) == 2 * 64 * 17 * 64 * 8
+        with pytest.raises(ibs.IbsError) as e:   # refused on the host before any device call
+            ibs.ibs_autotune(p, 256, 1 << 30)
+        assert e.value.status == ibs.IBS_ERR_NOT_UPLOADED
+        ibs.ibs_plan_set_tiles(p, [3, -1])
+        with pytest.raises(ibs.IbsError) as e:
+            ibs.ibs_plan_set_tiles(p, [4, 0])
+        assert e.value.status == ibs.IBS_ERR_INVALID_ARG
+    finally:
+        ibs.solver_plan_destroy(p)
     with pytest.raises(ibs.IbsError) as e:
         _plan(32, 16, 32, bc_x=ibs.IBS_DIRICHLET)
     assert e.value.status == ibs.IBS_ERR_UNSUPPORTED
