@@ -27,6 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp64_tflops": 78.6, "hbm_gbs": 8000.0}
+# HBM bytes per launch measured with rocprofv3 counters on the 256^3 step
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_256cube.json")
 
 
 def log(*a):
@@ -88,6 +90,8 @@ def main():
                          "shell; batch: 64 mixed-size jobs as one graph; serve: arrival-rate sweep")
     ap.add_argument("--count", type=int, default=2000, help="serve: requests per rate")
     ap.add_argument("--rates", type=str, default="100,200,500,1000,2000,5000")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this solver is single-GPU "
@@ -95,6 +99,8 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        return copy_calibration(args.copy_calibration)
     from paper_2406_19920_amd import ibsolve as ibs
 
     if args.config == "batch":
@@ -162,9 +168,11 @@ def main():
         return dict(ms=ms, per=per, kern=kern, hinfo=infos, pinfo=pinfo, tiles=tiles)
 
     def roofline(kern, steps):
+        from paper_2406_19920_amd import pmc
         dom_name = max(kern, key=lambda k: kern[k]["ms"])
         d = kern[dom_name]
         avg_ms = d["ms"] / d["launches"]
+        traffic = pmc.traffic_for(dom_name, TRAFFIC_FILE) if n == 256 and beta == 2.0 else None
         if dom_name in ("xgemm_f64", "zgemm_f64"):
             achieved = d["flops"] / d["launches"] / (avg_ms * 1e-3) / 1e12
             roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp64_tflops"],
@@ -173,7 +181,9 @@ def main():
             achieved = d["bytes"] / d["launches"] / (avg_ms * 1e-3) / 1e9
             roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_gbs"], "unit": "GB/s"}
         roof["frac"] = roof["achieved"] / roof["peak"]
-        roof["traffic"] = None
+        roof["traffic"] = traffic
+        roof["traffic_unit"] = "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+        roof["algorithmic_bytes_per_launch"] = d["bytes"] / d["launches"]
         roof["kernel"] = dom_name
         roof["avg_launch_ms"] = avg_ms
         breakdown = {k: {"ms_per_step": r["ms"] / steps,
@@ -224,6 +234,18 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def copy_calibration(nbytes):
+    """A plain device-to-device copy of nbytes, five times: the reference
+    reading for the HBM byte counters."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": src.numel() * 4, "repeats": 5}), flush=True)
 
 
 def bench_batch(args):

@@ -161,7 +161,9 @@ static ibs_status run_refined(Plan &p, SplitSet ss, float *const *W1, float *con
     }
     double cells = 0;
     for (int q = 0; q < ss.n; ++q) cells += (double)p.nz * ss.j[q].rows * p.nx;
-    const double xfl = 2.0 * p.nx * cells, zfl = 2.0 * p.nz * cells;
+    // algorithmic flops per cell: 2n for the plain transform, n folded
+    const double xfl = (can_fold_split(p.nx) ? 1.0 : 2.0) * p.nx * cells;
+    const double zfl = (can_fold_split(p.nz) ? 1.0 : 2.0) * p.nz * cells;
     JobSet js{};
     js.n = ss.n;
     void *info[4];

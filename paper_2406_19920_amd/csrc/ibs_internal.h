@@ -28,8 +28,10 @@ struct BlobLayout {
     size_t lo[NUM_KINDS], di[NUM_KINDS], up[NUM_KINDS];  // y operator rows
     size_t wy;               // Delta_j (pressure weights), ny doubles
     size_t dyc, dyf;         // cell heights [ny], centre distances [ny+1]
-    size_t sx_fwd, sx_inv;   // x transform, bf16x3 split, B-operand swizzle
-    size_t sz_fwd, sz_inv;   // z transform, bf16x3 split, A-operand swizzle
+    size_t sx_fwd, sx_inv;   // x transform, bf16x3 split, B-operand swizzle (nx % 64 != 0)
+    size_t sz_fwd, sz_inv;   // z transform, bf16x3 split, A-operand swizzle (nz % 64 != 0)
+    size_t sxf_fwd, sxf_inv; // folded x transform factors, bf16x3 split (nx % 64 == 0)
+    size_t szf_fwd, szf_inv; // folded z transform factors, bf16x3 split (nz % 64 == 0)
     size_t bmean;            // per-job weighted mean of the Poisson rhs (4 doubles)
     size_t xsum;             // per-job partial sums of Delta_j x (XSUM_SLOTS each)
     size_t done;             // per-job refinement stop flags (4 ints)
@@ -80,6 +82,18 @@ struct Plan {
     Profile prof;
 };
 
+// Rows of a plane that the x and z transforms visit.  The v component
+// (KIND_F) has ny + 1 rows per plane whose first and last are the wall
+// faces; its first row is left out of the transforms (the tridiagonal step
+// writes its zeros), so every component has ny transform rows per plane
+// and a batch of components splits into equal tiles.  Transform row t of a
+// [planes][rows][n] field is physical row phys_row(t).
+__host__ __device__ inline int skip_first_row(int kind) { return kind == KIND_F ? 1 : 0; }
+__host__ __device__ inline size_t phys_row(int t, int trows, int skip)
+{
+    return skip ? (size_t)t + (size_t)(t / trows) + 1 : (size_t)t;
+}
+
 // Per-component record for batched launches (passed by value).
 // The refined path reuses it with float work arrays (cast through the
 // pointers) and x the FP64 iterate.
@@ -109,6 +123,9 @@ hipError_t launch_xgemm_f64(const JobSet &js, int nz, int K, int N,
 // Folded FP64 transforms (valid when can_fold(n)).
 bool can_fold(int n);
 int fold_candidates();
+// Folded split transforms: the half length must hold whole 32-deep chunks,
+// and both factors' accumulators must fit one wave's registers.
+inline bool can_fold_split(int n) { return n % 64 == 0 && n <= 256; }
 hipError_t launch_xfold_f64(const JobSet &js, const Plan &p, bool inverse, hipStream_t s);
 hipError_t launch_zfold_f64(const JobSet &js, const Plan &p, bool inverse, hipStream_t s);
 hipError_t launch_zgemm_f64(const JobSet &js, int M, int K, int nx,

@@ -47,7 +47,8 @@ __global__ __launch_bounds__(256) void xfold_f64_kernel(JobSet js, int nz, int N
                                                         double s0, double s1)
 {
     const FieldJob &jb = js.j[blockIdx.z];
-    const int M = nz * jb.rows;
+    const int skip = skip_first_row(jb.kind), trows = jb.rows - skip;
+    const int M = nz * trows;
     const int H = N >> 1, HB = H >> 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wgm = 4 / wgn;
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(256) void xfold_f64_kernel(JobSet js, int nz, int N
     }
     const double *arow[WM];
 #pragma unroll
-    for (int i = 0; i < WM; ++i) arow[i] = A + (size_t)(row0 + 16 * i + (i < nrb ? li : 0)) * N;
+    for (int i = 0; i < WM; ++i) arow[i] = A + phys_row(row0 + 16 * i + (i < nrb ? li : 0), trows, skip) * N;
 
     for (int kc = 0; kc < HB; ++kc) {
         const int k0 = 16 * kc + 4 * lg;
@@ -137,10 +138,14 @@ __global__ __launch_bounds__(256) void xfold_f64_kernel(JobSet js, int nz, int N
         double ny = nyq[i];
         ny += __shfl_xor(ny, 16, 64);
         ny += __shfl_xor(ny, 32, 64);   // every lane of row li holds its sum
-        const size_t rb = (size_t)(row0 + 16 * i);
-        double ah[4];                   // A[row][H] of the lane's output rows
+        const int rb = row0 + 16 * i;
+        size_t orow[4];                 // physical output rows of the lane
+        double ah[4];                   // A[row][H] of those rows
 #pragma unroll
-        for (int q = 0; q < 4; ++q) ah[q] = A[(rb + lg + 4 * q) * N + H];
+        for (int q = 0; q < 4; ++q) {
+            orow[q] = phys_row(rb + lg + 4 * q, trows, skip) * N;
+            ah[q] = A[orow[q] + H];
+        }
         if (!INV) {
             double nyr[4];
 #pragma unroll
@@ -152,7 +157,7 @@ __global__ __launch_bounds__(256) void xfold_f64_kernel(JobSet js, int nz, int N
                 const double wa = (a == 0 ? s0 : s1) * ((a & 1) ? -1.0 : 1.0);   // Q[H][a]
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const size_t o = (rb + lg + 4 * q) * N;
+                    const size_t o = orow[q];
                     C[o + a] = fma(ah[q], wa, acc_c[i][j][q]);
                     double sv = acc_s[i][j][q];
                     if (a == 0) sv = fma(s0, nyr[q], sv);   // spectral index H: Nyquist
@@ -161,8 +166,8 @@ __global__ __launch_bounds__(256) void xfold_f64_kernel(JobSet js, int nz, int N
             }
         } else {
             if (cb0 == 0 && lg == 0) {   // physical point H of row li
-                const size_t r = rb + li;
-                C[r * N + H] = fma(A[r * N + H], sH, ny);
+                const size_t r = phys_row(rb + li, trows, skip) * N;
+                C[r + H] = fma(A[r + H], sH, ny);
             }
 #pragma unroll
             for (int j = 0; j < WN; ++j) {
@@ -171,7 +176,7 @@ __global__ __launch_bounds__(256) void xfold_f64_kernel(JobSet js, int nz, int N
                 const double sg = (ii & 1) ? -s0 : s0;   // Q[ii][H]
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const size_t o = (rb + lg + 4 * q) * N;
+                    const size_t o = orow[q];
                     const double u = fma(ah[q], sg, acc_c[i][j][q]), v = acc_s[i][j][q];
                     C[o + ii] = u + v;
                     if (ii != 0) C[o + N - ii] = u - v;
@@ -192,7 +197,9 @@ __global__ __launch_bounds__(256) void zfold_f64_kernel(JobSet js, int N, int nx
                                                         double s0, double s1)
 {
     const FieldJob &jb = js.j[blockIdx.z];
-    const int Ncol = jb.rows * nx;
+    const int skip = skip_first_row(jb.kind);
+    const int Ncol = (jb.rows - skip) * nx;
+    const size_t ldp = (size_t)jb.rows * nx;   // plane stride
     const int H = N >> 1, HB = H >> 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wgm = 4 / wgn;
@@ -203,8 +210,8 @@ __global__ __launch_bounds__(256) void zfold_f64_kernel(JobSet js, int N, int nx
     const int nrb = min(WM, HB - rb0);
     const int ncb = min(WN, (Ncol - col0) >> 4);
     const int li = lane & 15, lg = lane >> 4;
-    const double *__restrict__ B = jb.in;
-    double *__restrict__ C = jb.out;
+    const double *__restrict__ B = jb.in + skip * nx;
+    double *__restrict__ C = jb.out + skip * nx;
 
     d4 acc_c[WM][WN], acc_s[WM][WN];
     double nyq[WN];
@@ -240,8 +247,8 @@ __global__ __launch_bounds__(256) void zfold_f64_kernel(JobSet js, int N, int nx
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
                         const int kk = k0 + t;
-                        const double pv = col[(size_t)kk * Ncol];
-                        const double mv = col[(size_t)(kk == 0 ? H : N - kk) * Ncol];
+                        const double pv = col[(size_t)kk * ldp];
+                        const double mv = col[(size_t)(kk == 0 ? H : N - kk) * ldp];
                         xc[j][t] = kk == 0 ? pv : pv + mv;
                         xs[j][t] = kk == 0 ? mv : pv - mv;
                     }
@@ -249,8 +256,8 @@ __global__ __launch_bounds__(256) void zfold_f64_kernel(JobSet js, int N, int nx
                 } else {
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
-                        xc[j][t] = col[(size_t)(k0 + t) * Ncol];
-                        xs[j][t] = col[(size_t)(H + k0 + t) * Ncol];
+                        xc[j][t] = col[(size_t)(k0 + t) * ldp];
+                        xs[j][t] = col[(size_t)(H + k0 + t) * ldp];
                     }
                     nyq[j] = fma(k0 == 0 ? s0 : s1, xc[j][0], nyq[j]);
                     nyq[j] = fma(-s1, xc[j][1], nyq[j]);
@@ -281,8 +288,8 @@ __global__ __launch_bounds__(256) void zfold_f64_kernel(JobSet js, int N, int nx
         double ny = nyq[j];
         ny += __shfl_xor(ny, 16, 64);
         ny += __shfl_xor(ny, 32, 64);   // every lane of column li holds its sum
-        const double bh = B[(size_t)H * Ncol + cc];
-        if (INV && rb0 == 0 && lg == 0) C[(size_t)H * Ncol + cc] = fma(bh, sH, ny);
+        const double bh = B[(size_t)H * ldp + cc];
+        if (INV && rb0 == 0 && lg == 0) C[(size_t)H * ldp + cc] = fma(bh, sH, ny);
 #pragma unroll
         for (int i = 0; i < WM; ++i) {
             if (i >= nrb) break;
@@ -291,24 +298,27 @@ __global__ __launch_bounds__(256) void zfold_f64_kernel(JobSet js, int N, int nx
                 const int r = 16 * (rb0 + i) + lg + 4 * q;   // 0 <= r < H
                 if (!INV) {
                     const double wr = (r == 0 ? s0 : s1) * ((r & 1) ? -1.0 : 1.0);   // Q[H][r]
-                    C[(size_t)r * Ncol + cc] = fma(bh, wr, acc_c[i][j][q]);
+                    C[(size_t)r * ldp + cc] = fma(bh, wr, acc_c[i][j][q]);
                     double sv = acc_s[i][j][q];
                     if (r == 0) sv = fma(s0, ny, sv);   // plane H: Nyquist
-                    C[(size_t)(H + r) * Ncol + cc] = sv;
+                    C[(size_t)(H + r) * ldp + cc] = sv;
                 } else {
                     const double u = fma(bh, (r & 1) ? -s0 : s0, acc_c[i][j][q]), v = acc_s[i][j][q];
-                    C[(size_t)r * Ncol + cc] = u + v;
-                    if (r != 0) C[(size_t)(N - r) * Ncol + cc] = u - v;
+                    C[(size_t)r * ldp + cc] = u + v;
+                    if (r != 0) C[(size_t)(N - r) * ldp + cc] = u - v;
                 }
             }
         }
     }
 }
 
-static int max_rows(const JobSet &js)
+static int max_rows(const JobSet &js)   // transform rows per plane
 {
     int r = 0;
-    for (int q = 0; q < js.n; ++q) r = js.j[q].rows > r ? js.j[q].rows : r;
+    for (int q = 0; q < js.n; ++q) {
+        const int t = js.j[q].rows - skip_first_row(js.j[q].kind);
+        r = t > r ? t : r;
+    }
     return r;
 }
 

@@ -134,7 +134,8 @@ __global__ __launch_bounds__(512) void split_xgemm_kernel(SplitSet ss, int nz, i
     __shared__ b8 sq[(DB ? 2 : 1) * QCNT];
     if (skip && skip[blockIdx.z]) return;   // this job has already converged
     const SplitJob &jb = ss.j[blockIdx.z];
-    const int M = nz * jb.rows;
+    const int rskip = skip_first_row(jb.kind), trows = jb.rows - rskip;
+    const int M = nz * trows;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
     const int NB = N >> 4;
@@ -155,7 +156,7 @@ __global__ __launch_bounds__(512) void split_xgemm_kernel(SplitSet ss, int nz, i
 #pragma unroll
         for (int i = 0; i < WM; ++i) {
             if (i < nrb) {
-                load8<Tin>(A + (size_t)(row0 + 16 * i + li) * K + 32 * kc + 8 * lg, d[i]);
+                load8<Tin>(A + phys_row(row0 + 16 * i + li, trows, rskip) * K + 32 * kc + 8 * lg, d[i]);
             } else {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) d[i][e] = 0.f;
@@ -211,12 +212,22 @@ __global__ __launch_bounds__(512) void split_xgemm_kernel(SplitSet ss, int nz, i
 #pragma unroll
     for (int i = 0; i < WM; ++i) {
         if (i < nrb) {
+            size_t orow[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int t = row0 + 16 * i + 4 * lg + q;
+                orow[q] = phys_row(t, trows, rskip) * N;
+                // the skipped wall row before each plane's first transform
+                // row holds zeros in the FP64 result
+                if (MODE == 1 && rskip && t % trows == 0)
+                    for (int c = li; c < N; c += 16) jb.x[orow[q] - N + c] = 0.0;
+            }
 #pragma unroll
             for (int j = 0; j < NBT; ++j) {
                 if (j < NB) {
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const size_t o = (size_t)(row0 + 16 * i + 4 * lg + q) * N + 16 * j + li;
+                        const size_t o = orow[q] + 16 * j + li;
                         if (MODE == 0) {
                             jb.out[o] = acc[i][j][q];
                         } else if (MODE == 1) {
@@ -263,14 +274,17 @@ __global__ __launch_bounds__(512) void split_zgemm_kernel(SplitSet ss, int M, in
     __shared__ b8 sq[(DB ? 2 : 1) * QCNT];
     if (skip && skip[blockIdx.z]) return;
     const SplitJob &jb = ss.j[blockIdx.z];
-    const int Ncol = jb.rows * nx;
+    const int rskip = skip_first_row(jb.kind);
+    const int Ncol = (jb.rows - rskip) * nx;
+    const size_t ldp = (size_t)jb.rows * nx;   // plane stride
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
     const int MB = M >> 4;
     const int qcnt = MB * 3 * 64;
     const int col0 = (blockIdx.x * 8 + wave) * (16 * WN);
     const int ncb = col0 < Ncol ? min(WN, (Ncol - col0) >> 4) : 0;
-    const float *__restrict__ B = static_cast<const float *>(jb.in);
+    const float *__restrict__ B = static_cast<const float *>(jb.in) + rskip * nx;
+    float *__restrict__ C = jb.out + rskip * nx;
     const int KC = K >> 5;
 
     f4 acc[MBT][WN];
@@ -281,11 +295,11 @@ __global__ __launch_bounds__(512) void split_zgemm_kernel(SplitSet ss, int M, in
 
     float dcur[WN][8], dnext[WN][8];
     auto load_data = [&](int kc, float (&d)[WN][8]) {
-        const float *brow = B + (size_t)(32 * kc + 8 * lg) * Ncol + col0 + li;
+        const float *brow = B + (size_t)(32 * kc + 8 * lg) * ldp + col0 + li;
 #pragma unroll
         for (int j = 0; j < WN; ++j)
 #pragma unroll
-            for (int e = 0; e < 8; ++e) d[j][e] = (j < ncb) ? brow[(size_t)e * Ncol + 16 * j] : 0.f;
+            for (int e = 0; e < 8; ++e) d[j][e] = (j < ncb) ? brow[(size_t)e * ldp + 16 * j] : 0.f;
     };
     b8 qreg[QPER];
     q_load<QPER>(qs, qcnt, qreg);
@@ -337,7 +351,392 @@ __global__ __launch_bounds__(512) void split_zgemm_kernel(SplitSet ss, int M, in
                 if (j < ncb) {
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
-                        jb.out[(size_t)(16 * i + 4 * lg + q) * Ncol + col0 + 16 * j + li] = acc[i][j][q];
+                        C[(size_t)(16 * i + 4 * lg + q) * ldp + col0 + 16 * j + li] = acc[i][j][q];
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Folded transforms (n % 64 == 0).  The real Fourier basis is even or odd
+// under i -> n - i, so a length-n transform is two half-length products:
+//   forward: E[i] = X[i] + X[n-i], O[i] = X[i] - X[n-i] (E[0] = X[0],
+//            O[0] = X[H]); cos outputs = E Fc (+ X[H] Q[H][a]), sin and
+//            Nyquist outputs = O Fs (+ the alternating sum of E at H)
+//   inverse: U = Xc Fc (+ X[H] Q[i][H]), V = Xs Fs; X[i] = U + V,
+//            X[n-i] = U - V, X[H] = the alternating sum of Xc (+ X[H] Q[H][H])
+// (H = n/2).  Half the matrix-core work of the plain transform; the four
+// self-mirrored points are handled on the vector units.  The chunk of both
+// factors (2 x HB 16-blocks x 3 terms) is staged through LDS as above.
+// ---------------------------------------------------------------------------
+
+// x transform, a wave owning WM row blocks and all columns of both factors.
+// MODE as for the plain kernel (0: FP32 out, forward; 1: x = C; 2: x += C).
+template <int HBT, int WM, typename Tin, int MODE, bool INV>
+__global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, int N,
+                                                          const b8 *__restrict__ qs,
+                                                          double *__restrict__ red,
+                                                          const int *__restrict__ skip, double s0,
+                                                          double s1)
+{
+    constexpr int QCNT = 2 * HBT * 3 * 64;
+    constexpr bool DB = 2 * QCNT * 16 <= 144 * 1024;
+    constexpr int QPER = (QCNT + 511) / 512;
+    __shared__ b8 sq[(DB ? 2 : 1) * QCNT];
+    if (skip && skip[blockIdx.z]) return;
+    const SplitJob &jb = ss.j[blockIdx.z];
+    const int rskip = skip_first_row(jb.kind), trows = jb.rows - rskip;
+    const int M = nz * trows;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int H = N >> 1, HB = H >> 4;
+    const int qcnt = 2 * HB * 3 * 64;
+    const int row0 = (blockIdx.x * 8 + wave) * (16 * WM);
+    const int nrb = row0 < M ? min(WM, (M - row0) >> 4) : 0;
+    const Tin *__restrict__ A = static_cast<const Tin *>(jb.in);
+    const int KC = H >> 5;
+
+    f4 acc[WM][2][HBT];
+    double nyq[WM];
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+        nyq[i] = 0.0;
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int j = 0; j < HBT; ++j) acc[i][f][j] = (f4){0.f, 0.f, 0.f, 0.f};
+    }
+    const Tin *arow[WM];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+        arow[i] = A + phys_row(row0 + 16 * i + (i < nrb ? li : 0), trows, rskip) * N;
+
+    // forward: p = X[k], m = X[mirror k]; inverse: p = cos inputs, m = sin
+    // inputs.  The next chunk is loaded into the same registers once the
+    // current one has been split, so its loads run under the products.
+    float pc[WM][8], mc[WM][8];
+    auto load_data = [&](int kc) {
+        const int k0 = 32 * kc + 8 * lg;
+#pragma unroll
+        for (int i = 0; i < WM; ++i) {
+            if (i < nrb) {
+                load8<Tin>(arow[i] + k0, pc[i]);
+                if (!INV) {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const int kk = k0 + e;
+                        mc[i][e] = (float)arow[i][kk == 0 ? H : N - kk];
+                    }
+                } else {
+                    load8<Tin>(arow[i] + H + k0, mc[i]);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) { pc[i][e] = 0.f; mc[i][e] = 0.f; }
+            }
+        }
+    };
+    b8 qreg[QPER];
+    q_load<QPER>(qs, qcnt, qreg);
+    q_store<QPER>(sq, qcnt, qreg);
+    load_data(0);
+    for (int kc = 0; kc < KC; ++kc) {
+        __syncthreads();
+        const b8 *cur = sq + (DB ? (kc & 1) * QCNT : 0);
+        const bool more = kc + 1 < KC;
+        if (more) q_load<QPER>(qs + (size_t)(kc + 1) * qcnt, qcnt, qreg);
+        const int k0 = 32 * kc + 8 * lg;
+        b8 ae[WM][3], ao[WM][3];
+#pragma unroll
+        for (int i = 0; i < WM; ++i) {
+            float ev[8], ov[8];
+            if (!INV) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const bool self = k0 + e == 0;
+                    ev[e] = self ? pc[i][e] : pc[i][e] + mc[i][e];
+                    ov[e] = self ? mc[i][e] : pc[i][e] - mc[i][e];
+                    nyq[i] += (e & 1) ? -(double)ev[e] : (double)ev[e];
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    ev[e] = pc[i][e];
+                    ov[e] = mc[i][e];
+                    const double w = (k0 + e == 0) ? s0 : s1;
+                    nyq[i] += (e & 1) ? -w * (double)ev[e] : w * (double)ev[e];
+                }
+            }
+            split8(ev, ae[i]);
+            split8(ov, ao[i]);
+        }
+        if (more) load_data(kc + 1);
+        if (nrb > 0) {
+            constexpr int G = 2;
+#pragma unroll
+            for (int jg = 0; jg < HBT; jg += G) {
+                b8 bc[G][3], bs[G][3];
+#pragma unroll
+                for (int jj = 0; jj < G; ++jj)
+#pragma unroll
+                    for (int t = 0; t < 3; ++t) {
+                        bc[jj][t] = cur[((jg + jj) * 3 + t) * 64 + lane];
+                        bs[jj][t] = cur[((HB + jg + jj) * 3 + t) * 64 + lane];
+                    }
+#pragma unroll
+                for (int pr = 0; pr < 6; ++pr)
+#pragma unroll
+                    for (int jj = 0; jj < G; ++jj)
+#pragma unroll
+                        for (int i = 0; i < WM; ++i) {
+                            acc[i][0][jg + jj] = mma(ae[i][TA_[pr]], bc[jj][TB_[pr]], acc[i][0][jg + jj]);
+                            acc[i][1][jg + jj] = mma(ao[i][TA_[pr]], bs[jj][TB_[pr]], acc[i][1][jg + jj]);
+                        }
+            }
+        }
+        if (more) {
+            if (!DB) __syncthreads();
+            q_store<QPER>(sq + (DB ? ((kc + 1) & 1) * QCNT : 0), qcnt, qreg);
+        }
+    }
+
+    const double sH = (H & 1) ? -s0 : s0;
+    double sd = 0.0, sx = 0.0;
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+        if (i >= nrb) continue;
+        double ny = nyq[i];
+        ny += __shfl_xor(ny, 16, 64);
+        ny += __shfl_xor(ny, 32, 64);   // every lane of row li holds its sum
+        size_t orow[4];
+        double ah[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int t = row0 + 16 * i + 4 * lg + q;
+            orow[q] = phys_row(t, trows, rskip) * N;
+            ah[q] = (double)A[orow[q] + H];   // X[H] of the output row
+            if (MODE == 1 && rskip && t % trows == 0)
+                for (int c = li; c < N; c += 16) jb.x[orow[q] - N + c] = 0.0;
+        }
+        if (!INV) {
+            double nyr[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) nyr[q] = __shfl(ny, 4 * lg + q, 64);
+#pragma unroll
+            for (int j = 0; j < HBT; ++j) {
+                if (j >= HB) break;
+                const int a = 16 * j + li;
+                const double wa = (a == 0 ? s0 : s1) * ((a & 1) ? -1.0 : 1.0);   // Q[H][a]
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    jb.out[orow[q] + a] = (float)fma(ah[q], wa, (double)acc[i][0][j][q]);
+                    double sv = (double)acc[i][1][j][q];
+                    if (a == 0) sv = fma(s0, nyr[q], sv);   // spectral index H
+                    jb.out[orow[q] + H + a] = (float)sv;
+                }
+            }
+        } else {
+            if (lg == 0) {   // physical point H of row li
+                const size_t r = phys_row(row0 + 16 * i + li, trows, rskip) * N;
+                const double xh = fma((double)A[r + H], sH, ny);
+                if (MODE == 1) {
+                    jb.x[r + H] = xh;
+                } else {
+                    const double xn = jb.x[r + H] + xh;
+                    jb.x[r + H] = xn;
+                    sd += xh * xh;
+                    sx += xn * xn;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < HBT; ++j) {
+                if (j >= HB) break;
+                const int ii = 16 * j + li;
+                const double sg = (ii & 1) ? -s0 : s0;   // Q[ii][H]
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double u = fma(ah[q], sg, (double)acc[i][0][j][q]);
+                    const double v = (double)acc[i][1][j][q];
+                    const size_t o1 = orow[q] + ii, o2 = orow[q] + N - ii;
+                    if (MODE == 1) {
+                        jb.x[o1] = u + v;
+                        if (ii != 0) jb.x[o2] = u - v;
+                    } else {
+                        const double d1 = u + v, x1 = jb.x[o1] + d1;
+                        jb.x[o1] = x1;
+                        sd += d1 * d1;
+                        sx += x1 * x1;
+                        if (ii != 0) {
+                            const double d2 = u - v, x2 = jb.x[o2] + d2;
+                            jb.x[o2] = x2;
+                            sd += d2 * d2;
+                            sx += x2 * x2;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (MODE == 2) {
+        __shared__ double sm[2][8];
+        sd = wave_sum(sd);
+        sx = wave_sum(sx);
+        if (lane == 0) { sm[0][wave] = sd; sm[1][wave] = sx; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double a = 0.0, b = 0.0;
+            for (int w = 0; w < 8; ++w) { a += sm[0][w]; b += sm[1][w]; }
+            const size_t slot = (size_t)blockIdx.z * gridDim.x + blockIdx.x;
+            red[2 * slot] = a;
+            red[2 * slot + 1] = b;
+        }
+    }
+}
+
+// z transform, a wave owning all output rows of both factors and WN
+// column blocks; FP32 in and out.
+template <int HBT, int WN, bool INV>
+__global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, int nx,
+                                                          const b8 *__restrict__ qs,
+                                                          const int *__restrict__ skip, double s0,
+                                                          double s1)
+{
+    constexpr int QCNT = 2 * HBT * 3 * 64;
+    constexpr bool DB = 2 * QCNT * 16 <= 144 * 1024;
+    constexpr int QPER = (QCNT + 511) / 512;
+    __shared__ b8 sq[(DB ? 2 : 1) * QCNT];
+    if (skip && skip[blockIdx.z]) return;
+    const SplitJob &jb = ss.j[blockIdx.z];
+    const int rskip = skip_first_row(jb.kind);
+    const int Ncol = (jb.rows - rskip) * nx;
+    const size_t ldp = (size_t)jb.rows * nx;   // plane stride
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int H = N >> 1, HB = H >> 4;
+    const int qcnt = 2 * HB * 3 * 64;
+    const int col0 = (blockIdx.x * 8 + wave) * (16 * WN);
+    const int ncb = col0 < Ncol ? min(WN, (Ncol - col0) >> 4) : 0;
+    const float *__restrict__ B = static_cast<const float *>(jb.in) + rskip * nx;
+    float *__restrict__ C = jb.out + rskip * nx;
+    const int KC = H >> 5;
+
+    f4 acc[2][HBT][WN];
+    double nyq[WN];
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+        nyq[j] = 0.0;
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int i = 0; i < HBT; ++i) acc[f][i][j] = (f4){0.f, 0.f, 0.f, 0.f};
+    }
+    float pc[WN][8], mc[WN][8];   // next chunk reuses them once split
+    auto load_data = [&](int kc) {
+        const int k0 = 32 * kc + 8 * lg;
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+            const float *col = B + col0 + 16 * j + li;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int kk = k0 + e;
+                const bool ok = j < ncb;
+                pc[j][e] = ok ? col[(size_t)kk * ldp] : 0.f;
+                mc[j][e] = ok ? col[(size_t)(INV ? H + kk : (kk == 0 ? H : N - kk)) * ldp] : 0.f;
+            }
+        }
+    };
+    b8 qreg[QPER];
+    q_load<QPER>(qs, qcnt, qreg);
+    q_store<QPER>(sq, qcnt, qreg);
+    load_data(0);
+    for (int kc = 0; kc < KC; ++kc) {
+        __syncthreads();
+        const b8 *cur = sq + (DB ? (kc & 1) * QCNT : 0);
+        const bool more = kc + 1 < KC;
+        if (more) q_load<QPER>(qs + (size_t)(kc + 1) * qcnt, qcnt, qreg);
+        const int k0 = 32 * kc + 8 * lg;
+        b8 be[WN][3], bo[WN][3];
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+            float ev[8], ov[8];
+            if (!INV) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const bool self = k0 + e == 0;
+                    ev[e] = self ? pc[j][e] : pc[j][e] + mc[j][e];
+                    ov[e] = self ? mc[j][e] : pc[j][e] - mc[j][e];
+                    nyq[j] += (e & 1) ? -(double)ev[e] : (double)ev[e];
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    ev[e] = pc[j][e];
+                    ov[e] = mc[j][e];
+                    const double w = (k0 + e == 0) ? s0 : s1;
+                    nyq[j] += (e & 1) ? -w * (double)ev[e] : w * (double)ev[e];
+                }
+            }
+            split8(ev, be[j]);
+            split8(ov, bo[j]);
+        }
+        if (more) load_data(kc + 1);
+        if (ncb > 0) {
+            constexpr int G = 2;
+#pragma unroll
+            for (int ig = 0; ig < HBT; ig += G) {
+                b8 ac[G][3], as[G][3];
+#pragma unroll
+                for (int ii = 0; ii < G; ++ii)
+#pragma unroll
+                    for (int t = 0; t < 3; ++t) {
+                        ac[ii][t] = cur[((ig + ii) * 3 + t) * 64 + lane];
+                        as[ii][t] = cur[((HB + ig + ii) * 3 + t) * 64 + lane];
+                    }
+#pragma unroll
+                for (int pr = 0; pr < 6; ++pr)
+#pragma unroll
+                    for (int ii = 0; ii < G; ++ii)
+#pragma unroll
+                        for (int j = 0; j < WN; ++j) {
+                            acc[0][ig + ii][j] = mma(ac[ii][TA_[pr]], be[j][TB_[pr]], acc[0][ig + ii][j]);
+                            acc[1][ig + ii][j] = mma(as[ii][TA_[pr]], bo[j][TB_[pr]], acc[1][ig + ii][j]);
+                        }
+            }
+        }
+        if (more) {
+            if (!DB) __syncthreads();
+            q_store<QPER>(sq + (DB ? ((kc + 1) & 1) * QCNT : 0), qcnt, qreg);
+        }
+    }
+
+    const double sH = (H & 1) ? -s0 : s0;
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+        if (j >= ncb) continue;
+        const size_t cc = (size_t)(col0 + 16 * j + li);
+        double ny = nyq[j];
+        ny += __shfl_xor(ny, 16, 64);
+        ny += __shfl_xor(ny, 32, 64);   // every lane of column li holds its sum
+        const double bh = (double)B[(size_t)H * ldp + cc];
+        if (INV && lg == 0) C[(size_t)H * ldp + cc] = (float)fma(bh, sH, ny);
+#pragma unroll
+        for (int i = 0; i < HBT; ++i) {
+            if (i >= HB) break;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = 16 * i + 4 * lg + q;   // 0 <= r < H
+                if (!INV) {
+                    const double wr = (r == 0 ? s0 : s1) * ((r & 1) ? -1.0 : 1.0);   // Q[H][r]
+                    C[(size_t)r * ldp + cc] = (float)fma(bh, wr, (double)acc[0][i][j][q]);
+                    double sv = (double)acc[1][i][j][q];
+                    if (r == 0) sv = fma(s0, ny, sv);   // plane H: Nyquist
+                    C[(size_t)(H + r) * ldp + cc] = (float)sv;
+                } else {
+                    const double u = fma(bh, (r & 1) ? -s0 : s0, (double)acc[0][i][j][q]);
+                    const double v = (double)acc[1][i][j][q];
+                    C[(size_t)r * ldp + cc] = (float)(u + v);
+                    if (r != 0) C[(size_t)(N - r) * ldp + cc] = (float)(u - v);
                 }
             }
         }
@@ -489,10 +888,13 @@ __global__ __launch_bounds__(256) void refine_check_kernel(SplitSet ss, const do
     }
 }
 
-static int max_rows(const SplitSet &ss)
+static int max_rows(const SplitSet &ss)   // transform rows per plane
 {
     int r = 0;
-    for (int q = 0; q < ss.n; ++q) r = ss.j[q].rows > r ? ss.j[q].rows : r;
+    for (int q = 0; q < ss.n; ++q) {
+        const int t = ss.j[q].rows - skip_first_row(ss.j[q].kind);
+        r = t > r ? t : r;
+    }
     return r;
 }
 
@@ -502,11 +904,41 @@ static int max_rows(const SplitSet &ss)
 static int x_nbt(int N) { return N <= 64 ? 4 : (N <= 128 ? 8 : (N <= 256 ? 16 : 32)); }
 static constexpr int x_wm(int nbt) { return nbt == 4 ? 4 : (nbt == 32 ? 1 : 2); }
 
+// folded x tiling: HBT 16-blocks per factor (HB = nx/32 <= HBT), WM row
+// blocks per wave, at most 32 accumulator tiles per wave
+static int xf_hbt(int nx)
+{
+    const int hb = nx / 32;
+    return hb <= 2 ? 2 : hb <= 4 ? 4 : hb <= 6 ? 6 : 8;
+}
+static constexpr int xf_wm(int hbt) { return hbt <= 4 ? 2 : 1; }
+
 static void xgemm_grid(const SplitSet &ss, const Plan &p, dim3 &grid)
 {
-    const int wm = x_wm(x_nbt(p.nx));
+    const int wm = can_fold_split(p.nx) ? xf_wm(xf_hbt(p.nx)) : x_wm(x_nbt(p.nx));
     const int M = p.nz * max_rows(ss);
     grid = dim3((M + 8 * 16 * wm - 1) / (8 * 16 * wm), 1, ss.n);
+}
+
+template <int HBT, typename Tin, int MODE, bool INV>
+static void launch_xf(const SplitSet &ss, const Plan &p, const b8 *qs, double *red, const int *skip,
+                      dim3 grid, hipStream_t s)
+{
+    const double s0 = 1.0 / std::sqrt((double)p.nx), s1 = std::sqrt(2.0 / (double)p.nx);
+    hipLaunchKernelGGL((split_xfold_kernel<HBT, xf_wm(HBT), Tin, MODE, INV>), grid, dim3(512), 0, s,
+                       ss, p.nz, p.nx, qs, red, skip, s0, s1);
+}
+
+template <typename Tin, int MODE, bool INV>
+static void launch_xf_hb(const SplitSet &ss, const Plan &p, const b8 *qs, double *red, const int *skip,
+                         dim3 grid, hipStream_t s)
+{
+    switch (xf_hbt(p.nx)) {
+    case 2: launch_xf<2, Tin, MODE, INV>(ss, p, qs, red, skip, grid, s); break;
+    case 4: launch_xf<4, Tin, MODE, INV>(ss, p, qs, red, skip, grid, s); break;
+    case 6: launch_xf<6, Tin, MODE, INV>(ss, p, qs, red, skip, grid, s); break;
+    default: launch_xf<8, Tin, MODE, INV>(ss, p, qs, red, skip, grid, s); break;
+    }
 }
 
 template <int NBT, typename Tin, int MODE>
@@ -537,14 +969,23 @@ hipError_t launch_split_xgemm(const SplitSet &ss, const Plan &p, bool inverse, b
     const int *skip = pass >= 2 ? reinterpret_cast<const int *>(blob_ptr(p, p.lay.done)) : nullptr;
     dim3 grid;
     xgemm_grid(ss, p, grid);
-    const b8 *qs = reinterpret_cast<const b8 *>(blob_ptr(p, inverse ? p.lay.sx_inv : p.lay.sx_fwd));
     // each refinement pass keeps its update partials in a region of its own
     const size_t slots = (size_t)grid.x * grid.y * grid.z;
     const size_t region = 2 * slots;
     if (mode == 2 && (size_t)pass * region > p.lay.red_count) return hipErrorInvalidValue;
     double *red = blob_mut(p, p.lay.red) + (mode == 2 ? (size_t)(pass - 1) * region : 0);
+    if (in64 && mode != 0) return hipErrorInvalidValue;
+    if (inverse != (mode != 0)) return hipErrorInvalidValue;   // forward: FP32 out; inverse: FP64 x
+    if (can_fold_split(p.nx)) {
+        const b8 *qs = reinterpret_cast<const b8 *>(blob_ptr(p, inverse ? p.lay.sxf_inv : p.lay.sxf_fwd));
+        if (in64) launch_xf_hb<double, 0, false>(ss, p, qs, red, skip, grid, s);
+        else if (mode == 0) launch_xf_hb<float, 0, false>(ss, p, qs, red, skip, grid, s);
+        else if (mode == 1) launch_xf_hb<float, 1, true>(ss, p, qs, red, skip, grid, s);
+        else launch_xf_hb<float, 2, true>(ss, p, qs, red, skip, grid, s);
+        return hipGetLastError();
+    }
+    const b8 *qs = reinterpret_cast<const b8 *>(blob_ptr(p, inverse ? p.lay.sx_inv : p.lay.sx_fwd));
     if (in64) {
-        if (mode != 0) return hipErrorInvalidValue;
         launch_x_nb<double, 0>(ss, p, qs, red, skip, grid, s);
     } else if (mode == 0) {
         launch_x_nb<float, 0>(ss, p, qs, red, skip, grid, s);
@@ -558,9 +999,34 @@ hipError_t launch_split_xgemm(const SplitSet &ss, const Plan &p, bool inverse, b
 
 // z transform tiling: a wave owns all M = nz rows (MB <= MBT row blocks)
 // and WN column blocks.
+template <int HBT, int WN>
+static void launch_zf(const SplitSet &ss, const Plan &p, bool inverse, const b8 *qs, const int *skip,
+                      hipStream_t s)
+{
+    const int Ncol = max_rows(ss) * p.nx;
+    dim3 grid((Ncol + 8 * 16 * WN - 1) / (8 * 16 * WN), 1, ss.n);
+    const double s0 = 1.0 / std::sqrt((double)p.nz), s1 = std::sqrt(2.0 / (double)p.nz);
+    if (inverse)
+        hipLaunchKernelGGL((split_zfold_kernel<HBT, WN, true>), grid, dim3(512), 0, s, ss, p.nz, p.nx, qs,
+                           skip, s0, s1);
+    else
+        hipLaunchKernelGGL((split_zfold_kernel<HBT, WN, false>), grid, dim3(512), 0, s, ss, p.nz, p.nx, qs,
+                           skip, s0, s1);
+}
+
 hipError_t launch_split_zgemm(const SplitSet &ss, const Plan &p, bool inverse, int pass, hipStream_t s)
 {
     const int *skip = pass >= 2 ? reinterpret_cast<const int *>(blob_ptr(p, p.lay.done)) : nullptr;
+    if (can_fold_split(p.nz)) {
+        // folded: HBT 16-blocks per factor (HB = nz/32), WN column blocks per wave
+        const b8 *qs = reinterpret_cast<const b8 *>(blob_ptr(p, inverse ? p.lay.szf_inv : p.lay.szf_fwd));
+        const int hb = p.nz / 32;
+        if (hb <= 2) launch_zf<2, 2>(ss, p, inverse, qs, skip, s);
+        else if (hb <= 4) launch_zf<4, 1>(ss, p, inverse, qs, skip, s);
+        else if (hb <= 6) launch_zf<6, 1>(ss, p, inverse, qs, skip, s);
+        else launch_zf<8, 1>(ss, p, inverse, qs, skip, s);
+        return hipGetLastError();
+    }
     const int M = p.nz;
     const int Ncol = max_rows(ss) * p.nx;
     const b8 *qs = reinterpret_cast<const b8 *>(blob_ptr(p, inverse ? p.lay.sz_inv : p.lay.sz_fwd));

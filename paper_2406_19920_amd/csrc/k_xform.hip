@@ -33,7 +33,8 @@ __global__ __launch_bounds__(256) void xgemm_f64_kernel(JobSet js, int nz, int K
                                                         const double *__restrict__ bs, int wgn)
 {
     const FieldJob &jb = js.j[blockIdx.z];
-    const int M = nz * jb.rows;
+    const int skip = skip_first_row(jb.kind), trows = jb.rows - skip;
+    const int M = nz * trows;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wgm = 4 / wgn;
     const int wm = wave / wgn, wn = wave % wgn;
@@ -53,7 +54,7 @@ __global__ __launch_bounds__(256) void xgemm_f64_kernel(JobSet js, int nz, int K
     const double *arow[WM];
 #pragma unroll
     for (int i = 0; i < WM; ++i)
-        arow[i] = A + (size_t)(row0 + 16 * i + (i < nrb ? li : 0)) * K + 4 * lg;
+        arow[i] = A + phys_row(row0 + 16 * i + (i < nrb ? li : 0), trows, skip) * K + 4 * lg;
     for (int kc = 0; kc < (K >> 4); ++kc) {
         d4 a[WM], b[WN];
 #pragma unroll
@@ -80,19 +81,22 @@ __global__ __launch_bounds__(256) void xgemm_f64_kernel(JobSet js, int nz, int K
             if (j >= ncb) break;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                C[(size_t)(row0 + 16 * i + lg + 4 * q) * N + col0 + 16 * j + li] = acc[i][j][q];
+                C[phys_row(row0 + 16 * i + lg + 4 * q, trows, skip) * N + col0 + 16 * j + li] = acc[i][j][q];
         }
     }
 }
 
 // z transform: for job q, C = As * B with As the swizzled M x K matrix
-// (M = K = nz), B = in viewed as K x Ncol (Ncol = rows*nx), C = out (M x Ncol).
+// (M = K = nz), B = in viewed as K x Ncol (Ncol = transform rows * nx, at
+// plane stride rows * nx), C = out (M x Ncol).
 template <int WM, int WN>
 __global__ __launch_bounds__(256) void zgemm_f64_kernel(JobSet js, int M, int K, int nx,
                                                         const double *__restrict__ as, int wgn)
 {
     const FieldJob &jb = js.j[blockIdx.z];
-    const int Ncol = jb.rows * nx;
+    const int skip = skip_first_row(jb.kind);
+    const int Ncol = (jb.rows - skip) * nx;
+    const size_t ldp = (size_t)jb.rows * nx;   // plane stride
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wgm = 4 / wgn;
     const int wm = wave / wgn, wn = wave % wgn;
@@ -102,7 +106,7 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(JobSet js, int M, int K,
     const int nrb = min(WM, (M - row0) >> 4);
     const int ncb = min(WN, (Ncol - col0) >> 4);
     const int li = lane & 15, lg = lane >> 4;
-    const double *__restrict__ B = jb.in;
+    const double *__restrict__ B = jb.in + skip * nx;
     const int mb = M >> 4;
     d4 acc[WM][WN];
 #pragma unroll
@@ -116,12 +120,12 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(JobSet js, int M, int K,
             a[i] = (i < nrb) ? *reinterpret_cast<const d4 *>(
                                    as + (((size_t)kc * mb + (row0 >> 4) + i) * 64 + lane) * 4)
                              : (d4){0, 0, 0, 0};
-        const double *brow = B + (size_t)(16 * kc + 4 * lg) * Ncol + col0 + li;
+        const double *brow = B + (size_t)(16 * kc + 4 * lg) * ldp + col0 + li;
 #pragma unroll
         for (int j = 0; j < WN; ++j) {
             if (j < ncb) {
 #pragma unroll
-                for (int t = 0; t < 4; ++t) b[j][t] = brow[(size_t)t * Ncol + 16 * j];
+                for (int t = 0; t < 4; ++t) b[j][t] = brow[(size_t)t * ldp + 16 * j];
             } else {
                 b[j] = (d4){0, 0, 0, 0};
             }
@@ -133,7 +137,7 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(JobSet js, int M, int K,
 #pragma unroll
                 for (int j = 0; j < WN; ++j) acc[i][j] = mfma(a[i][t], b[j][t], acc[i][j]);
     }
-    double *__restrict__ C = jb.out;
+    double *__restrict__ C = jb.out + skip * nx;
 #pragma unroll
     for (int i = 0; i < WM; ++i) {
         if (i >= nrb) break;
@@ -142,15 +146,18 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(JobSet js, int M, int K,
             if (j >= ncb) break;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                C[(size_t)(row0 + 16 * i + lg + 4 * q) * Ncol + col0 + 16 * j + li] = acc[i][j][q];
+                C[(size_t)(row0 + 16 * i + lg + 4 * q) * ldp + col0 + 16 * j + li] = acc[i][j][q];
         }
     }
 }
 
-static int max_rows(const JobSet &js)
+static int max_rows(const JobSet &js)   // transform rows per plane
 {
     int r = 0;
-    for (int q = 0; q < js.n; ++q) r = js.j[q].rows > r ? js.j[q].rows : r;
+    for (int q = 0; q < js.n; ++q) {
+        const int t = js.j[q].rows - skip_first_row(js.j[q].kind);
+        r = t > r ? t : r;
+    }
     return r;
 }
 

@@ -167,6 +167,31 @@ static void swizzle_a_split(const double *A, int M, int K, uint16_t *out)
                         out[o++] = sp[3 * (size_t(16 * bi + (l % 16)) * K + 32 * kc + 8 * (l / 16) + e) + t];
 }
 
+// The two H x H factors of a folded transform, split and swizzled chunk by
+// chunk: per 32-deep chunk kc, factor f (0 cos, 1 sin), 16-block b, term t
+// and lane l, the 8 values of that lane (B operand: F[32 kc + 8 (l/16) + e]
+// [16 b + l%16]; A operand: F[16 b + l%16][32 kc + 8 (l/16) + e]).  One
+// chunk of both factors is contiguous.
+static void swizzle_split_pair(const std::vector<double> &F0, const std::vector<double> &F1, int H,
+                               bool a_operand, uint16_t *out)
+{
+    const std::vector<uint16_t> s0 = split_all(F0.data(), F0.size());
+    const std::vector<uint16_t> s1 = split_all(F1.data(), F1.size());
+    size_t o = 0;
+    for (int kc = 0; kc < H / 32; ++kc)
+        for (int f = 0; f < 2; ++f) {
+            const std::vector<uint16_t> &sp = f == 0 ? s0 : s1;
+            for (int b = 0; b < H / 16; ++b)
+                for (int t = 0; t < 3; ++t)
+                    for (int l = 0; l < 64; ++l)
+                        for (int e = 0; e < 8; ++e) {
+                            const int k = 32 * kc + 8 * (l / 16) + e, m = 16 * b + (l % 16);
+                            const size_t idx = a_operand ? size_t(m) * H + k : size_t(k) * H + m;
+                            out[o++] = sp[3 * idx + t];
+                        }
+        }
+}
+
 ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
 {
     if (d.nx < 16 || d.nz < 16 || d.nx > 1024 || d.nz > 1024 || d.nx % 16 || d.nz % 16) {
@@ -297,10 +322,15 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     L.dyc = take(sizeof(double) * ny);
     L.dyf = take(sizeof(double) * (ny + 1));
     const bool split = d.precision != IBS_FP64;
-    L.sx_fwd = take(split ? sizeof(uint16_t) * 3 * nx * nx : 0);
-    L.sx_inv = take(split ? sizeof(uint16_t) * 3 * nx * nx : 0);
-    L.sz_fwd = take(split ? sizeof(uint16_t) * 3 * nz * nz : 0);
-    L.sz_inv = take(split ? sizeof(uint16_t) * 3 * nz * nz : 0);
+    const bool sfold_x = split && can_fold_split(nx), sfold_z = split && can_fold_split(nz);
+    L.sx_fwd = take(split && !sfold_x ? sizeof(uint16_t) * 3 * nx * nx : 0);
+    L.sx_inv = take(split && !sfold_x ? sizeof(uint16_t) * 3 * nx * nx : 0);
+    L.sz_fwd = take(split && !sfold_z ? sizeof(uint16_t) * 3 * nz * nz : 0);
+    L.sz_inv = take(split && !sfold_z ? sizeof(uint16_t) * 3 * nz * nz : 0);
+    L.sxf_fwd = take(sfold_x ? sizeof(uint16_t) * 3 * 2 * hx2 : 0);
+    L.sxf_inv = take(sfold_x ? sizeof(uint16_t) * 3 * 2 * hx2 : 0);
+    L.szf_fwd = take(sfold_z ? sizeof(uint16_t) * 3 * 2 * hz2 : 0);
+    L.szf_inv = take(sfold_z ? sizeof(uint16_t) * 3 * 2 * hz2 : 0);
     L.bmean = take(sizeof(double) * 4);
     L.xsum = take(sizeof(double) * 4 * XSUM_SLOTS);
     L.done = take(sizeof(int) * 4);
@@ -355,7 +385,14 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
         swizzle_a(p->qz.data(), nz, nz, tmp.data());
         put(L.az_inv, tmp.data(), tmp.size());
     }
-    if (split) {
+    if (sfold_x) {
+        FoldFactors f(p->qx, nx);
+        std::vector<uint16_t> sw(size_t(3) * 2 * hx2);
+        swizzle_split_pair(f.c, f.s_fwd, nx / 2, false, sw.data());   // forward: E Qc, O Qs
+        std::memcpy(p->blob.data() + L.sxf_fwd, sw.data(), sw.size() * 2);
+        swizzle_split_pair(f.transposed(f.c), f.transposed(f.s_inv), nx / 2, false, sw.data());
+        std::memcpy(p->blob.data() + L.sxf_inv, sw.data(), sw.size() * 2);
+    } else if (split) {
         std::vector<double> tr(size_t(nx) * nx);
         std::vector<uint16_t> sw(size_t(3) * nx * nx);
         swizzle_b_split(p->qx.data(), nx, nx, sw.data());
@@ -364,6 +401,15 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
             for (int a = 0; a < nx; ++a) tr[size_t(a) * nx + i] = p->qx[size_t(i) * nx + a];
         swizzle_b_split(tr.data(), nx, nx, sw.data());
         std::memcpy(p->blob.data() + L.sx_inv, sw.data(), sw.size() * 2);
+    }
+    if (sfold_z) {
+        FoldFactors f(p->qz, nz);
+        std::vector<uint16_t> sw(size_t(3) * 2 * hz2);
+        swizzle_split_pair(f.transposed(f.c), f.transposed(f.s_fwd), nz / 2, true, sw.data());
+        std::memcpy(p->blob.data() + L.szf_fwd, sw.data(), sw.size() * 2);
+        swizzle_split_pair(f.c, f.s_inv, nz / 2, true, sw.data());
+        std::memcpy(p->blob.data() + L.szf_inv, sw.data(), sw.size() * 2);
+    } else if (split) {
         std::vector<double> trz(size_t(nz) * nz);
         std::vector<uint16_t> swz(size_t(3) * nz * nz);
         for (int k = 0; k < nz; ++k)

@@ -269,3 +269,27 @@ def test_tile_candidates_bitwise_equal(ibs):
     _say("autotune choices", ch)
     assert len(ch) == 2 and all(0 <= c < 4 for c in ch)
     np.testing.assert_array_equal(_host(S.poisson(_dev(b))), ref[0])
+
+
+@pytest.mark.parametrize("refined", [False, True])
+def test_v_walls_ignored_and_zeroed(ibs, refined):
+    """The v wall faces of the right-hand side are ignored (NaN there changes
+    nothing) and the v wall faces of the solution are written as zeros
+    whatever the output buffer held."""
+    nx, ny, nz = 64, 20, 32
+    _say("case v walls", refined)
+    prec = ibs.IBS_REFINED_BF16X3 if refined else ibs.IBS_FP64
+    S = ibs.Solver(nx, ny, nz, beta=1.0, precision=prec)
+    v = synth.scalar(nx, ny, nz, 3, rows=ny + 1)
+    v[:, 0, :] = 0
+    v[:, ny, :] = 0
+    (ref,) = S.helmholtz([1], [2e-3], [_dev(v)])
+    ref = _host(ref)
+    vn = v.copy()
+    vn[:, 0, :] = np.nan
+    vn[:, ny, :] = np.nan
+    out = torch.full((nz, ny + 1, nx), float("nan"), dtype=torch.float64, device="cuda")
+    S.helmholtz([1], [2e-3], [_dev(vn)], [out])
+    got = _host(out)
+    assert np.all(got[:, 0, :] == 0) and np.all(got[:, ny, :] == 0)
+    np.testing.assert_array_equal(got, ref)

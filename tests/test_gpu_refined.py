@@ -176,3 +176,33 @@ def test_refined_c3_manufactured(ibs):
              "predicted", inf.rel_residual, "status", inf.status)
         assert err < TOL
         assert inf.status == 0
+
+
+@pytest.mark.parametrize("refined,shape", [(False, (1024, 3, 32)), (False, (32, 768, 16)),
+                                           (True, (512, 5, 64)), (True, (64, 768, 32)),
+                                           (False, (16, 2, 16)), (True, (32, 2, 32))])
+def test_edge_sizes_manufactured(ibs, refined, shape):
+    """Largest and smallest supported extents (nx = 1024 FP64 / 512 refined,
+    ny = 768, ny = 2, n = 16): manufactured solutions, b = A x_true formed by
+    the oracle's long-double stencil."""
+    nx, ny, nz = shape
+    _say("case edge", refined, shape)
+    g = oracle.Grid(nx, ny, nz, beta=2.0)
+    prec = ibs.IBS_REFINED_BF16X3 if refined else ibs.IBS_FP64
+    S = ibs.Solver(nx, ny, nz, beta=2.0, precision=prec)
+    tol = TOL if refined else 1e-12
+    c = 0.125 * min(float(g.dyc.min()), 1.0 / nx) ** 2
+    xt = synth.manufactured(nx, ny, nz, seed=41)
+    xt = xt - oracle.weighted_mean(g, OP_P, xt)
+    r, _, _ = oracle.residual_ld(g, OP_P, 0.0, xt, np.zeros_like(xt))
+    err = _rel(_host(S.poisson(_dev(-r))), xt)
+    _say("poisson err", err)
+    assert err < tol
+    xt = synth.manufactured(nx, ny, nz, seed=42, rows=ny + 1)
+    xt[:, 0, :] = 0
+    xt[:, ny, :] = 0
+    r, _, _ = oracle.residual_ld(g, OP_V, c, xt, np.zeros_like(xt))
+    (x,) = S.helmholtz([1], [c], [_dev(-r)])
+    err = _rel(_host(x), xt)
+    _say("helmholtz v err", err)
+    assert err < tol
