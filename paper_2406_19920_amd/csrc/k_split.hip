@@ -550,12 +550,24 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                 }
             }
 #pragma unroll
-            for (int j = 0; j < HBT; ++j) {
-                if (j >= HB) break;
-                const int ii = 16 * j + li;
-                const double sg = (ii & 1) ? -s0 : s0;   // Q[ii][H]
+            for (int q = 0; q < 4; ++q) {
+                // the row's old values first (all loads in flight together;
+                // every position is distinct), then the updates
+                double xo[2][HBT];
+                if (MODE == 2) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                    for (int j = 0; j < HBT; ++j) {
+                        const int ii = 16 * j + li;
+                        const bool ok = j < HB;
+                        xo[0][j] = ok ? jb.x[orow[q] + ii] : 0.0;
+                        xo[1][j] = (ok && ii != 0) ? jb.x[orow[q] + N - ii] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < HBT; ++j) {
+                    if (j >= HB) break;
+                    const int ii = 16 * j + li;
+                    const double sg = (ii & 1) ? -s0 : s0;   // Q[ii][H]
                     const double u = fma(ah[q], sg, (double)acc[i][0][j][q]);
                     const double v = (double)acc[i][1][j][q];
                     const size_t o1 = orow[q] + ii, o2 = orow[q] + N - ii;
@@ -563,12 +575,12 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                         jb.x[o1] = u + v;
                         if (ii != 0) jb.x[o2] = u - v;
                     } else {
-                        const double d1 = u + v, x1 = jb.x[o1] + d1;
+                        const double d1 = u + v, x1 = xo[0][j] + d1;
                         jb.x[o1] = x1;
                         sd += d1 * d1;
                         sx += x1 * x1;
                         if (ii != 0) {
-                            const double d2 = u - v, x2 = jb.x[o2] + d2;
+                            const double d2 = u - v, x2 = xo[1][j] + d2;
                             jb.x[o2] = x2;
                             sd += d2 * d2;
                             sx += x2 * x2;
@@ -798,24 +810,31 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
             ru = j + 1 <= ny - 1;
             rl = j - 1 >= 1;
         }
+        // branch-free body (every load unconditional and in range, a missing
+        // neighbour reads the point itself), so unrolled iterations' loads
+        // can all be in flight together
+        const int du = ru ? nx : 0, dl = rl ? nx : 0;
+        const double wu = ru ? 1.0 : gu, wl = rl ? 1.0 : gl;
+        const bool pois = op == IBS_OP_POISSON;
+        const double cj = jb.c;
+        const double wD = (op != IBS_OP_HELMHOLTZ_V) ? D : 0.0;
+        const double *__restrict__ bb = jb.b;
+        float *__restrict__ rr = jb.r;
         double xm = x[(size_t)(k0 == 0 ? nz - 1 : k0 - 1) * plane + o];
         double xc = x[(size_t)k0 * plane + o];
 #pragma unroll 4
         for (int k = k0; k < k1; ++k) {
             const size_t c = (size_t)k * plane + o;
             const double xp = x[(size_t)(k + 1 == nz ? 0 : k + 1) * plane + o];
-            if (wall) {
-                jb.r[c] = 0.f;
-            } else {
-                const double xe = x[c - i + ip], xw = x[c - i + im];
-                const double xu = ru ? x[c + nx] : gu * xc;
-                const double xl = rl ? x[c - nx] : gl * xc;
-                double lap = ((xe - xc) - (xc - xw)) * ihx2 + ((xp - xc) - (xc - xm)) * ihz2;
-                lap += cu * (xu - xc) - cl * (xc - xl);
-                const double ax = (op == IBS_OP_POISSON) ? lap : xc - jb.c * lap;
-                jb.r[c] = (float)((jb.b[c] - bm) - ax);
-                if (op != IBS_OP_HELMHOLTZ_V) wx += D * xc;
-            }
+            const double xe = x[c - i + ip], xw = x[c - i + im];
+            const double xu = wu * x[c + du], xl = wl * x[c - dl];
+            const double bv = bb[c];
+            double lap = ((xe - xc) - (xc - xw)) * ihx2 + ((xp - xc) - (xc - xm)) * ihz2;
+            lap += cu * (xu - xc) - cl * (xc - xl);
+            const double ax = pois ? lap : xc - cj * lap;
+            const float rv = (float)((bv - bm) - ax);
+            rr[c] = wall ? 0.f : rv;
+            wx += wD * xc;
             xm = xc;
             xc = xp;
         }

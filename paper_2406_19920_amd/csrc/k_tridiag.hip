@@ -180,7 +180,7 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
         }
         const double sh = plx + plz;
         __syncthreads();
-        fetch(tile + 2 * (int)gridDim.x, pf, plx, plz);  // two tiles ahead
+        fetch(tile + 2 * (int)gridDim.x, pf, plx, plz);  // this buffer's next tile
         if (live) {
             const int a = a0 + p;
             const double sadd = pois ? sh : -jb.c * sh;   // pencil shift of the diagonal
@@ -342,12 +342,15 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
         for (int r2 = 0; r2 < M; ++r2)
             buf_store<T>((T)sx[(lrow + P * r2) * LDR + lcol], rs, voff + r2 * P * row_bytes, 0);
     };
+    // A block takes tiles in adjacent pairs (2b, 2b+1: neighbouring x-modes
+    // of one z-plane), so the two halves of each 128-byte line of a 4-byte
+    // field are read by the same block, back to back, through one L2.
     const int G = gridDim.x;
-    fetch(blockIdx.x, pfa, lxa, lza);
-    fetch(blockIdx.x + G, pfb, lxb, lzb);
-    for (int tile = blockIdx.x; tile < ntiles; tile += 2 * G) {
+    fetch(2 * blockIdx.x, pfa, lxa, lza);
+    fetch(2 * blockIdx.x + 1, pfb, lxb, lzb);
+    for (int tile = 2 * blockIdx.x; tile < ntiles; tile += 2 * G) {
         process(tile, pfa, lxa, lza);
-        if (tile + G < ntiles) process(tile + G, pfb, lxb, lzb);
+        if (tile + 1 < ntiles) process(tile + 1, pfb, lxb, lzb);
     }
 }
 
@@ -368,7 +371,8 @@ static hipError_t launch_pm(const JobSet &js, const TriParams &tp, hipStream_t s
     }();
     const int ntx = tp.nx / 16;
     const int ntiles = ntx * tp.nz * js.n;
-    const int grid = ntiles < resident ? ntiles : resident;
+    const int pairs = (ntiles + 1) / 2;
+    const int grid = pairs < resident ? pairs : resident;
     hipLaunchKernelGGL((tridiag_kernel<T, P, M>), dim3(grid), dim3(16 * P), 0, s, js, tp, ntx,
                        ntiles);
     return hipGetLastError();
