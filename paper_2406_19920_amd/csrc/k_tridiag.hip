@@ -25,6 +25,9 @@
 // beyond the system size are identity rows.  All arithmetic is FP64.
 #include "ibs_internal.h"
 
+#include <algorithm>
+#include <cmath>
+
 namespace ibs {
 
 // 1/d from the hardware reciprocal estimate refined by two Newton steps
@@ -68,6 +71,18 @@ static __device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t rs,
     buf_store_raw(v, rs, voff, soff);
 }
 
+// 1/d in the arithmetic type: FP64 as above; FP32 from the hardware
+// estimate and one Newton step.
+static __device__ __forceinline__ double rcpr(double d) { return rcp64(d); }
+static __device__ __forceinline__ float rcpr(float d)
+{
+    const float x = __builtin_amdgcn_rcpf(d);
+    return fmaf(x, fmaf(-d, x, 1.0f), x);
+}
+
+// Largest pencil condition number solved in FP32 arithmetic (refined path).
+constexpr double FP32_KAPPA = 16.0;
+
 struct TriParams {
     const double *lam_x, *lam_z;
     const double *lo[NUM_KINDS], *di[NUM_KINDS], *up[NUM_KINDS];
@@ -85,17 +100,18 @@ struct TriParams {
 };
 
 // T: storage type of the field (double, or float on the refined path);
-// the arithmetic is FP64 either way.
-template <typename T, int P, int M>
+// R: arithmetic type (double; float only for well-conditioned Helmholtz
+// systems of the refined path, whose refinement absorbs FP32 rounding).
+template <typename T, typename R, int P, int M>
 __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp, int ntx,
                                                          int ntiles)
 {
     constexpr int TA = 16;                 // pencils per tile
     constexpr int NT = TA * P;             // threads
     constexpr int NR = P * M;              // padded rows
-    constexpr int LDR = TA + 1;            // LDS row stride (doubles)
-    __shared__ double sx[NR * LDR];
-    __shared__ double slo[NR], sdi[NR], sup[NR], sw[NR];
+    constexpr int LDR = TA + 1;            // LDS row stride (elements)
+    __shared__ R sx[NR * LDR];
+    __shared__ R slo[NR], sdi[NR], sup[NR], sw[NR];
 
     const int tid = threadIdx.x;
     const int nx = tp.nx;
@@ -159,16 +175,16 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
         if (live && job != cur_job) {
             // rows of the job's operator without the pencil shift:
             // Poisson (lo, di, up); Helmholtz (-c lo, 1 - c di, -c up)
-            const double cj = jb.c;
+            const R cj = (R)jb.c;
             for (int j = tid; j < NR; j += NT) {
                 const bool real = j < n;
-                const double lo = real ? tp.lo[kind][j] : 0.0;
-                const double di = real ? tp.di[kind][j] : 0.0;
-                const double up = real ? tp.up[kind][j] : 0.0;
+                const R lo = real ? (R)tp.lo[kind][j] : R(0);
+                const R di = real ? (R)tp.di[kind][j] : R(0);
+                const R up = real ? (R)tp.up[kind][j] : R(0);
                 slo[j] = pois ? lo : -cj * lo;
-                sdi[j] = pois ? di : 1.0 - cj * di;
+                sdi[j] = pois ? di : R(1) - cj * di;
                 sup[j] = pois ? up : -cj * up;
-                sw[j] = (real && pois) ? tp.wy[j] : 0.0;
+                sw[j] = (real && pois) ? (R)tp.wy[j] : R(0);
             }
             cur_job = job;
         }
@@ -176,24 +192,24 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
 #pragma unroll
         for (int r = 0; r < M; ++r) {
             const int j = lrow + P * r;
-            sx[j * LDR + lcol] = (walls && (j == 0 || j == n - 1)) ? 0.0 : (double)pf[r];
+            sx[j * LDR + lcol] = (walls && (j == 0 || j == n - 1)) ? R(0) : (R)pf[r];
         }
-        const double sh = plx + plz;
+        const R sh = (R)(plx + plz);
         __syncthreads();
         fetch(tile + 2 * (int)gridDim.x, pf, plx, plz);  // this buffer's next tile
         if (live) {
             const int a = a0 + p;
-            const double sadd = pois ? sh : -jb.c * sh;   // pencil shift of the diagonal
+            const R sadd = pois ? sh : -(R)jb.c * sh;   // pencil shift of the diagonal
             const bool pinned = pois && a == 0 && c == 0;
 
-            double r[M];
+            R r[M];
 #pragma unroll
             for (int t = 0; t < M; ++t) r[t] = sx[(s + t) * LDR + p];
 
-            double removed = 0.0, rms = 0.0;
+            R removed = 0.0, rms = 0.0;
             if (pinned) {
                 // compatibility: remove the volume-weighted mean of this pencil's rhs
-                double swr = 0.0, sww = 0.0, swrr = 0.0;
+                R swr = 0.0, sww = 0.0, swrr = 0.0;
 #pragma unroll
                 for (int t = 0; t < M; ++t) {
                     swr += sw[s + t] * r[t];
@@ -206,7 +222,7 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
                     sww += __shfl_xor(sww, d, P);
                     swrr += __shfl_xor(swrr, d, P);
                 }
-                const double mean = swr / sww;
+                const R mean = swr / sww;
                 rms = sqrt(fmax(swrr / sww, 0.0));
                 removed = mean;
 #pragma unroll
@@ -215,7 +231,7 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
                 if (k == 0) r[0] = 0.0;  // pin the first point
             }
 
-            auto coef = [&](int j, double &A, double &B, double &C) {
+            auto coef = [&](int j, R &A, R &B, R &C) {
                 const bool real = j < n && !(pinned && j == 0);
                 A = real ? slo[j] : 0.0;
                 B = real ? sdi[j] + sadd : 1.0;
@@ -223,16 +239,16 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
             };
 
             // down-sweep: rows s+1 .. s+M-1 in the form al x_s + x_j + ga x_{j+1} = rho
-            double al[M], ga[M];
+            R al[M], ga[M];
             {
-                double A, B, C;
+                R A, B, C;
                 coef(s + 1, A, B, C);
-                double inv = rcp64(B);
+                R inv = rcpr(B);
                 al[1] = A * inv; ga[1] = C * inv; r[1] = r[1] * inv;
 #pragma unroll
                 for (int t = 2; t < M; ++t) {
                     coef(s + t, A, B, C);
-                    inv = rcp64(B - A * ga[t - 1]);
+                    inv = rcpr(B - A * ga[t - 1]);
                     al[t] = -A * al[t - 1] * inv;
                     ga[t] = C * inv;
                     r[t] = (r[t] - A * r[t - 1]) * inv;
@@ -241,50 +257,50 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
             // interior rows in terms of the chunk ends, x_j = bp + bq x_s + br x_e,
             // by back-substitution (no divisions), then the top row
             //   lam x_{s-1} + x_s + mu x_e = sig
-            double lam_u, mu_u, sig_u;
+            R lam_u, mu_u, sig_u;
             {
-                double bp = r[M - 2], bq = -al[M - 2], br = -ga[M - 2];
+                R bp = r[M - 2], bq = -al[M - 2], br = -ga[M - 2];
 #pragma unroll
                 for (int t = M - 3; t >= 1; --t) {
                     bp = r[t] - ga[t] * bp;
                     bq = -al[t] - ga[t] * bq;
                     br = -ga[t] * br;
                 }
-                double A, B, C;
+                R A, B, C;
                 coef(s, A, B, C);
-                const double inv = rcp64(B + C * bq);
+                const R inv = rcpr(B + C * bq);
                 lam_u = A * inv;
                 mu_u = C * br * inv;
                 sig_u = (r[0] - C * bp) * inv;
             }
 
             // reduced system in z_k = x_{last row of chunk k}
-            double lam1 = __shfl_down(lam_u, 1, P), mu1 = __shfl_down(mu_u, 1, P),
+            R lam1 = __shfl_down(lam_u, 1, P), mu1 = __shfl_down(mu_u, 1, P),
                    sig1 = __shfl_down(sig_u, 1, P);
             if (k == P - 1) { lam1 = 0.0; mu1 = 0.0; sig1 = 0.0; }
-            const double ae = al[M - 1], ge = ga[M - 1], re = r[M - 1];
-            double EA = -ae * lam_u;
-            double EB = 1.0 - ae * mu_u - ge * lam1;
-            double EC = -ge * mu1;
-            double ED = re - ae * sig_u - ge * sig1;
+            const R ae = al[M - 1], ge = ga[M - 1], re = r[M - 1];
+            R EA = -ae * lam_u;
+            R EB = 1.0 - ae * mu_u - ge * lam1;
+            R EC = -ge * mu1;
+            R ED = re - ae * sig_u - ge * sig1;
 #pragma unroll
             for (int d = 1; d < P; d <<= 1) {
-                double am = __shfl_up(EA, d, P), bm = __shfl_up(EB, d, P);
-                double cm = __shfl_up(EC, d, P), dm = __shfl_up(ED, d, P);
-                double ap = __shfl_down(EA, d, P), bp = __shfl_down(EB, d, P);
-                double cp = __shfl_down(EC, d, P), dp = __shfl_down(ED, d, P);
+                R am = __shfl_up(EA, d, P), bm = __shfl_up(EB, d, P);
+                R cm = __shfl_up(EC, d, P), dm = __shfl_up(ED, d, P);
+                R ap = __shfl_down(EA, d, P), bp = __shfl_down(EB, d, P);
+                R cp = __shfl_down(EC, d, P), dp = __shfl_down(ED, d, P);
                 if (k < d) { am = 0.0; bm = 1.0; cm = 0.0; dm = 0.0; }
                 if (k + d >= P) { ap = 0.0; bp = 1.0; cp = 0.0; dp = 0.0; }
-                const double k1 = EA * rcp64(bm), k2 = EC * rcp64(bp);
-                const double nA = -k1 * am, nC = -k2 * cp;
-                const double nB = EB - k1 * cm - k2 * ap;
-                const double nD = ED - k1 * dm - k2 * dp;
+                const R k1 = EA * rcpr(bm), k2 = EC * rcpr(bp);
+                const R nA = -k1 * am, nC = -k2 * cp;
+                const R nB = EB - k1 * cm - k2 * ap;
+                const R nD = ED - k1 * dm - k2 * dp;
                 EA = nA; EB = nB; EC = nC; ED = nD;
             }
-            const double z = ED * rcp64(EB);
-            double zm = __shfl_up(z, 1, P);
+            const R z = ED * rcpr(EB);
+            R zm = __shfl_up(z, 1, P);
             if (k == 0) zm = 0.0;
-            const double xs = sig_u - lam_u * zm - mu_u * z;
+            const R xs = sig_u - lam_u * zm - mu_u * z;
 
             // interior back-substitution, in place: r[t] becomes x[t]
             r[M - 1] = z;
@@ -294,7 +310,7 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
 
             if (pinned) {
                 // null mode: zero volume-weighted mean
-                double swx = 0.0, sww = 0.0;
+                R swx = 0.0, sww = 0.0;
 #pragma unroll
                 for (int t = 0; t < M; ++t) {
                     swx += sw[s + t] * r[t];
@@ -305,7 +321,7 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
                     swx += __shfl_xor(swx, d, P);
                     sww += __shfl_xor(sww, d, P);
                 }
-                double mx = swx / sww;
+                R mx = swx / sww;
                 if (tp.xsum) {
                     // refinement: steer the correction so that x + d has zero
                     // weighted mean (in this pencil's normalisation)
@@ -354,7 +370,7 @@ __global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp
     }
 }
 
-template <typename T, int P, int M>
+template <typename T, typename R, int P, int M>
 static hipError_t launch_pm(const JobSet &js, const TriParams &tp, hipStream_t s)
 {
     // persistent blocks walk the tiles (job, z-mode, 16 x-modes) in order;
@@ -362,7 +378,7 @@ static hipError_t launch_pm(const JobSet &js, const TriParams &tp, hipStream_t s
     // run back to back
     static const int resident = [] {
         int per_cu = 0, dev = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tridiag_kernel<T, P, M>, 16 * P, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tridiag_kernel<T, R, P, M>, 16 * P, 0) !=
                 hipSuccess ||
             hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -373,9 +389,48 @@ static hipError_t launch_pm(const JobSet &js, const TriParams &tp, hipStream_t s
     const int ntiles = ntx * tp.nz * js.n;
     const int pairs = (ntiles + 1) / 2;
     const int grid = pairs < resident ? pairs : resident;
-    hipLaunchKernelGGL((tridiag_kernel<T, P, M>), dim3(grid), dim3(16 * P), 0, s, js, tp, ntx,
+    hipLaunchKernelGGL((tridiag_kernel<T, R, P, M>), dim3(grid), dim3(16 * P), 0, s, js, tp, ntx,
                        ntiles);
     return hipGetLastError();
+}
+
+template <typename T, typename R>
+static hipError_t launch_by_rows(const JobSet &js, const TriParams &tp, int n, hipStream_t s)
+{
+    // lanes per pencil and rows per lane: short chunks keep the per-lane
+    // arrays in registers
+    if (n <= 48) return launch_pm<T, R, 16, 3>(js, tp, s);
+    if (n <= 80) return launch_pm<T, R, 16, 5>(js, tp, s);
+    if (n <= 112) return launch_pm<T, R, 16, 7>(js, tp, s);
+    if (n <= 144) return launch_pm<T, R, 16, 9>(js, tp, s);
+    if (n <= 224) return launch_pm<T, R, 32, 7>(js, tp, s);
+    if (n <= 288) return launch_pm<T, R, 32, 9>(js, tp, s);
+    if (n <= 352) return launch_pm<T, R, 32, 11>(js, tp, s);
+    if (n <= 416) return launch_pm<T, R, 32, 13>(js, tp, s);
+    if (n <= 544) return launch_pm<T, R, 32, 17>(js, tp, s);
+    if (n <= 672) return launch_pm<T, R, 32, 21>(js, tp, s);
+    if (n <= 800) return launch_pm<T, R, 32, 25>(js, tp, s);
+    return hipErrorInvalidValue;
+}
+
+// Upper bound on the condition number of every Helmholtz pencil matrix
+// (1 - c s) I - c T_kind of the jobs: its eigenvalues lie in
+// [1, 1 + c (max|s| + Gershgorin bound of -T)].
+static double helmholtz_kappa(const JobSet &js, const Plan &p)
+{
+    double smax = 0.0;
+    for (double v : p.lam_x) smax = std::max(smax, -v);
+    double szmax = 0.0;
+    for (double v : p.lam_z) szmax = std::max(szmax, -v);
+    double kap = 1.0;
+    for (int q = 0; q < js.n; ++q) {
+        const int kd = js.j[q].kind;
+        double g = 0.0;
+        for (size_t j = 0; j < p.di[kd].size(); ++j)
+            g = std::max(g, std::fabs(p.lo[kd][j]) + std::fabs(p.di[kd][j]) + std::fabs(p.up[kd][j]));
+        kap = std::max(kap, 1.0 + std::fabs(js.j[q].c) * (smax + szmax + g));
+    }
+    return kap;
 }
 
 template <typename T>
@@ -409,20 +464,13 @@ static hipError_t launch_tridiag(const JobSet &js, const Plan &p, bool poisson, 
     tp.inv_sqrt_nxnz = 1.0 / std::sqrt((double)p.nx * (double)p.nz);
     int n = 0;
     for (int q = 0; q < js.n; ++q) n = js.j[q].rows > n ? js.j[q].rows : n;
-    // lanes per pencil and rows per lane: short chunks keep the per-lane
-    // arrays in registers
-    if (n <= 48) return launch_pm<T, 16, 3>(js, tp, s);
-    if (n <= 80) return launch_pm<T, 16, 5>(js, tp, s);
-    if (n <= 112) return launch_pm<T, 16, 7>(js, tp, s);
-    if (n <= 144) return launch_pm<T, 16, 9>(js, tp, s);
-    if (n <= 224) return launch_pm<T, 32, 7>(js, tp, s);
-    if (n <= 288) return launch_pm<T, 32, 9>(js, tp, s);
-    if (n <= 352) return launch_pm<T, 32, 11>(js, tp, s);
-    if (n <= 416) return launch_pm<T, 32, 13>(js, tp, s);
-    if (n <= 544) return launch_pm<T, 32, 17>(js, tp, s);
-    if (n <= 672) return launch_pm<T, 32, 21>(js, tp, s);
-    if (n <= 800) return launch_pm<T, 32, 25>(js, tp, s);
-    return hipErrorInvalidValue;
+    // FP32 arithmetic where its rounding is far below what refinement
+    // removes anyway: FP32 data (refined path), Helmholtz, and pencil
+    // condition numbers bounded by FP32_KAPPA.
+    if constexpr (sizeof(T) == 4) {
+        if (!poisson && helmholtz_kappa(js, p) <= FP32_KAPPA) return launch_by_rows<T, float>(js, tp, n, s);
+    }
+    return launch_by_rows<T, double>(js, tp, n, s);
 }
 
 hipError_t launch_tridiag_f64(const JobSet &js, const Plan &p, bool poisson, hipStream_t s)
