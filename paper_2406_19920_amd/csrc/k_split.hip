@@ -373,63 +373,83 @@ __global__ __launch_bounds__(512) void split_zgemm_kernel(SplitSet ss, int M, in
 
 // x transform, a wave owning WM row blocks and all columns of both factors.
 // MODE as for the plain kernel (0: FP32 out, forward; 1: x = C; 2: x += C).
+// Persistent like the z kernel: block b takes row tiles b, b + G, ... over
+// the jobs still running as one pipeline of 32-deep chunks.  MODE 2 writes
+// the update sums of tile rt of job q to slot q * tiles_per_job + rt.
 template <int HBT, int WM, typename Tin, int MODE, bool INV>
 __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, int N,
                                                           const b8 *__restrict__ qs,
                                                           double *__restrict__ red,
                                                           const int *__restrict__ skip, double s0,
-                                                          double s1)
+                                                          double s1, int tiles_per_job)
 {
     constexpr int QCNT = 2 * HBT * 3 * 64;
     constexpr bool DB = 2 * QCNT * 16 <= 144 * 1024;
     constexpr int QPER = (QCNT + 511) / 512;
     __shared__ b8 sq[(DB ? 2 : 1) * QCNT];
-    if (skip && skip[blockIdx.z]) return;
-    const SplitJob &jb = ss.j[blockIdx.z];
-    const int rskip = skip_first_row(jb.kind), trows = jb.rows - rskip;
-    const int M = nz * trows;
+    __shared__ double sm[2][8];
+    int live[4], nlive = 0;   // jobs not yet converged (block-uniform)
+    for (int q = 0; q < ss.n; ++q)
+        if (!(skip && skip[q])) live[nlive++] = q;
+    const int ntiles = nlive * tiles_per_job;
+    const int G = gridDim.x;
+    const int my_tiles = (int)blockIdx.x < ntiles ? (ntiles - 1 - (int)blockIdx.x) / G + 1 : 0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
     const int H = N >> 1, HB = H >> 4;
     const int qcnt = 2 * HB * 3 * 64;
-    const int row0 = (blockIdx.x * 8 + wave) * (16 * WM);
-    const int nrb = row0 < M ? min(WM, (M - row0) >> 4) : 0;
-    const Tin *__restrict__ A = static_cast<const Tin *>(jb.in);
     const int KC = H >> 5;
+    const int nsteps = my_tiles * KC;
+    const double sH = (H & 1) ? -s0 : s0;
+
+    struct TileRef { int job, rt, rskip, trows, row0, nrb; const SplitJob *jb; };
+    auto tile_ref = [&](int i) {
+        const int t = (int)blockIdx.x + i * G;
+        TileRef r;
+        r.job = live[t / tiles_per_job];
+        r.rt = t % tiles_per_job;
+        r.jb = &ss.j[r.job];
+        r.rskip = skip_first_row(r.jb->kind);
+        r.trows = r.jb->rows - r.rskip;
+        const int M = nz * r.trows;
+        r.row0 = (r.rt * 8 + wave) * (16 * WM);
+        r.nrb = r.row0 < M ? min(WM, (M - r.row0) >> 4) : 0;
+        return r;
+    };
 
     f4 acc[WM][2][HBT];
     double nyq[WM];
+    auto clear = [&]() {
 #pragma unroll
-    for (int i = 0; i < WM; ++i) {
-        nyq[i] = 0.0;
+        for (int i = 0; i < WM; ++i) {
+            nyq[i] = 0.0;
 #pragma unroll
-        for (int f = 0; f < 2; ++f)
+            for (int f = 0; f < 2; ++f)
 #pragma unroll
-            for (int j = 0; j < HBT; ++j) acc[i][f][j] = (f4){0.f, 0.f, 0.f, 0.f};
-    }
-    const Tin *arow[WM];
-#pragma unroll
-    for (int i = 0; i < WM; ++i)
-        arow[i] = A + phys_row(row0 + 16 * i + (i < nrb ? li : 0), trows, rskip) * N;
-
+                for (int j = 0; j < HBT; ++j) acc[i][f][j] = (f4){0.f, 0.f, 0.f, 0.f};
+        }
+    };
     // forward: p = X[k], m = X[mirror k]; inverse: p = cos inputs, m = sin
     // inputs.  The next chunk is loaded into the same registers once the
     // current one has been split, so its loads run under the products.
     float pc[WM][8], mc[WM][8];
-    auto load_data = [&](int kc) {
-        const int k0 = 32 * kc + 8 * lg;
+    auto load_data = [&](int step) {
+        const TileRef r = tile_ref(step / KC);
+        const Tin *A = static_cast<const Tin *>(r.jb->in);
+        const int k0 = 32 * (step % KC) + 8 * lg;
 #pragma unroll
         for (int i = 0; i < WM; ++i) {
-            if (i < nrb) {
-                load8<Tin>(arow[i] + k0, pc[i]);
+            if (i < r.nrb) {
+                const Tin *arow = A + phys_row(r.row0 + 16 * i + li, r.trows, r.rskip) * N;
+                load8<Tin>(arow + k0, pc[i]);
                 if (!INV) {
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
                         const int kk = k0 + e;
-                        mc[i][e] = (float)arow[i][kk == 0 ? H : N - kk];
+                        mc[i][e] = (float)arow[kk == 0 ? H : N - kk];
                     }
                 } else {
-                    load8<Tin>(arow[i] + H + k0, mc[i]);
+                    load8<Tin>(arow + H + k0, mc[i]);
                 }
             } else {
 #pragma unroll
@@ -437,15 +457,18 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
             }
         }
     };
+    if (nsteps == 0) return;
+    clear();
     b8 qreg[QPER];
     q_load<QPER>(qs, qcnt, qreg);
     q_store<QPER>(sq, qcnt, qreg);
     load_data(0);
-    for (int kc = 0; kc < KC; ++kc) {
+    for (int step = 0; step < nsteps; ++step) {
+        const int kc = step % KC;
         __syncthreads();
-        const b8 *cur = sq + (DB ? (kc & 1) * QCNT : 0);
-        const bool more = kc + 1 < KC;
-        if (more) q_load<QPER>(qs + (size_t)(kc + 1) * qcnt, qcnt, qreg);
+        const b8 *cur = sq + (DB ? (step & 1) * QCNT : 0);
+        const bool more = step + 1 < nsteps;
+        if (more) q_load<QPER>(qs + (size_t)((step + 1) % KC) * qcnt, qcnt, qreg);
         const int k0 = 32 * kc + 8 * lg;
         b8 ae[WM][3], ao[WM][3];
 #pragma unroll
@@ -471,14 +494,14 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
             split8(ev, ae[i]);
             split8(ov, ao[i]);
         }
-        if (more) load_data(kc + 1);
-        if (nrb > 0) {
-            constexpr int G = 2;
+        if (more) load_data(step + 1);
+        {
+            constexpr int GR = (HBT >= 6 || WM >= 2) ? 1 : 2;   // register budget
 #pragma unroll
-            for (int jg = 0; jg < HBT; jg += G) {
-                b8 bc[G][3], bs[G][3];
+            for (int jg = 0; jg < HBT; jg += GR) {
+                b8 bc[GR][3], bs[GR][3];
 #pragma unroll
-                for (int jj = 0; jj < G; ++jj)
+                for (int jj = 0; jj < GR; ++jj)
 #pragma unroll
                     for (int t = 0; t < 3; ++t) {
                         bc[jj][t] = cur[((jg + jj) * 3 + t) * 64 + lane];
@@ -487,7 +510,7 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
 #pragma unroll
                 for (int pr = 0; pr < 6; ++pr)
 #pragma unroll
-                    for (int jj = 0; jj < G; ++jj)
+                    for (int jj = 0; jj < GR; ++jj)
 #pragma unroll
                         for (int i = 0; i < WM; ++i) {
                             acc[i][0][jg + jj] = mma(ae[i][TA_[pr]], bc[jj][TB_[pr]], acc[i][0][jg + jj]);
@@ -495,178 +518,206 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                         }
             }
         }
-        if (more) {
-            if (!DB) __syncthreads();
-            q_store<QPER>(sq + (DB ? ((kc + 1) & 1) * QCNT : 0), qcnt, qreg);
-        }
-    }
-
-    const double sH = (H & 1) ? -s0 : s0;
-    double sd = 0.0, sx = 0.0;
+        if (kc == KC - 1) {   // the tile is complete: store it
+            const TileRef r = tile_ref(step / KC);
+            const SplitJob &jb = *r.jb;
+            const Tin *A = static_cast<const Tin *>(jb.in);
+            double sd = 0.0, sx = 0.0;
 #pragma unroll
-    for (int i = 0; i < WM; ++i) {
-        if (i >= nrb) continue;
-        double ny = nyq[i];
-        ny += __shfl_xor(ny, 16, 64);
-        ny += __shfl_xor(ny, 32, 64);   // every lane of row li holds its sum
-        size_t orow[4];
-        double ah[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int t = row0 + 16 * i + 4 * lg + q;
-            orow[q] = phys_row(t, trows, rskip) * N;
-            ah[q] = (double)A[orow[q] + H];   // X[H] of the output row
-            if (MODE == 1 && rskip && t % trows == 0)
-                for (int c = li; c < N; c += 16) jb.x[orow[q] - N + c] = 0.0;
-        }
-        if (!INV) {
-            double nyr[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) nyr[q] = __shfl(ny, 4 * lg + q, 64);
-#pragma unroll
-            for (int j = 0; j < HBT; ++j) {
-                if (j >= HB) break;
-                const int a = 16 * j + li;
-                const double wa = (a == 0 ? s0 : s1) * ((a & 1) ? -1.0 : 1.0);   // Q[H][a]
+            for (int i = 0; i < WM; ++i) {
+                if (i >= r.nrb) continue;
+                double ny = nyq[i];
+                ny += __shfl_xor(ny, 16, 64);
+                ny += __shfl_xor(ny, 32, 64);   // every lane of row li holds its sum
+                size_t orow[4];
+                double ah[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    jb.out[orow[q] + a] = (float)fma(ah[q], wa, (double)acc[i][0][j][q]);
-                    double sv = (double)acc[i][1][j][q];
-                    if (a == 0) sv = fma(s0, nyr[q], sv);   // spectral index H
-                    jb.out[orow[q] + H + a] = (float)sv;
+                    const int t = r.row0 + 16 * i + 4 * lg + q;
+                    orow[q] = phys_row(t, r.trows, r.rskip) * N;
+                    ah[q] = (double)A[orow[q] + H];   // X[H] of the output row
+                    // the skipped wall row before each plane's first row
+                    // holds zeros in the FP64 result
+                    if (MODE == 1 && r.rskip && t % r.trows == 0)
+                        for (int c = li; c < N; c += 16) jb.x[orow[q] - N + c] = 0.0;
                 }
-            }
-        } else {
-            if (lg == 0) {   // physical point H of row li
-                const size_t r = phys_row(row0 + 16 * i + li, trows, rskip) * N;
-                const double xh = fma((double)A[r + H], sH, ny);
-                if (MODE == 1) {
-                    jb.x[r + H] = xh;
-                } else {
-                    const double xn = jb.x[r + H] + xh;
-                    jb.x[r + H] = xn;
-                    sd += xh * xh;
-                    sx += xn * xn;
-                }
-            }
+                if (!INV) {
+                    double nyr[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                // the row's old values first (all loads in flight together;
-                // every position is distinct), then the updates
-                double xo[2][HBT];
-                if (MODE == 2) {
+                    for (int q = 0; q < 4; ++q) nyr[q] = __shfl(ny, 4 * lg + q, 64);
 #pragma unroll
                     for (int j = 0; j < HBT; ++j) {
-                        const int ii = 16 * j + li;
-                        const bool ok = j < HB;
-                        xo[0][j] = ok ? jb.x[orow[q] + ii] : 0.0;
-                        xo[1][j] = (ok && ii != 0) ? jb.x[orow[q] + N - ii] : 0.0;
-                    }
-                }
+                        if (j >= HB) break;
+                        const int a = 16 * j + li;
+                        const double wa = (a == 0 ? s0 : s1) * ((a & 1) ? -1.0 : 1.0);   // Q[H][a]
 #pragma unroll
-                for (int j = 0; j < HBT; ++j) {
-                    if (j >= HB) break;
-                    const int ii = 16 * j + li;
-                    const double sg = (ii & 1) ? -s0 : s0;   // Q[ii][H]
-                    const double u = fma(ah[q], sg, (double)acc[i][0][j][q]);
-                    const double v = (double)acc[i][1][j][q];
-                    const size_t o1 = orow[q] + ii, o2 = orow[q] + N - ii;
-                    if (MODE == 1) {
-                        jb.x[o1] = u + v;
-                        if (ii != 0) jb.x[o2] = u - v;
-                    } else {
-                        const double d1 = u + v, x1 = xo[0][j] + d1;
-                        jb.x[o1] = x1;
-                        sd += d1 * d1;
-                        sx += x1 * x1;
-                        if (ii != 0) {
-                            const double d2 = u - v, x2 = xo[1][j] + d2;
-                            jb.x[o2] = x2;
-                            sd += d2 * d2;
-                            sx += x2 * x2;
+                        for (int q = 0; q < 4; ++q) {
+                            jb.out[orow[q] + a] = (float)fma(ah[q], wa, (double)acc[i][0][j][q]);
+                            double sv = (double)acc[i][1][j][q];
+                            if (a == 0) sv = fma(s0, nyr[q], sv);   // spectral index H
+                            jb.out[orow[q] + H + a] = (float)sv;
+                        }
+                    }
+                } else {
+                    if (lg == 0) {   // physical point H of row li
+                        const size_t rr = phys_row(r.row0 + 16 * i + li, r.trows, r.rskip) * N;
+                        const double xh = fma((double)A[rr + H], sH, ny);
+                        if (MODE == 1) {
+                            jb.x[rr + H] = xh;
+                        } else {
+                            const double xn = jb.x[rr + H] + xh;
+                            jb.x[rr + H] = xn;
+                            sd += xh * xh;
+                            sx += xn * xn;
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        // the row's old values first (all loads in flight
+                        // together; every position is distinct), then updates
+                        double xo[2][HBT];
+                        if (MODE == 2) {
+#pragma unroll
+                            for (int j = 0; j < HBT; ++j) {
+                                const int ii = 16 * j + li;
+                                const bool ok = j < HB;
+                                xo[0][j] = ok ? jb.x[orow[q] + ii] : 0.0;
+                                xo[1][j] = (ok && ii != 0) ? jb.x[orow[q] + N - ii] : 0.0;
+                            }
+                        }
+#pragma unroll
+                        for (int j = 0; j < HBT; ++j) {
+                            if (j >= HB) break;
+                            const int ii = 16 * j + li;
+                            const double sg = (ii & 1) ? -s0 : s0;   // Q[ii][H]
+                            const double u = fma(ah[q], sg, (double)acc[i][0][j][q]);
+                            const double v = (double)acc[i][1][j][q];
+                            const size_t o1 = orow[q] + ii, o2 = orow[q] + N - ii;
+                            if (MODE == 1) {
+                                jb.x[o1] = u + v;
+                                if (ii != 0) jb.x[o2] = u - v;
+                            } else {
+                                const double d1 = u + v, x1 = xo[0][j] + d1;
+                                jb.x[o1] = x1;
+                                sd += d1 * d1;
+                                sx += x1 * x1;
+                                if (ii != 0) {
+                                    const double d2 = u - v, x2 = xo[1][j] + d2;
+                                    jb.x[o2] = x2;
+                                    sd += d2 * d2;
+                                    sx += x2 * x2;
+                                }
+                            }
                         }
                     }
                 }
             }
+            if (MODE == 2) {
+                sd = wave_sum(sd);
+                sx = wave_sum(sx);
+                if (lane == 0) { sm[0][wave] = sd; sm[1][wave] = sx; }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    double a = 0.0, b = 0.0;
+                    for (int w = 0; w < 8; ++w) { a += sm[0][w]; b += sm[1][w]; }
+                    const size_t slot = (size_t)r.job * tiles_per_job + r.rt;
+                    red[2 * slot] = a;
+                    red[2 * slot + 1] = b;
+                }
+            }
+            clear();
         }
-    }
-    if (MODE == 2) {
-        __shared__ double sm[2][8];
-        sd = wave_sum(sd);
-        sx = wave_sum(sx);
-        if (lane == 0) { sm[0][wave] = sd; sm[1][wave] = sx; }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double a = 0.0, b = 0.0;
-            for (int w = 0; w < 8; ++w) { a += sm[0][w]; b += sm[1][w]; }
-            const size_t slot = (size_t)blockIdx.z * gridDim.x + blockIdx.x;
-            red[2 * slot] = a;
-            red[2 * slot + 1] = b;
+        if (more) {
+            if (!DB) __syncthreads();
+            q_store<QPER>(sq + (DB ? ((step + 1) & 1) * QCNT : 0), qcnt, qreg);
         }
     }
 }
 
 // z transform, a wave owning all output rows of both factors and WN
-// column blocks; FP32 in and out.
+// column blocks; FP32 in and out.  Persistent: block b takes column tiles
+// b, b + G, ... (G = gridDim.x) over the jobs still running, and streams
+// their 32-deep chunks as one pipeline, so the next tile's first chunk is
+// loaded while the current tile's last chunk is multiplied.
 template <int HBT, int WN, bool INV>
 __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, int nx,
                                                           const b8 *__restrict__ qs,
                                                           const int *__restrict__ skip, double s0,
-                                                          double s1)
+                                                          double s1, int tiles_per_job)
 {
     constexpr int QCNT = 2 * HBT * 3 * 64;
     constexpr bool DB = 2 * QCNT * 16 <= 144 * 1024;
     constexpr int QPER = (QCNT + 511) / 512;
     __shared__ b8 sq[(DB ? 2 : 1) * QCNT];
-    if (skip && skip[blockIdx.z]) return;
-    const SplitJob &jb = ss.j[blockIdx.z];
-    const int rskip = skip_first_row(jb.kind);
-    const int Ncol = (jb.rows - rskip) * nx;
-    const size_t ldp = (size_t)jb.rows * nx;   // plane stride
+    int live[4], nlive = 0;   // jobs not yet converged (block-uniform)
+    for (int q = 0; q < ss.n; ++q)
+        if (!(skip && skip[q])) live[nlive++] = q;
+    const int ntiles = nlive * tiles_per_job;
+    const int G = gridDim.x;
+    const int my_tiles = (int)blockIdx.x < ntiles ? (ntiles - 1 - (int)blockIdx.x) / G + 1 : 0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
     const int H = N >> 1, HB = H >> 4;
     const int qcnt = 2 * HB * 3 * 64;
-    const int col0 = (blockIdx.x * 8 + wave) * (16 * WN);
-    const int ncb = col0 < Ncol ? min(WN, (Ncol - col0) >> 4) : 0;
-    const float *__restrict__ B = static_cast<const float *>(jb.in) + rskip * nx;
-    float *__restrict__ C = jb.out + rskip * nx;
     const int KC = H >> 5;
+    const int nsteps = my_tiles * KC;
+    const double sH = (H & 1) ? -s0 : s0;
+
+    // tile -> job record and this wave's first column
+    struct TileRef { const SplitJob *jb; int rskip, Ncol, col0, ncb; size_t ldp; };
+    auto tile_ref = [&](int i) {
+        const int t = (int)blockIdx.x + i * G;
+        TileRef r;
+        r.jb = &ss.j[live[t / tiles_per_job]];
+        r.rskip = skip_first_row(r.jb->kind);
+        r.Ncol = (r.jb->rows - r.rskip) * nx;
+        r.ldp = (size_t)r.jb->rows * nx;
+        r.col0 = ((t % tiles_per_job) * 8 + wave) * (16 * WN);
+        r.ncb = r.col0 < r.Ncol ? min(WN, (r.Ncol - r.col0) >> 4) : 0;
+        return r;
+    };
 
     f4 acc[2][HBT][WN];
     double nyq[WN];
-#pragma unroll
-    for (int j = 0; j < WN; ++j) {
-        nyq[j] = 0.0;
-#pragma unroll
-        for (int f = 0; f < 2; ++f)
-#pragma unroll
-            for (int i = 0; i < HBT; ++i) acc[f][i][j] = (f4){0.f, 0.f, 0.f, 0.f};
-    }
-    float pc[WN][8], mc[WN][8];   // next chunk reuses them once split
-    auto load_data = [&](int kc) {
-        const int k0 = 32 * kc + 8 * lg;
+    auto clear = [&]() {
 #pragma unroll
         for (int j = 0; j < WN; ++j) {
-            const float *col = B + col0 + 16 * j + li;
+            nyq[j] = 0.0;
+#pragma unroll
+            for (int f = 0; f < 2; ++f)
+#pragma unroll
+                for (int i = 0; i < HBT; ++i) acc[f][i][j] = (f4){0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    float pc[WN][8], mc[WN][8];   // the chunk being split; then the next one
+    auto load_data = [&](int step) {
+        const TileRef r = tile_ref(step / KC);
+        const int k0 = 32 * (step % KC) + 8 * lg;
+        const float *B = static_cast<const float *>(r.jb->in) + r.rskip * nx;
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+            const float *col = B + r.col0 + 16 * j + li;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int kk = k0 + e;
-                const bool ok = j < ncb;
-                pc[j][e] = ok ? col[(size_t)kk * ldp] : 0.f;
-                mc[j][e] = ok ? col[(size_t)(INV ? H + kk : (kk == 0 ? H : N - kk)) * ldp] : 0.f;
+                const bool ok = j < r.ncb;
+                pc[j][e] = ok ? col[(size_t)kk * r.ldp] : 0.f;
+                mc[j][e] = ok ? col[(size_t)(INV ? H + kk : (kk == 0 ? H : N - kk)) * r.ldp] : 0.f;
             }
         }
     };
+    if (nsteps == 0) return;
+    clear();
     b8 qreg[QPER];
     q_load<QPER>(qs, qcnt, qreg);
     q_store<QPER>(sq, qcnt, qreg);
     load_data(0);
-    for (int kc = 0; kc < KC; ++kc) {
+    for (int step = 0; step < nsteps; ++step) {
+        const int kc = step % KC;
         __syncthreads();
-        const b8 *cur = sq + (DB ? (kc & 1) * QCNT : 0);
-        const bool more = kc + 1 < KC;
-        if (more) q_load<QPER>(qs + (size_t)(kc + 1) * qcnt, qcnt, qreg);
+        const b8 *cur = sq + (DB ? (step & 1) * QCNT : 0);
+        const bool more = step + 1 < nsteps;
+        if (more) q_load<QPER>(qs + (size_t)((step + 1) % KC) * qcnt, qcnt, qreg);
         const int k0 = 32 * kc + 8 * lg;
         b8 be[WN][3], bo[WN][3];
 #pragma unroll
@@ -692,14 +743,14 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
             split8(ev, be[j]);
             split8(ov, bo[j]);
         }
-        if (more) load_data(kc + 1);
-        if (ncb > 0) {
-            constexpr int G = 2;
+        if (more) load_data(step + 1);
+        {
+            constexpr int GR = HBT >= 6 ? 1 : 2;   // register budget
 #pragma unroll
-            for (int ig = 0; ig < HBT; ig += G) {
-                b8 ac[G][3], as[G][3];
+            for (int ig = 0; ig < HBT; ig += GR) {
+                b8 ac[GR][3], as[GR][3];
 #pragma unroll
-                for (int ii = 0; ii < G; ++ii)
+                for (int ii = 0; ii < GR; ++ii)
 #pragma unroll
                     for (int t = 0; t < 3; ++t) {
                         ac[ii][t] = cur[((ig + ii) * 3 + t) * 64 + lane];
@@ -708,7 +759,7 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
 #pragma unroll
                 for (int pr = 0; pr < 6; ++pr)
 #pragma unroll
-                    for (int ii = 0; ii < G; ++ii)
+                    for (int ii = 0; ii < GR; ++ii)
 #pragma unroll
                         for (int j = 0; j < WN; ++j) {
                             acc[0][ig + ii][j] = mma(ac[ii][TA_[pr]], be[j][TB_[pr]], acc[0][ig + ii][j]);
@@ -716,41 +767,45 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
                         }
             }
         }
-        if (more) {
-            if (!DB) __syncthreads();
-            q_store<QPER>(sq + (DB ? ((kc + 1) & 1) * QCNT : 0), qcnt, qreg);
-        }
-    }
-
-    const double sH = (H & 1) ? -s0 : s0;
+        if (kc == KC - 1) {   // the tile is complete: store it
+            const TileRef r = tile_ref(step / KC);
+            const float *B = static_cast<const float *>(r.jb->in) + r.rskip * nx;
+            float *C = r.jb->out + r.rskip * nx;
 #pragma unroll
-    for (int j = 0; j < WN; ++j) {
-        if (j >= ncb) continue;
-        const size_t cc = (size_t)(col0 + 16 * j + li);
-        double ny = nyq[j];
-        ny += __shfl_xor(ny, 16, 64);
-        ny += __shfl_xor(ny, 32, 64);   // every lane of column li holds its sum
-        const double bh = (double)B[(size_t)H * ldp + cc];
-        if (INV && lg == 0) C[(size_t)H * ldp + cc] = (float)fma(bh, sH, ny);
+            for (int j = 0; j < WN; ++j) {
+                if (j >= r.ncb) continue;
+                const size_t cc = (size_t)(r.col0 + 16 * j + li);
+                double ny = nyq[j];
+                ny += __shfl_xor(ny, 16, 64);
+                ny += __shfl_xor(ny, 32, 64);   // every lane of column li holds its sum
+                const double bh = (double)B[(size_t)H * r.ldp + cc];
+                if (INV && lg == 0) C[(size_t)H * r.ldp + cc] = (float)fma(bh, sH, ny);
 #pragma unroll
-        for (int i = 0; i < HBT; ++i) {
-            if (i >= HB) break;
+                for (int i = 0; i < HBT; ++i) {
+                    if (i >= HB) break;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int r = 16 * i + 4 * lg + q;   // 0 <= r < H
-                if (!INV) {
-                    const double wr = (r == 0 ? s0 : s1) * ((r & 1) ? -1.0 : 1.0);   // Q[H][r]
-                    C[(size_t)r * ldp + cc] = (float)fma(bh, wr, (double)acc[0][i][j][q]);
-                    double sv = (double)acc[1][i][j][q];
-                    if (r == 0) sv = fma(s0, ny, sv);   // plane H: Nyquist
-                    C[(size_t)(H + r) * ldp + cc] = (float)sv;
-                } else {
-                    const double u = fma(bh, (r & 1) ? -s0 : s0, (double)acc[0][i][j][q]);
-                    const double v = (double)acc[1][i][j][q];
-                    C[(size_t)r * ldp + cc] = (float)(u + v);
-                    if (r != 0) C[(size_t)(N - r) * ldp + cc] = (float)(u - v);
+                    for (int q = 0; q < 4; ++q) {
+                        const int rr = 16 * i + 4 * lg + q;   // 0 <= rr < H
+                        if (!INV) {
+                            const double wr = (rr == 0 ? s0 : s1) * ((rr & 1) ? -1.0 : 1.0);   // Q[H][rr]
+                            C[(size_t)rr * r.ldp + cc] = (float)fma(bh, wr, (double)acc[0][i][j][q]);
+                            double sv = (double)acc[1][i][j][q];
+                            if (rr == 0) sv = fma(s0, ny, sv);   // plane H: Nyquist
+                            C[(size_t)(H + rr) * r.ldp + cc] = (float)sv;
+                        } else {
+                            const double u = fma(bh, (rr & 1) ? -s0 : s0, (double)acc[0][i][j][q]);
+                            const double v = (double)acc[1][i][j][q];
+                            C[(size_t)rr * r.ldp + cc] = (float)(u + v);
+                            if (rr != 0) C[(size_t)(N - rr) * r.ldp + cc] = (float)(u - v);
+                        }
+                    }
                 }
             }
+            clear();
+        }
+        if (more) {
+            if (!DB) __syncthreads();
+            q_store<QPER>(sq + (DB ? ((step + 1) & 1) * QCNT : 0), qcnt, qreg);
         }
     }
 }
@@ -939,13 +994,30 @@ static void xgemm_grid(const SplitSet &ss, const Plan &p, dim3 &grid)
     grid = dim3((M + 8 * 16 * wm - 1) / (8 * 16 * wm), 1, ss.n);
 }
 
+// Workgroups of `kernel` (block size 512) resident on the device at once.
+template <typename K>
+static int resident_blocks(K kernel)
+{
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 512, 0) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        per_cu * cus <= 0)
+        return 256;
+    return per_cu * cus;
+}
+
 template <int HBT, typename Tin, int MODE, bool INV>
 static void launch_xf(const SplitSet &ss, const Plan &p, const b8 *qs, double *red, const int *skip,
                       dim3 grid, hipStream_t s)
 {
+    static const int resident = resident_blocks(split_xfold_kernel<HBT, xf_wm(HBT), Tin, MODE, INV>);
+    const int tiles_per_job = (int)grid.x;
+    const int ntiles = tiles_per_job * ss.n;
+    const int g = ntiles < resident ? ntiles : resident;
     const double s0 = 1.0 / std::sqrt((double)p.nx), s1 = std::sqrt(2.0 / (double)p.nx);
-    hipLaunchKernelGGL((split_xfold_kernel<HBT, xf_wm(HBT), Tin, MODE, INV>), grid, dim3(512), 0, s,
-                       ss, p.nz, p.nx, qs, red, skip, s0, s1);
+    hipLaunchKernelGGL((split_xfold_kernel<HBT, xf_wm(HBT), Tin, MODE, INV>), dim3(g), dim3(512), 0, s,
+                       ss, p.nz, p.nx, qs, red, skip, s0, s1, tiles_per_job);
 }
 
 template <typename Tin, int MODE, bool INV>
@@ -1018,19 +1090,26 @@ hipError_t launch_split_xgemm(const SplitSet &ss, const Plan &p, bool inverse, b
 
 // z transform tiling: a wave owns all M = nz rows (MB <= MBT row blocks)
 // and WN column blocks.
+
+template <int HBT, int WN, bool INV>
+static void launch_zf_dir(const SplitSet &ss, const Plan &p, const b8 *qs, const int *skip, hipStream_t s)
+{
+    static const int resident = resident_blocks(split_zfold_kernel<HBT, WN, INV>);
+    const int Ncol = max_rows(ss) * p.nx;
+    const int tiles_per_job = (Ncol + 8 * 16 * WN - 1) / (8 * 16 * WN);
+    const int ntiles = tiles_per_job * ss.n;
+    const int grid = ntiles < resident ? ntiles : resident;
+    const double s0 = 1.0 / std::sqrt((double)p.nz), s1 = std::sqrt(2.0 / (double)p.nz);
+    hipLaunchKernelGGL((split_zfold_kernel<HBT, WN, INV>), dim3(grid), dim3(512), 0, s, ss, p.nz, p.nx, qs,
+                       skip, s0, s1, tiles_per_job);
+}
+
 template <int HBT, int WN>
 static void launch_zf(const SplitSet &ss, const Plan &p, bool inverse, const b8 *qs, const int *skip,
                       hipStream_t s)
 {
-    const int Ncol = max_rows(ss) * p.nx;
-    dim3 grid((Ncol + 8 * 16 * WN - 1) / (8 * 16 * WN), 1, ss.n);
-    const double s0 = 1.0 / std::sqrt((double)p.nz), s1 = std::sqrt(2.0 / (double)p.nz);
-    if (inverse)
-        hipLaunchKernelGGL((split_zfold_kernel<HBT, WN, true>), grid, dim3(512), 0, s, ss, p.nz, p.nx, qs,
-                           skip, s0, s1);
-    else
-        hipLaunchKernelGGL((split_zfold_kernel<HBT, WN, false>), grid, dim3(512), 0, s, ss, p.nz, p.nx, qs,
-                           skip, s0, s1);
+    if (inverse) launch_zf_dir<HBT, WN, true>(ss, p, qs, skip, s);
+    else launch_zf_dir<HBT, WN, false>(ss, p, qs, skip, s);
 }
 
 hipError_t launch_split_zgemm(const SplitSet &ss, const Plan &p, bool inverse, int pass, hipStream_t s)
