@@ -98,6 +98,19 @@ static __device__ __forceinline__ double wave_sum(double v)
 // while the current chunk is multiplied.
 // ---------------------------------------------------------------------------
 
+// Copy `cnt` 16-byte fragments (global, contiguous; cnt a multiple of 64)
+// straight into LDS: each wave issues whole 64-fragment slices, lane l's
+// fragment landing at slice + 16 l bytes (checked on gfx950).  Completion is
+// awaited with s_waitcnt vmcnt before the barrier that publishes the data.
+static __device__ __forceinline__ void q_dma(const b8 *__restrict__ src, b8 *dst, int cnt)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int base = wave * 64; base < cnt; base += 512)
+        __builtin_amdgcn_global_load_lds(static_cast<const void *>(src + base + lane),
+                                         (__attribute__((address_space(3))) void *)(dst + base), 16, 0, 0);
+}
+static __device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0); }
+
 // Copy `cnt` 16-byte fragments (global, contiguous) into registers / LDS.
 template <int PER>
 static __device__ __forceinline__ void q_load(const b8 *__restrict__ src, int cnt, b8 (&r)[PER])
@@ -384,9 +397,8 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                                                           double s1, int tiles_per_job)
 {
     constexpr int QCNT = 2 * HBT * 3 * 64;
-    constexpr bool DB = 2 * QCNT * 16 <= 144 * 1024;
-    constexpr int QPER = (QCNT + 511) / 512;
-    __shared__ b8 sq[(DB ? 2 : 1) * QCNT];
+    static_assert(2 * QCNT * 16 <= 144 * 1024, "double-buffered factor chunk must fit LDS");
+    __shared__ b8 sq[2 * QCNT];
     __shared__ double sm[2][8];
     int live[4], nlive = 0;   // jobs not yet converged (block-uniform)
     for (int q = 0; q < ss.n; ++q)
@@ -459,16 +471,15 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
     };
     if (nsteps == 0) return;
     clear();
-    b8 qreg[QPER];
-    q_load<QPER>(qs, qcnt, qreg);
-    q_store<QPER>(sq, qcnt, qreg);
+    q_dma(qs, sq, qcnt);
     load_data(0);
+    wait_vm();
     for (int step = 0; step < nsteps; ++step) {
         const int kc = step % KC;
         __syncthreads();
-        const b8 *cur = sq + (DB ? (step & 1) * QCNT : 0);
+        const b8 *cur = sq + (step & 1) * QCNT;
         const bool more = step + 1 < nsteps;
-        if (more) q_load<QPER>(qs + (size_t)((step + 1) % KC) * qcnt, qcnt, qreg);
+        if (more) q_dma(qs + (size_t)((step + 1) % KC) * qcnt, sq + ((step + 1) & 1) * QCNT, qcnt);
         const int k0 = 32 * kc + 8 * lg;
         b8 ae[WM][3], ao[WM][3];
 #pragma unroll
@@ -627,10 +638,7 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
             }
             clear();
         }
-        if (more) {
-            if (!DB) __syncthreads();
-            q_store<QPER>(sq + (DB ? ((step + 1) & 1) * QCNT : 0), qcnt, qreg);
-        }
+        if (more) wait_vm();   // next chunk's factors and data have landed
     }
 }
 
@@ -646,9 +654,8 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
                                                           double s1, int tiles_per_job)
 {
     constexpr int QCNT = 2 * HBT * 3 * 64;
-    constexpr bool DB = 2 * QCNT * 16 <= 144 * 1024;
-    constexpr int QPER = (QCNT + 511) / 512;
-    __shared__ b8 sq[(DB ? 2 : 1) * QCNT];
+    static_assert(2 * QCNT * 16 <= 144 * 1024, "double-buffered factor chunk must fit LDS");
+    __shared__ b8 sq[2 * QCNT];
     int live[4], nlive = 0;   // jobs not yet converged (block-uniform)
     for (int q = 0; q < ss.n; ++q)
         if (!(skip && skip[q])) live[nlive++] = q;
@@ -708,16 +715,15 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
     };
     if (nsteps == 0) return;
     clear();
-    b8 qreg[QPER];
-    q_load<QPER>(qs, qcnt, qreg);
-    q_store<QPER>(sq, qcnt, qreg);
+    q_dma(qs, sq, qcnt);
     load_data(0);
+    wait_vm();
     for (int step = 0; step < nsteps; ++step) {
         const int kc = step % KC;
         __syncthreads();
-        const b8 *cur = sq + (DB ? (step & 1) * QCNT : 0);
+        const b8 *cur = sq + (step & 1) * QCNT;
         const bool more = step + 1 < nsteps;
-        if (more) q_load<QPER>(qs + (size_t)((step + 1) % KC) * qcnt, qcnt, qreg);
+        if (more) q_dma(qs + (size_t)((step + 1) % KC) * qcnt, sq + ((step + 1) & 1) * QCNT, qcnt);
         const int k0 = 32 * kc + 8 * lg;
         b8 be[WN][3], bo[WN][3];
 #pragma unroll
@@ -803,10 +809,7 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
             }
             clear();
         }
-        if (more) {
-            if (!DB) __syncthreads();
-            q_store<QPER>(sq + (DB ? ((step + 1) & 1) * QCNT : 0), qcnt, qreg);
-        }
+        if (more) wait_vm();   // next chunk's factors and data have landed
     }
 }
 
