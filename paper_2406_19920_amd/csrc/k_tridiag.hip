@@ -103,7 +103,7 @@ struct TriParams {
 // R: arithmetic type (double; float only for well-conditioned Helmholtz
 // systems of the refined path, whose refinement absorbs FP32 rounding).
 template <typename T, typename R, int P, int M>
-__global__ __launch_bounds__(16 * P) void tridiag_kernel(JobSet js, TriParams tp, int ntx,
+__global__ __launch_bounds__(16 * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tridiag_kernel(JobSet js, TriParams tp, int ntx,
                                                          int ntiles)
 {
     constexpr int TA = 16;                 // pencils per tile
