@@ -123,9 +123,8 @@ hipError_t launch_xgemm_f64(const JobSet &js, int nz, int K, int N,
 // Folded FP64 transforms (valid when can_fold(n)).
 bool can_fold(int n);
 int fold_candidates();
-// Folded split transforms: the half length must hold whole 32-deep chunks,
-// and both factors' accumulators must fit one wave's registers.
-inline bool can_fold_split(int n) { return n % 64 == 0 && n <= 256; }
+// Folded split transforms: the half length must hold whole 32-deep chunks.
+inline bool can_fold_split(int n) { return n % 64 == 0; }
 hipError_t launch_xfold_f64(const JobSet &js, const Plan &p, bool inverse, hipStream_t s);
 hipError_t launch_zfold_f64(const JobSet &js, const Plan &p, bool inverse, hipStream_t s);
 hipError_t launch_zgemm_f64(const JobSet &js, int M, int K, int nx,

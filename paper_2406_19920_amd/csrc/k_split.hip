@@ -389,36 +389,40 @@ __global__ __launch_bounds__(512) void split_zgemm_kernel(SplitSet ss, int M, in
 // Persistent like the z kernel: block b takes row tiles b, b + G, ... over
 // the jobs still running as one pipeline of 32-deep chunks.  MODE 2 writes
 // the update sums of tile rt of job q to slot q * tiles_per_job + rt.
-template <int HBT, int WM, typename Tin, int MODE, bool INV>
+template <int HBT, int WM, typename Tin, int MODE, bool INV, int FS>
 __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, int N,
                                                           const b8 *__restrict__ qs,
                                                           double *__restrict__ red,
                                                           const int *__restrict__ skip, double s0,
                                                           double s1, int tiles_per_job)
 {
-    constexpr int QCNT = 2 * HBT * 3 * 64;
+    // FS = 1: a pipeline step is one 32-deep chunk of both factors; FS = 2
+    // (large n): one factor at a time, so a double-buffered step fits LDS
+    constexpr int QCNT = (FS == 1 ? 2 : 1) * HBT * 3 * 64;
     static_assert(2 * QCNT * 16 <= 144 * 1024, "double-buffered factor chunk must fit LDS");
     __shared__ b8 sq[2 * QCNT];
     __shared__ double sm[2][8];
-    int live[4], nlive = 0;   // jobs not yet converged (block-uniform)
+    // jobs not yet converged (block-uniform), packed 8 bits each so that no
+    // private array is indexed at run time
+    int live = 0, nlive = 0;
     for (int q = 0; q < ss.n; ++q)
-        if (!(skip && skip[q])) live[nlive++] = q;
+        if (!(skip && skip[q])) live |= q << (8 * nlive++);
     const int ntiles = nlive * tiles_per_job;
     const int G = gridDim.x;
     const int my_tiles = (int)blockIdx.x < ntiles ? (ntiles - 1 - (int)blockIdx.x) / G + 1 : 0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
     const int H = N >> 1, HB = H >> 4;
-    const int qcnt = 2 * HB * 3 * 64;
+    const int qcnt = (FS == 1 ? 2 : 1) * HB * 3 * 64;
     const int KC = H >> 5;
-    const int nsteps = my_tiles * KC;
+    const int nsteps = my_tiles * KC * FS;
     const double sH = (H & 1) ? -s0 : s0;
 
     struct TileRef { int job, rt, rskip, trows, row0, nrb; const SplitJob *jb; };
     auto tile_ref = [&](int i) {
         const int t = (int)blockIdx.x + i * G;
         TileRef r;
-        r.job = live[t / tiles_per_job];
+        r.job = (live >> (8 * (t / tiles_per_job))) & 0xff;
         r.rt = t % tiles_per_job;
         r.jb = &ss.j[r.job];
         r.rskip = skip_first_row(r.jb->kind);
@@ -445,10 +449,10 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
     // inputs.  The next chunk is loaded into the same registers once the
     // current one has been split, so its loads run under the products.
     float pc[WM][8], mc[WM][8];
-    auto load_data = [&](int step) {
-        const TileRef r = tile_ref(step / KC);
+    auto load_data = [&](int chunk) {   // chunk = tile * KC + kc
+        const TileRef r = tile_ref(chunk / KC);
         const Tin *A = static_cast<const Tin *>(r.jb->in);
-        const int k0 = 32 * (step % KC) + 8 * lg;
+        const int k0 = 32 * (chunk % KC) + 8 * lg;
 #pragma unroll
         for (int i = 0; i < WM; ++i) {
             if (i < r.nrb) {
@@ -474,63 +478,92 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
     q_dma(qs, sq, qcnt);
     load_data(0);
     wait_vm();
+    b8 ae[WM][3], ao[WM][3];   // split E and O of the current chunk
     for (int step = 0; step < nsteps; ++step) {
-        const int kc = step % KC;
+        const int chunk = step / FS, f = step % FS;   // f: factor of this step (FS = 2)
+        const int kc = chunk % KC;
         __syncthreads();
         const b8 *cur = sq + (step & 1) * QCNT;
         const bool more = step + 1 < nsteps;
-        if (more) q_dma(qs + (size_t)((step + 1) % KC) * qcnt, sq + ((step + 1) & 1) * QCNT, qcnt);
+        if (more) q_dma(qs + (size_t)((step + 1) % (KC * FS)) * qcnt, sq + ((step + 1) & 1) * QCNT, qcnt);
         const int k0 = 32 * kc + 8 * lg;
-        b8 ae[WM][3], ao[WM][3];
+        if (f == 0) {
 #pragma unroll
-        for (int i = 0; i < WM; ++i) {
-            float ev[8], ov[8];
-            if (!INV) {
+            for (int i = 0; i < WM; ++i) {
+                float ev[8], ov[8];
+                if (!INV) {
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const bool self = k0 + e == 0;
-                    ev[e] = self ? pc[i][e] : pc[i][e] + mc[i][e];
-                    ov[e] = self ? mc[i][e] : pc[i][e] - mc[i][e];
-                    nyq[i] += (e & 1) ? -(double)ev[e] : (double)ev[e];
+                    for (int e = 0; e < 8; ++e) {
+                        const bool self = k0 + e == 0;
+                        ev[e] = self ? pc[i][e] : pc[i][e] + mc[i][e];
+                        ov[e] = self ? mc[i][e] : pc[i][e] - mc[i][e];
+                        nyq[i] += (e & 1) ? -(double)ev[e] : (double)ev[e];
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        ev[e] = pc[i][e];
+                        ov[e] = mc[i][e];
+                        const double w = (k0 + e == 0) ? s0 : s1;
+                        nyq[i] += (e & 1) ? -w * (double)ev[e] : w * (double)ev[e];
+                    }
                 }
-            } else {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    ev[e] = pc[i][e];
-                    ov[e] = mc[i][e];
-                    const double w = (k0 + e == 0) ? s0 : s1;
-                    nyq[i] += (e & 1) ? -w * (double)ev[e] : w * (double)ev[e];
-                }
+                split8(ev, ae[i]);
+                split8(ov, ao[i]);
             }
-            split8(ev, ae[i]);
-            split8(ov, ao[i]);
+            if (chunk + 1 < my_tiles * KC) load_data(chunk + 1);
         }
-        if (more) load_data(step + 1);
         {
             constexpr int GR = (HBT >= 6 || WM >= 2) ? 1 : 2;   // register budget
 #pragma unroll
             for (int jg = 0; jg < HBT; jg += GR) {
-                b8 bc[GR][3], bs[GR][3];
-#pragma unroll
-                for (int jj = 0; jj < GR; ++jj)
-#pragma unroll
-                    for (int t = 0; t < 3; ++t) {
-                        bc[jj][t] = cur[((jg + jj) * 3 + t) * 64 + lane];
-                        bs[jj][t] = cur[((HB + jg + jj) * 3 + t) * 64 + lane];
-                    }
-#pragma unroll
-                for (int pr = 0; pr < 6; ++pr)
+                if (FS == 1) {
+                    b8 bc[GR][3], bs[GR][3];
 #pragma unroll
                     for (int jj = 0; jj < GR; ++jj)
 #pragma unroll
-                        for (int i = 0; i < WM; ++i) {
-                            acc[i][0][jg + jj] = mma(ae[i][TA_[pr]], bc[jj][TB_[pr]], acc[i][0][jg + jj]);
-                            acc[i][1][jg + jj] = mma(ao[i][TA_[pr]], bs[jj][TB_[pr]], acc[i][1][jg + jj]);
+                        for (int t = 0; t < 3; ++t) {
+                            bc[jj][t] = cur[((jg + jj) * 3 + t) * 64 + lane];
+                            bs[jj][t] = cur[((HB + jg + jj) * 3 + t) * 64 + lane];
                         }
+#pragma unroll
+                    for (int pr = 0; pr < 6; ++pr)
+#pragma unroll
+                        for (int jj = 0; jj < GR; ++jj)
+#pragma unroll
+                            for (int i = 0; i < WM; ++i) {
+                                acc[i][0][jg + jj] = mma(ae[i][TA_[pr]], bc[jj][TB_[pr]], acc[i][0][jg + jj]);
+                                acc[i][1][jg + jj] = mma(ao[i][TA_[pr]], bs[jj][TB_[pr]], acc[i][1][jg + jj]);
+                            }
+                } else {
+                    // one factor per step: cos (E) on even steps, sin (O) on odd
+                    b8 bf[GR][3];
+#pragma unroll
+                    for (int jj = 0; jj < GR; ++jj)
+#pragma unroll
+                        for (int t = 0; t < 3; ++t) bf[jj][t] = cur[((jg + jj) * 3 + t) * 64 + lane];
+                    if (f == 0) {
+#pragma unroll
+                        for (int pr = 0; pr < 6; ++pr)
+#pragma unroll
+                            for (int jj = 0; jj < GR; ++jj)
+#pragma unroll
+                                for (int i = 0; i < WM; ++i)
+                                    acc[i][0][jg + jj] = mma(ae[i][TA_[pr]], bf[jj][TB_[pr]], acc[i][0][jg + jj]);
+                    } else {
+#pragma unroll
+                        for (int pr = 0; pr < 6; ++pr)
+#pragma unroll
+                            for (int jj = 0; jj < GR; ++jj)
+#pragma unroll
+                                for (int i = 0; i < WM; ++i)
+                                    acc[i][1][jg + jj] = mma(ao[i][TA_[pr]], bf[jj][TB_[pr]], acc[i][1][jg + jj]);
+                    }
+                }
             }
         }
-        if (kc == KC - 1) {   // the tile is complete: store it
-            const TileRef r = tile_ref(step / KC);
+        if (kc == KC - 1 && f == FS - 1) {   // the tile is complete: store it
+            const TileRef r = tile_ref(chunk / KC);
             const SplitJob &jb = *r.jb;
             const Tin *A = static_cast<const Tin *>(jb.in);
             double sd = 0.0, sx = 0.0;
@@ -558,7 +591,7 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                     for (int q = 0; q < 4; ++q) nyr[q] = __shfl(ny, 4 * lg + q, 64);
 #pragma unroll
                     for (int j = 0; j < HBT; ++j) {
-                        if (j >= HB) break;
+                        if (j >= HB) continue;
                         const int a = 16 * j + li;
                         const double wa = (a == 0 ? s0 : s1) * ((a & 1) ? -1.0 : 1.0);   // Q[H][a]
 #pragma unroll
@@ -584,39 +617,45 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                     }
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        // the row's old values first (all loads in flight
-                        // together; every position is distinct), then updates
-                        double xo[2][HBT];
-                        if (MODE == 2) {
+                        // the row's old values first, eight column blocks at a
+                        // time (all loads in flight together; every position
+                        // is distinct), then the updates
+                        constexpr int JG = HBT < 8 ? HBT : 8;
 #pragma unroll
-                            for (int j = 0; j < HBT; ++j) {
-                                const int ii = 16 * j + li;
-                                const bool ok = j < HB;
-                                xo[0][j] = ok ? jb.x[orow[q] + ii] : 0.0;
-                                xo[1][j] = (ok && ii != 0) ? jb.x[orow[q] + N - ii] : 0.0;
+                        for (int j0 = 0; j0 < HBT; j0 += JG) {
+                            double xo[2][JG];
+                            if (MODE == 2) {
+#pragma unroll
+                                for (int jj = 0; jj < JG; ++jj) {
+                                    const int ii = 16 * (j0 + jj) + li;
+                                    const bool ok = j0 + jj < HB;
+                                    xo[0][jj] = ok ? jb.x[orow[q] + ii] : 0.0;
+                                    xo[1][jj] = (ok && ii != 0) ? jb.x[orow[q] + N - ii] : 0.0;
+                                }
                             }
-                        }
 #pragma unroll
-                        for (int j = 0; j < HBT; ++j) {
-                            if (j >= HB) break;
-                            const int ii = 16 * j + li;
-                            const double sg = (ii & 1) ? -s0 : s0;   // Q[ii][H]
-                            const double u = fma(ah[q], sg, (double)acc[i][0][j][q]);
-                            const double v = (double)acc[i][1][j][q];
-                            const size_t o1 = orow[q] + ii, o2 = orow[q] + N - ii;
-                            if (MODE == 1) {
-                                jb.x[o1] = u + v;
-                                if (ii != 0) jb.x[o2] = u - v;
-                            } else {
-                                const double d1 = u + v, x1 = xo[0][j] + d1;
-                                jb.x[o1] = x1;
-                                sd += d1 * d1;
-                                sx += x1 * x1;
-                                if (ii != 0) {
-                                    const double d2 = u - v, x2 = xo[1][j] + d2;
-                                    jb.x[o2] = x2;
-                                    sd += d2 * d2;
-                                    sx += x2 * x2;
+                            for (int jj = 0; jj < JG; ++jj) {
+                                const int j = j0 + jj;
+                                if (j >= HB) continue;
+                                const int ii = 16 * j + li;
+                                const double sg = (ii & 1) ? -s0 : s0;   // Q[ii][H]
+                                const double u = fma(ah[q], sg, (double)acc[i][0][j][q]);
+                                const double v = (double)acc[i][1][j][q];
+                                const size_t o1 = orow[q] + ii, o2 = orow[q] + N - ii;
+                                if (MODE == 1) {
+                                    jb.x[o1] = u + v;
+                                    if (ii != 0) jb.x[o2] = u - v;
+                                } else {
+                                    const double d1 = u + v, x1 = xo[0][jj] + d1;
+                                    jb.x[o1] = x1;
+                                    sd += d1 * d1;
+                                    sx += x1 * x1;
+                                    if (ii != 0) {
+                                        const double d2 = u - v, x2 = xo[1][jj] + d2;
+                                        jb.x[o2] = x2;
+                                        sd += d2 * d2;
+                                        sx += x2 * x2;
+                                    }
                                 }
                             }
                         }
@@ -647,27 +686,31 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
 // b, b + G, ... (G = gridDim.x) over the jobs still running, and streams
 // their 32-deep chunks as one pipeline, so the next tile's first chunk is
 // loaded while the current tile's last chunk is multiplied.
-template <int HBT, int WN, bool INV>
+template <int HBT, int WN, bool INV, int FS>
 __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, int nx,
                                                           const b8 *__restrict__ qs,
                                                           const int *__restrict__ skip, double s0,
                                                           double s1, int tiles_per_job)
 {
-    constexpr int QCNT = 2 * HBT * 3 * 64;
+    // FS = 1: a pipeline step is one 32-deep chunk of both factors; FS = 2
+    // (large n): one factor at a time, so a double-buffered step fits LDS
+    constexpr int QCNT = (FS == 1 ? 2 : 1) * HBT * 3 * 64;
     static_assert(2 * QCNT * 16 <= 144 * 1024, "double-buffered factor chunk must fit LDS");
     __shared__ b8 sq[2 * QCNT];
-    int live[4], nlive = 0;   // jobs not yet converged (block-uniform)
+    // jobs not yet converged (block-uniform), packed 8 bits each so that no
+    // private array is indexed at run time
+    int live = 0, nlive = 0;
     for (int q = 0; q < ss.n; ++q)
-        if (!(skip && skip[q])) live[nlive++] = q;
+        if (!(skip && skip[q])) live |= q << (8 * nlive++);
     const int ntiles = nlive * tiles_per_job;
     const int G = gridDim.x;
     const int my_tiles = (int)blockIdx.x < ntiles ? (ntiles - 1 - (int)blockIdx.x) / G + 1 : 0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
     const int H = N >> 1, HB = H >> 4;
-    const int qcnt = 2 * HB * 3 * 64;
+    const int qcnt = (FS == 1 ? 2 : 1) * HB * 3 * 64;
     const int KC = H >> 5;
-    const int nsteps = my_tiles * KC;
+    const int nsteps = my_tiles * KC * FS;
     const double sH = (H & 1) ? -s0 : s0;
 
     // tile -> job record and this wave's first column
@@ -675,7 +718,7 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
     auto tile_ref = [&](int i) {
         const int t = (int)blockIdx.x + i * G;
         TileRef r;
-        r.jb = &ss.j[live[t / tiles_per_job]];
+        r.jb = &ss.j[(live >> (8 * (t / tiles_per_job))) & 0xff];
         r.rskip = skip_first_row(r.jb->kind);
         r.Ncol = (r.jb->rows - r.rskip) * nx;
         r.ldp = (size_t)r.jb->rows * nx;
@@ -697,9 +740,9 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
         }
     };
     float pc[WN][8], mc[WN][8];   // the chunk being split; then the next one
-    auto load_data = [&](int step) {
-        const TileRef r = tile_ref(step / KC);
-        const int k0 = 32 * (step % KC) + 8 * lg;
+    auto load_data = [&](int chunk) {   // chunk = tile * KC + kc
+        const TileRef r = tile_ref(chunk / KC);
+        const int k0 = 32 * (chunk % KC) + 8 * lg;
         const float *B = static_cast<const float *>(r.jb->in) + r.rskip * nx;
 #pragma unroll
         for (int j = 0; j < WN; ++j) {
@@ -718,63 +761,92 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
     q_dma(qs, sq, qcnt);
     load_data(0);
     wait_vm();
+    b8 be[WN][3], bo[WN][3];   // split E and O of the current chunk
     for (int step = 0; step < nsteps; ++step) {
-        const int kc = step % KC;
+        const int chunk = step / FS, f = step % FS;   // f: factor of this step (FS = 2)
+        const int kc = chunk % KC;
         __syncthreads();
         const b8 *cur = sq + (step & 1) * QCNT;
         const bool more = step + 1 < nsteps;
-        if (more) q_dma(qs + (size_t)((step + 1) % KC) * qcnt, sq + ((step + 1) & 1) * QCNT, qcnt);
+        if (more) q_dma(qs + (size_t)((step + 1) % (KC * FS)) * qcnt, sq + ((step + 1) & 1) * QCNT, qcnt);
         const int k0 = 32 * kc + 8 * lg;
-        b8 be[WN][3], bo[WN][3];
+        if (f == 0) {
 #pragma unroll
-        for (int j = 0; j < WN; ++j) {
-            float ev[8], ov[8];
-            if (!INV) {
+            for (int j = 0; j < WN; ++j) {
+                float ev[8], ov[8];
+                if (!INV) {
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const bool self = k0 + e == 0;
-                    ev[e] = self ? pc[j][e] : pc[j][e] + mc[j][e];
-                    ov[e] = self ? mc[j][e] : pc[j][e] - mc[j][e];
-                    nyq[j] += (e & 1) ? -(double)ev[e] : (double)ev[e];
+                    for (int e = 0; e < 8; ++e) {
+                        const bool self = k0 + e == 0;
+                        ev[e] = self ? pc[j][e] : pc[j][e] + mc[j][e];
+                        ov[e] = self ? mc[j][e] : pc[j][e] - mc[j][e];
+                        nyq[j] += (e & 1) ? -(double)ev[e] : (double)ev[e];
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        ev[e] = pc[j][e];
+                        ov[e] = mc[j][e];
+                        const double w = (k0 + e == 0) ? s0 : s1;
+                        nyq[j] += (e & 1) ? -w * (double)ev[e] : w * (double)ev[e];
+                    }
                 }
-            } else {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    ev[e] = pc[j][e];
-                    ov[e] = mc[j][e];
-                    const double w = (k0 + e == 0) ? s0 : s1;
-                    nyq[j] += (e & 1) ? -w * (double)ev[e] : w * (double)ev[e];
-                }
+                split8(ev, be[j]);
+                split8(ov, bo[j]);
             }
-            split8(ev, be[j]);
-            split8(ov, bo[j]);
+            if (chunk + 1 < my_tiles * KC) load_data(chunk + 1);
         }
-        if (more) load_data(step + 1);
         {
             constexpr int GR = HBT >= 6 ? 1 : 2;   // register budget
 #pragma unroll
             for (int ig = 0; ig < HBT; ig += GR) {
-                b8 ac[GR][3], as[GR][3];
-#pragma unroll
-                for (int ii = 0; ii < GR; ++ii)
-#pragma unroll
-                    for (int t = 0; t < 3; ++t) {
-                        ac[ii][t] = cur[((ig + ii) * 3 + t) * 64 + lane];
-                        as[ii][t] = cur[((HB + ig + ii) * 3 + t) * 64 + lane];
-                    }
-#pragma unroll
-                for (int pr = 0; pr < 6; ++pr)
+                if (FS == 1) {
+                    b8 ac[GR][3], as[GR][3];
 #pragma unroll
                     for (int ii = 0; ii < GR; ++ii)
 #pragma unroll
-                        for (int j = 0; j < WN; ++j) {
-                            acc[0][ig + ii][j] = mma(ac[ii][TA_[pr]], be[j][TB_[pr]], acc[0][ig + ii][j]);
-                            acc[1][ig + ii][j] = mma(as[ii][TA_[pr]], bo[j][TB_[pr]], acc[1][ig + ii][j]);
+                        for (int t = 0; t < 3; ++t) {
+                            ac[ii][t] = cur[((ig + ii) * 3 + t) * 64 + lane];
+                            as[ii][t] = cur[((HB + ig + ii) * 3 + t) * 64 + lane];
                         }
+#pragma unroll
+                    for (int pr = 0; pr < 6; ++pr)
+#pragma unroll
+                        for (int ii = 0; ii < GR; ++ii)
+#pragma unroll
+                            for (int j = 0; j < WN; ++j) {
+                                acc[0][ig + ii][j] = mma(ac[ii][TA_[pr]], be[j][TB_[pr]], acc[0][ig + ii][j]);
+                                acc[1][ig + ii][j] = mma(as[ii][TA_[pr]], bo[j][TB_[pr]], acc[1][ig + ii][j]);
+                            }
+                } else {
+                    // one factor per step: cos (E) on even steps, sin (O) on odd
+                    b8 af[GR][3];
+#pragma unroll
+                    for (int ii = 0; ii < GR; ++ii)
+#pragma unroll
+                        for (int t = 0; t < 3; ++t) af[ii][t] = cur[((ig + ii) * 3 + t) * 64 + lane];
+                    if (f == 0) {
+#pragma unroll
+                        for (int pr = 0; pr < 6; ++pr)
+#pragma unroll
+                            for (int ii = 0; ii < GR; ++ii)
+#pragma unroll
+                                for (int j = 0; j < WN; ++j)
+                                    acc[0][ig + ii][j] = mma(af[ii][TA_[pr]], be[j][TB_[pr]], acc[0][ig + ii][j]);
+                    } else {
+#pragma unroll
+                        for (int pr = 0; pr < 6; ++pr)
+#pragma unroll
+                            for (int ii = 0; ii < GR; ++ii)
+#pragma unroll
+                                for (int j = 0; j < WN; ++j)
+                                    acc[1][ig + ii][j] = mma(af[ii][TA_[pr]], bo[j][TB_[pr]], acc[1][ig + ii][j]);
+                    }
+                }
             }
         }
-        if (kc == KC - 1) {   // the tile is complete: store it
-            const TileRef r = tile_ref(step / KC);
+        if (kc == KC - 1 && f == FS - 1) {   // the tile is complete: store it
+            const TileRef r = tile_ref(chunk / KC);
             const float *B = static_cast<const float *>(r.jb->in) + r.rskip * nx;
             float *C = r.jb->out + r.rskip * nx;
 #pragma unroll
@@ -788,7 +860,7 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
                 if (INV && lg == 0) C[(size_t)H * r.ldp + cc] = (float)fma(bh, sH, ny);
 #pragma unroll
                 for (int i = 0; i < HBT; ++i) {
-                    if (i >= HB) break;
+                    if (i >= HB) continue;
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const int rr = 16 * i + 4 * lg + q;   // 0 <= rr < H
@@ -986,9 +1058,10 @@ static constexpr int x_wm(int nbt) { return nbt == 4 ? 4 : (nbt == 32 ? 1 : 2); 
 static int xf_hbt(int nx)
 {
     const int hb = nx / 32;
-    return hb <= 2 ? 2 : hb <= 4 ? 4 : hb <= 6 ? 6 : 8;
+    return hb <= 2 ? 2 : hb <= 4 ? 4 : hb <= 6 ? 6 : hb <= 8 ? 8 : hb <= 12 ? 12 : 16;
 }
 static constexpr int xf_wm(int hbt) { return hbt <= 4 ? 2 : 1; }
+static constexpr int f_steps(int hbt) { return hbt <= 8 ? 1 : 2; }   // factors per pipeline step: 2 / 1
 
 static void xgemm_grid(const SplitSet &ss, const Plan &p, dim3 &grid)
 {
@@ -1014,12 +1087,13 @@ template <int HBT, typename Tin, int MODE, bool INV>
 static void launch_xf(const SplitSet &ss, const Plan &p, const b8 *qs, double *red, const int *skip,
                       dim3 grid, hipStream_t s)
 {
-    static const int resident = resident_blocks(split_xfold_kernel<HBT, xf_wm(HBT), Tin, MODE, INV>);
+    static const int resident =
+        resident_blocks(split_xfold_kernel<HBT, xf_wm(HBT), Tin, MODE, INV, f_steps(HBT)>);
     const int tiles_per_job = (int)grid.x;
     const int ntiles = tiles_per_job * ss.n;
     const int g = ntiles < resident ? ntiles : resident;
     const double s0 = 1.0 / std::sqrt((double)p.nx), s1 = std::sqrt(2.0 / (double)p.nx);
-    hipLaunchKernelGGL((split_xfold_kernel<HBT, xf_wm(HBT), Tin, MODE, INV>), dim3(g), dim3(512), 0, s,
+    hipLaunchKernelGGL((split_xfold_kernel<HBT, xf_wm(HBT), Tin, MODE, INV, f_steps(HBT)>), dim3(g), dim3(512), 0, s,
                        ss, p.nz, p.nx, qs, red, skip, s0, s1, tiles_per_job);
 }
 
@@ -1031,7 +1105,9 @@ static void launch_xf_hb(const SplitSet &ss, const Plan &p, const b8 *qs, double
     case 2: launch_xf<2, Tin, MODE, INV>(ss, p, qs, red, skip, grid, s); break;
     case 4: launch_xf<4, Tin, MODE, INV>(ss, p, qs, red, skip, grid, s); break;
     case 6: launch_xf<6, Tin, MODE, INV>(ss, p, qs, red, skip, grid, s); break;
-    default: launch_xf<8, Tin, MODE, INV>(ss, p, qs, red, skip, grid, s); break;
+    case 8: launch_xf<8, Tin, MODE, INV>(ss, p, qs, red, skip, grid, s); break;
+    case 12: launch_xf<12, Tin, MODE, INV>(ss, p, qs, red, skip, grid, s); break;
+    default: launch_xf<16, Tin, MODE, INV>(ss, p, qs, red, skip, grid, s); break;
     }
 }
 
@@ -1097,13 +1173,13 @@ hipError_t launch_split_xgemm(const SplitSet &ss, const Plan &p, bool inverse, b
 template <int HBT, int WN, bool INV>
 static void launch_zf_dir(const SplitSet &ss, const Plan &p, const b8 *qs, const int *skip, hipStream_t s)
 {
-    static const int resident = resident_blocks(split_zfold_kernel<HBT, WN, INV>);
+    static const int resident = resident_blocks(split_zfold_kernel<HBT, WN, INV, f_steps(HBT)>);
     const int Ncol = max_rows(ss) * p.nx;
     const int tiles_per_job = (Ncol + 8 * 16 * WN - 1) / (8 * 16 * WN);
     const int ntiles = tiles_per_job * ss.n;
     const int grid = ntiles < resident ? ntiles : resident;
     const double s0 = 1.0 / std::sqrt((double)p.nz), s1 = std::sqrt(2.0 / (double)p.nz);
-    hipLaunchKernelGGL((split_zfold_kernel<HBT, WN, INV>), dim3(grid), dim3(512), 0, s, ss, p.nz, p.nx, qs,
+    hipLaunchKernelGGL((split_zfold_kernel<HBT, WN, INV, f_steps(HBT)>), dim3(grid), dim3(512), 0, s, ss, p.nz, p.nx, qs,
                        skip, s0, s1, tiles_per_job);
 }
 
@@ -1125,7 +1201,9 @@ hipError_t launch_split_zgemm(const SplitSet &ss, const Plan &p, bool inverse, i
         if (hb <= 2) launch_zf<2, 2>(ss, p, inverse, qs, skip, s);
         else if (hb <= 4) launch_zf<4, 1>(ss, p, inverse, qs, skip, s);
         else if (hb <= 6) launch_zf<6, 1>(ss, p, inverse, qs, skip, s);
-        else launch_zf<8, 1>(ss, p, inverse, qs, skip, s);
+        else if (hb <= 8) launch_zf<8, 1>(ss, p, inverse, qs, skip, s);
+        else if (hb <= 12) launch_zf<12, 1>(ss, p, inverse, qs, skip, s);
+        else launch_zf<16, 1>(ss, p, inverse, qs, skip, s);
         return hipGetLastError();
     }
     const int M = p.nz;
