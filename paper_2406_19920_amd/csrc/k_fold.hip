@@ -40,7 +40,7 @@ static __device__ __forceinline__ d4 mfma(double a, double b, d4 c)
 // physical row -> spectral row; inverse: spectral -> physical.  bc, bs:
 // the two H x H factors, swizzled as B operands.  A wave owns WM row
 // blocks and WN column blocks of both factors.
-template <int WM, int WN, bool INV>
+template <int WM, int WN, bool INV, bool PF>
 __global__ __launch_bounds__(256) void xfold_f64_kernel(JobSet js, int nz, int N,
                                                         const double *__restrict__ bc,
                                                         const double *__restrict__ bs, int wgn,
@@ -77,49 +77,72 @@ __global__ __launch_bounds__(256) void xfold_f64_kernel(JobSet js, int nz, int N
 #pragma unroll
     for (int i = 0; i < WM; ++i) arow[i] = A + phys_row(row0 + 16 * i + (i < nrb ? li : 0), trows, skip) * N;
 
-    for (int kc = 0; kc < HB; ++kc) {
+    // raw operands of one 16-deep chunk: the row data (forward: X[k] and
+    // X[mirror k]; inverse: cos and sin inputs) and both factors' fragments.
+    // The next chunk's are loaded while the current chunk is multiplied.
+    d4 pa[WM], ma[WM], fc[WN], fs[WN];
+    auto load = [&](int kc) {
         const int k0 = 16 * kc + 4 * lg;
-        d4 xc[WM], xs[WM];   // forward: E, O; inverse: cos and sin inputs
 #pragma unroll
         for (int i = 0; i < WM; ++i) {
             if (i < nrb) {
+                pa[i] = *reinterpret_cast<const d4 *>(arow[i] + k0);
                 if (!INV) {
-                    const d4 pv = *reinterpret_cast<const d4 *>(arow[i] + k0);
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
                         const int kk = k0 + t;
-                        const double mv = arow[i][kk == 0 ? H : N - kk];
-                        xc[i][t] = kk == 0 ? pv[t] : pv[t] + mv;
-                        xs[i][t] = kk == 0 ? mv : pv[t] - mv;
+                        ma[i][t] = arow[i][kk == 0 ? H : N - kk];
                     }
-                    // Nyquist output: sum of (-1)^i E[i]
-                    nyq[i] += (xc[i][0] - xc[i][1]) + (xc[i][2] - xc[i][3]);
                 } else {
-                    xc[i] = *reinterpret_cast<const d4 *>(arow[i] + k0);
-                    xs[i] = *reinterpret_cast<const d4 *>(arow[i] + H + k0);
-                    // physical point H: sum of Q[H][a] Xc[a], Q[H][a] = w_a (-1)^a
-                    nyq[i] = fma(k0 == 0 ? s0 : s1, xc[i][0], nyq[i]);
-                    nyq[i] = fma(-s1, xc[i][1], nyq[i]);
-                    nyq[i] = fma(s1, xc[i][2], nyq[i]);
-                    nyq[i] = fma(-s1, xc[i][3], nyq[i]);
+                    ma[i] = *reinterpret_cast<const d4 *>(arow[i] + H + k0);
                 }
             } else {
-                xc[i] = (d4){0, 0, 0, 0};
-                xs[i] = (d4){0, 0, 0, 0};
+                pa[i] = (d4){0, 0, 0, 0};
+                ma[i] = (d4){0, 0, 0, 0};
             }
         }
-        d4 b_c[WN], b_s[WN];
 #pragma unroll
         for (int j = 0; j < WN; ++j) {
             if (j < ncb) {
                 const size_t o = (((size_t)kc * HB + cb0 + j) * 64 + lane) * 4;
-                b_c[j] = *reinterpret_cast<const d4 *>(bc + o);
-                b_s[j] = *reinterpret_cast<const d4 *>(bs + o);
+                fc[j] = *reinterpret_cast<const d4 *>(bc + o);
+                fs[j] = *reinterpret_cast<const d4 *>(bs + o);
             } else {
-                b_c[j] = (d4){0, 0, 0, 0};
-                b_s[j] = (d4){0, 0, 0, 0};
+                fc[j] = (d4){0, 0, 0, 0};
+                fs[j] = (d4){0, 0, 0, 0};
             }
         }
+    };
+    if (PF) load(0);
+    for (int kc = 0; kc < HB; ++kc) {
+        const int k0 = 16 * kc + 4 * lg;
+        if (!PF) load(kc);   // no prefetch: fewer registers, more waves
+        d4 xc[WM], xs[WM];   // forward: E, O; inverse: cos and sin inputs
+#pragma unroll
+        for (int i = 0; i < WM; ++i) {
+            if (!INV) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const bool self = k0 + t == 0;
+                    xc[i][t] = self ? pa[i][t] : pa[i][t] + ma[i][t];
+                    xs[i][t] = self ? ma[i][t] : pa[i][t] - ma[i][t];
+                }
+                // Nyquist output: sum of (-1)^i E[i]
+                nyq[i] += (xc[i][0] - xc[i][1]) + (xc[i][2] - xc[i][3]);
+            } else {
+                xc[i] = pa[i];
+                xs[i] = ma[i];
+                // physical point H: sum of Q[H][a] Xc[a], Q[H][a] = w_a (-1)^a
+                nyq[i] = fma(k0 == 0 ? s0 : s1, xc[i][0], nyq[i]);
+                nyq[i] = fma(-s1, xc[i][1], nyq[i]);
+                nyq[i] = fma(s1, xc[i][2], nyq[i]);
+                nyq[i] = fma(-s1, xc[i][3], nyq[i]);
+            }
+        }
+        d4 b_c[WN], b_s[WN];
+#pragma unroll
+        for (int j = 0; j < WN; ++j) { b_c[j] = fc[j]; b_s[j] = fs[j]; }
+        if (PF && kc + 1 < HB) load(kc + 1);
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -190,7 +213,7 @@ __global__ __launch_bounds__(256) void xfold_f64_kernel(JobSet js, int nz, int N
 // rows*nx), multiplied from the left.  ac, as: the two H x H factors,
 // swizzled as A operands.  A wave owns WM row blocks (of both factors) and
 // WN column blocks.
-template <int WM, int WN, bool INV>
+template <int WM, int WN, bool INV, bool PF>
 __global__ __launch_bounds__(256) void zfold_f64_kernel(JobSet js, int N, int nx,
                                                         const double *__restrict__ ac,
                                                         const double *__restrict__ as, int wgn,
@@ -224,51 +247,67 @@ __global__ __launch_bounds__(256) void zfold_f64_kernel(JobSet js, int N, int nx
             acc_s[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
         }
     }
-    for (int kc = 0; kc < HB; ++kc) {
+    // raw operands of one 16-deep chunk (both factors' fragments; the
+    // column data: forward X[k] and X[mirror k], inverse cos and sin planes);
+    // the next chunk's are loaded while the current chunk is multiplied
+    d4 fa[WM], fb[WM], pa[WN], ma[WN];
+    auto load = [&](int kc) {
         const int k0 = 16 * kc + 4 * lg;
-        d4 a_c[WM], a_s[WM];
 #pragma unroll
         for (int i = 0; i < WM; ++i) {
             if (i < nrb) {
                 const size_t o = (((size_t)kc * HB + rb0 + i) * 64 + lane) * 4;
-                a_c[i] = *reinterpret_cast<const d4 *>(ac + o);
-                a_s[i] = *reinterpret_cast<const d4 *>(as + o);
+                fa[i] = *reinterpret_cast<const d4 *>(ac + o);
+                fb[i] = *reinterpret_cast<const d4 *>(as + o);
             } else {
-                a_c[i] = (d4){0, 0, 0, 0};
-                a_s[i] = (d4){0, 0, 0, 0};
+                fa[i] = (d4){0, 0, 0, 0};
+                fb[i] = (d4){0, 0, 0, 0};
             }
         }
-        d4 xc[WN], xs[WN];
 #pragma unroll
         for (int j = 0; j < WN; ++j) {
             if (j < ncb) {
                 const double *col = B + col0 + 16 * j + li;
-                if (!INV) {
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const int kk = k0 + t;
-                        const double pv = col[(size_t)kk * ldp];
-                        const double mv = col[(size_t)(kk == 0 ? H : N - kk) * ldp];
-                        xc[j][t] = kk == 0 ? pv : pv + mv;
-                        xs[j][t] = kk == 0 ? mv : pv - mv;
-                    }
-                    nyq[j] += (xc[j][0] - xc[j][1]) + (xc[j][2] - xc[j][3]);
-                } else {
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        xc[j][t] = col[(size_t)(k0 + t) * ldp];
-                        xs[j][t] = col[(size_t)(H + k0 + t) * ldp];
-                    }
-                    nyq[j] = fma(k0 == 0 ? s0 : s1, xc[j][0], nyq[j]);
-                    nyq[j] = fma(-s1, xc[j][1], nyq[j]);
-                    nyq[j] = fma(s1, xc[j][2], nyq[j]);
-                    nyq[j] = fma(-s1, xc[j][3], nyq[j]);
+                for (int t = 0; t < 4; ++t) {
+                    const int kk = k0 + t;
+                    pa[j][t] = col[(size_t)kk * ldp];
+                    ma[j][t] = col[(size_t)(INV ? H + kk : (kk == 0 ? H : N - kk)) * ldp];
                 }
             } else {
-                xc[j] = (d4){0, 0, 0, 0};
-                xs[j] = (d4){0, 0, 0, 0};
+                pa[j] = (d4){0, 0, 0, 0};
+                ma[j] = (d4){0, 0, 0, 0};
             }
         }
+    };
+    if (PF) load(0);
+    for (int kc = 0; kc < HB; ++kc) {
+        const int k0 = 16 * kc + 4 * lg;
+        if (!PF) load(kc);   // no prefetch: fewer registers, more waves
+        d4 a_c[WM], a_s[WM];
+#pragma unroll
+        for (int i = 0; i < WM; ++i) { a_c[i] = fa[i]; a_s[i] = fb[i]; }
+        d4 xc[WN], xs[WN];
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+            if (!INV) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const bool self = k0 + t == 0;
+                    xc[j][t] = self ? pa[j][t] : pa[j][t] + ma[j][t];
+                    xs[j][t] = self ? ma[j][t] : pa[j][t] - ma[j][t];
+                }
+                nyq[j] += (xc[j][0] - xc[j][1]) + (xc[j][2] - xc[j][3]);
+            } else {
+                xc[j] = pa[j];
+                xs[j] = ma[j];
+                nyq[j] = fma(k0 == 0 ? s0 : s1, xc[j][0], nyq[j]);
+                nyq[j] = fma(-s1, xc[j][1], nyq[j]);
+                nyq[j] = fma(s1, xc[j][2], nyq[j]);
+                nyq[j] = fma(-s1, xc[j][3], nyq[j]);
+            }
+        }
+        if (PF && kc + 1 < HB) load(kc + 1);
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -324,16 +363,18 @@ static int max_rows(const JobSet &js)   // transform rows per plane
 
 bool can_fold(int n) { return n % 32 == 0; }
 
-// Tile candidates (row blocks x column blocks per wave).  Every candidate
-// sums each output element in the same order, so the choice changes only
-// the speed, never the result.
-static constexpr int XF_WM[] = {2, 4, 4, 1};
-static constexpr int XF_WN[] = {2, 1, 2, 4};
-static constexpr int ZF_WM[] = {2, 1, 2, 4};
-static constexpr int ZF_WN[] = {2, 4, 4, 1};
-int fold_candidates() { return 4; }
+// Tile candidates (row blocks x column blocks per wave, and whether the next
+// chunk's operands are loaded ahead at the cost of registers).  Every
+// candidate sums each output element in the same order, so the choice
+// changes only the speed, never the result.
+static constexpr int XF_WM[] = {2, 4, 4, 1, 2, 1, 2, 1};
+static constexpr int XF_WN[] = {2, 1, 2, 4, 2, 4, 1, 2};
+static constexpr int ZF_WM[] = {2, 1, 2, 4, 2, 1, 2, 1};
+static constexpr int ZF_WN[] = {2, 4, 4, 1, 2, 4, 1, 2};
+static constexpr bool F_PF[] = {false, false, false, false, true, true, true, true};
+int fold_candidates() { return 8; }
 
-template <int WM, int WN>
+template <int WM, int WN, bool PF>
 static hipError_t xfold_launch(const JobSet &js, const Plan &p, bool inverse, hipStream_t s)
 {
     const int N = p.nx, HB = N / 32;
@@ -346,15 +387,15 @@ static hipError_t xfold_launch(const JobSet &js, const Plan &p, bool inverse, hi
     const double *bs = blob_ptr(p, inverse ? p.lay.fx_inv_s : p.lay.fx_fwd_s);
     const double s0 = 1.0 / std::sqrt((double)N), s1 = std::sqrt(2.0 / (double)N);
     if (inverse)
-        hipLaunchKernelGGL((xfold_f64_kernel<WM, WN, true>), grid, dim3(256), 0, s, js, p.nz, N, bc, bs,
+        hipLaunchKernelGGL((xfold_f64_kernel<WM, WN, true, PF>), grid, dim3(256), 0, s, js, p.nz, N, bc, bs,
                            wgn, s0, s1);
     else
-        hipLaunchKernelGGL((xfold_f64_kernel<WM, WN, false>), grid, dim3(256), 0, s, js, p.nz, N, bc,
+        hipLaunchKernelGGL((xfold_f64_kernel<WM, WN, false, PF>), grid, dim3(256), 0, s, js, p.nz, N, bc,
                            bs, wgn, s0, s1);
     return hipGetLastError();
 }
 
-template <int WM, int WN>
+template <int WM, int WN, bool PF>
 static hipError_t zfold_launch(const JobSet &js, const Plan &p, bool inverse, hipStream_t s)
 {
     const int N = p.nz, HB = N / 32;
@@ -367,21 +408,24 @@ static hipError_t zfold_launch(const JobSet &js, const Plan &p, bool inverse, hi
     const double *as = blob_ptr(p, inverse ? p.lay.fz_inv_s : p.lay.fz_fwd_s);
     const double s0 = 1.0 / std::sqrt((double)N), s1 = std::sqrt(2.0 / (double)N);
     if (inverse)
-        hipLaunchKernelGGL((zfold_f64_kernel<WM, WN, true>), grid, dim3(256), 0, s, js, N, p.nx, ac, as,
+        hipLaunchKernelGGL((zfold_f64_kernel<WM, WN, true, PF>), grid, dim3(256), 0, s, js, N, p.nx, ac, as,
                            wgn, s0, s1);
     else
-        hipLaunchKernelGGL((zfold_f64_kernel<WM, WN, false>), grid, dim3(256), 0, s, js, N, p.nx, ac,
+        hipLaunchKernelGGL((zfold_f64_kernel<WM, WN, false, PF>), grid, dim3(256), 0, s, js, N, p.nx, ac,
                            as, wgn, s0, s1);
     return hipGetLastError();
 }
 
+#define IBS_FOLD_CASE(F, T, c) \
+    case c: return F<T##_WM[c], T##_WN[c], F_PF[c]>(js, p, inverse, s);
+
 hipError_t launch_xfold_f64(const JobSet &js, const Plan &p, bool inverse, hipStream_t s)
 {
     switch (p.tune[TUNE_XFOLD] < 0 ? 0 : p.tune[TUNE_XFOLD]) {
-    case 0: return xfold_launch<XF_WM[0], XF_WN[0]>(js, p, inverse, s);
-    case 1: return xfold_launch<XF_WM[1], XF_WN[1]>(js, p, inverse, s);
-    case 2: return xfold_launch<XF_WM[2], XF_WN[2]>(js, p, inverse, s);
-    case 3: return xfold_launch<XF_WM[3], XF_WN[3]>(js, p, inverse, s);
+        IBS_FOLD_CASE(xfold_launch, XF, 0) IBS_FOLD_CASE(xfold_launch, XF, 1)
+        IBS_FOLD_CASE(xfold_launch, XF, 2) IBS_FOLD_CASE(xfold_launch, XF, 3)
+        IBS_FOLD_CASE(xfold_launch, XF, 4) IBS_FOLD_CASE(xfold_launch, XF, 5)
+        IBS_FOLD_CASE(xfold_launch, XF, 6) IBS_FOLD_CASE(xfold_launch, XF, 7)
     default: return hipErrorInvalidValue;
     }
 }
@@ -389,12 +433,13 @@ hipError_t launch_xfold_f64(const JobSet &js, const Plan &p, bool inverse, hipSt
 hipError_t launch_zfold_f64(const JobSet &js, const Plan &p, bool inverse, hipStream_t s)
 {
     switch (p.tune[TUNE_ZFOLD] < 0 ? 0 : p.tune[TUNE_ZFOLD]) {
-    case 0: return zfold_launch<ZF_WM[0], ZF_WN[0]>(js, p, inverse, s);
-    case 1: return zfold_launch<ZF_WM[1], ZF_WN[1]>(js, p, inverse, s);
-    case 2: return zfold_launch<ZF_WM[2], ZF_WN[2]>(js, p, inverse, s);
-    case 3: return zfold_launch<ZF_WM[3], ZF_WN[3]>(js, p, inverse, s);
+        IBS_FOLD_CASE(zfold_launch, ZF, 0) IBS_FOLD_CASE(zfold_launch, ZF, 1)
+        IBS_FOLD_CASE(zfold_launch, ZF, 2) IBS_FOLD_CASE(zfold_launch, ZF, 3)
+        IBS_FOLD_CASE(zfold_launch, ZF, 4) IBS_FOLD_CASE(zfold_launch, ZF, 5)
+        IBS_FOLD_CASE(zfold_launch, ZF, 6) IBS_FOLD_CASE(zfold_launch, ZF, 7)
     default: return hipErrorInvalidValue;
     }
 }
+#undef IBS_FOLD_CASE
 
 }  // namespace ibs

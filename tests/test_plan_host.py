@@ -90,7 +90,7 @@ def test_plan_bytes_and_errors():
         assert e.value.status == ibs.IBS_ERR_NOT_UPLOADED
         ibs.ibs_plan_set_tiles(p, [3, -1])
         with pytest.raises(ibs.IbsError) as e:
-            ibs.ibs_plan_set_tiles(p, [4, 0])
+            ibs.ibs_plan_set_tiles(p, [8, 0])
         assert e.value.status == ibs.IBS_ERR_INVALID_ARG
     finally:
         ibs.solver_plan_destroy(p)
