@@ -90,10 +90,16 @@ def main():
                          "shell; batch: 64 mixed-size jobs as one graph; serve: arrival-rate sweep")
     ap.add_argument("--count", type=int, default=2000, help="serve: requests per rate")
     ap.add_argument("--rates", type=str, default="100,200,500,1000,2000,5000")
+    ap.add_argument("--geometries", type=int, default=0,
+                    help="serve: draw requests from a pool of this many (n, beta) grids so plans "
+                         "are reused (0: every request on a grid of its own)")
     ap.add_argument("--passes", type=int, default=2,
                     help="refinement pass cap of the refined path (0: library default, up to 3 for "
                          "the pressure problem); the 256^3 workload converges in 2, and a cap "
                          "above that only adds launches whose kernels return at once")
+    ap.add_argument("--tiles", type=str, default="",
+                    help="FP64 transform tile choices 'X,Z' to use instead of autotuning (keeps "
+                         "the tuner's trial launches out of counter runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -128,7 +134,13 @@ def main():
         kw = {} if precision == ibs.IBS_FP64 else {"max_iter": args.passes}
         S = ibs.Solver(n, n, n, beta=beta, precision=precision, **kw)
         # measured tile shapes for this grid (set-up, outside the timed region)
-        tiles = S.autotune() if precision == ibs.IBS_FP64 else None
+        tiles = None
+        if precision == ibs.IBS_FP64:
+            if args.tiles:
+                tiles = [int(t) for t in args.tiles.split(",")]
+                ibs.ibs_plan_set_tiles(S.plan, tiles)
+            else:
+                tiles = S.autotune()
         xu, xv, xw = S.empty(1), S.empty(2), S.empty(3)
         b = S.empty(0)
         phi = S.empty(0)
@@ -308,7 +320,7 @@ def bench_serve(args):
     torch.cuda.synchronize()
     rows = []
     for i, rate in enumerate(rates):
-        reqs = synth.serving_requests(rate, args.count, seed=5 + i)
+        reqs = synth.serving_requests(rate, args.count, seed=5 + i, geometries=args.geometries)
         srv = serve.Server(ex, 96 << 30, 8)
         res = srv.run(reqs)
         d = res.summary()
@@ -324,7 +336,9 @@ def bench_serve(args):
            "data": "synthetic",
            "config": {"workload": "Poisson-process arrivals; 50/50 Poisson or Helmholtz x3; 50/50 FP64 "
                                   "or refined; n log-uniform [32,384] (multiple of 32); beta ~ U[0,3]; "
-                                  "8 slots, 96 GiB budget", "rates": rates},
+                                  + (f"(n, beta) from a pool of {args.geometries} grids; " if args.geometries
+                                     else "a new grid per request; ")
+                                  + "8 slots, 96 GiB budget", "rates": rates},
            "sweep": rows}
     print(json.dumps(out), flush=True)
 

@@ -126,8 +126,10 @@ ibs_status solver_plan(const ibs_grid_desc *desc, ibs_plan *out);
  * IBS_OP_HELMHOLTZ_U for a Helmholtz batch of ncomp (1..3) components (the
  * count covers any mix of u, v, w); ncomp is ignored for Poisson.
  * const_bytes: size of the device constant buffer for solver_plan_upload();
- * work_bytes: minimum workspace for one solve call.  Either output pointer
- * may be NULL. */
+ * work_bytes: minimum workspace for one solve call: one FP64 field per
+ * component on the FP64 path, three FP32 fields per component on the
+ * refined path (cells of a field: nz * ny * nx, or nz * (ny+1) * nx for a
+ * Helmholtz batch).  Either output pointer may be NULL. */
 ibs_status solver_plan_bytes(ibs_plan plan, int32_t op, int32_t ncomp,
                              size_t *const_bytes, size_t *work_bytes);
 

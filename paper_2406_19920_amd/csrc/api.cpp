@@ -89,10 +89,14 @@ ibs_status profile_suspend(ibs_plan plan, bool *was_on)
 }
 void profile_resume(ibs_plan plan, bool was_on) { reinterpret_cast<Plan *>(plan)->prof.on = was_on; }
 
+// FP64 path: one FP64 scratch field per component.  Refined path: three
+// FP32 fields per component (two transform buffers and the stored first
+// iterate).
 size_t work_bytes_for(const Plan &p, int op, int ncomp)
 {
-    if (op == IBS_OP_POISSON) return field_doubles(p, p.ny) * sizeof(double);
-    return (size_t)ncomp * field_doubles(p, p.ny + 1) * sizeof(double);
+    const size_t per = p.desc.precision == IBS_FP64 ? sizeof(double) : 3 * sizeof(float);
+    if (op == IBS_OP_POISSON) return field_doubles(p, p.ny) * per;
+    return (size_t)ncomp * field_doubles(p, p.ny + 1) * per;
 }
 
 static double total_cells(const JobSet &js, const Plan &p)
@@ -150,9 +154,11 @@ static ibs_status run_fp64_pipeline(Plan &p, JobSet js, double *W, double *X, bo
 // Refined path: pass 0 solves A x = b with the split-precision transforms;
 // every later pass forms r = b - A x in FP64 (stored FP32), solves A d = r
 // the same way and updates x += d in FP64.  The job records carry the
-// right-hand side (b), the FP64 iterate (x) and two FP32 work fields each.
-static ibs_status run_refined(Plan &p, SplitSet ss, float *const *W1, float *const *W2, bool poisson,
-                              int passes, hipStream_t s)
+// right-hand side (b), the FP64 iterate (x) and three FP32 work fields each:
+// two transform buffers and W3, which holds the first iterate in FP32 when a
+// second pass follows (that pass then writes x = W3 + d).
+static ibs_status run_refined(Plan &p, SplitSet ss, float *const *W1, float *const *W2,
+                              float *const *W3, bool poisson, int passes, hipStream_t s)
 {
     hipError_t e;
     if (passes > max_refine_passes(ss, p)) {
@@ -175,10 +181,17 @@ static ibs_status run_refined(Plan &p, SplitSet ss, float *const *W1, float *con
         js.j[q].kind = ss.j[q].kind;
         js.j[q].c = ss.j[q].c;
     }
+    // With a second pass to come, the first iterate is only FP32-accurate
+    // and the second pass rewrites x: keep it in FP32 in W3 until then.
+    const bool x32 = passes >= 2;
     for (int pass = 0; pass < passes; ++pass) {
+        const bool xs32 = x32 && pass <= 1;
+        for (int q = 0; q < ss.n; ++q)
+            ss.j[q].xs = xs32 ? static_cast<void *>(W3[q]) : static_cast<void *>(ss.j[q].x);
         if (pass > 0) {
             for (int q = 0; q < ss.n; ++q) ss.j[q].r = W2[q];
-            e = timed(p, PK_RESIDUAL, 10.0 * cells, 20.0 * cells, s, [&] { return launch_residual_f32(ss, p, pass, s); });
+            e = timed(p, PK_RESIDUAL, 10.0 * cells, (xs32 ? 16.0 : 20.0) * cells, s,
+                      [&] { return launch_residual_f32(ss, p, pass, xs32, s); });
             if (e != hipSuccess) return hip_fail(e, "residual (refined)");
         }
         for (int q = 0; q < ss.n; ++q) {
@@ -198,8 +211,9 @@ static ibs_status run_refined(Plan &p, SplitSet ss, float *const *W1, float *con
         e = timed(p, PK_ZGEMM_SPLIT, zfl, 8.0 * cells, s, [&] { return launch_split_zgemm(ss, p, true, pass, s); });
         if (e != hipSuccess) return hip_fail(e, "z inverse (split)");
         for (int q = 0; q < ss.n; ++q) ss.j[q].in = W1[q];
-        const int mode = pass == 0 ? 1 : 2;
-        e = timed(p, PK_UPDATE, xfl, (pass == 0 ? 12.0 : 20.0) * cells, s,
+        const int mode = pass == 0 ? (xs32 ? 3 : 1) : (xs32 ? 4 : 2);
+        const double ub = mode == 3 ? 8.0 : (mode == 1 ? 12.0 : (mode == 4 ? 16.0 : 20.0));
+        e = timed(p, PK_UPDATE, xfl, ub * cells, s,
                   [&] { return launch_split_xgemm(ss, p, true, false, mode, pass, s); });
         if (e != hipSuccess) return hip_fail(e, "x inverse + update (split)");
         if (pass >= 1) {
@@ -306,7 +320,8 @@ ibs_status solve_poisson(ibs_plan plan, const double *b, double *phi, void *work
         ss.j[0].info = info;
         float *W1 = static_cast<float *>(work);
         float *W2 = W1 + field_doubles(p, p.ny);
-        return run_refined(p, ss, &W1, &W2, true, default_passes(p, true), s);
+        float *W3 = W2 + field_doubles(p, p.ny);
+        return run_refined(p, ss, &W1, &W2, &W3, true, default_passes(p, true), s);
     }
     double *W = static_cast<double *>(work);
     JobSet js{};
@@ -350,7 +365,7 @@ ibs_status solve_helmholtz_batch(ibs_plan plan, int32_t ncomp, const int32_t *co
     if (p.desc.precision != IBS_FP64) {
         SplitSet ss{};
         ss.n = ncomp;
-        float *W1[4], *W2[4];
+        float *W1[4], *W2[4], *W3[4];
         for (int q = 0; q < ncomp; ++q) {
             if (x[q] == r[q]) { set_error("the refined path needs x[q] distinct from r[q]"); return IBS_ERR_INVALID_ARG; }
             ss.j[q].b = r[q];
@@ -360,10 +375,11 @@ ibs_status solve_helmholtz_batch(ibs_plan plan, int32_t ncomp, const int32_t *co
             ss.j[q].op = comp[q] + 1;
             ss.j[q].c = c[q];
             ss.j[q].info = js.j[q].info;
-            W1[q] = reinterpret_cast<float *>(W + q * stride);
+            W1[q] = static_cast<float *>(work) + 3 * q * stride;
             W2[q] = W1[q] + stride;
+            W3[q] = W2[q] + stride;
         }
-        return run_refined(p, ss, W1, W2, false, default_passes(p, false), s);
+        return run_refined(p, ss, W1, W2, W3, false, default_passes(p, false), s);
     }
     for (int q = 0; q < ncomp; ++q) { js.j[q].in = r[q]; js.j[q].out = W + q * stride; }
     double *Ws[4], *Xs[4];

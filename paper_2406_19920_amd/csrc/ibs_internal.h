@@ -147,6 +147,8 @@ struct SplitJob {
     const void *in;     // x transforms: FP64 (first pass) or FP32 input rows
     float *out;         // FP32 output (forward passes, z passes)
     double *x;          // x inverse: FP64 iterate (store or += update)
+    void *xs;           // stored iterate the residual and the update read: x itself, or
+                        // (first two passes of a multi-pass solve) an FP32 workspace field
     const double *b;    // residual: right-hand side
     float *r;           // residual: FP32 output
     int rows;           // rows per z-plane
@@ -160,7 +162,8 @@ struct SplitSet {
     int n;
 };
 // x transform: in (FP64 when in64, else FP32) -> out (FP32), or, for the
-// inverse (mode 1: x = result, mode 2: x += result with norm partials).
+// inverse: mode 1: x = result; 2: x += result with norm partials; 3: xs =
+// result in FP32; 4: x = xs (FP32) + result with norm partials.
 // pass: refinement pass of an update (mode 2), selecting its partial-sum region.
 // Kernels of pass >= 2 return at once for jobs whose stop flag is set.
 hipError_t launch_split_xgemm(const SplitSet &ss, const Plan &p, bool inverse, bool in64, int mode,
@@ -170,7 +173,8 @@ hipError_t launch_split_zgemm(const SplitSet &ss, const Plan &p, bool inverse, i
 // pass: refinement pass (0 records the rhs mean; later passes steer the
 // Poisson correction so that x + d has zero weighted mean)
 hipError_t launch_tridiag_f32(const JobSet &js, const Plan &p, bool poisson, int pass, hipStream_t s);
-hipError_t launch_residual_f32(const SplitSet &ss, const Plan &p, int pass, hipStream_t s);
+// x32: the stored iterate xs is FP32 (else FP64)
+hipError_t launch_residual_f32(const SplitSet &ss, const Plan &p, int pass, bool x32, hipStream_t s);
 int residual_tiles(const Plan &p);   // residual blocks (x-sum partials) per job
 // After pass >= 1: predict the error, write the report, set the stop flag.
 hipError_t launch_refine_check(const SplitSet &ss, const Plan &p, int pass, hipStream_t s);

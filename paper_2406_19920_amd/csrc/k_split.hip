@@ -17,6 +17,7 @@
 #include "ibs_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace ibs {
 
@@ -24,6 +25,34 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 typedef float fv8 __attribute__((ext_vector_type(8)));
 typedef double dv4 __attribute__((ext_vector_type(4)));
+
+// Inverse x transform epilogues.  MODE 1 stores the iterate x = C (FP64);
+// MODE 3 stores it in FP32 in the job's stored-iterate field xs (the first
+// pass of a multi-pass solve: its result is only FP32-accurate, and the next
+// pass rewrites x); MODE 2 updates x += C from the FP64 x; MODE 4 writes
+// x = xs + C from the FP32 xs.  Modes 2 and 4 also sum C^2 and x^2.
+template <int MODE> struct XStore {
+    static constexpr bool store = MODE == 1 || MODE == 3;
+    static constexpr bool update = MODE == 2 || MODE == 4;
+    // the skipped wall rows are zeroed by the first pass: in x (MODE 1), or
+    // in both xs and x (MODE 3; MODE 4 then writes the transform rows only)
+    static constexpr bool zero_walls = MODE == 1 || MODE == 3;
+    typedef typename std::conditional<MODE >= 3, float, double>::type T;   // stored iterate
+};
+template <int MODE>
+static __device__ __forceinline__ typename XStore<MODE>::T *stored_iterate(const SplitJob &jb)
+{
+    if constexpr (MODE >= 3) return static_cast<float *>(jb.xs);
+    else return jb.x;
+}
+// where the epilogue writes: xs for MODE 3, x otherwise
+template <int MODE>
+static __device__ __forceinline__ typename std::conditional<MODE == 3, float, double>::type *
+xdest(const SplitJob &jb)
+{
+    if constexpr (MODE == 3) return static_cast<float *>(jb.xs);
+    else return jb.x;
+}
 
 static __device__ __forceinline__ f4 mma(b8 a, b8 b, f4 c)
 {
@@ -133,8 +162,8 @@ static __device__ __forceinline__ void q_store(b8 *__restrict__ dst, int cnt, co
 
 // x transform: C = A B, A = the field's rows (M = nz*rows, K = nx), B the
 // split swizzled nx x nx matrix.  A wave owns WM row blocks (16 rows each)
-// and all N = 16 NB columns (NB <= NBT).  MODE 0: FP32 out; MODE 1: FP64
-// x = C; MODE 2: FP64 x += C with per-block sums of C^2 and x^2 into red.
+// and all N = 16 NB columns (NB <= NBT).  MODE 0: FP32 out; MODE 1..4 as
+// in XStore (per-block sums of C^2 and x^2 into red for the updates).
 template <int NBT, int WM, typename Tin, int MODE>
 __global__ __launch_bounds__(512) void split_xgemm_kernel(SplitSet ss, int nz, int K, int N,
                                                           const b8 *__restrict__ qs,
@@ -231,9 +260,13 @@ __global__ __launch_bounds__(512) void split_xgemm_kernel(SplitSet ss, int nz, i
                 const int t = row0 + 16 * i + 4 * lg + q;
                 orow[q] = phys_row(t, trows, rskip) * N;
                 // the skipped wall row before each plane's first transform
-                // row holds zeros in the FP64 result
-                if (MODE == 1 && rskip && t % trows == 0)
-                    for (int c = li; c < N; c += 16) jb.x[orow[q] - N + c] = 0.0;
+                // row holds zeros in the result
+                if constexpr (MODE != 0 && XStore<MODE>::zero_walls)
+                    if (rskip && t % trows == 0)
+                        for (int c = li; c < N; c += 16) {
+                            xdest<MODE>(jb)[orow[q] - N + c] = 0;
+                            if (MODE == 3) jb.x[orow[q] - N + c] = 0.0;
+                        }
             }
 #pragma unroll
             for (int j = 0; j < NBT; ++j) {
@@ -241,13 +274,13 @@ __global__ __launch_bounds__(512) void split_xgemm_kernel(SplitSet ss, int nz, i
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const size_t o = orow[q] + 16 * j + li;
-                        if (MODE == 0) {
+                        if constexpr (MODE == 0) {
                             jb.out[o] = acc[i][j][q];
-                        } else if (MODE == 1) {
-                            jb.x[o] = (double)acc[i][j][q];
+                        } else if constexpr (XStore<MODE>::store) {
+                            xdest<MODE>(jb)[o] = acc[i][j][q];
                         } else {
                             const double d = (double)acc[i][j][q];
-                            const double xn = jb.x[o] + d;
+                            const double xn = (double)stored_iterate<MODE>(jb)[o] + d;
                             jb.x[o] = xn;
                             sd += d * d;
                             sx += xn * xn;
@@ -257,7 +290,7 @@ __global__ __launch_bounds__(512) void split_xgemm_kernel(SplitSet ss, int nz, i
             }
         }
     }
-    if (MODE == 2) {
+    if (MODE == 2 || MODE == 4) {
         __shared__ double sm[2][8];
         sd = wave_sum(sd);
         sx = wave_sum(sx);
@@ -385,7 +418,7 @@ __global__ __launch_bounds__(512) void split_zgemm_kernel(SplitSet ss, int M, in
 // ---------------------------------------------------------------------------
 
 // x transform, a wave owning WM row blocks and all columns of both factors.
-// MODE as for the plain kernel (0: FP32 out, forward; 1: x = C; 2: x += C).
+// MODE as for the plain kernel (0: FP32 out, forward; 1..4 as in XStore).
 // Persistent like the z kernel: block b takes row tiles b, b + G, ... over
 // the jobs still running as one pipeline of 32-deep chunks.  MODE 2 writes
 // the update sums of tile rt of job q to slot q * tiles_per_job + rt.
@@ -581,9 +614,13 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                     orow[q] = phys_row(t, r.trows, r.rskip) * N;
                     ah[q] = (double)A[orow[q] + H];   // X[H] of the output row
                     // the skipped wall row before each plane's first row
-                    // holds zeros in the FP64 result
-                    if (MODE == 1 && r.rskip && t % r.trows == 0)
-                        for (int c = li; c < N; c += 16) jb.x[orow[q] - N + c] = 0.0;
+                    // holds zeros in the result
+                    if constexpr (MODE != 0 && XStore<MODE>::zero_walls)
+                        if (r.rskip && t % r.trows == 0)
+                            for (int c = li; c < N; c += 16) {
+                                xdest<MODE>(jb)[orow[q] - N + c] = 0;
+                                if (MODE == 3) jb.x[orow[q] - N + c] = 0.0;
+                            }
                 }
                 if (!INV) {
                     double nyr[4];
@@ -603,14 +640,18 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                         }
                     }
                 } else {
+                    // destination and stored iterate held in registers: the
+                    // job record is not reloaded after each store
+                    auto *const xd = xdest<MODE>(jb);
+                    const auto *const xold = stored_iterate<MODE>(jb);
                     if (lg == 0) {   // physical point H of row li
                         const size_t rr = phys_row(r.row0 + 16 * i + li, r.trows, r.rskip) * N;
                         const double xh = fma((double)A[rr + H], sH, ny);
-                        if (MODE == 1) {
-                            jb.x[rr + H] = xh;
+                        if constexpr (XStore<MODE>::store) {
+                            xd[rr + H] = xh;
                         } else {
-                            const double xn = jb.x[rr + H] + xh;
-                            jb.x[rr + H] = xn;
+                            const double xn = (double)xold[rr + H] + xh;
+                            xd[rr + H] = xn;
                             sd += xh * xh;
                             sx += xn * xn;
                         }
@@ -623,15 +664,22 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                         constexpr int JG = HBT < 8 ? HBT : 8;
 #pragma unroll
                         for (int j0 = 0; j0 < HBT; j0 += JG) {
-                            double xo[2][JG];
-                            if (MODE == 2) {
+                            typedef typename XStore<MODE>::T Tx;   // kept in its stored type
+                            Tx xo[2][JG];
+                            if constexpr (XStore<MODE>::update) {
+                                // a position the row lacks is neither read
+                                // nor used (its store below is skipped too)
 #pragma unroll
                                 for (int jj = 0; jj < JG; ++jj) {
                                     const int ii = 16 * (j0 + jj) + li;
                                     const bool ok = j0 + jj < HB;
-                                    xo[0][jj] = ok ? jb.x[orow[q] + ii] : 0.0;
-                                    xo[1][jj] = (ok && ii != 0) ? jb.x[orow[q] + N - ii] : 0.0;
+                                    if (ok) xo[0][jj] = xold[orow[q] + ii];
+                                    if (ok && ii != 0) xo[1][jj] = xold[orow[q] + N - ii];
                                 }
+                                // all of them have landed before the first
+                                // store (else each later use would wait on
+                                // the stores issued meanwhile)
+                                wait_vm();
                             }
 #pragma unroll
                             for (int jj = 0; jj < JG; ++jj) {
@@ -642,17 +690,17 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                                 const double u = fma(ah[q], sg, (double)acc[i][0][j][q]);
                                 const double v = (double)acc[i][1][j][q];
                                 const size_t o1 = orow[q] + ii, o2 = orow[q] + N - ii;
-                                if (MODE == 1) {
-                                    jb.x[o1] = u + v;
-                                    if (ii != 0) jb.x[o2] = u - v;
+                                if constexpr (XStore<MODE>::store) {
+                                    xd[o1] = u + v;
+                                    if (ii != 0) xd[o2] = u - v;
                                 } else {
                                     const double d1 = u + v, x1 = xo[0][jj] + d1;
-                                    jb.x[o1] = x1;
+                                    xd[o1] = x1;
                                     sd += d1 * d1;
                                     sx += x1 * x1;
                                     if (ii != 0) {
                                         const double d2 = u - v, x2 = xo[1][jj] + d2;
-                                        jb.x[o2] = x2;
+                                        xd[o2] = x2;
                                         sd += d2 * d2;
                                         sx += x2 * x2;
                                     }
@@ -662,7 +710,7 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                     }
                 }
             }
-            if (MODE == 2) {
+            if (XStore<MODE>::update) {
                 sd = wave_sum(sd);
                 sx = wave_sum(sx);
                 if (lane == 0) { sm[0][wave] = sd; sm[1][wave] = sx; }
@@ -885,8 +933,9 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
     }
 }
 
-// FP32 residual r = b - A x of the FP64 iterate (7-point stencils of
-// Section 2.1).  For the pressure problem the weighted mean of b (recorded
+// FP32 residual r = b - A x of the stored iterate xs (FP64, or FP32 after
+// the first pass; either way evaluated in FP64) with the 7-point stencils of
+// Section 2.1.  For the pressure problem the weighted mean of b (recorded
 // by the first pass) is subtracted first: that constant lies in the null
 // space of every correction, and left in r its FP32 rounding would swamp the
 // shrinking residual.  The same pass sums Delta_j x per block (fixed block
@@ -896,6 +945,7 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
 // along z, keeping x at k-1, k, k+1 in registers (each x value is read from
 // HBM about once; x and y neighbours come from the same or adjacent blocks'
 // lines).  grid: (tiles per job, jobs), the same tile count for all jobs.
+template <typename Tx>
 __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, int ny, int nz,
                                                            double ihx2, double ihz2,
                                                            const double *__restrict__ dyc,
@@ -910,7 +960,7 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
     const SplitJob &jb = ss.j[job];
     const int op = jb.op, rows = jb.rows;
     const size_t plane = (size_t)rows * nx;
-    const double *__restrict__ x = jb.x;
+    const Tx *__restrict__ x = static_cast<const Tx *>(jb.xs);
     const double bm = (op == IBS_OP_POISSON) ? bmean[job] : 0.0;
     const int kz = blockIdx.x / tiles_xy, txy = blockIdx.x - kz * tiles_xy;
     const int tj = txy / tiles_x, ti = txy - tj * tiles_x;
@@ -950,14 +1000,14 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
         const double wD = (op != IBS_OP_HELMHOLTZ_V) ? D : 0.0;
         const double *__restrict__ bb = jb.b;
         float *__restrict__ rr = jb.r;
-        double xm = x[(size_t)(k0 == 0 ? nz - 1 : k0 - 1) * plane + o];
-        double xc = x[(size_t)k0 * plane + o];
+        double xm = (double)x[(size_t)(k0 == 0 ? nz - 1 : k0 - 1) * plane + o];
+        double xc = (double)x[(size_t)k0 * plane + o];
 #pragma unroll 4
         for (int k = k0; k < k1; ++k) {
             const size_t c = (size_t)k * plane + o;
-            const double xp = x[(size_t)(k + 1 == nz ? 0 : k + 1) * plane + o];
-            const double xe = x[c - i + ip], xw = x[c - i + im];
-            const double xu = wu * x[c + du], xl = wl * x[c - dl];
+            const double xp = (double)x[(size_t)(k + 1 == nz ? 0 : k + 1) * plane + o];
+            const double xe = (double)x[c - i + ip], xw = (double)x[c - i + im];
+            const double xu = wu * (double)x[c + du], xl = wl * (double)x[c - dl];
             const double bv = bb[c];
             double lap = ((xe - xc) - (xc - xw)) * ihx2 + ((xp - xc) - (xc - xm)) * ihz2;
             lap += cu * (xu - xc) - cl * (xc - xl);
@@ -1142,27 +1192,32 @@ hipError_t launch_split_xgemm(const SplitSet &ss, const Plan &p, bool inverse, b
     // each refinement pass keeps its update partials in a region of its own
     const size_t slots = (size_t)grid.x * grid.y * grid.z;
     const size_t region = 2 * slots;
-    if (mode == 2 && (size_t)pass * region > p.lay.red_count) return hipErrorInvalidValue;
-    double *red = blob_mut(p, p.lay.red) + (mode == 2 ? (size_t)(pass - 1) * region : 0);
+    const bool upd = mode == 2 || mode == 4;
+    if (mode < 0 || mode > 4) return hipErrorInvalidValue;
+    if (upd && (pass < 1 || (size_t)pass * region > p.lay.red_count)) return hipErrorInvalidValue;
+    double *red = blob_mut(p, p.lay.red) + (upd ? (size_t)(pass - 1) * region : 0);
     if (in64 && mode != 0) return hipErrorInvalidValue;
-    if (inverse != (mode != 0)) return hipErrorInvalidValue;   // forward: FP32 out; inverse: FP64 x
+    if (inverse != (mode != 0)) return hipErrorInvalidValue;   // forward: FP32 out; inverse: iterate
     if (can_fold_split(p.nx)) {
         const b8 *qs = reinterpret_cast<const b8 *>(blob_ptr(p, inverse ? p.lay.sxf_inv : p.lay.sxf_fwd));
-        if (in64) launch_xf_hb<double, 0, false>(ss, p, qs, red, skip, grid, s);
-        else if (mode == 0) launch_xf_hb<float, 0, false>(ss, p, qs, red, skip, grid, s);
-        else if (mode == 1) launch_xf_hb<float, 1, true>(ss, p, qs, red, skip, grid, s);
-        else launch_xf_hb<float, 2, true>(ss, p, qs, red, skip, grid, s);
+        switch (in64 ? -1 : mode) {
+        case -1: launch_xf_hb<double, 0, false>(ss, p, qs, red, skip, grid, s); break;
+        case 0: launch_xf_hb<float, 0, false>(ss, p, qs, red, skip, grid, s); break;
+        case 1: launch_xf_hb<float, 1, true>(ss, p, qs, red, skip, grid, s); break;
+        case 2: launch_xf_hb<float, 2, true>(ss, p, qs, red, skip, grid, s); break;
+        case 3: launch_xf_hb<float, 3, true>(ss, p, qs, red, skip, grid, s); break;
+        default: launch_xf_hb<float, 4, true>(ss, p, qs, red, skip, grid, s); break;
+        }
         return hipGetLastError();
     }
     const b8 *qs = reinterpret_cast<const b8 *>(blob_ptr(p, inverse ? p.lay.sx_inv : p.lay.sx_fwd));
-    if (in64) {
-        launch_x_nb<double, 0>(ss, p, qs, red, skip, grid, s);
-    } else if (mode == 0) {
-        launch_x_nb<float, 0>(ss, p, qs, red, skip, grid, s);
-    } else if (mode == 1) {
-        launch_x_nb<float, 1>(ss, p, qs, red, skip, grid, s);
-    } else {
-        launch_x_nb<float, 2>(ss, p, qs, red, skip, grid, s);
+    switch (in64 ? -1 : mode) {
+    case -1: launch_x_nb<double, 0>(ss, p, qs, red, skip, grid, s); break;
+    case 0: launch_x_nb<float, 0>(ss, p, qs, red, skip, grid, s); break;
+    case 1: launch_x_nb<float, 1>(ss, p, qs, red, skip, grid, s); break;
+    case 2: launch_x_nb<float, 2>(ss, p, qs, red, skip, grid, s); break;
+    case 3: launch_x_nb<float, 3>(ss, p, qs, red, skip, grid, s); break;
+    default: launch_x_nb<float, 4>(ss, p, qs, red, skip, grid, s); break;
     }
     return hipGetLastError();
 }
@@ -1240,17 +1295,20 @@ int residual_tiles(const Plan &p)
     return t;
 }
 
-hipError_t launch_residual_f32(const SplitSet &ss, const Plan &p, int pass, hipStream_t s)
+hipError_t launch_residual_f32(const SplitSet &ss, const Plan &p, int pass, bool x32, hipStream_t s)
 {
     const int *skip = pass >= 2 ? reinterpret_cast<const int *>(blob_ptr(p, p.lay.done)) : nullptr;
     int tiles_x, tiles_xy, rz, tiles;
     residual_tiling(p, tiles_x, tiles_xy, rz, tiles);
     if (tiles > XSUM_SLOTS) return hipErrorInvalidValue;
     dim3 grid(tiles, ss.n);
-    hipLaunchKernelGGL(residual_f32_kernel, grid, dim3(256), 0, s, ss, p.nx, p.ny, p.nz,
-                       1.0 / (p.hx * p.hx), 1.0 / (p.hz * p.hz), blob_ptr(p, p.lay.dyc),
-                       blob_ptr(p, p.lay.dyf), blob_ptr(p, p.lay.bmean), blob_mut(p, p.lay.xsum),
-                       skip, tiles_x, tiles_xy, rz);
+    auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, grid, dim3(256), 0, s, ss, p.nx, p.ny, p.nz, 1.0 / (p.hx * p.hx),
+                           1.0 / (p.hz * p.hz), blob_ptr(p, p.lay.dyc), blob_ptr(p, p.lay.dyf),
+                           blob_ptr(p, p.lay.bmean), blob_mut(p, p.lay.xsum), skip, tiles_x, tiles_xy, rz);
+    };
+    if (x32) go(residual_f32_kernel<float>);
+    else go(residual_f32_kernel<double>);
     return hipGetLastError();
 }
 

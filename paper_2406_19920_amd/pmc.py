@@ -37,9 +37,9 @@ CLASSES = {
     "divergence": (r"\bdivergence_kernel\b", ("k_stencil.hip",)),
     "correct": (r"\bcorrect_kernel\b", ("k_stencil.hip",)),
     "residual": (r"\bresidual_f32_kernel\b", ("k_split.hip",)),
-    "xgemm_split": (r"\bsplit_x\w*kernel<\d+, \d+, (double|float), 0(, false)?>", ("k_split.hip",)),
+    "xgemm_split": (r"\bsplit_x\w*kernel<\d+, \d+, (double|float), 0(, false)?(, \d+)?>", ("k_split.hip",)),
     "zgemm_split": (r"\bsplit_z\w*kernel<", ("k_split.hip",)),
-    "update": (r"\bsplit_x\w*kernel<\d+, \d+, float, [12](, true)?>", ("k_split.hip",)),
+    "update": (r"\bsplit_x\w*kernel<\d+, \d+, float, [12](, true)?(, \d+)?>", ("k_split.hip",)),
 }
 
 

@@ -51,8 +51,9 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
         # one workspace per slot, sized for the largest request (a plan then
         # holds only its constants; the workspace is needed only while a
-        # request runs, and a slot runs one request at a time)
-        self.work_bytes = 3 * 8 * nmax * (nmax + 1) * nmax
+        # request runs, and a slot runs one request at a time): a Helmholtz
+        # batch of 3 components on the refined path, 12 bytes per cell each
+        self.work_bytes = 3 * 12 * nmax * (nmax + 1) * nmax
         self.slot_work = [torch.empty(self.work_bytes, dtype=torch.uint8, device=self.device)
                           for _ in range(slots)]
 

@@ -206,3 +206,45 @@ def test_edge_sizes_manufactured(ibs, refined, shape):
     err = _rel(_host(x), xt)
     _say("helmholtz v err", err)
     assert err < tol
+
+
+@pytest.mark.parametrize("shape", [(64, 24, 64), (96, 20, 32)])
+def test_forced_extra_passes(ibs, shape):
+    """Passes beyond convergence forced by an unreachable tolerance: the first
+    pass keeps its iterate in FP32, the second writes x = x0 + d, later ones
+    update the FP64 x.  Every pass count stays at the oracle's solution, the
+    v wall rows stay exactly zero, and the report says NOT_CONVERGED after
+    exactly max_iter passes.  nx = 64 takes the folded transforms, nx = 96
+    the plain ones."""
+    nx, ny, nz = shape
+    _say("case forced passes", shape)
+    g = oracle.Grid(nx, ny, nz, beta=2.0)
+    c = 0.125 * min(float(g.dyc.min()), 1.0 / nx) ** 2
+    xp = synth.manufactured(nx, ny, nz, seed=51)
+    xp = xp - oracle.weighted_mean(g, OP_P, xp)
+    rp, _, _ = oracle.residual_ld(g, OP_P, 0.0, xp, np.zeros_like(xp))
+    xs = [synth.manufactured(nx, ny, nz, seed=52 + q, rows=ny + 1 if q == 1 else None)
+          for q in range(3)]
+    xs[1][:, 0, :] = 0
+    xs[1][:, ny, :] = 0
+    rs = [oracle.residual_ld(g, op, c, xt, np.zeros_like(xt))[0]
+          for op, xt in zip((OP_U, OP_V, OP_W), xs)]
+    for passes in (2, 3, 4):
+        S = ibs.Solver(nx, ny, nz, beta=2.0, precision=ibs.IBS_REFINED_BF16X3,
+                       max_iter=passes, tol=1e-300)
+        err = _rel(_host(S.poisson(_dev(-rp))), xp)
+        inf = S.read_info(0)
+        _say("passes", passes, "poisson err", err, "status", inf.status, "iters", inf.iters)
+        assert err < TOL
+        assert inf.status == ibs.IBS_ERR_NOT_CONVERGED and inf.iters == passes
+        outs = S.helmholtz([0, 1, 2], [c] * 3, [_dev(-r) for r in rs])
+        for q, (x, xt) in enumerate(zip(outs, xs)):
+            xh = _host(x)
+            err = _rel(xh, xt)
+            inf = S.read_info(q)
+            _say("passes", passes, "comp", q, "err", err, "iters", inf.iters)
+            assert err < TOL
+            assert inf.iters == passes
+            if q == 1:
+                assert not xh[:, 0, :].any() and not xh[:, ny, :].any()
+        S.close()

@@ -61,6 +61,13 @@ def test_plan_bytes_and_errors():
         assert wb == 64 ** 3 * 8 and cb >= 4 * 64 * 64 * 8
         _, wh = ibs.solver_plan_bytes(p, ibs.IBS_OP_HELMHOLTZ_U, 3)
         assert wh == 3 * 64 * 65 * 64 * 8
+        # the refined path holds three FP32 fields per component
+        pr = _plan(64, 64, 64, precision=ibs.IBS_REFINED_BF16X3)
+        try:
+            assert ibs.solver_plan_bytes(pr, ibs.IBS_OP_POISSON)[1] == 64 ** 3 * 12
+            assert ibs.solver_plan_bytes(pr, ibs.IBS_OP_HELMHOLTZ_U, 2)[1] == 2 * 64 * 65 * 64 * 12
+        finally:
+            ibs.solver_plan_destroy(pr)
         with pytest.raises(ibs.IbsError) as e:
             ibs.solver_plan_bytes(p, 9)
         assert e.value.status == ibs.IBS_ERR_INVALID_ARG

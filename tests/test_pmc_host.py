@@ -40,9 +40,33 @@ def test_traffic_reduction(tmp_path, monkeypatch):
     assert abs(z["write_bytes_per_launch"] - 200.0 * 1024) < 1e-6
     assert z["dispatches"] == [2, 2]
     assert "update" in d["kernels"] and "xgemm_split" not in d["kernels"]
+    assert d["kernels"]["update"]["dispatches"] == [1, 1]
     assert pmc.traffic_for("zgemm_split", str(out)) == z["bytes_per_launch"]
     # a changed kernel source invalidates the stored figure
     d["kernels"]["zgemm_split"]["source_hash"] = "0" * 16
     json.dump(d, open(out, "w"))
     assert pmc.traffic_for("zgemm_split", str(out)) is None
     assert pmc.traffic_for("zgemm_split", str(tmp_path / "missing.json")) is None
+
+
+def test_class_patterns():
+    """Kernel names as rocprofv3 prints them map onto one class each."""
+    import re
+    names = {
+        "ibs::split_xfold_kernel<8, 1, double, 0, false, 1>": "xgemm_split",
+        "ibs::split_xfold_kernel<8, 1, float, 0, false, 2>": "xgemm_split",
+        "ibs::split_xgemm_kernel<16, 2, double, 0>": "xgemm_split",
+        "ibs::split_xfold_kernel<8, 1, float, 1, true, 1>": "update",
+        "ibs::split_xfold_kernel<8, 1, float, 2, true, 2>": "update",
+        "ibs::split_xgemm_kernel<16, 2, float, 2>": "update",
+        "ibs::split_zfold_kernel<8, 1, true, 1>": "zgemm_split",
+        "ibs::split_zgemm_kernel<16, 2>": "zgemm_split",
+        "ibs::xfold_f64_kernel<1, 4, true, false>": "xgemm_f64",
+        "ibs::zfold_f64_kernel<4, 1, false, true>": "zgemm_f64",
+        "ibs::tridiag_kernel<float, float, 8, 9>": "tridiag_f32",
+        "ibs::tridiag_kernel<double, double, 8, 9>": "tridiag_f64",
+        "ibs::residual_f32_kernel(ibs::SplitSet, int)": "residual",
+    }
+    for name, cls in names.items():
+        hits = [c for c, (pat, _) in pmc.CLASSES.items() if re.search(pat, "void " + name)]
+        assert hits == [cls], (name, hits)

@@ -136,3 +136,19 @@ def test_request_generator_recipe():
     assert ns.min() >= 32 and ns.max() <= 384 and np.all(ns % 32 == 0)
     assert 0.45 < np.mean([r["kind"] == "poisson" for r in reqs]) < 0.55
     assert 0.45 < np.mean([r["refined"] for r in reqs]) < 0.55
+
+
+def test_geometry_pool_reuses_plans():
+    reqs = synth.serving_requests(rate=1000, count=400, seed=4, nmin=32, nmax=128, geometries=5)
+    grids = {(r["n"], r["beta"]) for r in reqs}
+    assert len(grids) <= 5
+    assert all(r["n"] % 32 == 0 and 32 <= r["n"] <= 128 and 0.0 <= r["beta"] <= 3.0 for r in reqs)
+    # the pool depends on the seed alone, not on the rate
+    other = synth.serving_requests(rate=50, count=400, seed=4, nmin=32, nmax=128, geometries=5)
+    assert {(r["n"], r["beta"]) for r in other} == grids
+    srv, ex, _ = _server()
+    res = srv.run(reqs)
+    d = res.summary()
+    assert d["completed"] == 400
+    # one miss per plan key at most per concurrent use; most requests hit
+    assert d["plan_hits"] > 300 and d["plan_hits"] + d["plan_misses"] == 400
