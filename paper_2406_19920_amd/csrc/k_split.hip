@@ -512,13 +512,29 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
     load_data(0);
     wait_vm();
     b8 ae[WM][3], ao[WM][3];   // split E and O of the current chunk
+    // X[H] of the tile's output rows (and, inverse, of rows li), loaded at
+    // the start of the tile's last step so that the epilogue does not wait
+    Tin ahp[WM][4], xhp[WM];
     for (int step = 0; step < nsteps; ++step) {
         const int chunk = step / FS, f = step % FS;   // f: factor of this step (FS = 2)
         const int kc = chunk % KC;
+        const bool last = kc == KC - 1 && f == FS - 1;   // the tile completes this step
         __syncthreads();
         const b8 *cur = sq + (step & 1) * QCNT;
         const bool more = step + 1 < nsteps;
         if (more) q_dma(qs + (size_t)((step + 1) % (KC * FS)) * qcnt, sq + ((step + 1) & 1) * QCNT, qcnt);
+        if (last) {
+            const TileRef r = tile_ref(chunk / KC);
+            const Tin *A = static_cast<const Tin *>(r.jb->in);
+#pragma unroll
+            for (int i = 0; i < WM; ++i) {
+                if (i >= r.nrb) continue;   // wave-uniform
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    ahp[i][q] = A[phys_row(r.row0 + 16 * i + 4 * lg + q, r.trows, r.rskip) * N + H];
+                if (INV) xhp[i] = A[phys_row(r.row0 + 16 * i + li, r.trows, r.rskip) * N + H];
+            }
+        }
         const int k0 = 32 * kc + 8 * lg;
         if (f == 0) {
 #pragma unroll
@@ -595,10 +611,12 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                 }
             }
         }
-        if (kc == KC - 1 && f == FS - 1) {   // the tile is complete: store it
+        // next step's factors and data, and this tile's X[H] values, have
+        // landed (the epilogue's stores below are left in flight)
+        if (more || last) wait_vm();
+        if (last) {   // the tile is complete: store it
             const TileRef r = tile_ref(chunk / KC);
             const SplitJob &jb = *r.jb;
-            const Tin *A = static_cast<const Tin *>(jb.in);
             double sd = 0.0, sx = 0.0;
 #pragma unroll
             for (int i = 0; i < WM; ++i) {
@@ -612,7 +630,7 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                 for (int q = 0; q < 4; ++q) {
                     const int t = r.row0 + 16 * i + 4 * lg + q;
                     orow[q] = phys_row(t, r.trows, r.rskip) * N;
-                    ah[q] = (double)A[orow[q] + H];   // X[H] of the output row
+                    ah[q] = (double)ahp[i][q];   // X[H] of the output row
                     // the skipped wall row before each plane's first row
                     // holds zeros in the result
                     if constexpr (MODE != 0 && XStore<MODE>::zero_walls)
@@ -646,7 +664,7 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                     const auto *const xold = stored_iterate<MODE>(jb);
                     if (lg == 0) {   // physical point H of row li
                         const size_t rr = phys_row(r.row0 + 16 * i + li, r.trows, r.rskip) * N;
-                        const double xh = fma((double)A[rr + H], sH, ny);
+                        const double xh = fma((double)xhp[i], sH, ny);
                         if constexpr (XStore<MODE>::store) {
                             xd[rr + H] = xh;
                         } else {
@@ -725,7 +743,6 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
             }
             clear();
         }
-        if (more) wait_vm();   // next chunk's factors and data have landed
     }
 }
 
@@ -810,13 +827,22 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
     load_data(0);
     wait_vm();
     b8 be[WN][3], bo[WN][3];   // split E and O of the current chunk
+    float bhp[WN];   // plane H of the tile's columns, loaded at its last step
     for (int step = 0; step < nsteps; ++step) {
         const int chunk = step / FS, f = step % FS;   // f: factor of this step (FS = 2)
         const int kc = chunk % KC;
+        const bool last = kc == KC - 1 && f == FS - 1;   // the tile completes this step
         __syncthreads();
         const b8 *cur = sq + (step & 1) * QCNT;
         const bool more = step + 1 < nsteps;
         if (more) q_dma(qs + (size_t)((step + 1) % (KC * FS)) * qcnt, sq + ((step + 1) & 1) * QCNT, qcnt);
+        if (last) {
+            const TileRef r = tile_ref(chunk / KC);
+            const float *B = static_cast<const float *>(r.jb->in) + r.rskip * nx;
+#pragma unroll
+            for (int j = 0; j < WN; ++j)
+                if (j < r.ncb) bhp[j] = B[(size_t)H * r.ldp + r.col0 + 16 * j + li];   // wave-uniform
+        }
         const int k0 = 32 * kc + 8 * lg;
         if (f == 0) {
 #pragma unroll
@@ -893,9 +919,11 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
                 }
             }
         }
-        if (kc == KC - 1 && f == FS - 1) {   // the tile is complete: store it
+        // next step's factors and data, and this tile's plane-H values, have
+        // landed (the epilogue's stores below are left in flight)
+        if (more || last) wait_vm();
+        if (last) {   // the tile is complete: store it
             const TileRef r = tile_ref(chunk / KC);
-            const float *B = static_cast<const float *>(r.jb->in) + r.rskip * nx;
             float *C = r.jb->out + r.rskip * nx;
 #pragma unroll
             for (int j = 0; j < WN; ++j) {
@@ -904,7 +932,7 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
                 double ny = nyq[j];
                 ny += __shfl_xor(ny, 16, 64);
                 ny += __shfl_xor(ny, 32, 64);   // every lane of column li holds its sum
-                const double bh = (double)B[(size_t)H * r.ldp + cc];
+                const double bh = (double)bhp[j];
                 if (INV && lg == 0) C[(size_t)H * r.ldp + cc] = (float)fma(bh, sH, ny);
 #pragma unroll
                 for (int i = 0; i < HBT; ++i) {
@@ -929,7 +957,6 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
             }
             clear();
         }
-        if (more) wait_vm();   // next chunk's factors and data have landed
     }
 }
 
