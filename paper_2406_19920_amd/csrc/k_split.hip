@@ -110,6 +110,16 @@ __device__ __forceinline__ void load8<double>(const double *p, float *v)
     }
 }
 
+// The same from an element-aligned (not vector-aligned) address.
+template <typename Tin>
+static __device__ __forceinline__ void load8u(const Tin *p, float *v)
+{
+    Tin x[8];
+    __builtin_memcpy(x, p, sizeof(x));
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (float)x[e];
+}
+
 static __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -492,10 +502,18 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                 const Tin *arow = A + phys_row(r.row0 + 16 * i + li, r.trows, r.rskip) * N;
                 load8<Tin>(arow + k0, pc[i]);
                 if (!INV) {
+                    // mirrored points N - kk (kk = k0 .. k0+7) as one 8-wide
+                    // run, reversed in registers; kk = 0 pairs with point H
+                    // instead, so lanes with k0 = 0 read the run N-8 .. N-1
+                    const bool z0 = k0 == 0;
+                    float mv[8];
+                    load8u<Tin>(arow + (z0 ? N - 8 : N - k0 - 7), mv);
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const int kk = k0 + e;
-                        mc[i][e] = (float)arow[kk == 0 ? H : N - kk];
+                    for (int e = 0; e < 8; ++e)
+                        mc[i][e] = z0 ? (e == 0 ? 0.f : mv[8 - e]) : mv[7 - e];
+                    if (chunk % KC == 0) {   // wave-uniform: X[H] once per tile
+                        const float xh = (float)arow[H];
+                        if (z0) mc[i][0] = xh;
                     }
                 } else {
                     load8<Tin>(arow + H + k0, mc[i]);
