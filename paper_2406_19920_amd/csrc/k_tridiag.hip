@@ -109,9 +109,18 @@ __global__ __launch_bounds__(16 * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
     constexpr int TA = 16;                 // pencils per tile
     constexpr int NT = TA * P;             // threads
     constexpr int NR = P * M;              // padded rows
+    // LDS row of system row j: for even M each chunk of M rows is followed
+    // by one unused row, so the P lanes of a pencil, which walk rows M
+    // apart, hit distinct banks
+    constexpr int MS = M + (M % 2 == 0 ? 1 : 0);
+    constexpr int NRS = P * MS;            // LDS rows
+    auto lr = [](int j) {
+        if constexpr (MS == M) return j;
+        else return (j / M) * MS + j % M;
+    };
     constexpr int LDR = TA + 1;            // LDS row stride (elements)
-    __shared__ R sx[NR * LDR];
-    __shared__ R slo[NR], sdi[NR], sup[NR], sw[NR];
+    __shared__ R sx[NRS * LDR];
+    __shared__ R slo[NRS], sdi[NRS], sup[NRS], sw[NRS];
 
     const int tid = threadIdx.x;
     const int nx = tp.nx;
@@ -155,7 +164,8 @@ __global__ __launch_bounds__(16 * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
         plx = tp.lam_x[a0 + p];
         plz = tp.lam_z[c];
         const auto rs = plane_rsrc(job, c, live);
-        const uint32_t voff = (uint32_t)(a0 + lcol) * sizeof(T) + (uint32_t)lrow * row_bytes;
+        const uint32_t sys0 = skip_first_row(js.j[job].kind);   // first row of the system
+        const uint32_t voff = (uint32_t)(a0 + lcol) * sizeof(T) + (lrow + sys0) * row_bytes;
 #pragma unroll
         for (int r = 0; r < M; ++r) pf[r] = buf_load<T>(rs, voff + r * P * row_bytes, 0);
     };
@@ -169,7 +179,8 @@ __global__ __launch_bounds__(16 * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
         int job, c, a0;
         decode(tile, job, c, a0);
         const FieldJob &jb = js.j[job];
-        const int n = jb.rows, kind = jb.kind;
+        // the v systems leave out the first wall row (kept at zero below)
+        const int kind = jb.kind, sys0 = skip_first_row(kind), n = jb.rows - sys0;
         const bool live = !((skipmask >> job) & 1);   // block-uniform
         __syncthreads();  // the previous tile's LDS is no longer read
         if (live && job != cur_job) {
@@ -178,13 +189,13 @@ __global__ __launch_bounds__(16 * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
             const R cj = (R)jb.c;
             for (int j = tid; j < NR; j += NT) {
                 const bool real = j < n;
-                const R lo = real ? (R)tp.lo[kind][j] : R(0);
-                const R di = real ? (R)tp.di[kind][j] : R(0);
-                const R up = real ? (R)tp.up[kind][j] : R(0);
-                slo[j] = pois ? lo : -cj * lo;
-                sdi[j] = pois ? di : R(1) - cj * di;
-                sup[j] = pois ? up : -cj * up;
-                sw[j] = (real && pois) ? (R)tp.wy[j] : R(0);
+                const R lo = real ? (R)tp.lo[kind][j + sys0] : R(0);
+                const R di = real ? (R)tp.di[kind][j + sys0] : R(0);
+                const R up = real ? (R)tp.up[kind][j + sys0] : R(0);
+                slo[lr(j)] = pois ? lo : -cj * lo;
+                sdi[lr(j)] = pois ? di : R(1) - cj * di;
+                sup[lr(j)] = pois ? up : -cj * up;
+                sw[lr(j)] = (real && pois) ? (R)tp.wy[j] : R(0);
             }
             cur_job = job;
         }
@@ -192,7 +203,7 @@ __global__ __launch_bounds__(16 * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
 #pragma unroll
         for (int r = 0; r < M; ++r) {
             const int j = lrow + P * r;
-            sx[j * LDR + lcol] = (walls && (j == 0 || j == n - 1)) ? R(0) : (R)pf[r];
+            sx[lr(j) * LDR + lcol] = (walls && j == n - 1) ? R(0) : (R)pf[r];
         }
         const R sh = (R)(plx + plz);
         __syncthreads();
@@ -204,7 +215,7 @@ __global__ __launch_bounds__(16 * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
 
             R r[M];
 #pragma unroll
-            for (int t = 0; t < M; ++t) r[t] = sx[(s + t) * LDR + p];
+            for (int t = 0; t < M; ++t) r[t] = sx[(k * MS + t) * LDR + p];
 
             R removed = 0.0, rms = 0.0;
             if (pinned) {
@@ -212,9 +223,9 @@ __global__ __launch_bounds__(16 * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
                 R swr = 0.0, sww = 0.0, swrr = 0.0;
 #pragma unroll
                 for (int t = 0; t < M; ++t) {
-                    swr += sw[s + t] * r[t];
-                    sww += sw[s + t];
-                    swrr += sw[s + t] * r[t] * r[t];
+                    swr += sw[k * MS + t] * r[t];
+                    sww += sw[k * MS + t];
+                    swrr += sw[k * MS + t] * r[t] * r[t];
                 }
 #pragma unroll
                 for (int d = 1; d < P; d <<= 1) {
@@ -233,9 +244,9 @@ __global__ __launch_bounds__(16 * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
 
             auto coef = [&](int j, R &A, R &B, R &C) {
                 const bool real = j < n && !(pinned && j == 0);
-                A = real ? slo[j] : 0.0;
-                B = real ? sdi[j] + sadd : 1.0;
-                C = real ? sup[j] : 0.0;
+                A = real ? slo[lr(j)] : 0.0;
+                B = real ? sdi[lr(j)] + sadd : 1.0;
+                C = real ? sup[lr(j)] : 0.0;
             };
 
             // down-sweep: rows s+1 .. s+M-1 in the form al x_s + x_j + ga x_{j+1} = rho
@@ -313,8 +324,8 @@ __global__ __launch_bounds__(16 * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
                 R swx = 0.0, sww = 0.0;
 #pragma unroll
                 for (int t = 0; t < M; ++t) {
-                    swx += sw[s + t] * r[t];
-                    sww += sw[s + t];
+                    swx += sw[k * MS + t] * r[t];
+                    sww += sw[k * MS + t];
                 }
 #pragma unroll
                 for (int d = 1; d < P; d <<= 1) {
@@ -337,7 +348,7 @@ __global__ __launch_bounds__(16 * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
                     if (s + t < n) r[t] -= mx;
             }
 #pragma unroll
-            for (int t = 0; t < M; ++t) sx[(s + t) * LDR + p] = r[t];
+            for (int t = 0; t < M; ++t) sx[(k * MS + t) * LDR + p] = r[t];
 
             if (pinned && k == 0 && tp.record_mean) tp.bmean[job] = removed * tp.inv_sqrt_nxnz;
             if (a0 == 0 && c == 0 && tid == 0 && jb.info) {
@@ -353,10 +364,13 @@ __global__ __launch_bounds__(16 * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
         }  // live
         __syncthreads();
         const auto rs = plane_rsrc(job, c, live);
-        const uint32_t voff = (uint32_t)(a0 + lcol) * sizeof(T) + (uint32_t)lrow * row_bytes;
+        const uint32_t voff = (uint32_t)(a0 + lcol) * sizeof(T) + (lrow + sys0) * row_bytes;
 #pragma unroll
         for (int r2 = 0; r2 < M; ++r2)
-            buf_store<T>((T)sx[(lrow + P * r2) * LDR + lcol], rs, voff + r2 * P * row_bytes, 0);
+            buf_store<T>((T)sx[lr(lrow + P * r2) * LDR + lcol], rs, voff + r2 * P * row_bytes, 0);
+        // the left-out wall row holds zeros (an offset past the range drops
+        // the store of every other lane)
+        buf_store<T>(T(0), rs, (sys0 && lrow == 0) ? (uint32_t)(a0 + lcol) * sizeof(T) : 0xFFFFFFF0u, 0);
     };
     // A block takes tiles in adjacent pairs (2b, 2b+1: neighbouring x-modes
     // of one z-plane), so the two halves of each 128-byte line of a 4-byte
@@ -404,6 +418,7 @@ static hipError_t launch_by_rows(const JobSet &js, const TriParams &tp, int n, h
     if (n <= 112) return launch_pm<T, R, 16, 7>(js, tp, s);
     if (n <= 144) return launch_pm<T, R, 16, 9>(js, tp, s);
     if (n <= 224) return launch_pm<T, R, 32, 7>(js, tp, s);
+    if (n <= 256) return launch_pm<T, R, 32, 8>(js, tp, s);
     if (n <= 288) return launch_pm<T, R, 32, 9>(js, tp, s);
     if (n <= 352) return launch_pm<T, R, 32, 11>(js, tp, s);
     if (n <= 416) return launch_pm<T, R, 32, 13>(js, tp, s);
@@ -463,7 +478,10 @@ static hipError_t launch_tridiag(const JobSet &js, const Plan &p, bool poisson, 
     if (pass >= 2) tp.skip = reinterpret_cast<const int *>(blob_ptr(p, p.lay.done));
     tp.inv_sqrt_nxnz = 1.0 / std::sqrt((double)p.nx * (double)p.nz);
     int n = 0;
-    for (int q = 0; q < js.n; ++q) n = js.j[q].rows > n ? js.j[q].rows : n;
+    for (int q = 0; q < js.n; ++q) {
+        const int rows = js.j[q].rows - skip_first_row(js.j[q].kind);   // system rows
+        n = rows > n ? rows : n;
+    }
     // FP32 arithmetic where its rounding is far below what refinement
     // removes anyway: FP32 data (refined path), Helmholtz, and pencil
     // condition numbers bounded by FP32_KAPPA.
