@@ -489,38 +489,32 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
         }
     };
     // forward: p = X[k], m = X[mirror k]; inverse: p = cos inputs, m = sin
-    // inputs.  The next chunk is loaded into the same registers once the
-    // current one has been split, so its loads run under the products.
-    float pc[WM][8], mc[WM][8];
+    // inputs.  The next chunk is loaded, raw, into the same registers once
+    // the current one has been split; nothing reads them before the step's
+    // closing wait, so the loads run under the products.
+    Tin rp[WM][8], rm[WM][8], rxh[WM];
     auto load_data = [&](int chunk) {   // chunk = tile * KC + kc
         const TileRef r = tile_ref(chunk / KC);
         const Tin *A = static_cast<const Tin *>(r.jb->in);
         const int k0 = 32 * (chunk % KC) + 8 * lg;
 #pragma unroll
         for (int i = 0; i < WM; ++i) {
-            if (i < r.nrb) {
+            if (i < r.nrb) {   // wave-uniform
                 const Tin *arow = A + phys_row(r.row0 + 16 * i + li, r.trows, r.rskip) * N;
-                load8<Tin>(arow + k0, pc[i]);
+                __builtin_memcpy(rp[i], arow + k0, sizeof(rp[i]));
                 if (!INV) {
                     // mirrored points N - kk (kk = k0 .. k0+7) as one 8-wide
-                    // run, reversed in registers; kk = 0 pairs with point H
+                    // run, reversed at the split; kk = 0 pairs with point H
                     // instead, so lanes with k0 = 0 read the run N-8 .. N-1
-                    const bool z0 = k0 == 0;
-                    float mv[8];
-                    load8u<Tin>(arow + (z0 ? N - 8 : N - k0 - 7), mv);
-#pragma unroll
-                    for (int e = 0; e < 8; ++e)
-                        mc[i][e] = z0 ? (e == 0 ? 0.f : mv[8 - e]) : mv[7 - e];
-                    if (chunk % KC == 0) {   // wave-uniform: X[H] once per tile
-                        const float xh = (float)arow[H];
-                        if (z0) mc[i][0] = xh;
-                    }
+                    __builtin_memcpy(rm[i], arow + (k0 == 0 ? N - 8 : N - k0 - 7), sizeof(rm[i]));
+                    if (chunk % KC == 0) rxh[i] = arow[H];   // wave-uniform: once per tile
                 } else {
-                    load8<Tin>(arow + H + k0, mc[i]);
+                    __builtin_memcpy(rm[i], arow + H + k0, sizeof(rm[i]));
                 }
             } else {
 #pragma unroll
-                for (int e = 0; e < 8; ++e) { pc[i][e] = 0.f; mc[i][e] = 0.f; }
+                for (int e = 0; e < 8; ++e) { rp[i][e] = 0; rm[i][e] = 0; }
+                rxh[i] = 0;
             }
         }
     };
@@ -540,7 +534,6 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
         __syncthreads();
         const b8 *cur = sq + (step & 1) * QCNT;
         const bool more = step + 1 < nsteps;
-        if (more) q_dma(qs + (size_t)((step + 1) % (KC * FS)) * qcnt, sq + ((step + 1) & 1) * QCNT, qcnt);
         if (last) {
             const TileRef r = tile_ref(chunk / KC);
             const Tin *A = static_cast<const Tin *>(r.jb->in);
@@ -557,20 +550,27 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
         if (f == 0) {
 #pragma unroll
             for (int i = 0; i < WM; ++i) {
-                float ev[8], ov[8];
+                float ev[8], ov[8], pc[8], mc[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    pc[e] = (float)rp[i][e];
+                    if (INV) mc[e] = (float)rm[i][e];
+                    else if (k0 == 0) mc[e] = (float)(e == 0 ? rxh[i] : rm[i][8 - e]);
+                    else mc[e] = (float)rm[i][7 - e];
+                }
                 if (!INV) {
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
                         const bool self = k0 + e == 0;
-                        ev[e] = self ? pc[i][e] : pc[i][e] + mc[i][e];
-                        ov[e] = self ? mc[i][e] : pc[i][e] - mc[i][e];
+                        ev[e] = self ? pc[e] : pc[e] + mc[e];
+                        ov[e] = self ? mc[e] : pc[e] - mc[e];
                         nyq[i] += (e & 1) ? -(double)ev[e] : (double)ev[e];
                     }
                 } else {
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
-                        ev[e] = pc[i][e];
-                        ov[e] = mc[i][e];
+                        ev[e] = pc[e];
+                        ov[e] = mc[e];
                         const double w = (k0 + e == 0) ? s0 : s1;
                         nyq[i] += (e & 1) ? -w * (double)ev[e] : w * (double)ev[e];
                     }
@@ -629,6 +629,11 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                 }
             }
         }
+        // the next step's factors go to the other LDS buffer only now, after
+        // this step's last LDS read: issued earlier, the compiler would make
+        // those reads wait for the copy (and, the memory counter being in
+        // order, for the data loads issued before it)
+        if (more) q_dma(qs + (size_t)((step + 1) % (KC * FS)) * qcnt, sq + ((step + 1) & 1) * QCNT, qcnt);
         // next step's factors and data, and this tile's X[H] values, have
         // landed (the epilogue's stores below are left in flight)
         if (more || last) wait_vm();
