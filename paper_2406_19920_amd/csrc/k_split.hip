@@ -534,6 +534,12 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
         __syncthreads();
         const b8 *cur = sq + (step & 1) * QCNT;
         const bool more = step + 1 < nsteps;
+        // the next step's factors go to the other LDS buffer.  The update
+        // modes issue the copy only after this step's last LDS read: there
+        // the compiler would otherwise make those reads wait for it (and,
+        // the memory counter being in order, for the data loads before it)
+        constexpr bool EARLY_COPY = !XStore<MODE>::update;
+        if (EARLY_COPY && more) q_dma(qs + (size_t)((step + 1) % (KC * FS)) * qcnt, sq + ((step + 1) & 1) * QCNT, qcnt);
         if (last) {
             const TileRef r = tile_ref(chunk / KC);
             const Tin *A = static_cast<const Tin *>(r.jb->in);
@@ -629,11 +635,7 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                 }
             }
         }
-        // the next step's factors go to the other LDS buffer only now, after
-        // this step's last LDS read: issued earlier, the compiler would make
-        // those reads wait for the copy (and, the memory counter being in
-        // order, for the data loads issued before it)
-        if (more) q_dma(qs + (size_t)((step + 1) % (KC * FS)) * qcnt, sq + ((step + 1) & 1) * QCNT, qcnt);
+        if (!EARLY_COPY && more) q_dma(qs + (size_t)((step + 1) % (KC * FS)) * qcnt, sq + ((step + 1) & 1) * QCNT, qcnt);
         // next step's factors and data, and this tile's X[H] values, have
         // landed (the epilogue's stores below are left in flight)
         if (more || last) wait_vm();
