@@ -248,3 +248,31 @@ def test_forced_extra_passes(ibs, shape):
             if q == 1:
                 assert not xh[:, 0, :].any() and not xh[:, ny, :].any()
         S.close()
+
+
+def test_refined_256_planes_manufactured(ibs):
+    """nx = nz = 256, the transform tiles of the 256^3 step (few y rows so
+    the case stays small): Poisson and a u, v, w Helmholtz batch, with
+    manufactured solutions."""
+    nx, ny, nz = 256, 12, 256
+    _say("case refined 256 planes")
+    g = oracle.Grid(nx, ny, nz, beta=2.0)
+    c = 0.125 * min(float(g.dyc.min()), 1.0 / nx) ** 2
+    S = ibs.Solver(nx, ny, nz, beta=2.0, precision=ibs.IBS_REFINED_BF16X3)
+    xp = synth.manufactured(nx, ny, nz, seed=61)
+    xp = xp - oracle.weighted_mean(g, OP_P, xp)
+    rp, _, _ = oracle.residual_ld(g, OP_P, 0.0, xp, np.zeros_like(xp))
+    err = _rel(_host(S.poisson(_dev(-rp))), xp)
+    _say("poisson err", err, "passes", S.read_info(0).iters)
+    assert err < TOL and S.read_info(0).status == 0
+    xs = [synth.manufactured(nx, ny, nz, seed=62 + q, rows=ny + 1 if q == 1 else None)
+          for q in range(3)]
+    xs[1][:, 0, :] = 0
+    xs[1][:, ny, :] = 0
+    rs = [oracle.residual_ld(g, op, c, xt, np.zeros_like(xt))[0]
+          for op, xt in zip((OP_U, OP_V, OP_W), xs)]
+    outs = S.helmholtz([0, 1, 2], [c] * 3, [_dev(-r) for r in rs])
+    for q, (x, xt) in enumerate(zip(outs, xs)):
+        err = _rel(_host(x), xt)
+        _say("comp", q, "err", err)
+        assert err < TOL and S.read_info(q).status == 0
