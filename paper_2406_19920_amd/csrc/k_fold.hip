@@ -80,25 +80,27 @@ __global__ __launch_bounds__(256) void xfold_f64_kernel(JobSet js, int nz, int N
     // raw operands of one 16-deep chunk: the row data (forward: X[k] and
     // X[mirror k]; inverse: cos and sin inputs) and both factors' fragments.
     // The next chunk's are loaded while the current chunk is multiplied.
+    // forward: ma holds the mirrored run X[N-k0-3 .. N-k0] as loaded (one
+    // 4-wide load), reversed where it is used; kk = 0 pairs with X[H]
+    // instead, so lanes with k0 = 0 load the run N-4 .. N-1 and xh = X[H]
     d4 pa[WM], ma[WM], fc[WN], fs[WN];
+    double xh[WM];
     auto load = [&](int kc) {
         const int k0 = 16 * kc + 4 * lg;
 #pragma unroll
         for (int i = 0; i < WM; ++i) {
-            if (i < nrb) {
+            if (i < nrb) {   // wave-uniform
                 pa[i] = *reinterpret_cast<const d4 *>(arow[i] + k0);
                 if (!INV) {
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const int kk = k0 + t;
-                        ma[i][t] = arow[i][kk == 0 ? H : N - kk];
-                    }
+                    __builtin_memcpy(&ma[i], arow[i] + (k0 == 0 ? N - 4 : N - k0 - 3), sizeof(d4));
+                    if (kc == 0) xh[i] = arow[i][H];   // wave-uniform
                 } else {
                     ma[i] = *reinterpret_cast<const d4 *>(arow[i] + H + k0);
                 }
             } else {
                 pa[i] = (d4){0, 0, 0, 0};
                 ma[i] = (d4){0, 0, 0, 0};
+                xh[i] = 0.0;
             }
         }
 #pragma unroll
@@ -124,8 +126,9 @@ __global__ __launch_bounds__(256) void xfold_f64_kernel(JobSet js, int nz, int N
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const bool self = k0 + t == 0;
-                    xc[i][t] = self ? pa[i][t] : pa[i][t] + ma[i][t];
-                    xs[i][t] = self ? ma[i][t] : pa[i][t] - ma[i][t];
+                    const double m = k0 == 0 ? (t == 0 ? xh[i] : ma[i][4 - t]) : ma[i][3 - t];
+                    xc[i][t] = self ? pa[i][t] : pa[i][t] + m;
+                    xs[i][t] = self ? m : pa[i][t] - m;
                 }
                 // Nyquist output: sum of (-1)^i E[i]
                 nyq[i] += (xc[i][0] - xc[i][1]) + (xc[i][2] - xc[i][3]);
