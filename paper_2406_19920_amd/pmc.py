@@ -39,7 +39,7 @@ CLASSES = {
     "residual": (r"\bresidual_f32_kernel\b", ("k_split.hip",)),
     "xgemm_split": (r"\bsplit_x\w*kernel<\d+, \d+, (double|float), 0(, false)?(, \d+)?>", ("k_split.hip",)),
     "zgemm_split": (r"\bsplit_z\w*kernel<", ("k_split.hip",)),
-    "update": (r"\bsplit_x\w*kernel<\d+, \d+, float, [12](, true)?(, \d+)?>", ("k_split.hip",)),
+    "update": (r"\bsplit_x\w*kernel<\d+, \d+, float, [1-4](, true)?(, \d+)?>", ("k_split.hip",)),
 }
 
 

@@ -58,6 +58,9 @@ def test_class_patterns():
         "ibs::split_xgemm_kernel<16, 2, double, 0>": "xgemm_split",
         "ibs::split_xfold_kernel<8, 1, float, 1, true, 1>": "update",
         "ibs::split_xfold_kernel<8, 1, float, 2, true, 2>": "update",
+        "ibs::split_xfold_kernel<8, 1, float, 3, true, 1>": "update",
+        "ibs::split_xfold_kernel<16, 1, float, 4, true, 2>": "update",
+        "ibs::split_xgemm_kernel<16, 2, float, 4>": "update",
         "ibs::split_xgemm_kernel<16, 2, float, 2>": "update",
         "ibs::split_zfold_kernel<8, 1, true, 1>": "zgemm_split",
         "ibs::split_zgemm_kernel<16, 2>": "zgemm_split",
