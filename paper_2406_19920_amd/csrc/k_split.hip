@@ -110,16 +110,6 @@ __device__ __forceinline__ void load8<double>(const double *p, float *v)
     }
 }
 
-// The same from an element-aligned (not vector-aligned) address.
-template <typename Tin>
-static __device__ __forceinline__ void load8u(const Tin *p, float *v)
-{
-    Tin x[8];
-    __builtin_memcpy(x, p, sizeof(x));
-#pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = (float)x[e];
-}
-
 static __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
