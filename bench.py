@@ -27,6 +27,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp64_tflops": 78.6, "hbm_gbs": 8000.0}
+# peak rate (TFLOP/s) each kernel class's algorithmic flops are priced at in
+# the whole-step roofline: FP64 matrix cores, bf16 matrix cores (dense), or
+# the vector units (FP64 78.6, FP32 157.3)
+CLASS_PEAK = {"xgemm_f64": 78.6, "zgemm_f64": 78.6, "xgemm_split": 2500.0, "zgemm_split": 2500.0,
+              "update": 2500.0, "tridiag_f64": 78.6, "tridiag_f32": 157.3, "divergence": 78.6,
+              "correct": 78.6, "residual": 78.6}
 # HBM bytes per launch measured with rocprofv3 counters on the 256^3 step
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_256cube.json")
 
@@ -50,8 +56,18 @@ def h_min(ny, beta, ly=1.0):
     return float(np.diff(yf).min())
 
 
-def cpu_baseline(n_sample, beta, seed):
-    """The oracle (C/OpenMP CG) on the same step at a reduced grid."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_step(n_sample, beta, seed):
+    """Seconds for one full step of the oracle (C/OpenMP CG) at n_sample^3."""
     import oracle
     from oracle import OP_P, OP_U, OP_V, OP_W
     g = oracle.Grid(n_sample, n_sample, n_sample, beta=beta)
@@ -65,14 +81,29 @@ def cpu_baseline(n_sample, beta, seed):
     phi, _ = oracle.solve(g, OP_P, b)
     gu, gv, gw = oracle.gradient(g, phi)
     us -= gu; vs -= gv; ws -= gw
-    dt = time.perf_counter() - t0
-    cells = n_sample ** 3
-    return {"value": 4 * cells / dt / 1e6, "unit": "Mcell-solves/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(n_sample, beta, seed, n_single=64):
+    """The oracle on the same step at a reduced grid, on all host threads,
+    and on one thread at a smaller grid."""
+    import oracle
+    dt = cpu_step(n_sample, beta, seed)
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        dt1 = cpu_step(n_single, beta, seed)
+    finally:
+        oracle.set_num_threads(threads)
+    return {"value": 4 * n_sample ** 3 / dt / 1e6, "unit": "Mcell-solves/s",
+            "cores": threads, "kind": "oracle",
             "sample": f"one full step (3 Helmholtz + divergence + Poisson + correction) of the "
                       f"same workload at {n_sample}^3 (beta={beta}, same c rule), "
                       f"{dt:.1f} s; the CG iteration count grows with the grid, so this "
-                      f"overstates the oracle's rate at 256^3"}
+                      f"overstates the oracle's rate at 256^3",
+            "single_thread": {"value": 4 * n_single ** 3 / dt1 / 1e6, "unit": "Mcell-solves/s",
+                              "sample": f"the same step at {n_single}^3 on one thread, {dt1:.1f} s"},
+            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
 
 
 def main():
@@ -203,6 +234,12 @@ def main():
         roof["algorithmic_bytes_per_launch"] = d["bytes"] / d["launches"]
         roof["kernel"] = dom_name
         roof["avg_launch_ms"] = avg_ms
+        # whole step: sum over classes of max(flops / peak, bytes / HBM peak),
+        # over the measured kernel time of a step
+        roof_ms = sum(max(r["flops"] / (CLASS_PEAK.get(k, PEAK["fp64_tflops"]) * 1e12),
+                          r["bytes"] / (PEAK["hbm_gbs"] * 1e9)) * 1e3 for k, r in kern.items()) / steps
+        kern_ms = sum(r["ms"] for r in kern.values()) / steps
+        roof["step_roofline"] = {"roofline_ms": roof_ms, "kernel_ms": kern_ms, "frac": roof_ms / kern_ms}
         breakdown = {k: {"ms_per_step": r["ms"] / steps,
                          "launches_per_step": r["launches"] / steps,
                          "tflops": r["flops"] / (r["ms"] * 1e-3) / 1e12 if r["ms"] else None,
