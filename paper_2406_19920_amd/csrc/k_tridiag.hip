@@ -102,11 +102,11 @@ struct TriParams {
 // T: storage type of the field (double, or float on the refined path);
 // R: arithmetic type (double; float only for well-conditioned Helmholtz
 // systems of the refined path, whose refinement absorbs FP32 rounding).
-template <typename T, typename R, int P, int M>
-__global__ __launch_bounds__(16 * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tridiag_kernel(JobSet js, TriParams tp, int ntx,
+template <typename T, typename R, int P, int M, int TA>
+__global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tridiag_kernel(JobSet js, TriParams tp, int ntx,
                                                          int ntiles)
 {
-    constexpr int TA = 16;                 // pencils per tile
+    // TA: pencils per tile
     constexpr int NT = TA * P;             // threads
     constexpr int NR = P * M;              // padded rows
     // LDS row of system row j: for even M each chunk of M rows is followed
@@ -387,23 +387,26 @@ __global__ __launch_bounds__(16 * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
 template <typename T, typename R, int P, int M>
 static hipError_t launch_pm(const JobSet &js, const TriParams &tp, hipStream_t s)
 {
-    // persistent blocks walk the tiles (job, z-mode, 16 x-modes) in order;
+    // pencils per tile: 16, or 8 with FP64 arithmetic, whose registers
+    // allow fewer waves per SIMD (blocks of 4 waves then still fill them)
+    constexpr int TA = sizeof(R) == 8 && P == 32 ? 8 : 16;
+    // persistent blocks walk the tiles (job, z-mode, TA x-modes) in order;
     // as many blocks as are resident at once, so that every block's tiles
     // run back to back
     static const int resident = [] {
         int per_cu = 0, dev = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tridiag_kernel<T, R, P, M>, 16 * P, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tridiag_kernel<T, R, P, M, TA>, TA * P, 0) !=
                 hipSuccess ||
             hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             return 1024;
         return per_cu * cus > 0 ? per_cu * cus : 1024;
     }();
-    const int ntx = tp.nx / 16;
+    const int ntx = tp.nx / TA;
     const int ntiles = ntx * tp.nz * js.n;
     const int pairs = (ntiles + 1) / 2;
     const int grid = pairs < resident ? pairs : resident;
-    hipLaunchKernelGGL((tridiag_kernel<T, R, P, M>), dim3(grid), dim3(16 * P), 0, s, js, tp, ntx,
+    hipLaunchKernelGGL((tridiag_kernel<T, R, P, M, TA>), dim3(grid), dim3(TA * P), 0, s, js, tp, ntx,
                        ntiles);
     return hipGetLastError();
 }
