@@ -517,6 +517,7 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
     // X[H] of the tile's output rows (and, inverse, of rows li), loaded at
     // the start of the tile's last step so that the epilogue does not wait
     Tin ahp[WM][4], xhp[WM];
+    typename XStore<MODE>::T xhold[WM];   // update modes: old iterate at point H of rows li
     for (int step = 0; step < nsteps; ++step) {
         const int chunk = step / FS, f = step % FS;   // f: factor of this step (FS = 2)
         const int kc = chunk % KC;
@@ -540,6 +541,8 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                 for (int q = 0; q < 4; ++q)
                     ahp[i][q] = A[phys_row(r.row0 + 16 * i + 4 * lg + q, r.trows, r.rskip) * N + H];
                 if (INV) xhp[i] = A[phys_row(r.row0 + 16 * i + li, r.trows, r.rskip) * N + H];
+                if constexpr (XStore<MODE>::update)
+                    xhold[i] = stored_iterate<MODE>(*r.jb)[phys_row(r.row0 + 16 * i + li, r.trows, r.rskip) * N + H];
             }
         }
         const int k0 = 32 * kc + 8 * lg;
@@ -683,59 +686,66 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                         if constexpr (XStore<MODE>::store) {
                             xd[rr + H] = xh;
                         } else {
-                            const double xn = (double)xold[rr + H] + xh;
+                            const double xn = (double)xhold[i] + xh;
                             xd[rr + H] = xn;
                             sd += xh * xh;
                             sx += xn * xn;
                         }
                     }
+                    // the rows' old values first, eight column blocks and (an
+                    // FP32 iterate) two rows at a time (all loads in flight
+                    // together; every position is distinct), then the updates
+                    typedef typename XStore<MODE>::T Tx;   // kept in its stored type
+                    constexpr int JG = HBT < 8 ? HBT : 8;
+                    constexpr int QG = (XStore<MODE>::update && sizeof(Tx) == 4 && HBT <= 8) ? 2 : 1;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        // the row's old values first, eight column blocks at a
-                        // time (all loads in flight together; every position
-                        // is distinct), then the updates
-                        constexpr int JG = HBT < 8 ? HBT : 8;
+                    for (int q0 = 0; q0 < 4; q0 += QG) {
 #pragma unroll
                         for (int j0 = 0; j0 < HBT; j0 += JG) {
-                            typedef typename XStore<MODE>::T Tx;   // kept in its stored type
-                            Tx xo[2][JG];
+                            Tx xo[QG][2][JG];
                             if constexpr (XStore<MODE>::update) {
                                 // a position the row lacks is neither read
                                 // nor used (its store below is skipped too)
 #pragma unroll
-                                for (int jj = 0; jj < JG; ++jj) {
-                                    const int ii = 16 * (j0 + jj) + li;
-                                    const bool ok = j0 + jj < HB;
-                                    if (ok) xo[0][jj] = xold[orow[q] + ii];
-                                    if (ok && ii != 0) xo[1][jj] = xold[orow[q] + N - ii];
-                                }
+                                for (int qq = 0; qq < QG; ++qq)
+#pragma unroll
+                                    for (int jj = 0; jj < JG; ++jj) {
+                                        const int ii = 16 * (j0 + jj) + li;
+                                        const bool ok = j0 + jj < HB;
+                                        if (ok) xo[qq][0][jj] = xold[orow[q0 + qq] + ii];
+                                        if (ok && ii != 0) xo[qq][1][jj] = xold[orow[q0 + qq] + N - ii];
+                                    }
                                 // all of them have landed before the first
                                 // store (else each later use would wait on
                                 // the stores issued meanwhile)
                                 wait_vm();
                             }
 #pragma unroll
-                            for (int jj = 0; jj < JG; ++jj) {
-                                const int j = j0 + jj;
-                                if (j >= HB) continue;
-                                const int ii = 16 * j + li;
-                                const double sg = (ii & 1) ? -s0 : s0;   // Q[ii][H]
-                                const double u = fma(ah[q], sg, (double)acc[i][0][j][q]);
-                                const double v = (double)acc[i][1][j][q];
-                                const size_t o1 = orow[q] + ii, o2 = orow[q] + N - ii;
-                                if constexpr (XStore<MODE>::store) {
-                                    xd[o1] = u + v;
-                                    if (ii != 0) xd[o2] = u - v;
-                                } else {
-                                    const double d1 = u + v, x1 = xo[0][jj] + d1;
-                                    xd[o1] = x1;
-                                    sd += d1 * d1;
-                                    sx += x1 * x1;
-                                    if (ii != 0) {
-                                        const double d2 = u - v, x2 = xo[1][jj] + d2;
-                                        xd[o2] = x2;
-                                        sd += d2 * d2;
-                                        sx += x2 * x2;
+                            for (int qq = 0; qq < QG; ++qq) {
+                                const int q = q0 + qq;
+#pragma unroll
+                                for (int jj = 0; jj < JG; ++jj) {
+                                    const int j = j0 + jj;
+                                    if (j >= HB) continue;
+                                    const int ii = 16 * j + li;
+                                    const double sg = (ii & 1) ? -s0 : s0;   // Q[ii][H]
+                                    const double u = fma(ah[q], sg, (double)acc[i][0][j][q]);
+                                    const double v = (double)acc[i][1][j][q];
+                                    const size_t o1 = orow[q] + ii, o2 = orow[q] + N - ii;
+                                    if constexpr (XStore<MODE>::store) {
+                                        xd[o1] = u + v;
+                                        if (ii != 0) xd[o2] = u - v;
+                                    } else {
+                                        const double d1 = u + v, x1 = xo[qq][0][jj] + d1;
+                                        xd[o1] = x1;
+                                        sd += d1 * d1;
+                                        sx += x1 * x1;
+                                        if (ii != 0) {
+                                            const double d2 = u - v, x2 = xo[qq][1][jj] + d2;
+                                            xd[o2] = x2;
+                                            sd += d2 * d2;
+                                            sx += x2 * x2;
+                                        }
                                     }
                                 }
                             }
