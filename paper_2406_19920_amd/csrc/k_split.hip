@@ -693,11 +693,12 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                         }
                     }
                     // the rows' old values first, eight column blocks and (an
-                    // FP32 iterate) two rows at a time (all loads in flight
-                    // together; every position is distinct), then the updates
+                    // FP32 iterate) all four rows at a time (all loads in
+                    // flight together; every position is distinct), then the
+                    // updates
                     typedef typename XStore<MODE>::T Tx;   // kept in its stored type
                     constexpr int JG = HBT < 8 ? HBT : 8;
-                    constexpr int QG = (XStore<MODE>::update && sizeof(Tx) == 4 && HBT <= 8) ? 2 : 1;
+                    constexpr int QG = (XStore<MODE>::update && sizeof(Tx) == 4 && HBT <= 8) ? 4 : 1;
 #pragma unroll
                     for (int q0 = 0; q0 < 4; q0 += QG) {
 #pragma unroll
