@@ -398,6 +398,7 @@ def bench_c3(args):
     res = {}
     for path, prec in (("refined", ibs.IBS_REFINED_BF16X3), ("fp64", ibs.IBS_FP64)):
         S = ibs.Solver(nx, ny, nz, beta=beta, precision=prec)
+        tiles = S.autotune() if prec == ibs.IBS_FP64 else None   # set-up, untimed
         xu, xv, xw = S.empty(1), S.empty(2), S.empty(3)
         b, phi = S.empty(0), S.empty(0)
 
@@ -415,8 +416,23 @@ def bench_c3(args):
             step()
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        status = [S.read_info(q).status for q in range(3)]
+        passes = [S.read_info(q).iters for q in range(3)]
+        # live per-kernel time per step (HIP events on the launch stream)
+        ibs.ibs_profile(S.plan, True)
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        kern = {}
+        for kid, name in enumerate(ibs.PROFILE_KERNELS):
+            r = ibs.ibs_profile_read(S.plan, kid)
+            if r["launches"]:
+                kern[name] = {"ms_per_step": r["ms"] / args.steps,
+                              "gbs": r["bytes"] / (r["ms"] * 1e-3) / 1e9 if r["ms"] else None,
+                              "tflops": r["flops"] / (r["ms"] * 1e-3) / 1e12 if r["ms"] else None}
+        ibs.ibs_profile(S.plan, False)
         res[path] = {"value": 4 * nx * ny * nz / (ms * 1e-3) / 1e6, "ms_per_step": ms,
-                     "status": [S.read_info(q).status for q in range(3)]}
+                     "status": status, "helmholtz_passes": passes, "tiles": tiles, "kernels": kern}
         S.close()
     out = {"metric": "Mcell-solves/s at 512x384x384 (refined to 1e-10; FP64 alongside)",
            "value": res["refined"]["value"], "unit": "Mcell-solves/s", "n_gpus": 1,
