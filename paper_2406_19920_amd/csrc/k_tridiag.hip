@@ -387,9 +387,11 @@ __global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
 template <typename T, typename R, int P, int M>
 static hipError_t launch_pm(const JobSet &js, const TriParams &tp, hipStream_t s)
 {
-    // pencils per tile: 16, or 8 with FP64 arithmetic, whose registers
-    // allow fewer waves per SIMD (blocks of 4 waves then still fill them)
-    constexpr int TA = sizeof(R) == 8 && P == 32 ? 8 : 16;
+    // pencils per tile: 16, or 8 for FP32 data with FP64 arithmetic, whose
+    // registers allow fewer waves per SIMD (blocks of 4 waves then still
+    // fill them; with FP64 data the 16-wide tiles measured as fast with
+    // less traffic)
+    constexpr int TA = sizeof(R) == 8 && sizeof(T) == 4 && P == 32 ? 8 : 16;
     // persistent blocks walk the tiles (job, z-mode, TA x-modes) in order;
     // as many blocks as are resident at once, so that every block's tiles
     // run back to back
