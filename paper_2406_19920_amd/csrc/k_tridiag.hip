@@ -13,16 +13,18 @@
 // the weighted mean is removed, which fixes the null mode at zero mean.
 //
 // Layout and parallel scheme (an MI355X design, not the paper's
-// thread-per-pencil Thomas sweep): a tile is 16 consecutive x-modes of one
-// z-plane, all rows.  Persistent workgroups walk the tiles; each tile is
-// read row by row (128-byte coalesced segments) into registers while the
-// previous tile is being solved, then staged through LDS.  Each pencil is split into P (16 or 32)
-// chunks of M consecutive rows, one lane per chunk.  Every lane eliminates its chunk
-// with two local sweeps (down and up), leaving one equation per lane that
-// couples the last unknowns of neighbouring chunks; that reduced tridiagonal
-// system of P equations is solved by parallel cyclic reduction with
-// wavefront shuffles; the lanes then back-substitute their interiors.  Rows
-// beyond the system size are identity rows.  All arithmetic is FP64.
+// thread-per-pencil Thomas sweep): a tile is 16 (or 8) consecutive x-modes
+// of one z-plane, all rows.  Persistent workgroups walk the tiles in
+// adjacent pairs; each tile is read row by row into registers while the
+// previous tile is being solved, then staged through LDS.  Each pencil is
+// split into P (16 or 32) chunks of M consecutive rows, one lane per chunk.
+// Every lane eliminates its chunk with two local sweeps (down and up),
+// leaving one equation per lane that couples the last unknowns of
+// neighbouring chunks; that reduced tridiagonal system of P equations is
+// solved by parallel cyclic reduction with wavefront shuffles; the lanes
+// then back-substitute their interiors.  Rows beyond the system size are
+// identity rows.  The arithmetic is FP64, or FP32 for Helmholtz launches
+// whose pencil condition numbers are provably small (refined path).
 #include "ibs_internal.h"
 
 #include <algorithm>
