@@ -518,8 +518,13 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
     // the start of the tile's last step so that the epilogue does not wait
     Tin ahp[WM][4], xhp[WM];
     typename XStore<MODE>::T xhold[WM];   // update modes: old iterate at point H of rows li
-    for (int step = 0; step < nsteps; ++step) {
-        const int chunk = step / FS, f = step % FS;   // f: factor of this step (FS = 2)
+    // one chunk per iteration; its FS steps unrolled, so that the factor
+    // of a step is known at compile time and the data loads of a chunk go
+    // straight into the registers the next chunk reads
+    for (int step0 = 0; step0 < nsteps; step0 += FS) {
+#pragma unroll
+        for (int f = 0; f < FS; ++f) {   // f: factor of this step (FS = 2)
+        const int step = step0 + f, chunk = step / FS;
         const int kc = chunk % KC;
         const bool last = kc == KC - 1 && f == FS - 1;   // the tile completes this step
         __syncthreads();
@@ -769,6 +774,7 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
             }
             clear();
         }
+        }
     }
 }
 
@@ -854,14 +860,25 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
     wait_vm();
     b8 be[WN][3], bo[WN][3];   // split E and O of the current chunk
     float bhp[WN];   // plane H of the tile's columns, loaded at its last step
-    for (int step = 0; step < nsteps; ++step) {
-        const int chunk = step / FS, f = step % FS;   // f: factor of this step (FS = 2)
+    // one chunk per iteration; its FS steps unrolled, so that the factor
+    // of a step is known at compile time and the data loads of a chunk go
+    // straight into the registers the next chunk reads
+    for (int step0 = 0; step0 < nsteps; step0 += FS) {
+#pragma unroll
+        for (int f = 0; f < FS; ++f) {   // f: factor of this step (FS = 2)
+        const int step = step0 + f, chunk = step / FS;
         const int kc = chunk % KC;
         const bool last = kc == KC - 1 && f == FS - 1;   // the tile completes this step
         __syncthreads();
         const b8 *cur = sq + (step & 1) * QCNT;
         const bool more = step + 1 < nsteps;
-        if (more) q_dma(qs + (size_t)((step + 1) % (KC * FS)) * qcnt, sq + ((step + 1) & 1) * QCNT, qcnt);
+        // the next step's factors go to the other LDS buffer: at the step
+        // start with both factors per step; with one factor per step the
+        // compiler would make this step's LDS reads wait for that copy (and,
+        // the memory counter being in order, for the data loads), so there it
+        // is issued after the products
+        constexpr bool EARLY_COPY = FS == 1;
+        if (EARLY_COPY && more) q_dma(qs + (size_t)((step + 1) % (KC * FS)) * qcnt, sq + ((step + 1) & 1) * QCNT, qcnt);
         if (last) {
             const TileRef r = tile_ref(chunk / KC);
             const float *B = static_cast<const float *>(r.jb->in) + r.rskip * nx;
@@ -945,6 +962,7 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
                 }
             }
         }
+        if (!EARLY_COPY && more) q_dma(qs + (size_t)((step + 1) % (KC * FS)) * qcnt, sq + ((step + 1) & 1) * QCNT, qcnt);
         // next step's factors and data, and this tile's plane-H values, have
         // landed (the epilogue's stores below are left in flight)
         if (more || last) wait_vm();
@@ -982,6 +1000,7 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
                 }
             }
             clear();
+        }
         }
     }
 }
