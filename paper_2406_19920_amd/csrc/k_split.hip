@@ -872,12 +872,9 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
         __syncthreads();
         const b8 *cur = sq + (step & 1) * QCNT;
         const bool more = step + 1 < nsteps;
-        // the next step's factors go to the other LDS buffer: at the step
-        // start with both factors per step; with one factor per step the
-        // compiler would make this step's LDS reads wait for that copy (and,
-        // the memory counter being in order, for the data loads), so there it
-        // is issued after the products
-        constexpr bool EARLY_COPY = FS == 1;
+        // the next step's factors go to the other LDS buffer, at the step
+        // start (the copy runs under the products)
+        constexpr bool EARLY_COPY = true;
         if (EARLY_COPY && more) q_dma(qs + (size_t)((step + 1) % (KC * FS)) * qcnt, sq + ((step + 1) & 1) * QCNT, qcnt);
         if (last) {
             const TileRef r = tile_ref(chunk / KC);
