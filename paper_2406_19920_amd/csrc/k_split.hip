@@ -140,6 +140,10 @@ static __device__ __forceinline__ void q_dma(const b8 *__restrict__ src, b8 *dst
 }
 static __device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0); }
 
+// The refinement updates write their partial sums (sum of d^2, sum of x^2)
+// per wave: slot (block slot * UPD_WAVES + wave), no LDS reduction.
+constexpr int UPD_WAVES = 8;
+
 // Copy `cnt` 16-byte fragments (global, contiguous) into registers / LDS.
 template <int PER>
 static __device__ __forceinline__ void q_load(const b8 *__restrict__ src, int cnt, b8 (&r)[PER])
@@ -291,17 +295,12 @@ __global__ __launch_bounds__(512) void split_xgemm_kernel(SplitSet ss, int nz, i
         }
     }
     if (MODE == 2 || MODE == 4) {
-        __shared__ double sm[2][8];
         sd = wave_sum(sd);
         sx = wave_sum(sx);
-        if (lane == 0) { sm[0][wave] = sd; sm[1][wave] = sx; }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double a = 0.0, b = 0.0;
-            for (int w = 0; w < 8; ++w) { a += sm[0][w]; b += sm[1][w]; }
-            const size_t slot = (size_t)blockIdx.z * gridDim.x + blockIdx.x;
-            red[2 * slot] = a;
-            red[2 * slot + 1] = b;
+        if (lane == 0) {
+            const size_t slot = ((size_t)blockIdx.z * gridDim.x + blockIdx.x) * UPD_WAVES + wave;
+            red[2 * slot] = sd;
+            red[2 * slot + 1] = sx;
         }
     }
 }
@@ -434,7 +433,6 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
     constexpr int QCNT = (FS == 1 ? 2 : 1) * HBT * 3 * 64;
     static_assert(2 * QCNT * 16 <= 144 * 1024, "double-buffered factor chunk must fit LDS");
     __shared__ b8 sq[2 * QCNT];
-    __shared__ double sm[2][8];
     // jobs not yet converged (block-uniform), packed 8 bits each so that no
     // private array is indexed at run time
     int live = 0, nlive = 0;
@@ -530,12 +528,12 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
         __syncthreads();
         const b8 *cur = sq + (step & 1) * QCNT;
         const bool more = step + 1 < nsteps;
-        // the next step's factors go to the other LDS buffer.  The update
-        // modes issue the copy only after this step's last LDS read: there
-        // the compiler would otherwise make those reads wait for it (and,
-        // the memory counter being in order, for the data loads before it)
-        constexpr bool EARLY_COPY = !XStore<MODE>::update;
-        if (EARLY_COPY && more) q_dma(qs + (size_t)((step + 1) % (KC * FS)) * qcnt, sq + ((step + 1) & 1) * QCNT, qcnt);
+        // the next step's factors go to the other LDS buffer, at the step
+        // start (the copy runs under the products).  No other LDS object
+        // or barrier may appear in the loop: with one, the compiler made the
+        // products' LDS reads wait for this copy (and, the memory counter
+        // being in order, for the data loads after it)
+        if (more) q_dma(qs + (size_t)((step + 1) % (KC * FS)) * qcnt, sq + ((step + 1) & 1) * QCNT, qcnt);
         if (last) {
             const TileRef r = tile_ref(chunk / KC);
             const Tin *A = static_cast<const Tin *>(r.jb->in);
@@ -633,7 +631,6 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                 }
             }
         }
-        if (!EARLY_COPY && more) q_dma(qs + (size_t)((step + 1) % (KC * FS)) * qcnt, sq + ((step + 1) & 1) * QCNT, qcnt);
         // next step's factors and data, and this tile's X[H] values, have
         // landed (the epilogue's stores below are left in flight)
         if (more || last) wait_vm();
@@ -762,14 +759,10 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
             if (XStore<MODE>::update) {
                 sd = wave_sum(sd);
                 sx = wave_sum(sx);
-                if (lane == 0) { sm[0][wave] = sd; sm[1][wave] = sx; }
-                __syncthreads();
-                if (threadIdx.x == 0) {
-                    double a = 0.0, b = 0.0;
-                    for (int w = 0; w < 8; ++w) { a += sm[0][w]; b += sm[1][w]; }
-                    const size_t slot = (size_t)r.job * tiles_per_job + r.rt;
-                    red[2 * slot] = a;
-                    red[2 * slot + 1] = b;
+                if (lane == 0) {
+                    const size_t slot = ((size_t)r.job * tiles_per_job + r.rt) * UPD_WAVES + wave;
+                    red[2 * slot] = sd;
+                    red[2 * slot + 1] = sx;
                 }
             }
             clear();
@@ -874,8 +867,7 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
         const bool more = step + 1 < nsteps;
         // the next step's factors go to the other LDS buffer, at the step
         // start (the copy runs under the products)
-        constexpr bool EARLY_COPY = true;
-        if (EARLY_COPY && more) q_dma(qs + (size_t)((step + 1) % (KC * FS)) * qcnt, sq + ((step + 1) & 1) * QCNT, qcnt);
+        if (more) q_dma(qs + (size_t)((step + 1) % (KC * FS)) * qcnt, sq + ((step + 1) & 1) * QCNT, qcnt);
         if (last) {
             const TileRef r = tile_ref(chunk / KC);
             const float *B = static_cast<const float *>(r.jb->in) + r.rskip * nx;
@@ -959,7 +951,6 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
                 }
             }
         }
-        if (!EARLY_COPY && more) q_dma(qs + (size_t)((step + 1) % (KC * FS)) * qcnt, sq + ((step + 1) & 1) * QCNT, qcnt);
         // next step's factors and data, and this tile's plane-H values, have
         // landed (the epilogue's stores below are left in flight)
         if (more || last) wait_vm();
@@ -1259,7 +1250,7 @@ hipError_t launch_split_xgemm(const SplitSet &ss, const Plan &p, bool inverse, b
     dim3 grid;
     xgemm_grid(ss, p, grid);
     // each refinement pass keeps its update partials in a region of its own
-    const size_t slots = (size_t)grid.x * grid.y * grid.z;
+    const size_t slots = (size_t)grid.x * grid.y * grid.z * UPD_WAVES;
     const size_t region = 2 * slots;
     const bool upd = mode == 2 || mode == 4;
     if (mode < 0 || mode > 4) return hipErrorInvalidValue;
@@ -1390,15 +1381,15 @@ static size_t update_slots(const SplitSet &ss, const Plan &p)
 
 int max_refine_passes(const SplitSet &ss, const Plan &p)
 {
-    return (int)(p.lay.red_count / (2 * update_slots(ss, p))) + 1;
+    return (int)(p.lay.red_count / (2 * update_slots(ss, p) * UPD_WAVES)) + 1;
 }
 
 hipError_t launch_refine_check(const SplitSet &ss, const Plan &p, int pass, hipStream_t s)
 {
     dim3 grid;
     xgemm_grid(ss, p, grid);
-    const int per_job = (int)(grid.x * grid.y);
-    const size_t region = 2 * (size_t)grid.x * grid.y * grid.z;
+    const int per_job = (int)(grid.x * grid.y) * UPD_WAVES;
+    const size_t region = 2 * (size_t)grid.x * grid.y * grid.z * UPD_WAVES;
     const double *red = blob_ptr(p, p.lay.red);
     const double *last = red + (size_t)(pass - 1) * region;
     const double *prev = pass >= 2 ? red + (size_t)(pass - 2) * region : nullptr;

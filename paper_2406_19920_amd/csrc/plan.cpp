@@ -334,7 +334,7 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     L.bmean = take(sizeof(double) * 4);
     L.xsum = take(sizeof(double) * 4 * XSUM_SLOTS);
     L.done = take(sizeof(int) * 4);
-    L.red_count = 131072;
+    L.red_count = 524288;   // update partials: per wave, per tile, per refinement pass
     L.red = take(sizeof(double) * L.red_count);
     L.total = o;
     p->blob.assign(L.total, 0);
