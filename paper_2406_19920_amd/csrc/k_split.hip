@@ -1001,10 +1001,13 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
 // shrinking residual.  The same pass sums Delta_j x per block (fixed block
 // layout and order), so the next correction can also remove the weighted
 // mean that x has picked up from the FP32 transforms.
-// A block owns 4 rows x 64 columns of rz consecutive z planes and marches
-// along z, keeping x at k-1, k, k+1 in registers (each x value is read from
-// HBM about once; x and y neighbours come from the same or adjacent blocks'
-// lines).  grid: (tiles per job, jobs), the same tile count for all jobs.
+// A block owns RB whole rows (RB = 256 / (nx/4): a thread takes 4
+// consecutive points of a row, a row's threads its whole width, so the x
+// neighbours, periodic ones included, are in the row's own lines) of rz
+// consecutive z planes and marches along z, keeping x at k-1, k, k+1 in
+// registers (each x value is read from HBM about once; y neighbours come
+// from the same or adjacent blocks' rows).  grid: (tiles per job, jobs),
+// the same tile count for all jobs.
 template <typename Tx>
 __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, int ny, int nz,
                                                            double ihx2, double ihz2,
@@ -1012,9 +1015,12 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
                                                            const double *__restrict__ dyf,
                                                            const double *__restrict__ bmean,
                                                            double *__restrict__ xsum,
-                                                           const int *__restrict__ skip, int tiles_x,
-                                                           int tiles_xy, int rz)
+                                                           const int *__restrict__ skip, int rb_rows,
+                                                           int tiles_y, int rz)
 {
+    typedef Tx tx4 __attribute__((ext_vector_type(4)));
+    typedef double dv4_ __attribute__((ext_vector_type(4)));
+    typedef float fv4 __attribute__((ext_vector_type(4)));
     const int job = blockIdx.y;
     if (skip && skip[job]) return;
     const SplitJob &jb = ss.j[job];
@@ -1022,15 +1028,16 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
     const size_t plane = (size_t)rows * nx;
     const Tx *__restrict__ x = static_cast<const Tx *>(jb.xs);
     const double bm = (op == IBS_OP_POISSON) ? bmean[job] : 0.0;
-    const int kz = blockIdx.x / tiles_xy, txy = blockIdx.x - kz * tiles_xy;
-    const int tj = txy / tiles_x, ti = txy - tj * tiles_x;
+    const int kz = blockIdx.x / tiles_y, ty = blockIdx.x - kz * tiles_y;
     const int k0 = kz * rz, k1 = min(nz, k0 + rz);
-    const int j = tj * 4 + (threadIdx.x >> 6), i = ti * 64 + (threadIdx.x & 63);
+    const int tr = nx >> 2;                       // threads per row
+    const int t = threadIdx.x % tr, rb = threadIdx.x / tr;
+    const int j = ty * rb_rows + rb, i0 = 4 * t;
     double wx = 0.0;
-    if (j < rows && i < nx) {
+    if (rb < rb_rows && j < rows) {
         const bool wall = op == IBS_OP_HELMHOLTZ_V && (j == 0 || j == ny);
-        const int ip = (i + 1 == nx) ? 0 : i + 1, im = (i == 0) ? nx - 1 : i - 1;
-        const size_t o = (size_t)j * nx + i;
+        const int iw = (i0 == 0) ? nx - 1 : i0 - 1, ie = (i0 + 4 == nx) ? 0 : i0 + 4;
+        const size_t o = (size_t)j * nx;          // row start within a plane
         // y part in difference form, cu (x_up - x) - cl (x - x_lo); a missing
         // neighbour is the boundary ghost g x (g = 1 Neumann, -1 mirror, 0 wall)
         double D = 0.0, cu = 0.0, cl = 0.0, gu = 0.0, gl = 0.0;
@@ -1051,8 +1058,8 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
             rl = j - 1 >= 1;
         }
         // branch-free body (every load unconditional and in range, a missing
-        // neighbour reads the point itself), so unrolled iterations' loads
-        // can all be in flight together
+        // neighbour reads the row itself), so unrolled iterations' loads can
+        // all be in flight together
         const int du = ru ? nx : 0, dl = rl ? nx : 0;
         const double wu = ru ? 1.0 : gu, wl = rl ? 1.0 : gl;
         const bool pois = op == IBS_OP_POISSON;
@@ -1060,21 +1067,30 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
         const double wD = (op != IBS_OP_HELMHOLTZ_V) ? D : 0.0;
         const double *__restrict__ bb = jb.b;
         float *__restrict__ rr = jb.r;
-        double xm = (double)x[(size_t)(k0 == 0 ? nz - 1 : k0 - 1) * plane + o];
-        double xc = (double)x[(size_t)k0 * plane + o];
-#pragma unroll 4
+        auto ld4 = [&](size_t at) { return *reinterpret_cast<const tx4 *>(x + at); };
+        tx4 xm = ld4((size_t)(k0 == 0 ? nz - 1 : k0 - 1) * plane + o + i0);
+        tx4 xc = ld4((size_t)k0 * plane + o + i0);
+#pragma unroll 2
         for (int k = k0; k < k1; ++k) {
-            const size_t c = (size_t)k * plane + o;
-            const double xp = (double)x[(size_t)(k + 1 == nz ? 0 : k + 1) * plane + o];
-            const double xe = (double)x[c - i + ip], xw = (double)x[c - i + im];
-            const double xu = wu * (double)x[c + du], xl = wl * (double)x[c - dl];
-            const double bv = bb[c];
-            double lap = ((xe - xc) - (xc - xw)) * ihx2 + ((xp - xc) - (xc - xm)) * ihz2;
-            lap += cu * (xu - xc) - cl * (xc - xl);
-            const double ax = pois ? lap : xc - cj * lap;
-            const float rv = (float)((bv - bm) - ax);
-            rr[c] = wall ? 0.f : rv;
-            wx += wD * xc;
+            const size_t c = (size_t)k * plane + o;   // this row of plane k
+            const tx4 xp = ld4((size_t)(k + 1 == nz ? 0 : k + 1) * plane + o + i0);
+            const tx4 xu = ld4(c + du + i0), xl = ld4(c - dl + i0);
+            const double xwe = (double)x[c + iw], xee = (double)x[c + ie];
+            const dv4_ bv = *reinterpret_cast<const dv4_ *>(bb + c + i0);
+            fv4 rv;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const double xcc = (double)xc[e];
+                const double xw = e == 0 ? xwe : (double)xc[e - 1];
+                const double xe = e == 3 ? xee : (double)xc[e + 1];
+                double lap = ((xe - xcc) - (xcc - xw)) * ihx2 +
+                             (((double)xp[e] - xcc) - (xcc - (double)xm[e])) * ihz2;
+                lap += cu * (wu * (double)xu[e] - xcc) - cl * (xcc - wl * (double)xl[e]);
+                const double ax = pois ? lap : xcc - cj * lap;
+                rv[e] = wall ? 0.f : (float)((bv[e] - bm) - ax);
+                wx += wD * xcc;
+            }
+            *reinterpret_cast<fv4 *>(rr + c + i0) = rv;
             xm = xc;
             xc = xp;
         }
@@ -1337,35 +1353,36 @@ hipError_t launch_split_zgemm(const SplitSet &ss, const Plan &p, bool inverse, i
     return hipGetLastError();
 }
 
-// Residual tiling: 4 x 64 (y, x) tiles times z chunks of rz planes, with at
-// most XSUM_SLOTS blocks per job (one x-sum partial each).
-static void residual_tiling(const Plan &p, int &tiles_x, int &tiles_xy, int &rz, int &tiles)
+// Residual tiling: groups of rb_rows whole rows (256 threads, 4 points per
+// thread) times z chunks of rz planes, with at most XSUM_SLOTS blocks per
+// job (one x-sum partial each).
+static void residual_tiling(const Plan &p, int &rb_rows, int &tiles_y, int &rz, int &tiles)
 {
-    tiles_x = (p.nx + 63) / 64;
-    tiles_xy = ((p.ny + 1 + 3) / 4) * tiles_x;
-    const int chunks = std::max(1, std::min((p.nz + 7) / 8, XSUM_SLOTS / tiles_xy));
+    rb_rows = std::max(1, 256 / (p.nx / 4));
+    tiles_y = (p.ny + 1 + rb_rows - 1) / rb_rows;
+    const int chunks = std::max(1, std::min((p.nz + 7) / 8, XSUM_SLOTS / tiles_y));
     rz = (p.nz + chunks - 1) / chunks;
-    tiles = tiles_xy * ((p.nz + rz - 1) / rz);
+    tiles = tiles_y * ((p.nz + rz - 1) / rz);
 }
 
 int residual_tiles(const Plan &p)
 {
-    int tx, txy, rz, t;
-    residual_tiling(p, tx, txy, rz, t);
+    int rb, ty, rz, t;
+    residual_tiling(p, rb, ty, rz, t);
     return t;
 }
 
 hipError_t launch_residual_f32(const SplitSet &ss, const Plan &p, int pass, bool x32, hipStream_t s)
 {
     const int *skip = pass >= 2 ? reinterpret_cast<const int *>(blob_ptr(p, p.lay.done)) : nullptr;
-    int tiles_x, tiles_xy, rz, tiles;
-    residual_tiling(p, tiles_x, tiles_xy, rz, tiles);
-    if (tiles > XSUM_SLOTS) return hipErrorInvalidValue;
+    int rb_rows, tiles_y, rz, tiles;
+    residual_tiling(p, rb_rows, tiles_y, rz, tiles);
+    if (tiles > XSUM_SLOTS || p.nx % 4 || p.nx / 4 > 256) return hipErrorInvalidValue;
     dim3 grid(tiles, ss.n);
     auto go = [&](auto kernel) {
         hipLaunchKernelGGL(kernel, grid, dim3(256), 0, s, ss, p.nx, p.ny, p.nz, 1.0 / (p.hx * p.hx),
                            1.0 / (p.hz * p.hz), blob_ptr(p, p.lay.dyc), blob_ptr(p, p.lay.dyf),
-                           blob_ptr(p, p.lay.bmean), blob_mut(p, p.lay.xsum), skip, tiles_x, tiles_xy, rz);
+                           blob_ptr(p, p.lay.bmean), blob_mut(p, p.lay.xsum), skip, rb_rows, tiles_y, rz);
     };
     if (x32) go(residual_f32_kernel<float>);
     else go(residual_f32_kernel<double>);
