@@ -156,6 +156,42 @@ def test_projection_divergence_free(ibs):
     assert np.all(_host(vd)[:, 0, :] == 0)
 
 
+@pytest.mark.parametrize("shape", [(48, 7, 16), (16, 33, 48), (1024, 3, 16), (80, 5, 48), (256, 2, 272)])
+def test_stencils_shapes(ibs, shape):
+    """Divergence (kernel E2) and projection plus pressure update (eq. g, h)
+    against the oracle's divergence and gradient on shapes whose row blocks
+    and z chunks are ragged (nx/4 not a power of two, ny+1 rows not a
+    multiple of the rows per block, one row per block at nx = 1024)."""
+    nx, ny, nz = shape
+    _say("case stencils", shape)
+    g = oracle.Grid(nx, ny, nz, beta=1.5)
+    u, v, w = synth.velocity(nx, ny, nz, seed=11)
+    phi = synth.scalar(nx, ny, nz, 12)
+    p0 = synth.scalar(nx, ny, nz, 13)
+    lap = synth.scalar(nx, ny, nz, 14)
+    S = ibs.Solver(nx, ny, nz, beta=1.5)
+    b = _host(S.divergence(_dev(u), _dev(v), _dev(w), scale=0.7))
+    bo = oracle.divergence(g, u, v, w, scale=0.7)
+    assert np.abs(b - bo).max() < 1e-14 * np.abs(bo).max()
+    gs, cp = 0.3, 0.05
+    ud, vd, wd, pd = _dev(u), _dev(v), _dev(w), _dev(p0)
+    S.correct(_dev(phi), ud, vd, wd, gs, p=pd, lap_phi=_dev(lap), cp=cp)
+    gu, gv, gw = oracle.gradient(g, phi)
+    for got, ref in ((ud, u - gs * gu), (wd, w - gs * gw), (pd, p0 + phi - cp * lap)):
+        ref_s = np.abs(ref).max()
+        assert np.abs(_host(got) - ref).max() < 1e-14 * ref_s
+    vref = v - gs * gv
+    vref[:, 0, :] = 0
+    vref[:, ny, :] = 0
+    assert np.abs(_host(vd) - vref).max() < 1e-14 * np.abs(vref).max()
+    vg = _host(vd)
+    assert np.all(vg[:, 0, :] == 0) and np.all(vg[:, ny, :] == 0)
+    # without the pressure update u, v, w are corrected the same way
+    ud2 = _dev(u)
+    S.correct(_dev(phi), ud2, _dev(v), _dev(w), gs)
+    np.testing.assert_array_equal(_host(ud2), _host(ud))
+
+
 def test_deterministic_bitwise(ibs):
     n = 48
     b = synth.scalar(n, n, n, 9)
