@@ -180,10 +180,11 @@ def test_refined_c3_manufactured(ibs):
 
 @pytest.mark.parametrize("refined,shape", [(False, (1024, 3, 32)), (False, (32, 768, 16)),
                                            (True, (512, 5, 64)), (True, (64, 768, 32)),
-                                           (False, (16, 2, 16)), (True, (32, 2, 32))])
+                                           (False, (16, 2, 16)), (True, (32, 2, 32)),
+                                           (True, (64, 4, 512)), (False, (32, 3, 1024))])
 def test_edge_sizes_manufactured(ibs, refined, shape):
-    """Largest and smallest supported extents (nx = 1024 FP64 / 512 refined,
-    ny = 768, ny = 2, n = 16): manufactured solutions, b = A x_true formed by
+    """Largest and smallest supported extents (nx or nz = 1024 FP64 / 512
+    refined, ny = 768, ny = 2, n = 16): manufactured solutions, b = A x_true formed by
     the oracle's long-double stencil."""
     nx, ny, nz = shape
     _say("case edge", refined, shape)
