@@ -1,6 +1,8 @@
 // Host plan builder: grid, y operators, x/z eigenbases, device blob image.
 #include <cmath>
 #include <cstring>
+#include <memory>
+#include <mutex>
 #include <new>
 
 #include "ibs_internal.h"
@@ -192,6 +194,121 @@ static void swizzle_split_pair(const std::vector<double> &F0, const std::vector<
         }
 }
 
+// Everything a plan holds for one periodic axis depends only on its length
+// n, its spacing h, which axis it is (x: B operand of the products, z: A
+// operand) and whether the split tables are needed: the eigenbasis, the
+// eigenvalues, and the blob images of the FP64 and split transforms along
+// it.  Grids that share an axis (a serving mix whose y stretching differs
+// from request to request) take these from a small process-wide cache.
+struct AxisTables {
+    std::vector<double> Q, lam;
+    std::vector<double> f64[4];        // folded: fwd_c, fwd_s, inv_c, inv_s; plain: fwd, inv
+    std::vector<uint16_t> split[2];    // fwd, inv (folded pairs or plain); empty without split
+    size_t bytes() const
+    {
+        size_t b = (Q.size() + lam.size()) * sizeof(double);
+        for (const auto &v : f64) b += v.size() * sizeof(double);
+        for (const auto &v : split) b += v.size() * sizeof(uint16_t);
+        return b;
+    }
+};
+
+static std::shared_ptr<const AxisTables> build_axis(int n, double h, bool z_axis, bool split)
+{
+    auto t = std::make_shared<AxisTables>();
+    fourier_basis(n, h, t->Q, t->lam);
+    const std::vector<double> &Q = t->Q;
+    const int hn = n / 2;
+    const size_t h2 = size_t(hn) * hn;
+    if (can_fold(n)) {
+        FoldFactors f(Q, n);
+        for (auto &v : t->f64) v.resize(h2);
+        if (!z_axis) {
+            swizzle_b(f.c.data(), hn, hn, t->f64[0].data());                   // forward: E Qc
+            swizzle_b(f.s_fwd.data(), hn, hn, t->f64[1].data());               // forward: O Qs
+            swizzle_b(f.transposed(f.c).data(), hn, hn, t->f64[2].data());     // inverse: Xc Qc^T
+            swizzle_b(f.transposed(f.s_inv).data(), hn, hn, t->f64[3].data()); // inverse: Xs Qs^T
+        } else {
+            swizzle_a(f.transposed(f.c).data(), hn, hn, t->f64[0].data());     // forward: Qc^T E
+            swizzle_a(f.transposed(f.s_fwd).data(), hn, hn, t->f64[1].data()); // forward: Qs^T O
+            swizzle_a(f.c.data(), hn, hn, t->f64[2].data());                   // inverse: Qc Xc
+            swizzle_a(f.s_inv.data(), hn, hn, t->f64[3].data());               // inverse: Qs Xs
+        }
+    } else {
+        std::vector<double> tr(size_t(n) * n);
+        for (int i = 0; i < n; ++i)
+            for (int a = 0; a < n; ++a) tr[size_t(a) * n + i] = Q[size_t(i) * n + a];
+        t->f64[0].resize(size_t(n) * n);
+        t->f64[1].resize(size_t(n) * n);
+        if (!z_axis) {
+            swizzle_b(Q.data(), n, n, t->f64[0].data());    // x forward: C = X Q
+            swizzle_b(tr.data(), n, n, t->f64[1].data());   // x inverse: C = Xhat Q^T
+        } else {
+            swizzle_a(tr.data(), n, n, t->f64[0].data());   // z forward: A = Q^T
+            swizzle_a(Q.data(), n, n, t->f64[1].data());    // z inverse: A = Q
+        }
+    }
+    if (split) {
+        if (can_fold_split(n)) {
+            FoldFactors f(Q, n);
+            t->split[0].resize(size_t(3) * 2 * h2);
+            t->split[1].resize(size_t(3) * 2 * h2);
+            if (!z_axis) {
+                swizzle_split_pair(f.c, f.s_fwd, hn, false, t->split[0].data());   // forward: E Qc, O Qs
+                swizzle_split_pair(f.transposed(f.c), f.transposed(f.s_inv), hn, false, t->split[1].data());
+            } else {
+                swizzle_split_pair(f.transposed(f.c), f.transposed(f.s_fwd), hn, true, t->split[0].data());
+                swizzle_split_pair(f.c, f.s_inv, hn, true, t->split[1].data());
+            }
+        } else {
+            std::vector<double> tr(size_t(n) * n);
+            for (int i = 0; i < n; ++i)
+                for (int a = 0; a < n; ++a) tr[size_t(a) * n + i] = Q[size_t(i) * n + a];
+            t->split[0].resize(size_t(3) * n * n);
+            t->split[1].resize(size_t(3) * n * n);
+            if (!z_axis) {
+                swizzle_b_split(Q.data(), n, n, t->split[0].data());
+                swizzle_b_split(tr.data(), n, n, t->split[1].data());
+            } else {
+                swizzle_a_split(tr.data(), n, n, t->split[0].data());
+                swizzle_a_split(Q.data(), n, n, t->split[1].data());
+            }
+        }
+    }
+    return t;
+}
+
+// Cache of axis tables, at most AXIS_CACHE_BYTES of host memory (oldest
+// entries dropped first).  Plans copy what they need, so dropping an entry
+// never affects an existing plan.
+constexpr size_t AXIS_CACHE_BYTES = size_t(256) << 20;
+static std::shared_ptr<const AxisTables> axis_tables(int n, double h, bool z_axis, bool split)
+{
+    struct Entry {
+        int n;
+        double h;
+        bool z, split;
+        std::shared_ptr<const AxisTables> t;
+    };
+    static std::mutex mu;
+    static std::vector<Entry> cache;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        for (const Entry &e : cache)
+            if (e.n == n && e.h == h && e.z == z_axis && e.split == split) return e.t;
+    }
+    std::shared_ptr<const AxisTables> t = build_axis(n, h, z_axis, split);
+    std::lock_guard<std::mutex> lock(mu);
+    size_t total = t->bytes();
+    for (const Entry &e : cache) total += e.t->bytes();
+    while (!cache.empty() && total > AXIS_CACHE_BYTES) {
+        total -= cache.front().t->bytes();
+        cache.erase(cache.begin());
+    }
+    if (t->bytes() <= AXIS_CACHE_BYTES) cache.push_back(Entry{n, h, z_axis, split, t});
+    return t;
+}
+
 ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
 {
     if (d.nx < 16 || d.nz < 16 || d.nx > 1024 || d.nz > 1024 || d.nx % 16 || d.nz % 16) {
@@ -290,8 +407,13 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
         p->di[KIND_F][j] = -(lo + up);
     }
 
-    fourier_basis(nx, p->hx, p->qx, p->lam_x);
-    fourier_basis(nz, p->hz, p->qz, p->lam_z);
+    const bool split = d.precision != IBS_FP64;
+    const std::shared_ptr<const AxisTables> ax = axis_tables(nx, p->hx, false, split);
+    const std::shared_ptr<const AxisTables> az = axis_tables(nz, p->hz, true, split);
+    p->qx = ax->Q;
+    p->lam_x = ax->lam;
+    p->qz = az->Q;
+    p->lam_z = az->lam;
 
     // blob layout
     BlobLayout &L = p->lay;
@@ -321,7 +443,6 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     L.wy = take(sizeof(double) * ny);
     L.dyc = take(sizeof(double) * ny);
     L.dyf = take(sizeof(double) * (ny + 1));
-    const bool split = d.precision != IBS_FP64;
     const bool sfold_x = split && can_fold_split(nx), sfold_z = split && can_fold_split(nz);
     L.sx_fwd = take(split && !sfold_x ? sizeof(uint16_t) * 3 * nx * nx : 0);
     L.sx_inv = take(split && !sfold_x ? sizeof(uint16_t) * 3 * nx * nx : 0);
@@ -341,83 +462,32 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     auto put = [&](size_t off, const double *src, size_t n) {
         std::memcpy(p->blob.data() + off, src, n * sizeof(double));
     };
+    auto put16 = [&](size_t off, const std::vector<uint16_t> &src) {
+        std::memcpy(p->blob.data() + off, src.data(), src.size() * sizeof(uint16_t));
+    };
     if (fold_x) {
-        FoldFactors f(p->qx, nx);
-        std::vector<double> tmp(hx2);
-        swizzle_b(f.c.data(), nx / 2, nx / 2, tmp.data());   // forward: E Qc
-        put(L.fx_fwd_c, tmp.data(), tmp.size());
-        swizzle_b(f.s_fwd.data(), nx / 2, nx / 2, tmp.data());   // forward: O Qs
-        put(L.fx_fwd_s, tmp.data(), tmp.size());
-        swizzle_b(f.transposed(f.c).data(), nx / 2, nx / 2, tmp.data());   // inverse: Xc Qc^T
-        put(L.fx_inv_c, tmp.data(), tmp.size());
-        swizzle_b(f.transposed(f.s_inv).data(), nx / 2, nx / 2, tmp.data());   // inverse: Xs Qs^T
-        put(L.fx_inv_s, tmp.data(), tmp.size());
+        put(L.fx_fwd_c, ax->f64[0].data(), hx2);
+        put(L.fx_fwd_s, ax->f64[1].data(), hx2);
+        put(L.fx_inv_c, ax->f64[2].data(), hx2);
+        put(L.fx_inv_s, ax->f64[3].data(), hx2);
     } else {
-        std::vector<double> tmp(size_t(nx) * nx), tr(size_t(nx) * nx);
-        // x forward: C = X Q (contract over grid index i)
-        swizzle_b(p->qx.data(), nx, nx, tmp.data());
-        put(L.bx_fwd, tmp.data(), tmp.size());
-        // x inverse: C = Xhat Q^T
-        for (int i = 0; i < nx; ++i)
-            for (int a = 0; a < nx; ++a) tr[size_t(a) * nx + i] = p->qx[size_t(i) * nx + a];
-        swizzle_b(tr.data(), nx, nx, tmp.data());
-        put(L.bx_inv, tmp.data(), tmp.size());
+        put(L.bx_fwd, ax->f64[0].data(), size_t(nx) * nx);
+        put(L.bx_inv, ax->f64[1].data(), size_t(nx) * nx);
     }
     if (fold_z) {
-        FoldFactors f(p->qz, nz);
-        std::vector<double> tmp(hz2);
-        swizzle_a(f.transposed(f.c).data(), nz / 2, nz / 2, tmp.data());   // forward: Qc^T E
-        put(L.fz_fwd_c, tmp.data(), tmp.size());
-        swizzle_a(f.transposed(f.s_fwd).data(), nz / 2, nz / 2, tmp.data());   // forward: Qs^T O
-        put(L.fz_fwd_s, tmp.data(), tmp.size());
-        swizzle_a(f.c.data(), nz / 2, nz / 2, tmp.data());   // inverse: Qc Xc
-        put(L.fz_inv_c, tmp.data(), tmp.size());
-        swizzle_a(f.s_inv.data(), nz / 2, nz / 2, tmp.data());   // inverse: Qs Xs
-        put(L.fz_inv_s, tmp.data(), tmp.size());
+        put(L.fz_fwd_c, az->f64[0].data(), hz2);
+        put(L.fz_fwd_s, az->f64[1].data(), hz2);
+        put(L.fz_inv_c, az->f64[2].data(), hz2);
+        put(L.fz_inv_s, az->f64[3].data(), hz2);
     } else {
-        std::vector<double> tmp(size_t(nz) * nz), tr(size_t(nz) * nz);
-        // z forward: Xhat[c] = sum_k Q[k][c] X[k]  -> A = Q^T
-        for (int k = 0; k < nz; ++k)
-            for (int c = 0; c < nz; ++c) tr[size_t(c) * nz + k] = p->qz[size_t(k) * nz + c];
-        swizzle_a(tr.data(), nz, nz, tmp.data());
-        put(L.az_fwd, tmp.data(), tmp.size());
-        // z inverse: X[k] = sum_c Q[k][c] Xhat[c] -> A = Q
-        swizzle_a(p->qz.data(), nz, nz, tmp.data());
-        put(L.az_inv, tmp.data(), tmp.size());
+        put(L.az_fwd, az->f64[0].data(), size_t(nz) * nz);
+        put(L.az_inv, az->f64[1].data(), size_t(nz) * nz);
     }
-    if (sfold_x) {
-        FoldFactors f(p->qx, nx);
-        std::vector<uint16_t> sw(size_t(3) * 2 * hx2);
-        swizzle_split_pair(f.c, f.s_fwd, nx / 2, false, sw.data());   // forward: E Qc, O Qs
-        std::memcpy(p->blob.data() + L.sxf_fwd, sw.data(), sw.size() * 2);
-        swizzle_split_pair(f.transposed(f.c), f.transposed(f.s_inv), nx / 2, false, sw.data());
-        std::memcpy(p->blob.data() + L.sxf_inv, sw.data(), sw.size() * 2);
-    } else if (split) {
-        std::vector<double> tr(size_t(nx) * nx);
-        std::vector<uint16_t> sw(size_t(3) * nx * nx);
-        swizzle_b_split(p->qx.data(), nx, nx, sw.data());
-        std::memcpy(p->blob.data() + L.sx_fwd, sw.data(), sw.size() * 2);
-        for (int i = 0; i < nx; ++i)
-            for (int a = 0; a < nx; ++a) tr[size_t(a) * nx + i] = p->qx[size_t(i) * nx + a];
-        swizzle_b_split(tr.data(), nx, nx, sw.data());
-        std::memcpy(p->blob.data() + L.sx_inv, sw.data(), sw.size() * 2);
-    }
-    if (sfold_z) {
-        FoldFactors f(p->qz, nz);
-        std::vector<uint16_t> sw(size_t(3) * 2 * hz2);
-        swizzle_split_pair(f.transposed(f.c), f.transposed(f.s_fwd), nz / 2, true, sw.data());
-        std::memcpy(p->blob.data() + L.szf_fwd, sw.data(), sw.size() * 2);
-        swizzle_split_pair(f.c, f.s_inv, nz / 2, true, sw.data());
-        std::memcpy(p->blob.data() + L.szf_inv, sw.data(), sw.size() * 2);
-    } else if (split) {
-        std::vector<double> trz(size_t(nz) * nz);
-        std::vector<uint16_t> swz(size_t(3) * nz * nz);
-        for (int k = 0; k < nz; ++k)
-            for (int c = 0; c < nz; ++c) trz[size_t(c) * nz + k] = p->qz[size_t(k) * nz + c];
-        swizzle_a_split(trz.data(), nz, nz, swz.data());
-        std::memcpy(p->blob.data() + L.sz_fwd, swz.data(), swz.size() * 2);
-        swizzle_a_split(p->qz.data(), nz, nz, swz.data());
-        std::memcpy(p->blob.data() + L.sz_inv, swz.data(), swz.size() * 2);
+    if (split) {
+        put16(sfold_x ? L.sxf_fwd : L.sx_fwd, ax->split[0]);
+        put16(sfold_x ? L.sxf_inv : L.sx_inv, ax->split[1]);
+        put16(sfold_z ? L.szf_fwd : L.sz_fwd, az->split[0]);
+        put16(sfold_z ? L.szf_inv : L.sz_inv, az->split[1]);
     }
     put(L.lam_x, p->lam_x.data(), nx);
     put(L.lam_z, p->lam_z.data(), nz);

@@ -112,6 +112,31 @@ def test_plan_bytes_and_errors():
     assert e.value.status == ibs.IBS_ERR_INVALID_ARG
 
 
+def test_axis_tables_shared_between_plans():
+    """Plans that share an axis length take that axis's tables from a
+    process-wide cache: a plan built after others with the same nx or nz
+    (different ny, stretching, precision or axis role) exports exactly the
+    tables a plan of its own would, for both the folded and plain sizes."""
+    R, F = ibs.IBS_REFINED_BF16X3, ibs.IBS_FP64
+    cases = [(64, 10, 96, 0.0, F), (96, 30, 64, 2.0, R), (64, 7, 64, 1.0, R), (96, 12, 96, 3.0, F),
+             (64, 10, 96, 0.0, F)]
+    ref = {}
+    for nx, ny, nz, beta, prec in cases:
+        p = _plan(nx, ny, nz, beta=beta, precision=prec)
+        try:
+            Qx = ibs.ibs_plan_export(p, 1).reshape(nx, nx)
+            Qz = ibs.ibs_plan_export(p, 2).reshape(nz, nz)
+            lx, lz = ibs.ibs_plan_export(p, 3), ibs.ibs_plan_export(p, 4)
+        finally:
+            ibs.solver_plan_destroy(p)
+        for n, Q, lam in ((nx, Qx, lx), (nz, Qz, lz)):
+            np.testing.assert_allclose(Q.T @ Q, np.eye(n), atol=1e-14)
+            if n in ref:
+                np.testing.assert_array_equal(Q, ref[n][0])
+                np.testing.assert_array_equal(lam, ref[n][1])
+            ref[n] = (Q.copy(), lam.copy())
+
+
 # ------------------------------------------------------------------------
 # host emulation of the separable algorithm from the plan tables
 # ------------------------------------------------------------------------
