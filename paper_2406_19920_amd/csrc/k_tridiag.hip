@@ -13,8 +13,8 @@
 // the weighted mean is removed, which fixes the null mode at zero mean.
 //
 // Layout and parallel scheme (an MI355X design, not the paper's
-// thread-per-pencil Thomas sweep): a tile is 16 (or 8) consecutive x-modes
-// of one z-plane, all rows.  Persistent workgroups walk the tiles in
+// thread-per-pencil Thomas sweep): a tile is 16 (8 or 32, by arithmetic
+// type) consecutive x-modes of one z-plane, all rows.  Persistent workgroups walk the tiles in
 // adjacent pairs; each tile is read row by row into registers while the
 // previous tile is being solved, then staged through LDS.  Each pencil is
 // split into P (16 or 32) chunks of M consecutive rows, one lane per chunk.
@@ -389,11 +389,13 @@ __global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
 template <typename T, typename R, int P, int M>
 static hipError_t launch_pm(const JobSet &js, const TriParams &tp, hipStream_t s)
 {
-    // pencils per tile: 16, or 8 for FP32 data with FP64 arithmetic, whose
+    // pencils per tile: 16; 8 for FP32 data with FP64 arithmetic, whose
     // registers allow fewer waves per SIMD (blocks of 4 waves then still
     // fill them; with FP64 data the 16-wide tiles measured as fast with
-    // less traffic)
-    constexpr int TA = sizeof(R) == 8 && sizeof(T) == 4 && P == 32 ? 8 : 16;
+    // less traffic); 32 for FP32 arithmetic over 32 lanes of up to 9 rows
+    // (a tile row is one whole 128-byte line; 16-wave blocks, 5 % faster)
+    constexpr int TA = sizeof(R) == 8 && sizeof(T) == 4 && P == 32 ? 8
+                       : (sizeof(R) == 4 && P == 32 && M <= 9) ? 32 : 16;
     // persistent blocks walk the tiles (job, z-mode, TA x-modes) in order;
     // as many blocks as are resident at once, so that every block's tiles
     // run back to back
