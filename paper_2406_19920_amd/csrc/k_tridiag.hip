@@ -298,16 +298,18 @@ __global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
             R ED = re - ae * sig_u - ge * sig1;
 #pragma unroll
             for (int d = 1; d < P; d <<= 1) {
-                R am = __shfl_up(EA, d, P), bm = __shfl_up(EB, d, P);
-                R cm = __shfl_up(EC, d, P), dm = __shfl_up(ED, d, P);
-                R ap = __shfl_down(EA, d, P), bp = __shfl_down(EB, d, P);
-                R cp = __shfl_down(EC, d, P), dp = __shfl_down(ED, d, P);
-                if (k < d) { am = 0.0; bm = 1.0; cm = 0.0; dm = 0.0; }
-                if (k + d >= P) { ap = 0.0; bp = 1.0; cp = 0.0; dp = 0.0; }
-                const R k1 = EA * rcpr(bm), k2 = EC * rcpr(bp);
-                const R nA = -k1 * am, nC = -k2 * cp;
-                const R nB = EB - k1 * cm - k2 * ap;
-                const R nD = ED - k1 * dm - k2 * dp;
+                // each lane scales its row to a unit diagonal (one division)
+                // and the neighbours at distance d eliminate with it: three
+                // values cross lanes each way instead of four
+                const R ib = rcpr(EB);
+                const R ua = EA * ib, uc = EC * ib, ud = ED * ib;
+                R am = __shfl_up(ua, d, P), cm = __shfl_up(uc, d, P), dm = __shfl_up(ud, d, P);
+                R ap = __shfl_down(ua, d, P), cp = __shfl_down(uc, d, P), dp = __shfl_down(ud, d, P);
+                if (k < d) { am = 0.0; cm = 0.0; dm = 0.0; }
+                if (k + d >= P) { ap = 0.0; cp = 0.0; dp = 0.0; }
+                const R nA = -EA * am, nC = -EC * cp;
+                const R nB = EB - EA * cm - EC * ap;
+                const R nD = ED - EA * dm - EC * dp;
                 EA = nA; EB = nB; EC = nC; ED = nD;
             }
             const R z = ED * rcpr(EB);
