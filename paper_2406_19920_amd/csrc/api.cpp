@@ -500,11 +500,16 @@ ibs_status ibs_autotune(ibs_plan plan, void *scratch, size_t scratch_bytes, int3
     const Knob knobs[NUM_TUNE] = {{TUNE_XFOLD, can_fold(p.nx), launch_xfold_f64},
                                   {TUNE_ZFOLD, can_fold(p.nz), launch_zfold_f64}};
     ibs_status st = IBS_OK;
+    // candidates timed in interleaved rounds, each keeping its fastest
+    // round, so that a transient slowdown of one measurement (clock ramp,
+    // another process) does not decide between candidates a few per cent
+    // apart
+    constexpr int ROUNDS = 3;
     for (const Knob &k : knobs) {
         if (!k.applies) { p.tune[k.id] = -1; continue; }
-        int best = 0;
-        float best_ms = 0.f;
-        for (int cand = 0; cand < fold_candidates() && st == IBS_OK; ++cand) {
+        std::vector<float> cand_ms(fold_candidates(), 0.f);
+        for (int trial_no = 0; trial_no < ROUNDS * fold_candidates() && st == IBS_OK; ++trial_no) {
+            const int round = trial_no / fold_candidates(), cand = trial_no % fold_candidates();
             p.tune[k.id] = cand;
             auto trial = [&](int reps) {
                 hipError_t r = hipSuccess;
@@ -525,8 +530,11 @@ ibs_status ibs_autotune(ibs_plan plan, void *scratch, size_t scratch_bytes, int3
                 st = hip_fail(e, "autotune trial");
                 break;
             }
-            if (cand == 0 || ms < best_ms) { best = cand; best_ms = ms; }
+            if (round == 0 || ms < cand_ms[cand]) cand_ms[cand] = ms;
         }
+        int best = 0;
+        for (int cand = 1; cand < fold_candidates(); ++cand)
+            if (cand_ms[cand] < cand_ms[best]) best = cand;
         p.tune[k.id] = best;
     }
     hipEventDestroy(ev[0]);

@@ -121,7 +121,12 @@ __global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
         else return (j / M) * MS + j % M;
     };
     constexpr int LDR = TA + 1;            // LDS row stride (elements)
-    __shared__ R sx[NRS * LDR];
+    // Two staging buffers (alternate tiles) where they fit: a tile's
+    // staging then needs no barrier against the previous tile's write-back,
+    // which reads the other buffer (the barriers of the tile in between
+    // order it after the write-back of the tile before).
+    constexpr bool DB = P == 32 && M <= 9;
+    __shared__ R sx[(DB ? 2 : 1) * NRS * LDR];
     __shared__ R slo[NRS], sdi[NRS], sup[NRS], sw[NRS];
 
     const int tid = threadIdx.x;
@@ -177,14 +182,17 @@ __global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
     T pfa[M], pfb[M];
     double lxa, lza, lxb, lzb;
     int cur_job = -1;
-    auto process = [&](const int tile, T (&pf)[M], double &plx, double &plz) {
+    auto process = [&](const int tile, T (&pf)[M], double &plx, double &plz, R *sx) {
         int job, c, a0;
         decode(tile, job, c, a0);
         const FieldJob &jb = js.j[job];
         // the v systems leave out the first wall row (kept at zero below)
         const int kind = jb.kind, sys0 = skip_first_row(kind), n = jb.rows - sys0;
         const bool live = !((skipmask >> job) & 1);   // block-uniform
-        __syncthreads();  // the previous tile's LDS is no longer read
+        // the previous tile's staging buffer is no longer read (the
+        // coefficient rows below are free once its solve, which ends with a
+        // barrier, is done)
+        if constexpr (!DB) __syncthreads();
         if (live && job != cur_job) {
             // rows of the job's operator without the pencil shift:
             // Poisson (lo, di, up); Helmholtz (-c lo, 1 - c di, -c up)
@@ -383,8 +391,8 @@ __global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
     fetch(2 * blockIdx.x, pfa, lxa, lza);
     fetch(2 * blockIdx.x + 1, pfb, lxb, lzb);
     for (int tile = 2 * blockIdx.x; tile < ntiles; tile += 2 * G) {
-        process(tile, pfa, lxa, lza);
-        if (tile + 1 < ntiles) process(tile + 1, pfb, lxb, lzb);
+        process(tile, pfa, lxa, lza, sx);
+        if (tile + 1 < ntiles) process(tile + 1, pfb, lxb, lzb, DB ? sx + NRS * LDR : sx);
     }
 }
 
