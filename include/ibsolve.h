@@ -65,10 +65,13 @@ typedef enum {
 
 typedef enum {
     IBS_FP64 = 0,           /* every stage in FP64                              */
-    IBS_REFINED_FP16X2 = 1, /* split-FP16 transforms, FP32 accumulation,
-                               refined against an FP64 residual                */
-    IBS_REFINED_BF16X3 = 2, /* split-BF16 (3 terms) transforms, FP32 accum.     */
-    IBS_REFINED_AUTO = 3    /* library picks the split scheme                   */
+    IBS_REFINED_FP16X2 = 1, /* reserved: split-FP16 transforms; not built, so
+                               solver_plan() returns IBS_ERR_UNSUPPORTED        */
+    IBS_REFINED_BF16X3 = 2, /* split-BF16 (3 terms) transforms, FP32
+                               accumulation, FP32 work arrays, refined against
+                               an FP64 residual                                 */
+    IBS_REFINED_AUTO = 3    /* reserved: library-chosen split scheme; not
+                               built, so IBS_ERR_UNSUPPORTED                    */
 } ibs_precision;
 
 typedef enum { IBS_PERIODIC = 0, IBS_DIRICHLET = 1, IBS_NEUMANN = 2 } ibs_bc;
@@ -88,12 +91,19 @@ typedef struct {
     int32_t bc_x, bc_z;       /* ibs_bc                                      */
     int32_t bc_y_vel, bc_y_p; /* ibs_bc                                      */
     int32_t precision;        /* ibs_precision                               */
-    double tol;               /* refined path: target ||delta||/||x|| (1e-10 if <= 0) */
-    int32_t max_iter;         /* refined path: most solve passes, >= 1 (0:
+    double tol;               /* refined path: target predicted relative
+                                 error of x (1e-10 if <= 0)                  */
+    int32_t max_iter;         /* refined path: most solve passes, 0..8 (0:
                                  3 for Poisson, 2 for Helmholtz); passes stop
-                                 early once the predicted error meets tol    */
-    int32_t strict_compat;    /* 1: Poisson rhs with nonzero weighted mean
-                                 reports IBS_ERR_INCOMPATIBLE_RHS in info    */
+                                 early once the predicted error meets tol.
+                                 A single pass (max_iter = 1) measures no
+                                 correction, so its report is always
+                                 IBS_ERR_NOT_CONVERGED with NaN estimates    */
+    int32_t strict_compat;    /* 1: a Poisson rhs whose volume-weighted mean
+                                 exceeds 1e-10 times its weighted rms
+                                 (checked in FP64 on b itself) reports
+                                 IBS_ERR_INCOMPATIBLE_RHS in info (the solve
+                                 still runs, with the mean removed)          */
 } ibs_grid_desc;
 
 /* Per-solve report, written by the device at the end of the solve.  Must
@@ -129,14 +139,19 @@ ibs_status solver_plan(const ibs_grid_desc *desc, ibs_plan *out);
  * work_bytes: minimum workspace for one solve call: one FP64 field per
  * component on the FP64 path, three FP32 fields per component on the
  * refined path (cells of a field: nz * ny * nx, or nz * (ny+1) * nx for a
- * Helmholtz batch).  Either output pointer may be NULL. */
+ * Helmholtz batch), followed by the call's mutable state (mean of the
+ * rhs, refinement stop flags, reduction partials; under 2 MB at 512^3).
+ * Either output pointer may be NULL. */
 ibs_status solver_plan_bytes(ibs_plan plan, int32_t op, int32_t ncomp,
                              size_t *const_bytes, size_t *work_bytes);
 
 /* Copy the plan's constants into dev_const (device memory, >= const_bytes,
  * 256-byte aligned) on stream.  The plan remembers dev_const; it must stay
  * allocated while the plan is used.  The copy reads host memory owned by
- * the plan, so the plan must outlive the copy. */
+ * the plan, so the plan must outlive the copy.  After the upload the
+ * device constants are only read: solves on one plan may run concurrently
+ * (on different streams, from different host threads) as long as each call
+ * has a workspace of its own; calls that share a workspace race. */
 ibs_status solver_plan_upload(ibs_plan plan, void *dev_const, size_t bytes,
                               void *stream);
 
@@ -147,10 +162,12 @@ ibs_status solver_plan_destroy(ibs_plan plan);
  * compatibility; reported in info->removed_mean) and phi is returned with
  * zero volume-weighted mean (the null mode; internally the singular
  * (0,0) pencil is pinned at its first point as in Section 2.3.3, item
- * S2.1, then shifted).  b: [nz][ny][nx] device, read only; phi: same shape,
- * may alias b.  work: device buffer of >= work_bytes (solver_plan_bytes
- * with IBS_OP_POISSON).  Errors: IBS_ERR_INVALID_ARG, IBS_ERR_NOT_UPLOADED,
- * IBS_ERR_WORKSPACE_TOO_SMALL, IBS_ERR_HIP. */
+ * S2.1, then shifted).  b: [nz][ny][nx] device, read only; phi: same shape.
+ * FP64 path: phi may alias b.  Refined path: phi must not alias b (later
+ * passes re-read b; IBS_ERR_INVALID_ARG).  work: device buffer of >=
+ * work_bytes (solver_plan_bytes with IBS_OP_POISSON), 32-byte aligned, not
+ * shared with a concurrent call.  Errors: IBS_ERR_INVALID_ARG,
+ * IBS_ERR_NOT_UPLOADED, IBS_ERR_WORKSPACE_TOO_SMALL, IBS_ERR_HIP. */
 ibs_status solve_poisson(ibs_plan plan, const double *b, double *phi, void *work,
                          size_t work_bytes, ibs_solve_info *info, void *stream);
 
@@ -159,8 +176,10 @@ ibs_status solve_poisson(ibs_plan plan, const double *b, double *phi, void *work
  * 1 = v, 2 = w} selects the grid of component q (u, w: Dirichlet wall by a
  * mirror ghost, Appendix B alpha = 2; v: wall-face values, alpha = 1).
  * comp, c, r, x are HOST arrays of ncomp entries; r[q], x[q] are device
- * fields of the component's shape; x[q] may alias r[q]; c[q] >= 0.
- * info: NULL or ncomp records.  Errors as solve_poisson. */
+ * fields of the component's shape; c[q] >= 0.  FP64 path: x[q] may alias
+ * r[q].  Refined path: x[q] must not alias r[q] (IBS_ERR_INVALID_ARG).
+ * info: NULL or ncomp records.  work as for solve_poisson, sized with
+ * IBS_OP_HELMHOLTZ_U and ncomp.  Errors as solve_poisson. */
 ibs_status solve_helmholtz_batch(ibs_plan plan, int32_t ncomp, const int32_t *comp,
                                  const double *c, const double *const *r,
                                  double *const *x, void *work, size_t work_bytes,
@@ -170,11 +189,15 @@ ibs_status solve_helmholtz_batch(ibs_plan plan, int32_t ncomp, const int32_t *co
  * IBS_OP_HELMHOLTZ_{U,V,W} (A = I - c L), with the 7-point stencil.  x, b, r
  * device fields of the op's shape (r may not alias x).  norms2: NULL or a
  * device double[2] receiving ||r||_2^2 and ||b||_2^2 over the unknowns
- * (deterministic fixed-order reduction).  Uses no workspace beyond an
- * internal region of the plan's constant buffer; calls on one plan must not
- * overlap in time.  Errors: IBS_ERR_INVALID_ARG, IBS_ERR_NOT_UPLOADED. */
+ * (deterministic fixed-order reduction).  work: only read when norms2 is
+ * not NULL (then the reduction partials go there): a 32-byte aligned device
+ * buffer of >= the work_bytes solver_plan_bytes() gives for IBS_OP_POISSON
+ * (op 0) or IBS_OP_HELMHOLTZ_U with ncomp 1 (ops 1..3), not shared with a
+ * concurrent call; may be NULL otherwise.  Errors: IBS_ERR_INVALID_ARG,
+ * IBS_ERR_NOT_UPLOADED, IBS_ERR_WORKSPACE_TOO_SMALL. */
 ibs_status residual(ibs_plan plan, int32_t op, double c, const double *x,
-                    const double *b, double *r, double *norms2, void *stream);
+                    const double *b, double *r, double *norms2, void *work,
+                    size_t work_bytes, void *stream);
 
 /* RHS of the Poisson problem (kernel E2 of Section 2.3.2):
  * b = scale * D(u, v, w), D the staggered divergence.  v's wall faces are
@@ -199,8 +222,9 @@ typedef struct ibs_batch_s *ibs_batch;
  * IBS_OP_HELMHOLTZ_U for a Helmholtz batch of ncomp components (comp, c,
  * rhs, x as in solve_helmholtz_batch).  Every pointer is captured as is:
  * the buffers must stay allocated, and at the same addresses, for the
- * lifetime of the batch.  Solves of one plan must share their plan's
- * scratch serially, so the batch never overlaps two jobs of one plan. */
+ * lifetime of the batch.  Jobs that share a workspace are ordered one after
+ * the other (same graph branch); jobs with distinct workspaces may overlap,
+ * whether or not they share a plan. */
 typedef struct {
     ibs_plan plan;
     int32_t op;
@@ -265,7 +289,7 @@ ibs_status ibs_profile_read(ibs_plan plan, int32_t kernel, double *ms, int64_t *
 #define IBS_NUM_TUNE 2   /* 0: folded FP64 x transform, 1: folded FP64 z transform */
 ibs_status ibs_autotune_bytes(ibs_plan plan, size_t *bytes);
 ibs_status ibs_autotune(ibs_plan plan, void *scratch, size_t scratch_bytes, int32_t *choices,
-                        hipStream_t stream);
+                        void *stream);
 ibs_status ibs_plan_set_tiles(ibs_plan plan, const int32_t *choices, int32_t n);
 
 /* Thread-local text of the last error (never NULL). */

@@ -89,14 +89,74 @@ ibs_status profile_suspend(ibs_plan plan, bool *was_on)
 }
 void profile_resume(ibs_plan plan, bool was_on) { reinterpret_cast<Plan *>(plan)->prof.on = was_on; }
 
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Upper bound on the passes; the device stops earlier once the predicted
+// error meets tol.  The Helmholtz systems are well conditioned (two passes
+// reach ~1e-13); the pressure problem on large stretched grids may need a
+// third.
+static int default_passes(const Plan &p, bool poisson)
+{
+    if (p.desc.max_iter > 0) return p.desc.max_iter;
+    return poisson ? 3 : 2;
+}
+
 // FP64 path: one FP64 scratch field per component.  Refined path: three
 // FP32 fields per component (two transform buffers and the stored first
 // iterate).
-size_t work_bytes_for(const Plan &p, int op, int ncomp)
+size_t field_bytes_for(const Plan &p, int op, int ncomp)
 {
     const size_t per = p.desc.precision == IBS_FP64 ? sizeof(double) : 3 * sizeof(float);
     if (op == IBS_OP_POISSON) return field_doubles(p, p.ny) * per;
     return (size_t)ncomp * field_doubles(p, p.ny + 1) * per;
+}
+
+// Doubles of the state's reduction region: the update partials of every
+// refinement pass (refined path), at least the residual() partials.
+static size_t red_doubles(const Plan &p, int op, int ncomp)
+{
+    size_t n = 2 * (size_t)RESID_SLOTS;
+    if (p.desc.precision != IBS_FP64) {
+        const int nc = op == IBS_OP_POISSON ? 1 : ncomp;
+        const size_t upd = (size_t)default_passes(p, op == IBS_OP_POISSON) * update_region(p, nc);
+        n = upd > n ? upd : n;
+    }
+    return n;
+}
+
+// State layout (after the fields, 256-byte aligned): bmean[4], done[4],
+// incompat[4], xsum[4][XSUM_SLOTS], compat[2 COMPAT_SLOTS], red[...].
+size_t state_bytes_for(const Plan &p, int op, int ncomp)
+{
+    size_t o = align256(STATE_JOBS * sizeof(double));
+    o += align256(2 * STATE_JOBS * sizeof(int));
+    o += align256((size_t)STATE_JOBS * XSUM_SLOTS * sizeof(double));
+    o += align256(2 * (size_t)COMPAT_SLOTS * sizeof(double));
+    o += align256(red_doubles(p, op, ncomp) * sizeof(double));
+    return o;
+}
+
+State state_in(const Plan &p, void *work, int op, int ncomp)
+{
+    unsigned char *b = static_cast<unsigned char *>(work) + align256(field_bytes_for(p, op, ncomp));
+    State st;
+    st.bmean = reinterpret_cast<double *>(b);
+    b += align256(STATE_JOBS * sizeof(double));
+    st.done = reinterpret_cast<int *>(b);
+    st.incompat = st.done + STATE_JOBS;
+    b += align256(2 * STATE_JOBS * sizeof(int));
+    st.xsum = reinterpret_cast<double *>(b);
+    b += align256((size_t)STATE_JOBS * XSUM_SLOTS * sizeof(double));
+    st.compat = reinterpret_cast<double *>(b);
+    b += align256(2 * (size_t)COMPAT_SLOTS * sizeof(double));
+    st.red = reinterpret_cast<double *>(b);
+    st.red_count = red_doubles(p, op, ncomp);
+    return st;
+}
+
+size_t work_bytes_for(const Plan &p, int op, int ncomp)
+{
+    return align256(field_bytes_for(p, op, ncomp)) + state_bytes_for(p, op, ncomp);
 }
 
 static double total_cells(const JobSet &js, const Plan &p)
@@ -109,7 +169,7 @@ static double total_cells(const JobSet &js, const Plan &p)
 // The five FP64 stages.  js.j[q].in holds the right-hand side; W[q] is the
 // job's scratch field and X[q] its output.
 static ibs_status run_fp64_pipeline_multi(Plan &p, JobSet js, double *const *W, double *const *X,
-                                          bool poisson, hipStream_t s)
+                                          const State &st, bool poisson, hipStream_t s)
 {
     hipError_t e;
     const double cells = total_cells(js, p);
@@ -134,7 +194,7 @@ static ibs_status run_fp64_pipeline_multi(Plan &p, JobSet js, double *const *W, 
     e = timed(p, PK_ZGEMM, zflop, rw, s, [&] { return zform(false); });
     if (e != hipSuccess) return hip_fail(e, "z forward");
     for (int q = 0; q < js.n; ++q) js.j[q].in = X[q];
-    e = timed(p, PK_TRIDIAG, 20.0 * cells, rw, s, [&] { return launch_tridiag_f64(js, p, poisson, s); });
+    e = timed(p, PK_TRIDIAG, 20.0 * cells, rw, s, [&] { return launch_tridiag_f64(js, p, st, poisson, s); });
     if (e != hipSuccess) return hip_fail(e, "tridiagonal");
     for (int q = 0; q < js.n; ++q) { js.j[q].in = X[q]; js.j[q].out = W[q]; }
     e = timed(p, PK_ZGEMM, zflop, rw, s, [&] { return zform(true); });
@@ -145,10 +205,10 @@ static ibs_status run_fp64_pipeline_multi(Plan &p, JobSet js, double *const *W, 
     return IBS_OK;
 }
 
-static ibs_status run_fp64_pipeline(Plan &p, JobSet js, double *W, double *X, bool poisson,
-                                    hipStream_t s)
+static ibs_status run_fp64_pipeline(Plan &p, JobSet js, double *W, double *X, const State &st,
+                                    bool poisson, hipStream_t s)
 {
-    return run_fp64_pipeline_multi(p, js, &W, &X, poisson, s);
+    return run_fp64_pipeline_multi(p, js, &W, &X, st, poisson, s);
 }
 
 // Refined path: pass 0 solves A x = b with the split-precision transforms;
@@ -157,14 +217,25 @@ static ibs_status run_fp64_pipeline(Plan &p, JobSet js, double *W, double *X, bo
 // right-hand side (b), the FP64 iterate (x) and three FP32 work fields each:
 // two transform buffers and W3, which holds the first iterate in FP32 when a
 // second pass follows (that pass then writes x = W3 + d).
-static ibs_status run_refined(Plan &p, SplitSet ss, float *const *W1, float *const *W2,
-                              float *const *W3, bool poisson, int passes, hipStream_t s)
+// Every condition a refined launcher would refuse, checked on the host
+// before anything of the call is enqueued.
+static ibs_status check_refined(const Plan &p, int ncomp, int passes, const State &st)
 {
-    hipError_t e;
-    if (passes > max_refine_passes(ss, p)) {
-        set_error("max_iter exceeds the refinement passes this plan's scratch can record");
+    if (passes < 1 || passes > MAX_PASSES) {
+        set_error("refinement passes out of range");
         return IBS_ERR_INVALID_ARG;
     }
+    if ((size_t)(passes > 1 ? passes - 1 : 0) * update_region(p, ncomp) > st.red_count) {
+        set_error("workspace state too small for the refinement passes");
+        return IBS_ERR_WORKSPACE_TOO_SMALL;
+    }
+    return IBS_OK;
+}
+
+static ibs_status run_refined(Plan &p, SplitSet ss, float *const *W1, float *const *W2,
+                              float *const *W3, const State &st, bool poisson, int passes, hipStream_t s)
+{
+    hipError_t e;
     double cells = 0;
     for (int q = 0; q < ss.n; ++q) cells += (double)p.nz * ss.j[q].rows * p.nx;
     // algorithmic flops per cell: 2n for the plain transform, n folded
@@ -191,7 +262,7 @@ static ibs_status run_refined(Plan &p, SplitSet ss, float *const *W1, float *con
         if (pass > 0) {
             for (int q = 0; q < ss.n; ++q) ss.j[q].r = W2[q];
             e = timed(p, PK_RESIDUAL, 10.0 * cells, (xs32 ? 16.0 : 20.0) * cells, s,
-                      [&] { return launch_residual_f32(ss, p, pass, xs32, s); });
+                      [&] { return launch_residual_f32(ss, p, st, pass, xs32, s); });
             if (e != hipSuccess) return hip_fail(e, "residual (refined)");
         }
         for (int q = 0; q < ss.n; ++q) {
@@ -199,39 +270,47 @@ static ibs_status run_refined(Plan &p, SplitSet ss, float *const *W1, float *con
             ss.j[q].out = W1[q];
         }
         e = timed(p, PK_XGEMM_SPLIT, xfl, (pass == 0 ? 12.0 : 8.0) * cells, s,
-                  [&] { return launch_split_xgemm(ss, p, false, pass == 0, 0, pass, s); });
+                  [&] { return launch_split_xgemm(ss, p, st, false, pass == 0, 0, pass, s); });
         if (e != hipSuccess) return hip_fail(e, "x forward (split)");
         for (int q = 0; q < ss.n; ++q) { ss.j[q].in = W1[q]; ss.j[q].out = W2[q]; }
-        e = timed(p, PK_ZGEMM_SPLIT, zfl, 8.0 * cells, s, [&] { return launch_split_zgemm(ss, p, false, pass, s); });
+        e = timed(p, PK_ZGEMM_SPLIT, zfl, 8.0 * cells, s, [&] { return launch_split_zgemm(ss, p, st, false, pass, s); });
         if (e != hipSuccess) return hip_fail(e, "z forward (split)");
         for (int q = 0; q < ss.n; ++q) js.j[q].info = pass == 0 ? info[q] : nullptr;
-        e = timed(p, PK_TRIDIAG_F32, 20.0 * cells, 8.0 * cells, s, [&] { return launch_tridiag_f32(js, p, poisson, pass, s); });
+        e = timed(p, PK_TRIDIAG_F32, 20.0 * cells, 8.0 * cells, s, [&] { return launch_tridiag_f32(js, p, st, poisson, pass, s); });
         if (e != hipSuccess) return hip_fail(e, "tridiagonal (refined)");
         for (int q = 0; q < ss.n; ++q) { ss.j[q].in = W2[q]; ss.j[q].out = W1[q]; }
-        e = timed(p, PK_ZGEMM_SPLIT, zfl, 8.0 * cells, s, [&] { return launch_split_zgemm(ss, p, true, pass, s); });
+        e = timed(p, PK_ZGEMM_SPLIT, zfl, 8.0 * cells, s, [&] { return launch_split_zgemm(ss, p, st, true, pass, s); });
         if (e != hipSuccess) return hip_fail(e, "z inverse (split)");
         for (int q = 0; q < ss.n; ++q) ss.j[q].in = W1[q];
         const int mode = pass == 0 ? (xs32 ? 3 : 1) : (xs32 ? 4 : 2);
         const double ub = mode == 3 ? 8.0 : (mode == 1 ? 12.0 : (mode == 4 ? 16.0 : 20.0));
         e = timed(p, PK_UPDATE, xfl, ub * cells, s,
-                  [&] { return launch_split_xgemm(ss, p, true, false, mode, pass, s); });
+                  [&] { return launch_split_xgemm(ss, p, st, true, false, mode, pass, s); });
         if (e != hipSuccess) return hip_fail(e, "x inverse + update (split)");
-        if (pass >= 1) {
-            e = launch_refine_check(ss, p, pass, s);
+        // a one-pass solve has no error estimate: pass 0's check says so
+        if (pass >= 1 || passes == 1) {
+            e = launch_refine_check(ss, p, st, pass, s);
             if (e != hipSuccess) return hip_fail(e, "refinement check");
         }
     }
     return IBS_OK;
 }
 
-// Upper bound on the passes; the device stops earlier once the predicted
-// error meets tol.  The Helmholtz systems are well conditioned (two passes
-// reach ~1e-13); the pressure problem on large stretched grids may need a
-// third.
-static int default_passes(const Plan &p, bool poisson)
+// Strict compatibility (Poisson): the weighted mean of b against its
+// weighted rms, in FP64 on b itself; partials before the solve, the
+// verdict after it (so that it overrides the status the solve wrote).
+static ibs_status compat_begin(Plan &p, const double *b, const State &st, hipStream_t s)
 {
-    if (p.desc.max_iter > 0) return p.desc.max_iter;
-    return poisson ? 3 : 2;
+    if (!p.desc.strict_compat) return IBS_OK;
+    hipError_t e = launch_compat_partials(p, &b, 1, st, s);
+    return e == hipSuccess ? IBS_OK : hip_fail(e, "compatibility partials");
+}
+static ibs_status compat_end(Plan &p, ibs_solve_info *info, const State &st, hipStream_t s)
+{
+    if (!p.desc.strict_compat) return IBS_OK;
+    void *inf = info;
+    hipError_t e = launch_compat_final(p, &inf, 1, st, s);
+    return e == hipSuccess ? IBS_OK : hip_fail(e, "compatibility check");
 }
 
 }  // namespace ibs
@@ -300,15 +379,22 @@ ibs_status solver_plan_destroy(ibs_plan plan)
 ibs_status solve_poisson(ibs_plan plan, const double *b, double *phi, void *work, size_t work_bytes,
                          ibs_solve_info *info, void *stream)
 {
-    ibs_status st = check_plan(plan);
-    if (st != IBS_OK) return st;
+    ibs_status chk = check_plan(plan);
+    if (chk != IBS_OK) return chk;
     Plan &p = *reinterpret_cast<Plan *>(plan);
     if (!b || !phi || !work) { set_error("b, phi and work must be non-NULL"); return IBS_ERR_INVALID_ARG; }
     if (!aligned32(b) || !aligned32(phi) || !aligned32(work)) { set_error("device arrays must be 32-byte aligned"); return IBS_ERR_INVALID_ARG; }
     if (work_bytes < work_bytes_for(p, IBS_OP_POISSON, 1)) { set_error("workspace too small"); return IBS_ERR_WORKSPACE_TOO_SMALL; }
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const State st = state_in(p, work, IBS_OP_POISSON, 1);
     if (p.desc.precision != IBS_FP64) {
         if (phi == b) { set_error("the refined path needs phi distinct from b"); return IBS_ERR_INVALID_ARG; }
+        ibs_status v = check_refined(p, 1, default_passes(p, true), st);
+        if (v != IBS_OK) return v;
+    }
+    ibs_status r = compat_begin(p, b, st, s);
+    if (r != IBS_OK) return r;
+    if (p.desc.precision != IBS_FP64) {
         SplitSet ss{};
         ss.n = 1;
         ss.j[0].b = b;
@@ -321,7 +407,8 @@ ibs_status solve_poisson(ibs_plan plan, const double *b, double *phi, void *work
         float *W1 = static_cast<float *>(work);
         float *W2 = W1 + field_doubles(p, p.ny);
         float *W3 = W2 + field_doubles(p, p.ny);
-        return run_refined(p, ss, &W1, &W2, &W3, true, default_passes(p, true), s);
+        r = run_refined(p, ss, &W1, &W2, &W3, st, true, default_passes(p, true), s);
+        return r != IBS_OK ? r : compat_end(p, info, st, s);
     }
     double *W = static_cast<double *>(work);
     JobSet js{};
@@ -333,16 +420,16 @@ ibs_status solve_poisson(ibs_plan plan, const double *b, double *phi, void *work
     // x forward: b -> W; z forward: W -> phi; pencils in place on phi;
     // z inverse: phi -> W; x inverse: W -> phi
     js.j[0].in = b; js.j[0].out = W;
-    ibs_status r = run_fp64_pipeline(p, js, W, phi, true, s);
-    return r;
+    r = run_fp64_pipeline(p, js, W, phi, st, true, s);
+    return r != IBS_OK ? r : compat_end(p, info, st, s);
 }
 
 ibs_status solve_helmholtz_batch(ibs_plan plan, int32_t ncomp, const int32_t *comp, const double *c,
                                  const double *const *r, double *const *x, void *work,
                                  size_t work_bytes, ibs_solve_info *info, void *stream)
 {
-    ibs_status st = check_plan(plan);
-    if (st != IBS_OK) return st;
+    ibs_status chk = check_plan(plan);
+    if (chk != IBS_OK) return chk;
     Plan &p = *reinterpret_cast<Plan *>(plan);
     if (ncomp < 1 || ncomp > 3) { set_error("ncomp must be 1..3"); return IBS_ERR_INVALID_ARG; }
     if (!comp || !c || !r || !x || !work) { set_error("comp, c, r, x and work must be non-NULL"); return IBS_ERR_INVALID_ARG; }
@@ -362,6 +449,7 @@ ibs_status solve_helmholtz_batch(ibs_plan plan, int32_t ncomp, const int32_t *co
         js.j[q].info = info ? info + q : nullptr;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const State st = state_in(p, work, IBS_OP_HELMHOLTZ_U, ncomp);
     if (p.desc.precision != IBS_FP64) {
         SplitSet ss{};
         ss.n = ncomp;
@@ -379,28 +467,37 @@ ibs_status solve_helmholtz_batch(ibs_plan plan, int32_t ncomp, const int32_t *co
             W2[q] = W1[q] + stride;
             W3[q] = W2[q] + stride;
         }
-        return run_refined(p, ss, W1, W2, W3, false, default_passes(p, false), s);
+        ibs_status v = check_refined(p, ncomp, default_passes(p, false), st);
+        if (v != IBS_OK) return v;
+        return run_refined(p, ss, W1, W2, W3, st, false, default_passes(p, false), s);
     }
     for (int q = 0; q < ncomp; ++q) { js.j[q].in = r[q]; js.j[q].out = W + q * stride; }
     double *Ws[4], *Xs[4];
     for (int q = 0; q < ncomp; ++q) { Ws[q] = W + q * stride; Xs[q] = x[q]; }
-    return run_fp64_pipeline_multi(p, js, Ws, Xs, false, s);
+    return run_fp64_pipeline_multi(p, js, Ws, Xs, st, false, s);
 }
 
 ibs_status residual(ibs_plan plan, int32_t op, double c, const double *x, const double *b, double *r,
-                    double *norms2, void *stream)
+                    double *norms2, void *work, size_t work_bytes, void *stream)
 {
-    ibs_status st = check_plan(plan);
-    if (st != IBS_OK) return st;
+    ibs_status chk = check_plan(plan);
+    if (chk != IBS_OK) return chk;
     Plan &p = *reinterpret_cast<Plan *>(plan);
     if (op < IBS_OP_POISSON || op > IBS_OP_HELMHOLTZ_W) { set_error("bad op"); return IBS_ERR_INVALID_ARG; }
     if (!x || !b || !r) { set_error("x, b, r must be non-NULL"); return IBS_ERR_INVALID_ARG; }
     if (r == x) { set_error("r may not alias x"); return IBS_ERR_INVALID_ARG; }
     if (!std::isfinite(c)) { set_error("c must be finite"); return IBS_ERR_INVALID_ARG; }
+    double *red = nullptr;
+    if (norms2) {
+        const int wop = op == IBS_OP_POISSON ? IBS_OP_POISSON : IBS_OP_HELMHOLTZ_U;
+        if (!work || !aligned32(work)) { set_error("norms2 needs a 32-byte aligned workspace"); return IBS_ERR_INVALID_ARG; }
+        if (work_bytes < work_bytes_for(p, wop, 1)) { set_error("workspace too small"); return IBS_ERR_WORKSPACE_TOO_SMALL; }
+        red = state_in(p, work, wop, 1).red;
+    }
     const double cells = (double)p.nz * (op == IBS_OP_HELMHOLTZ_V ? p.ny + 1 : p.ny) * p.nx;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = timed(p, PK_RESIDUAL, 10.0 * cells, 24.0 * cells, s,
-                         [&] { return launch_residual(p, op, c, x, b, r, norms2, s); });
+                         [&] { return launch_residual(p, op, c, x, b, r, norms2, red, s); });
     if (e != hipSuccess) return hip_fail(e, "residual");
     return IBS_OK;
 }
@@ -408,8 +505,8 @@ ibs_status residual(ibs_plan plan, int32_t op, double c, const double *x, const 
 ibs_status ibs_divergence(ibs_plan plan, const double *u, const double *v, const double *w, double *b,
                           double scale, void *stream)
 {
-    ibs_status st = check_plan(plan);
-    if (st != IBS_OK) return st;
+    ibs_status chk = check_plan(plan);
+    if (chk != IBS_OK) return chk;
     Plan &p = *reinterpret_cast<Plan *>(plan);
     if (!u || !v || !w || !b) { set_error("u, v, w, b must be non-NULL"); return IBS_ERR_INVALID_ARG; }
     const double cells = (double)p.nz * p.ny * p.nx;
@@ -423,8 +520,8 @@ ibs_status ibs_divergence(ibs_plan plan, const double *u, const double *v, const
 ibs_status ibs_correct(ibs_plan plan, const double *phi, double *u, double *v, double *w, double g,
                        double *pres, const double *lap_phi, double cp, void *stream)
 {
-    ibs_status st = check_plan(plan);
-    if (st != IBS_OK) return st;
+    ibs_status chk = check_plan(plan);
+    if (chk != IBS_OK) return chk;
     Plan &p = *reinterpret_cast<Plan *>(plan);
     if (!phi || !u || !v || !w) { set_error("phi, u, v, w must be non-NULL"); return IBS_ERR_INVALID_ARG; }
     if (pres && cp != 0.0 && !lap_phi) { set_error("lap_phi is required when p != NULL and cp != 0"); return IBS_ERR_INVALID_ARG; }
@@ -472,8 +569,9 @@ ibs_status ibs_autotune_bytes(ibs_plan plan, size_t *bytes)
 }
 
 ibs_status ibs_autotune(ibs_plan plan, void *scratch, size_t scratch_bytes, int32_t *choices,
-                        hipStream_t stream)
+                        void *stream_ptr)
 {
+    hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
     if (!plan || !scratch) { set_error("plan and scratch must be non-NULL"); return IBS_ERR_INVALID_ARG; }
     Plan &p = *reinterpret_cast<Plan *>(plan);
     if (!p.dev_const) { set_error("solver_plan_upload() has not been called"); return IBS_ERR_NOT_UPLOADED; }

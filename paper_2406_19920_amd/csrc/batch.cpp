@@ -3,9 +3,11 @@
 // ibs_batch_build() records every job's launches once (stream capture) into
 // a graph whose independent branches ("lanes") the GPU may run side by
 // side; ibs_batch_launch() replays the whole batch with one hipGraphLaunch.
-// All solves that use the same plan are placed on the same lane (a plan's
-// scratch region is shared by its calls, which therefore must not overlap),
-// and lanes are balanced greedily by the work of their jobs.
+// All solves that use the same workspace are placed on the same lane (the
+// workspace holds a call's fields and mutable state, so calls sharing it
+// must not overlap), and lanes are balanced greedily by the work of their
+// jobs.  The plans' device constants are only read, so jobs of one plan
+// with distinct workspaces may run side by side.
 #include <algorithm>
 #include <map>
 #include <string>
@@ -48,19 +50,21 @@ ibs_status ibs_batch_build(const ibs_batch_job *jobs, int32_t njobs, int32_t nla
         if (j.op != IBS_OP_POISSON && j.op != IBS_OP_HELMHOLTZ_U) { set_error("job op must be IBS_OP_POISSON or IBS_OP_HELMHOLTZ_U"); return IBS_ERR_INVALID_ARG; }
         if (j.op == IBS_OP_HELMHOLTZ_U && (j.ncomp < 1 || j.ncomp > 3)) { set_error("Helmholtz job ncomp must be 1..3"); return IBS_ERR_INVALID_ARG; }
     }
-    // lane per plan, greedy by work (cells x solve count)
-    std::map<ibs_plan, double> cost;
+    // lane per workspace, greedy by work (cells x solve count)
+    std::map<void *, double> cost;
+    std::map<ibs_plan, int> plans;
     for (int q = 0; q < njobs; ++q) {
         Plan *p = reinterpret_cast<Plan *>(jobs[q].plan);
         const double cells = (double)p->nx * p->ny * p->nz;
-        cost[jobs[q].plan] += cells * (jobs[q].op == IBS_OP_POISSON ? 1 : jobs[q].ncomp);
+        cost[jobs[q].work] += cells * (jobs[q].op == IBS_OP_POISSON ? 1 : jobs[q].ncomp);
+        plans[jobs[q].plan] = 1;
     }
-    std::vector<std::pair<double, ibs_plan>> order;
+    std::vector<std::pair<double, void *>> order;
     for (auto &kv : cost) order.push_back({kv.second, kv.first});
-    std::sort(order.begin(), order.end(), [](auto &a, auto &b) { return a.first > b.first; });
+    std::stable_sort(order.begin(), order.end(), [](auto &a, auto &b) { return a.first > b.first; });
     const int L = std::min<int>(nlanes, (int)order.size());
     std::vector<double> load(L, 0.0);
-    std::map<ibs_plan, int> lane_of;
+    std::map<void *, int> lane_of;
     for (auto &o : order) {
         int best = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         lane_of[o.second] = best;
@@ -74,7 +78,7 @@ ibs_status ibs_batch_build(const ibs_batch_job *jobs, int32_t njobs, int32_t nla
     ibs_status st = IBS_OK;
     ibs_batch_s *b = new ibs_batch_s();
     std::vector<std::pair<ibs_plan, bool>> suspended;
-    for (auto &kv : cost) {
+    for (auto &kv : plans) {
         bool was = false;
         profile_suspend(kv.first, &was);
         suspended.push_back({kv.first, was});
@@ -95,7 +99,7 @@ ibs_status ibs_batch_build(const ibs_batch_job *jobs, int32_t njobs, int32_t nla
     for (int l = 0; l < L; ++l) hipStreamWaitEvent(lanes[l], evs[L], 0);
     for (int q = 0; q < njobs && st == IBS_OK; ++q) {
         const ibs_batch_job &j = jobs[q];
-        hipStream_t s = lanes[lane_of[j.plan]];
+        hipStream_t s = lanes[lane_of[j.work]];
         if (j.op == IBS_OP_POISSON) {
             st = solve_poisson(j.plan, j.rhs[0], j.x[0], j.work, j.work_bytes, j.info, s);
         } else {

@@ -32,12 +32,26 @@ struct BlobLayout {
     size_t sz_fwd, sz_inv;   // z transform, bf16x3 split, A-operand swizzle (nz % 64 != 0)
     size_t sxf_fwd, sxf_inv; // folded x transform factors, bf16x3 split (nx % 64 == 0)
     size_t szf_fwd, szf_inv; // folded z transform factors, bf16x3 split (nz % 64 == 0)
-    size_t bmean;            // per-job weighted mean of the Poisson rhs (4 doubles)
-    size_t xsum;             // per-job partial sums of Delta_j x (XSUM_SLOTS each)
-    size_t done;             // per-job refinement stop flags (4 ints)
-    size_t red;              // reduction scratch (doubles)
-    size_t red_count;        // number of doubles in the reduction scratch
     size_t total;
+};
+
+// Per-call mutable state of a solve, kept in the caller's workspace after
+// the work fields (the plan's device blob is read-only once uploaded, so
+// calls on one plan may run concurrently on different streams when each
+// brings its own workspace).
+constexpr int STATE_JOBS = 4;        // jobs (components) per call
+constexpr int XSUM_SLOTS = 4096;     // max residual blocks per job (fixed order: deterministic sums)
+constexpr int COMPAT_SLOTS = 2048;   // max blocks of the compatibility reduction
+constexpr int RESID_SLOTS = 4096;    // max blocks of the residual() norm reduction
+constexpr int MAX_PASSES = 8;        // most refinement passes a solve may take (max_iter)
+struct State {
+    double *bmean = nullptr;   // per job: weighted mean of the Poisson rhs
+    double *xsum = nullptr;    // per job: partial sums of Delta_j x (XSUM_SLOTS each)
+    int *done = nullptr;       // per job: refinement stop flags
+    int *incompat = nullptr;   // per job: strict compatibility check failed
+    double *compat = nullptr;  // compatibility partials (2 per block)
+    double *red = nullptr;     // refinement update partials, then residual() partials
+    size_t red_count = 0;      // doubles in red
 };
 
 // Kernel classes for the optional live profile (HIP events around launches).
@@ -113,6 +127,11 @@ struct JobSet {
 // Error reporting
 void set_error(const std::string &msg);
 
+// Workspace of one solve call: the work fields and the state after them.
+size_t field_bytes_for(const Plan &p, int op, int ncomp);
+size_t state_bytes_for(const Plan &p, int op, int ncomp);
+State state_in(const Plan &p, void *work, int op, int ncomp);
+
 // ---- kernel launchers (return hipError_t of the launch) --------------------
 // C[M x N] = A[M x K] * Bs, A row-major (lda), Bs the swizzled K x N matrix;
 // batched over the jobs of js (A = js.j[q].in, C = js.j[q].out, M = nz*rows).
@@ -131,7 +150,7 @@ hipError_t launch_zgemm_f64(const JobSet &js, int M, int K, int nx,
                             const double *as, hipStream_t s);
 // Tridiagonal pencils along y, in place on js.j[q].out ([nz][rows][nx]).
 // poisson: pressure operator (pin + weighted-mean handling of pencil 0,0).
-hipError_t launch_tridiag_f64(const JobSet &js, const Plan &p, bool poisson,
+hipError_t launch_tridiag_f64(const JobSet &js, const Plan &p, const State &st, bool poisson,
                               hipStream_t s);
 hipError_t launch_divergence(const Plan &p, const double *u, const double *v,
                              const double *w, double *b, double scale, hipStream_t s);
@@ -139,10 +158,17 @@ hipError_t launch_correct(const Plan &p, const double *phi, double *u, double *v
                           double *w, double g, double *pr, const double *lap,
                           double cp, hipStream_t s);
 hipError_t launch_residual(const Plan &p, int op, double c, const double *x,
-                           const double *b, double *r, double *norms2, hipStream_t s);
+                           const double *b, double *r, double *norms2, double *red, hipStream_t s);
+// Strict compatibility check of a Poisson rhs in FP64 (weighted mean against
+// weighted rms, on b itself): partial sums, then the verdict per job, which
+// sets st.incompat and, through the job's report, IBS_ERR_INCOMPATIBLE_RHS.
+hipError_t launch_compat_partials(const Plan &p, const double *const *b, int njobs, const State &st,
+                                  hipStream_t s);
+hipError_t launch_compat_final(const Plan &p, void *const *info, int njobs, const State &st,
+                               hipStream_t s);
+int compat_blocks(const Plan &p);
 
 // ---- refined (split-precision) path ---------------------------------------
-constexpr int XSUM_SLOTS = 4096;   // max residual blocks per job (fixed order: deterministic sums)
 struct SplitJob {
     const void *in;     // x transforms: FP64 (first pass) or FP32 input rows
     float *out;         // FP32 output (forward passes, z passes)
@@ -166,18 +192,23 @@ struct SplitSet {
 // result in FP32; 4: x = xs (FP32) + result with norm partials.
 // pass: refinement pass of an update (mode 2), selecting its partial-sum region.
 // Kernels of pass >= 2 return at once for jobs whose stop flag is set.
-hipError_t launch_split_xgemm(const SplitSet &ss, const Plan &p, bool inverse, bool in64, int mode,
-                              int pass, hipStream_t s);
-int max_refine_passes(const SplitSet &ss, const Plan &p);
-hipError_t launch_split_zgemm(const SplitSet &ss, const Plan &p, bool inverse, int pass, hipStream_t s);
+hipError_t launch_split_xgemm(const SplitSet &ss, const Plan &p, const State &st, bool inverse, bool in64,
+                              int mode, int pass, hipStream_t s);
+// Doubles of update partials one refinement pass of ncomp jobs writes.
+size_t update_region(const Plan &p, int ncomp);
+hipError_t launch_split_zgemm(const SplitSet &ss, const Plan &p, const State &st, bool inverse, int pass,
+                              hipStream_t s);
 // pass: refinement pass (0 records the rhs mean; later passes steer the
 // Poisson correction so that x + d has zero weighted mean)
-hipError_t launch_tridiag_f32(const JobSet &js, const Plan &p, bool poisson, int pass, hipStream_t s);
+hipError_t launch_tridiag_f32(const JobSet &js, const Plan &p, const State &st, bool poisson, int pass,
+                              hipStream_t s);
 // x32: the stored iterate xs is FP32 (else FP64)
-hipError_t launch_residual_f32(const SplitSet &ss, const Plan &p, int pass, bool x32, hipStream_t s);
+hipError_t launch_residual_f32(const SplitSet &ss, const Plan &p, const State &st, int pass, bool x32,
+                               hipStream_t s);
 int residual_tiles(const Plan &p);   // residual blocks (x-sum partials) per job
 // After pass >= 1: predict the error, write the report, set the stop flag.
-hipError_t launch_refine_check(const SplitSet &ss, const Plan &p, int pass, hipStream_t s);
+// pass 0 (a one-pass solve): no estimate exists; the report says so.
+hipError_t launch_refine_check(const SplitSet &ss, const Plan &p, const State &st, int pass, hipStream_t s);
 
 inline const double *blob_ptr(const Plan &p, size_t off) {
     return reinterpret_cast<const double *>(static_cast<const unsigned char *>(p.dev_const) + off);

@@ -1137,8 +1137,23 @@ __global__ __launch_bounds__(256) void refine_check_kernel(SplitSet ss, const do
                                                            int *__restrict__ done)
 {
     const int job = blockIdx.x;
-    if (pass >= 2 && done[job]) return;     // stopped earlier: report stands
     const SplitJob &jb = ss.j[job];
+    if (pass == 0) {
+        // one pass only: no correction was measured, so no error estimate
+        // exists; the report says NOT_CONVERGED with unknown (NaN) error
+        if (threadIdx.x == 0) {
+            done[job] = 0;
+            if (jb.info) {
+                ibs_solve_info *inf = static_cast<ibs_solve_info *>(jb.info);
+                inf->iters = 1;
+                inf->rel_correction = __builtin_nan("");
+                inf->rel_residual = __builtin_nan("");
+                if (inf->status == IBS_OK) inf->status = IBS_ERR_NOT_CONVERGED;
+            }
+        }
+        return;
+    }
+    if (pass >= 2 && done[job]) return;     // stopped earlier: report stands
     const size_t off = (size_t)job * slots_per_job * 2;
     const double2 last = sum_pairs(red_last + off, slots_per_job);
     double rprev = 1.0;
@@ -1259,21 +1274,17 @@ static void launch_x_nb(const SplitSet &ss, const Plan &p, const b8 *qs, double 
 
 static size_t update_slots(const SplitSet &ss, const Plan &p);
 
-hipError_t launch_split_xgemm(const SplitSet &ss, const Plan &p, bool inverse, bool in64, int mode,
-                              int pass, hipStream_t s)
+hipError_t launch_split_xgemm(const SplitSet &ss, const Plan &p, const State &st, bool inverse, bool in64,
+                              int mode, int pass, hipStream_t s)
 {
-    const int *skip = pass >= 2 ? reinterpret_cast<const int *>(blob_ptr(p, p.lay.done)) : nullptr;
+    // the caller (run_refined) has checked the mode, pass and state size
+    const int *skip = pass >= 2 ? st.done : nullptr;
     dim3 grid;
     xgemm_grid(ss, p, grid);
     // each refinement pass keeps its update partials in a region of its own
-    const size_t slots = (size_t)grid.x * grid.y * grid.z * UPD_WAVES;
-    const size_t region = 2 * slots;
+    const size_t region = update_region(p, ss.n);
     const bool upd = mode == 2 || mode == 4;
-    if (mode < 0 || mode > 4) return hipErrorInvalidValue;
-    if (upd && (pass < 1 || (size_t)pass * region > p.lay.red_count)) return hipErrorInvalidValue;
-    double *red = blob_mut(p, p.lay.red) + (upd ? (size_t)(pass - 1) * region : 0);
-    if (in64 && mode != 0) return hipErrorInvalidValue;
-    if (inverse != (mode != 0)) return hipErrorInvalidValue;   // forward: FP32 out; inverse: iterate
+    double *red = st.red + (upd ? (size_t)(pass - 1) * region : 0);
     if (can_fold_split(p.nx)) {
         const b8 *qs = reinterpret_cast<const b8 *>(blob_ptr(p, inverse ? p.lay.sxf_inv : p.lay.sxf_fwd));
         switch (in64 ? -1 : mode) {
@@ -1322,9 +1333,10 @@ static void launch_zf(const SplitSet &ss, const Plan &p, bool inverse, const b8 
     else launch_zf_dir<HBT, WN, false>(ss, p, qs, skip, s);
 }
 
-hipError_t launch_split_zgemm(const SplitSet &ss, const Plan &p, bool inverse, int pass, hipStream_t s)
+hipError_t launch_split_zgemm(const SplitSet &ss, const Plan &p, const State &st, bool inverse, int pass,
+                              hipStream_t s)
 {
-    const int *skip = pass >= 2 ? reinterpret_cast<const int *>(blob_ptr(p, p.lay.done)) : nullptr;
+    const int *skip = pass >= 2 ? st.done : nullptr;
     if (can_fold_split(p.nz)) {
         // folded: HBT 16-blocks per factor (HB = nz/32), WN column blocks per wave
         const b8 *qs = reinterpret_cast<const b8 *>(blob_ptr(p, inverse ? p.lay.szf_inv : p.lay.szf_fwd));
@@ -1372,46 +1384,49 @@ int residual_tiles(const Plan &p)
     return t;
 }
 
-hipError_t launch_residual_f32(const SplitSet &ss, const Plan &p, int pass, bool x32, hipStream_t s)
+hipError_t launch_residual_f32(const SplitSet &ss, const Plan &p, const State &st, int pass, bool x32,
+                               hipStream_t s)
 {
-    const int *skip = pass >= 2 ? reinterpret_cast<const int *>(blob_ptr(p, p.lay.done)) : nullptr;
+    // the tiling fits XSUM_SLOTS and nx / 4 <= 256 threads per row for
+    // every grid the refined plan accepts (nx % 32 == 0, nx <= 512; checked
+    // when the plan is built)
+    const int *skip = pass >= 2 ? st.done : nullptr;
     int rb_rows, tiles_y, rz, tiles;
     residual_tiling(p, rb_rows, tiles_y, rz, tiles);
-    if (tiles > XSUM_SLOTS || p.nx % 4 || p.nx / 4 > 256) return hipErrorInvalidValue;
     dim3 grid(tiles, ss.n);
     auto go = [&](auto kernel) {
         hipLaunchKernelGGL(kernel, grid, dim3(256), 0, s, ss, p.nx, p.ny, p.nz, 1.0 / (p.hx * p.hx),
                            1.0 / (p.hz * p.hz), blob_ptr(p, p.lay.dyc), blob_ptr(p, p.lay.dyf),
-                           blob_ptr(p, p.lay.bmean), blob_mut(p, p.lay.xsum), skip, rb_rows, tiles_y, rz);
+                           st.bmean, st.xsum, skip, rb_rows, tiles_y, rz);
     };
     if (x32) go(residual_f32_kernel<float>);
     else go(residual_f32_kernel<double>);
     return hipGetLastError();
 }
 
-static size_t update_slots(const SplitSet &ss, const Plan &p)
+// Rows of the transform tiling are those of every component (ny; the v
+// component's first wall row is left out), so the update partials depend
+// only on the grid and the component count.
+size_t update_region(const Plan &p, int ncomp)
 {
+    SplitSet ss{};
+    ss.n = ncomp;
+    for (int q = 0; q < ncomp; ++q) { ss.j[q].rows = p.ny; ss.j[q].kind = KIND_C; }
     dim3 grid;
     xgemm_grid(ss, p, grid);
-    return (size_t)grid.x * grid.y * grid.z;
+    return 2 * (size_t)grid.x * grid.y * grid.z * UPD_WAVES;
 }
 
-int max_refine_passes(const SplitSet &ss, const Plan &p)
-{
-    return (int)(p.lay.red_count / (2 * update_slots(ss, p) * UPD_WAVES)) + 1;
-}
-
-hipError_t launch_refine_check(const SplitSet &ss, const Plan &p, int pass, hipStream_t s)
+hipError_t launch_refine_check(const SplitSet &ss, const Plan &p, const State &st, int pass, hipStream_t s)
 {
     dim3 grid;
     xgemm_grid(ss, p, grid);
     const int per_job = (int)(grid.x * grid.y) * UPD_WAVES;
-    const size_t region = 2 * (size_t)grid.x * grid.y * grid.z * UPD_WAVES;
-    const double *red = blob_ptr(p, p.lay.red);
-    const double *last = red + (size_t)(pass - 1) * region;
-    const double *prev = pass >= 2 ? red + (size_t)(pass - 2) * region : nullptr;
+    const size_t region = update_region(p, ss.n);
+    const double *last = pass >= 1 ? st.red + (size_t)(pass - 1) * region : nullptr;
+    const double *prev = pass >= 2 ? st.red + (size_t)(pass - 2) * region : nullptr;
     hipLaunchKernelGGL(refine_check_kernel, dim3(ss.n), dim3(256), 0, s, ss, last, prev, per_job,
-                       pass, p.desc.tol, reinterpret_cast<int *>(blob_mut(p, p.lay.done)));
+                       pass, p.desc.tol, st.done);
     return hipGetLastError();
 }
 

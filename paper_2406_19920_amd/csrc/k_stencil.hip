@@ -198,18 +198,113 @@ hipError_t launch_correct(const Plan &p, const double *phi, double *u, double *v
 }
 
 hipError_t launch_residual(const Plan &p, int op, double c, const double *x, const double *b,
-                           double *r, double *norms2, hipStream_t s)
+                           double *r, double *norms2, double *red, hipStream_t s)
 {
     Geo g = geo_of(p);
     const int rows = (op == IBS_OP_HELMHOLTZ_V) ? p.ny + 1 : p.ny;
     const int nrow = rows * p.nz;
-    const int cap = (int)(p.lay.red_count / 2);
-    const int nblk = nrow < cap ? nrow : cap;
-    double *red = norms2 ? blob_mut(p, p.lay.red) : nullptr;
+    const int nblk = nrow < RESID_SLOTS ? nrow : RESID_SLOTS;
+    if (!norms2) red = nullptr;
     hipLaunchKernelGGL(residual_kernel, dim3(nblk), dim3(256), 0, s, g, op, c, x, b, r, red);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !norms2) return e;
     hipLaunchKernelGGL(reduce_pairs_kernel, dim3(1), dim3(256), 0, s, red, nblk, norms2);
+    return hipGetLastError();
+}
+
+// Strict compatibility, first stage: block q of job j walks the cell rows
+// (j, k) = q, q + G, ... (fixed order) and writes its partial sums of
+// Delta_j b and Delta_j b^2 to part[2 (j * G + q) ..].
+__global__ __launch_bounds__(256) void compat_partials_kernel(Geo g, const double *__restrict__ b0,
+                                                              const double *__restrict__ b1,
+                                                              const double *__restrict__ b2,
+                                                              const double *__restrict__ b3,
+                                                              double *__restrict__ part)
+{
+    __shared__ double sm[8];
+    const int job = blockIdx.y;
+    const double *__restrict__ b = job == 0 ? b0 : job == 1 ? b1 : job == 2 ? b2 : b3;
+    const int nrow = g.ny * g.nz;
+    double s1 = 0.0, s2 = 0.0;
+    for (int rw = blockIdx.x; rw < nrow; rw += gridDim.x) {
+        const int j = rw % g.ny;
+        const double w = g.dyc[j];
+        const double *row = b + (size_t)rw * g.nx;
+        for (int i = threadIdx.x; i < g.nx; i += blockDim.x) {
+            const double v = row[i];
+            s1 += w * v;
+            s2 += w * v * v;
+        }
+    }
+    const double t1 = block_sum(s1, sm);
+    __syncthreads();
+    const double t2 = block_sum(s2, sm);
+    if (threadIdx.x == 0) {
+        const size_t slot = (size_t)job * gridDim.x + blockIdx.x;
+        part[2 * slot] = t1;
+        part[2 * slot + 1] = t2;
+    }
+}
+
+// Second stage, one block per job: mean = sum(W b) / sum(W), rms =
+// sqrt(sum(W b^2) / sum(W)); the rhs is incompatible when |mean| > 1e-10
+// rms (a compatible rhs, such as the divergence of a field with no wall
+// flux, has a mean at rounding level, ~1e-16 rms).  The verdict is kept in
+// incompat[job] and overrides the status of the job's report.
+__global__ __launch_bounds__(256) void compat_final_kernel(Geo g, const double *__restrict__ part,
+                                                           int nblk, void *info0, void *info1,
+                                                           void *info2, void *info3,
+                                                           int *__restrict__ incompat)
+{
+    __shared__ double sm[8];
+    const int job = blockIdx.x;
+    double a = 0.0, c = 0.0;
+    for (int q = threadIdx.x; q < nblk; q += blockDim.x) {
+        a += part[2 * ((size_t)job * nblk + q)];
+        c += part[2 * ((size_t)job * nblk + q) + 1];
+    }
+    const double s1 = block_sum(a, sm);
+    __syncthreads();
+    const double s2 = block_sum(c, sm);
+    if (threadIdx.x == 0) {
+        double wsum = 0.0;
+        for (int j = 0; j < g.ny; ++j) wsum += g.dyc[j];
+        wsum *= (double)g.nx * (double)g.nz;
+        const double mean = s1 / wsum;
+        const double rms = sqrt(fmax(s2 / wsum, 0.0));
+        const bool bad = fabs(mean) > 1e-10 * rms;
+        incompat[job] = bad ? 1 : 0;
+        void *info = job == 0 ? info0 : job == 1 ? info1 : job == 2 ? info2 : info3;
+        if (bad && info) static_cast<ibs_solve_info *>(info)->status = IBS_ERR_INCOMPATIBLE_RHS;
+    }
+}
+
+int compat_blocks(const Plan &p)
+{
+    const int nrow = p.ny * p.nz;
+    return nrow < COMPAT_SLOTS ? nrow : COMPAT_SLOTS;
+}
+
+hipError_t launch_compat_partials(const Plan &p, const double *const *b, int njobs, const State &st,
+                                  hipStream_t s)
+{
+    if (njobs < 1 || njobs > STATE_JOBS || (size_t)njobs * compat_blocks(p) > COMPAT_SLOTS)
+        return hipErrorInvalidValue;
+    Geo g = geo_of(p);
+    const double *bb[4] = {b[0], njobs > 1 ? b[1] : b[0], njobs > 2 ? b[2] : b[0], njobs > 3 ? b[3] : b[0]};
+    hipLaunchKernelGGL(compat_partials_kernel, dim3(compat_blocks(p), njobs), dim3(256), 0, s, g, bb[0],
+                       bb[1], bb[2], bb[3], st.compat);
+    return hipGetLastError();
+}
+
+hipError_t launch_compat_final(const Plan &p, void *const *info, int njobs, const State &st, hipStream_t s)
+{
+    if (njobs < 1 || njobs > STATE_JOBS) return hipErrorInvalidValue;
+    Geo g = geo_of(p);
+    void *in[4] = {info[0], njobs > 1 ? info[1] : nullptr, njobs > 2 ? info[2] : nullptr,
+                   njobs > 3 ? info[3] : nullptr};
+    hipLaunchKernelGGL(compat_final_kernel, dim3(njobs), dim3(256), 0, s, g, st.compat, compat_blocks(p),
+                       in[0], in[1], in[2], in[3], st.incompat);
     return hipGetLastError();
 }
 

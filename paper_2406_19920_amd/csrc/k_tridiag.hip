@@ -97,7 +97,6 @@ struct TriParams {
     double wsum_y;      // sum of Delta_j
     int nx, nz;
     int poisson;
-    int strict;
     double inv_sqrt_nxnz;
 };
 
@@ -227,24 +226,21 @@ __global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
 #pragma unroll
             for (int t = 0; t < M; ++t) r[t] = sx[(k * MS + t) * LDR + p];
 
-            R removed = 0.0, rms = 0.0;
+            R removed = 0.0;
             if (pinned) {
                 // compatibility: remove the volume-weighted mean of this pencil's rhs
-                R swr = 0.0, sww = 0.0, swrr = 0.0;
+                R swr = 0.0, sww = 0.0;
 #pragma unroll
                 for (int t = 0; t < M; ++t) {
                     swr += sw[k * MS + t] * r[t];
                     sww += sw[k * MS + t];
-                    swrr += sw[k * MS + t] * r[t] * r[t];
                 }
 #pragma unroll
                 for (int d = 1; d < P; d <<= 1) {
                     swr += __shfl_xor(swr, d, P);
                     sww += __shfl_xor(sww, d, P);
-                    swrr += __shfl_xor(swrr, d, P);
                 }
                 const R mean = swr / sww;
-                rms = sqrt(fmax(swrr / sww, 0.0));
                 removed = mean;
 #pragma unroll
                 for (int t = 0; t < M; ++t)
@@ -366,9 +362,8 @@ __global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
             if (a0 == 0 && c == 0 && tid == 0 && jb.info) {
                 ibs_solve_info *inf = static_cast<ibs_solve_info *>(jb.info);
                 const double rm = removed * tp.inv_sqrt_nxnz;
-                const bool bad = pois && tp.strict && fabs(removed) > 1e-10 * rms;
                 inf->iters = 1;
-                inf->status = bad ? IBS_ERR_INCOMPATIBLE_RHS : IBS_OK;
+                inf->status = IBS_OK;
                 inf->rel_residual = 0.0;
                 inf->rel_correction = 0.0;
                 inf->removed_mean = pois ? rm : 0.0;
@@ -468,7 +463,8 @@ static double helmholtz_kappa(const JobSet &js, const Plan &p)
 }
 
 template <typename T>
-static hipError_t launch_tridiag(const JobSet &js, const Plan &p, bool poisson, int pass, hipStream_t s)
+static hipError_t launch_tridiag(const JobSet &js, const Plan &p, const State &st, bool poisson, int pass,
+                                 hipStream_t s)
 {
     TriParams tp;
     tp.lam_x = blob_ptr(p, p.lay.lam_x);
@@ -479,7 +475,7 @@ static hipError_t launch_tridiag(const JobSet &js, const Plan &p, bool poisson, 
         tp.up[kd] = blob_ptr(p, p.lay.up[kd]);
     }
     tp.wy = blob_ptr(p, p.lay.wy);
-    tp.bmean = blob_mut(p, p.lay.bmean);
+    tp.bmean = st.bmean;
     tp.xsum = nullptr;
     tp.record_mean = 1;
     tp.skip = nullptr;
@@ -488,13 +484,12 @@ static hipError_t launch_tridiag(const JobSet &js, const Plan &p, bool poisson, 
     tp.nx = p.nx;
     tp.nz = p.nz;
     tp.poisson = poisson ? 1 : 0;
-    tp.strict = p.desc.strict_compat ? 1 : 0;
     tp.nxsum = residual_tiles(p);
     if (pass > 0) {
         tp.record_mean = 0;
-        tp.xsum = blob_ptr(p, p.lay.xsum);
+        tp.xsum = st.xsum;
     }
-    if (pass >= 2) tp.skip = reinterpret_cast<const int *>(blob_ptr(p, p.lay.done));
+    if (pass >= 2) tp.skip = st.done;
     tp.inv_sqrt_nxnz = 1.0 / std::sqrt((double)p.nx * (double)p.nz);
     int n = 0;
     for (int q = 0; q < js.n; ++q) {
@@ -510,14 +505,15 @@ static hipError_t launch_tridiag(const JobSet &js, const Plan &p, bool poisson, 
     return launch_by_rows<T, double>(js, tp, n, s);
 }
 
-hipError_t launch_tridiag_f64(const JobSet &js, const Plan &p, bool poisson, hipStream_t s)
+hipError_t launch_tridiag_f64(const JobSet &js, const Plan &p, const State &st, bool poisson, hipStream_t s)
 {
-    return launch_tridiag<double>(js, p, poisson, 0, s);
+    return launch_tridiag<double>(js, p, st, poisson, 0, s);
 }
 
-hipError_t launch_tridiag_f32(const JobSet &js, const Plan &p, bool poisson, int pass, hipStream_t s)
+hipError_t launch_tridiag_f32(const JobSet &js, const Plan &p, const State &st, bool poisson, int pass,
+                              hipStream_t s)
 {
-    return launch_tridiag<float>(js, p, poisson, pass, s);
+    return launch_tridiag<float>(js, p, st, poisson, pass, s);
 }
 
 }  // namespace ibs

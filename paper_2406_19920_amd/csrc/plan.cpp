@@ -328,6 +328,19 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
         set_error("unknown precision");
         return IBS_ERR_INVALID_ARG;
     }
+    if (d.precision == IBS_REFINED_FP16X2 || d.precision == IBS_REFINED_AUTO) {
+        set_error("only the bfloat16x3 split scheme is built (IBS_REFINED_BF16X3); "
+                  "IBS_REFINED_FP16X2 and IBS_REFINED_AUTO are not served");
+        return IBS_ERR_UNSUPPORTED;
+    }
+    if (d.max_iter < 0 || d.max_iter > MAX_PASSES) {
+        set_error("max_iter must be in [0, " + std::to_string(MAX_PASSES) + "]");
+        return IBS_ERR_INVALID_ARG;
+    }
+    if (!(d.tol >= 0.0) && !(d.tol <= 0.0)) {
+        set_error("tol must not be NaN");
+        return IBS_ERR_INVALID_ARG;
+    }
     if (d.precision != IBS_FP64 && (d.nx % 32 || d.nz % 32 || d.nx > 512 || d.nz > 512)) {
         set_error("the refined path needs nx and nz to be multiples of 32, at most 512");
         return IBS_ERR_UNSUPPORTED;
@@ -452,11 +465,6 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     L.sxf_inv = take(sfold_x ? sizeof(uint16_t) * 3 * 2 * hx2 : 0);
     L.szf_fwd = take(sfold_z ? sizeof(uint16_t) * 3 * 2 * hz2 : 0);
     L.szf_inv = take(sfold_z ? sizeof(uint16_t) * 3 * 2 * hz2 : 0);
-    L.bmean = take(sizeof(double) * 4);
-    L.xsum = take(sizeof(double) * 4 * XSUM_SLOTS);
-    L.done = take(sizeof(int) * 4);
-    L.red_count = 524288;   // update partials: per wave, per tile, per refinement pass
-    L.red = take(sizeof(double) * L.red_count);
     L.total = o;
     p->blob.assign(L.total, 0);
     auto put = [&](size_t off, const double *src, size_t n) {

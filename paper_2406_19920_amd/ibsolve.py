@@ -88,7 +88,7 @@ def _load():
     L.solve_poisson.argtypes = [vp, vp, vp, vp, sz, vp, vp]
     L.solve_helmholtz_batch.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl),
                                         ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz, vp, vp]
-    L.residual.argtypes = [vp, i32, dbl, vp, vp, vp, vp, vp]
+    L.residual.argtypes = [vp, i32, dbl, vp, vp, vp, vp, vp, sz, vp]
     L.ibs_divergence.argtypes = [vp, vp, vp, vp, vp, dbl, vp]
     L.ibs_correct.argtypes = [vp, vp, vp, vp, vp, dbl, vp, vp, dbl, vp]
     L.ibs_plan_export.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(sz)]
@@ -178,8 +178,8 @@ def solve_helmholtz_batch(plan, comps, cs, rs, xs, work, work_bytes, info, strea
            "solve_helmholtz_batch")
 
 
-def residual(plan, op, c, x, b, r, norms2, stream):
-    _check(lib.residual(plan, op, c, x, b, r, norms2, stream), "residual")
+def residual(plan, op, c, x, b, r, norms2, work, work_bytes, stream):
+    _check(lib.residual(plan, op, c, x, b, r, norms2, work, work_bytes, stream), "residual")
 
 
 def ibs_divergence(plan, u, v, w, b, scale, stream):
@@ -319,7 +319,8 @@ class Solver:
         r = self.empty(op) if r is None else r
         n2 = self.torch.zeros(2, dtype=self.torch.float64, device=self.device) if norms else None
         residual(self.plan, op, c, x.data_ptr(), b.data_ptr(), r.data_ptr(),
-                 n2.data_ptr() if n2 is not None else None, self.stream())
+                 n2.data_ptr() if n2 is not None else None, self.work.data_ptr(),
+                 self.work_bytes, self.stream())
         return (r, n2) if norms else r
 
     def divergence(self, u, v, w, scale=1.0, b=None):

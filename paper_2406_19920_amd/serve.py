@@ -4,11 +4,15 @@ Requests (one pressure Poisson solve, or the three Helmholtz components of
 one fractional step) arrive over time.  The loop admits a waiting request as
 soon as a slot is free and the device memory it needs fits the HBM budget,
 so requests that arrive while others are on the GPU start immediately and
-overlap with them (one HIP stream per slot).  Plans (eigenvector tables and
-workspace) stay resident in an LRU cache keyed by (grid, stretching,
-precision) and count against the budget; fields are allocated per request
-and released on completion.  Completion is detected by polling per-request
-events; latency runs from arrival to completion.
+overlap with them (one HIP stream and one workspace per slot).  Plans
+(eigenvector tables) stay resident in an LRU cache keyed by (grid,
+stretching, precision) and count against the budget; a plan's device
+constants are only read, so requests on the same grid run side by side.
+Fields are allocated per request and released on completion.  A request
+that does not fit yet is passed over by later ones that do, at most
+`max_bypass` times in a row, after which admission waits for it (no
+starvation).  Completion is detected by polling per-request events; latency
+runs from arrival to completion.
 
 The scheduler talks to an executor.  GpuExecutor drives the C ABI (every
 solve step runs in the library's HIP kernels); tests substitute a fake
@@ -51,11 +55,22 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
         # one workspace per slot, sized for the largest request (a plan then
         # holds only its constants; the workspace is needed only while a
-        # request runs, and a slot runs one request at a time): a Helmholtz
-        # batch of 3 components on the refined path, 12 bytes per cell each
-        self.work_bytes = 3 * 12 * nmax * (nmax + 1) * nmax
+        # request runs, and a slot runs one request at a time): the larger of
+        # the two precisions' Helmholtz batch of 3 components at nmax
+        need = 0
+        for prec in (ibsolve.IBS_FP64, ibsolve.IBS_REFINED_BF16X3):
+            pl = ibsolve.solver_plan(ibsolve.make_desc(nmax, nmax, nmax, precision=prec))
+            try:
+                for op, nc in ((ibsolve.IBS_OP_POISSON, 1), (ibsolve.IBS_OP_HELMHOLTZ_U, 3)):
+                    need = max(need, ibsolve.solver_plan_bytes(pl, op, nc)[1])
+            finally:
+                ibsolve.solver_plan_destroy(pl)
+        self.work_bytes = need
         self.slot_work = [torch.empty(self.work_bytes, dtype=torch.uint8, device=self.device)
                           for _ in range(slots)]
+        # device bytes held for the executor's lifetime (counted against the
+        # serving budget)
+        self.fixed_bytes = slots * need
 
     def prepare(self, req):
         """Host-only plan build (thread-safe; the C call releases the GIL).
@@ -128,15 +143,16 @@ class GpuExecutor:
 
 
 class PlanCache:
-    """LRU cache of resident plans.  A cached plan is lent to one request at
-    a time (its workspace and scratch are single-use).  Host-side plan
-    builds for waiting requests run ahead on a worker pool."""
+    """LRU cache of resident plans.  A cached plan may serve several
+    requests at once (each brings its slot's workspace); plans in use are
+    never evicted.  Host-side plan builds for waiting requests run ahead on
+    a worker pool."""
 
     def __init__(self, executor, capacity_bytes: int, workers: int = 4):
         self.ex = executor
         self.capacity = capacity_bytes
         self.items = collections.OrderedDict()   # key -> solver
-        self.busy = set()
+        self.refs = collections.Counter()        # key -> requests in flight
         self.bytes = 0
         self.hits = 0
         self.misses = 0
@@ -160,16 +176,14 @@ class PlanCache:
         k = plan_key(req)
         S = self.items.get(k)
         if S is not None:
-            if k in self.busy:
-                return None, 0
             self.items.move_to_end(k)
-            self.busy.add(k)
+            self.refs[k] += 1
             self.hits += 1
             return S, 0
         prepared = self._prepared(req)
         need = prepared[1]
         while self.bytes + need > self.capacity or need > budget_left:
-            victim = next((kk for kk in self.items if kk not in self.busy), None)
+            victim = next((kk for kk in self.items if self.refs[kk] == 0), None)
             if victim is None:
                 self.futures[k] = _Done(prepared)     # keep it for the next attempt
                 return None, 0
@@ -180,14 +194,17 @@ class PlanCache:
             self.ex.close_solver(old)
         S = self.ex.make_solver(req, prepared)
         self.items[k] = S
-        self.busy.add(k)
+        self.refs[k] += 1
         nb = self.ex.solver_bytes(S)
         self.bytes += nb
         self.misses += 1
         return S, nb
 
     def release(self, req):
-        self.busy.discard(plan_key(req))
+        k = plan_key(req)
+        self.refs[k] -= 1
+        if self.refs[k] <= 0:
+            del self.refs[k]
 
     def close(self):
         for S in self.items.values():
@@ -247,7 +264,10 @@ class ServeResult:
 
 class Server:
     def __init__(self, executor, hbm_budget_bytes: int, slots: int = 8, keep_outputs: bool = False,
-                 clock=time.perf_counter, idle=lambda: time.sleep(20e-6), plan_workers: int = 4):
+                 clock=time.perf_counter, idle=lambda: time.sleep(20e-6), plan_workers: int = 4,
+                 max_bypass: int | None = None, lookahead: int = 32):
+        self.max_bypass = 2 * slots if max_bypass is None else max_bypass
+        self.lookahead = lookahead
         self.ex = executor
         self.budget = int(hbm_budget_bytes)
         self.slots = slots
@@ -259,15 +279,17 @@ class Server:
     def run(self, requests) -> ServeResult:
         """Serve requests (dicts with rid, arrival, kind, refined, n, beta, seed;
         sorted by arrival).  A request that can never fit is rejected up front."""
+        fixed = getattr(self.ex, "fixed_bytes", 0)
         for r in requests:
-            if field_bytes(r["n"], r["kind"]) > self.budget:
+            if fixed + field_bytes(r["n"], r["kind"]) > self.budget:
                 raise ValueError(f"request {r['rid']} needs more than the HBM budget")
-        pending = collections.deque()
+        pending = []
         inflight = [None] * self.slots
-        used = self.cache.bytes
+        used = self.cache.bytes + fixed
         lat, cell_solves, outputs, order = [], 0, {}, []
         nreq, nxt, done = len(requests), 0, 0
         max_inflight, peak = 0, used
+        bypassed = 0     # admissions that went ahead of the current oldest request
         self.ex.synchronize()
         t0 = self.clock()
         while done < nreq:
@@ -287,19 +309,24 @@ class Server:
                     inflight[s] = None
                     done += 1
                     progressed = True
-            while pending:
+            idx = 0
+            while idx < min(len(pending), self.lookahead):
                 s = next((i for i, f in enumerate(inflight) if f is None), None)
                 if s is None:
                     break
-                req = pending[0]
+                if idx > 0 and bypassed >= self.max_bypass:
+                    break        # the oldest request has waited long enough
+                req = pending[idx]
                 fb = field_bytes(req["n"], req["kind"])
-                if used + fb > self.budget:
-                    break
-                S, nb = self.cache.acquire(req, self.budget - used - fb)
+                S, nb = None, 0
+                if used + fb <= self.budget:
+                    S, nb = self.cache.acquire(req, self.budget - used - fb)
                 if S is None:
-                    break
+                    idx += 1     # does not fit now: try a later request
+                    continue
                 used += nb
-                pending.popleft()
+                del pending[idx]
+                bypassed = bypassed + 1 if idx > 0 else 0
                 ev, fields, outs, cells = self.ex.launch(s, req, S)
                 cell_solves += cells
                 inflight[s] = InFlight(req, ev, fields, outs, fb, self.clock() - t0)

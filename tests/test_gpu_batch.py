@@ -72,3 +72,58 @@ def test_batch_rejects_bad_job(mods):
     with pytest.raises(ibs.IbsError) as e:
         ibs.ibs_batch_build([rec], 2)
     assert e.value.status == ibs.IBS_ERR_INVALID_ARG
+
+
+def _rel(a, b):
+    d = (a - b).ravel()
+    return max(float(np.linalg.norm(d) / np.linalg.norm(b.ravel())),
+               float(np.abs(d).max() / np.abs(b).max()))
+
+
+@pytest.mark.parametrize("refined", [True, False])
+def test_batch_mixed_sizes_manufactured(mods, refined):
+    """Jobs at the mixed-size batch's own grid sizes (96x128x96 and
+    192x256x192, stretched), replayed as one graph: all four solves of each
+    job (u, v, w Helmholtz and Poisson) return the manufactured solutions
+    (x_true seeded; b = A x_true formed by the oracle's long-double stencil
+    on the CPU), in l2 and max norm."""
+    from oracle import OP_U, OP_V, OP_W
+    from paper_2406_19920_amd import synth
+    batch, ibs = mods
+    prec = ibs.IBS_REFINED_BF16X3 if refined else ibs.IBS_FP64
+    tol = 1e-10 if refined else 1e-12
+    specs = [dict(nx=96, ny=128, nz=96, beta=1.2, seed=1100),
+             dict(nx=192, ny=256, nz=192, beta=2.4, seed=1101),
+             dict(nx=64, ny=64, nz=64, beta=0.3, seed=1102)]
+    print("case batch mixed sizes manufactured", refined, flush=True)
+    B = batch.Batch(specs, precision=prec, nlanes=3)
+    truth = []
+    for j in B.jobs:
+        s = j.spec
+        g = oracle.Grid(s["nx"], s["ny"], s["nz"], beta=s["beta"])
+        xs = []
+        for q, op in enumerate((OP_U, OP_V, OP_W)):
+            rows = s["ny"] + 1 if op == OP_V else None
+            xt = synth.manufactured(s["nx"], s["ny"], s["nz"], seed=s["seed"] + 10 * q, rows=rows)
+            if op == OP_V:
+                xt[:, 0, :] = 0
+                xt[:, s["ny"], :] = 0
+            r, _, _ = oracle.residual_ld(g, op, j.c, xt, np.zeros_like(xt))
+            j.r[q].copy_(torch.from_numpy(-r))
+            xs.append(xt)
+        xp = synth.manufactured(s["nx"], s["ny"], s["nz"], seed=s["seed"] + 77)
+        xp = xp - oracle.weighted_mean(g, OP_P, xp)
+        r, _, _ = oracle.residual_ld(g, OP_P, 0.0, xp, np.zeros_like(xp))
+        j.b.copy_(torch.from_numpy(-r))
+        truth.append(xs + [xp])
+    torch.cuda.synchronize()
+    B.launch()
+    torch.cuda.synchronize()
+    for q, (j, tr) in enumerate(zip(B.jobs, truth)):
+        for k, (o, t) in enumerate(zip(j.outputs(), tr)):
+            err = _rel(o.cpu().numpy(), t)
+            print("job", q, j.spec["nx"], j.spec["ny"], "solve", k, "err", err, flush=True)
+            assert err < tol
+        for k in range(4):
+            assert j.solver.read_info(k).status == 0
+    B.close()

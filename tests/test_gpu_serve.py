@@ -1,22 +1,31 @@
 """Serving on the GPU: requests that overlap on the device (continuous
 batching over per-slot streams) give the same result as each request run
-alone (bitwise: same plan, fixed tiles and reduction orders)."""
+alone (bitwise: same plan, fixed tiles and reduction orders), and a sample
+of served results (both kinds, both precisions) matches the oracle."""
 import numpy as np
 import pytest
 
+import oracle
+from oracle import OP_P, OP_U, OP_V, OP_W
 from paper_2406_19920_amd import synth
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-def test_mixed_equals_alone():
+def _rel(a, b):
+    d = (a - b).ravel()
+    return max(float(np.linalg.norm(d) / np.linalg.norm(b.ravel())),
+               float(np.abs(d).max() / np.abs(b).max()))
+
+
+def test_mixed_equals_alone_and_oracle():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2406_19920_amd import serve
     print("case serve mixed vs alone", flush=True)
     reqs = synth.serving_requests(rate=3000, count=24, seed=11, nmin=32, nmax=96)
-    ex = serve.GpuExecutor(slots=4)
+    ex = serve.GpuExecutor(slots=4, nmax=96)
     srv = serve.Server(ex, 8 << 30, slots=4, keep_outputs=True)
     res = srv.run(reqs)
     s = res.summary()
@@ -28,4 +37,33 @@ def test_mixed_equals_alone():
         mixed = res.outputs[r["rid"]]
         for a, m in zip(alone, mixed):
             np.testing.assert_array_equal(a.numpy(), m.numpy(), err_msg=f"request {r['rid']}")
+    # the smallest request of each (kind, precision) against the oracle; the
+    # right-hand sides are regenerated from the request's seed exactly as the
+    # executor drew them
+    sample = {}
+    for r in sorted(reqs, key=lambda r: r["n"]):
+        sample.setdefault((r["kind"], r["refined"]), r)
+    assert len(sample) == 4
+    for (kind, refined), r in sorted(sample.items()):
+        n = r["n"]
+        g = oracle.Grid(n, n, n, beta=r["beta"])
+        tol = 1e-10 if refined else 1e-12
+        got = res.outputs[r["rid"]]
+        if kind == "poisson":
+            b = synth.device_normal((n, n, n), r["seed"], "cuda").cpu().numpy()
+            xo, _ = oracle.solve(g, OP_P, b)
+            errs = [_rel(got[0].numpy(), xo)]
+        else:
+            c = 0.125 * min(float(g.dyc.min()), 1.0 / n) ** 2
+            errs = []
+            for q, op in enumerate((OP_U, OP_V, OP_W)):
+                shape = g.shape(op)
+                f = synth.device_normal(shape, r["seed"] * 4 + op, "cuda").cpu().numpy()
+                if op == OP_V:
+                    f[:, 0, :] = 0
+                    f[:, n, :] = 0
+                xo, _ = oracle.solve(g, op, f, c=c)
+                errs.append(_rel(got[q].numpy(), xo))
+        print("served", kind, "refined" if refined else "fp64", "n", n, "errs", errs, flush=True)
+        assert max(errs) < tol
     srv.close()

@@ -89,7 +89,49 @@ def test_all_complete_fifo_and_overlap():
     assert np.all(res.latencies > 0)
     s = res.summary()
     assert s["p99_ms"] >= s["p50_ms"] > 0
-    assert ex.max_same_plan == 1                           # a plan never runs twice at once
+
+
+def test_same_grid_requests_overlap():
+    """A plan's device constants are read-only: requests on one grid run
+    side by side (each on its own slot workspace)."""
+    reqs = [dict(rid=i, arrival=0.0, kind="helmholtz", refined=True, n=64, beta=1.0, seed=i)
+            for i in range(6)]
+    srv, ex, _ = _server(slots=3)
+    res = srv.run(reqs)
+    assert res.completed == 6
+    assert ex.max_same_plan == 3
+    assert res.plan_misses == 1 and res.plan_hits == 5
+
+
+def test_head_of_line_bypass_bounded():
+    """A request that does not fit while others run is passed over by later
+    ones that fit, at most max_bypass times; then admission waits for it and
+    it completes (no starvation)."""
+    big = dict(rid=1, arrival=1e-6, kind="helmholtz", refined=False, n=128, beta=0.0, seed=1)
+    small = [dict(rid=i, arrival=(0.0 if i == 0 else 2e-6), kind="poisson", refined=False, n=32,
+                  beta=0.0, seed=i) for i in [0] + list(range(2, 12))]
+    reqs = sorted([big] + small, key=lambda r: r["arrival"])
+    plan_bytes = 8 * 128 ** 2 * 4 + 8 * 32 ** 2 * 4
+    budget = serve.field_bytes(128, "helmholtz") + plan_bytes + serve.field_bytes(32, "poisson") // 2
+    # the big request fits only when nothing else runs; solves last far
+    # longer than the simulated clock's idle tick
+    srv, ex, _ = _server(budget=budget, slots=4, rate_cells_per_s=1e6)
+    srv.max_bypass = 3
+    res = srv.run(reqs)
+    assert res.completed == len(reqs)
+    order = res.admit_order
+    pos = order.index(1)
+    assert order[0] == 0
+    assert pos == 1 + 3                # later small ones went past the big one, max_bypass of them
+    assert res.peak_bytes <= budget
+
+
+def test_fixed_executor_bytes_count_against_budget():
+    reqs = [dict(rid=0, arrival=0.0, kind="poisson", refined=False, n=32, beta=0.0, seed=0)]
+    srv, ex, _ = _server(budget=serve.field_bytes(32, "poisson") + (1 << 20))
+    ex.fixed_bytes = 1 << 21
+    with pytest.raises(ValueError):
+        srv.run(reqs)
 
 
 def test_budget_limits_concurrency():
