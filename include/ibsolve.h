@@ -185,6 +185,23 @@ ibs_status solve_helmholtz_batch(ibs_plan plan, int32_t ncomp, const int32_t *co
                                  double *const *x, void *work, size_t work_bytes,
                                  ibs_solve_info *info, void *stream);
 
+/* Pressure Poisson problem exactly as solve_poisson(), for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): no workspace argument,
+ * and no allocation.  The work fields and per-call state live in a fixed
+ * array of IBS_NOALLOC_SCRATCH_BYTES inside this library, one per GPU,
+ * held until the process ends; a grid whose Poisson workspace
+ * (solver_plan_bytes) exceeds it is refused with
+ * IBS_ERR_WORKSPACE_TOO_SMALL before anything is enqueued.  Every call on
+ * one GPU shares that GPU's array: calls that overlap in time on one GPU
+ * (other streams, other host threads) race and must be ordered by the
+ * caller.  Results are bitwise those of solve_poisson().  Errors as
+ * solve_poisson, and IBS_ERR_HIP if the array's address cannot be resolved
+ * on the current device. */
+#define IBS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+ibs_status solve_poisson_noalloc(ibs_plan plan, const double *b, double *phi,
+                                 ibs_solve_info *info, void *stream);
+
 /* Residual r = b - A x in FP64 for op IBS_OP_POISSON (A = L_p) or
  * IBS_OP_HELMHOLTZ_{U,V,W} (A = I - c L), with the 7-point stencil.  x, b, r
  * device fields of the op's shape (r may not alias x).  norms2: NULL or a

@@ -31,7 +31,8 @@ IBS_OP_POISSON, IBS_OP_HELMHOLTZ_U, IBS_OP_HELMHOLTZ_V, IBS_OP_HELMHOLTZ_W = 0, 
 
 # every exported entry point of include/ibsolve.h
 EXPORTS = ("solver_plan", "solver_plan_bytes", "solver_plan_upload", "solver_plan_destroy",
-           "solve_poisson", "solve_helmholtz_batch", "residual", "ibs_divergence",
+           "solve_poisson", "solve_poisson_noalloc", "solve_helmholtz_batch", "residual",
+           "ibs_divergence",
            "ibs_correct", "ibs_plan_export", "ibs_profile", "ibs_profile_read",
            "ibs_batch_build", "ibs_batch_launch", "ibs_batch_destroy",
            "ibs_autotune_bytes", "ibs_autotune", "ibs_plan_set_tiles",
@@ -86,6 +87,7 @@ def _load():
     L.solver_plan_upload.argtypes = [vp, vp, sz, vp]
     L.solver_plan_destroy.argtypes = [vp]
     L.solve_poisson.argtypes = [vp, vp, vp, vp, sz, vp, vp]
+    L.solve_poisson_noalloc.argtypes = [vp, vp, vp, vp, vp]
     L.solve_helmholtz_batch.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl),
                                         ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz, vp, vp]
     L.residual.argtypes = [vp, i32, dbl, vp, vp, vp, vp, vp, sz, vp]
@@ -166,6 +168,13 @@ def solver_plan_destroy(plan: int):
 
 def solve_poisson(plan, b, phi, work, work_bytes, info, stream):
     _check(lib.solve_poisson(plan, b, phi, work, work_bytes, info, stream), "solve_poisson")
+
+
+IBS_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def solve_poisson_noalloc(plan, b, phi, info, stream):
+    _check(lib.solve_poisson_noalloc(plan, b, phi, info, stream), "solve_poisson_noalloc")
 
 
 def solve_helmholtz_batch(plan, comps, cs, rs, xs, work, work_bytes, info, stream):
