@@ -71,6 +71,8 @@ def lib():
         L.orc_weights.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
         L.orc_residual_ld.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
                                       dp, dp, dp, dp]
+        L.orc_residual_bc_ld.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
+                                         dp, dp, dp, dp, dp, dp]
         L.orc_solve.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
                                 dp, dp, ctypes.c_double, ctypes.c_int,
                                 ctypes.c_void_p]
@@ -207,6 +209,54 @@ def residual_ld(g: Grid, op: int, c: float, x, b):
     norms = np.zeros(2)
     lib().orc_residual_ld(g.cptr, op, c, _dp(x), _dp(b), _dp(r), _dp(norms))
     return r, float(norms[0]), float(norms[1])
+
+
+def wall_shape(g: Grid) -> tuple:
+    """Shape of one wall-data plane: [nz][nx] (one value per wall column)."""
+    return (g.nz, g.nx)
+
+
+def residual_bc_ld(g: Grid, op: int, c: float, x, b, lo=None, hi=None):
+    """r = b - A(x; lo, hi): the operator with inhomogeneous wall data at
+    y = 0 (lo) and y = ly (hi), each [nz][nx] or None (zero), evaluated from
+    the flux form in long double.  Poisson: lo, hi are the prescribed wall
+    fluxes d(phi)/dy; u, w: wall values through the mirror ghost 2g - f_0
+    (Appendix B, alpha = 2); v: wall-face values (alpha = 1).  Returns
+    (r, ||r||_2, ||b||_2)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    dat = []
+    for d in (lo, hi):
+        if d is None:
+            dat.append(None)
+        else:
+            d = np.ascontiguousarray(d, dtype=np.float64)
+            assert d.shape == wall_shape(g)
+            dat.append(d)
+    r = np.zeros(g.shape(op))
+    norms = np.zeros(2)
+    lib().orc_residual_bc_ld(g.cptr, op, c, _dp(x), _dp(b),
+                             _dp(dat[0]) if dat[0] is not None else None,
+                             _dp(dat[1]) if dat[1] is not None else None, _dp(r), _dp(norms))
+    return r, float(norms[0]), float(norms[1])
+
+
+def solve_bc(g: Grid, op: int, b, lo=None, hi=None, c: float = 0.0, tol: float = 1e-14):
+    """Solve A(x; lo, hi) = b with inhomogeneous wall data (Appendix B's
+    boundary terms, Section 2.3.3): the operator is affine in the data, so
+    x solves the homogeneous system with right-hand side b - A(0; lo, hi),
+    the data's contribution evaluated by the flux form at x = 0.  Poisson:
+    the weighted mean of that right-hand side is removed as in solve() and
+    x has zero weighted mean.  v: the returned wall faces hold the data.
+    Returns (x, info)."""
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    zero = np.zeros(g.shape(op))
+    r0, _, _ = residual_bc_ld(g, op, c, zero, b, lo, hi)   # b - A(0; lo, hi)
+    x, info = solve(g, op, r0, c=c, tol=tol)
+    if op == OP_V:
+        x[:, 0, :] = 0.0 if lo is None else lo
+        x[:, g.ny, :] = 0.0 if hi is None else hi
+    return x, info
 
 
 @dataclass

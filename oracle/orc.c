@@ -292,8 +292,27 @@ void orc_weights(const orc_geom *g, int op, double *w)
 /* x, b, r in the caller's full array layout.  Returns ||r||_2 and     */
 /* ||b||_2 (over the unknowns) through norms[0], norms[1].             */
 /* ------------------------------------------------------------------ */
+/* lo, hi: wall data of column (i, k) at y = 0 and y = ly ([nz][nx] arrays,
+ * NULL = homogeneous).  Poisson: the prescribed flux d(phi)/dy on the wall
+ * face (Neumann).  u, w: the wall value of the velocity, imposed through
+ * the mirror ghost f_ghost = 2 g - f_0, i.e. the wall flux
+ * (f_0 - g)/(Delta_0/2) (Appendix B, alpha = 2).  v: the value of the wall
+ * face itself (alpha = 1). */
+static long double wall_at(const double *data, const orc_geom *g, int i, int k)
+{
+    return data ? (long double)data[(int64_t)k * g->nx + i] : 0.0L;
+}
+
+static long double flux_apply_bc_ld(const orc_geom *g, int op, int i, int j, int k,
+                                    const double *x, const double *lo, const double *hi);
 static long double flux_apply_ld(const orc_geom *g, int op, int i, int j, int k,
                                  const double *x)
+{
+    return flux_apply_bc_ld(g, op, i, j, k, x, NULL, NULL);
+}
+
+static long double flux_apply_bc_ld(const orc_geom *g, int op, int i, int j, int k,
+                                    const double *x, const double *lo, const double *hi)
 {
     const int nx = g->nx, ny = g->ny, nz = g->nz;
     long double hx = g->hx, hz = g->hz;
@@ -306,13 +325,13 @@ static long double flux_apply_ld(const orc_geom *g, int op, int i, int j, int k,
         long double D = g->dyc[j];
         long double fu, fl;
         if (j + 1 < ny) fu = ((long double)x[at(g, i, j + 1, k)] - xc) / (long double)g->dyf[j + 1];
-        else fu = (op == 0) ? 0.0L : (0.0L - xc) / (D / 2.0L);
+        else fu = (op == 0) ? wall_at(hi, g, i, k) : (wall_at(hi, g, i, k) - xc) / (D / 2.0L);
         if (j > 0) fl = (xc - (long double)x[at(g, i, j - 1, k)]) / (long double)g->dyf[j];
-        else fl = (op == 0) ? 0.0L : (xc - 0.0L) / (D / 2.0L);
+        else fl = (op == 0) ? wall_at(lo, g, i, k) : (xc - wall_at(lo, g, i, k)) / (D / 2.0L);
         lap += (fu - fl) / D;
     } else {
-        long double vu = (j + 1 <= ny - 1) ? (long double)x[vidx(g, i, j + 1, k)] : 0.0L;
-        long double vl = (j - 1 >= 1) ? (long double)x[vidx(g, i, j - 1, k)] : 0.0L;
+        long double vu = (j + 1 <= ny - 1) ? (long double)x[vidx(g, i, j + 1, k)] : wall_at(hi, g, i, k);
+        long double vl = (j - 1 >= 1) ? (long double)x[vidx(g, i, j - 1, k)] : wall_at(lo, g, i, k);
         long double fu = (vu - xc) / (long double)g->dyc[j];
         long double fl = (xc - vl) / (long double)g->dyc[j - 1];
         lap += (fu - fl) / (long double)g->dyf[j];
@@ -320,8 +339,21 @@ static long double flux_apply_ld(const orc_geom *g, int op, int i, int j, int k,
     return lap;
 }
 
+void orc_residual_bc_ld(const orc_geom *g, int op, double c, const double *x,
+                        const double *b, const double *lo, const double *hi,
+                        double *r, double *norms);
 void orc_residual_ld(const orc_geom *g, int op, double c, const double *x,
                      const double *b, double *r, double *norms)
+{
+    orc_residual_bc_ld(g, op, c, x, b, NULL, NULL, r, norms);
+}
+
+/* As orc_residual_ld, with inhomogeneous wall data lo, hi (see wall_at):
+ * r = b - A(x; lo, hi), the operator applied with the wall fluxes or
+ * values the data prescribe. */
+void orc_residual_bc_ld(const orc_geom *g, int op, double c, const double *x,
+                        const double *b, const double *lo, const double *hi,
+                        double *r, double *norms)
 {
     int64_t n = n_unknowns(g, op);
     long double rr = 0.0L, bb = 0.0L;
@@ -330,7 +362,7 @@ void orc_residual_ld(const orc_geom *g, int op, double c, const double *x,
         int i, j, k;
         unknown_ijk(g, op, q, &i, &j, &k);
         int64_t a = unknown_to_array(g, op, q);
-        long double lap = flux_apply_ld(g, op, i, j, k, x);
+        long double lap = flux_apply_bc_ld(g, op, i, j, k, x, lo, hi);
         long double ax = (op == 0) ? lap : (long double)x[a] - (long double)c * lap;
         long double res = (long double)b[a] - ax;
         r[a] = (double)res;

@@ -281,3 +281,84 @@ def test_oracle_accuracy_64cube_eigenmode():
     err = np.linalg.norm((x - m).ravel()) / np.linalg.norm(m.ravel())
     assert err < 1e-14, (err, info)
     assert info.rel_residual < 1e-14
+
+
+# ------------------------------------------------------------------------
+# Inhomogeneous wall data (Appendix B's boundary terms)
+# ------------------------------------------------------------------------
+def _planes(g, value):
+    return np.full(oracle.wall_shape(g), float(value))
+
+
+def test_wall_data_closed_forms():
+    """Profiles the discrete operators reproduce exactly, with their wall
+    data: phi = y^2/2 on a uniform grid (Neumann data dphi/dy = y at the
+    walls: b = 1), u = y at cell centres and v = y at faces on a stretched
+    grid (Dirichlet data g = y at the walls: the mirror ghost and the face
+    values are exact for linear profiles, so L u = 0 and (I - cL) u = u).
+    A sign or factor error in the wall terms fails these."""
+    nx, ny, nz = 6, 9, 4
+    g = oracle.Grid(nx, ny, nz)
+    phi = np.broadcast_to((g.yc ** 2 / 2)[None, :, None], g.shape(OP_P)).copy()
+    lo, hi = _planes(g, 0.0), _planes(g, 1.0)
+    r, rn, _ = oracle.residual_bc_ld(g, OP_P, 0.0, phi, np.ones(g.shape(OP_P)), lo, hi)
+    assert np.abs(r).max() < 1e-12
+    x, _ = oracle.solve_bc(g, OP_P, np.ones(g.shape(OP_P)), lo, hi)
+    ref = phi - oracle.weighted_mean(g, OP_P, phi)
+    assert np.abs(x - ref).max() < 1e-12
+    gs = oracle.Grid(nx, ny, nz, beta=2.0)
+    c = 3e-3
+    lo, hi = _planes(gs, 0.0), _planes(gs, 1.0)
+    for op, prof in ((OP_U, gs.yc), (OP_W, gs.yc), (OP_V, gs.yf)):
+        f = np.broadcast_to(prof[None, :, None], gs.shape(op)).copy()
+        r, _, _ = oracle.residual_bc_ld(gs, op, c, f, f, lo, hi)
+        assert np.abs(r).max() < 1e-12, op
+        x, _ = oracle.solve_bc(gs, op, f, lo, hi, c=c)
+        assert np.abs(x - f).max() < 1e-12, op
+
+
+def test_wall_data_matches_appendix_b_terms():
+    """On a uniform grid (h = ly/ny) the data's contribution to the right-hand
+    side is the boundary column of Appendix B, rewritten for (I - cL) x = r
+    (the paper's row times -c, its A2 = 1/h^2) and L_p phi = b:
+    u, w (alpha = 2): r_0 += 2 c g_lo / h^2, r_{ny-1} += 2 c g_hi / h^2;
+    v (alpha = 1): r at faces 1 and ny-1 += c g / h^2;
+    Poisson: b_0 += A2 h BC_lo = BC_lo / h, b_{ny-1} -= BC_hi / h."""
+    nx, ny, nz = 4, 6, 3
+    g = oracle.Grid(nx, ny, nz)
+    h = 1.0 / ny
+    rng = np.random.default_rng(5)
+    lo, hi = rng.standard_normal(oracle.wall_shape(g)), rng.standard_normal(oracle.wall_shape(g))
+    c = 0.02
+    for op in (OP_P, OP_U, OP_V, OP_W):
+        zero = np.zeros(g.shape(op))
+        t, _, _ = oracle.residual_bc_ld(g, op, 0.0 if op == OP_P else c, zero, zero, lo, hi)
+        exp = np.zeros(g.shape(op))
+        if op == OP_P:
+            exp[:, 0, :] += lo / h
+            exp[:, ny - 1, :] -= hi / h
+        elif op == OP_V:
+            exp[:, 1, :] += c * lo / h ** 2
+            exp[:, ny - 1, :] += c * hi / h ** 2
+        else:
+            exp[:, 0, :] += 2 * c * lo / h ** 2
+            exp[:, ny - 1, :] += 2 * c * hi / h ** 2
+        assert np.abs(t - exp).max() < 1e-10 * np.abs(exp).max(), op
+
+
+def test_wall_data_superposition():
+    """The problem is affine in the data: the solution with data is the
+    homogeneous solution plus the response to the data alone."""
+    nx, ny, nz = 8, 7, 6
+    g = oracle.Grid(nx, ny, nz, beta=1.5)
+    rng = np.random.default_rng(7)
+    lo, hi = rng.standard_normal(oracle.wall_shape(g)), rng.standard_normal(oracle.wall_shape(g))
+    for op, c in ((OP_P, 0.0), (OP_U, 1e-2), (OP_V, 1e-2)):
+        b = synth.scalar(nx, ny, nz, 3, rows=ny + 1 if op == OP_V else None)
+        if op == OP_V:
+            b[:, 0, :] = 0
+            b[:, ny, :] = 0
+        x, _ = oracle.solve_bc(g, op, b, lo, hi, c=c)
+        x0, _ = oracle.solve(g, op, b, c=c)
+        xd, _ = oracle.solve_bc(g, op, np.zeros_like(b), lo, hi, c=c)
+        assert np.abs(x - (x0 + xd)).max() < 1e-11 * np.abs(x).max(), op
