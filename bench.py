@@ -84,11 +84,33 @@ def cpu_step(n_sample, beta, seed):
     return time.perf_counter() - t0
 
 
-def cpu_baseline(n_sample, beta, seed, n_single=64):
+def cpu_helmholtz_headline(n, beta, u, v, w):
+    """Seconds for the headline step's three Helmholtz solves by the oracle
+    at the headline size itself (same inputs, same c)."""
+    import oracle
+    from oracle import OP_U, OP_V, OP_W
+    g = oracle.Grid(n, n, n, beta=beta)
+    c = 0.125 * float(g.dyc.min()) ** 2
+    t0 = time.perf_counter()
+    for op, f in ((OP_U, u), (OP_V, v), (OP_W, w)):
+        oracle.solve(g, op, f, c=c)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(n_sample, beta, seed, n_single=64, headline=None):
     """The oracle on the same step at a reduced grid, on all host threads,
-    and on one thread at a smaller grid."""
+    and on one thread at a smaller grid; with headline = (n, u, v, w) also
+    the step's three Helmholtz solves at the headline size."""
     import oracle
     dt = cpu_step(n_sample, beta, seed)
+    head = None
+    if headline is not None:
+        nh, u, v, w = headline
+        dth = cpu_helmholtz_headline(nh, beta, u, v, w)
+        head = {"value": 3 * nh ** 3 / dth / 1e6, "unit": "Mcell-solves/s",
+                "sample": f"the three Helmholtz solves of the {nh}^3 step itself (same inputs and c), "
+                          f"{dth:.1f} s; the step's Poisson solve at {nh}^3 (CG, thousands of "
+                          f"iterations) is left out to bound the run"}
     threads = oracle.num_threads()
     oracle.set_num_threads(1)
     try:
@@ -103,6 +125,7 @@ def cpu_baseline(n_sample, beta, seed, n_single=64):
                       f"overstates the oracle's rate at 256^3",
             "single_thread": {"value": 4 * n_single ** 3 / dt1 / 1e6, "unit": "Mcell-solves/s",
                               "sample": f"the same step at {n_single}^3 on one thread, {dt1:.1f} s"},
+            "headline_size_helmholtz": head,
             "cpu_model": cpu_model(), "nproc": os.cpu_count()}
 
 
@@ -116,6 +139,9 @@ def main():
     ap.add_argument("--path", choices=["refined", "fp64", "both"], default="both")
     ap.add_argument("--cpu-sample", type=int, default=160)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra-configs", action="store_true",
+                    help="skip the shortened 512x384x384, 64-job batch and serving runs that the "
+                         "default run appends under 'configs'")
     ap.add_argument("--config", choices=["c2", "c3", "batch", "serve"], default="c2",
                     help="c2: 256^3 step (default); c3: 512x384x384 refined step with a forcing "
                          "shell; batch: 64 mixed-size jobs as one graph; serve: arrival-rate sweep")
@@ -266,10 +292,27 @@ def main():
         if any(results[path]["status"]):
             log(f"WARNING: path {path} status {results[path]['status']} (non-zero: not converged)")
 
+    # the other configurations, shortened, in the same run (their own
+    # --config modes run them in full)
+    configs = None
+    if not args.no_extra_configs and n == 256 and beta == 2.0:
+        configs = {}
+        log("config c3")
+        c3, c3w = run_c3(5, 1)
+        configs["c3"] = {"workload": c3w, "steps": 5, "warmup": 1,
+                         "refined": {k: c3["refined"][k] for k in ("value", "ms_per_step", "status", "passes")},
+                         "fp64": {k: c3["fp64"][k] for k in ("value", "ms_per_step", "status", "passes")},
+                         "unit": "Mcell-solves/s"}
+        log("config c4")
+        configs["c4"] = run_batch(5, 1)
+        log("config c5")
+        rows, nwarm, w5 = run_serve([200.0, 1000.0, 5000.0], 300)
+        configs["c5"] = {"workload": w5, "unit": "Mcell-solves/s", "sweep": rows}
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle at {args.cpu_sample}^3")
-        cpu = cpu_baseline(args.cpu_sample, beta, seed=2)
+        cpu = cpu_baseline(args.cpu_sample, beta, seed=2, headline=(n, u, v, w))
 
     head = results[paths[0]]
     out = {
@@ -288,6 +331,7 @@ def main():
         "roofline": head["roofline"],
         "paths": results,
         "cpu_baseline": cpu,
+        "configs": configs,
     }
     print(json.dumps(out), flush=True)
 
@@ -304,47 +348,57 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_bytes": src.numel() * 4, "repeats": 5}), flush=True)
 
 
-def bench_batch(args):
+def run_batch(steps, warmup, njobs=64):
     """64 independent refined Poisson + 3 Helmholtz jobs of mixed sizes,
-    recorded once into one HIP graph and replayed."""
+    recorded once into one HIP graph and replayed; returns a summary."""
     import torch
     from paper_2406_19920_amd import batch, ibsolve as ibs, synth
-    specs = synth.batch_specs(64, seed=4)
+    specs = synth.batch_specs(njobs, seed=4)
     log("building batch of", len(specs), "jobs")
     B = batch.Batch(specs, precision=ibs.IBS_REFINED_BF16X3, nlanes=8)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         B.launch()
     torch.cuda.synchronize()
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
     evs[0].record()
-    for k in range(args.steps):
+    for k in range(steps):
         B.launch()
         evs[k + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)])
-    ms = wall * 1e3 / args.steps
+    per = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(steps)])
+    ms = wall * 1e3 / steps
     status = [j.solver.read_info(q).status for j in B.jobs for q in (0, 1, 2, 3)]
-    out = {"metric": "Mcell-solves/s, 64 mixed-size refined jobs (Poisson + 3 Helmholtz) as one graph",
-           "value": B.cell_solves / (ms * 1e-3) / 1e6, "unit": "Mcell-solves/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None,
-           "dtype": "bf16x3 MFMA, f32 accumulate, f64 residual/iterate", "data": "synthetic",
-           "config": {"workload": "64 jobs, sizes uniform over 64^3, 96x128x96, 128^3, 192x256x192, "
-                                  "beta ~ U[0,3], seeds 1000+i, one graph launch",
-                      "cell_solves_per_launch": B.cell_solves, "nlanes": 8},
+    out = {"value": B.cell_solves / (ms * 1e-3) / 1e6, "unit": "Mcell-solves/s",
+           "ms_per_launch": ms, "launches": steps,
+           "workload": f"{njobs} jobs, sizes uniform over 64^3, 96x128x96, 128^3, 192x256x192, "
+                       "beta ~ U[0,3], seeds 1000+i, refined, one graph launch, 8 lanes",
+           "cell_solves_per_launch": B.cell_solves,
            "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))},
            "all_status_ok": all(s == 0 for s in status)}
     B.close()
+    return out
+
+
+def bench_batch(args):
+    r = run_batch(args.steps, args.warmup)
+    out = {"metric": "Mcell-solves/s, 64 mixed-size refined jobs (Poisson + 3 Helmholtz) as one graph",
+           "value": r["value"], "unit": "Mcell-solves/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_launch"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16x3 MFMA, f32 accumulate, f64 residual/iterate", "data": "synthetic",
+           "config": {"workload": r["workload"], "cell_solves_per_launch": r["cell_solves_per_launch"],
+                      "nlanes": 8},
+           "latency_ms": r["latency_ms"], "all_status_ok": r["all_status_ok"]}
     print(json.dumps(out), flush=True)
 
 
-def bench_serve(args):
-    """Poisson-process arrivals at each rate, continuous batching over 8 slots."""
+def run_serve(rates, count, geometries=0):
+    """Poisson-process arrivals at each rate, continuous batching over 8
+    slots; one summary row per rate."""
     import torch
     from paper_2406_19920_amd import serve, synth
-    rates = [float(r) for r in args.rates.split(",")]
     ex = serve.GpuExecutor(slots=8)
     # warm-up: load every kernel once for each kind and precision
     warm = [dict(rid=i, arrival=0.0, kind=k, refined=rf, n=n, beta=1.0, seed=i)
@@ -356,7 +410,7 @@ def bench_serve(args):
     torch.cuda.synchronize()
     rows = []
     for i, rate in enumerate(rates):
-        reqs = synth.serving_requests(rate, args.count, seed=5 + i, geometries=args.geometries)
+        reqs = synth.serving_requests(rate, count, seed=5 + i, geometries=geometries)
         srv = serve.Server(ex, 96 << 30, 8)
         res = srv.run(reqs)
         d = res.summary()
@@ -364,24 +418,31 @@ def bench_serve(args):
         rows.append(d)
         srv.close()
         log(json.dumps(d))
+    workload = ("Poisson-process arrivals; 50/50 Poisson or Helmholtz x3; 50/50 FP64 or refined; "
+                "n log-uniform [32,384] (multiple of 32); beta ~ U[0,3]; "
+                + (f"(n, beta) from a pool of {geometries} grids; " if geometries
+                   else "a new grid per request; ")
+                + f"8 slots, 96 GiB budget; {count} requests per rate")
+    return rows, len(warm), workload
+
+
+def bench_serve(args):
+    rates = [float(r) for r in args.rates.split(",")]
+    rows, nwarm, workload = run_serve(rates, args.count, args.geometries)
     best = max(rows, key=lambda d: d["mcell_solves_per_s"])
     out = {"metric": "serving: Mcell-solves/s and p50/p99 latency vs arrival rate",
            "value": best["mcell_solves_per_s"], "unit": "Mcell-solves/s", "n_gpus": 1,
-           "steps": args.count, "warmup": len(warm), "ms_per_step": None, "higher_is_better": True,
+           "steps": args.count, "warmup": nwarm, "ms_per_step": None, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64 and refined (50/50)",
            "data": "synthetic",
-           "config": {"workload": "Poisson-process arrivals; 50/50 Poisson or Helmholtz x3; 50/50 FP64 "
-                                  "or refined; n log-uniform [32,384] (multiple of 32); beta ~ U[0,3]; "
-                                  + (f"(n, beta) from a pool of {args.geometries} grids; " if args.geometries
-                                     else "a new grid per request; ")
-                                  + "8 slots, 96 GiB budget", "rates": rates},
+           "config": {"workload": workload, "rates": rates},
            "sweep": rows}
     print(json.dumps(out), flush=True)
 
 
-def bench_c3(args):
-    """512x384x384 (x, y, z) refined step; RHS = N(0,1) plus a smoothed-delta
-    forcing shell (radius 0.1 Lx)."""
+def run_c3(steps, warmup):
+    """512x384x384 (x, y, z) step on both paths; RHS = N(0,1) plus a
+    smoothed-delta forcing shell (radius 0.1 Lx)."""
     import torch
     from paper_2406_19920_amd import ibsolve as ibs, synth
     nx, ny, nz, beta = 512, 384, 384, 2.0
@@ -408,39 +469,45 @@ def bench_c3(args):
             S.poisson(b, phi)
             S.correct(phi, xu, xv, xw, 1.0)
 
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             step()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             step()
         torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        ms = (time.perf_counter() - t0) * 1e3 / steps
         status = [S.read_info(q).status for q in range(4)]
         passes = {"helmholtz": [S.read_info(q).iters for q in (1, 2, 3)], "poisson": S.read_info(0).iters}
         # live per-kernel time per step (HIP events on the launch stream)
         ibs.ibs_profile(S.plan, True)
-        for _ in range(args.steps):
+        for _ in range(steps):
             step()
         torch.cuda.synchronize()
         kern = {}
         for kid, name in enumerate(ibs.PROFILE_KERNELS):
             r = ibs.ibs_profile_read(S.plan, kid)
             if r["launches"]:
-                kern[name] = {"ms_per_step": r["ms"] / args.steps,
+                kern[name] = {"ms_per_step": r["ms"] / steps,
                               "gbs": r["bytes"] / (r["ms"] * 1e-3) / 1e9 if r["ms"] else None,
                               "tflops": r["flops"] / (r["ms"] * 1e-3) / 1e12 if r["ms"] else None}
         ibs.ibs_profile(S.plan, False)
         res[path] = {"value": 4 * nx * ny * nz / (ms * 1e-3) / 1e6, "ms_per_step": ms,
                      "status": status, "passes": passes, "tiles": tiles, "kernels": kern}
         S.close()
+    del ru, rv, rw
+    torch.cuda.empty_cache()
+    return res, "512x384x384, beta=2, N(0,1) + forcing shell, c=%.4e" % c
+
+
+def bench_c3(args):
+    res, workload = run_c3(args.steps, args.warmup)
     out = {"metric": "Mcell-solves/s at 512x384x384 (refined to 1e-10; FP64 alongside)",
            "value": res["refined"]["value"], "unit": "Mcell-solves/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["refined"]["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "bf16x3 MFMA, f32 accumulate, f64 residual/iterate", "data": "synthetic",
-           "config": {"workload": "512x384x384, beta=2, N(0,1) + forcing shell, c=%.4e" % c},
-           "paths": res}
+           "config": {"workload": workload}, "paths": res}
     print(json.dumps(out), flush=True)
 
 

@@ -222,6 +222,28 @@ ibs_status residual(ibs_plan plan, int32_t op, double c, const double *x,
 ibs_status ibs_divergence(ibs_plan plan, const double *u, const double *v,
                           const double *w, double *b, double scale, void *stream);
 
+/* Inhomogeneous wall data (Section 2.3.3, subroutine BC2.2; Appendix B's
+ * boundary terms): adds to the right-hand side rhs of op (in place) the
+ * contribution of prescribed data at the walls y = 0 (lo) and y = ly (hi),
+ * so that the homogeneous solve of the modified rhs returns the solution
+ * with that data.  lo, hi: device arrays [nz][nx] (one value per wall
+ * column), either may be NULL (zero data).
+ *   IBS_OP_POISSON: the wall flux dphi/dy (Neumann data);
+ *     b[0] += lo/Delta_0, b[ny-1] -= hi/Delta_{ny-1} (c unused).
+ *   IBS_OP_HELMHOLTZ_U / _W: the wall value of the velocity (mirror ghost
+ *     2g - f_0, Appendix B alpha = 2); r[0] += 2c lo/Delta_0^2,
+ *     r[ny-1] += 2c hi/Delta_{ny-1}^2, c the coefficient of the solve.
+ *   IBS_OP_HELMHOLTZ_V: the value of the wall face itself (alpha = 1);
+ *     r at face 1 += c lo/(Delta_0 delta_1), at face ny-1 += c hi/
+ *     (Delta_{ny-1} delta_{ny-1}).  The solve writes 0 to the solution's
+ *     wall faces; the caller stores lo/hi there.
+ * A Poisson rhs with Neumann data is compatible when the weighted mean of
+ * the modified rhs is zero (the solve removes what is not).  Call it once
+ * per rhs, before the solve, on the solve's stream.  Errors:
+ * IBS_ERR_INVALID_ARG, IBS_ERR_NOT_UPLOADED, IBS_ERR_HIP. */
+ibs_status ibs_wall_data(ibs_plan plan, int32_t op, double c, const double *lo,
+                         const double *hi, double *rhs, void *stream);
+
 /* Projection, eq. (g), and pressure update, eq. (h) (kernel E3):
  * u -= g dphi/dx, v -= g dphi/dy (interior faces; walls set to 0),
  * w -= g dphi/dz; if p != NULL: p += phi - cp * lap_phi, where lap_phi is the

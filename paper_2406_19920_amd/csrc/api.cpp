@@ -534,6 +534,22 @@ ibs_status ibs_correct(ibs_plan plan, const double *phi, double *u, double *v, d
     return IBS_OK;
 }
 
+ibs_status ibs_wall_data(ibs_plan plan, int32_t op, double c, const double *lo, const double *hi,
+                         double *rhs, void *stream)
+{
+    ibs_status chk = check_plan(plan);
+    if (chk != IBS_OK) return chk;
+    Plan &p = *reinterpret_cast<Plan *>(plan);
+    if (op < IBS_OP_POISSON || op > IBS_OP_HELMHOLTZ_W) { set_error("bad op"); return IBS_ERR_INVALID_ARG; }
+    if (!rhs) { set_error("rhs must be non-NULL"); return IBS_ERR_INVALID_ARG; }
+    if (!std::isfinite(c) || (op != IBS_OP_POISSON && c < 0.0)) { set_error("c must be finite and >= 0"); return IBS_ERR_INVALID_ARG; }
+    if (!lo && !hi) return IBS_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_wall_data(p, op, c, lo, hi, rhs, s);
+    if (e != hipSuccess) return hip_fail(e, "wall data");
+    return IBS_OK;
+}
+
 ibs_status ibs_profile(ibs_plan plan, int32_t enable)
 {
     if (!plan) { set_error("plan is NULL"); return IBS_ERR_INVALID_ARG; }

@@ -32,6 +32,8 @@ struct BlobLayout {
     size_t sz_fwd, sz_inv;   // z transform, bf16x3 split, A-operand swizzle (nz % 64 != 0)
     size_t sxf_fwd, sxf_inv; // folded x transform factors, bf16x3 split (nx % 64 == 0)
     size_t szf_fwd, szf_inv; // folded z transform factors, bf16x3 split (nz % 64 == 0)
+    size_t lane_mask;        // refined: per z-mode bit mask of FP64-lane x-tiles (uint32 [nz])
+    size_t lane_list;        // refined: FP64-lane tiles, (c << 8) | t (int [lane_len])
     size_t total;
 };
 
@@ -44,6 +46,11 @@ constexpr int XSUM_SLOTS = 4096;     // max residual blocks per job (fixed order
 constexpr int COMPAT_SLOTS = 2048;   // max blocks of the compatibility reduction
 constexpr int RESID_SLOTS = 4096;    // max blocks of the residual() norm reduction
 constexpr int MAX_PASSES = 8;        // most refinement passes a solve may take (max_iter)
+// Refined path: pressure pencils whose condition bound 1 + g/|s| (g the
+// Gershgorin bound of the y operator, s the pencil's transverse eigenvalue)
+// exceeds this are solved with FP64 arithmetic (the FP64 lane); the rest in
+// FP32, whose rounding the refinement then removes.
+constexpr double LANE64_KAPPA = 1000.0;
 struct State {
     double *bmean = nullptr;   // per job: weighted mean of the Poisson rhs
     double *xsum = nullptr;    // per job: partial sums of Delta_j x (XSUM_SLOTS each)
@@ -91,6 +98,7 @@ struct Plan {
     std::vector<double> lo[NUM_KINDS], di[NUM_KINDS], up[NUM_KINDS];
     int rows[NUM_KINDS];
     BlobLayout lay;
+    int lane_len = 0;                              // FP64-lane tiles (refined pressure pencils)
     std::vector<unsigned char> blob;               // host image of the blob
     void *dev_const = nullptr;
     Profile prof;
@@ -159,6 +167,9 @@ hipError_t launch_correct(const Plan &p, const double *phi, double *u, double *v
                           double cp, hipStream_t s);
 hipError_t launch_residual(const Plan &p, int op, double c, const double *x,
                            const double *b, double *r, double *norms2, double *red, hipStream_t s);
+// rhs += the contribution of inhomogeneous wall data lo, hi ([nz][nx]).
+hipError_t launch_wall_data(const Plan &p, int op, double c, const double *lo, const double *hi,
+                            double *rhs, hipStream_t s);
 // Strict compatibility check of a Poisson rhs in FP64 (weighted mean against
 // weighted rms, on b itself): partial sums, then the verdict per job, which
 // sets st.incompat and, through the job's report, IBS_ERR_INCOMPATIBLE_RHS.

@@ -197,6 +197,54 @@ hipError_t launch_correct(const Plan &p, const double *phi, double *u, double *v
     return hipGetLastError();
 }
 
+// Inhomogeneous wall data (Appendix B's boundary terms, the pencil
+// right-hand sides BC2.2 forms): the operator with data is the homogeneous
+// one plus a term in the rows next to the walls, so the data move to the
+// right-hand side there before the transforms (transforming the data planes
+// and correcting the pencils, as the paper does, gives the same result by
+// linearity).  One thread per wall column (i, k); lo/hi null = zero data.
+//   Poisson (data: wall flux dphi/dy): b_0 += lo/Delta_0,
+//                                       b_{ny-1} -= hi/Delta_{ny-1}
+//   u, w (data: wall value, mirror ghost 2g - f_0):
+//       r_0 += 2c lo/Delta_0^2,  r_{ny-1} += 2c hi/Delta_{ny-1}^2
+//   v (data: wall-face value): r_1 += c lo/(Delta_0 delta_1),
+//       r_{ny-1} += c hi/(Delta_{ny-1} delta_{ny-1})
+__global__ __launch_bounds__(256) void wall_data_kernel(Geo g, int op, double c,
+                                                        const double *__restrict__ lo,
+                                                        const double *__restrict__ hi,
+                                                        double *__restrict__ rhs)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (i >= g.nx) return;
+    const size_t col = (size_t)k * g.nx + i;
+    const double gl = lo ? lo[col] : 0.0, gh = hi ? hi[col] : 0.0;
+    const int rows = op == IBS_OP_HELMHOLTZ_V ? g.ny + 1 : g.ny;
+    double *pl = rhs + ((size_t)k * rows) * g.nx + i;   // row 0 of this column
+    const size_t nx = g.nx;
+    const double D0 = g.dyc[0], D1 = g.dyc[g.ny - 1];
+    if (op == IBS_OP_POISSON) {
+        pl[0] += gl / D0;
+        pl[(g.ny - 1) * nx] -= gh / D1;
+    } else if (op == IBS_OP_HELMHOLTZ_V) {
+        pl[nx] += c * gl / (D0 * g.dyf[1]);
+        pl[(g.ny - 1) * nx] += c * gh / (D1 * g.dyf[g.ny - 1]);
+    } else {
+        pl[0] += 2.0 * c * gl / (D0 * D0);
+        pl[(g.ny - 1) * nx] += 2.0 * c * gh / (D1 * D1);
+    }
+}
+
+hipError_t launch_wall_data(const Plan &p, int op, double c, const double *lo, const double *hi,
+                            double *rhs, hipStream_t s)
+{
+    Geo g = geo_of(p);
+    dim3 blk = row_block(p.nx);
+    dim3 grid((p.nx + blk.x - 1) / blk.x, p.nz);
+    hipLaunchKernelGGL(wall_data_kernel, grid, blk, 0, s, g, op, c, lo, hi, rhs);
+    return hipGetLastError();
+}
+
 hipError_t launch_residual(const Plan &p, int op, double c, const double *x, const double *b,
                            double *r, double *norms2, double *red, hipStream_t s)
 {

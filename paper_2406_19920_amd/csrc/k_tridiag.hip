@@ -98,6 +98,14 @@ struct TriParams {
     int nx, nz;
     int poisson;
     double inv_sqrt_nxnz;
+    // pressure pencils of the refined path: the plan lists the 32-wide
+    // x-tiles (per z-mode) holding a pencil too ill-conditioned for FP32
+    // arithmetic (the FP64 lane).  lane_mode 0: every tile; 1: every tile
+    // but the FP64-lane ones (FP32 arithmetic); 2: only the FP64-lane tiles.
+    const unsigned *lane_mask;   // per z-mode: bit t = x-tile [32t, 32t+32) is in the FP64 lane
+    const int *lane_list;        // FP64-lane tiles as (c << 8) | t
+    int lane_len;
+    int lane_mode;
 };
 
 // T: storage type of the field (double, or float on the refined path);
@@ -127,6 +135,7 @@ __global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
     constexpr bool DB = P == 32 && M <= 9;
     __shared__ R sx[(DB ? 2 : 1) * NRS * LDR];
     __shared__ R slo[NRS], sdi[NRS], sup[NRS], sw[NRS];
+    __shared__ double xs_sm[NT / 64];   // per-wave sums of the x-sum partials
 
     const int tid = threadIdx.x;
     const int nx = tp.nx;
@@ -156,17 +165,32 @@ __global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
                                                  live ? (int)(jb.rows * row_bytes) : 0, 0x00020000);
     };
     auto decode = [&](int tile, int &job, int &c, int &a0) {
-        job = tile / (tp.nz * ntx);
-        const int rem = tile - job * tp.nz * ntx;
-        c = rem / ntx;
-        a0 = (rem - c * ntx) * TA;
+        if (tp.lane_mode == 2) {
+            // the listed 32-wide tiles, each as 32 / TA tiles of TA pencils
+            constexpr int per = 32 / TA;
+            const int per_job = tp.lane_len * per;
+            job = tile / per_job;
+            const int rem = tile - job * per_job;
+            const int e = tp.lane_list[rem / per];
+            c = e >> 8;
+            a0 = (e & 0xff) * 32 + (rem % per) * TA;
+        } else {
+            job = tile / (tp.nz * ntx);
+            const int rem = tile - job * tp.nz * ntx;
+            c = rem / ntx;
+            a0 = (rem - c * ntx) * TA;
+        }
+    };
+    // tiles left to the FP64 lane (lane_mode 1): block-uniform
+    auto lane_skipped = [&](int c, int a0) {
+        return tp.lane_mode == 1 && ((tp.lane_mask[c] >> (a0 >> 5)) & 1u);
     };
     // raw values only: conversion and wall rows are applied when the tile is
     // staged, so that nothing here waits for the loads
     auto fetch = [&](int tile, T (&pf)[M], double &plx, double &plz) {
         int job, c, a0;
         decode(tile < ntiles ? tile : ntiles - 1, job, c, a0);
-        const bool live = tile < ntiles && !((skipmask >> job) & 1);
+        const bool live = tile < ntiles && !((skipmask >> job) & 1) && !lane_skipped(c, a0);
         plx = tp.lam_x[a0 + p];
         plz = tp.lam_z[c];
         const auto rs = plane_rsrc(job, c, live);
@@ -187,7 +211,7 @@ __global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
         const FieldJob &jb = js.j[job];
         // the v systems leave out the first wall row (kept at zero below)
         const int kind = jb.kind, sys0 = skip_first_row(kind), n = jb.rows - sys0;
-        const bool live = !((skipmask >> job) & 1);   // block-uniform
+        const bool live = !((skipmask >> job) & 1) && !lane_skipped(c, a0);   // block-uniform
         // the previous tile's staging buffer is no longer read (the
         // coefficient rows below are free once its solve, which ends with a
         // barrier, is done)
@@ -215,6 +239,17 @@ __global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
             sx[lr(j) * LDR + lcol] = (walls && j == n - 1) ? R(0) : (R)pf[r];
         }
         const R sh = (R)(plx + plz);
+        if (live && tp.xsum && pois && a0 == 0 && c == 0) {
+            // refinement passes: the residual's partial sums of Delta_j x,
+            // summed by the whole block for the pinned pencil (fixed order:
+            // strided per thread, a butterfly per wave, the waves in order)
+            const double *xsp = tp.xsum + (size_t)job * XSUM_SLOTS;
+            double part = 0.0;
+            for (int q = tid; q < tp.nxsum; q += NT) part += xsp[q];
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) part += __shfl_xor(part, d, 64);
+            if ((tid & 63) == 0) xs_sm[tid >> 6] = part;
+        }
         __syncthreads();
         fetch(tile + 2 * (int)gridDim.x, pf, plx, plz);  // this buffer's next tile
         if (live) {
@@ -344,11 +379,9 @@ __global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
                 if (tp.xsum) {
                     // refinement: steer the correction so that x + d has zero
                     // weighted mean (in this pencil's normalisation)
-                    const double *xs = tp.xsum + (size_t)job * XSUM_SLOTS;
                     double part = 0.0;
-                    for (int q = k; q < tp.nxsum; q += P) part += xs[q];
 #pragma unroll
-                    for (int d = 1; d < P; d <<= 1) part += __shfl_xor(part, d, P);
+                    for (int w = 0; w < NT / 64; ++w) part += xs_sm[w];
                     mx += part * tp.inv_sqrt_nxnz / tp.wsum_y;
                 }
 #pragma unroll
@@ -413,8 +446,10 @@ static hipError_t launch_pm(const JobSet &js, const TriParams &tp, hipStream_t s
             return 1024;
         return per_cu * cus > 0 ? per_cu * cus : 1024;
     }();
+    static_assert(32 % TA == 0, "FP64-lane tiles are 32 pencils wide");
     const int ntx = tp.nx / TA;
-    const int ntiles = ntx * tp.nz * js.n;
+    const int ntiles = tp.lane_mode == 2 ? js.n * tp.lane_len * (32 / TA) : ntx * tp.nz * js.n;
+    if (ntiles == 0) return hipSuccess;
     const int pairs = (ntiles + 1) / 2;
     const int grid = pairs < resident ? pairs : resident;
     hipLaunchKernelGGL((tridiag_kernel<T, R, P, M, TA>), dim3(grid), dim3(TA * P), 0, s, js, tp, ntx,
@@ -491,6 +526,10 @@ static hipError_t launch_tridiag(const JobSet &js, const Plan &p, const State &s
     }
     if (pass >= 2) tp.skip = st.done;
     tp.inv_sqrt_nxnz = 1.0 / std::sqrt((double)p.nx * (double)p.nz);
+    tp.lane_mask = nullptr;
+    tp.lane_list = nullptr;
+    tp.lane_len = 0;
+    tp.lane_mode = 0;
     int n = 0;
     for (int q = 0; q < js.n; ++q) {
         const int rows = js.j[q].rows - skip_first_row(js.j[q].kind);   // system rows
@@ -501,6 +540,20 @@ static hipError_t launch_tridiag(const JobSet &js, const Plan &p, const State &s
     // condition numbers bounded by FP32_KAPPA.
     if constexpr (sizeof(T) == 4) {
         if (!poisson && helmholtz_kappa(js, p) <= FP32_KAPPA) return launch_by_rows<T, float>(js, tp, n, s);
+        if (poisson && p.lane_len > 0) {
+            // pressure pencils: FP32 arithmetic on every tile but the FP64
+            // lane's, then FP64 arithmetic on the lane's tiles (disjoint
+            // pencils; the lane holds the singular (0,0) pencil and every
+            // pencil whose condition bound exceeds LANE64_KAPPA)
+            tp.lane_mask = reinterpret_cast<const unsigned *>(blob_ptr(p, p.lay.lane_mask));
+            tp.lane_list = reinterpret_cast<const int *>(blob_ptr(p, p.lay.lane_list));
+            tp.lane_len = p.lane_len;
+            tp.lane_mode = 1;
+            hipError_t e = launch_by_rows<T, float>(js, tp, n, s);
+            if (e != hipSuccess) return e;
+            tp.lane_mode = 2;
+            return launch_by_rows<T, double>(js, tp, n, s);
+        }
     }
     return launch_by_rows<T, double>(js, tp, n, s);
 }

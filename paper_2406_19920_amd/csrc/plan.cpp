@@ -1,4 +1,5 @@
 // Host plan builder: grid, y operators, x/z eigenbases, device blob image.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -465,6 +466,32 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     L.sxf_inv = take(sfold_x ? sizeof(uint16_t) * 3 * 2 * hx2 : 0);
     L.szf_fwd = take(sfold_z ? sizeof(uint16_t) * 3 * 2 * hz2 : 0);
     L.szf_inv = take(sfold_z ? sizeof(uint16_t) * 3 * 2 * hz2 : 0);
+    // FP64 lane of the refined pressure pencils: a 32-wide x-tile of z-mode
+    // c joins it when any of its pencils is singular or has a condition
+    // bound 1 + g/|s| above LANE64_KAPPA
+    std::vector<uint32_t> lane_mask;
+    std::vector<int> lane_list;
+    if (split) {
+        double g = 0.0;
+        for (int j = 0; j < ny; ++j)
+            g = std::max(g, std::fabs(p->lo[KIND_P][j]) + std::fabs(p->di[KIND_P][j]) + std::fabs(p->up[KIND_P][j]));
+        lane_mask.assign(nz, 0u);
+        for (int c = 0; c < nz; ++c)
+            for (int t = 0; t < nx / 32; ++t) {
+                bool need = false;
+                for (int a = 32 * t; a < 32 * t + 32 && !need; ++a) {
+                    const double sabs = std::fabs(p->lam_x[a] + p->lam_z[c]);
+                    need = sabs == 0.0 || 1.0 + g / sabs > LANE64_KAPPA;
+                }
+                if (need) {
+                    lane_mask[c] |= 1u << t;
+                    lane_list.push_back((c << 8) | t);
+                }
+            }
+    }
+    p->lane_len = (int)lane_list.size();
+    L.lane_mask = take(sizeof(uint32_t) * lane_mask.size());
+    L.lane_list = take(sizeof(int) * lane_list.size());
     L.total = o;
     p->blob.assign(L.total, 0);
     auto put = [&](size_t off, const double *src, size_t n) {
@@ -497,6 +524,8 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
         put16(sfold_z ? L.szf_fwd : L.sz_fwd, az->split[0]);
         put16(sfold_z ? L.szf_inv : L.sz_inv, az->split[1]);
     }
+    if (!lane_mask.empty()) std::memcpy(p->blob.data() + L.lane_mask, lane_mask.data(), 4 * lane_mask.size());
+    if (!lane_list.empty()) std::memcpy(p->blob.data() + L.lane_list, lane_list.data(), 4 * lane_list.size());
     put(L.lam_x, p->lam_x.data(), nx);
     put(L.lam_z, p->lam_z.data(), nz);
     for (int kd = 0; kd < NUM_KINDS; ++kd) {

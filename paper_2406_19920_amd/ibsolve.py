@@ -32,7 +32,7 @@ IBS_OP_POISSON, IBS_OP_HELMHOLTZ_U, IBS_OP_HELMHOLTZ_V, IBS_OP_HELMHOLTZ_W = 0, 
 # every exported entry point of include/ibsolve.h
 EXPORTS = ("solver_plan", "solver_plan_bytes", "solver_plan_upload", "solver_plan_destroy",
            "solve_poisson", "solve_poisson_noalloc", "solve_helmholtz_batch", "residual",
-           "ibs_divergence",
+           "ibs_divergence", "ibs_wall_data",
            "ibs_correct", "ibs_plan_export", "ibs_profile", "ibs_profile_read",
            "ibs_batch_build", "ibs_batch_launch", "ibs_batch_destroy",
            "ibs_autotune_bytes", "ibs_autotune", "ibs_plan_set_tiles",
@@ -92,6 +92,7 @@ def _load():
                                         ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz, vp, vp]
     L.residual.argtypes = [vp, i32, dbl, vp, vp, vp, vp, vp, sz, vp]
     L.ibs_divergence.argtypes = [vp, vp, vp, vp, vp, dbl, vp]
+    L.ibs_wall_data.argtypes = [vp, i32, dbl, vp, vp, vp, vp]
     L.ibs_correct.argtypes = [vp, vp, vp, vp, vp, dbl, vp, vp, dbl, vp]
     L.ibs_plan_export.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(sz)]
     L.ibs_profile.argtypes = [vp, i32]
@@ -193,6 +194,10 @@ def residual(plan, op, c, x, b, r, norms2, work, work_bytes, stream):
 
 def ibs_divergence(plan, u, v, w, b, scale, stream):
     _check(lib.ibs_divergence(plan, u, v, w, b, scale, stream), "ibs_divergence")
+
+
+def ibs_wall_data(plan, op, c, lo, hi, rhs, stream):
+    _check(lib.ibs_wall_data(plan, op, c, lo, hi, rhs, stream), "ibs_wall_data")
 
 
 def ibs_correct(plan, phi, u, v, w, g, p, lap_phi, cp, stream):
@@ -337,6 +342,18 @@ class Solver:
         ibs_divergence(self.plan, u.data_ptr(), v.data_ptr(), w.data_ptr(), b.data_ptr(), scale,
                        self.stream())
         return b
+
+    def wall_data(self, op, rhs, lo=None, hi=None, c=0.0):
+        """Add the wall data's contribution to rhs in place (lo, hi:
+        [nz][nx] device tensors or None)."""
+        self._chk(rhs, op)
+        for d in (lo, hi):
+            if d is not None:
+                assert d.dtype == self.torch.float64 and d.is_contiguous()
+                assert tuple(d.shape) == (self.nz, self.nx)
+        ibs_wall_data(self.plan, op, c, lo.data_ptr() if lo is not None else None,
+                      hi.data_ptr() if hi is not None else None, rhs.data_ptr(), self.stream())
+        return rhs
 
     def correct(self, phi, u, v, w, g, p=None, lap_phi=None, cp=0.0):
         ibs_correct(self.plan, phi.data_ptr(), u.data_ptr(), v.data_ptr(), w.data_ptr(), g,
