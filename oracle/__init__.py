@@ -94,7 +94,8 @@ class _CGeom(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("hx", ctypes.c_double), ("hz", ctypes.c_double),
                 ("dyc", ctypes.POINTER(ctypes.c_double)),
-                ("dyf", ctypes.POINTER(ctypes.c_double))]
+                ("dyf", ctypes.POINTER(ctypes.c_double)),
+                ("py", ctypes.c_int)]
 
 
 class _CInfo(ctypes.Structure):
@@ -107,7 +108,10 @@ class _CInfo(ctypes.Structure):
 class Grid:
     """Staggered grid: uniform periodic x and z, walls in y (optionally
     tanh-stretched faces).  Section 2.1 describes the uniform staggered grid;
-    the tanh stretching in y is this library's extension."""
+    the tanh stretching in y is this library's extension.  periodic_y: the
+    triply periodic branch (Section 2.3.3, items S1 and S2): y wraps, no
+    walls, v has ny faces, and delta_0 = delta_ny is the distance between
+    the centres of cells ny-1 and 0 across the wrap."""
     nx: int
     ny: int
     nz: int
@@ -116,6 +120,7 @@ class Grid:
     lz: float = 1.0
     beta: float = 0.0
     yf_in: np.ndarray | None = None
+    periodic_y: bool = False
     yf: np.ndarray = field(init=False)
     yc: np.ndarray = field(init=False)
     dyc: np.ndarray = field(init=False)
@@ -136,8 +141,12 @@ class Grid:
                             _dp(self.yf), _dp(self.yc), _dp(self.dyc), _dp(self.dyf))
         if rc != 0:
             raise ValueError(f"orc_grid failed ({rc})")
+        if self.periodic_y:
+            if ny < 3:
+                raise ValueError("periodic y needs ny >= 3")
+            self.dyf[0] = self.dyf[ny] = 0.5 * (self.dyc[0] + self.dyc[ny - 1])
         self._c = _CGeom(self.nx, self.ny, self.nz, self.hx, self.hz,
-                         _dp(self.dyc), _dp(self.dyf))
+                         _dp(self.dyc), _dp(self.dyf), 1 if self.periodic_y else 0)
 
     @property
     def hx(self) -> float:
@@ -148,7 +157,9 @@ class Grid:
         return self.lz / self.nz
 
     def shape(self, op: int) -> tuple:
-        return (self.nz, self.ny + 1, self.nx) if op == OP_V else (self.nz, self.ny, self.nx)
+        if op == OP_V and not self.periodic_y:
+            return (self.nz, self.ny + 1, self.nx)
+        return (self.nz, self.ny, self.nx)
 
     @property
     def cptr(self):
@@ -195,7 +206,7 @@ def weights(g: Grid, op: int) -> np.ndarray:
 
 def unknowns_of(g: Grid, op: int, x: np.ndarray) -> np.ndarray:
     """Flatten a full-layout field to the unknown ordering (drops v walls)."""
-    if op == OP_V:
+    if op == OP_V and not g.periodic_y:
         return np.ascontiguousarray(x[:, 1:g.ny, :]).reshape(-1)
     return np.ascontiguousarray(x).reshape(-1)
 
@@ -250,6 +261,8 @@ def solve_bc(g: Grid, op: int, b, lo=None, hi=None, c: float = 0.0, tol: float =
     x has zero weighted mean.  v: the returned wall faces hold the data.
     Returns (x, info)."""
     b = np.ascontiguousarray(b, dtype=np.float64)
+    if g.periodic_y:
+        raise ValueError("wall data need walls (periodic y has none)")
     zero = np.zeros(g.shape(op))
     r0, _, _ = residual_bc_ld(g, op, c, zero, b, lo, hi)   # b - A(0; lo, hi)
     x, info = solve(g, op, r0, c=c, tol=tol)

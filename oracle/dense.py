@@ -12,7 +12,10 @@ differences on a staggered grid) and Appendix B (wall rows):
   (faces <- cells, zero on the wall faces: homogeneous Neumann);
 * the operator for u and w (stored at cell-centre height) uses, at a wall,
   the flux of a mirror ghost value (Dirichlet u = 0 half a cell away);
-* the operator for v (interior y faces) is G_y D_y with wall values v = 0.
+* the operator for v (interior y faces) is G_y D_y with wall values v = 0;
+* periodic y (the triply periodic branch): the y differences wrap, the
+  pressure Laplacian is still literally D G, u and w take D_y G_y and v
+  G_y D_y over all ny faces.
 
 The dense solve uses ``numpy.linalg.solve``.  For the singular Neumann
 pressure problem it solves the bordered system
@@ -75,6 +78,27 @@ def gy_cells_to_faces_dirichlet_mirror(g: Grid) -> np.ndarray:
     return m
 
 
+def dy_faces_to_cells_periodic(g: Grid) -> np.ndarray:
+    """(ny x ny), periodic y: (F_{j+1} - F_j)/Delta_j, face ny = face 0."""
+    ny = g.ny
+    m = np.zeros((ny, ny))
+    for j in range(ny):
+        m[j, (j + 1) % ny] += 1.0 / g.dyc[j]
+        m[j, j] -= 1.0 / g.dyc[j]
+    return m
+
+
+def gy_cells_to_faces_periodic(g: Grid) -> np.ndarray:
+    """(ny x ny), periodic y: (f_j - f_{j-1})/delta_j on every face, face 0
+    between cells ny-1 and 0 (delta_0 across the wrap)."""
+    ny = g.ny
+    m = np.zeros((ny, ny))
+    for j in range(ny):
+        m[j, j] += 1.0 / g.dyf[j]
+        m[j, (j - 1) % ny] -= 1.0 / g.dyf[j]
+    return m
+
+
 def _k3(az, ay, ax):
     return np.kron(az, np.kron(ay, ax))
 
@@ -83,7 +107,7 @@ def divergence_matrix(g: Grid) -> np.ndarray:
     """D: cells <- (u faces, v faces incl. walls, w faces)."""
     Ix, Iy, Iz = np.eye(g.nx), np.eye(g.ny), np.eye(g.nz)
     Du = _k3(Iz, Iy, _circ_diff_fwd(g.nx, g.hx))
-    Dv = _k3(Iz, dy_faces_to_cells(g), Ix)
+    Dv = _k3(Iz, dy_faces_to_cells_periodic(g) if g.periodic_y else dy_faces_to_cells(g), Ix)
     Dw = _k3(_circ_diff_fwd(g.nz, g.hz), Iy, Ix)
     return np.hstack([Du, Dv, Dw])
 
@@ -92,7 +116,7 @@ def gradient_matrix(g: Grid) -> np.ndarray:
     """G: (u faces, v faces incl. walls, w faces) <- cells."""
     Ix, Iy, Iz = np.eye(g.nx), np.eye(g.ny), np.eye(g.nz)
     Gu = _k3(Iz, Iy, _circ_diff_bwd(g.nx, g.hx))
-    Gv = _k3(Iz, gy_cells_to_faces_neumann(g), Ix)
+    Gv = _k3(Iz, gy_cells_to_faces_periodic(g) if g.periodic_y else gy_cells_to_faces_neumann(g), Ix)
     Gw = _k3(_circ_diff_bwd(g.nz, g.hz), Iy, Ix)
     return np.vstack([Gu, Gv, Gw])
 
@@ -104,7 +128,15 @@ def laplacian(g: Grid, op: int) -> np.ndarray:
         return divergence_matrix(g) @ gradient_matrix(g)
     Lx = _circ_diff_bwd(g.nx, g.hx) @ _circ_diff_fwd(g.nx, g.hx)
     Lz = _circ_diff_bwd(g.nz, g.hz) @ _circ_diff_fwd(g.nz, g.hz)
-    if op in (OP_U, OP_W):
+    if g.periodic_y:
+        Iy = np.eye(g.ny)
+        if op in (OP_U, OP_W):
+            Ly = dy_faces_to_cells_periodic(g) @ gy_cells_to_faces_periodic(g)
+        elif op == OP_V:
+            Ly = gy_cells_to_faces_periodic(g) @ dy_faces_to_cells_periodic(g)
+        else:
+            raise ValueError(op)
+    elif op in (OP_U, OP_W):
         Ly = dy_faces_to_cells(g) @ gy_cells_to_faces_dirichlet_mirror(g)
         Iy = np.eye(g.ny)
     elif op == OP_V:
@@ -117,7 +149,10 @@ def laplacian(g: Grid, op: int) -> np.ndarray:
 
 
 def weights(g: Grid, op: int) -> np.ndarray:
-    if op == OP_V:
+    if op == OP_V and g.periodic_y:
+        wy = g.dyf[:g.ny]
+        nyu = g.ny
+    elif op == OP_V:
         wy = g.dyf[1:g.ny]
         nyu = g.ny - 1
     else:
@@ -135,7 +170,8 @@ def operator(g: Grid, op: int, c: float = 0.0) -> np.ndarray:
 
 def solve(g: Grid, op: int, b: np.ndarray, c: float = 0.0) -> np.ndarray:
     """Dense solve; b and the result in the full array layout."""
-    if op == OP_V:
+    walls = op == OP_V and not g.periodic_y
+    if walls:
         rhs = np.ascontiguousarray(b[:, 1:g.ny, :]).reshape(-1)
     else:
         rhs = np.ascontiguousarray(b).reshape(-1)
@@ -151,7 +187,7 @@ def solve(g: Grid, op: int, b: np.ndarray, c: float = 0.0) -> np.ndarray:
     else:
         sol = np.linalg.solve(A, rhs)
     out = np.zeros(g.shape(op))
-    if op == OP_V:
+    if walls:
         out[:, 1:g.ny, :] = sol.reshape(g.nz, g.ny - 1, g.nx)
     else:
         out[...] = sol.reshape(g.shape(op))

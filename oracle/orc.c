@@ -34,6 +34,13 @@
  * [nz][ny+1][nx], faces j = 0 and j = ny being the walls (ignored on input,
  * written as zero on output).
  *
+ * Triply periodic variant (geometry flag py; the paper's 3-periodic branch,
+ * Section 2.3.3, items S1 and S2): y wraps like x and z, every operator uses
+ * its interior formula everywhere (the distance across the wrap,
+ * (Delta_0 + Delta_{ny-1})/2, is delta_0 = delta_ny), v has ny faces
+ * ([nz][ny][nx], face ny being face 0), and the pressure's null mode is
+ * fixed by the same zero weighted mean.
+ *
  * Operator codes: 0 = pressure Poisson (A = L_p), 1 = u Helmholtz,
  * 2 = v Helmholtz, 3 = w Helmholtz (A = I - c L).
  */
@@ -50,7 +57,12 @@ typedef struct {
     double hx, hz;
     const double *dyc; /* [ny]    cell heights Delta_j                  */
     const double *dyf; /* [ny+1]  centre-to-centre distances delta_j,   */
-                       /*         valid for j = 1..ny-1                 */
+                       /*         valid for j = 1..ny-1 (periodic y:    */
+                       /*         also j = 0 and ny, the distance       */
+                       /*         across the wrap)                      */
+    int py;            /* 1: y periodic too (the triply periodic        */
+                       /*    branch, Section 2.3.3, items S1/S2): no    */
+                       /*    walls, v has ny faces [nz][ny][nx]         */
 } orc_geom;
 
 typedef struct {
@@ -100,9 +112,10 @@ static inline int64_t cidx(const orc_geom *g, int i, int j, int k)
 {
     return ((int64_t)k * g->ny + j) * g->nx + i;
 }
+static inline int vrows(const orc_geom *g) { return g->py ? g->ny : g->ny + 1; }
 static inline int64_t vidx(const orc_geom *g, int i, int j, int k)
 {
-    return ((int64_t)k * (g->ny + 1) + j) * g->nx + i;
+    return ((int64_t)k * vrows(g) + j) * g->nx + i;
 }
 static inline int wrap(int i, int n) { return (i % n + n) % n; }
 
@@ -120,7 +133,8 @@ void orc_divergence(const orc_geom *g, const double *u, const double *v,
         for (int j = 0; j < g->ny; ++j)
             for (int i = 0; i < g->nx; ++i) {
                 double du = (u[cidx(g, wrap(i + 1, g->nx), j, k)] - u[cidx(g, i, j, k)]) / g->hx;
-                double dv = (v[vidx(g, i, j + 1, k)] - v[vidx(g, i, j, k)]) / g->dyc[j];
+                int jt = (g->py && j + 1 == g->ny) ? 0 : j + 1;   /* face ny = face 0 */
+                double dv = (v[vidx(g, i, jt, k)] - v[vidx(g, i, j, k)]) / g->dyc[j];
                 double dw = (w[cidx(g, i, j, wrap(k + 1, g->nz))] - w[cidx(g, i, j, k)]) / g->hz;
                 b[cidx(g, i, j, k)] = scale * (du + dv + dw);
             }
@@ -134,8 +148,19 @@ void orc_gradient(const orc_geom *g, const double *phi, double *gu, double *gv,
 {
 #pragma omp parallel for collapse(2)
     for (int k = 0; k < g->nz; ++k)
-        for (int j = 0; j <= g->ny; ++j)
+        for (int j = 0; j < vrows(g); ++j)
             for (int i = 0; i < g->nx; ++i) {
+                if (g->py) {
+                    /* every face is interior; face 0 lies between cells
+                     * ny-1 and 0, dyf[0] apart */
+                    gu[cidx(g, i, j, k)] =
+                        (phi[cidx(g, i, j, k)] - phi[cidx(g, wrap(i - 1, g->nx), j, k)]) / g->hx;
+                    gw[cidx(g, i, j, k)] =
+                        (phi[cidx(g, i, j, k)] - phi[cidx(g, i, j, wrap(k - 1, g->nz))]) / g->hz;
+                    gv[vidx(g, i, j, k)] =
+                        (phi[cidx(g, i, j, k)] - phi[cidx(g, i, wrap(j - 1, g->ny), k)]) / g->dyf[j];
+                    continue;
+                }
                 if (j < g->ny) {
                     gu[cidx(g, i, j, k)] =
                         (phi[cidx(g, i, j, k)] - phi[cidx(g, wrap(i - 1, g->nx), j, k)]) / g->hx;
@@ -154,25 +179,32 @@ void orc_gradient(const orc_geom *g, const double *phi, double *gu, double *gv,
 /* Unknown numbering.                                                  */
 /* ------------------------------------------------------------------ */
 
+/* y unknowns per column: v has the interior faces 1..ny-1 with walls, all
+ * ny faces when y is periodic; cell fields have ny */
+static int ny_unknowns(const orc_geom *g, int op)
+{
+    return (op == 2 && !g->py) ? g->ny - 1 : g->ny;
+}
+static int first_y(const orc_geom *g, int op) { return (op == 2 && !g->py) ? 1 : 0; }
 static int64_t n_unknowns(const orc_geom *g, int op)
 {
-    int nyu = (op == 2) ? g->ny - 1 : g->ny;
-    return (int64_t)g->nx * nyu * g->nz;
+    return (int64_t)g->nx * ny_unknowns(g, op) * g->nz;
 }
-/* (i, j, k) of unknown number r; for op 2, j is the face index 1..ny-1 */
+/* (i, j, k) of unknown number r; for op 2 with walls, j is the face index
+ * 1..ny-1 */
 static void unknown_ijk(const orc_geom *g, int op, int64_t r, int *i, int *j,
                         int *k)
 {
-    int nyu = (op == 2) ? g->ny - 1 : g->ny;
+    int nyu = ny_unknowns(g, op);
     *i = (int)(r % g->nx);
     int64_t t = r / g->nx;
-    *j = (int)(t % nyu) + (op == 2 ? 1 : 0);
+    *j = (int)(t % nyu) + first_y(g, op);
     *k = (int)(t / nyu);
 }
 static int64_t unknown_id(const orc_geom *g, int op, int i, int j, int k)
 {
-    int nyu = (op == 2) ? g->ny - 1 : g->ny;
-    int jj = (op == 2) ? j - 1 : j;
+    int nyu = ny_unknowns(g, op);
+    int jj = j - first_y(g, op);
     return ((int64_t)k * nyu + jj) * g->nx + i;
 }
 /* position of unknown r in the caller's full array layout */
@@ -217,6 +249,25 @@ static int laplacian_row(const orc_geom *g, int op, int i, int j, int k,
     n = add_entry(cols, vals, n, unknown_id(g, op, i, j, wrap(k - 1, g->nz)), az);
     n = add_entry(cols, vals, n, unknown_id(g, op, i, j, wrap(k + 1, g->nz)), az);
     const int ny = g->ny;
+    if (g->py) {
+        /* periodic y: the same interior formulas everywhere, neighbours
+         * wrapping (cells: fluxes over delta; faces: over Delta) */
+        int jn = wrap(j + 1, ny), js = wrap(j - 1, ny);
+        double au, al;
+        if (op == 2) {
+            double d = g->dyf[j];
+            au = 1.0 / (g->dyc[j] * d);
+            al = 1.0 / (g->dyc[js] * d);
+        } else {
+            double D = g->dyc[j];
+            au = 1.0 / (g->dyf[j + 1] * D);
+            al = 1.0 / (g->dyf[j] * D);
+        }
+        n = add_entry(cols, vals, n, me, -au - al);
+        n = add_entry(cols, vals, n, unknown_id(g, op, i, jn, k), au);
+        n = add_entry(cols, vals, n, unknown_id(g, op, i, js, k), al);
+        return n;
+    }
     if (op == 0 || op == 1 || op == 3) {
         /* cell-centre height: (F_{j+1/2} - F_{j-1/2}) / Delta_j */
         double D = g->dyc[j];
@@ -321,6 +372,20 @@ static long double flux_apply_bc_ld(const orc_geom *g, int op, int i, int j, int
     long double xe = x[at(g, wrap(i + 1, nx), j, k)], xw = x[at(g, wrap(i - 1, nx), j, k)];
     long double xt = x[at(g, i, j, wrap(k + 1, nz))], xb = x[at(g, i, j, wrap(k - 1, nz))];
     long double lap = ((xe - xc) / hx - (xc - xw) / hx) / hx + ((xt - xc) / hz - (xc - xb) / hz) / hz;
+    if (g->py) {
+        int jn = wrap(j + 1, ny), js = wrap(j - 1, ny);
+        long double xn = x[at(g, i, jn, k)], xs = x[at(g, i, js, k)];
+        if (op == 2) {
+            long double fu = (xn - xc) / (long double)g->dyc[j];
+            long double fl = (xc - xs) / (long double)g->dyc[js];
+            lap += (fu - fl) / (long double)g->dyf[j];
+        } else {
+            long double fu = (xn - xc) / (long double)g->dyf[j + 1];
+            long double fl = (xc - xs) / (long double)g->dyf[j];
+            lap += (fu - fl) / (long double)g->dyc[j];
+        }
+        return lap;
+    }
     if (op != 2) {
         long double D = g->dyc[j];
         long double fu, fl;
@@ -369,7 +434,7 @@ void orc_residual_bc_ld(const orc_geom *g, int op, double c, const double *x,
         rr += res * res;
         bb += (long double)b[a] * (long double)b[a];
     }
-    if (op == 2) {
+    if (op == 2 && !g->py) {
         for (int k = 0; k < g->nz; ++k)
             for (int i = 0; i < g->nx; ++i) {
                 r[vidx(g, i, 0, k)] = 0.0;
@@ -524,7 +589,7 @@ int orc_solve(const orc_geom *g, int op, double c, const double *b_in, double *x
         for (int64_t q = 0; q < n; ++q) x[q] -= m;
     }
     /* write out, evaluate the long double residual of the projected b */
-    int64_t nfull = (op == 2) ? (int64_t)g->nx * (g->ny + 1) * g->nz
+    int64_t nfull = (op == 2) ? (int64_t)g->nx * vrows(g) * g->nz
                               : (int64_t)g->nx * g->ny * g->nz;
     double *full_b = calloc(nfull, sizeof(double));
     full_r = calloc(nfull, sizeof(double));

@@ -362,3 +362,97 @@ def test_wall_data_superposition():
         x0, _ = oracle.solve(g, op, b, c=c)
         xd, _ = oracle.solve_bc(g, op, np.zeros_like(b), lo, hi, c=c)
         assert np.abs(x - (x0 + xd)).max() < 1e-11 * np.abs(x).max(), op
+
+
+# ------------------------------------------------------------------------
+# Triply periodic branch (Section 2.3.3, items S1 and S2): y wraps too
+# ------------------------------------------------------------------------
+def _mode_y_periodic(ny, b, op, kind):
+    """Fourier modes in y: cells at j + 1/2, v faces at j."""
+    j = np.arange(ny) + (0.0 if op == OP_V else 0.5)
+    return np.cos(2 * np.pi * b * j / ny) if kind == "c" else np.sin(2 * np.pi * b * j / ny)
+
+
+@pytest.mark.parametrize("op", [OP_P, OP_U, OP_V, OP_W])
+@pytest.mark.parametrize("shape", [(8, 6, 4), (16, 12, 10), (12, 16, 8)])
+def test_periodic_p1_eigenmodes(op, shape):
+    """Products of 1-D Fourier modes are exact eigenvectors of every
+    operator, with the modified wavenumbers of Appendix A in all three
+    directions (the 3-D sum kappa'^2, as in subroutines S1 and S2)."""
+    nx, ny, nz = shape
+    g = oracle.Grid(nx, ny, nz, lx=1.0, ly=1.3, lz=0.7, periodic_y=True)
+    rng = np.random.default_rng(6)
+    c = 2e-3
+    for _ in range(4):
+        a, b, cz = (int(rng.integers(0, n // 2 + 1)) for n in (nx, ny, nz))
+        if op == OP_P and a == 0 and b == 0 and cz == 0:
+            b = 1
+        m = (_mode_x(nz, cz, "c" if rng.random() < 0.5 or cz == 0 else "s")[:, None, None]
+             * _mode_y_periodic(ny, b, op, "c" if rng.random() < 0.5 or b == 0 else "s")[None, :, None]
+             * _mode_x(nx, a, "c" if rng.random() < 0.5 or a == 0 else "s")[None, None, :])
+        if np.abs(m).max() < 1e-8:
+            continue
+        lam = (_lam_periodic(nx, g.hx, a) + _lam_periodic(nz, g.hz, cz)
+               + _lam_periodic(ny, g.ly / ny, b))
+        if op == OP_P:
+            x, info = oracle.solve(g, op, lam * m)
+            ref = m - oracle.weighted_mean(g, OP_P, m)
+        else:
+            x, info = oracle.solve(g, op, (1.0 - c * lam) * m, c=c)
+            ref = m
+        err = np.linalg.norm((x - ref).ravel()) / np.linalg.norm(ref.ravel())
+        assert err < 1e-13, (op, shape, a, b, cz, err, info)
+
+
+@pytest.mark.parametrize("beta", [0.0, 2.0])
+@pytest.mark.parametrize("shape", [(8, 6, 4), (4, 8, 8), (3, 5, 2), (6, 3, 4)])
+@pytest.mark.parametrize("op", [OP_P, OP_U, OP_V, OP_W])
+def test_periodic_p2_dense_bruteforce(op, shape, beta):
+    nx, ny, nz = shape
+    g = oracle.Grid(nx, ny, nz, beta=beta, periodic_y=True)
+    b = synth.scalar(nx, ny, nz, seed=12)
+    c = 0.0 if op == OP_P else 3e-3
+    xd = dense.solve(g, op, b, c)
+    xo, info = oracle.solve(g, op, b, c=c)
+    err = np.linalg.norm((xo - xd).ravel()) / np.linalg.norm(xd.ravel())
+    assert err < 1e-13, (err, info)
+
+
+@pytest.mark.parametrize("beta", [0.0, 2.0])
+@pytest.mark.parametrize("op", [OP_P, OP_U, OP_V, OP_W])
+def test_periodic_p3_structure(op, beta):
+    g = oracle.Grid(6, 7, 5, lx=1.2, ly=0.9, lz=0.8, beta=beta, periodic_y=True)
+    if op == OP_P:
+        A = _csr_dense(g, op)
+        np.testing.assert_allclose(A, dense.divergence_matrix(g) @ dense.gradient_matrix(g),
+                                   rtol=1e-13, atol=1e-9)
+        L = A
+        assert np.abs(L @ np.ones(L.shape[0])).max() < 1e-9 * np.abs(L).max()
+    else:
+        c = 0.37
+        A = _csr_dense(g, op, c)
+        np.testing.assert_allclose(A, np.eye(A.shape[0]) - c * dense.laplacian(g, op),
+                                   rtol=1e-13, atol=1e-9)
+        L = (np.eye(A.shape[0]) - A) / c
+        # no walls: constants are in the null space of every Laplacian
+        assert np.abs(L @ np.ones(L.shape[0])).max() < 1e-9 * np.abs(L).max()
+    w = oracle.weights(g, op)
+    np.testing.assert_allclose(w, dense.weights(g, op), rtol=1e-15)
+    WL = w[:, None] * L
+    assert np.abs(WL - WL.T).max() < 1e-12 * np.abs(WL).max()
+    x = synth.scalar(6, 7, 5, 3)
+    r, _, _ = oracle.residual_ld(g, op, 0.0 if op == OP_P else 0.37, x, np.zeros_like(x))
+    np.testing.assert_allclose(oracle.unknowns_of(g, op, -r), A @ x.reshape(-1), rtol=1e-10,
+                               atol=1e-9 * np.abs(A).max())
+
+
+def test_periodic_p4_projection_divergence_free():
+    nx, ny, nz = 16, 12, 8
+    g = oracle.Grid(nx, ny, nz, beta=1.0, periodic_y=True)
+    u, v, w = (synth.scalar(nx, ny, nz, s) for s in (1, 2, 3))
+    d0 = oracle.divergence(g, u, v, w)
+    phi, info = oracle.solve(g, OP_P, d0)
+    assert abs(info.removed_mean) < 1e-12 * np.abs(d0).max()   # periodic: compatible
+    gu, gv, gw = oracle.gradient(g, phi)
+    d1 = oracle.divergence(g, u - gu, v - gv, w - gw)
+    assert np.abs(d1).max() <= 1e-12 * np.abs(d0).max()
