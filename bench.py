@@ -303,6 +303,10 @@ def main():
                          "refined": {k: c3["refined"][k] for k in ("value", "ms_per_step", "status", "passes")},
                          "fp64": {k: c3["fp64"][k] for k in ("value", "ms_per_step", "status", "passes")},
                          "unit": "Mcell-solves/s"}
+        log("config 3p")
+        r3, w3 = run_3p(10, 2)
+        configs["triply_periodic"] = {"workload": w3, "steps": 10, "warmup": 2,
+                                      "unit": "Mcell-solves/s", **r3}
         log("config c4")
         configs["c4"] = run_batch(5, 1)
         log("config c5")
@@ -498,6 +502,51 @@ def run_c3(steps, warmup):
     del ru, rv, rw
     torch.cuda.empty_cache()
     return res, "512x384x384, beta=2, N(0,1) + forcing shell, c=%.4e" % c
+
+
+def run_3p(steps, warmup, n=256):
+    """The triply periodic branch (periodic y too, uniform grid; cyclic y
+    pencils) at n^3, both paths: one step of 3 Helmholtz + divergence +
+    Poisson + correction on N(0,1) low-pass filtered velocities."""
+    import torch
+    from paper_2406_19920_amd import ibsolve as ibs, synth
+    dev = torch.device("cuda:0")
+    log(f"inputs {n}^3 triply periodic")
+    u, v, w = synth.filtered_velocity(n, n, n, seed=6, kmax=16.0, zero_wall_v=False)
+    v = np.ascontiguousarray(v[:, :n, :])
+    c = 0.125 * (1.0 / n) ** 2
+    ru, rv, rw = (torch.from_numpy(a).to(dev) for a in (u, v, w))
+    res = {}
+    for path, prec in (("refined", ibs.IBS_REFINED_BF16X3), ("fp64", ibs.IBS_FP64)):
+        kw = {"max_iter": 2} if prec != ibs.IBS_FP64 else {}
+        S = ibs.Solver(n, n, n, precision=prec, bc_y_vel=ibs.IBS_PERIODIC, bc_y_p=ibs.IBS_PERIODIC, **kw)
+        tiles = S.autotune() if prec == ibs.IBS_FP64 else None   # set-up, untimed
+        xu, xv, xw = S.empty(1), S.empty(2), S.empty(3)
+        b, phi = S.empty(0), S.empty(0)
+
+        def step():
+            S.helmholtz([0, 1, 2], [c, c, c], [ru, rv, rw], [xu, xv, xw], info_slot=1)
+            S.divergence(xu, xv, xw, 1.0, b)
+            S.poisson(b, phi)
+            S.correct(phi, xu, xv, xw, 1.0)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        res[path] = {"value": 4 * n ** 3 / (ms * 1e-3) / 1e6, "ms_per_step": ms,
+                     "status": [S.read_info(q).status for q in range(4)],
+                     "passes": {"helmholtz": [S.read_info(q).iters for q in (1, 2, 3)],
+                                "poisson": S.read_info(0).iters},
+                     "predicted_rel_err": ([S.read_info(q).rel_residual for q in range(4)]
+                                           if prec != ibs.IBS_FP64 else None),
+                     "tiles": tiles}
+        S.close()
+    return res, f"{n}^3 uniform, periodic in x, y and z, N(0,1) filtered to k <= 16, c = {c:.4e}"
 
 
 def bench_c3(args):

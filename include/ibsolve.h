@@ -80,8 +80,15 @@ typedef enum { IBS_PERIODIC = 0, IBS_DIRICHLET = 1, IBS_NEUMANN = 2 } ibs_bc;
  * hx = lx/nx, hz = lz/nz; y faces y_f[j] = (ly/2)(1 + tanh(beta(2j/ny-1))/
  * tanh(beta)), j = 0..ny (beta = 0: uniform), unless y_faces is given.
  * Supported: nx, nz multiples of 16 in [16, 1024] (refined path: multiples
- * of 32, at most 512); ny in [2, 768];
- * bc_x = bc_z = IBS_PERIODIC; bc_y_vel = IBS_DIRICHLET; bc_y_p = IBS_NEUMANN. */
+ * of 32, at most 512); ny in [2, 768]; bc_x = bc_z = IBS_PERIODIC and
+ * either walls in y (bc_y_vel = IBS_DIRICHLET, bc_y_p = IBS_NEUMANN) or
+ * periodic y (bc_y_vel = bc_y_p = IBS_PERIODIC: the triply periodic
+ * branch of Section 2.3.3, items S1/S2; ny in {48, 64, 80, 96, 128, 160,
+ * 192, 256, 320, 384, 512}; the y faces, stretched or not, wrap: the
+ * centres of cells ny-1 and 0 are (Delta_0 + Delta_{ny-1})/2 apart).  With
+ * periodic y there are no walls: v is [nz][ny][nx] (face j at y_f[j],
+ * face ny being face 0), the y pencils are cyclic, and the pressure's null
+ * mode is fixed by the same zero volume-weighted mean. */
 typedef struct {
     int32_t nx, ny, nz;
     double lx, ly, lz;        /* <= 0 means 1                                */
@@ -293,7 +300,10 @@ ibs_status ibs_batch_destroy(ibs_batch batch);
  * table: 0 y faces [ny+1]; 1 Q_x [nx*nx] (row-major, Q[i*nx+a] = mode a at
  * grid index i); 2 Q_z [nz*nz]; 3 lambda_x [nx]; 4 lambda_z [nz];
  * 5+3*kind+{0,1,2}: lower, diagonal, upper coefficients [ny+1] of the y
- * operator of kind 0 (pressure), 1 (u, w), 2 (v, rows = faces 0..ny).
+ * operator of kind 0 (pressure), 1 (u, w), 2 (v, rows = faces 0..ny), 3 (v
+ * of a periodic-y plan, rows = faces 0..ny-1).  With periodic y, kinds 0
+ * and 1 hold the cyclic cell operator; lower[0] and upper[ny-1] are then
+ * the corner couplings (row 0 to row ny-1 and back).
  * out: host array of n doubles; n must equal the table length (queried by
  * passing out = NULL, which returns the length through *n). */
 ibs_status ibs_plan_export(ibs_plan plan, int32_t table, double *out, size_t *n);

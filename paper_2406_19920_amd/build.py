@@ -15,8 +15,8 @@ OUT = os.path.join(HERE, "libibsolve.so")
 OBJDIR = os.path.join(HERE, "_build")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["api.cpp", "plan.cpp", "k_xform.hip", "k_fold.hip", "k_tridiag.hip", "k_stencil.hip", "k_split.hip",
-           "batch.cpp", "noalloc.hip"]
+SOURCES = ["api.cpp", "plan.cpp", "k_xform.hip", "k_fold.hip", "k_tridiag.hip", "k_tridiag_cyc.hip",
+           "k_stencil.hip", "k_split.hip", "batch.cpp", "noalloc.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE,
          # no packed FP32 instructions in device code

@@ -443,8 +443,8 @@ ibs_status solve_helmholtz_batch(ibs_plan plan, int32_t ncomp, const int32_t *co
         if (comp[q] < 0 || comp[q] > 2) { set_error("comp must be 0 (u), 1 (v) or 2 (w)"); return IBS_ERR_INVALID_ARG; }
         if (!(c[q] >= 0.0) || !std::isfinite(c[q])) { set_error("c must be finite and >= 0"); return IBS_ERR_INVALID_ARG; }
         if (!r[q] || !x[q] || !aligned32(r[q]) || !aligned32(x[q])) { set_error("r[q], x[q] must be non-NULL and 32-byte aligned"); return IBS_ERR_INVALID_ARG; }
-        js.j[q].rows = comp[q] == 1 ? p.ny + 1 : p.ny;
-        js.j[q].kind = comp[q] == 1 ? KIND_F : KIND_C;
+        js.j[q].rows = comp_rows(p, comp[q]);
+        js.j[q].kind = comp_kind(p, comp[q]);
         js.j[q].c = c[q];
         js.j[q].info = info ? info + q : nullptr;
     }
@@ -494,7 +494,7 @@ ibs_status residual(ibs_plan plan, int32_t op, double c, const double *x, const 
         if (work_bytes < work_bytes_for(p, wop, 1)) { set_error("workspace too small"); return IBS_ERR_WORKSPACE_TOO_SMALL; }
         red = state_in(p, work, wop, 1).red;
     }
-    const double cells = (double)p.nz * (op == IBS_OP_HELMHOLTZ_V ? p.ny + 1 : p.ny) * p.nx;
+    const double cells = (double)p.nz * comp_rows(p, op - 1) * p.nx;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = timed(p, PK_RESIDUAL, 10.0 * cells, 24.0 * cells, s,
                          [&] { return launch_residual(p, op, c, x, b, r, norms2, red, s); });
@@ -543,6 +543,7 @@ ibs_status ibs_wall_data(ibs_plan plan, int32_t op, double c, const double *lo, 
     if (op < IBS_OP_POISSON || op > IBS_OP_HELMHOLTZ_W) { set_error("bad op"); return IBS_ERR_INVALID_ARG; }
     if (!rhs) { set_error("rhs must be non-NULL"); return IBS_ERR_INVALID_ARG; }
     if (!std::isfinite(c) || (op != IBS_OP_POISSON && c < 0.0)) { set_error("c must be finite and >= 0"); return IBS_ERR_INVALID_ARG; }
+    if (p.py) { set_error("wall data need walls; this plan is periodic in y"); return IBS_ERR_UNSUPPORTED; }
     if (!lo && !hi) return IBS_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = launch_wall_data(p, op, c, lo, hi, rhs, s);

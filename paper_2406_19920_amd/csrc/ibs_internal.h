@@ -15,7 +15,10 @@ namespace ibs {
 //   KIND_P: pressure, cell centres, homogeneous Neumann walls (n = ny rows)
 //   KIND_C: u and w, cell-centre height, Dirichlet wall by mirror ghost
 //   KIND_F: v, y faces incl. the two wall faces as identity rows (n = ny+1)
-enum { KIND_P = 0, KIND_C = 1, KIND_F = 2, NUM_KINDS = 3 };
+//   KIND_PF: v when y is periodic (the triply periodic branch): ny faces,
+//            no walls, cyclic.  With periodic y, KIND_P and KIND_C hold
+//            the cyclic cell-centre operator (the same for p, u and w).
+enum { KIND_P = 0, KIND_C = 1, KIND_F = 2, KIND_PF = 3, NUM_KINDS = 4 };
 
 // Byte offsets of the tables inside the device constant blob.
 struct BlobLayout {
@@ -51,6 +54,11 @@ constexpr int MAX_PASSES = 8;        // most refinement passes a solve may take 
 // exceeds this are solved with FP64 arithmetic (the FP64 lane); the rest in
 // FP32, whose rounding the refinement then removes.
 constexpr double LANE64_KAPPA = 1000.0;
+// Cyclic pencils (periodic y) lose more to FP32 rounding at the same bound
+// (the reduced system's last step divides by EA + EB + EC, which cancels
+// towards the near-null constant mode): measured 1e-10 after two passes at
+// a bound of 935 on a 96 x 96 x 64 grid; their lane takes bounds above 100.
+constexpr double LANE64_KAPPA_CYCLIC = 100.0;
 struct State {
     double *bmean = nullptr;   // per job: weighted mean of the Poisson rhs
     double *xsum = nullptr;    // per job: partial sums of Delta_j x (XSUM_SLOTS each)
@@ -89,6 +97,7 @@ static_assert(NUM_TUNE == IBS_NUM_TUNE, "tuning knobs and the ABI disagree");
 
 struct Plan {
     ibs_grid_desc desc;
+    bool py = false;                               // y periodic (no walls)
     int tune[NUM_TUNE] = {-1, -1};   // candidate index per knob; -1 = default
     int nx, ny, nz;
     double hx, hz;
@@ -134,6 +143,16 @@ struct JobSet {
 
 // Error reporting
 void set_error(const std::string &msg);
+
+// Row counts the cyclic tridiagonal (periodic y) is built for.
+bool cyclic_rows_supported(int n);
+// y rows of a component's field: v (comp 1) has ny + 1 with walls, ny
+// when y is periodic; u, w, p have ny.
+inline int comp_rows(const Plan &p, int comp) { return comp == 1 && !p.py ? p.ny + 1 : p.ny; }
+inline int comp_kind(const Plan &p, int comp)
+{
+    return comp == 1 ? (p.py ? KIND_PF : KIND_F) : KIND_C;
+}
 
 // Workspace of one solve call: the work fields and the state after them.
 size_t field_bytes_for(const Plan &p, int op, int ncomp);

@@ -1016,7 +1016,7 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
                                                            const double *__restrict__ bmean,
                                                            double *__restrict__ xsum,
                                                            const int *__restrict__ skip, int rb_rows,
-                                                           int tiles_y, int rz)
+                                                           int tiles_y, int rz, int py)
 {
     typedef Tx tx4 __attribute__((ext_vector_type(4)));
     typedef double dv4_ __attribute__((ext_vector_type(4)));
@@ -1035,14 +1035,27 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
     const int j = ty * rb_rows + rb, i0 = 4 * t;
     double wx = 0.0;
     if (rb < rb_rows && j < rows) {
-        const bool wall = op == IBS_OP_HELMHOLTZ_V && (j == 0 || j == ny);
+        const bool wall = !py && op == IBS_OP_HELMHOLTZ_V && (j == 0 || j == ny);
         const int iw = (i0 == 0) ? nx - 1 : i0 - 1, ie = (i0 + 4 == nx) ? 0 : i0 + 4;
         const size_t o = (size_t)j * nx;          // row start within a plane
         // y part in difference form, cu (x_up - x) - cl (x - x_lo); a missing
         // neighbour is the boundary ghost g x (g = 1 Neumann, -1 mirror, 0 wall)
         double D = 0.0, cu = 0.0, cl = 0.0, gu = 0.0, gl = 0.0;
         bool ru = false, rl = false;
-        if (op != IBS_OP_HELMHOLTZ_V) {
+        if (py) {
+            // periodic y: interior formulas everywhere, neighbours wrapping
+            // (delta_0 = delta_ny is the distance across the wrap)
+            if (op != IBS_OP_HELMHOLTZ_V) {
+                D = dyc[j];
+                cu = 1.0 / (dyf[j + 1] * D);
+                cl = 1.0 / (dyf[j] * D);
+            } else {
+                cu = 1.0 / (dyc[j] * dyf[j]);
+                cl = 1.0 / (dyc[j == 0 ? ny - 1 : j - 1] * dyf[j]);
+            }
+            ru = true;
+            rl = true;
+        } else if (op != IBS_OP_HELMHOLTZ_V) {
             D = dyc[j];
             const double gb = (op == IBS_OP_POISSON) ? 1.0 : -1.0;
             ru = j + 1 < ny;
@@ -1060,7 +1073,10 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
         // branch-free body (every load unconditional and in range, a missing
         // neighbour reads the row itself), so unrolled iterations' loads can
         // all be in flight together
-        const int du = ru ? nx : 0, dl = rl ? nx : 0;
+        // (periodic y: the neighbour of the last row is row 0, of row 0 the last)
+        const int wrapoff = -(rows - 1) * nx;
+        const int du = ru ? (py && j + 1 == rows ? wrapoff : nx) : 0;
+        const int dl = rl ? (py && j == 0 ? wrapoff : nx) : 0;
         const double wu = ru ? 1.0 : gu, wl = rl ? 1.0 : gl;
         const bool pois = op == IBS_OP_POISSON;
         const double cj = jb.c;
@@ -1074,7 +1090,7 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
         for (int k = k0; k < k1; ++k) {
             const size_t c = (size_t)k * plane + o;   // this row of plane k
             const tx4 xp = ld4((size_t)(k + 1 == nz ? 0 : k + 1) * plane + o + i0);
-            const tx4 xu = ld4(c + du + i0), xl = ld4(c - dl + i0);
+            const tx4 xu = ld4((size_t)((ptrdiff_t)c + du + i0)), xl = ld4((size_t)((ptrdiff_t)c - dl + i0));
             const double xwe = (double)x[c + iw], xee = (double)x[c + ie];
             const dv4_ bv = *reinterpret_cast<const dv4_ *>(bb + c + i0);
             fv4 rv;
@@ -1397,7 +1413,7 @@ hipError_t launch_residual_f32(const SplitSet &ss, const Plan &p, const State &s
     auto go = [&](auto kernel) {
         hipLaunchKernelGGL(kernel, grid, dim3(256), 0, s, ss, p.nx, p.ny, p.nz, 1.0 / (p.hx * p.hx),
                            1.0 / (p.hz * p.hz), blob_ptr(p, p.lay.dyc), blob_ptr(p, p.lay.dyf),
-                           st.bmean, st.xsum, skip, rb_rows, tiles_y, rz);
+                           st.bmean, st.xsum, skip, rb_rows, tiles_y, rz, p.py ? 1 : 0);
     };
     if (x32) go(residual_f32_kernel<float>);
     else go(residual_f32_kernel<double>);

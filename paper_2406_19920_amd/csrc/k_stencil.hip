@@ -12,13 +12,15 @@ struct Geo {
     int nx, ny, nz;
     double ihx, ihz;          // 1/hx, 1/hz
     const double *dyc;        // Delta_j [ny]
-    const double *dyf;        // delta_j [ny+1]
+    const double *dyf;        // delta_j [ny+1] (periodic y: delta_0 = delta_ny across the wrap)
+    int py;                   // periodic y: no walls, v has ny faces
 };
 
 static Geo geo_of(const Plan &p)
 {
     Geo g;
     g.nx = p.nx; g.ny = p.ny; g.nz = p.nz;
+    g.py = p.py ? 1 : 0;
     g.ihx = 1.0 / p.hx; g.ihz = 1.0 / p.hz;
     g.dyc = blob_ptr(p, p.lay.dyc);
     g.dyf = blob_ptr(p, p.lay.dyf);
@@ -38,9 +40,11 @@ __global__ __launch_bounds__(256) void divergence_kernel(Geo g, const double *__
     const size_t c = (size_t)k * plane + (size_t)j * g.nx + i;
     const int ip = (i + 1 == g.nx) ? 0 : i + 1;
     const size_t kp = (k + 1 == g.nz) ? 0 : (size_t)(k + 1);
-    const size_t vc = ((size_t)k * (g.ny + 1) + j) * g.nx + i;
+    const size_t vc = ((size_t)k * (g.ny + 1 - g.py) + j) * g.nx + i;
+    // the face above cell j: j + 1, or face 0 at the top when y is periodic
+    const size_t vn = (g.py && j + 1 == g.ny) ? vc - (size_t)j * g.nx : vc + g.nx;
     const double du = (u[c - i + ip] - u[c]) * g.ihx;
-    const double dv = (v[vc + g.nx] - v[vc]) / g.dyc[j];
+    const double dv = (v[vn] - v[vc]) / g.dyc[j];
     const double dw = (w[kp * plane + (size_t)j * g.nx + i] - w[c]) * g.ihz;
     b[c] = scale * (du + dv + dw);
 }
@@ -57,7 +61,7 @@ __global__ __launch_bounds__(256) void correct_kernel(Geo g, const double *__res
     const int j = blockIdx.y, k = blockIdx.z;
     if (i >= g.nx) return;
     const size_t plane = (size_t)g.ny * g.nx;
-    const size_t vc = ((size_t)k * (g.ny + 1) + j) * g.nx + i;
+    const size_t vc = ((size_t)k * (g.ny + 1 - g.py) + j) * g.nx + i;
     if (j < g.ny) {
         const size_t c = (size_t)k * plane + (size_t)j * g.nx + i;
         const int im = (i == 0) ? g.nx - 1 : i - 1;
@@ -67,6 +71,7 @@ __global__ __launch_bounds__(256) void correct_kernel(Geo g, const double *__res
         w[c] -= gs * (ph - phi[km * plane + (size_t)j * g.nx + i]) * g.ihz;
         if (pr) pr[c] += ph - (cp != 0.0 ? cp * lap[c] : 0.0);
         if (j > 0) v[vc] -= gs * (ph - phi[c - g.nx]) / g.dyf[j];
+        else if (g.py) v[vc] -= gs * (ph - phi[c + (size_t)(g.ny - 1) * g.nx]) / g.dyf[0];   // across the wrap
         else v[vc] = 0.0;
     } else {
         v[vc] = 0.0;
@@ -98,7 +103,7 @@ __global__ __launch_bounds__(256) void residual_kernel(Geo g, int op, double cc,
                                                        double *__restrict__ red)
 {
     __shared__ double sm[8];
-    const int rows = (op == IBS_OP_HELMHOLTZ_V) ? g.ny + 1 : g.ny;
+    const int rows = (op == IBS_OP_HELMHOLTZ_V && !g.py) ? g.ny + 1 : g.ny;
     const size_t plane = (size_t)rows * g.nx;
     const int nrow = rows * g.nz;
     double rr = 0.0, bb = 0.0;
@@ -118,7 +123,15 @@ __global__ __launch_bounds__(256) void residual_kernel(Geo g, int op, double cc,
             double lap = ((xe - xc) - (xc - xw)) * (g.ihx * g.ihx) +
                          ((xt - xc) - (xc - xb)) * (g.ihz * g.ihz);
             bool unknown = true;
-            if (op != IBS_OP_HELMHOLTZ_V) {
+            if (g.py) {
+                // periodic y: interior formulas everywhere, neighbours wrapping
+                const int jn = (j + 1 == g.ny) ? 0 : j + 1, js = (j == 0) ? g.ny - 1 : j - 1;
+                const double xn = x[c + (ptrdiff_t)(jn - j) * g.nx], xs = x[c + (ptrdiff_t)(js - j) * g.nx];
+                if (op == IBS_OP_HELMHOLTZ_V)
+                    lap += ((xn - xc) / g.dyc[j] - (xc - xs) / g.dyc[js]) / g.dyf[j];
+                else
+                    lap += ((xn - xc) / g.dyf[j + 1] - (xc - xs) / g.dyf[j]) / g.dyc[j];
+            } else if (op != IBS_OP_HELMHOLTZ_V) {
                 const double D = g.dyc[j];
                 double fu, fl;
                 if (j + 1 < g.ny) fu = (x[c + g.nx] - xc) / g.dyf[j + 1];
@@ -192,7 +205,7 @@ hipError_t launch_correct(const Plan &p, const double *phi, double *u, double *v
 {
     Geo g = geo_of(p);
     dim3 blk = row_block(p.nx);
-    dim3 grid((p.nx + blk.x - 1) / blk.x, p.ny + 1, p.nz);
+    dim3 grid((p.nx + blk.x - 1) / blk.x, p.py ? p.ny : p.ny + 1, p.nz);   // the v face rows
     hipLaunchKernelGGL(correct_kernel, grid, blk, 0, s, g, phi, u, v, w, gs, pr, lap, cp);
     return hipGetLastError();
 }
@@ -249,7 +262,7 @@ hipError_t launch_residual(const Plan &p, int op, double c, const double *x, con
                            double *r, double *norms2, double *red, hipStream_t s)
 {
     Geo g = geo_of(p);
-    const int rows = (op == IBS_OP_HELMHOLTZ_V) ? p.ny + 1 : p.ny;
+    const int rows = comp_rows(p, op - 1);
     const int nrow = rows * p.nz;
     const int nblk = nrow < RESID_SLOTS ? nrow : RESID_SLOTS;
     if (!norms2) red = nullptr;

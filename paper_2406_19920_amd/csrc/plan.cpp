@@ -320,9 +320,15 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
         set_error("ny must be in [2, 1024]");
         return IBS_ERR_UNSUPPORTED;
     }
-    if (d.bc_x != IBS_PERIODIC || d.bc_z != IBS_PERIODIC || d.bc_y_vel != IBS_DIRICHLET ||
-        d.bc_y_p != IBS_NEUMANN) {
-        set_error("only periodic x/z with Dirichlet velocity / Neumann pressure walls in y are supported");
+    const bool walls_y = d.bc_y_vel == IBS_DIRICHLET && d.bc_y_p == IBS_NEUMANN;
+    const bool periodic_y = d.bc_y_vel == IBS_PERIODIC && d.bc_y_p == IBS_PERIODIC;
+    if (d.bc_x != IBS_PERIODIC || d.bc_z != IBS_PERIODIC || !(walls_y || periodic_y)) {
+        set_error("supported: periodic x/z with either Dirichlet velocity / Neumann pressure walls in y, "
+                  "or periodic y (triply periodic)");
+        return IBS_ERR_UNSUPPORTED;
+    }
+    if (periodic_y && !cyclic_rows_supported(d.ny)) {
+        set_error("periodic y needs ny in {48, 64, 80, 96, 128, 160, 192, 256, 320, 384, 512}");
         return IBS_ERR_UNSUPPORTED;
     }
     if (d.precision < IBS_FP64 || d.precision > IBS_REFINED_AUTO) {
@@ -354,6 +360,7 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     if (!p) { set_error("out of host memory"); return IBS_ERR_INVALID_ARG; }
     p->desc = d;
     p->desc.y_faces = nullptr;
+    p->py = periodic_y;
     const double lx = d.lx > 0 ? d.lx : 1.0, ly = d.ly > 0 ? d.ly : 1.0, lz = d.lz > 0 ? d.lz : 1.0;
     p->desc.lx = lx; p->desc.ly = ly; p->desc.lz = lz;
     if (p->desc.tol <= 0) p->desc.tol = 1e-10;
@@ -387,17 +394,39 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
         }
     }
     for (int j = 1; j < ny; ++j) p->dyf[j] = p->yc[j] - p->yc[j - 1];
+    // periodic y: the centres of cells ny-1 and 0 are (Delta_{ny-1} +
+    // Delta_0)/2 apart across the wrap; that distance is delta_0 = delta_ny
+    if (p->py) p->dyf[0] = p->dyf[ny] = 0.5 * (p->dyc[0] + p->dyc[ny - 1]);
 
     // y operators, one tridiagonal row per unknown (unweighted Laplacian in y)
     p->rows[KIND_P] = ny;
     p->rows[KIND_C] = ny;
     p->rows[KIND_F] = ny + 1;
+    p->rows[KIND_PF] = ny;
     for (int kd = 0; kd < NUM_KINDS; ++kd) {
         p->lo[kd].assign(ny + 1, 0.0);
         p->di[kd].assign(ny + 1, 0.0);
         p->up[kd].assign(ny + 1, 0.0);
     }
-    for (int j = 0; j < ny; ++j) {
+    for (int j = 0; p->py && j < ny; ++j) {
+        // periodic y: the interior rows everywhere; lo[0] couples row 0 to
+        // row ny-1 and up[ny-1] row ny-1 to row 0 (the cyclic corners).
+        // Cells (p, u, w): (F_{j+1/2} - F_{j-1/2}) / Delta_j, fluxes over
+        // delta; faces (v): fluxes over Delta, divided by delta_j.
+        const double lo = 1.0 / (p->dyf[j] * p->dyc[j]);
+        const double up = 1.0 / (p->dyf[j + 1] * p->dyc[j]);
+        for (int kd : {KIND_P, KIND_C}) {
+            p->lo[kd][j] = lo;
+            p->up[kd][j] = up;
+            p->di[kd][j] = -(lo + up);
+        }
+        const double flo = 1.0 / (p->dyf[j] * p->dyc[(j + ny - 1) % ny]);
+        const double fup = 1.0 / (p->dyf[j] * p->dyc[j]);
+        p->lo[KIND_PF][j] = flo;
+        p->up[KIND_PF][j] = fup;
+        p->di[KIND_PF][j] = -(flo + fup);
+    }
+    for (int j = 0; !p->py && j < ny; ++j) {
         // cell-centre rows: (F_{j+1/2} - F_{j-1/2}) / Delta_j
         double lo = (j > 0) ? 1.0 / (p->dyf[j] * p->dyc[j]) : 0.0;
         double up = (j + 1 < ny) ? 1.0 / (p->dyf[j + 1] * p->dyc[j]) : 0.0;
@@ -411,7 +440,7 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
         p->up[KIND_C][j] = up;
         p->di[KIND_C][j] = -(lo + up) - wall;
     }
-    for (int j = 1; j < ny; ++j) {
+    for (int j = 1; !p->py && j < ny; ++j) {
         // face rows: ((v_{j+1}-v_j)/Delta_j - (v_j-v_{j-1})/Delta_{j-1}) / delta_j;
         // the wall rows 0 and ny stay zero (their unknowns are pinned to 0)
         double lo = 1.0 / (p->dyf[j] * p->dyc[j - 1]);
@@ -468,7 +497,7 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     L.szf_inv = take(sfold_z ? sizeof(uint16_t) * 3 * 2 * hz2 : 0);
     // FP64 lane of the refined pressure pencils: a 32-wide x-tile of z-mode
     // c joins it when any of its pencils is singular or has a condition
-    // bound 1 + g/|s| above LANE64_KAPPA
+    // bound 1 + g/|s| above LANE64_KAPPA (LANE64_KAPPA_CYCLIC when y is periodic)
     std::vector<uint32_t> lane_mask;
     std::vector<int> lane_list;
     if (split) {
@@ -481,7 +510,7 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
                 bool need = false;
                 for (int a = 32 * t; a < 32 * t + 32 && !need; ++a) {
                     const double sabs = std::fabs(p->lam_x[a] + p->lam_z[c]);
-                    need = sabs == 0.0 || 1.0 + g / sabs > LANE64_KAPPA;
+                    need = sabs == 0.0 || 1.0 + g / sabs > (p->py ? LANE64_KAPPA_CYCLIC : LANE64_KAPPA);
                 }
                 if (need) {
                     lane_mask[c] |= 1u << t;

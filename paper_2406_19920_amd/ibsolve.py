@@ -299,8 +299,14 @@ class Solver:
     def stream(self) -> int:
         return self.torch.cuda.current_stream(self.device).cuda_stream
 
+    @property
+    def periodic_y(self) -> bool:
+        """Triply periodic plan: no walls, v has ny faces."""
+        return self.desc.bc_y_vel == IBS_PERIODIC
+
     def shape(self, op=IBS_OP_POISSON):
-        return (self.nz, self.ny + 1 if op == IBS_OP_HELMHOLTZ_V else self.ny, self.nx)
+        walls = op == IBS_OP_HELMHOLTZ_V and not self.periodic_y
+        return (self.nz, self.ny + 1 if walls else self.ny, self.nx)
 
     def empty(self, op=IBS_OP_POISSON):
         return self.torch.empty(self.shape(op), dtype=self.torch.float64, device=self.device)
