@@ -364,7 +364,7 @@ static int max_rows(const JobSet &js)   // transform rows per plane
     return r;
 }
 
-bool can_fold(int n) { return n % 32 == 0; }
+// can_fold() is defined with the plan builder (host code).
 
 // Tile candidates (row blocks x column blocks per wave, and whether the next
 // chunk's operands are loaded ahead at the cost of registers).  Every

@@ -26,14 +26,8 @@ static hipError_t launch_cyclic(const JobSet &js, const TriParams &tp, int n, hi
     }
 }
 
-bool cyclic_rows_supported(int n)
-{
-    switch (n) {
-    case 48: case 64: case 80: case 96: case 128: case 160: case 192: case 256: case 320: case 384:
-    case 512: return true;
-    default: return false;
-    }
-}
+// cyclic_rows_supported() (the sizes above) is defined with the plan
+// builder (host code).
 
 hipError_t launch_cyclic_dd(const JobSet &js, const TriParams &tp, int n, hipStream_t s)
 {

@@ -12,6 +12,21 @@ namespace ibs {
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// The FP64 transforms fold the real Fourier basis when the half length is a
+// whole number of 16-blocks.
+bool can_fold(int n) { return n % 32 == 0; }
+
+// Row counts the cyclic tridiagonal is instantiated for (periodic y): the
+// P chunks of M rows hold the system exactly, n = P M (k_tridiag_cyc.hip).
+bool cyclic_rows_supported(int n)
+{
+    switch (n) {
+    case 48: case 64: case 80: case 96: case 128: case 160: case 192: case 256: case 320: case 384:
+    case 512: return true;
+    default: return false;
+    }
+}
+
 // Real orthonormal Fourier basis of the periodic 3-point second difference
 // (its eigenvectors; eigenvalues are minus the modified wavenumber squared,
 // -(2/h^2)(1 - cos(kappa h)) = -(4/h^2) sin^2(pi k / N), Appendix A).
