@@ -142,9 +142,10 @@ def main():
     ap.add_argument("--no-extra-configs", action="store_true",
                     help="skip the shortened 512x384x384, 64-job batch and serving runs that the "
                          "default run appends under 'configs'")
-    ap.add_argument("--config", choices=["c2", "c3", "batch", "serve"], default="c2",
+    ap.add_argument("--config", choices=["c2", "c3", "batch", "serve", "rk3"], default="c2",
                     help="c2: 256^3 step (default); c3: 512x384x384 refined step with a forcing "
-                         "shell; batch: 64 mixed-size jobs as one graph; serve: arrival-rate sweep")
+                         "shell; batch: 64 mixed-size jobs as one graph; serve: arrival-rate sweep; "
+                         "rk3: full Runge-Kutta step with immersed markers at --n^3")
     ap.add_argument("--count", type=int, default=2000, help="serve: requests per rate")
     ap.add_argument("--rates", type=str, default="100,200,500,1000,2000,5000")
     ap.add_argument("--geometries", type=int, default=0,
@@ -176,6 +177,8 @@ def main():
         return bench_serve(args)
     if args.config == "c3":
         return bench_c3(args)
+    if args.config == "rk3":
+        return bench_rk3(args)
 
     n, beta = args.n, args.beta
     dev = torch.device("cuda:0")
@@ -307,6 +310,10 @@ def main():
         r3, w3 = run_3p(10, 2)
         configs["triply_periodic"] = {"workload": w3, "steps": 10, "warmup": 2,
                                       "unit": "Mcell-solves/s", **r3}
+        log("config rk3")
+        rr, wr = run_rk3(5, 1)
+        configs["rk3_step"] = {"workload": wr, "steps": 5, "warmup": 1,
+                               "unit": "Mcell-steps/s (cells x full RK3 steps per second)", **rr}
         log("config c4")
         configs["c4"] = run_batch(5, 1)
         log("config c5")
@@ -549,6 +556,70 @@ def run_3p(steps, warmup, n=256):
     return res, f"{n}^3 uniform, periodic in x, y and z, N(0,1) filtered to k <= 16, c = {c:.4e}"
 
 
+def run_rk3(steps, warmup, n=256):
+    """A full three-stage Runge-Kutta step (each stage: explicit estimate,
+    immersed-boundary forcing, 3 Helmholtz solves, divergence, Poisson,
+    projection and pressure update) at n^3 on a uniform wall-bounded grid,
+    with a sphere of markers (radius 0.15, one marker per h^2 of surface),
+    both paths.  Velocities: N(0,1) low-pass filtered to k <= 16; dt from a
+    convective CFL of 0.2; Re = 1000."""
+    import torch
+    from paper_2406_19920_amd import ibsolve as ibs, synth
+    dev = torch.device("cuda:0")
+    log(f"inputs {n}^3 RK3 step with markers")
+    u0, v0, w0 = synth.filtered_velocity(n, n, n, seed=8, kmax=16.0)
+    p0 = synth.scalar(n, n, n, seed=9)
+    h = 1.0 / n
+    radius = 0.15
+    nm = int(4.0 * np.pi * radius * radius / (h * h))
+    X = synth.sphere_markers(nm, radius)
+    rng = np.random.default_rng(10)
+    UD = 0.1 * rng.standard_normal((nm, 3))
+    umax = max(np.abs(a).max() for a in (u0, v0, w0))
+    dt, re = 0.2 * h / umax, 1000.0
+    rk3 = [(4 / 15, 4 / 15, 8 / 15, 0.0), (1 / 15, 1 / 15, 5 / 12, -17 / 60),
+           (1 / 6, 1 / 6, 3 / 4, -5 / 12)]
+    coefs = [dict(alpha=a, beta=b, gamma=g, zeta=z, dt=dt, re=re) for a, b, g, z in rk3]
+    markers, ud = (torch.from_numpy(a).to(dev) for a in (X, UD))
+    dvol = torch.full((nm,), h ** 3, dtype=torch.float64, device=dev)
+    force = torch.zeros((nm, 3), dtype=torch.float64, device=dev)
+    res = {}
+    for path, prec in (("refined", ibs.IBS_REFINED_BF16X3), ("fp64", ibs.IBS_FP64)):
+        S = ibs.Solver(n, n, n, precision=prec)
+        tiles = S.autotune() if prec == ibs.IBS_FP64 else None   # set-up, untimed
+        u, v, w, p = (torch.from_numpy(a).to(dev) for a in (u0, v0, w0, p0))
+        nu, nv, nw = (torch.zeros_like(t) for t in (u, v, w))
+
+        def step():
+            for k in coefs:
+                S.rk_stage(u, v, w, p, nu, nv, nw, k, markers, ud, dvol, force)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        status = [S.read_info(4 + q).status for q in range(4)]
+        ibs.ibs_profile(S.plan, True)
+        step()
+        torch.cuda.synchronize()
+        kern = {}
+        for kid, name in enumerate(ibs.PROFILE_KERNELS):
+            r = ibs.ibs_profile_read(S.plan, kid)
+            if r["launches"]:
+                kern[name] = {"ms_per_step": r["ms"], "launches": r["launches"],
+                              "gbs": r["bytes"] / (r["ms"] * 1e-3) / 1e9 if r["ms"] else None}
+        ibs.ibs_profile(S.plan, False)
+        res[path] = {"value": n ** 3 / (ms * 1e-3) / 1e6, "ms_per_step": ms, "status": status,
+                     "finite": bool(torch.isfinite(u).all()), "tiles": tiles, "kernels": kern}
+        S.close()
+    return res, (f"{n}^3 uniform walls, RK3 (3 sub-steps), {nm} markers on a sphere r={radius}, "
+                 f"dt={dt:.3e}, Re={re:g}")
+
+
 def bench_c3(args):
     res, workload = run_c3(args.steps, args.warmup)
     out = {"metric": "Mcell-solves/s at 512x384x384 (refined to 1e-10; FP64 alongside)",
@@ -557,6 +628,17 @@ def bench_c3(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "bf16x3 MFMA, f32 accumulate, f64 residual/iterate", "data": "synthetic",
            "config": {"workload": workload}, "paths": res}
+    print(json.dumps(out), flush=True)
+
+
+def bench_rk3(args):
+    res, workload = run_rk3(args.steps, args.warmup, args.n)
+    out = {"metric": f"Mcell-steps/s, full RK3 step with immersed markers at {args.n}^3",
+           "value": res["refined"]["value"], "unit": "Mcell-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["refined"]["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64 stencils; solves bf16x3 MFMA refined (FP64 path alongside)",
+           "data": "synthetic", "config": {"workload": workload}, "paths": res}
     print(json.dumps(out), flush=True)
 
 

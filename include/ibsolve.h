@@ -251,6 +251,52 @@ ibs_status ibs_divergence(ibs_plan plan, const double *u, const double *v,
 ibs_status ibs_wall_data(ibs_plan plan, int32_t op, double c, const double *lo,
                          const double *hi, double *rhs, void *stream);
 
+/* ---- One Runge-Kutta sub-step of the fractional-step method ------------
+ * (Section 2.1, eqs. a-h; kernels E1, L1, E2, E3 and the solves of Section
+ * 2.3): with stage coefficients alpha, beta, gamma, zeta (user supplied,
+ * e.g. a low-storage RK3), time step dt and Reynolds number Re,
+ *   (a) u^e = u + dt[(alpha+beta)/Re L u - (alpha+beta) G p - gamma N(u)
+ *               - zeta N(u of the stage before)]
+ *   (b-d) immersed boundary: U^e(X) interpolated with the Roma three-point
+ *       kernel, F = (U^d - U^e)/dt, f spread back with dV_eta
+ *   (e) (I - c L) u_s = u^e - c L u + dt f,   c = beta dt / Re
+ *   (f) L_p phi = D u_s / ((alpha+beta) dt)
+ *   (g) u = u_s - (alpha+beta) dt G phi;  (h) p += phi - c D u_s / ((alpha+beta) dt)
+ * (u_s: the intermediate velocity).
+ * N(u) is the convective term div(u u) in divergence form on the staggered
+ * grid (second-order central differences; products on the faces/edges
+ * where their derivatives need them, from arithmetic means). */
+typedef struct {
+    double alpha, beta, gamma, zeta;   /* stage coefficients of eq. (a)         */
+    double dt, re;                     /* time step (> 0), Reynolds number (> 0) */
+} ibs_rk_coef;
+
+typedef struct {
+    double *u, *v, *w, *p;   /* device; in: u^{n-1}, p^{n-1}; out: u^n, p^n (in place) */
+    double *nu, *nv, *nw;    /* device, shaped like u, v, w; in: N of the stage before
+                                (read only when zeta != 0); out: N(u^{n-1}) for the next
+                                stage (may be the same arrays) */
+    const double *markers;   /* device [nmarkers][3] marker positions (x, y, z), or NULL */
+    const double *ud;        /* device [nmarkers][3] prescribed velocity U^d            */
+    const double *dvol;      /* device [nmarkers] volume dV_eta of each marker          */
+    double *force;           /* device [nmarkers][3] out: F, or NULL                    */
+    int32_t nmarkers;        /* 0: no immersed body                                     */
+} ibs_stage_fields;
+
+/* Workspace bytes for ibs_rk_stage() on this plan (u^e and the Helmholtz
+ * right-hand sides, the Poisson fields, and one solve's workspace). */
+ibs_status ibs_stage_bytes(ibs_plan plan, size_t *work_bytes);
+
+/* One sub-step, asynchronous on stream.  The Helmholtz and Poisson solves
+ * run in the plan's precision; info: NULL or 4 device records (Helmholtz
+ * u, v, w, then Poisson).  With markers the grid must be uniform in y (the
+ * kernel's spacing; IBS_ERR_UNSUPPORTED otherwise); the spreading adds by
+ * atomics, so results with markers are reproducible to rounding, not
+ * bitwise.  Errors: IBS_ERR_INVALID_ARG, IBS_ERR_UNSUPPORTED,
+ * IBS_ERR_NOT_UPLOADED, IBS_ERR_WORKSPACE_TOO_SMALL, IBS_ERR_HIP. */
+ibs_status ibs_rk_stage(ibs_plan plan, const ibs_rk_coef *coef, const ibs_stage_fields *fields,
+                        void *work, size_t work_bytes, ibs_solve_info *info, void *stream);
+
 /* Projection, eq. (g), and pressure update, eq. (h) (kernel E3):
  * u -= g dphi/dx, v -= g dphi/dy (interior faces; walls set to 0),
  * w -= g dphi/dz; if p != NULL: p += phi - cp * lap_phi, where lap_phi is the
@@ -317,7 +363,8 @@ ibs_status ibs_plan_export(ibs_plan plan, int32_t table, double *out, size_t *n)
  * the method needs, not counter readings).  Kernel classes: 0 x transform
  * (FP64 matrix cores), 1 z transform (FP64), 2 y tridiagonal (FP64),
  * 3 divergence, 4 correction, 5 residual, 6 x transform (split),
- * 7 z transform (split), 8 y tridiagonal (FP32 data), 9 refinement update.
+ * 7 z transform (split), 8 y tridiagonal (FP32 data), 9 refinement update,
+ * 10 explicit estimate of a Runge-Kutta stage, 11 immersed-boundary forcing.
  * Any output pointer may be NULL. */
 ibs_status ibs_profile(ibs_plan plan, int32_t enable);
 ibs_status ibs_profile_read(ibs_plan plan, int32_t kernel, double *ms, int64_t *launches,

@@ -551,6 +551,103 @@ ibs_status ibs_wall_data(ibs_plan plan, int32_t op, double c, const double *lo, 
     return IBS_OK;
 }
 
+// Workspace of a sub-step: u^e and r (three fields each, v-shaped
+// stride), b and phi (cell fields), then one solve's workspace (the larger
+// of the Helmholtz batch of three and the Poisson solve; they run one
+// after the other).
+static size_t stage_field_doubles(const Plan &p) { return field_doubles(p, p.ny + 1); }
+static size_t stage_solver_offset(const Plan &p)
+{
+    return align256((6 * stage_field_doubles(p) + 2 * field_doubles(p, p.ny)) * sizeof(double));
+}
+static size_t stage_solver_bytes(const Plan &p)
+{
+    const size_t h = work_bytes_for(p, IBS_OP_HELMHOLTZ_U, 3), q = work_bytes_for(p, IBS_OP_POISSON, 1);
+    return h > q ? h : q;
+}
+
+ibs_status ibs_stage_bytes(ibs_plan plan, size_t *work_bytes)
+{
+    if (!plan || !work_bytes) { set_error("plan and work_bytes must be non-NULL"); return IBS_ERR_INVALID_ARG; }
+    const Plan &p = *reinterpret_cast<Plan *>(plan);
+    *work_bytes = stage_solver_offset(p) + stage_solver_bytes(p);
+    return IBS_OK;
+}
+
+ibs_status ibs_rk_stage(ibs_plan plan, const ibs_rk_coef *coef, const ibs_stage_fields *f, void *work,
+                        size_t work_bytes, ibs_solve_info *info, void *stream)
+{
+    ibs_status chk = check_plan(plan);
+    if (chk != IBS_OK) return chk;
+    Plan &p = *reinterpret_cast<Plan *>(plan);
+    if (!coef || !f || !work) { set_error("coef, fields and work must be non-NULL"); return IBS_ERR_INVALID_ARG; }
+    const ibs_rk_coef &k = *coef;
+    const bool finite = std::isfinite(k.alpha) && std::isfinite(k.beta) && std::isfinite(k.gamma) &&
+                        std::isfinite(k.zeta) && std::isfinite(k.dt) && std::isfinite(k.re);
+    if (!finite || !(k.dt > 0.0) || !(k.re > 0.0) || !(k.beta >= 0.0) || !(k.alpha + k.beta > 0.0)) {
+        set_error("coefficients must be finite with dt > 0, re > 0, beta >= 0 and alpha + beta > 0");
+        return IBS_ERR_INVALID_ARG;
+    }
+    const void *ptrs[] = {f->u, f->v, f->w, f->p, f->nu, f->nv, f->nw};
+    for (const void *q : ptrs)
+        if (!q || !aligned32(q)) { set_error("u, v, w, p, nu, nv, nw must be non-NULL and 32-byte aligned"); return IBS_ERR_INVALID_ARG; }
+    if (f->nmarkers < 0 || (f->nmarkers > 0 && (!f->markers || !f->ud || !f->dvol))) {
+        set_error("nmarkers must be >= 0, with markers, ud and dvol when it is positive");
+        return IBS_ERR_INVALID_ARG;
+    }
+    if (f->nmarkers > 0) {
+        const double h = p.desc.ly / p.ny;
+        for (double d : p.dyc)
+            if (std::fabs(d - h) > 1e-12 * h) {
+                set_error("the immersed boundary needs a uniform spacing in y");
+                return IBS_ERR_UNSUPPORTED;
+            }
+    }
+    size_t need = 0;
+    ibs_stage_bytes(plan, &need);
+    if (work_bytes < need) { set_error("workspace smaller than ibs_stage_bytes()"); return IBS_ERR_WORKSPACE_TOO_SMALL; }
+    if (!aligned32(work)) { set_error("work must be 32-byte aligned"); return IBS_ERR_INVALID_ARG; }
+
+    double *W = static_cast<double *>(work);
+    const size_t fs = stage_field_doubles(p);
+    FsStage s{};
+    s.alpha = k.alpha; s.beta = k.beta; s.gamma = k.gamma; s.zeta = k.zeta; s.dt = k.dt; s.re = k.re;
+    s.u = f->u; s.v = f->v; s.w = f->w; s.p = f->p;
+    s.nu = f->nu; s.nv = f->nv; s.nw = f->nw;
+    s.ue = W; s.ve = W + fs; s.we = W + 2 * fs;
+    s.ru = W + 3 * fs; s.rv = W + 4 * fs; s.rw = W + 5 * fs;
+    s.markers = f->markers; s.ud = f->ud; s.dvol = f->dvol; s.force = f->force; s.nmarkers = f->nmarkers;
+    double *b = W + 6 * fs, *phi = b + field_doubles(p, p.ny);
+    void *sw = static_cast<unsigned char *>(work) + stage_solver_offset(p);
+    const size_t swb = stage_solver_bytes(p);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const double c = k.beta * k.dt / k.re, g = (k.alpha + k.beta) * k.dt;
+
+    // algorithmic traffic of the explicit estimate: u, v, w, p (+ the previous
+    // N when zeta != 0) read, u^e, r and N written, 8 bytes each per cell
+    const double cells = (double)p.nx * p.ny * p.nz;
+    const double ebytes = 8.0 * cells * (k.zeta != 0.0 ? 16.0 : 13.0);
+    hipError_t e = timed(p, PK_EXPLICIT, 150.0 * cells, ebytes, st,
+                         [&] { return launch_explicit(p, s, st); });   // (a) and the rhs of (e)
+    if (e != hipSuccess) return hip_fail(e, "explicit estimate");
+    // per marker and component: 27 reads and 27 atomic updates
+    const double ibytes = (double)f->nmarkers * 3 * 27 * 24.0;
+    e = timed(p, PK_IBM, (double)f->nmarkers * 3 * 27 * 8.0, ibytes, st,
+              [&] { return launch_ibm(p, s, st); });                  // (b)-(d), into the rhs
+    if (e != hipSuccess) return hip_fail(e, "immersed boundary");
+    const int32_t comps[3] = {0, 1, 2};
+    const double cs[3] = {c, c, c};
+    const double *rs[3] = {s.ru, s.rv, s.rw};
+    double *xs[3] = {f->u, f->v, f->w};
+    ibs_status r = solve_helmholtz_batch(plan, 3, comps, cs, rs, xs, sw, swb, info, stream);   // (e)
+    if (r != IBS_OK) return r;
+    r = ibs_divergence(plan, f->u, f->v, f->w, b, 1.0 / g, stream);                          // rhs of (f)
+    if (r != IBS_OK) return r;
+    r = solve_poisson(plan, b, phi, sw, swb, info ? info + 3 : nullptr, stream);              // (f)
+    if (r != IBS_OK) return r;
+    return ibs_correct(plan, phi, f->u, f->v, f->w, g, f->p, b, c, stream);                  // (g), (h)
+}
+
 ibs_status ibs_profile(ibs_plan plan, int32_t enable)
 {
     if (!plan) { set_error("plan is NULL"); return IBS_ERR_INVALID_ARG; }

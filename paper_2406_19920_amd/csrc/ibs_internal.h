@@ -72,7 +72,7 @@ struct State {
 // Kernel classes for the optional live profile (HIP events around launches).
 enum {
     PK_XGEMM = 0, PK_ZGEMM, PK_TRIDIAG, PK_DIVERGENCE, PK_CORRECT, PK_RESIDUAL,
-    PK_XGEMM_SPLIT, PK_ZGEMM_SPLIT, PK_TRIDIAG_F32, PK_UPDATE, NUM_PK
+    PK_XGEMM_SPLIT, PK_ZGEMM_SPLIT, PK_TRIDIAG_F32, PK_UPDATE, PK_EXPLICIT, PK_IBM, NUM_PK
 };
 
 struct ProfRec {
@@ -186,6 +186,21 @@ hipError_t launch_correct(const Plan &p, const double *phi, double *u, double *v
                           double cp, hipStream_t s);
 hipError_t launch_residual(const Plan &p, int op, double c, const double *x,
                            const double *b, double *r, double *norms2, double *red, hipStream_t s);
+// One Runge-Kutta sub-step around the solves (explicit estimate, immersed
+// boundary forcing): the fields and coefficients its kernels take.
+struct FsStage {
+    double alpha, beta, gamma, zeta, dt, re;
+    const double *u, *v, *w, *p;          // u^{n-1}, p^{n-1}
+    double *nu, *nv, *nw;                 // in: N of the stage before (zeta != 0); out: N(u^{n-1})
+    double *ue, *ve, *we;                 // u^e (eq. a)
+    double *ru, *rv, *rw;                 // Helmholtz right-hand sides (eq. e)
+    const double *markers, *ud, *dvol;    // immersed boundary: X_eta, U^d, dV_eta
+    double *force;                        // F at the markers, or null
+    int nmarkers;
+};
+hipError_t launch_explicit(const Plan &p, const FsStage &s, hipStream_t st);
+hipError_t launch_ibm(const Plan &p, const FsStage &s, hipStream_t st);
+
 // rhs += the contribution of inhomogeneous wall data lo, hi ([nz][nx]).
 hipError_t launch_wall_data(const Plan &p, int op, double c, const double *lo, const double *hi,
                             double *rhs, hipStream_t s);

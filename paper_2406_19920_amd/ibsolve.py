@@ -32,7 +32,7 @@ IBS_OP_POISSON, IBS_OP_HELMHOLTZ_U, IBS_OP_HELMHOLTZ_V, IBS_OP_HELMHOLTZ_W = 0, 
 # every exported entry point of include/ibsolve.h
 EXPORTS = ("solver_plan", "solver_plan_bytes", "solver_plan_upload", "solver_plan_destroy",
            "solve_poisson", "solve_poisson_noalloc", "solve_helmholtz_batch", "residual",
-           "ibs_divergence", "ibs_wall_data",
+           "ibs_divergence", "ibs_wall_data", "ibs_stage_bytes", "ibs_rk_stage",
            "ibs_correct", "ibs_plan_export", "ibs_profile", "ibs_profile_read",
            "ibs_batch_build", "ibs_batch_launch", "ibs_batch_destroy",
            "ibs_autotune_bytes", "ibs_autotune", "ibs_plan_set_tiles",
@@ -41,7 +41,7 @@ EXPORTS = ("solver_plan", "solver_plan_bytes", "solver_plan_upload", "solver_pla
 IBS_NUM_TUNE = 2
 
 PROFILE_KERNELS = ("xgemm_f64", "zgemm_f64", "tridiag_f64", "divergence", "correct", "residual",
-                   "xgemm_split", "zgemm_split", "tridiag_f32", "update")
+                   "xgemm_split", "zgemm_split", "tridiag_f32", "update", "explicit", "ibm")
 
 
 class ibs_grid_desc(ctypes.Structure):
@@ -71,6 +71,18 @@ class ibs_batch_job(ctypes.Structure):
                 ("info", ctypes.c_void_p)]
 
 
+class ibs_rk_coef(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("zeta", ctypes.c_double), ("dt", ctypes.c_double), ("re", ctypes.c_double)]
+
+
+class ibs_stage_fields(ctypes.Structure):
+    _fields_ = [("u", ctypes.c_void_p), ("v", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("p", ctypes.c_void_p), ("nu", ctypes.c_void_p), ("nv", ctypes.c_void_p),
+                ("nw", ctypes.c_void_p), ("markers", ctypes.c_void_p), ("ud", ctypes.c_void_p),
+                ("dvol", ctypes.c_void_p), ("force", ctypes.c_void_p), ("nmarkers", ctypes.c_int32)]
+
+
 class IbsError(RuntimeError):
     def __init__(self, status: int, where: str, msg: str):
         super().__init__(f"{where}: status {status}: {msg}")
@@ -93,6 +105,9 @@ def _load():
     L.residual.argtypes = [vp, i32, dbl, vp, vp, vp, vp, vp, sz, vp]
     L.ibs_divergence.argtypes = [vp, vp, vp, vp, vp, dbl, vp]
     L.ibs_wall_data.argtypes = [vp, i32, dbl, vp, vp, vp, vp]
+    L.ibs_stage_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    L.ibs_rk_stage.argtypes = [vp, ctypes.POINTER(ibs_rk_coef), ctypes.POINTER(ibs_stage_fields), vp, sz,
+                               vp, vp]
     L.ibs_correct.argtypes = [vp, vp, vp, vp, vp, dbl, vp, vp, dbl, vp]
     L.ibs_plan_export.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(sz)]
     L.ibs_profile.argtypes = [vp, i32]
@@ -194,6 +209,17 @@ def residual(plan, op, c, x, b, r, norms2, work, work_bytes, stream):
 
 def ibs_divergence(plan, u, v, w, b, scale, stream):
     _check(lib.ibs_divergence(plan, u, v, w, b, scale, stream), "ibs_divergence")
+
+
+def ibs_stage_bytes(plan) -> int:
+    n = ctypes.c_size_t()
+    _check(lib.ibs_stage_bytes(plan, ctypes.byref(n)), "ibs_stage_bytes")
+    return n.value
+
+
+def ibs_rk_stage(plan, coef, fields, work, work_bytes, info, stream):
+    _check(lib.ibs_rk_stage(plan, ctypes.byref(coef), ctypes.byref(fields), work, work_bytes, info,
+                            stream), "ibs_rk_stage")
 
 
 def ibs_wall_data(plan, op, c, lo, hi, rhs, stream):
@@ -348,6 +374,35 @@ class Solver:
         ibs_divergence(self.plan, u.data_ptr(), v.data_ptr(), w.data_ptr(), b.data_ptr(), scale,
                        self.stream())
         return b
+
+    def rk_stage(self, u, v, w, p, nu, nv, nw, coef, markers=None, ud=None, dvol=None, force=None,
+                 work=None, info_slot=4):
+        """One Runge-Kutta sub-step in place on u, v, w, p (eqs. a-h); nu, nv,
+        nw: N of the stage before on input (read when zeta != 0), N of the
+        input velocity on output.  coef: dict alpha, beta, gamma, zeta, dt,
+        re.  Marker arrays: device tensors [nm][3], [nm][3], [nm] (and
+        force [nm][3] or None).  Reports in info slots info_slot..+3."""
+        torch = self.torch
+        for t, op in ((u, 1), (v, 2), (w, 3), (p, 0), (nu, 1), (nv, 2), (nw, 3)):
+            self._chk(t, op)
+        c = ibs_rk_coef(coef["alpha"], coef["beta"], coef["gamma"], coef["zeta"], coef["dt"], coef["re"])
+        f = ibs_stage_fields()
+        f.u, f.v, f.w, f.p = u.data_ptr(), v.data_ptr(), w.data_ptr(), p.data_ptr()
+        f.nu, f.nv, f.nw = nu.data_ptr(), nv.data_ptr(), nw.data_ptr()
+        nm = 0 if markers is None else int(markers.shape[0])
+        if nm:
+            for t in (markers, ud, dvol):
+                assert t.dtype == torch.float64 and t.is_contiguous() and t.device == self.device
+            f.markers, f.ud, f.dvol = markers.data_ptr(), ud.data_ptr(), dvol.data_ptr()
+            f.force = force.data_ptr() if force is not None else None
+        f.nmarkers = nm
+        nb = ibs_stage_bytes(self.plan)
+        if work is None:
+            if getattr(self, "_stage_work", None) is None or self._stage_work.numel() < nb:
+                self._stage_work = torch.empty(nb, dtype=torch.uint8, device=self.device)
+            work = self._stage_work
+        ibs_rk_stage(self.plan, c, f, work.data_ptr(), work.numel(), self.info[info_slot].data_ptr(),
+                     self.stream())
 
     def wall_data(self, op, rhs, lo=None, hi=None, c=0.0):
         """Add the wall data's contribution to rhs in place (lo, hi:

@@ -113,6 +113,18 @@ def forcing_shell(nx: int, ny: int, nz: int, seed: int, radius_frac: float = 0.1
     return fu, fv, fw
 
 
+def sphere_markers(count: int, radius: float, centre=(0.5, 0.5, 0.5)) -> np.ndarray:
+    """count points spread evenly over a sphere (golden-angle spiral), as
+    [count][3] physical coordinates (x, y, z): the Lagrangian markers of a
+    synthetic immersed body."""
+    q = np.arange(count) + 0.5
+    zc = 1.0 - 2.0 * q / count
+    th = np.pi * (1.0 + 5.0 ** 0.5) * q
+    r = np.sqrt(np.maximum(0.0, 1.0 - zc * zc))
+    return np.stack([centre[0] + radius * r * np.cos(th), centre[1] + radius * r * np.sin(th),
+                     centre[2] + radius * zc], axis=1)
+
+
 def manufactured(nx: int, ny: int, nz: int, seed: int, rows: int | None = None,
                  kmax: float | None = 8.0, noise: float = 1e-3):
     """A smooth seeded field plus a small white-noise part: used as a known
