@@ -287,6 +287,12 @@ def ibs_batch_destroy(batch: int):
 
 # ---------------------------------------------------------------------------
 # torch-owned buffers around one plan
+def info_record(row) -> ibs_solve_info:
+    """Decode one report record from a device or host float64 row."""
+    raw = row.cpu().numpy().tobytes()[:INFO_BYTES]
+    return ibs_solve_info.from_buffer_copy(raw)
+
+
 # ---------------------------------------------------------------------------
 class Solver:
     """One plan plus the device buffers it needs (torch allocations)."""
@@ -341,15 +347,24 @@ class Solver:
         assert t.dtype == self.torch.float64 and t.is_contiguous() and t.device == self.device
         assert tuple(t.shape) == self.shape(op), (tuple(t.shape), self.shape(op))
 
-    def poisson(self, b, phi=None):
+    def _info_ptr(self, info, slot, n):
+        """Device address of n report records: rows of `info` (a float64
+        tensor [>= n][INFO_BYTES/8] of the caller's) or the Solver's own."""
+        if info is None:
+            return self.info[slot].data_ptr()
+        assert info.dtype == self.torch.float64 and info.is_contiguous() and info.device == self.device
+        assert info.shape[0] >= n and info.shape[1] * 8 >= INFO_BYTES
+        return info.data_ptr()
+
+    def poisson(self, b, phi=None, info=None):
         self._chk(b, IBS_OP_POISSON)
         phi = self.empty() if phi is None else phi
         self._chk(phi, IBS_OP_POISSON)
         solve_poisson(self.plan, b.data_ptr(), phi.data_ptr(), self.work.data_ptr(),
-                      self.work_bytes, self.info.data_ptr(), self.stream())
+                      self.work_bytes, self._info_ptr(info, 0, 1), self.stream())
         return phi
 
-    def helmholtz(self, comps, cs, rs, xs=None, info_slot=0):
+    def helmholtz(self, comps, cs, rs, xs=None, info_slot=0, info=None):
         ops = [c + 1 for c in comps]
         if xs is None:
             xs = [self.empty(op) for op in ops]
@@ -358,7 +373,7 @@ class Solver:
             self._chk(x, op)
         solve_helmholtz_batch(self.plan, list(comps), list(cs), [r.data_ptr() for r in rs],
                               [x.data_ptr() for x in xs], self.work.data_ptr(), self.work_bytes,
-                              self.info[info_slot].data_ptr(), self.stream())
+                              self._info_ptr(info, info_slot, len(comps)), self.stream())
         return xs
 
     def residual(self, op, c, x, b, r=None, norms=False):
@@ -445,8 +460,11 @@ class Solver:
         return j
 
     def read_info(self, q=0):
-        raw = self.info[q].cpu().numpy().tobytes()[:INFO_BYTES]
-        return ibs_solve_info.from_buffer_copy(raw)
+        return info_record(self.info[q])
+
+    def new_info(self, n=4):
+        """A zeroed device buffer for n report records (see _info_ptr)."""
+        return self.torch.zeros((n, INFO_BYTES // 8), dtype=self.torch.float64, device=self.device)
 
     def close(self):
         if self.plan:

@@ -14,6 +14,14 @@ that does not fit yet is passed over by later ones that do, at most
 starvation).  Completion is detected by polling per-request events; latency
 runs from arrival to completion.
 
+Failure recovery: each request writes its solve reports (ibs_solve_info)
+into a small buffer of its own.  When a refined-precision request completes
+with IBS_ERR_NOT_CONVERGED (the device's error estimate missed tol within
+the pass cap), it goes back to the head of the queue as an FP64 request on
+the same grid, and only that second solve's result is delivered (latency
+still runs from the original arrival).  Any other non-zero status is
+recorded as a failed request.
+
 The scheduler talks to an executor.  GpuExecutor drives the C ABI (every
 solve step runs in the library's HIP kernels); tests substitute a fake
 executor to check admission and ordering on the CPU.
@@ -38,8 +46,11 @@ def field_bytes(n: int, kind: str) -> int:
     return 2 * 8 * (2 * cells + n * (n + 1) * n)
 
 
+NOT_CONVERGED = 5     # IBS_ERR_NOT_CONVERGED
+
+
 def plan_key(req):
-    return (req["n"], round(req["beta"], 12), req["refined"])
+    return (req["n"], round(req["beta"], 12), req["refined"], req.get("max_iter", 0))
 
 
 class GpuExecutor:
@@ -78,7 +89,8 @@ class GpuExecutor:
         ibs = self.ibs
         n = req["n"]
         prec = ibs.IBS_REFINED_BF16X3 if req["refined"] else ibs.IBS_FP64
-        plan = ibs.solver_plan(ibs.make_desc(n, n, n, beta=req["beta"], precision=prec))
+        plan = ibs.solver_plan(ibs.make_desc(n, n, n, beta=req["beta"], precision=prec,
+                                             max_iter=req.get("max_iter", 0)))
         cb, wp = ibs.solver_plan_bytes(plan, ibs.IBS_OP_POISSON)
         _, wh = ibs.solver_plan_bytes(plan, ibs.IBS_OP_HELMHOLTZ_U, 3)
         if max(wp, wh) > self.work_bytes:
@@ -94,7 +106,7 @@ class GpuExecutor:
         n = req["n"]
         prec = ibs.IBS_REFINED_BF16X3 if req["refined"] else ibs.IBS_FP64
         S = ibs.Solver(n, n, n, beta=req["beta"], precision=prec, device=self.device,
-                       plan=prepared[0], alloc_work=False)
+                       plan=prepared[0], alloc_work=False, max_iter=req.get("max_iter", 0))
         # the constants were copied on the current stream; make them visible
         # to the slot streams before first use
         self.torch.cuda.current_stream(self.device).synchronize()
@@ -109,17 +121,19 @@ class GpuExecutor:
         S.close()
 
     def launch(self, slot, req, S):
-        """Enqueue the request; returns (event, fields, outputs, cell_solves)."""
+        """Enqueue the request; returns (event, fields, outputs, cell_solves,
+        report), report being the request's device buffer of solve reports."""
         from .batch import cn_coefficient
         torch = self.torch
         stream = self.streams[slot]
         n = req["n"]
         S.work, S.work_bytes = self.slot_work[slot], self.work_bytes
         with torch.cuda.stream(stream):
+            info = S.new_info(3)
             if req["kind"] == "poisson":
                 b = synth.device_normal(S.shape(0), req["seed"], self.device)
                 phi = S.empty(0)
-                S.poisson(b, phi)
+                S.poisson(b, phi, info=info)
                 fields, outs, cells = [b, phi], [phi], n ** 3
             else:
                 rs = [synth.device_normal(S.shape(op), req["seed"] * 4 + op, self.device)
@@ -128,11 +142,16 @@ class GpuExecutor:
                 rs[1][:, n, :] = 0
                 xs = [S.empty(op) for op in (1, 2, 3)]
                 c = cn_coefficient(S)
-                S.helmholtz([0, 1, 2], [c, c, c], rs, xs)
+                S.helmholtz([0, 1, 2], [c, c, c], rs, xs, info=info)
                 fields, outs, cells = rs + xs, xs, 3 * n ** 3
             ev = torch.cuda.Event()
             ev.record(stream)
-        return ev, fields, outs, cells
+        return ev, fields, outs, cells, (info, 1 if req["kind"] == "poisson" else 3)
+
+    def statuses(self, report):
+        """Status of each solve of a completed request."""
+        info, n = report
+        return [self.ibs.info_record(info[q]).status for q in range(n)]
 
     @staticmethod
     def fetch(outs):
@@ -236,6 +255,8 @@ class InFlight:
     outputs: list
     bytes: int
     admitted: float
+    cells: int = 0
+    report: object = None
 
 
 @dataclass
@@ -250,6 +271,8 @@ class ServeResult:
     peak_bytes: int = 0
     plan_hits: int = 0
     plan_misses: int = 0
+    fallbacks: list = field(default_factory=list)   # rids re-run on the FP64 path
+    failed: dict = field(default_factory=dict)      # rid -> statuses of a failed request
 
     def summary(self) -> dict:
         lat = self.latencies * 1e3
@@ -259,7 +282,8 @@ class ServeResult:
                 "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
                 "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
                 "max_inflight": self.max_inflight, "peak_bytes": self.peak_bytes,
-                "plan_hits": self.plan_hits, "plan_misses": self.plan_misses}
+                "plan_hits": self.plan_hits, "plan_misses": self.plan_misses,
+                "fallbacks": len(self.fallbacks), "failed": len(self.failed)}
 
 
 class Server:
@@ -287,6 +311,7 @@ class Server:
         inflight = [None] * self.slots
         used = self.cache.bytes + fixed
         lat, cell_solves, outputs, order = [], 0, {}, []
+        fallbacks, failed = [], {}
         nreq, nxt, done = len(requests), 0, 0
         max_inflight, peak = 0, used
         bypassed = 0     # admissions that went ahead of the current oldest request
@@ -301,14 +326,26 @@ class Server:
             progressed = False
             for s, f in enumerate(inflight):
                 if f is not None and f.event.query():
-                    lat.append(self.clock() - t0 - f.req["arrival"])
-                    if self.keep:
-                        outputs[f.req["rid"]] = self.ex.fetch(f.outputs)
+                    st = self.ex.statuses(f.report)
                     used -= f.bytes
                     self.cache.release(f.req)
                     inflight[s] = None
-                    done += 1
                     progressed = True
+                    if f.req["refined"] and NOT_CONVERGED in st:
+                        # recover on the FP64 path, ahead of every waiting request
+                        retry = dict(f.req, refined=False, max_iter=0)
+                        fallbacks.append(f.req["rid"])
+                        pending.insert(0, retry)
+                        self.cache.prefetch(retry)
+                        continue
+                    lat.append(self.clock() - t0 - f.req["arrival"])
+                    if any(st):
+                        failed[f.req["rid"]] = st
+                    else:
+                        cell_solves += f.cells
+                    if self.keep:
+                        outputs[f.req["rid"]] = self.ex.fetch(f.outputs)
+                    done += 1
             idx = 0
             while idx < min(len(pending), self.lookahead):
                 s = next((i for i, f in enumerate(inflight) if f is None), None)
@@ -327,9 +364,8 @@ class Server:
                 used += nb
                 del pending[idx]
                 bypassed = bypassed + 1 if idx > 0 else 0
-                ev, fields, outs, cells = self.ex.launch(s, req, S)
-                cell_solves += cells
-                inflight[s] = InFlight(req, ev, fields, outs, fb, self.clock() - t0)
+                ev, fields, outs, cells, report = self.ex.launch(s, req, S)
+                inflight[s] = InFlight(req, ev, fields, outs, fb, self.clock() - t0, cells, report)
                 used += fb
                 order.append(req["rid"])
                 progressed = True
@@ -339,12 +375,12 @@ class Server:
                 self.idle()
         makespan = self.clock() - t0
         return ServeResult(np.array(lat), makespan, cell_solves, done, outputs, max_inflight, order,
-                           peak, self.cache.hits, self.cache.misses)
+                           peak, self.cache.hits, self.cache.misses, fallbacks, failed)
 
     def run_alone(self, req):
         """Run one request by itself (for the alone-versus-mixed check)."""
         S, _ = self.cache.acquire(req, self.budget)
-        ev, fields, outs, _ = self.ex.launch(0, req, S)
+        ev, fields, outs, _, _ = self.ex.launch(0, req, S)
         self.ex.synchronize()
         self.cache.release(req)
         return self.ex.fetch(outs)

@@ -67,3 +67,41 @@ def test_mixed_equals_alone_and_oracle():
         print("served", kind, "refined" if refined else "fp64", "n", n, "errs", errs, flush=True)
         assert max(errs) < tol
     srv.close()
+
+
+def test_refined_not_converged_falls_back_to_fp64():
+    """Refined requests capped at one pass cannot reach tol and report
+    NOT_CONVERGED; the server re-runs them on the FP64 path and delivers
+    that result, which matches the oracle to the FP64 bound."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_19920_amd import serve
+    print("case serve fallback", flush=True)
+    reqs = [dict(rid=0, arrival=0.0, kind="poisson", refined=True, n=48, beta=1.5, seed=31, max_iter=1),
+            dict(rid=1, arrival=0.0, kind="helmholtz", refined=True, n=32, beta=1.0, seed=32, max_iter=1),
+            dict(rid=2, arrival=0.0, kind="poisson", refined=True, n=32, beta=0.5, seed=33)]
+    ex = serve.GpuExecutor(slots=2, nmax=64)
+    srv = serve.Server(ex, 4 << 30, slots=2, keep_outputs=True)
+    res = srv.run(reqs)
+    print("summary", res.summary(), "fallbacks", res.fallbacks, flush=True)
+    assert res.completed == 3 and not res.failed
+    assert sorted(res.fallbacks) == [0, 1]
+    for r in reqs:
+        n = r["n"]
+        g = oracle.Grid(n, n, n, beta=r["beta"])
+        got = res.outputs[r["rid"]]
+        if r["kind"] == "poisson":
+            b = synth.device_normal((n, n, n), r["seed"], "cuda").cpu().numpy()
+            errs = [_rel(got[0].numpy(), oracle.solve(g, OP_P, b)[0])]
+        else:
+            c = 0.125 * min(float(g.dyc.min()), 1.0 / n) ** 2
+            errs = []
+            for q, op in enumerate((OP_U, OP_V, OP_W)):
+                f = synth.device_normal(g.shape(op), r["seed"] * 4 + op, "cuda").cpu().numpy()
+                if op == OP_V:
+                    f[:, 0, :] = 0
+                    f[:, n, :] = 0
+                errs.append(_rel(got[q].numpy(), oracle.solve(g, op, f, c=c)[0]))
+        print("request", r["rid"], "errs", errs, flush=True)
+        assert max(errs) < (1e-12 if r["rid"] in res.fallbacks else 1e-10)
+    srv.close()

@@ -29,8 +29,10 @@ class FakeEvent:
 class FakeExecutor:
     """Duration proportional to the cells solved; bytes proportional to n^3."""
 
-    def __init__(self, clock, rate_cells_per_s=1e9, fail_rid=None):
+    def __init__(self, clock, rate_cells_per_s=1e9, fail_rid=None, diverge=(), bad=()):
         self.clock = clock
+        self.diverge = set(diverge)    # rids whose refined solve reports NOT_CONVERGED
+        self.bad = set(bad)            # rids that report another error on every path
         self.rate = rate_cells_per_s
         self.fail_rid = fail_rid
         self.running = []
@@ -62,7 +64,19 @@ class FakeExecutor:
         same = sum(1 for e in live if e[1] == S["key"]) + 1
         self.max_same_plan = max(self.max_same_plan, same)
         self.running = live + [(ev, S["key"])]
-        return ev, [], [req["rid"]], cells
+        n = 1 if req["kind"] == "poisson" else 3
+        if req["rid"] in self.bad:
+            st = [6] * n
+        elif req["refined"] and req["rid"] in self.diverge:
+            st = [0] * (n - 1) + [serve.NOT_CONVERGED]
+        else:
+            st = [0] * n
+        self.launched = getattr(self, "launched", []) + [(req["rid"], req["refined"])]
+        return ev, [], [(req["rid"], req["refined"])], cells, st
+
+    @staticmethod
+    def statuses(report):
+        return report
 
     @staticmethod
     def fetch(outs):
@@ -194,3 +208,37 @@ def test_geometry_pool_reuses_plans():
     assert d["completed"] == 400
     # one miss per plan key at most per concurrent use; most requests hit
     assert d["plan_hits"] > 300 and d["plan_hits"] + d["plan_misses"] == 400
+
+
+def test_not_converged_refined_request_falls_back_to_fp64():
+    """A refined request reporting NOT_CONVERGED is re-run once on the FP64
+    path, ahead of the queue; the FP64 result is the one delivered, its
+    latency runs from the original arrival, and its cells count once."""
+    reqs = synth.serving_requests(2000.0, 40, seed=3, nmin=32, nmax=96)
+    refined = [r["rid"] for r in reqs if r["refined"]]
+    fp64 = [r["rid"] for r in reqs if not r["refined"]]
+    diverge = refined[:3] + fp64[:1]          # the FP64 one must not be retried
+    srv, ex, _ = _server(diverge=diverge)
+    res = srv.run(reqs)
+    assert res.completed == len(reqs) and len(res.latencies) == len(reqs)
+    assert sorted(res.fallbacks) == sorted(refined[:3])
+    assert not res.failed
+    for rid in refined[:3]:
+        assert res.outputs[rid] == [(rid, False)]            # delivered from the FP64 re-run
+        assert ex.launched.count((rid, True)) == 1 and ex.launched.count((rid, False)) == 1
+    for rid in refined[3:]:
+        assert res.outputs[rid] == [(rid, True)]
+    cells = sum(r["n"] ** 3 * (1 if r["kind"] == "poisson" else 3) for r in reqs)
+    assert res.cell_solves == cells
+    assert res.summary()["fallbacks"] == 3
+
+
+def test_other_errors_are_reported_not_retried():
+    reqs = synth.serving_requests(500.0, 12, seed=4, nmin=32, nmax=64)
+    bad = [reqs[2]["rid"], reqs[5]["rid"]]
+    srv, ex, _ = _server(bad=bad)
+    res = srv.run(reqs)
+    assert res.completed == len(reqs)
+    assert sorted(res.failed) == sorted(bad)
+    assert not res.fallbacks
+    assert len(ex.launched) == len(reqs)
