@@ -95,7 +95,7 @@ class _CGeom(ctypes.Structure):
                 ("hx", ctypes.c_double), ("hz", ctypes.c_double),
                 ("dyc", ctypes.POINTER(ctypes.c_double)),
                 ("dyf", ctypes.POINTER(ctypes.c_double)),
-                ("py", ctypes.c_int)]
+                ("py", ctypes.c_int), ("wx", ctypes.c_int)]
 
 
 class _CInfo(ctypes.Structure):
@@ -111,7 +111,11 @@ class Grid:
     the tanh stretching in y is this library's extension.  periodic_y: the
     triply periodic branch (Section 2.3.3, items S1 and S2): y wraps, no
     walls, v has ny faces, and delta_0 = delta_ny is the distance between
-    the centres of cells ny-1 and 0 across the wrap."""
+    the centres of cells ny-1 and 0 across the wrap.  periodic_x=False: walls
+    at x = 0 and x = lx (the paper's non-periodic direction, Section 3.2):
+    u Dirichlet (zero on the wall faces; slot 0 of u is the wall face x = 0,
+    the face x = lx is not stored), v and w Dirichlet through a mirror ghost,
+    the pressure homogeneous Neumann."""
     nx: int
     ny: int
     nz: int
@@ -121,6 +125,7 @@ class Grid:
     beta: float = 0.0
     yf_in: np.ndarray | None = None
     periodic_y: bool = False
+    periodic_x: bool = True
     yf: np.ndarray = field(init=False)
     yc: np.ndarray = field(init=False)
     dyc: np.ndarray = field(init=False)
@@ -146,7 +151,10 @@ class Grid:
                 raise ValueError("periodic y needs ny >= 3")
             self.dyf[0] = self.dyf[ny] = 0.5 * (self.dyc[0] + self.dyc[ny - 1])
         self._c = _CGeom(self.nx, self.ny, self.nz, self.hx, self.hz,
-                         _dp(self.dyc), _dp(self.dyf), 1 if self.periodic_y else 0)
+                         _dp(self.dyc), _dp(self.dyf), 1 if self.periodic_y else 0,
+                         0 if self.periodic_x else 1)
+        if not self.periodic_x and self.nx < 3:
+            raise ValueError("walls in x need nx >= 3")
 
     @property
     def hx(self) -> float:
@@ -205,9 +213,12 @@ def weights(g: Grid, op: int) -> np.ndarray:
 
 
 def unknowns_of(g: Grid, op: int, x: np.ndarray) -> np.ndarray:
-    """Flatten a full-layout field to the unknown ordering (drops v walls)."""
+    """Flatten a full-layout field to the unknown ordering (drops the wall
+    faces of v, and of u with x walls)."""
     if op == OP_V and not g.periodic_y:
         return np.ascontiguousarray(x[:, 1:g.ny, :]).reshape(-1)
+    if op == OP_U and not g.periodic_x:
+        return np.ascontiguousarray(x[:, :, 1:]).reshape(-1)
     return np.ascontiguousarray(x).reshape(-1)
 
 

@@ -15,7 +15,12 @@ differences on a staggered grid) and Appendix B (wall rows):
 * the operator for v (interior y faces) is G_y D_y with wall values v = 0;
 * periodic y (the triply periodic branch): the y differences wrap, the
   pressure Laplacian is still literally D G, u and w take D_y G_y and v
-  G_y D_y over all ny faces.
+  G_y D_y over all ny faces;
+* walls in x (``periodic_x=False``): the x differences stop at the walls.
+  The u slots are faces 0..nx-1 with slot 0 the wall face (a zero column
+  of D_x, a zero row of G_x) and the face nx absent (zero), so L_p = D G
+  is again literal; u takes G_x D_x on the interior faces 1..nx-1, and v,
+  w the mirror-ghost rows in x, as u and w have at the y walls.
 
 The dense solve uses ``numpy.linalg.solve``.  For the singular Neumann
 pressure problem it solves the bordered system
@@ -99,6 +104,46 @@ def gy_cells_to_faces_periodic(g: Grid) -> np.ndarray:
     return m
 
 
+def dx_faces_to_cells_walls(n: int, h: float) -> np.ndarray:
+    """(n x n), x walls: (F_{i+1} - F_i)/h with the face slots 0..n-1, slot
+    0 the wall face (its column is zero: u = 0 there) and face n absent."""
+    m = np.zeros((n, n))
+    for i in range(n):
+        if i + 1 < n:
+            m[i, i + 1] = 1.0 / h
+        if i >= 1:
+            m[i, i] = -1.0 / h
+    return m
+
+
+def gx_cells_to_faces_walls(n: int, h: float) -> np.ndarray:
+    """(n x n), x walls: (f_i - f_{i-1})/h on the face slots 1..n-1, zero on
+    the wall slot 0 (homogeneous Neumann)."""
+    m = np.zeros((n, n))
+    for i in range(1, n):
+        m[i, i] = 1.0 / h
+        m[i, i - 1] = -1.0 / h
+    return m
+
+
+def lx_mirror_walls(n: int, h: float) -> np.ndarray:
+    """(n x n) x part of the Laplacian of a cell-centred (in x) velocity with
+    Dirichlet walls: D over the n+1 faces of the gradient whose wall faces
+    take the mirror ghost (opposite sign, one cell away): 2 f_0/h and
+    -2 f_{n-1}/h."""
+    G = np.zeros((n + 1, n))
+    for i in range(1, n):
+        G[i, i] = 1.0 / h
+        G[i, i - 1] = -1.0 / h
+    G[0, 0] = 2.0 / h
+    G[n, n - 1] = -2.0 / h
+    D = np.zeros((n, n + 1))
+    for i in range(n):
+        D[i, i + 1] = 1.0 / h
+        D[i, i] = -1.0 / h
+    return D @ G
+
+
 def _k3(az, ay, ax):
     return np.kron(az, np.kron(ay, ax))
 
@@ -106,7 +151,8 @@ def _k3(az, ay, ax):
 def divergence_matrix(g: Grid) -> np.ndarray:
     """D: cells <- (u faces, v faces incl. walls, w faces)."""
     Ix, Iy, Iz = np.eye(g.nx), np.eye(g.ny), np.eye(g.nz)
-    Du = _k3(Iz, Iy, _circ_diff_fwd(g.nx, g.hx))
+    Dx = _circ_diff_fwd(g.nx, g.hx) if g.periodic_x else dx_faces_to_cells_walls(g.nx, g.hx)
+    Du = _k3(Iz, Iy, Dx)
     Dv = _k3(Iz, dy_faces_to_cells_periodic(g) if g.periodic_y else dy_faces_to_cells(g), Ix)
     Dw = _k3(_circ_diff_fwd(g.nz, g.hz), Iy, Ix)
     return np.hstack([Du, Dv, Dw])
@@ -115,7 +161,8 @@ def divergence_matrix(g: Grid) -> np.ndarray:
 def gradient_matrix(g: Grid) -> np.ndarray:
     """G: (u faces, v faces incl. walls, w faces) <- cells."""
     Ix, Iy, Iz = np.eye(g.nx), np.eye(g.ny), np.eye(g.nz)
-    Gu = _k3(Iz, Iy, _circ_diff_bwd(g.nx, g.hx))
+    Gx = _circ_diff_bwd(g.nx, g.hx) if g.periodic_x else gx_cells_to_faces_walls(g.nx, g.hx)
+    Gu = _k3(Iz, Iy, Gx)
     Gv = _k3(Iz, gy_cells_to_faces_periodic(g) if g.periodic_y else gy_cells_to_faces_neumann(g), Ix)
     Gw = _k3(_circ_diff_bwd(g.nz, g.hz), Iy, Ix)
     return np.vstack([Gu, Gv, Gw])
@@ -126,7 +173,14 @@ def laplacian(g: Grid, op: int) -> np.ndarray:
     Ix, Iz = np.eye(g.nx), np.eye(g.nz)
     if op == OP_P:
         return divergence_matrix(g) @ gradient_matrix(g)
-    Lx = _circ_diff_bwd(g.nx, g.hx) @ _circ_diff_fwd(g.nx, g.hx)
+    if g.periodic_x:
+        Lx = _circ_diff_bwd(g.nx, g.hx) @ _circ_diff_fwd(g.nx, g.hx)
+    elif op == OP_U:
+        full = gx_cells_to_faces_walls(g.nx, g.hx) @ dx_faces_to_cells_walls(g.nx, g.hx)
+        Lx = full[1:, 1:]
+        Ix = np.eye(g.nx - 1)
+    else:
+        Lx = lx_mirror_walls(g.nx, g.hx)
     Lz = _circ_diff_bwd(g.nz, g.hz) @ _circ_diff_fwd(g.nz, g.hz)
     if g.periodic_y:
         Iy = np.eye(g.ny)
@@ -149,6 +203,7 @@ def laplacian(g: Grid, op: int) -> np.ndarray:
 
 
 def weights(g: Grid, op: int) -> np.ndarray:
+    nxu = g.nx - 1 if (op == OP_U and not g.periodic_x) else g.nx
     if op == OP_V and g.periodic_y:
         wy = g.dyf[:g.ny]
         nyu = g.ny
@@ -158,7 +213,7 @@ def weights(g: Grid, op: int) -> np.ndarray:
     else:
         wy = g.dyc
         nyu = g.ny
-    return np.broadcast_to((g.hx * g.hz * wy)[None, :, None], (g.nz, nyu, g.nx)).reshape(-1).copy()
+    return np.broadcast_to((g.hx * g.hz * wy)[None, :, None], (g.nz, nyu, nxu)).reshape(-1).copy()
 
 
 def operator(g: Grid, op: int, c: float = 0.0) -> np.ndarray:
@@ -171,8 +226,11 @@ def operator(g: Grid, op: int, c: float = 0.0) -> np.ndarray:
 def solve(g: Grid, op: int, b: np.ndarray, c: float = 0.0) -> np.ndarray:
     """Dense solve; b and the result in the full array layout."""
     walls = op == OP_V and not g.periodic_y
+    xwalls = op == OP_U and not g.periodic_x
     if walls:
         rhs = np.ascontiguousarray(b[:, 1:g.ny, :]).reshape(-1)
+    elif xwalls:
+        rhs = np.ascontiguousarray(b[:, :, 1:]).reshape(-1)
     else:
         rhs = np.ascontiguousarray(b).reshape(-1)
     A = operator(g, op, c)
@@ -189,6 +247,8 @@ def solve(g: Grid, op: int, b: np.ndarray, c: float = 0.0) -> np.ndarray:
     out = np.zeros(g.shape(op))
     if walls:
         out[:, 1:g.ny, :] = sol.reshape(g.nz, g.ny - 1, g.nx)
+    elif xwalls:
+        out[:, :, 1:] = sol.reshape(g.nz, g.ny, g.nx - 1)
     else:
         out[...] = sol.reshape(g.shape(op))
     return out

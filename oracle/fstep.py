@@ -257,6 +257,8 @@ def stage(g: Grid, u, v, w, p, coef, n_prev=None, markers=None, ud=None, dvol=No
     n_prev: (N_u, N_v, N_w) of the stage before (needed when zeta != 0).
     Returns dict with u, v, w, p (the new fields), n (N of the input
     velocity, for the next stage), force ([nm][3] or None), phi, ue."""
+    if not g.periodic_x:
+        raise ValueError("the sub-step is written for a periodic x")
     al, be, ga, ze = (coef[k] for k in ("alpha", "beta", "gamma", "zeta"))
     dt, re = coef["dt"], coef["re"]
     vel = [np.asarray(a, dtype=np.float64) for a in (u, v, w)]

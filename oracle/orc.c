@@ -41,6 +41,16 @@
  * ([nz][ny][nx], face ny being face 0), and the pressure's null mode is
  * fixed by the same zero weighted mean.
  *
+ * Walls in x (geometry flag wx; the non-periodic direction of the paper's
+ * inflow-outflow example, Section 3.2, as walls): the faces x = 0 and
+ * x = lx bound the domain.  The x-face velocity u is Dirichlet there (zero
+ * on both wall faces) and keeps the [nz][ny][nx] layout: slot i holds face
+ * i, slot 0 being the wall face x = 0 (ignored on input, written as zero on
+ * output; the wall face x = lx is not stored), so its unknowns are faces
+ * 1..nx-1.  v and w (cell centres in x) take the mirror-ghost Dirichlet
+ * row, as u and w do at the y walls; the pressure takes homogeneous Neumann
+ * (zero flux through the walls), so its null mode is again the constant.
+ *
  * Operator codes: 0 = pressure Poisson (A = L_p), 1 = u Helmholtz,
  * 2 = v Helmholtz, 3 = w Helmholtz (A = I - c L).
  */
@@ -63,6 +73,8 @@ typedef struct {
     int py;            /* 1: y periodic too (the triply periodic        */
                        /*    branch, Section 2.3.3, items S1/S2): no    */
                        /*    walls, v has ny faces [nz][ny][nx]         */
+    int wx;            /* 1: walls at x = 0 and x = lx instead of the   */
+                       /*    periodic x (see the header comment)        */
 } orc_geom;
 
 typedef struct {
@@ -132,7 +144,10 @@ void orc_divergence(const orc_geom *g, const double *u, const double *v,
     for (int k = 0; k < g->nz; ++k)
         for (int j = 0; j < g->ny; ++j)
             for (int i = 0; i < g->nx; ++i) {
-                double du = (u[cidx(g, wrap(i + 1, g->nx), j, k)] - u[cidx(g, i, j, k)]) / g->hx;
+                /* x walls: u = 0 on the wall faces 0 and nx */
+                double ue = (g->wx && i + 1 == g->nx) ? 0.0 : u[cidx(g, wrap(i + 1, g->nx), j, k)];
+                double uw = (g->wx && i == 0) ? 0.0 : u[cidx(g, i, j, k)];
+                double du = (ue - uw) / g->hx;
                 int jt = (g->py && j + 1 == g->ny) ? 0 : j + 1;   /* face ny = face 0 */
                 double dv = (v[vidx(g, i, jt, k)] - v[vidx(g, i, j, k)]) / g->dyc[j];
                 double dw = (w[cidx(g, i, j, wrap(k + 1, g->nz))] - w[cidx(g, i, j, k)]) / g->hz;
@@ -140,9 +155,10 @@ void orc_divergence(const orc_geom *g, const double *u, const double *v,
             }
 }
 
-/* Components of G(phi): (phi_i - phi_{i-1})/hx on x-faces,
- * (phi_j - phi_{j-1})/delta_j on interior y-faces (zero on the wall faces:
- * homogeneous Neumann), (phi_k - phi_{k-1})/hz on z-faces. */
+/* Components of G(phi): (phi_i - phi_{i-1})/hx on x-faces (zero on the
+ * wall face 0 with x walls), (phi_j - phi_{j-1})/delta_j on interior
+ * y-faces (zero on the wall faces: homogeneous Neumann), (phi_k -
+ * phi_{k-1})/hz on z-faces. */
 void orc_gradient(const orc_geom *g, const double *phi, double *gu, double *gv,
                   double *gw)
 {
@@ -153,7 +169,7 @@ void orc_gradient(const orc_geom *g, const double *phi, double *gu, double *gv,
                 if (g->py) {
                     /* every face is interior; face 0 lies between cells
                      * ny-1 and 0, dyf[0] apart */
-                    gu[cidx(g, i, j, k)] =
+                    gu[cidx(g, i, j, k)] = (g->wx && i == 0) ? 0.0 :
                         (phi[cidx(g, i, j, k)] - phi[cidx(g, wrap(i - 1, g->nx), j, k)]) / g->hx;
                     gw[cidx(g, i, j, k)] =
                         (phi[cidx(g, i, j, k)] - phi[cidx(g, i, j, wrap(k - 1, g->nz))]) / g->hz;
@@ -162,7 +178,7 @@ void orc_gradient(const orc_geom *g, const double *phi, double *gu, double *gv,
                     continue;
                 }
                 if (j < g->ny) {
-                    gu[cidx(g, i, j, k)] =
+                    gu[cidx(g, i, j, k)] = (g->wx && i == 0) ? 0.0 :
                         (phi[cidx(g, i, j, k)] - phi[cidx(g, wrap(i - 1, g->nx), j, k)]) / g->hx;
                     gw[cidx(g, i, j, k)] =
                         (phi[cidx(g, i, j, k)] - phi[cidx(g, i, j, wrap(k - 1, g->nz))]) / g->hz;
@@ -186,26 +202,32 @@ static int ny_unknowns(const orc_geom *g, int op)
     return (op == 2 && !g->py) ? g->ny - 1 : g->ny;
 }
 static int first_y(const orc_geom *g, int op) { return (op == 2 && !g->py) ? 1 : 0; }
+/* x unknowns per row: u has the interior faces 1..nx-1 with x walls */
+static int nx_unknowns(const orc_geom *g, int op)
+{
+    return (op == 1 && g->wx) ? g->nx - 1 : g->nx;
+}
+static int first_x(const orc_geom *g, int op) { return (op == 1 && g->wx) ? 1 : 0; }
 static int64_t n_unknowns(const orc_geom *g, int op)
 {
-    return (int64_t)g->nx * ny_unknowns(g, op) * g->nz;
+    return (int64_t)nx_unknowns(g, op) * ny_unknowns(g, op) * g->nz;
 }
 /* (i, j, k) of unknown number r; for op 2 with walls, j is the face index
- * 1..ny-1 */
+ * 1..ny-1; for op 1 with x walls, i is the face index 1..nx-1 */
 static void unknown_ijk(const orc_geom *g, int op, int64_t r, int *i, int *j,
                         int *k)
 {
-    int nyu = ny_unknowns(g, op);
-    *i = (int)(r % g->nx);
-    int64_t t = r / g->nx;
+    int nyu = ny_unknowns(g, op), nxu = nx_unknowns(g, op);
+    *i = (int)(r % nxu) + first_x(g, op);
+    int64_t t = r / nxu;
     *j = (int)(t % nyu) + first_y(g, op);
     *k = (int)(t / nyu);
 }
 static int64_t unknown_id(const orc_geom *g, int op, int i, int j, int k)
 {
-    int nyu = ny_unknowns(g, op);
-    int jj = j - first_y(g, op);
-    return ((int64_t)k * nyu + jj) * g->nx + i;
+    int nyu = ny_unknowns(g, op), nxu = nx_unknowns(g, op);
+    int jj = j - first_y(g, op), ii = i - first_x(g, op);
+    return ((int64_t)k * nyu + jj) * nxu + ii;
 }
 /* position of unknown r in the caller's full array layout */
 static int64_t unknown_to_array(const orc_geom *g, int op, int64_t r)
@@ -242,10 +264,31 @@ static int laplacian_row(const orc_geom *g, int op, int i, int j, int k,
     int n = 0;
     const double ax = 1.0 / (g->hx * g->hx), az = 1.0 / (g->hz * g->hz);
     int64_t me = unknown_id(g, op, i, j, k);
-    /* periodic x and z: (f_{i+1} - 2 f_i + f_{i-1}) / h^2 */
-    n = add_entry(cols, vals, n, me, -2.0 * ax - 2.0 * az);
-    n = add_entry(cols, vals, n, unknown_id(g, op, wrap(i - 1, g->nx), j, k), ax);
-    n = add_entry(cols, vals, n, unknown_id(g, op, wrap(i + 1, g->nx), j, k), ax);
+    /* periodic z: (f_{k+1} - 2 f_k + f_{k-1}) / h^2 */
+    n = add_entry(cols, vals, n, me, -2.0 * az);
+    if (!g->wx) { /* periodic x: the same */
+        n = add_entry(cols, vals, n, me, -2.0 * ax);
+        n = add_entry(cols, vals, n, unknown_id(g, op, wrap(i - 1, g->nx), j, k), ax);
+        n = add_entry(cols, vals, n, unknown_id(g, op, wrap(i + 1, g->nx), j, k), ax);
+    } else if (op == 1) { /* x faces 1..nx-1, wall values u_0 = u_nx = 0 */
+        n = add_entry(cols, vals, n, me, -2.0 * ax);
+        if (i + 1 <= g->nx - 1) n = add_entry(cols, vals, n, unknown_id(g, op, i + 1, j, k), ax);
+        if (i - 1 >= 1) n = add_entry(cols, vals, n, unknown_id(g, op, i - 1, j, k), ax);
+    } else { /* cell centres in x: interior flux, or at a wall zero flux
+              * (pressure, Neumann) or the mirror-ghost flux -2 f/hx (v, w) */
+        if (i + 1 < g->nx) {
+            n = add_entry(cols, vals, n, me, -ax);
+            n = add_entry(cols, vals, n, unknown_id(g, op, i + 1, j, k), ax);
+        } else if (op != 0) {
+            n = add_entry(cols, vals, n, me, -2.0 * ax);
+        }
+        if (i > 0) {
+            n = add_entry(cols, vals, n, me, -ax);
+            n = add_entry(cols, vals, n, unknown_id(g, op, i - 1, j, k), ax);
+        } else if (op != 0) {
+            n = add_entry(cols, vals, n, me, -2.0 * ax);
+        }
+    }
     n = add_entry(cols, vals, n, unknown_id(g, op, i, j, wrap(k - 1, g->nz)), az);
     n = add_entry(cols, vals, n, unknown_id(g, op, i, j, wrap(k + 1, g->nz)), az);
     const int ny = g->ny;
@@ -369,9 +412,23 @@ static long double flux_apply_bc_ld(const orc_geom *g, int op, int i, int j, int
     long double hx = g->hx, hz = g->hz;
     int64_t (*at)(const orc_geom *, int, int, int) = (op == 2) ? vidx : cidx;
     long double xc = x[at(g, i, j, k)];
-    long double xe = x[at(g, wrap(i + 1, nx), j, k)], xw = x[at(g, wrap(i - 1, nx), j, k)];
     long double xt = x[at(g, i, j, wrap(k + 1, nz))], xb = x[at(g, i, j, wrap(k - 1, nz))];
-    long double lap = ((xe - xc) / hx - (xc - xw) / hx) / hx + ((xt - xc) / hz - (xc - xb) / hz) / hz;
+    long double fe, fw;   /* x fluxes through the east and west sides */
+    if (!g->wx) {
+        fe = ((long double)x[at(g, wrap(i + 1, nx), j, k)] - xc) / hx;
+        fw = (xc - (long double)x[at(g, wrap(i - 1, nx), j, k)]) / hx;
+    } else if (op == 1) { /* faces: wall values u_0 = u_nx = 0 */
+        long double xe = (i + 1 <= nx - 1) ? (long double)x[at(g, i + 1, j, k)] : 0.0L;
+        long double xw = (i - 1 >= 1) ? (long double)x[at(g, i - 1, j, k)] : 0.0L;
+        fe = (xe - xc) / hx;
+        fw = (xc - xw) / hx;
+    } else { /* cells: Neumann (pressure) or mirror ghost (v, w) at a wall */
+        fe = (i + 1 < nx) ? ((long double)x[at(g, i + 1, j, k)] - xc) / hx
+                          : (op == 0 ? 0.0L : -xc / (hx / 2.0L));
+        fw = (i > 0) ? (xc - (long double)x[at(g, i - 1, j, k)]) / hx
+                     : (op == 0 ? 0.0L : xc / (hx / 2.0L));
+    }
+    long double lap = (fe - fw) / hx + ((xt - xc) / hz - (xc - xb) / hz) / hz;
     if (g->py) {
         int jn = wrap(j + 1, ny), js = wrap(j - 1, ny);
         long double xn = x[at(g, i, jn, k)], xs = x[at(g, i, js, k)];
@@ -440,6 +497,10 @@ void orc_residual_bc_ld(const orc_geom *g, int op, double c, const double *x,
                 r[vidx(g, i, 0, k)] = 0.0;
                 r[vidx(g, i, g->ny, k)] = 0.0;
             }
+    }
+    if (op == 1 && g->wx) { /* the wall face x = 0 */
+        for (int k = 0; k < g->nz; ++k)
+            for (int j = 0; j < g->ny; ++j) r[cidx(g, 0, j, k)] = 0.0;
     }
     if (norms) {
         norms[0] = sqrt((double)rr);
