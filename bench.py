@@ -310,6 +310,9 @@ def main():
         r3, w3 = run_3p(10, 2)
         configs["triply_periodic"] = {"workload": w3, "steps": 10, "warmup": 2,
                                       "unit": "Mcell-solves/s", **r3}
+        log("config xw")
+        rx, wx = run_xw(10, 2)
+        configs["x_walls"] = {"workload": wx, "steps": 10, "warmup": 2, "unit": "Mcell-solves/s", **rx}
         log("config rk3")
         rr, wr = run_rk3(5, 1)
         configs["rk3_step"] = {"workload": wr, "steps": 5, "warmup": 1,
@@ -554,6 +557,51 @@ def run_3p(steps, warmup, n=256):
                      "tiles": tiles}
         S.close()
     return res, f"{n}^3 uniform, periodic in x, y and z, N(0,1) filtered to k <= 16, c = {c:.4e}"
+
+
+def run_xw(steps, warmup, n=256, beta=2.0):
+    """Walls in x (Dirichlet velocity, Neumann pressure at x = 0 and x = lx;
+    unfolded cosine/sine transforms in x) at n^3 with tanh-stretched walls
+    in y, both paths: one step of 3 Helmholtz + divergence + Poisson +
+    correction on N(0,1) velocities."""
+    import torch
+    from paper_2406_19920_amd import ibsolve as ibs
+    dev = torch.device("cuda:0")
+    log(f"inputs {n}^3 walls in x")
+    u, v, w = make_inputs(n, beta, seed=12)
+    u[:, :, 0] = 0.0
+    c = 0.125 * h_min(n, beta) ** 2
+    ru, rv, rw = (torch.from_numpy(a).to(dev) for a in (u, v, w))
+    res = {}
+    for path, prec in (("refined", ibs.IBS_REFINED_BF16X3), ("fp64", ibs.IBS_FP64)):
+        kw = {"max_iter": 2} if prec != ibs.IBS_FP64 else {}
+        S = ibs.Solver(n, n, n, beta=beta, precision=prec, bc_x=ibs.IBS_DIRICHLET, **kw)
+        tiles = S.autotune() if prec == ibs.IBS_FP64 else None   # set-up, untimed
+        xu, xv, xw = S.empty(1), S.empty(2), S.empty(3)
+        b, phi = S.empty(0), S.empty(0)
+
+        def step():
+            S.helmholtz([0, 1, 2], [c, c, c], [ru, rv, rw], [xu, xv, xw], info_slot=1)
+            S.divergence(xu, xv, xw, 1.0, b)
+            S.poisson(b, phi)
+            S.correct(phi, xu, xv, xw, 1.0)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        res[path] = {"value": 4 * n ** 3 / (ms * 1e-3) / 1e6, "ms_per_step": ms,
+                     "status": [S.read_info(q).status for q in range(4)],
+                     "passes": {"helmholtz": [S.read_info(q).iters for q in (1, 2, 3)],
+                                "poisson": S.read_info(0).iters},
+                     "tiles": tiles}
+        S.close()
+    return res, (f"{n}^3, walls in x (uniform) and y (tanh beta={beta}), periodic z, "
+                 f"N(0,1) rhs, c = {c:.4e}")
 
 
 def run_rk3(steps, warmup, n=256):

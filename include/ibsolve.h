@@ -80,15 +80,27 @@ typedef enum { IBS_PERIODIC = 0, IBS_DIRICHLET = 1, IBS_NEUMANN = 2 } ibs_bc;
  * hx = lx/nx, hz = lz/nz; y faces y_f[j] = (ly/2)(1 + tanh(beta(2j/ny-1))/
  * tanh(beta)), j = 0..ny (beta = 0: uniform), unless y_faces is given.
  * Supported: nx, nz multiples of 16 in [16, 1024] (refined path: multiples
- * of 32, at most 512); ny in [2, 768]; bc_x = bc_z = IBS_PERIODIC and
- * either walls in y (bc_y_vel = IBS_DIRICHLET, bc_y_p = IBS_NEUMANN) or
+ * of 32, at most 512); ny in [2, 768]; bc_z = IBS_PERIODIC; bc_x =
+ * IBS_PERIODIC or IBS_DIRICHLET (walls in x, below); and in y
+ * either walls (bc_y_vel = IBS_DIRICHLET, bc_y_p = IBS_NEUMANN) or
  * periodic y (bc_y_vel = bc_y_p = IBS_PERIODIC: the triply periodic
  * branch of Section 2.3.3, items S1/S2; ny in {48, 64, 80, 96, 128, 160,
  * 192, 256, 320, 384, 512}; the y faces, stretched or not, wrap: the
  * centres of cells ny-1 and 0 are (Delta_0 + Delta_{ny-1})/2 apart).  With
  * periodic y there are no walls: v is [nz][ny][nx] (face j at y_f[j],
  * face ny being face 0), the y pencils are cyclic, and the pressure's null
- * mode is fixed by the same zero volume-weighted mean. */
+ * mode is fixed by the same zero volume-weighted mean.
+ * Walls in x (bc_x = IBS_DIRICHLET; the non-periodic direction of the
+ * paper's inflow-outflow example, Section 3.2, closed by walls; uniform x):
+ * homogeneous Dirichlet velocity and Neumann pressure at x = 0 and x = lx.
+ * Every field keeps its [nz][rows][nx] layout.  u's slot i holds the face
+ * x = i hx: slot 0 is the wall face x = 0 (ignored on input, written as
+ * zero on output; residual() reports 0 there) and the wall face x = lx is
+ * not stored; its unknowns are slots 1..nx-1.  v and w (cell centres in x)
+ * take the mirror-ghost Dirichlet row at the walls, the pressure zero flux.
+ * The x transforms are then the cosine (pressure), sine-on-centres (v, w)
+ * and sine-on-faces (u) eigenbases of the wall-bounded x operators, as
+ * plain (unfolded) matrix products; ibs_rk_stage() is not served. */
 typedef struct {
     int32_t nx, ny, nz;
     double lx, ly, lz;        /* <= 0 means 1                                */
@@ -349,7 +361,9 @@ ibs_status ibs_batch_destroy(ibs_batch batch);
  * operator of kind 0 (pressure), 1 (u, w), 2 (v, rows = faces 0..ny), 3 (v
  * of a periodic-y plan, rows = faces 0..ny-1).  With periodic y, kinds 0
  * and 1 hold the cyclic cell operator; lower[0] and upper[ny-1] are then
- * the corner couplings (row 0 to row ny-1 and back).
+ * the corner couplings (row 0 to row ny-1 and back).  Tables 1 and 3 are
+ * the pressure's x basis; with walls in x, 17 and 18 are Q_x of v/w and of
+ * u, 19 and 20 their lambda_x (periodic x: the same as 1 and 3).
  * out: host array of n doubles; n must equal the table length (queried by
  * passing out = NULL, which returns the length through *n). */
 ibs_status ibs_plan_export(ibs_plan plan, int32_t table, double *out, size_t *n);

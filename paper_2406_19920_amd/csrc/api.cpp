@@ -174,10 +174,14 @@ static ibs_status run_fp64_pipeline_multi(Plan &p, JobSet js, double *const *W, 
     hipError_t e;
     const double cells = total_cells(js, p);
     // matrix-core flops per cell: 2n for the plain transform, n folded
-    const bool fx = can_fold(p.nx), fz = can_fold(p.nz);
+    const bool fx = x_folds(p), fz = can_fold(p.nz);
     const double xflop = (fx ? 1.0 : 2.0) * p.nx * cells, zflop = (fz ? 1.0 : 2.0) * p.nz * cells;
     const double rw = 16.0 * cells;
-    const double *xb_f = blob_ptr(p, p.lay.bx_fwd), *xb_i = blob_ptr(p, p.lay.bx_inv);
+    const double *xb_f[NUM_XK], *xb_i[NUM_XK];
+    for (int k = 0; k < NUM_XK; ++k) {
+        xb_f[k] = blob_ptr(p, p.lay.bx_fwd[k]);
+        xb_i[k] = blob_ptr(p, p.lay.bx_inv[k]);
+    }
     const double *za_f = blob_ptr(p, p.lay.az_fwd), *za_i = blob_ptr(p, p.lay.az_inv);
     auto xform = [&](bool inverse) {
         return fx ? launch_xfold_f64(js, p, inverse, s)
@@ -239,7 +243,7 @@ static ibs_status run_refined(Plan &p, SplitSet ss, float *const *W1, float *con
     double cells = 0;
     for (int q = 0; q < ss.n; ++q) cells += (double)p.nz * ss.j[q].rows * p.nx;
     // algorithmic flops per cell: 2n for the plain transform, n folded
-    const double xfl = (can_fold_split(p.nx) ? 1.0 : 2.0) * p.nx * cells;
+    const double xfl = (x_folds_split(p) ? 1.0 : 2.0) * p.nx * cells;
     const double zfl = (can_fold_split(p.nz) ? 1.0 : 2.0) * p.nz * cells;
     JobSet js{};
     js.n = ss.n;
@@ -250,6 +254,7 @@ static ibs_status run_refined(Plan &p, SplitSet ss, float *const *W1, float *con
         js.j[q].in = js.j[q].out;
         js.j[q].rows = ss.j[q].rows;
         js.j[q].kind = ss.j[q].kind;
+        js.j[q].xk = ss.j[q].xk;
         js.j[q].c = ss.j[q].c;
     }
     // With a second pass to come, the first iterate is only FP32-accurate
@@ -401,6 +406,7 @@ ibs_status solve_poisson(ibs_plan plan, const double *b, double *phi, void *work
         ss.j[0].x = phi;
         ss.j[0].rows = p.ny;
         ss.j[0].kind = KIND_P;
+        ss.j[0].xk = XK_P;
         ss.j[0].op = IBS_OP_POISSON;
         ss.j[0].c = 0.0;
         ss.j[0].info = info;
@@ -445,6 +451,7 @@ ibs_status solve_helmholtz_batch(ibs_plan plan, int32_t ncomp, const int32_t *co
         if (!r[q] || !x[q] || !aligned32(r[q]) || !aligned32(x[q])) { set_error("r[q], x[q] must be non-NULL and 32-byte aligned"); return IBS_ERR_INVALID_ARG; }
         js.j[q].rows = comp_rows(p, comp[q]);
         js.j[q].kind = comp_kind(p, comp[q]);
+        js.j[q].xk = comp_xkind(p, comp[q]);
         js.j[q].c = c[q];
         js.j[q].info = info ? info + q : nullptr;
     }
@@ -460,6 +467,7 @@ ibs_status solve_helmholtz_batch(ibs_plan plan, int32_t ncomp, const int32_t *co
             ss.j[q].x = x[q];
             ss.j[q].rows = js.j[q].rows;
             ss.j[q].kind = js.j[q].kind;
+            ss.j[q].xk = js.j[q].xk;
             ss.j[q].op = comp[q] + 1;
             ss.j[q].c = c[q];
             ss.j[q].info = js.j[q].info;
@@ -588,6 +596,10 @@ ibs_status ibs_rk_stage(ibs_plan plan, const ibs_rk_coef *coef, const ibs_stage_
         set_error("coefficients must be finite with dt > 0, re > 0, beta >= 0 and alpha + beta > 0");
         return IBS_ERR_INVALID_ARG;
     }
+    if (p.wx) {
+        set_error("the Runge-Kutta stage is built for a periodic x (walls in x are served by the solves)");
+        return IBS_ERR_UNSUPPORTED;
+    }
     const void *ptrs[] = {f->u, f->v, f->w, f->p, f->nu, f->nv, f->nw};
     for (const void *q : ptrs)
         if (!q || !aligned32(q)) { set_error("u, v, w, p, nu, nv, nw must be non-NULL and 32-byte aligned"); return IBS_ERR_INVALID_ARG; }
@@ -709,7 +721,7 @@ ibs_status ibs_autotune(ibs_plan plan, void *scratch, size_t scratch_bytes, int3
         return hip_fail(e, "autotune event");
     }
     struct Knob { int id; bool applies; hipError_t (*launch)(const JobSet &, const Plan &, bool, hipStream_t); };
-    const Knob knobs[NUM_TUNE] = {{TUNE_XFOLD, can_fold(p.nx), launch_xfold_f64},
+    const Knob knobs[NUM_TUNE] = {{TUNE_XFOLD, x_folds(p), launch_xfold_f64},
                                   {TUNE_ZFOLD, can_fold(p.nz), launch_zfold_f64}};
     ibs_status st = IBS_OK;
     // candidates timed in interleaved rounds, each keeping its fastest
@@ -774,14 +786,19 @@ ibs_status ibs_plan_export(ibs_plan plan, int32_t table, double *out, size_t *n)
     const std::vector<double> *v = nullptr;
     switch (table) {
     case 0: v = &p.yf; break;
-    case 1: v = &p.qx; break;
+    case 1: v = &p.qx[XK_P]; break;
     case 2: v = &p.qz; break;
-    case 3: v = &p.lam_x; break;
+    case 3: v = &p.lam_x[XK_P]; break;
     case 4: v = &p.lam_z; break;
     default:
         if (table >= 5 && table < 5 + 3 * NUM_KINDS) {
             const int kd = (table - 5) / 3, which = (table - 5) % 3;
             v = which == 0 ? &p.lo[kd] : (which == 1 ? &p.di[kd] : &p.up[kd]);
+        } else if (table >= 5 + 3 * NUM_KINDS && table < 5 + 3 * NUM_KINDS + 4) {
+            // the x bases and eigenvalues of v/w (XK_C) and u (XK_F)
+            const int t = table - 5 - 3 * NUM_KINDS;
+            const int xk = (t % 2 == 0) ? XK_C : XK_F;
+            v = t < 2 ? &p.qx[xk] : &p.lam_x[xk];
         }
     }
     if (!v) { set_error("unknown table"); return IBS_ERR_INVALID_ARG; }

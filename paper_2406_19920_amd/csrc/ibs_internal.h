@@ -20,18 +20,30 @@ namespace ibs {
 //            the cyclic cell-centre operator (the same for p, u and w).
 enum { KIND_P = 0, KIND_C = 1, KIND_F = 2, KIND_PF = 3, NUM_KINDS = 4 };
 
+// Kinds of x operator (the eigenbasis of a field's x transform).  Periodic
+// x: one real Fourier basis serves every field (the tables of kinds 1 and 2
+// alias those of kind 0).  Walls in x (bc_x = IBS_DIRICHLET):
+//   XK_P: pressure, cell centres, homogeneous Neumann (cosine series)
+//   XK_C: v and w, cell centres, Dirichlet by mirror ghost (sine series)
+//   XK_F: u, x faces; slot 0 is the wall face x = 0 and face nx is not
+//         stored; the basis has a zero column 0 (and zero row 0), so the
+//         wall slot transforms to zero both ways (sine series on 1..nx-1)
+enum { XK_P = 0, XK_C = 1, XK_F = 2, NUM_XK = 3 };
+
 // Byte offsets of the tables inside the device constant blob.
 struct BlobLayout {
-    size_t bx_fwd, bx_inv;   // x transform as B operand of C = A B, swizzled (nx % 32 != 0)
+    size_t bx_fwd[NUM_XK], bx_inv[NUM_XK];   // x transform per x kind, B operand of C = A B,
+                                             // swizzled (unfolded x: nx % 32 != 0 or walls)
     size_t az_fwd, az_inv;   // z transform as A operand of C = A B, swizzled (nz % 32 != 0)
     // folded transforms (n % 32 == 0): the two H x H factors (H = n/2)
     size_t fx_fwd_c, fx_fwd_s, fx_inv_c, fx_inv_s;   // B-operand swizzle
     size_t fz_fwd_c, fz_fwd_s, fz_inv_c, fz_inv_s;   // A-operand swizzle
-    size_t lam_x, lam_z;     // eigenvalues (double)
+    size_t lam_x[NUM_XK], lam_z;   // eigenvalues (double), x per x kind
     size_t lo[NUM_KINDS], di[NUM_KINDS], up[NUM_KINDS];  // y operator rows
     size_t wy;               // Delta_j (pressure weights), ny doubles
     size_t dyc, dyf;         // cell heights [ny], centre distances [ny+1]
-    size_t sx_fwd, sx_inv;   // x transform, bf16x3 split, B-operand swizzle (nx % 64 != 0)
+    size_t sx_fwd[NUM_XK], sx_inv[NUM_XK];   // x transform per x kind, bf16x3 split, B-operand
+                                             // swizzle (unfolded x: nx % 64 != 0 or walls)
     size_t sz_fwd, sz_inv;   // z transform, bf16x3 split, A-operand swizzle (nz % 64 != 0)
     size_t sxf_fwd, sxf_inv; // folded x transform factors, bf16x3 split (nx % 64 == 0)
     size_t szf_fwd, szf_inv; // folded z transform factors, bf16x3 split (nz % 64 == 0)
@@ -98,12 +110,13 @@ static_assert(NUM_TUNE == IBS_NUM_TUNE, "tuning knobs and the ABI disagree");
 struct Plan {
     ibs_grid_desc desc;
     bool py = false;                               // y periodic (no walls)
+    bool wx = false;                               // walls at x = 0 and x = lx
     int tune[NUM_TUNE] = {-1, -1};   // candidate index per knob; -1 = default
     int nx, ny, nz;
     double hx, hz;
     std::vector<double> yf, yc, dyc, dyf;          // grid
-    std::vector<double> qx, qz;                    // Q[i][a], row-major n x n
-    std::vector<double> lam_x, lam_z;
+    std::vector<double> qx[NUM_XK], qz;            // Q[i][a], row-major n x n (x: per x kind)
+    std::vector<double> lam_x[NUM_XK], lam_z;
     std::vector<double> lo[NUM_KINDS], di[NUM_KINDS], up[NUM_KINDS];
     int rows[NUM_KINDS];
     BlobLayout lay;
@@ -133,6 +146,8 @@ struct FieldJob {
     double *out;        // output field
     int rows;           // rows per z-plane (ny or ny+1)
     int kind;           // KIND_*
+    int xk;             // XK_* (x operator)
+    const void *xq;     // x transform matrix of this job (set by the x launchers)
     double c;           // Helmholtz coefficient (Poisson: unused)
     void *info;         // ibs_solve_info* or null
 };
@@ -153,6 +168,11 @@ inline int comp_kind(const Plan &p, int comp)
 {
     return comp == 1 ? (p.py ? KIND_PF : KIND_F) : KIND_C;
 }
+// x kind of a component (u 0, v 1, w 2); the pressure is XK_P.
+inline int comp_xkind(const Plan &p, int comp)
+{
+    return !p.wx ? XK_P : (comp == 0 ? XK_F : XK_C);
+}
 
 // Workspace of one solve call: the work fields and the state after them.
 size_t field_bytes_for(const Plan &p, int op, int ncomp);
@@ -160,10 +180,11 @@ size_t state_bytes_for(const Plan &p, int op, int ncomp);
 State state_in(const Plan &p, void *work, int op, int ncomp);
 
 // ---- kernel launchers (return hipError_t of the launch) --------------------
-// C[M x N] = A[M x K] * Bs, A row-major (lda), Bs the swizzled K x N matrix;
-// batched over the jobs of js (A = js.j[q].in, C = js.j[q].out, M = nz*rows).
+// C[M x N] = A[M x K] * Bs, A row-major (lda), Bs the swizzled K x N matrix
+// of the job's x kind (bs[js.j[q].xk]); batched over the jobs of js
+// (A = js.j[q].in, C = js.j[q].out, M = nz*rows).
 hipError_t launch_xgemm_f64(const JobSet &js, int nz, int K, int N,
-                            const double *bs, hipStream_t s);
+                            const double *const bs[NUM_XK], hipStream_t s);
 // C[M x Ncol] = As * B, As the swizzled M x K matrix, B row-major (K x Ncol),
 // Ncol = rows * nx per job.
 // Folded FP64 transforms (valid when can_fold(n)).
@@ -171,6 +192,10 @@ bool can_fold(int n);
 int fold_candidates();
 // Folded split transforms: the half length must hold whole 32-deep chunks.
 inline bool can_fold_split(int n) { return n % 64 == 0; }
+// The folds use the Fourier basis's mirror symmetry: x folds only when x is
+// periodic (z always is).
+inline bool x_folds(const Plan &p) { return !p.wx && can_fold(p.nx); }
+inline bool x_folds_split(const Plan &p) { return !p.wx && can_fold_split(p.nx); }
 hipError_t launch_xfold_f64(const JobSet &js, const Plan &p, bool inverse, hipStream_t s);
 hipError_t launch_zfold_f64(const JobSet &js, const Plan &p, bool inverse, hipStream_t s);
 hipError_t launch_zgemm_f64(const JobSet &js, int M, int K, int nx,
@@ -224,6 +249,8 @@ struct SplitJob {
     float *r;           // residual: FP32 output
     int rows;           // rows per z-plane
     int kind;
+    int xk;             // XK_* (x operator)
+    const void *xq;     // x transform matrix of this job (set by the x launchers)
     int op;             // IBS_OP_* of the job (residual stencil)
     double c;
     void *info;

@@ -180,6 +180,8 @@ __global__ __launch_bounds__(512) void split_xgemm_kernel(SplitSet ss, int nz, i
     __shared__ b8 sq[(DB ? 2 : 1) * QCNT];
     if (skip && skip[blockIdx.z]) return;   // this job has already converged
     const SplitJob &jb = ss.j[blockIdx.z];
+    // the job's own matrix when the jobs' x operators differ (walls in x)
+    const b8 *__restrict__ qj = jb.xq ? static_cast<const b8 *>(jb.xq) : qs;
     const int rskip = skip_first_row(jb.kind), trows = jb.rows - rskip;
     const int M = nz * trows;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -210,7 +212,7 @@ __global__ __launch_bounds__(512) void split_xgemm_kernel(SplitSet ss, int nz, i
         }
     };
     b8 qreg[QPER];
-    q_load<QPER>(qs, qcnt, qreg);
+    q_load<QPER>(qj, qcnt, qreg);
     q_store<QPER>(sq, qcnt, qreg);
     load_data(0, dcur);
     for (int kc = 0; kc < KC; ++kc) {
@@ -218,7 +220,7 @@ __global__ __launch_bounds__(512) void split_xgemm_kernel(SplitSet ss, int nz, i
         const b8 *cur = sq + (DB ? (kc & 1) * QCNT : 0);
         const bool more = kc + 1 < KC;
         if (more) {
-            q_load<QPER>(qs + (size_t)(kc + 1) * qcnt, qcnt, qreg);
+            q_load<QPER>(qj + (size_t)(kc + 1) * qcnt, qcnt, qreg);
             load_data(kc + 1, dnext);
         }
         b8 a[WM][3];
@@ -1016,7 +1018,7 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
                                                            const double *__restrict__ bmean,
                                                            double *__restrict__ xsum,
                                                            const int *__restrict__ skip, int rb_rows,
-                                                           int tiles_y, int rz, int py)
+                                                           int tiles_y, int rz, int py, int wxw)
 {
     typedef Tx tx4 __attribute__((ext_vector_type(4)));
     typedef double dv4_ __attribute__((ext_vector_type(4)));
@@ -1083,6 +1085,11 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
         const double wD = (op != IBS_OP_HELMHOLTZ_V) ? D : 0.0;
         const double *__restrict__ bb = jb.b;
         float *__restrict__ rr = jb.r;
+        // walls in x: the ghost beyond a wall is gx x (1 pressure, -1 v and
+        // w, 0 u); u's slot 0 is the wall face itself (residual 0) and the
+        // west neighbour of slot 1 that wall (0)
+        const bool xw_u = wxw && op == IBS_OP_HELMHOLTZ_U;
+        const double gx = pois ? 1.0 : (op == IBS_OP_HELMHOLTZ_U ? 0.0 : -1.0);
         auto ld4 = [&](size_t at) { return *reinterpret_cast<const tx4 *>(x + at); };
         tx4 xm = ld4((size_t)(k0 == 0 ? nz - 1 : k0 - 1) * plane + o + i0);
         tx4 xc = ld4((size_t)k0 * plane + o + i0);
@@ -1097,13 +1104,21 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const double xcc = (double)xc[e];
-                const double xw = e == 0 ? xwe : (double)xc[e - 1];
-                const double xe = e == 3 ? xee : (double)xc[e + 1];
+                double xw = e == 0 ? xwe : (double)xc[e - 1];
+                double xe = e == 3 ? xee : (double)xc[e + 1];
+                bool xwall = false;
+                if (wxw) {
+                    const int i = i0 + e;
+                    if (i == 0) xw = gx * xcc;
+                    if (i + 1 == nx) xe = gx * xcc;
+                    if (xw_u && i == 1) xw = 0.0;
+                    xwall = xw_u && i == 0;
+                }
                 double lap = ((xe - xcc) - (xcc - xw)) * ihx2 +
                              (((double)xp[e] - xcc) - (xcc - (double)xm[e])) * ihz2;
                 lap += cu * (wu * (double)xu[e] - xcc) - cl * (xcc - wl * (double)xl[e]);
                 const double ax = pois ? lap : xcc - cj * lap;
-                rv[e] = wall ? 0.f : (float)((bv[e] - bm) - ax);
+                rv[e] = (wall || xwall) ? 0.f : (float)((bv[e] - bm) - ax);
                 wx += wD * xcc;
             }
             *reinterpret_cast<fv4 *>(rr + c + i0) = rv;
@@ -1222,7 +1237,7 @@ static constexpr int f_steps(int hbt) { return hbt <= 8 ? 1 : 2; }   // factors 
 
 static void xgemm_grid(const SplitSet &ss, const Plan &p, dim3 &grid)
 {
-    const int wm = can_fold_split(p.nx) ? xf_wm(xf_hbt(p.nx)) : x_wm(x_nbt(p.nx));
+    const int wm = x_folds_split(p) ? xf_wm(xf_hbt(p.nx)) : x_wm(x_nbt(p.nx));
     const int M = p.nz * max_rows(ss);
     grid = dim3((M + 8 * 16 * wm - 1) / (8 * 16 * wm), 1, ss.n);
 }
@@ -1301,7 +1316,7 @@ hipError_t launch_split_xgemm(const SplitSet &ss, const Plan &p, const State &st
     const size_t region = update_region(p, ss.n);
     const bool upd = mode == 2 || mode == 4;
     double *red = st.red + (upd ? (size_t)(pass - 1) * region : 0);
-    if (can_fold_split(p.nx)) {
+    if (x_folds_split(p)) {
         const b8 *qs = reinterpret_cast<const b8 *>(blob_ptr(p, inverse ? p.lay.sxf_inv : p.lay.sxf_fwd));
         switch (in64 ? -1 : mode) {
         case -1: launch_xf_hb<double, 0, false>(ss, p, qs, red, skip, grid, s); break;
@@ -1313,14 +1328,17 @@ hipError_t launch_split_xgemm(const SplitSet &ss, const Plan &p, const State &st
         }
         return hipGetLastError();
     }
-    const b8 *qs = reinterpret_cast<const b8 *>(blob_ptr(p, inverse ? p.lay.sx_inv : p.lay.sx_fwd));
+    const size_t *tab = inverse ? p.lay.sx_inv : p.lay.sx_fwd;
+    const b8 *qs = reinterpret_cast<const b8 *>(blob_ptr(p, tab[XK_P]));
+    SplitSet sj = ss;   // each job's matrix for its x operator
+    for (int q = 0; q < sj.n; ++q) sj.j[q].xq = blob_ptr(p, tab[sj.j[q].xk]);
     switch (in64 ? -1 : mode) {
-    case -1: launch_x_nb<double, 0>(ss, p, qs, red, skip, grid, s); break;
-    case 0: launch_x_nb<float, 0>(ss, p, qs, red, skip, grid, s); break;
-    case 1: launch_x_nb<float, 1>(ss, p, qs, red, skip, grid, s); break;
-    case 2: launch_x_nb<float, 2>(ss, p, qs, red, skip, grid, s); break;
-    case 3: launch_x_nb<float, 3>(ss, p, qs, red, skip, grid, s); break;
-    default: launch_x_nb<float, 4>(ss, p, qs, red, skip, grid, s); break;
+    case -1: launch_x_nb<double, 0>(sj, p, qs, red, skip, grid, s); break;
+    case 0: launch_x_nb<float, 0>(sj, p, qs, red, skip, grid, s); break;
+    case 1: launch_x_nb<float, 1>(sj, p, qs, red, skip, grid, s); break;
+    case 2: launch_x_nb<float, 2>(sj, p, qs, red, skip, grid, s); break;
+    case 3: launch_x_nb<float, 3>(sj, p, qs, red, skip, grid, s); break;
+    default: launch_x_nb<float, 4>(sj, p, qs, red, skip, grid, s); break;
     }
     return hipGetLastError();
 }
@@ -1413,7 +1431,7 @@ hipError_t launch_residual_f32(const SplitSet &ss, const Plan &p, const State &s
     auto go = [&](auto kernel) {
         hipLaunchKernelGGL(kernel, grid, dim3(256), 0, s, ss, p.nx, p.ny, p.nz, 1.0 / (p.hx * p.hx),
                            1.0 / (p.hz * p.hz), blob_ptr(p, p.lay.dyc), blob_ptr(p, p.lay.dyf),
-                           st.bmean, st.xsum, skip, rb_rows, tiles_y, rz, p.py ? 1 : 0);
+                           st.bmean, st.xsum, skip, rb_rows, tiles_y, rz, p.py ? 1 : 0, p.wx ? 1 : 0);
     };
     if (x32) go(residual_f32_kernel<float>);
     else go(residual_f32_kernel<double>);

@@ -14,6 +14,8 @@ struct Geo {
     const double *dyc;        // Delta_j [ny]
     const double *dyf;        // delta_j [ny+1] (periodic y: delta_0 = delta_ny across the wrap)
     int py;                   // periodic y: no walls, v has ny faces
+    int wx;                   // walls in x: u slot 0 is the wall face x = 0
+                              // (zero), face nx is not stored (zero)
 };
 
 static Geo geo_of(const Plan &p)
@@ -21,6 +23,7 @@ static Geo geo_of(const Plan &p)
     Geo g;
     g.nx = p.nx; g.ny = p.ny; g.nz = p.nz;
     g.py = p.py ? 1 : 0;
+    g.wx = p.wx ? 1 : 0;
     g.ihx = 1.0 / p.hx; g.ihz = 1.0 / p.hz;
     g.dyc = blob_ptr(p, p.lay.dyc);
     g.dyf = blob_ptr(p, p.lay.dyf);
@@ -43,7 +46,10 @@ __global__ __launch_bounds__(256) void divergence_kernel(Geo g, const double *__
     const size_t vc = ((size_t)k * (g.ny + 1 - g.py) + j) * g.nx + i;
     // the face above cell j: j + 1, or face 0 at the top when y is periodic
     const size_t vn = (g.py && j + 1 == g.ny) ? vc - (size_t)j * g.nx : vc + g.nx;
-    const double du = (u[c - i + ip] - u[c]) * g.ihx;
+    // with walls in x the wall faces x = 0 and x = lx carry u = 0
+    const double ue = (g.wx && ip == 0) ? 0.0 : u[c - i + ip];
+    const double uw = (g.wx && i == 0) ? 0.0 : u[c];
+    const double du = (ue - uw) * g.ihx;
     const double dv = (v[vn] - v[vc]) / g.dyc[j];
     const double dw = (w[kp * plane + (size_t)j * g.nx + i] - w[c]) * g.ihz;
     b[c] = scale * (du + dv + dw);
@@ -67,7 +73,8 @@ __global__ __launch_bounds__(256) void correct_kernel(Geo g, const double *__res
         const int im = (i == 0) ? g.nx - 1 : i - 1;
         const size_t km = (k == 0) ? (size_t)(g.nz - 1) : (size_t)(k - 1);
         const double ph = phi[c];
-        u[c] -= gs * (ph - phi[c - i + im]) * g.ihx;
+        if (g.wx && i == 0) u[c] = 0.0;   // the wall face x = 0
+        else u[c] -= gs * (ph - phi[c - i + im]) * g.ihx;
         w[c] -= gs * (ph - phi[km * plane + (size_t)j * g.nx + i]) * g.ihz;
         if (pr) pr[c] += ph - (cp != 0.0 ? cp * lap[c] : 0.0);
         if (j > 0) v[vc] -= gs * (ph - phi[c - g.nx]) / g.dyf[j];
@@ -117,12 +124,22 @@ __global__ __launch_bounds__(256) void residual_kernel(Geo g, int op, double cc,
             const size_t kp = (k + 1 == g.nz) ? 0 : (size_t)(k + 1);
             const size_t km = (k == 0) ? (size_t)(g.nz - 1) : (size_t)(k - 1);
             const double xc = x[c];
-            const double xe = x[c - i + ip], xw = x[c - i + im];
+            double xe = x[c - i + ip], xw = x[c - i + im];
+            bool unknown = true;
+            if (g.wx) {
+                // walls in x: a missing neighbour is the wall's ghost, xc
+                // (pressure, Neumann), -xc (v, w, mirror) or 0 (u: the wall
+                // faces; slot 0 is the wall x = 0 itself)
+                const double gx = op == IBS_OP_POISSON ? xc : (op == IBS_OP_HELMHOLTZ_U ? 0.0 : -xc);
+                if (op == IBS_OP_HELMHOLTZ_U && i == 1) xw = 0.0;
+                if (i == 0) xw = gx;
+                if (i + 1 == g.nx) xe = gx;
+                if (op == IBS_OP_HELMHOLTZ_U && i == 0) unknown = false;
+            }
             const double xt = x[kp * plane + (size_t)j * g.nx + i];
             const double xb = x[km * plane + (size_t)j * g.nx + i];
             double lap = ((xe - xc) - (xc - xw)) * (g.ihx * g.ihx) +
                          ((xt - xc) - (xc - xb)) * (g.ihz * g.ihz);
-            bool unknown = true;
             if (g.py) {
                 // periodic y: interior formulas everywhere, neighbours wrapping
                 const int jn = (j + 1 == g.ny) ? 0 : j + 1, js = (j == 0) ? g.ny - 1 : j - 1;

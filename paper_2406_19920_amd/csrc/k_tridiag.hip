@@ -32,7 +32,8 @@ static hipError_t launch_by_rows(const JobSet &js, const TriParams &tp, int n, h
 static double helmholtz_kappa(const JobSet &js, const Plan &p)
 {
     double smax = 0.0;
-    for (double v : p.lam_x) smax = std::max(smax, -v);
+    for (int xk = 0; xk < NUM_XK; ++xk)
+        for (double v : p.lam_x[xk]) smax = std::max(smax, -v);
     double szmax = 0.0;
     for (double v : p.lam_z) szmax = std::max(szmax, -v);
     double kap = 1.0;
@@ -64,7 +65,7 @@ static hipError_t launch_tridiag(const JobSet &js, const Plan &p, const State &s
                                  hipStream_t s)
 {
     TriParams tp;
-    tp.lam_x = blob_ptr(p, p.lay.lam_x);
+    for (int xk = 0; xk < NUM_XK; ++xk) tp.lam_x[xk] = blob_ptr(p, p.lay.lam_x[xk]);
     tp.lam_z = blob_ptr(p, p.lay.lam_z);
     for (int kd = 0; kd < NUM_KINDS; ++kd) {
         tp.lo[kd] = blob_ptr(p, p.lay.lo[kd]);

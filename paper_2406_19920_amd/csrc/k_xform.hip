@@ -1,4 +1,4 @@
-// Eigen-transforms of the two periodic directions as FP64 matrix-core GEMMs.
+// Eigen-transforms of the x and z directions as FP64 matrix-core GEMMs.
 //
 // The x transform contracts the innermost (x) index of every row of a
 // [nz][rows][nx] field with an nx x nx matrix (forward: Q, inverse: Q^T);
@@ -6,7 +6,8 @@
 // field viewed as an nz x (rows*nx) matrix from the left by an nz x nz matrix
 // (forward: Q^T, inverse: Q).  These are the dense-matrix counterpart of the
 // paper's 2-D FFT over the periodic directions (Section 2.3.3, items S1.1,
-// S1.2, S2.1, S2.2).
+// S1.2, S2.1, S2.2); with walls in x, Q is the eigenbasis of the field's
+// wall-bounded x operator (cosine or sine series), one matrix per job.
 //
 // Instruction: V_MFMA_F64_16X16X4_F64.  Per lane l of the 64-wide wave: A
 // element (row l%16, k l/16), B element (k l/16, col l%16); result element q
@@ -26,13 +27,14 @@ static __device__ __forceinline__ d4 mfma(double a, double b, d4 c)
 }
 
 // x transform: for job q, C = A * B with A = in (M x K row-major, M = nz*rows),
-// B = swizzled K x N matrix, C = out (M x N row-major).  Workgroup of 4 waves
-// laid out wgm x wgn; each wave owns a (16*WM) x (16*WN) tile.
+// B = the job's swizzled K x N matrix (xq), C = out (M x N row-major).
+// Workgroup of 4 waves laid out wgm x wgn; each wave owns a (16*WM) x
+// (16*WN) tile.
 template <int WM, int WN>
-__global__ __launch_bounds__(256) void xgemm_f64_kernel(JobSet js, int nz, int K, int N,
-                                                        const double *__restrict__ bs, int wgn)
+__global__ __launch_bounds__(256) void xgemm_f64_kernel(JobSet js, int nz, int K, int N, int wgn)
 {
     const FieldJob &jb = js.j[blockIdx.z];
+    const double *__restrict__ bs = static_cast<const double *>(jb.xq);
     const int skip = skip_first_row(jb.kind), trows = jb.rows - skip;
     const int M = nz * trows;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -161,9 +163,11 @@ static int max_rows(const JobSet &js)   // transform rows per plane
     return r;
 }
 
-hipError_t launch_xgemm_f64(const JobSet &js, int nz, int K, int N, const double *bs,
+hipError_t launch_xgemm_f64(const JobSet &js_in, int nz, int K, int N, const double *const bs[NUM_XK],
                             hipStream_t s)
 {
+    JobSet js = js_in;
+    for (int q = 0; q < js.n; ++q) js.j[q].xq = bs[js.j[q].xk];
     constexpr int WM = 4, WN = 4;
     const int M = nz * max_rows(js);
     // arrange the 4 waves over columns first (up to N/64 of them)
@@ -172,7 +176,7 @@ hipError_t launch_xgemm_f64(const JobSet &js, int nz, int K, int N, const double
     int wgm = 4 / wgn;
     dim3 grid((M + 16 * WM * wgm - 1) / (16 * WM * wgm), (N + 16 * WN * wgn - 1) / (16 * WN * wgn),
               js.n);
-    hipLaunchKernelGGL((xgemm_f64_kernel<WM, WN>), grid, dim3(256), 0, s, js, nz, K, N, bs, wgn);
+    hipLaunchKernelGGL((xgemm_f64_kernel<WM, WN>), grid, dim3(256), 0, s, js, nz, K, N, wgn);
     return hipGetLastError();
 }
 

@@ -65,6 +65,53 @@ static void fourier_basis(int N, double h, std::vector<double> &Q, std::vector<d
     }
 }
 
+// Orthonormal eigenbases of the wall-bounded 3-point second differences on
+// n uniform cells of width h (x walls), each with its eigenvalues
+// -(4/h^2) sin^2(pi a / (2n)):
+//   XK_P, Neumann on cell centres:    cos(pi a (i + 1/2) / n), a = 0..n-1
+//   XK_C, mirror Dirichlet, centres:  sin(pi a (i + 1/2) / n), a = 1..n
+//                                     (column a - 1)
+//   XK_F, Dirichlet on faces 1..n-1:  sin(pi a i / n), a = 1..n-1 (column
+//                                     a); column 0 and row 0 (the wall slot)
+//                                     zero, eigenvalue 0
+// scaled to unit norm (sqrt(2/n), or sqrt(1/n) for the constant and the
+// alternating columns).  Angles reduced exactly: every one is pi m / (2n)
+// with m = (a (2i + 1)) mod 4n or 2 (a i mod 2n), evaluated in long double.
+static void wall_basis(int n, double h, int xk, std::vector<double> &Q, std::vector<double> &lam)
+{
+    Q.assign(size_t(n) * n, 0.0);
+    lam.assign(n, 0.0);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    std::vector<long double> cs(4 * n), sn(4 * n);
+    for (int m = 0; m < 4 * n; ++m) {
+        const long double th = pi * (long double)m / (2.0L * n);
+        cs[m] = std::cos(th);
+        sn[m] = std::sin(th);
+    }
+    const long double r1 = std::sqrt(1.0L / n), r2 = std::sqrt(2.0L / n);
+    auto eig = [&](int a) {
+        const long double sk = sn[a % (4 * n)];   // sin(pi a / (2n))
+        return (double)(-(4.0L / ((long double)h * h)) * sk * sk);
+    };
+    for (int col = 0; col < n; ++col) {
+        int a = col;
+        if (xk == XK_C) a = col + 1;
+        if (xk == XK_F && col == 0) continue;   // the wall slot
+        lam[col] = eig(a);
+        for (int i = 0; i < n; ++i) {
+            long double v;
+            if (xk == XK_F) {
+                v = r2 * sn[(2LL * (((long long)a * i) % (2 * n))) % (4 * n)];
+            } else {
+                const int m = (int)(((long long)a * (2 * i + 1)) % (4 * n));
+                const long double scale = (a == 0 || a == n) ? r1 : r2;
+                v = scale * (xk == XK_P ? cs[m] : sn[m]);
+            }
+            Q[size_t(i) * n + col] = (double)v;
+        }
+    }
+}
+
 // Swizzle a K x N row-major matrix B into the per-lane fragment order of
 // the 16x16x4 FP64 matrix-core instruction: for every 16-deep K chunk kc and
 // 16-wide column block bj, lane l (0..63) holds four consecutive values
@@ -229,14 +276,18 @@ struct AxisTables {
     }
 };
 
-static std::shared_ptr<const AxisTables> build_axis(int n, double h, bool z_axis, bool split)
+// basis: -1 the periodic Fourier basis; XK_* a wall-bounded x basis (never
+// folded: the folds rest on the Fourier basis's mirror symmetry).
+static std::shared_ptr<const AxisTables> build_axis(int n, double h, bool z_axis, bool split, int basis)
 {
     auto t = std::make_shared<AxisTables>();
-    fourier_basis(n, h, t->Q, t->lam);
+    if (basis < 0) fourier_basis(n, h, t->Q, t->lam);
+    else wall_basis(n, h, basis, t->Q, t->lam);
     const std::vector<double> &Q = t->Q;
     const int hn = n / 2;
     const size_t h2 = size_t(hn) * hn;
-    if (can_fold(n)) {
+    const bool fourier = basis < 0;
+    if (fourier && can_fold(n)) {
         FoldFactors f(Q, n);
         for (auto &v : t->f64) v.resize(h2);
         if (!z_axis) {
@@ -265,7 +316,7 @@ static std::shared_ptr<const AxisTables> build_axis(int n, double h, bool z_axis
         }
     }
     if (split) {
-        if (can_fold_split(n)) {
+        if (fourier && can_fold_split(n)) {
             FoldFactors f(Q, n);
             t->split[0].resize(size_t(3) * 2 * h2);
             t->split[1].resize(size_t(3) * 2 * h2);
@@ -298,12 +349,14 @@ static std::shared_ptr<const AxisTables> build_axis(int n, double h, bool z_axis
 // entries dropped first).  Plans copy what they need, so dropping an entry
 // never affects an existing plan.
 constexpr size_t AXIS_CACHE_BYTES = size_t(256) << 20;
-static std::shared_ptr<const AxisTables> axis_tables(int n, double h, bool z_axis, bool split)
+static std::shared_ptr<const AxisTables> axis_tables(int n, double h, bool z_axis, bool split,
+                                                     int basis = -1)
 {
     struct Entry {
         int n;
         double h;
         bool z, split;
+        int basis;
         std::shared_ptr<const AxisTables> t;
     };
     static std::mutex mu;
@@ -311,9 +364,9 @@ static std::shared_ptr<const AxisTables> axis_tables(int n, double h, bool z_axi
     {
         std::lock_guard<std::mutex> lock(mu);
         for (const Entry &e : cache)
-            if (e.n == n && e.h == h && e.z == z_axis && e.split == split) return e.t;
+            if (e.n == n && e.h == h && e.z == z_axis && e.split == split && e.basis == basis) return e.t;
     }
-    std::shared_ptr<const AxisTables> t = build_axis(n, h, z_axis, split);
+    std::shared_ptr<const AxisTables> t = build_axis(n, h, z_axis, split, basis);
     std::lock_guard<std::mutex> lock(mu);
     size_t total = t->bytes();
     for (const Entry &e : cache) total += e.t->bytes();
@@ -321,7 +374,7 @@ static std::shared_ptr<const AxisTables> axis_tables(int n, double h, bool z_axi
         total -= cache.front().t->bytes();
         cache.erase(cache.begin());
     }
-    if (t->bytes() <= AXIS_CACHE_BYTES) cache.push_back(Entry{n, h, z_axis, split, t});
+    if (t->bytes() <= AXIS_CACHE_BYTES) cache.push_back(Entry{n, h, z_axis, split, basis, t});
     return t;
 }
 
@@ -337,9 +390,11 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     }
     const bool walls_y = d.bc_y_vel == IBS_DIRICHLET && d.bc_y_p == IBS_NEUMANN;
     const bool periodic_y = d.bc_y_vel == IBS_PERIODIC && d.bc_y_p == IBS_PERIODIC;
-    if (d.bc_x != IBS_PERIODIC || d.bc_z != IBS_PERIODIC || !(walls_y || periodic_y)) {
-        set_error("supported: periodic x/z with either Dirichlet velocity / Neumann pressure walls in y, "
-                  "or periodic y (triply periodic)");
+    if ((d.bc_x != IBS_PERIODIC && d.bc_x != IBS_DIRICHLET) || d.bc_z != IBS_PERIODIC ||
+        !(walls_y || periodic_y)) {
+        set_error("supported: x periodic or walls (bc_x = IBS_DIRICHLET: Dirichlet velocity, Neumann "
+                  "pressure), periodic z, and in y either Dirichlet velocity / Neumann pressure walls "
+                  "or periodic (triply periodic)");
         return IBS_ERR_UNSUPPORTED;
     }
     if (periodic_y && !cyclic_rows_supported(d.ny)) {
@@ -376,6 +431,7 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     p->desc = d;
     p->desc.y_faces = nullptr;
     p->py = periodic_y;
+    p->wx = d.bc_x == IBS_DIRICHLET;
     const double lx = d.lx > 0 ? d.lx : 1.0, ly = d.ly > 0 ? d.ly : 1.0, lz = d.lz > 0 ? d.lz : 1.0;
     p->desc.lx = lx; p->desc.ly = ly; p->desc.lz = lz;
     if (p->desc.tol <= 0) p->desc.tol = 1e-10;
@@ -466,21 +522,29 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     }
 
     const bool split = d.precision != IBS_FP64;
-    const std::shared_ptr<const AxisTables> ax = axis_tables(nx, p->hx, false, split);
+    // x: one Fourier table set (periodic), or one per x kind (walls)
+    std::shared_ptr<const AxisTables> ax[NUM_XK];
+    for (int k = 0; k < NUM_XK; ++k)
+        ax[k] = (p->wx || k == 0) ? axis_tables(nx, p->hx, false, split, p->wx ? k : -1) : ax[0];
     const std::shared_ptr<const AxisTables> az = axis_tables(nz, p->hz, true, split);
-    p->qx = ax->Q;
-    p->lam_x = ax->lam;
+    for (int k = 0; k < NUM_XK; ++k) {
+        p->qx[k] = ax[k]->Q;
+        p->lam_x[k] = ax[k]->lam;
+    }
     p->qz = az->Q;
     p->lam_z = az->lam;
+    const int nxk = p->wx ? NUM_XK : 1;   // distinct x tables
 
     // blob layout
     BlobLayout &L = p->lay;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
-    const bool fold_x = can_fold(nx), fold_z = can_fold(nz);
+    const bool fold_x = x_folds(*p), fold_z = can_fold(nz);
     const size_t hx2 = size_t(nx / 2) * (nx / 2), hz2 = size_t(nz / 2) * (nz / 2);
-    L.bx_fwd = take(fold_x ? 0 : sizeof(double) * nx * nx);
-    L.bx_inv = take(fold_x ? 0 : sizeof(double) * nx * nx);
+    for (int k = 0; k < NUM_XK; ++k) {
+        L.bx_fwd[k] = k < nxk ? take(fold_x ? 0 : sizeof(double) * nx * nx) : L.bx_fwd[0];
+        L.bx_inv[k] = k < nxk ? take(fold_x ? 0 : sizeof(double) * nx * nx) : L.bx_inv[0];
+    }
     L.az_fwd = take(fold_z ? 0 : sizeof(double) * nz * nz);
     L.az_inv = take(fold_z ? 0 : sizeof(double) * nz * nz);
     L.fx_fwd_c = take(fold_x ? sizeof(double) * hx2 : 0);
@@ -491,7 +555,7 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     L.fz_fwd_s = take(fold_z ? sizeof(double) * hz2 : 0);
     L.fz_inv_c = take(fold_z ? sizeof(double) * hz2 : 0);
     L.fz_inv_s = take(fold_z ? sizeof(double) * hz2 : 0);
-    L.lam_x = take(sizeof(double) * nx);
+    for (int k = 0; k < NUM_XK; ++k) L.lam_x[k] = k < nxk ? take(sizeof(double) * nx) : L.lam_x[0];
     L.lam_z = take(sizeof(double) * nz);
     for (int kd = 0; kd < NUM_KINDS; ++kd) {
         L.lo[kd] = take(sizeof(double) * (ny + 1));
@@ -501,9 +565,11 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     L.wy = take(sizeof(double) * ny);
     L.dyc = take(sizeof(double) * ny);
     L.dyf = take(sizeof(double) * (ny + 1));
-    const bool sfold_x = split && can_fold_split(nx), sfold_z = split && can_fold_split(nz);
-    L.sx_fwd = take(split && !sfold_x ? sizeof(uint16_t) * 3 * nx * nx : 0);
-    L.sx_inv = take(split && !sfold_x ? sizeof(uint16_t) * 3 * nx * nx : 0);
+    const bool sfold_x = split && x_folds_split(*p), sfold_z = split && can_fold_split(nz);
+    for (int k = 0; k < NUM_XK; ++k) {
+        L.sx_fwd[k] = k < nxk ? take(split && !sfold_x ? sizeof(uint16_t) * 3 * nx * nx : 0) : L.sx_fwd[0];
+        L.sx_inv[k] = k < nxk ? take(split && !sfold_x ? sizeof(uint16_t) * 3 * nx * nx : 0) : L.sx_inv[0];
+    }
     L.sz_fwd = take(split && !sfold_z ? sizeof(uint16_t) * 3 * nz * nz : 0);
     L.sz_inv = take(split && !sfold_z ? sizeof(uint16_t) * 3 * nz * nz : 0);
     L.sxf_fwd = take(sfold_x ? sizeof(uint16_t) * 3 * 2 * hx2 : 0);
@@ -524,7 +590,7 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
             for (int t = 0; t < nx / 32; ++t) {
                 bool need = false;
                 for (int a = 32 * t; a < 32 * t + 32 && !need; ++a) {
-                    const double sabs = std::fabs(p->lam_x[a] + p->lam_z[c]);
+                    const double sabs = std::fabs(p->lam_x[XK_P][a] + p->lam_z[c]);
                     need = sabs == 0.0 || 1.0 + g / sabs > (p->py ? LANE64_KAPPA_CYCLIC : LANE64_KAPPA);
                 }
                 if (need) {
@@ -545,13 +611,15 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
         std::memcpy(p->blob.data() + off, src.data(), src.size() * sizeof(uint16_t));
     };
     if (fold_x) {
-        put(L.fx_fwd_c, ax->f64[0].data(), hx2);
-        put(L.fx_fwd_s, ax->f64[1].data(), hx2);
-        put(L.fx_inv_c, ax->f64[2].data(), hx2);
-        put(L.fx_inv_s, ax->f64[3].data(), hx2);
+        put(L.fx_fwd_c, ax[0]->f64[0].data(), hx2);
+        put(L.fx_fwd_s, ax[0]->f64[1].data(), hx2);
+        put(L.fx_inv_c, ax[0]->f64[2].data(), hx2);
+        put(L.fx_inv_s, ax[0]->f64[3].data(), hx2);
     } else {
-        put(L.bx_fwd, ax->f64[0].data(), size_t(nx) * nx);
-        put(L.bx_inv, ax->f64[1].data(), size_t(nx) * nx);
+        for (int k = 0; k < nxk; ++k) {
+            put(L.bx_fwd[k], ax[k]->f64[0].data(), size_t(nx) * nx);
+            put(L.bx_inv[k], ax[k]->f64[1].data(), size_t(nx) * nx);
+        }
     }
     if (fold_z) {
         put(L.fz_fwd_c, az->f64[0].data(), hz2);
@@ -563,14 +631,21 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
         put(L.az_inv, az->f64[1].data(), size_t(nz) * nz);
     }
     if (split) {
-        put16(sfold_x ? L.sxf_fwd : L.sx_fwd, ax->split[0]);
-        put16(sfold_x ? L.sxf_inv : L.sx_inv, ax->split[1]);
+        if (sfold_x) {
+            put16(L.sxf_fwd, ax[0]->split[0]);
+            put16(L.sxf_inv, ax[0]->split[1]);
+        } else {
+            for (int k = 0; k < nxk; ++k) {
+                put16(L.sx_fwd[k], ax[k]->split[0]);
+                put16(L.sx_inv[k], ax[k]->split[1]);
+            }
+        }
         put16(sfold_z ? L.szf_fwd : L.sz_fwd, az->split[0]);
         put16(sfold_z ? L.szf_inv : L.sz_inv, az->split[1]);
     }
     if (!lane_mask.empty()) std::memcpy(p->blob.data() + L.lane_mask, lane_mask.data(), 4 * lane_mask.size());
     if (!lane_list.empty()) std::memcpy(p->blob.data() + L.lane_list, lane_list.data(), 4 * lane_list.size());
-    put(L.lam_x, p->lam_x.data(), nx);
+    for (int k = 0; k < nxk; ++k) put(L.lam_x[k], p->lam_x[k].data(), nx);
     put(L.lam_z, p->lam_z.data(), nz);
     for (int kd = 0; kd < NUM_KINDS; ++kd) {
         put(L.lo[kd], p->lo[kd].data(), ny + 1);

@@ -77,7 +77,7 @@ def test_refined_not_converged_falls_back_to_fp64():
         pytest.skip("no GPU")
     from paper_2406_19920_amd import serve
     print("case serve fallback", flush=True)
-    reqs = [dict(rid=0, arrival=0.0, kind="poisson", refined=True, n=48, beta=1.5, seed=31, max_iter=1),
+    reqs = [dict(rid=0, arrival=0.0, kind="poisson", refined=True, n=64, beta=1.5, seed=31, max_iter=1),
             dict(rid=1, arrival=0.0, kind="helmholtz", refined=True, n=32, beta=1.0, seed=32, max_iter=1),
             dict(rid=2, arrival=0.0, kind="poisson", refined=True, n=32, beta=0.5, seed=33)]
     ex = serve.GpuExecutor(slots=2, nmax=64)

@@ -169,9 +169,13 @@ def test_plan_bytes_and_errors():
         assert e.value.status == ibs.IBS_ERR_INVALID_ARG
     finally:
         ibs.solver_plan_destroy(p)
-    with pytest.raises(ibs.IbsError) as e:
-        _plan(32, 16, 32, bc_x=ibs.IBS_DIRICHLET)
-    assert e.value.status == ibs.IBS_ERR_UNSUPPORTED
+    # x walls are served; Neumann x (no meaning for the velocity) and
+    # non-periodic z are not
+    ibs.solver_plan_destroy(_plan(32, 16, 32, bc_x=ibs.IBS_DIRICHLET))
+    for kw in (dict(bc_x=ibs.IBS_NEUMANN), dict(bc_z=ibs.IBS_DIRICHLET)):
+        with pytest.raises(ibs.IbsError) as e:
+            _plan(32, 16, 32, **kw)
+        assert e.value.status == ibs.IBS_ERR_UNSUPPORTED
     # only the bfloat16x3 split scheme is built: the other refined names are
     # refused rather than silently served by it
     for prec in (ibs.IBS_REFINED_FP16X2, ibs.IBS_REFINED_AUTO):
@@ -349,5 +353,120 @@ def test_periodic_plan_rules():
         # v has ny faces: the Helmholtz workspace is as for cell fields or more
         _, wh = ibs.solver_plan_bytes(p, ibs.IBS_OP_HELMHOLTZ_U, 3)
         assert wh >= 3 * 32 * 64 * 32 * 8
+    finally:
+        ibs.solver_plan_destroy(p)
+
+
+# ------------------------------------------------------------------------
+# walls in x: the plan's x bases and a host emulation against the oracle
+# ------------------------------------------------------------------------
+def _x_tables(p, nx, xk):
+    """(Q, lambda) of x kind xk (0 pressure, 1 v/w, 2 u) from the exports."""
+    if xk == 0:
+        return ibs.ibs_plan_export(p, 1).reshape(nx, nx), ibs.ibs_plan_export(p, 3)
+    base = 5 + 3 * 4
+    q = ibs.ibs_plan_export(p, base + (0 if xk == 1 else 1)).reshape(nx, nx)
+    lam = ibs.ibs_plan_export(p, base + (2 if xk == 1 else 3))
+    return q, lam
+
+
+def _x_operator(nx, h, xk):
+    """The wall-bounded 1-D x operator, written out: Neumann cells (xk 0),
+    mirror-ghost Dirichlet cells (1), Dirichlet faces 1..nx-1 with the wall
+    slot 0 decoupled and zero (2)."""
+    T = np.zeros((nx, nx))
+    for i in range(nx):
+        for d in (-1, 1):
+            jn = i + d
+            if xk == 2:
+                if i == 0:
+                    break
+                T[i, i] -= 1.0 / h ** 2
+                if 1 <= jn <= nx - 1:
+                    T[i, jn] += 1.0 / h ** 2
+            elif 0 <= jn < nx:
+                T[i, i] -= 1.0 / h ** 2
+                T[i, jn] += 1.0 / h ** 2
+            elif xk == 1:
+                T[i, i] -= 2.0 / h ** 2
+    return T
+
+
+@pytest.mark.parametrize("nx", [16, 48, 64, 256])
+def test_x_wall_bases_diagonalise_the_x_operators(nx):
+    p = _plan(nx, 8, 32, lx=1.7, bc_x=ibs.IBS_DIRICHLET)
+    h = 1.7 / nx
+    try:
+        for xk in range(3):
+            Q, lam = _x_tables(p, nx, xk)
+            T = _x_operator(nx, h, xk)
+            np.testing.assert_allclose(T @ Q, Q * lam[None, :], rtol=0, atol=1e-11 / h ** 2)
+            keep = np.arange(nx) if xk != 2 else np.arange(1, nx)
+            Qk = Q[np.ix_(keep, keep)] if xk == 2 else Q
+            np.testing.assert_allclose(Qk.T @ Qk, np.eye(len(keep)), atol=1e-14)
+            if xk == 2:
+                assert np.all(Q[0, :] == 0) and np.all(Q[:, 0] == 0) and lam[0] == 0
+            # every eigenvalue is the modified wavenumber of its mode
+            assert np.all(lam <= 0) and lam.min() >= -4.0 / h ** 2
+        assert ibs.ibs_plan_export(p, 3)[0] == 0.0        # the pressure's constant mode
+    finally:
+        ibs.solver_plan_destroy(p)
+
+
+def _emulate_xwalls(p, nx, ny, nz, op, rhs, c=0.0):
+    xk = {OP_P: 0, OP_U: 2, OP_V: 1, OP_W: 1}[op]
+    Qx, lx = _x_tables(p, nx, xk)
+    Qz = ibs.ibs_plan_export(p, 2).reshape(nz, nz)
+    lz = ibs.ibs_plan_export(p, 4)
+    kind = {OP_P: 0, OP_U: 1, OP_W: 1, OP_V: 2}[op]
+    lo, di, up = _tables(p, kind)
+    n = ny + 1 if op == OP_V else ny
+    lo, di, up = lo[:n], di[:n], up[:n]
+    f = rhs.copy()
+    if op == OP_V:
+        f[:, 0, :] = 0
+        f[:, ny, :] = 0
+    h = np.einsum("kc,kja->cja", Qz, f @ Qx)
+    dyc = np.diff(ibs.ibs_plan_export(p, 0))
+    out = np.zeros_like(h)
+    for cz in range(nz):
+        for a in range(nx):
+            s = lx[a] + lz[cz]
+            if op == OP_P:
+                A = np.diag(di + s) + np.diag(lo[1:], -1) + np.diag(up[:-1], 1)
+            else:
+                A = np.eye(n) * (1 - c * s) - c * (np.diag(di) + np.diag(lo[1:], -1) + np.diag(up[:-1], 1))
+            rr = h[cz, :, a].copy()
+            if op == OP_P and a == 0 and cz == 0:
+                rr -= (dyc @ rr) / dyc.sum()
+                A[0, :] = 0
+                A[0, 0] = 1
+                rr[0] = 0
+                x = np.linalg.solve(A, rr)
+                x -= (dyc @ x) / dyc.sum()
+            elif op == OP_V:
+                x = np.zeros(n)
+                x[1:n - 1] = np.linalg.solve(A[1:n - 1, 1:n - 1], rr[1:n - 1])
+            else:
+                x = np.linalg.solve(A, rr)
+            out[cz, :, a] = x
+    return np.einsum("kc,cja->kja", Qz, out) @ Qx.T
+
+
+@pytest.mark.parametrize("beta", [0.0, 2.0])
+@pytest.mark.parametrize("op", [OP_P, OP_U, OP_V, OP_W])
+def test_host_emulation_xwalls_matches_oracle(op, beta):
+    nx, ny, nz = 16, 12, 32
+    p = _plan(nx, ny, nz, beta=beta, bc_x=ibs.IBS_DIRICHLET)
+    try:
+        g = oracle.Grid(nx, ny, nz, beta=beta, periodic_x=False)
+        rhs = synth.scalar(nx, ny, nz, 23, rows=ny + 1 if op == OP_V else None)
+        c = 0.0 if op == OP_P else 2e-3
+        xo, _ = oracle.solve(g, op, rhs, c=c)
+        xe = _emulate_xwalls(p, nx, ny, nz, op, rhs, c=c)
+        err = np.linalg.norm(xe - xo) / np.linalg.norm(xo)
+        assert err < 1e-13, err
+        if op == OP_U:
+            assert np.abs(xe[:, :, 0]).max() == 0.0
     finally:
         ibs.solver_plan_destroy(p)
