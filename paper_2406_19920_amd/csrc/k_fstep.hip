@@ -10,9 +10,10 @@
 // convective term in divergence form, each product formed on the face or
 // edge where its derivative needs it from arithmetic means of the
 // neighbouring values; with walls, v = 0 on the wall faces and no product
-// crosses them.  One thread per (i, j, k): the u and w faces of cell (i, j,
-// k) and the v face j below it (rows 0..ny with walls: the wall faces get
-// zeros); x fastest across the lanes, neighbours through L2.
+// crosses them.  One thread per (i, j) of a block's tile, marching in z:
+// the u and w faces of cell (i, j, k) and the v face j below it (rows
+// 0..ny with walls: the wall faces get zeros); neighbours from an LDS ring
+// of three planes.
 //
 // ibm_kernel (L1): one thread per marker: for each component, the 3 x 3 x 3
 // support of the Roma three-point kernel on that component's grid,
@@ -40,7 +41,21 @@ struct FsCoef {
 // y rows of v: ny + 1 with walls, ny when periodic
 static __device__ __forceinline__ int vrows(const FsGeo &g) { return g.py ? g.ny : g.ny + 1; }
 
-__global__ __launch_bounds__(256) void explicit_kernel(FsGeo g, FsCoef cf, const double *__restrict__ u,
+// Tiling of the explicit kernel: a block owns ETX x ETY (x, y) points, one
+// thread each, and marches through EKZ consecutive z planes.  The planes
+// k-1, k, k+1 of u, v, w, p sit in LDS as a ring of three tiles with a
+// one-point halo in x and y, so each plane of each field is read from HBM
+// once per block (plus the halo, which the neighbouring tiles on the same
+// XCD share in L2) instead of once per neighbour; the loads of plane k+2
+// are in flight while plane k is computed.  (A four-slot ring with one
+// barrier per plane needs 32 x 8 tiles to fit beside a second block and
+// measured slower: three waves per SIMD instead of four.)
+constexpr int ETX = 32, ETY = 16, ENT = ETX * ETY;
+constexpr int EHX = ETX + 2, EHY = ETY + 2, EPL = EHX * EHY;
+constexpr int EKZ = 16;                               // nz is a multiple of 16
+constexpr int EPER = (4 * EPL + ENT - 1) / ENT;       // staged values per thread and plane
+
+__global__ __launch_bounds__(ENT) void explicit_kernel(FsGeo g, FsCoef cf, const double *__restrict__ u,
                                                        const double *__restrict__ v,
                                                        const double *__restrict__ w,
                                                        const double *__restrict__ p,
@@ -49,111 +64,171 @@ __global__ __launch_bounds__(256) void explicit_kernel(FsGeo g, FsCoef cf, const
                                                        double *we, double *ru, double *rv, double *rw,
                                                        double *nu_out, double *nv_out, double *nw_out)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y, k = blockIdx.z;
-    if (i >= g.nx) return;
+    __shared__ double sm[3][4 * EPL];   // ring slot, then field (u, v, w, p) x tile
     const int nx = g.nx, ny = g.ny, nz = g.nz, vr = vrows(g);
-    const int ip = i + 1 == nx ? 0 : i + 1, im = i == 0 ? nx - 1 : i - 1;
-    const int kp = k + 1 == nz ? 0 : k + 1, km = k == 0 ? nz - 1 : k - 1;
-    // cell fields (u, w, p: [nz][ny][nx]) and v ([nz][vr][nx])
-    auto C = [&](const double *a, int kk, int jj, int ii) { return a[((size_t)kk * ny + jj) * nx + ii]; };
-    auto V = [&](int kk, int jj, int ii) {
-        // wall faces read as zero (their stored values are ignored)
-        if (!g.py && (jj <= 0 || jj >= ny)) return 0.0;
-        if (g.py) jj = jj < 0 ? jj + ny : (jj >= ny ? jj - ny : jj);
-        return v[((size_t)kk * vr + jj) * nx + ii];
-    };
+    // XCD-aware order: the hardware deals consecutive blocks to the 8 XCDs
+    // in turn; block b takes tile (b % 8) * per + b / 8, so each XCD walks a
+    // contiguous run of tiles (x fastest, then y, then z) and the halo lines
+    // that neighbouring tiles share are fetched into its own L2 once
+    const int gx = (nx + ETX - 1) / ETX, gy = (vr + ETY - 1) / ETY, ntile = gx * gy * (nz / EKZ);
+    const int per = (ntile + 7) / 8;
+    const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (tile >= ntile) return;   // whole block: before any barrier
+    const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
+    const int tx = threadIdx.x % ETX, ty = threadIdx.x / ETX;
+    const int i0 = bx * ETX, j0 = by * ETY, k0 = bz * EKZ;
+    const int k1 = k0 + EKZ;
+    const int i = i0 + tx, j = j0 + ty;
+
+    // staging of one plane: this thread's EPER (field, tile point) values
+    double stg[EPER];
+#define ETILE_FETCH(kk_)                                                                       \
+    do {                                                                                       \
+        const int kq = (kk_);                                                                  \
+        const int kw = kq < 0 ? kq + nz : (kq >= nz ? kq - nz : kq);                           \
+        _Pragma("unroll") for (int e = 0; e < EPER; ++e) {                                     \
+            const int idx = threadIdx.x + e * ENT;                                             \
+            double val = 0.0;                                                                  \
+            if (idx < 4 * EPL) {                                                               \
+                const int f = idx / EPL, r = idx - f * EPL;                                    \
+                const int hy = r / EHX, hx = r - hy * EHX;                                     \
+                int gi = i0 - 1 + hx;                                                          \
+                gi = gi < 0 ? gi + nx : (gi >= nx ? gi - nx : gi);                             \
+                int gj = j0 - 1 + hy;                                                          \
+                const int rows = f == 1 ? vr : ny;                                             \
+                if (g.py) gj = gj < 0 ? gj + ny : (gj >= ny ? gj - ny : gj);                   \
+                if (gj >= 0 && gj < rows && gi < nx) {                                         \
+                    const double *src = f == 0 ? u : (f == 1 ? v : (f == 2 ? w : p));          \
+                    val = src[((size_t)kw * rows + gj) * nx + gi];                             \
+                }                                                                              \
+            }                                                                                  \
+            stg[e] = val;                                                                      \
+        }                                                                                      \
+    } while (0)
+#define ETILE_PUT(kk_)                                                                         \
+    do {                                                                                       \
+        double *dst = sm[((kk_) - k0 + 1) % 3];                                                \
+        _Pragma("unroll") for (int e = 0; e < EPER; ++e) {                                     \
+            const int idx = threadIdx.x + e * ENT;                                             \
+            if (idx < 4 * EPL) dst[idx] = stg[e];                                              \
+        }                                                                                      \
+    } while (0)
+
     const double ihx = 1.0 / g.hx, ihz = 1.0 / g.hz;
     const double vis = cf.ab / cf.re;
     const bool zprev = cf.zet != 0.0;
 
-    if (j < ny) {
-        const size_t o = ((size_t)k * ny + j) * nx + i;
-        const int jn = j + 1 < ny ? j + 1 : (g.py ? 0 : -1);   // -1: wall above
-        const int js = j > 0 ? j - 1 : (g.py ? ny - 1 : -1);   // -1: wall below
-        const double D = g.dyc[j];
-        // y part of the Laplacian of a cell-height field f at row j (mirror
-        // ghost at a wall; fluxes over delta, delta_0 = delta_ny across the
-        // periodic wrap)
-        auto lapy = [&](const double *f) {
-            const double fc = C(f, k, j, i);
-            const double fu = jn >= 0 ? (C(f, k, jn, i) - fc) / g.dyf[j + 1] : -fc / (0.5 * D);
-            const double fl = js >= 0 ? (fc - C(f, k, js, i)) / g.dyf[j] : fc / (0.5 * D);
-            return (fu - fl) / D;
+    // rows outside a field (beyond a wall) are staged as zero; the formulas
+    // below never use them
+    ETILE_FETCH(k0 - 1);
+    ETILE_PUT(k0 - 1);
+    ETILE_FETCH(k0);
+    ETILE_PUT(k0);
+    ETILE_FETCH(k0 + 1);
+    for (int k = k0; k < k1; ++k) {
+        ETILE_PUT(k + 1);   // into the slot of plane k-2
+        __syncthreads();
+        if (k + 2 <= k1) ETILE_FETCH(k + 2);
+        // field f at plane k + dk, row j + dj, column i + di (tile offsets)
+        auto L = [&](int f, int dk, int dj, int di) {
+            return sm[(k - k0 + 1 + dk) % 3][f * EPL + (ty + 1 + dj) * EHX + (tx + 1 + di)];
         };
-        // ---- u at x-face (i, j, k)
-        {
-            const double uc = C(u, k, j, i);
-            const double lap = (C(u, k, j, ip) - 2.0 * uc + C(u, k, j, im)) * ihx * ihx +
-                               (C(u, kp, j, i) - 2.0 * uc + C(u, km, j, i)) * ihz * ihz + lapy(u);
-            const double gp = (C(p, k, j, i) - C(p, k, j, im)) * ihx;
-            const double c1 = 0.5 * (uc + C(u, k, j, ip)), c0 = 0.5 * (C(u, k, j, im) + uc);
-            const double dxx = (c1 * c1 - c0 * c0) * ihx;
-            // y fluxes v u on the faces j (below) and j+1 (above) at x-face i
-            const double fb = js >= 0 ? 0.5 * (V(k, j, i) + V(k, j, im)) * 0.5 * (C(u, k, js, i) + uc) : 0.0;
-            const double ft = jn >= 0 ? 0.5 * (V(k, j + 1, i) + V(k, j + 1, im)) * 0.5 * (uc + C(u, k, jn, i)) : 0.0;
-            const double dyy = (ft - fb) / D;
-            const double zb = 0.5 * (C(w, k, j, i) + C(w, k, j, im)) * 0.5 * (C(u, km, j, i) + uc);
-            const double zt = 0.5 * (C(w, kp, j, i) + C(w, kp, j, im)) * 0.5 * (uc + C(u, kp, j, i));
-            const double N = dxx + dyy + (zt - zb) * ihz;
-            double e = uc + cf.dt * (vis * lap - cf.ab * gp - cf.gam * N);
-            if (zprev) e -= cf.dt * cf.zet * nu_prev[o];
-            ue[o] = e;
-            ru[o] = e - cf.c * lap;
-            nu_out[o] = N;
+        // v with its wall faces read as zero (their stored values are ignored)
+        auto V = [&](int dk, int dj, int di) {
+            const int jj = j + dj;
+            if (!g.py && (jj <= 0 || jj >= ny)) return 0.0;
+            return L(1, dk, dj, di);
+        };
+        if (i < nx && j < ny) {
+            const size_t o = ((size_t)k * ny + j) * nx + i;
+            const bool hn = g.py || j + 1 < ny;   // a cell row above (else the wall)
+            const bool hs = g.py || j > 0;        // a cell row below
+            const double D = g.dyc[j];
+            // y part of the Laplacian of a cell-height field at row j
+            // (mirror ghost at a wall; fluxes over delta, delta_0 = delta_ny
+            // across the periodic wrap)
+            auto lapy = [&](int f) {
+                const double fc = L(f, 0, 0, 0);
+                const double fu = hn ? (L(f, 0, 1, 0) - fc) / g.dyf[j + 1] : -fc / (0.5 * D);
+                const double fl = hs ? (fc - L(f, 0, -1, 0)) / g.dyf[j] : fc / (0.5 * D);
+                return (fu - fl) / D;
+            };
+            // ---- u at x-face (i, j, k)
+            {
+                const double uc = L(0, 0, 0, 0);
+                const double lap = (L(0, 0, 0, 1) - 2.0 * uc + L(0, 0, 0, -1)) * ihx * ihx +
+                                   (L(0, 1, 0, 0) - 2.0 * uc + L(0, -1, 0, 0)) * ihz * ihz + lapy(0);
+                const double gp = (L(3, 0, 0, 0) - L(3, 0, 0, -1)) * ihx;
+                const double c1 = 0.5 * (uc + L(0, 0, 0, 1)), c0 = 0.5 * (L(0, 0, 0, -1) + uc);
+                const double dxx = (c1 * c1 - c0 * c0) * ihx;
+                // y fluxes v u on the faces j (below) and j+1 (above) at x-face i
+                const double fb = hs ? 0.5 * (V(0, 0, 0) + V(0, 0, -1)) * 0.5 * (L(0, 0, -1, 0) + uc) : 0.0;
+                const double ft = hn ? 0.5 * (V(0, 1, 0) + V(0, 1, -1)) * 0.5 * (uc + L(0, 0, 1, 0)) : 0.0;
+                const double dyy = (ft - fb) / D;
+                const double zb = 0.5 * (L(2, 0, 0, 0) + L(2, 0, 0, -1)) * 0.5 * (L(0, -1, 0, 0) + uc);
+                const double zt = 0.5 * (L(2, 1, 0, 0) + L(2, 1, 0, -1)) * 0.5 * (uc + L(0, 1, 0, 0));
+                const double N = dxx + dyy + (zt - zb) * ihz;
+                double e = uc + cf.dt * (vis * lap - cf.ab * gp - cf.gam * N);
+                if (zprev) e -= cf.dt * cf.zet * nu_prev[o];
+                ue[o] = e;
+                ru[o] = e - cf.c * lap;
+                nu_out[o] = N;
+            }
+            // ---- w at z-face (i, j, k): the x <-> z mirror of u
+            {
+                const double wc = L(2, 0, 0, 0);
+                const double lap = (L(2, 0, 0, 1) - 2.0 * wc + L(2, 0, 0, -1)) * ihx * ihx +
+                                   (L(2, 1, 0, 0) - 2.0 * wc + L(2, -1, 0, 0)) * ihz * ihz + lapy(2);
+                const double gp = (L(3, 0, 0, 0) - L(3, -1, 0, 0)) * ihz;
+                const double c1 = 0.5 * (wc + L(2, 1, 0, 0)), c0 = 0.5 * (L(2, -1, 0, 0) + wc);
+                const double dzz = (c1 * c1 - c0 * c0) * ihz;
+                const double fb = hs ? 0.5 * (V(0, 0, 0) + V(-1, 0, 0)) * 0.5 * (L(2, 0, -1, 0) + wc) : 0.0;
+                const double ft = hn ? 0.5 * (V(0, 1, 0) + V(-1, 1, 0)) * 0.5 * (wc + L(2, 0, 1, 0)) : 0.0;
+                const double dyy = (ft - fb) / D;
+                const double xb = 0.5 * (L(0, 0, 0, 0) + L(0, -1, 0, 0)) * 0.5 * (L(2, 0, 0, -1) + wc);
+                const double xt = 0.5 * (L(0, 0, 0, 1) + L(0, -1, 0, 1)) * 0.5 * (wc + L(2, 0, 0, 1));
+                const double N = (xt - xb) * ihx + dyy + dzz;
+                double e = wc + cf.dt * (vis * lap - cf.ab * gp - cf.gam * N);
+                if (zprev) e -= cf.dt * cf.zet * nw_prev[o];
+                we[o] = e;
+                rw[o] = e - cf.c * lap;
+                nw_out[o] = N;
+            }
         }
-        // ---- w at z-face (i, j, k): the x <-> z mirror of u
-        {
-            const double wc = C(w, k, j, i);
-            const double lap = (C(w, k, j, ip) - 2.0 * wc + C(w, k, j, im)) * ihx * ihx +
-                               (C(w, kp, j, i) - 2.0 * wc + C(w, km, j, i)) * ihz * ihz + lapy(w);
-            const double gp = (C(p, k, j, i) - C(p, km, j, i)) * ihz;
-            const double c1 = 0.5 * (wc + C(w, kp, j, i)), c0 = 0.5 * (C(w, km, j, i) + wc);
-            const double dzz = (c1 * c1 - c0 * c0) * ihz;
-            const double fb = js >= 0 ? 0.5 * (V(k, j, i) + V(km, j, i)) * 0.5 * (C(w, k, js, i) + wc) : 0.0;
-            const double ft = jn >= 0 ? 0.5 * (V(k, j + 1, i) + V(km, j + 1, i)) * 0.5 * (wc + C(w, k, jn, i)) : 0.0;
-            const double dyy = (ft - fb) / D;
-            const double xb = 0.5 * (C(u, k, j, i) + C(u, km, j, i)) * 0.5 * (C(w, k, j, im) + wc);
-            const double xt = 0.5 * (C(u, k, j, ip) + C(u, km, j, ip)) * 0.5 * (wc + C(w, k, j, ip));
-            const double N = (xt - xb) * ihx + dyy + dzz;
-            double e = wc + cf.dt * (vis * lap - cf.ab * gp - cf.gam * N);
-            if (zprev) e -= cf.dt * cf.zet * nw_prev[o];
-            we[o] = e;
-            rw[o] = e - cf.c * lap;
-            nw_out[o] = N;
+        // ---- v at y-face (i, j, k)
+        if (i < nx && j < vr) {
+            const size_t o = ((size_t)k * vr + j) * nx + i;
+            if (!g.py && (j == 0 || j == ny)) {   // wall faces
+                ve[o] = 0.0;
+                rv[o] = 0.0;
+                nv_out[o] = 0.0;
+            } else {
+                const int jm = j > 0 ? j - 1 : ny - 1;   // cell below the face (wraps when periodic)
+                const double vc = V(0, 0, 0);
+                const double d = g.dyf[j];
+                const double lapy = ((V(0, 1, 0) - vc) / g.dyc[j] - (vc - V(0, -1, 0)) / g.dyc[jm]) / d;
+                const double lap = (V(0, 0, 1) - 2.0 * vc + V(0, 0, -1)) * ihx * ihx +
+                                   (V(1, 0, 0) - 2.0 * vc + V(-1, 0, 0)) * ihz * ihz + lapy;
+                const double gp = (L(3, 0, 0, 0) - L(3, 0, -1, 0)) / d;
+                const double c1 = 0.5 * (vc + V(0, 1, 0)), c0 = 0.5 * (V(0, -1, 0) + vc);
+                const double dyy = (c1 * c1 - c0 * c0) / d;
+                // x fluxes u v on the x-faces i and i+1 at y-face j
+                const double xb = 0.5 * (L(0, 0, -1, 0) + L(0, 0, 0, 0)) * 0.5 * (vc + V(0, 0, -1));
+                const double xt = 0.5 * (L(0, 0, -1, 1) + L(0, 0, 0, 1)) * 0.5 * (V(0, 0, 1) + vc);
+                const double zb = 0.5 * (L(2, 0, -1, 0) + L(2, 0, 0, 0)) * 0.5 * (vc + V(-1, 0, 0));
+                const double zt = 0.5 * (L(2, 1, -1, 0) + L(2, 1, 0, 0)) * 0.5 * (V(1, 0, 0) + vc);
+                const double N = (xt - xb) * ihx + dyy + (zt - zb) * ihz;
+                double e = vc + cf.dt * (vis * lap - cf.ab * gp - cf.gam * N);
+                if (zprev) e -= cf.dt * cf.zet * nv_prev[o];
+                ve[o] = e;
+                rv[o] = e - cf.c * lap;
+                nv_out[o] = N;
+            }
         }
+        __syncthreads();   // the slot of plane k-1 is refilled next
     }
-    // ---- v at y-face (i, j, k)
-    if (j < vr) {
-        const size_t o = ((size_t)k * vr + j) * nx + i;
-        if (!g.py && (j == 0 || j == ny)) {   // wall faces
-            ve[o] = 0.0;
-            rv[o] = 0.0;
-            nv_out[o] = 0.0;
-            return;
-        }
-        const int jm = j > 0 ? j - 1 : ny - 1;       // cell below the face (wraps when periodic)
-        const int jc = j;                            // cell above the face (j < ny here)
-        const double vc = V(k, j, i);
-        const double d = g.dyf[j];
-        const double lapy = ((V(k, j + 1, i) - vc) / g.dyc[jc] - (vc - V(k, j - 1, i)) / g.dyc[jm]) / d;
-        const double lap = (V(k, j, ip) - 2.0 * vc + V(k, j, im)) * ihx * ihx +
-                           (V(kp, j, i) - 2.0 * vc + V(km, j, i)) * ihz * ihz + lapy;
-        const double gp = (C(p, k, jc, i) - C(p, k, jm, i)) / d;
-        const double c1 = 0.5 * (vc + V(k, j + 1, i)), c0 = 0.5 * (V(k, j - 1, i) + vc);
-        const double dyy = (c1 * c1 - c0 * c0) / d;
-        // x fluxes u v on the x-faces i and i+1 at y-face j
-        const double xb = 0.5 * (C(u, k, jm, i) + C(u, k, jc, i)) * 0.5 * (vc + V(k, j, im));
-        const double xt = 0.5 * (C(u, k, jm, ip) + C(u, k, jc, ip)) * 0.5 * (V(k, j, ip) + vc);
-        const double zb = 0.5 * (C(w, k, jm, i) + C(w, k, jc, i)) * 0.5 * (vc + V(km, j, i));
-        const double zt = 0.5 * (C(w, kp, jm, i) + C(w, kp, jc, i)) * 0.5 * (V(kp, j, i) + vc);
-        const double N = (xt - xb) * ihx + dyy + (zt - zb) * ihz;
-        double e = vc + cf.dt * (vis * lap - cf.ab * gp - cf.gam * N);
-        if (zprev) e -= cf.dt * cf.zet * nv_prev[o];
-        ve[o] = e;
-        rv[o] = e - cf.c * lap;
-        nv_out[o] = N;
-    }
+#undef ETILE_FETCH
+#undef ETILE_PUT
 }
 
 // Roma, Peskin and Berger's three-point regularised delta, grid units.
@@ -245,9 +320,10 @@ hipError_t launch_explicit(const Plan &p, const FsStage &s, hipStream_t st)
     cf.dt = s.dt;
     cf.re = s.re;
     cf.c = s.beta * s.dt / s.re;
-    const int blk = p.nx >= 256 ? 256 : ((p.nx + 63) / 64) * 64;
-    dim3 grid((p.nx + blk - 1) / blk, p.py ? p.ny : p.ny + 1, p.nz);
-    hipLaunchKernelGGL(explicit_kernel, grid, dim3(blk), 0, st, g, cf, s.u, s.v, s.w, s.p, s.nu, s.nv, s.nw,
+    const int vr = p.py ? p.ny : p.ny + 1;
+    const int ntile = ((p.nx + ETX - 1) / ETX) * ((vr + ETY - 1) / ETY) * (p.nz / EKZ);
+    dim3 grid(8 * ((ntile + 7) / 8));   // a whole number of blocks per XCD
+    hipLaunchKernelGGL(explicit_kernel, grid, dim3(ENT), 0, st, g, cf, s.u, s.v, s.w, s.p, s.nu, s.nv, s.nw,
                        s.ue, s.ve, s.we, s.ru, s.rv, s.rw, s.nu, s.nv, s.nw);
     return hipGetLastError();
 }

@@ -30,14 +30,33 @@ static Geo geo_of(const Plan &p)
     return g;
 }
 
+// XCD-aware order of the row blocks: the hardware deals consecutive blocks
+// to the 8 XCDs in turn, so block b takes tile (b % 8) * per + b / 8 (per =
+// ceil(ntiles / 8)), and each XCD walks a contiguous run of rows, x blocks
+// fastest, then y, then z: the neighbouring rows and planes a stencil reads
+// were mostly fetched into that XCD's own L2 by the blocks just before.
+// Returns false for the padding blocks of the last XCD's run.
+static __device__ __forceinline__ bool xcd_tile(int gx, int rows, int nz, int &bx, int &j, int &k)
+{
+    const int ntiles = gx * rows * nz, per = (ntiles + 7) / 8;
+    const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (t >= ntiles) return false;
+    bx = t % gx;
+    const int r = t / gx;
+    j = r % rows;
+    k = r / rows;
+    return true;
+}
+
 // b = scale * ((u_{i+1}-u_i)/hx + (v_{j+1}-v_j)/Delta_j + (w_{k+1}-w_k)/hz)
 __global__ __launch_bounds__(256) void divergence_kernel(Geo g, const double *__restrict__ u,
                                                          const double *__restrict__ v,
                                                          const double *__restrict__ w,
                                                          double *__restrict__ b, double scale)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y, k = blockIdx.z;
+    int bx, j, k;
+    if (!xcd_tile((g.nx + blockDim.x - 1) / blockDim.x, g.ny, g.nz, bx, j, k)) return;
+    const int i = bx * blockDim.x + threadIdx.x;
     if (i >= g.nx) return;
     const size_t plane = (size_t)g.ny * g.nx;
     const size_t c = (size_t)k * plane + (size_t)j * g.nx + i;
@@ -63,8 +82,9 @@ __global__ __launch_bounds__(256) void correct_kernel(Geo g, const double *__res
                                                       double *__restrict__ pr,
                                                       const double *__restrict__ lap, double cp)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y, k = blockIdx.z;
+    int bx, j, k;
+    if (!xcd_tile((g.nx + blockDim.x - 1) / blockDim.x, g.ny + 1 - g.py, g.nz, bx, j, k)) return;
+    const int i = bx * blockDim.x + threadIdx.x;
     if (i >= g.nx) return;
     const size_t plane = (size_t)g.ny * g.nx;
     const size_t vc = ((size_t)k * (g.ny + 1 - g.py) + j) * g.nx + i;
@@ -206,13 +226,19 @@ __global__ __launch_bounds__(256) void reduce_pairs_kernel(const double *__restr
 }
 
 static dim3 row_block(int nx) { return dim3(nx >= 256 ? 256 : ((nx + 63) / 64) * 64); }
+// one-dimensional grid of xcd_tile's order: a whole number of blocks per XCD
+static dim3 xcd_grid(int nx, dim3 blk, int rows, int nz)
+{
+    const int ntiles = (int)((nx + blk.x - 1) / blk.x) * rows * nz;
+    return dim3(8 * ((ntiles + 7) / 8));
+}
 
 hipError_t launch_divergence(const Plan &p, const double *u, const double *v, const double *w,
                              double *b, double scale, hipStream_t s)
 {
     Geo g = geo_of(p);
     dim3 blk = row_block(p.nx);
-    dim3 grid((p.nx + blk.x - 1) / blk.x, p.ny, p.nz);
+    dim3 grid = xcd_grid(p.nx, blk, p.ny, p.nz);
     hipLaunchKernelGGL(divergence_kernel, grid, blk, 0, s, g, u, v, w, b, scale);
     return hipGetLastError();
 }
@@ -222,7 +248,7 @@ hipError_t launch_correct(const Plan &p, const double *phi, double *u, double *v
 {
     Geo g = geo_of(p);
     dim3 blk = row_block(p.nx);
-    dim3 grid((p.nx + blk.x - 1) / blk.x, p.py ? p.ny : p.ny + 1, p.nz);   // the v face rows
+    dim3 grid = xcd_grid(p.nx, blk, p.py ? p.ny : p.ny + 1, p.nz);   // the v face rows
     hipLaunchKernelGGL(correct_kernel, grid, blk, 0, s, g, phi, u, v, w, gs, pr, lap, cp);
     return hipGetLastError();
 }

@@ -40,6 +40,8 @@ CLASSES = {
     "xgemm_split": (r"\bsplit_x\w*kernel<\d+, \d+, (double|float), 0(, false)?(, \d+)?>", ("k_split.hip",)),
     "zgemm_split": (r"\bsplit_z\w*kernel<", ("k_split.hip",)),
     "update": (r"\bsplit_x\w*kernel<\d+, \d+, float, [1-4](, true)?(, \d+)?>", ("k_split.hip",)),
+    "explicit": (r"\bexplicit_kernel\b", ("k_fstep.hip",)),
+    "ibm": (r"\bibm_kernel\b", ("k_fstep.hip",)),
 }
 
 
