@@ -1030,14 +1030,7 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
     const size_t plane = (size_t)rows * nx;
     const Tx *__restrict__ x = static_cast<const Tx *>(jb.xs);
     const double bm = (op == IBS_OP_POISSON) ? bmean[job] : 0.0;
-    // XCD-aware tile order (consecutive blocks go to the 8 XCDs in turn; the
-    // grid's x extent is a multiple of 8): block b takes tile (b % 8) * per
-    // + b / 8, so an XCD's blocks hold adjacent row tiles and the y
-    // neighbours they share come from its own L2
-    const int ntiles = tiles_y * ((nz + rz - 1) / rz), per = (int)(gridDim.x / 8);
-    const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-    if (tile >= ntiles) return;   // whole block, before any barrier
-    const int kz = tile / tiles_y, ty = tile - kz * tiles_y;
+    const int kz = blockIdx.x / tiles_y, ty = blockIdx.x - kz * tiles_y;
     const int k0 = kz * rz, k1 = min(nz, k0 + rz);
     const int tr = nx >> 2;                       // threads per row
     const int t = threadIdx.x % tr, rb = threadIdx.x / tr;
@@ -1138,7 +1131,7 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
     if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = wx;
     __syncthreads();
     if (threadIdx.x == 0)
-        xsum[(size_t)job * XSUM_SLOTS + tile] = sm[0] + sm[1] + sm[2] + sm[3];
+        xsum[(size_t)job * XSUM_SLOTS + blockIdx.x] = sm[0] + sm[1] + sm[2] + sm[3];
 }
 
 // After refinement pass p >= 1, one block per job sums the update partials of
@@ -1434,7 +1427,7 @@ hipError_t launch_residual_f32(const SplitSet &ss, const Plan &p, const State &s
     const int *skip = pass >= 2 ? st.done : nullptr;
     int rb_rows, tiles_y, rz, tiles;
     residual_tiling(p, rb_rows, tiles_y, rz, tiles);
-    dim3 grid(8 * ((tiles + 7) / 8), ss.n);
+    dim3 grid(tiles, ss.n);
     auto go = [&](auto kernel) {
         hipLaunchKernelGGL(kernel, grid, dim3(256), 0, s, ss, p.nx, p.ny, p.nz, 1.0 / (p.hx * p.hx),
                            1.0 / (p.hz * p.hz), blob_ptr(p, p.lay.dyc), blob_ptr(p, p.lay.dyf),

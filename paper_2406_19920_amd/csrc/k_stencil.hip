@@ -35,7 +35,10 @@ static Geo geo_of(const Plan &p)
 // ceil(ntiles / 8)), and each XCD walks a contiguous run of rows, x blocks
 // fastest, then y, then z: the neighbouring rows and planes a stencil reads
 // were mostly fetched into that XCD's own L2 by the blocks just before.
-// Returns false for the padding blocks of the last XCD's run.
+// Returns false for the padding blocks of the last XCD's run.  Used by the
+// correction (2 % faster in same-box runs, HBM traffic 1.14x -> 1.00x of
+// algorithmic); the divergence keeps the hardware's round-robin order, in
+// which it measured 4 % faster although it fetches 1.25x.
 static __device__ __forceinline__ bool xcd_tile(int gx, int rows, int nz, int &bx, int &j, int &k)
 {
     const int ntiles = gx * rows * nz, per = (ntiles + 7) / 8;
@@ -54,9 +57,8 @@ __global__ __launch_bounds__(256) void divergence_kernel(Geo g, const double *__
                                                          const double *__restrict__ w,
                                                          double *__restrict__ b, double scale)
 {
-    int bx, j, k;
-    if (!xcd_tile((g.nx + blockDim.x - 1) / blockDim.x, g.ny, g.nz, bx, j, k)) return;
-    const int i = bx * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y, k = blockIdx.z;
     if (i >= g.nx) return;
     const size_t plane = (size_t)g.ny * g.nx;
     const size_t c = (size_t)k * plane + (size_t)j * g.nx + i;
@@ -238,7 +240,7 @@ hipError_t launch_divergence(const Plan &p, const double *u, const double *v, co
 {
     Geo g = geo_of(p);
     dim3 blk = row_block(p.nx);
-    dim3 grid = xcd_grid(p.nx, blk, p.ny, p.nz);
+    dim3 grid((p.nx + blk.x - 1) / blk.x, p.ny, p.nz);
     hipLaunchKernelGGL(divergence_kernel, grid, blk, 0, s, g, u, v, w, b, scale);
     return hipGetLastError();
 }
