@@ -433,7 +433,7 @@ def run_serve(rates, count, geometries=0):
         srv.close()
         log(json.dumps(d))
     workload = ("Poisson-process arrivals; 50/50 Poisson or Helmholtz x3; 50/50 FP64 or refined; "
-                "n log-uniform [32,384] (multiple of 32); beta ~ U[0,3]; "
+                "n log-uniform [32,384] (multiple of 16; refined requests multiple of 32); beta ~ U[0,3]; "
                 + (f"(n, beta) from a pool of {geometries} grids; " if geometries
                    else "a new grid per request; ")
                 + f"8 slots, 96 GiB budget; {count} requests per rate")

@@ -161,24 +161,28 @@ def device_normal(shape, seed: int, device):
 
 
 def serving_requests(rate: float, count: int, seed: int, nmin: int = 32, nmax: int = 384,
-                     multiple: int = 32, beta_max: float = 3.0, geometries: int = 0):
+                     multiple: int = 16, multiple_refined: int = 32, beta_max: float = 3.0,
+                     geometries: int = 0):
     """Request stream of the serving workload: Poisson-process arrivals at
     `rate` per second; kind 50/50 pressure Poisson or Helmholtz x3; precision
-    50/50 FP64 or refined; cubic grid n log-uniform on [nmin, nmax] rounded
-    to a multiple of `multiple`; tanh beta ~ U[0, beta_max]; per-request
-    seeds.  With `geometries` > 0 the (n, beta) pairs are drawn once into a
-    pool of that many and each request takes one of them uniformly (clients
-    re-solving on a few grids, so plans can be reused); with 0 every request
-    draws its own grid.  Returns a list of dicts sorted by arrival time
-    (seconds)."""
+    50/50 FP64 or refined; cubic grid n log-uniform on [nmin, nmax], rounded
+    to a multiple of `multiple` (FP64 requests) or `multiple_refined`
+    (refined requests: the split matrix-core path takes multiples of 32);
+    tanh beta ~ U[0, beta_max]; per-request seeds.  With `geometries` > 0
+    the (n, beta) pairs are drawn once into a pool of that many and each
+    request takes one of them uniformly (clients re-solving on a few grids,
+    so plans can be reused; n is rounded per request as above); with 0
+    every request draws its own grid.  Returns a list of dicts sorted by
+    arrival time (seconds)."""
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate, size=count)
     t = np.cumsum(gaps) - gaps[0]
 
+    def rounded(n, m):
+        return int(max(m, min(nmax - nmax % m, m * round(n / m))))
+
     def grid(g):
-        n = float(np.exp(g.uniform(np.log(nmin), np.log(nmax))))
-        n = int(max(multiple, min(nmax, multiple * round(n / multiple))))
-        return n, float(g.uniform(0.0, beta_max))
+        return float(np.exp(g.uniform(np.log(nmin), np.log(nmax)))), float(g.uniform(0.0, beta_max))
 
     pool = None
     if geometries > 0:
@@ -187,14 +191,14 @@ def serving_requests(rate: float, count: int, seed: int, nmin: int = 32, nmax: i
     out = []
     for i in range(count):
         if pool is None:
-            n = float(np.exp(rng.uniform(np.log(nmin), np.log(nmax))))
-            n = int(max(multiple, min(nmax, multiple * round(n / multiple))))
+            nraw = float(np.exp(rng.uniform(np.log(nmin), np.log(nmax))))
         else:
-            n, beta = pool[int(rng.integers(geometries))]
+            nraw, beta = pool[int(rng.integers(geometries))]
         kind = "poisson" if rng.random() < 0.5 else "helmholtz"
         refined = bool(rng.random() < 0.5)
         if pool is None:
             beta = float(rng.uniform(0.0, beta_max))
+        n = rounded(nraw, multiple_refined if refined else multiple)
         out.append(dict(rid=i, arrival=float(t[i]), kind=kind, refined=refined, n=n,
                         beta=beta, seed=int(seed * 100003 + i)))
     return out

@@ -189,7 +189,10 @@ def test_request_generator_recipe():
     assert np.all(np.diff(arr) >= 0)
     assert abs(len(reqs) / arr[-1] - 1000) < 100            # Poisson rate
     ns = np.array([r["n"] for r in reqs])
-    assert ns.min() >= 32 and ns.max() <= 384 and np.all(ns % 32 == 0)
+    rf = np.array([r["refined"] for r in reqs])
+    assert ns.min() >= 32 and ns.max() <= 384
+    assert np.all(ns[rf] % 32 == 0) and np.all(ns[~rf] % 16 == 0)
+    assert np.any(ns[~rf] % 32 == 16)          # FP64 requests use the finer sizes
     assert 0.45 < np.mean([r["kind"] == "poisson" for r in reqs]) < 0.55
     assert 0.45 < np.mean([r["refined"] for r in reqs]) < 0.55
 
@@ -197,8 +200,10 @@ def test_request_generator_recipe():
 def test_geometry_pool_reuses_plans():
     reqs = synth.serving_requests(rate=1000, count=400, seed=4, nmin=32, nmax=128, geometries=5)
     grids = {(r["n"], r["beta"]) for r in reqs}
-    assert len(grids) <= 5
-    assert all(r["n"] % 32 == 0 and 32 <= r["n"] <= 128 and 0.0 <= r["beta"] <= 3.0 for r in reqs)
+    assert len(grids) <= 10                     # each pool grid, rounded per precision
+    assert len({r["beta"] for r in reqs}) <= 5
+    assert all(r["n"] % (32 if r["refined"] else 16) == 0 and 32 <= r["n"] <= 128
+               and 0.0 <= r["beta"] <= 3.0 for r in reqs)
     # the pool depends on the seed alone, not on the rate
     other = synth.serving_requests(rate=50, count=400, seed=4, nmin=32, nmax=128, geometries=5)
     assert {(r["n"], r["beta"]) for r in other} == grids
@@ -207,7 +212,7 @@ def test_geometry_pool_reuses_plans():
     d = res.summary()
     assert d["completed"] == 400
     # one miss per plan key at most per concurrent use; most requests hit
-    assert d["plan_hits"] > 300 and d["plan_hits"] + d["plan_misses"] == 400
+    assert d["plan_hits"] > 280 and d["plan_hits"] + d["plan_misses"] == 400
 
 
 def test_not_converged_refined_request_falls_back_to_fp64():
