@@ -23,17 +23,28 @@ def cn_coefficient(solver) -> float:
     return 0.125 * hmin * hmin
 
 
+# boundary kinds a job spec may name (key "bc"; default "walls": walls in y,
+# periodic x and z)
+BC_KINDS = {
+    "walls": {},
+    "periodic_y": dict(bc_y_vel=ibs.IBS_PERIODIC, bc_y_p=ibs.IBS_PERIODIC),
+    "walls_x": dict(bc_x=ibs.IBS_DIRICHLET),
+}
+
+
 class Job:
     def __init__(self, spec, precision, device):
         nx, ny, nz = spec["nx"], spec["ny"], spec["nz"]
         self.spec = spec
-        self.solver = ibs.Solver(nx, ny, nz, beta=spec["beta"], precision=precision, device=device)
+        self.solver = ibs.Solver(nx, ny, nz, beta=spec["beta"], precision=precision, device=device,
+                                 **BC_KINDS[spec.get("bc", "walls")])
         S = self.solver
         self.c = spec.get("c", cn_coefficient(S))
         seed = spec["seed"]
         self.r = [synth.device_normal(S.shape(op), seed * 8 + op, S.device) for op in (1, 2, 3)]
-        self.r[1][:, 0, :] = 0
-        self.r[1][:, ny, :] = 0
+        if not S.periodic_y:
+            self.r[1][:, 0, :] = 0
+            self.r[1][:, ny, :] = 0
         self.b = synth.device_normal(S.shape(0), seed * 8 + 5, S.device)
         self.x = [S.empty(op) for op in (1, 2, 3)]
         self.phi = S.empty(0)

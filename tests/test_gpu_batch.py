@@ -127,3 +127,51 @@ def test_batch_mixed_sizes_manufactured(mods, refined):
         for k in range(4):
             assert j.solver.read_info(k).status == 0
     B.close()
+
+
+@pytest.mark.parametrize("refined", [True, False])
+def test_batch_boundary_kinds(mods, refined):
+    """Jobs with walls in y, periodic y and walls in x in one graph: each
+    equals the same job run alone (bitwise) and all four solves match the
+    oracle (l2 and max norm)."""
+    from oracle import OP_U, OP_V, OP_W
+    batch, ibs = mods
+    prec = ibs.IBS_REFINED_BF16X3 if refined else ibs.IBS_FP64
+    tol = 1e-10 if refined else 1e-12
+    specs = [dict(nx=64, ny=48, nz=32, beta=0.0, seed=1200, bc="periodic_y"),
+             dict(nx=64, ny=40, nz=32, beta=1.5, seed=1201, bc="walls_x"),
+             dict(nx=32, ny=24, nz=64, beta=2.0, seed=1202, bc="walls"),
+             dict(nx=32, ny=64, nz=32, beta=1.0, seed=1203, bc="walls_x")]
+    print("case batch boundary kinds", refined, flush=True)
+    B = batch.Batch(specs, precision=prec, nlanes=3)
+    alone = []
+    for j in B.jobs:
+        j.run_eager()
+        torch.cuda.synchronize()
+        alone.append([o.cpu().numpy().copy() for o in j.outputs()])
+    for rep in range(2):
+        for j in B.jobs:
+            for o in j.outputs():
+                o.fill_(float("nan"))
+        B.launch()
+        torch.cuda.synchronize()
+        for q, j in enumerate(B.jobs):
+            for a, o in zip(alone[q], j.outputs()):
+                np.testing.assert_array_equal(o.cpu().numpy(), a, err_msg=f"job {q} replay {rep}")
+    for q, j in enumerate(B.jobs):
+        s = j.spec
+        g = oracle.Grid(s["nx"], s["ny"], s["nz"], beta=s["beta"], periodic_y=s["bc"] == "periodic_y",
+                        periodic_x=s["bc"] != "walls_x")
+        outs = j.outputs()
+        for k, op in enumerate((OP_U, OP_V, OP_W)):
+            ref, _ = oracle.solve(g, op, j.r[k].cpu().numpy(), c=j.c)
+            err = _rel(outs[k].cpu().numpy(), ref)
+            print("job", q, s["bc"], "comp", k, "err", err, flush=True)
+            assert err < tol
+        ref, _ = oracle.solve(g, OP_P, j.b.cpu().numpy())
+        err = _rel(outs[3].cpu().numpy(), ref)
+        print("job", q, s["bc"], "poisson err", err, flush=True)
+        assert err < tol
+        for k in range(4):
+            assert j.solver.read_info(k).status == 0
+    B.close()

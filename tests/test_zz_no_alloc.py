@@ -47,6 +47,33 @@ def test_noalloc_matches_workspace_entry(refined):
         S.close()
 
 
+@pytest.mark.parametrize("refined", [False, True])
+def test_noalloc_boundary_kinds(refined):
+    """Periodic y and walls in x through the allocation-free entry point:
+    bitwise equal to solve_poisson() with a workspace, two calls in a row
+    (the second smaller)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_19920_amd import ibsolve as ibs
+    prec = ibs.IBS_REFINED_BF16X3 if refined else ibs.IBS_FP64
+    print("case noalloc boundary kinds", "refined" if refined else "fp64", flush=True)
+    cases = (((96, 64, 64), dict(bc_y_vel=ibs.IBS_PERIODIC, bc_y_p=ibs.IBS_PERIODIC), 5),
+             ((64, 40, 32), dict(bc_x=ibs.IBS_DIRICHLET, beta=1.5), 6))
+    for (nx, ny, nz), kw, seed in cases:
+        S = ibs.Solver(nx, ny, nz, precision=prec, **kw)
+        assert S.work_p <= ibs.IBS_NOALLOC_SCRATCH_BYTES
+        bd = torch.from_numpy(synth.scalar(nx, ny, nz, seed)).to("cuda")
+        ref = S.poisson(bd)
+        phi = torch.full_like(bd, float("nan"))
+        info = torch.zeros(8, dtype=torch.float64, device="cuda")
+        ibs.solve_poisson_noalloc(S.plan, bd.data_ptr(), phi.data_ptr(), info.data_ptr(), S.stream())
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(phi.cpu().numpy(), ref.cpu().numpy())
+        inf = ibs.ibs_solve_info.from_buffer_copy(info.cpu().numpy().tobytes()[:ibs.INFO_BYTES])
+        assert inf.status == 0
+        S.close()
+
+
 def test_noalloc_refuses_oversize_grid():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
