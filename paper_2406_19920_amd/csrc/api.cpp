@@ -636,9 +636,10 @@ ibs_status ibs_rk_stage(ibs_plan plan, const ibs_rk_coef *coef, const ibs_stage_
     const double c = k.beta * k.dt / k.re, g = (k.alpha + k.beta) * k.dt;
 
     // algorithmic traffic of the explicit estimate: u, v, w, p (+ the previous
-    // N when zeta != 0) read, u^e, r and N written, 8 bytes each per cell
+    // N when zeta != 0) read, r and N (+ u^e when markers interpolate it)
+    // written, 8 bytes each per cell
     const double cells = (double)p.nx * p.ny * p.nz;
-    const double ebytes = 8.0 * cells * (k.zeta != 0.0 ? 16.0 : 13.0);
+    const double ebytes = 8.0 * cells * (10.0 + (k.zeta != 0.0 ? 3.0 : 0.0) + (f->nmarkers > 0 ? 3.0 : 0.0));
     hipError_t e = timed(p, PK_EXPLICIT, 150.0 * cells, ebytes, st,
                          [&] { return launch_explicit(p, s, st); });   // (a) and the rhs of (e)
     if (e != hipSuccess) return hip_fail(e, "explicit estimate");

@@ -6,7 +6,8 @@
 //                  - gamma N(u) - zeta N_prev ]                    (eq. a)
 // together with the Helmholtz right-hand side without the forcing,
 //   r = u^e - c L u,  c = beta dt / Re                             (eq. e)
-// and N(u) itself (kept for the next stage's zeta term).  N is the
+// and N(u) itself (kept for the next stage's zeta term); u^e is written only
+// when markers will interpolate it.  N is the
 // convective term in divergence form, each product formed on the face or
 // edge where its derivative needs it from arithmetic means of the
 // neighbouring values; with walls, v = 0 on the wall faces and no product
@@ -62,7 +63,8 @@ __global__ __launch_bounds__(ENT) void explicit_kernel(FsGeo g, FsCoef cf, const
                                                        const double *nu_prev, const double *nv_prev,
                                                        const double *nw_prev, double *ue, double *ve,
                                                        double *we, double *ru, double *rv, double *rw,
-                                                       double *nu_out, double *nv_out, double *nw_out)
+                                                       double *nu_out, double *nv_out, double *nw_out,
+                                                       int keep_ue)
 {
     __shared__ double sm[3][4 * EPL];   // ring slot, then field (u, v, w, p) x tile
     const int nx = g.nx, ny = g.ny, nz = g.nz, vr = vrows(g);
@@ -118,6 +120,21 @@ __global__ __launch_bounds__(ENT) void explicit_kernel(FsGeo g, FsCoef cf, const
     const double vis = cf.ab / cf.re;
     const bool zprev = cf.zet != 0.0;
 
+    // a thread keeps its (i, j) through the march: the y metric of its row
+    // as reciprocals, once (cell rows: 1/Delta_j, 1/delta_j, 1/delta_{j+1},
+    // and 2/Delta_j for the mirror-ghost flux; face rows: 1/delta_j and
+    // 1/Delta of the cells above and below)
+    const bool crow = i < nx && j < ny;
+    const double iD = crow ? 1.0 / g.dyc[j] : 0.0;
+    const double i2D = 2.0 * iD;
+    const double idn = crow && (g.py || j + 1 < ny) ? 1.0 / g.dyf[j + 1] : 0.0;
+    const double ids = crow && (g.py || j > 0) ? 1.0 / g.dyf[j] : 0.0;
+    const bool frow = i < nx && j < vr && (g.py || (j > 0 && j < ny));
+    const int jm = j > 0 ? j - 1 : ny - 1;   // the cell below a face (wraps when periodic)
+    const double ifd = frow ? 1.0 / g.dyf[j] : 0.0;
+    const double ifa = frow ? 1.0 / g.dyc[j] : 0.0;
+    const double ifb = frow ? 1.0 / g.dyc[jm] : 0.0;
+
     // rows outside a field (beyond a wall) are staged as zero; the formulas
     // below never use them
     ETILE_FETCH(k0 - 1);
@@ -139,19 +156,18 @@ __global__ __launch_bounds__(ENT) void explicit_kernel(FsGeo g, FsCoef cf, const
             if (!g.py && (jj <= 0 || jj >= ny)) return 0.0;
             return L(1, dk, dj, di);
         };
-        if (i < nx && j < ny) {
+        if (crow) {
             const size_t o = ((size_t)k * ny + j) * nx + i;
             const bool hn = g.py || j + 1 < ny;   // a cell row above (else the wall)
             const bool hs = g.py || j > 0;        // a cell row below
-            const double D = g.dyc[j];
             // y part of the Laplacian of a cell-height field at row j
             // (mirror ghost at a wall; fluxes over delta, delta_0 = delta_ny
             // across the periodic wrap)
             auto lapy = [&](int f) {
                 const double fc = L(f, 0, 0, 0);
-                const double fu = hn ? (L(f, 0, 1, 0) - fc) / g.dyf[j + 1] : -fc / (0.5 * D);
-                const double fl = hs ? (fc - L(f, 0, -1, 0)) / g.dyf[j] : fc / (0.5 * D);
-                return (fu - fl) / D;
+                const double fu = hn ? (L(f, 0, 1, 0) - fc) * idn : -fc * i2D;
+                const double fl = hs ? (fc - L(f, 0, -1, 0)) * ids : fc * i2D;
+                return (fu - fl) * iD;
             };
             // ---- u at x-face (i, j, k)
             {
@@ -164,13 +180,13 @@ __global__ __launch_bounds__(ENT) void explicit_kernel(FsGeo g, FsCoef cf, const
                 // y fluxes v u on the faces j (below) and j+1 (above) at x-face i
                 const double fb = hs ? 0.5 * (V(0, 0, 0) + V(0, 0, -1)) * 0.5 * (L(0, 0, -1, 0) + uc) : 0.0;
                 const double ft = hn ? 0.5 * (V(0, 1, 0) + V(0, 1, -1)) * 0.5 * (uc + L(0, 0, 1, 0)) : 0.0;
-                const double dyy = (ft - fb) / D;
+                const double dyy = (ft - fb) * iD;
                 const double zb = 0.5 * (L(2, 0, 0, 0) + L(2, 0, 0, -1)) * 0.5 * (L(0, -1, 0, 0) + uc);
                 const double zt = 0.5 * (L(2, 1, 0, 0) + L(2, 1, 0, -1)) * 0.5 * (uc + L(0, 1, 0, 0));
                 const double N = dxx + dyy + (zt - zb) * ihz;
                 double e = uc + cf.dt * (vis * lap - cf.ab * gp - cf.gam * N);
                 if (zprev) e -= cf.dt * cf.zet * nu_prev[o];
-                ue[o] = e;
+                if (keep_ue) ue[o] = e;
                 ru[o] = e - cf.c * lap;
                 nu_out[o] = N;
             }
@@ -184,13 +200,13 @@ __global__ __launch_bounds__(ENT) void explicit_kernel(FsGeo g, FsCoef cf, const
                 const double dzz = (c1 * c1 - c0 * c0) * ihz;
                 const double fb = hs ? 0.5 * (V(0, 0, 0) + V(-1, 0, 0)) * 0.5 * (L(2, 0, -1, 0) + wc) : 0.0;
                 const double ft = hn ? 0.5 * (V(0, 1, 0) + V(-1, 1, 0)) * 0.5 * (wc + L(2, 0, 1, 0)) : 0.0;
-                const double dyy = (ft - fb) / D;
+                const double dyy = (ft - fb) * iD;
                 const double xb = 0.5 * (L(0, 0, 0, 0) + L(0, -1, 0, 0)) * 0.5 * (L(2, 0, 0, -1) + wc);
                 const double xt = 0.5 * (L(0, 0, 0, 1) + L(0, -1, 0, 1)) * 0.5 * (wc + L(2, 0, 0, 1));
                 const double N = (xt - xb) * ihx + dyy + dzz;
                 double e = wc + cf.dt * (vis * lap - cf.ab * gp - cf.gam * N);
                 if (zprev) e -= cf.dt * cf.zet * nw_prev[o];
-                we[o] = e;
+                if (keep_ue) we[o] = e;
                 rw[o] = e - cf.c * lap;
                 nw_out[o] = N;
             }
@@ -199,19 +215,17 @@ __global__ __launch_bounds__(ENT) void explicit_kernel(FsGeo g, FsCoef cf, const
         if (i < nx && j < vr) {
             const size_t o = ((size_t)k * vr + j) * nx + i;
             if (!g.py && (j == 0 || j == ny)) {   // wall faces
-                ve[o] = 0.0;
+                if (keep_ue) ve[o] = 0.0;
                 rv[o] = 0.0;
                 nv_out[o] = 0.0;
             } else {
-                const int jm = j > 0 ? j - 1 : ny - 1;   // cell below the face (wraps when periodic)
                 const double vc = V(0, 0, 0);
-                const double d = g.dyf[j];
-                const double lapy = ((V(0, 1, 0) - vc) / g.dyc[j] - (vc - V(0, -1, 0)) / g.dyc[jm]) / d;
+                const double lapy = ((V(0, 1, 0) - vc) * ifa - (vc - V(0, -1, 0)) * ifb) * ifd;
                 const double lap = (V(0, 0, 1) - 2.0 * vc + V(0, 0, -1)) * ihx * ihx +
                                    (V(1, 0, 0) - 2.0 * vc + V(-1, 0, 0)) * ihz * ihz + lapy;
-                const double gp = (L(3, 0, 0, 0) - L(3, 0, -1, 0)) / d;
+                const double gp = (L(3, 0, 0, 0) - L(3, 0, -1, 0)) * ifd;
                 const double c1 = 0.5 * (vc + V(0, 1, 0)), c0 = 0.5 * (V(0, -1, 0) + vc);
-                const double dyy = (c1 * c1 - c0 * c0) / d;
+                const double dyy = (c1 * c1 - c0 * c0) * ifd;
                 // x fluxes u v on the x-faces i and i+1 at y-face j
                 const double xb = 0.5 * (L(0, 0, -1, 0) + L(0, 0, 0, 0)) * 0.5 * (vc + V(0, 0, -1));
                 const double xt = 0.5 * (L(0, 0, -1, 1) + L(0, 0, 0, 1)) * 0.5 * (V(0, 0, 1) + vc);
@@ -220,7 +234,7 @@ __global__ __launch_bounds__(ENT) void explicit_kernel(FsGeo g, FsCoef cf, const
                 const double N = (xt - xb) * ihx + dyy + (zt - zb) * ihz;
                 double e = vc + cf.dt * (vis * lap - cf.ab * gp - cf.gam * N);
                 if (zprev) e -= cf.dt * cf.zet * nv_prev[o];
-                ve[o] = e;
+                if (keep_ue) ve[o] = e;
                 rv[o] = e - cf.c * lap;
                 nv_out[o] = N;
             }
@@ -324,7 +338,7 @@ hipError_t launch_explicit(const Plan &p, const FsStage &s, hipStream_t st)
     const int ntile = ((p.nx + ETX - 1) / ETX) * ((vr + ETY - 1) / ETY) * (p.nz / EKZ);
     dim3 grid(8 * ((ntile + 7) / 8));   // a whole number of blocks per XCD
     hipLaunchKernelGGL(explicit_kernel, grid, dim3(ENT), 0, st, g, cf, s.u, s.v, s.w, s.p, s.nu, s.nv, s.nw,
-                       s.ue, s.ve, s.we, s.ru, s.rv, s.rw, s.nu, s.nv, s.nw);
+                       s.ue, s.ve, s.we, s.ru, s.rv, s.rw, s.nu, s.nv, s.nw, s.nmarkers > 0 ? 1 : 0);
     return hipGetLastError();
 }
 
