@@ -95,7 +95,7 @@ class _CGeom(ctypes.Structure):
                 ("hx", ctypes.c_double), ("hz", ctypes.c_double),
                 ("dyc", ctypes.POINTER(ctypes.c_double)),
                 ("dyf", ctypes.POINTER(ctypes.c_double)),
-                ("py", ctypes.c_int), ("wx", ctypes.c_int)]
+                ("py", ctypes.c_int), ("wx", ctypes.c_int), ("wz", ctypes.c_int)]
 
 
 class _CInfo(ctypes.Structure):
@@ -115,7 +115,8 @@ class Grid:
     at x = 0 and x = lx (the paper's non-periodic direction, Section 3.2):
     u Dirichlet (zero on the wall faces; slot 0 of u is the wall face x = 0,
     the face x = lx is not stored), v and w Dirichlet through a mirror ghost,
-    the pressure homogeneous Neumann."""
+    the pressure homogeneous Neumann.  periodic_z=False: the same walls at
+    z = 0 and z = lz (w's plane 0 is the wall face z = 0)."""
     nx: int
     ny: int
     nz: int
@@ -126,6 +127,7 @@ class Grid:
     yf_in: np.ndarray | None = None
     periodic_y: bool = False
     periodic_x: bool = True
+    periodic_z: bool = True
     yf: np.ndarray = field(init=False)
     yc: np.ndarray = field(init=False)
     dyc: np.ndarray = field(init=False)
@@ -152,9 +154,11 @@ class Grid:
             self.dyf[0] = self.dyf[ny] = 0.5 * (self.dyc[0] + self.dyc[ny - 1])
         self._c = _CGeom(self.nx, self.ny, self.nz, self.hx, self.hz,
                          _dp(self.dyc), _dp(self.dyf), 1 if self.periodic_y else 0,
-                         0 if self.periodic_x else 1)
+                         0 if self.periodic_x else 1, 0 if self.periodic_z else 1)
         if not self.periodic_x and self.nx < 3:
             raise ValueError("walls in x need nx >= 3")
+        if not self.periodic_z and self.nz < 3:
+            raise ValueError("walls in z need nz >= 3")
 
     @property
     def hx(self) -> float:
@@ -219,6 +223,8 @@ def unknowns_of(g: Grid, op: int, x: np.ndarray) -> np.ndarray:
         return np.ascontiguousarray(x[:, 1:g.ny, :]).reshape(-1)
     if op == OP_U and not g.periodic_x:
         return np.ascontiguousarray(x[:, :, 1:]).reshape(-1)
+    if op == OP_W and not g.periodic_z:
+        return np.ascontiguousarray(x[1:, :, :]).reshape(-1)
     return np.ascontiguousarray(x).reshape(-1)
 
 

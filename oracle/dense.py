@@ -20,7 +20,9 @@ differences on a staggered grid) and Appendix B (wall rows):
   The u slots are faces 0..nx-1 with slot 0 the wall face (a zero column
   of D_x, a zero row of G_x) and the face nx absent (zero), so L_p = D G
   is again literal; u takes G_x D_x on the interior faces 1..nx-1, and v,
-  w the mirror-ghost rows in x, as u and w have at the y walls.
+  w the mirror-ghost rows in x, as u and w have at the y walls;
+* walls in z (``periodic_z=False``): the same along z, w's plane 0 being
+  the wall face.
 
 The dense solve uses ``numpy.linalg.solve``.  For the singular Neumann
 pressure problem it solves the bordered system
@@ -154,7 +156,8 @@ def divergence_matrix(g: Grid) -> np.ndarray:
     Dx = _circ_diff_fwd(g.nx, g.hx) if g.periodic_x else dx_faces_to_cells_walls(g.nx, g.hx)
     Du = _k3(Iz, Iy, Dx)
     Dv = _k3(Iz, dy_faces_to_cells_periodic(g) if g.periodic_y else dy_faces_to_cells(g), Ix)
-    Dw = _k3(_circ_diff_fwd(g.nz, g.hz), Iy, Ix)
+    Dz = _circ_diff_fwd(g.nz, g.hz) if g.periodic_z else dx_faces_to_cells_walls(g.nz, g.hz)
+    Dw = _k3(Dz, Iy, Ix)
     return np.hstack([Du, Dv, Dw])
 
 
@@ -164,7 +167,8 @@ def gradient_matrix(g: Grid) -> np.ndarray:
     Gx = _circ_diff_bwd(g.nx, g.hx) if g.periodic_x else gx_cells_to_faces_walls(g.nx, g.hx)
     Gu = _k3(Iz, Iy, Gx)
     Gv = _k3(Iz, gy_cells_to_faces_periodic(g) if g.periodic_y else gy_cells_to_faces_neumann(g), Ix)
-    Gw = _k3(_circ_diff_bwd(g.nz, g.hz), Iy, Ix)
+    Gz = _circ_diff_bwd(g.nz, g.hz) if g.periodic_z else gx_cells_to_faces_walls(g.nz, g.hz)
+    Gw = _k3(Gz, Iy, Ix)
     return np.vstack([Gu, Gv, Gw])
 
 
@@ -181,7 +185,14 @@ def laplacian(g: Grid, op: int) -> np.ndarray:
         Ix = np.eye(g.nx - 1)
     else:
         Lx = lx_mirror_walls(g.nx, g.hx)
-    Lz = _circ_diff_bwd(g.nz, g.hz) @ _circ_diff_fwd(g.nz, g.hz)
+    if g.periodic_z:
+        Lz = _circ_diff_bwd(g.nz, g.hz) @ _circ_diff_fwd(g.nz, g.hz)
+    elif op == OP_W:
+        full = gx_cells_to_faces_walls(g.nz, g.hz) @ dx_faces_to_cells_walls(g.nz, g.hz)
+        Lz = full[1:, 1:]
+        Iz = np.eye(g.nz - 1)
+    else:
+        Lz = lx_mirror_walls(g.nz, g.hz)
     if g.periodic_y:
         Iy = np.eye(g.ny)
         if op in (OP_U, OP_W):
@@ -204,6 +215,7 @@ def laplacian(g: Grid, op: int) -> np.ndarray:
 
 def weights(g: Grid, op: int) -> np.ndarray:
     nxu = g.nx - 1 if (op == OP_U and not g.periodic_x) else g.nx
+    nzu = g.nz - 1 if (op == OP_W and not g.periodic_z) else g.nz
     if op == OP_V and g.periodic_y:
         wy = g.dyf[:g.ny]
         nyu = g.ny
@@ -213,7 +225,7 @@ def weights(g: Grid, op: int) -> np.ndarray:
     else:
         wy = g.dyc
         nyu = g.ny
-    return np.broadcast_to((g.hx * g.hz * wy)[None, :, None], (g.nz, nyu, nxu)).reshape(-1).copy()
+    return np.broadcast_to((g.hx * g.hz * wy)[None, :, None], (nzu, nyu, nxu)).reshape(-1).copy()
 
 
 def operator(g: Grid, op: int, c: float = 0.0) -> np.ndarray:
@@ -227,10 +239,13 @@ def solve(g: Grid, op: int, b: np.ndarray, c: float = 0.0) -> np.ndarray:
     """Dense solve; b and the result in the full array layout."""
     walls = op == OP_V and not g.periodic_y
     xwalls = op == OP_U and not g.periodic_x
+    zwalls = op == OP_W and not g.periodic_z
     if walls:
         rhs = np.ascontiguousarray(b[:, 1:g.ny, :]).reshape(-1)
     elif xwalls:
         rhs = np.ascontiguousarray(b[:, :, 1:]).reshape(-1)
+    elif zwalls:
+        rhs = np.ascontiguousarray(b[1:, :, :]).reshape(-1)
     else:
         rhs = np.ascontiguousarray(b).reshape(-1)
     A = operator(g, op, c)
@@ -249,6 +264,8 @@ def solve(g: Grid, op: int, b: np.ndarray, c: float = 0.0) -> np.ndarray:
         out[:, 1:g.ny, :] = sol.reshape(g.nz, g.ny - 1, g.nx)
     elif xwalls:
         out[:, :, 1:] = sol.reshape(g.nz, g.ny, g.nx - 1)
+    elif zwalls:
+        out[1:, :, :] = sol.reshape(g.nz - 1, g.ny, g.nx)
     else:
         out[...] = sol.reshape(g.shape(op))
     return out

@@ -50,6 +50,9 @@
  * 1..nx-1.  v and w (cell centres in x) take the mirror-ghost Dirichlet
  * row, as u and w do at the y walls; the pressure takes homogeneous Neumann
  * (zero flux through the walls), so its null mode is again the constant.
+ * Walls in z (flag wz) are the same construction along z: w's plane k holds
+ * the face z = k hz, plane 0 being the wall face (unknowns: planes
+ * 1..nz-1); u and v take the mirror-ghost row, the pressure zero flux.
  *
  * Operator codes: 0 = pressure Poisson (A = L_p), 1 = u Helmholtz,
  * 2 = v Helmholtz, 3 = w Helmholtz (A = I - c L).
@@ -75,6 +78,8 @@ typedef struct {
                        /*    walls, v has ny faces [nz][ny][nx]         */
     int wx;            /* 1: walls at x = 0 and x = lx instead of the   */
                        /*    periodic x (see the header comment)        */
+    int wz;            /* 1: walls at z = 0 and z = lz, the same way    */
+                       /*    (w's plane 0 is the wall face z = 0)       */
 } orc_geom;
 
 typedef struct {
@@ -148,9 +153,12 @@ void orc_divergence(const orc_geom *g, const double *u, const double *v,
                 double ue = (g->wx && i + 1 == g->nx) ? 0.0 : u[cidx(g, wrap(i + 1, g->nx), j, k)];
                 double uw = (g->wx && i == 0) ? 0.0 : u[cidx(g, i, j, k)];
                 double du = (ue - uw) / g->hx;
+                /* z walls: w = 0 on the wall faces 0 and nz */
+                double wt = (g->wz && k + 1 == g->nz) ? 0.0 : w[cidx(g, i, j, wrap(k + 1, g->nz))];
+                double wb = (g->wz && k == 0) ? 0.0 : w[cidx(g, i, j, k)];
                 int jt = (g->py && j + 1 == g->ny) ? 0 : j + 1;   /* face ny = face 0 */
                 double dv = (v[vidx(g, i, jt, k)] - v[vidx(g, i, j, k)]) / g->dyc[j];
-                double dw = (w[cidx(g, i, j, wrap(k + 1, g->nz))] - w[cidx(g, i, j, k)]) / g->hz;
+                double dw = (wt - wb) / g->hz;
                 b[cidx(g, i, j, k)] = scale * (du + dv + dw);
             }
 }
@@ -171,7 +179,7 @@ void orc_gradient(const orc_geom *g, const double *phi, double *gu, double *gv,
                      * ny-1 and 0, dyf[0] apart */
                     gu[cidx(g, i, j, k)] = (g->wx && i == 0) ? 0.0 :
                         (phi[cidx(g, i, j, k)] - phi[cidx(g, wrap(i - 1, g->nx), j, k)]) / g->hx;
-                    gw[cidx(g, i, j, k)] =
+                    gw[cidx(g, i, j, k)] = (g->wz && k == 0) ? 0.0 :
                         (phi[cidx(g, i, j, k)] - phi[cidx(g, i, j, wrap(k - 1, g->nz))]) / g->hz;
                     gv[vidx(g, i, j, k)] =
                         (phi[cidx(g, i, j, k)] - phi[cidx(g, i, wrap(j - 1, g->ny), k)]) / g->dyf[j];
@@ -180,7 +188,7 @@ void orc_gradient(const orc_geom *g, const double *phi, double *gu, double *gv,
                 if (j < g->ny) {
                     gu[cidx(g, i, j, k)] = (g->wx && i == 0) ? 0.0 :
                         (phi[cidx(g, i, j, k)] - phi[cidx(g, wrap(i - 1, g->nx), j, k)]) / g->hx;
-                    gw[cidx(g, i, j, k)] =
+                    gw[cidx(g, i, j, k)] = (g->wz && k == 0) ? 0.0 :
                         (phi[cidx(g, i, j, k)] - phi[cidx(g, i, j, wrap(k - 1, g->nz))]) / g->hz;
                 }
                 if (j == 0 || j == g->ny)
@@ -208,9 +216,15 @@ static int nx_unknowns(const orc_geom *g, int op)
     return (op == 1 && g->wx) ? g->nx - 1 : g->nx;
 }
 static int first_x(const orc_geom *g, int op) { return (op == 1 && g->wx) ? 1 : 0; }
+/* z planes of unknowns: w has the interior faces 1..nz-1 with z walls */
+static int nz_unknowns(const orc_geom *g, int op)
+{
+    return (op == 3 && g->wz) ? g->nz - 1 : g->nz;
+}
+static int first_z(const orc_geom *g, int op) { return (op == 3 && g->wz) ? 1 : 0; }
 static int64_t n_unknowns(const orc_geom *g, int op)
 {
-    return (int64_t)nx_unknowns(g, op) * ny_unknowns(g, op) * g->nz;
+    return (int64_t)nx_unknowns(g, op) * ny_unknowns(g, op) * nz_unknowns(g, op);
 }
 /* (i, j, k) of unknown number r; for op 2 with walls, j is the face index
  * 1..ny-1; for op 1 with x walls, i is the face index 1..nx-1 */
@@ -221,13 +235,13 @@ static void unknown_ijk(const orc_geom *g, int op, int64_t r, int *i, int *j,
     *i = (int)(r % nxu) + first_x(g, op);
     int64_t t = r / nxu;
     *j = (int)(t % nyu) + first_y(g, op);
-    *k = (int)(t / nyu);
+    *k = (int)(t / nyu) + first_z(g, op);
 }
 static int64_t unknown_id(const orc_geom *g, int op, int i, int j, int k)
 {
     int nyu = ny_unknowns(g, op), nxu = nx_unknowns(g, op);
-    int jj = j - first_y(g, op), ii = i - first_x(g, op);
-    return ((int64_t)k * nyu + jj) * nxu + ii;
+    int jj = j - first_y(g, op), ii = i - first_x(g, op), kk = k - first_z(g, op);
+    return ((int64_t)kk * nyu + jj) * nxu + ii;
 }
 /* position of unknown r in the caller's full array layout */
 static int64_t unknown_to_array(const orc_geom *g, int op, int64_t r)
@@ -264,8 +278,28 @@ static int laplacian_row(const orc_geom *g, int op, int i, int j, int k,
     int n = 0;
     const double ax = 1.0 / (g->hx * g->hx), az = 1.0 / (g->hz * g->hz);
     int64_t me = unknown_id(g, op, i, j, k);
-    /* periodic z: (f_{k+1} - 2 f_k + f_{k-1}) / h^2 */
-    n = add_entry(cols, vals, n, me, -2.0 * az);
+    if (!g->wz) { /* periodic z: (f_{k+1} - 2 f_k + f_{k-1}) / h^2 */
+        n = add_entry(cols, vals, n, me, -2.0 * az);
+        n = add_entry(cols, vals, n, unknown_id(g, op, i, j, wrap(k - 1, g->nz)), az);
+        n = add_entry(cols, vals, n, unknown_id(g, op, i, j, wrap(k + 1, g->nz)), az);
+    } else if (op == 3) { /* z faces 1..nz-1, wall values w_0 = w_nz = 0 */
+        n = add_entry(cols, vals, n, me, -2.0 * az);
+        if (k + 1 <= g->nz - 1) n = add_entry(cols, vals, n, unknown_id(g, op, i, j, k + 1), az);
+        if (k - 1 >= 1) n = add_entry(cols, vals, n, unknown_id(g, op, i, j, k - 1), az);
+    } else { /* cell centres in z: Neumann (pressure) or mirror ghost (u, v) */
+        if (k + 1 < g->nz) {
+            n = add_entry(cols, vals, n, me, -az);
+            n = add_entry(cols, vals, n, unknown_id(g, op, i, j, k + 1), az);
+        } else if (op != 0) {
+            n = add_entry(cols, vals, n, me, -2.0 * az);
+        }
+        if (k > 0) {
+            n = add_entry(cols, vals, n, me, -az);
+            n = add_entry(cols, vals, n, unknown_id(g, op, i, j, k - 1), az);
+        } else if (op != 0) {
+            n = add_entry(cols, vals, n, me, -2.0 * az);
+        }
+    }
     if (!g->wx) { /* periodic x: the same */
         n = add_entry(cols, vals, n, me, -2.0 * ax);
         n = add_entry(cols, vals, n, unknown_id(g, op, wrap(i - 1, g->nx), j, k), ax);
@@ -289,8 +323,6 @@ static int laplacian_row(const orc_geom *g, int op, int i, int j, int k,
             n = add_entry(cols, vals, n, me, -2.0 * ax);
         }
     }
-    n = add_entry(cols, vals, n, unknown_id(g, op, i, j, wrap(k - 1, g->nz)), az);
-    n = add_entry(cols, vals, n, unknown_id(g, op, i, j, wrap(k + 1, g->nz)), az);
     const int ny = g->ny;
     if (g->py) {
         /* periodic y: the same interior formulas everywhere, neighbours
@@ -412,7 +444,21 @@ static long double flux_apply_bc_ld(const orc_geom *g, int op, int i, int j, int
     long double hx = g->hx, hz = g->hz;
     int64_t (*at)(const orc_geom *, int, int, int) = (op == 2) ? vidx : cidx;
     long double xc = x[at(g, i, j, k)];
-    long double xt = x[at(g, i, j, wrap(k + 1, nz))], xb = x[at(g, i, j, wrap(k - 1, nz))];
+    long double ft, fb;   /* z fluxes through the top and bottom sides */
+    if (!g->wz) {
+        ft = ((long double)x[at(g, i, j, wrap(k + 1, nz))] - xc) / hz;
+        fb = (xc - (long double)x[at(g, i, j, wrap(k - 1, nz))]) / hz;
+    } else if (op == 3) { /* faces: wall values w_0 = w_nz = 0 */
+        long double xt = (k + 1 <= nz - 1) ? (long double)x[at(g, i, j, k + 1)] : 0.0L;
+        long double xb = (k - 1 >= 1) ? (long double)x[at(g, i, j, k - 1)] : 0.0L;
+        ft = (xt - xc) / hz;
+        fb = (xc - xb) / hz;
+    } else { /* cells: Neumann (pressure) or mirror ghost (u, v) at a wall */
+        ft = (k + 1 < nz) ? ((long double)x[at(g, i, j, k + 1)] - xc) / hz
+                          : (op == 0 ? 0.0L : -xc / (hz / 2.0L));
+        fb = (k > 0) ? (xc - (long double)x[at(g, i, j, k - 1)]) / hz
+                     : (op == 0 ? 0.0L : xc / (hz / 2.0L));
+    }
     long double fe, fw;   /* x fluxes through the east and west sides */
     if (!g->wx) {
         fe = ((long double)x[at(g, wrap(i + 1, nx), j, k)] - xc) / hx;
@@ -428,7 +474,7 @@ static long double flux_apply_bc_ld(const orc_geom *g, int op, int i, int j, int
         fw = (i > 0) ? (xc - (long double)x[at(g, i - 1, j, k)]) / hx
                      : (op == 0 ? 0.0L : xc / (hx / 2.0L));
     }
-    long double lap = (fe - fw) / hx + ((xt - xc) / hz - (xc - xb) / hz) / hz;
+    long double lap = (fe - fw) / hx + (ft - fb) / hz;
     if (g->py) {
         int jn = wrap(j + 1, ny), js = wrap(j - 1, ny);
         long double xn = x[at(g, i, jn, k)], xs = x[at(g, i, js, k)];
@@ -501,6 +547,10 @@ void orc_residual_bc_ld(const orc_geom *g, int op, double c, const double *x,
     if (op == 1 && g->wx) { /* the wall face x = 0 */
         for (int k = 0; k < g->nz; ++k)
             for (int j = 0; j < g->ny; ++j) r[cidx(g, 0, j, k)] = 0.0;
+    }
+    if (op == 3 && g->wz) { /* the wall face z = 0 */
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) r[cidx(g, i, j, 0)] = 0.0;
     }
     if (norms) {
         norms[0] = sqrt((double)rr);
