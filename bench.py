@@ -313,6 +313,9 @@ def main():
         log("config xw")
         rx, wx = run_xw(10, 2)
         configs["x_walls"] = {"workload": wx, "steps": 10, "warmup": 2, "unit": "Mcell-solves/s", **rx}
+        log("config duct")
+        rd, wd = run_xw(10, 2, walls_z=True)
+        configs["duct"] = {"workload": wd, "steps": 10, "warmup": 2, "unit": "Mcell-solves/s", **rd}
         log("config rk3")
         rr, wr = run_rk3(5, 1)
         configs["rk3_step"] = {"workload": wr, "steps": 5, "warmup": 1,
@@ -559,23 +562,26 @@ def run_3p(steps, warmup, n=256):
     return res, f"{n}^3 uniform, periodic in x, y and z, N(0,1) filtered to k <= 16, c = {c:.4e}"
 
 
-def run_xw(steps, warmup, n=256, beta=2.0):
+def run_xw(steps, warmup, n=256, beta=2.0, walls_z=False):
     """Walls in x (Dirichlet velocity, Neumann pressure at x = 0 and x = lx;
-    unfolded cosine/sine transforms in x) at n^3 with tanh-stretched walls
-    in y, both paths: one step of 3 Helmholtz + divergence + Poisson +
-    correction on N(0,1) velocities."""
+    unfolded cosine/sine transforms in x), and in z too when walls_z (a
+    duct), at n^3 with tanh-stretched walls in y, both paths: one step of 3
+    Helmholtz + divergence + Poisson + correction on N(0,1) velocities."""
     import torch
     from paper_2406_19920_amd import ibsolve as ibs
     dev = torch.device("cuda:0")
-    log(f"inputs {n}^3 walls in x")
+    log(f"inputs {n}^3 walls in x" + (" and z" if walls_z else ""))
     u, v, w = make_inputs(n, beta, seed=12)
     u[:, :, 0] = 0.0
+    if walls_z:
+        w[0] = 0.0
+    kwz = {"bc_z": ibs.IBS_DIRICHLET} if walls_z else {}
     c = 0.125 * h_min(n, beta) ** 2
     ru, rv, rw = (torch.from_numpy(a).to(dev) for a in (u, v, w))
     res = {}
     for path, prec in (("refined", ibs.IBS_REFINED_BF16X3), ("fp64", ibs.IBS_FP64)):
         kw = {"max_iter": 2} if prec != ibs.IBS_FP64 else {}
-        S = ibs.Solver(n, n, n, beta=beta, precision=prec, bc_x=ibs.IBS_DIRICHLET, **kw)
+        S = ibs.Solver(n, n, n, beta=beta, precision=prec, bc_x=ibs.IBS_DIRICHLET, **kw, **kwz)
         tiles = S.autotune() if prec == ibs.IBS_FP64 else None   # set-up, untimed
         xu, xv, xw = S.empty(1), S.empty(2), S.empty(3)
         b, phi = S.empty(0), S.empty(0)
@@ -600,8 +606,9 @@ def run_xw(steps, warmup, n=256, beta=2.0):
                                 "poisson": S.read_info(0).iters},
                      "tiles": tiles}
         S.close()
-    return res, (f"{n}^3, walls in x (uniform) and y (tanh beta={beta}), periodic z, "
-                 f"N(0,1) rhs, c = {c:.4e}")
+    walls = "walls in x and z (uniform) and y" if walls_z else "walls in x (uniform) and y"
+    return res, (f"{n}^3, {walls} (tanh beta={beta})" + ("" if walls_z else ", periodic z")
+                 + f", N(0,1) rhs, c = {c:.4e}")
 
 
 def run_rk3(steps, warmup, n=256):

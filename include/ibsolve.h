@@ -80,8 +80,8 @@ typedef enum { IBS_PERIODIC = 0, IBS_DIRICHLET = 1, IBS_NEUMANN = 2 } ibs_bc;
  * hx = lx/nx, hz = lz/nz; y faces y_f[j] = (ly/2)(1 + tanh(beta(2j/ny-1))/
  * tanh(beta)), j = 0..ny (beta = 0: uniform), unless y_faces is given.
  * Supported: nx, nz multiples of 16 in [16, 1024] (refined path: multiples
- * of 32, at most 512); ny in [2, 768]; bc_z = IBS_PERIODIC; bc_x =
- * IBS_PERIODIC or IBS_DIRICHLET (walls in x, below); and in y
+ * of 32, at most 512); ny in [2, 768]; bc_x and bc_z each IBS_PERIODIC or
+ * IBS_DIRICHLET (walls, below); and in y
  * either walls (bc_y_vel = IBS_DIRICHLET, bc_y_p = IBS_NEUMANN) or
  * periodic y (bc_y_vel = bc_y_p = IBS_PERIODIC: the triply periodic
  * branch of Section 2.3.3, items S1/S2; ny in {48, 64, 80, 96, 128, 160,
@@ -100,7 +100,11 @@ typedef enum { IBS_PERIODIC = 0, IBS_DIRICHLET = 1, IBS_NEUMANN = 2 } ibs_bc;
  * take the mirror-ghost Dirichlet row at the walls, the pressure zero flux.
  * The x transforms are then the cosine (pressure), sine-on-centres (v, w)
  * and sine-on-faces (u) eigenbases of the wall-bounded x operators, as
- * plain (unfolded) matrix products; ibs_rk_stage() is not served. */
+ * plain (unfolded) matrix products; ibs_rk_stage() is not served.
+ * Walls in z (bc_z = IBS_DIRICHLET) are the same along z, w being the
+ * face-normal component: w's plane 0 is the wall face z = 0 (ignored on
+ * input, zero on output), the face z = lz is not stored; u and v take the
+ * mirror-ghost row.  Walls in x and z together make a duct. */
 typedef struct {
     int32_t nx, ny, nz;
     double lx, ly, lz;        /* <= 0 means 1                                */
@@ -363,7 +367,9 @@ ibs_status ibs_batch_destroy(ibs_batch batch);
  * and 1 hold the cyclic cell operator; lower[0] and upper[ny-1] are then
  * the corner couplings (row 0 to row ny-1 and back).  Tables 1 and 3 are
  * the pressure's x basis; with walls in x, 17 and 18 are Q_x of v/w and of
- * u, 19 and 20 their lambda_x (periodic x: the same as 1 and 3).
+ * u, 19 and 20 their lambda_x (periodic x: the same as 1 and 3); with walls
+ * in z, 21 and 22 are Q_z of u/v and of w, 23 and 24 their lambda_z
+ * (periodic z: the same as 2 and 4).
  * out: host array of n doubles; n must equal the table length (queried by
  * passing out = NULL, which returns the length through *n). */
 ibs_status ibs_plan_export(ibs_plan plan, int32_t table, double *out, size_t *n);

@@ -174,7 +174,7 @@ static ibs_status run_fp64_pipeline_multi(Plan &p, JobSet js, double *const *W, 
     hipError_t e;
     const double cells = total_cells(js, p);
     // matrix-core flops per cell: 2n for the plain transform, n folded
-    const bool fx = x_folds(p), fz = can_fold(p.nz);
+    const bool fx = x_folds(p), fz = z_folds(p);
     const double xflop = (fx ? 1.0 : 2.0) * p.nx * cells, zflop = (fz ? 1.0 : 2.0) * p.nz * cells;
     const double rw = 16.0 * cells;
     const double *xb_f[NUM_XK], *xb_i[NUM_XK];
@@ -182,7 +182,11 @@ static ibs_status run_fp64_pipeline_multi(Plan &p, JobSet js, double *const *W, 
         xb_f[k] = blob_ptr(p, p.lay.bx_fwd[k]);
         xb_i[k] = blob_ptr(p, p.lay.bx_inv[k]);
     }
-    const double *za_f = blob_ptr(p, p.lay.az_fwd), *za_i = blob_ptr(p, p.lay.az_inv);
+    const double *za_f[NUM_XK], *za_i[NUM_XK];
+    for (int k = 0; k < NUM_XK; ++k) {
+        za_f[k] = blob_ptr(p, p.lay.az_fwd[k]);
+        za_i[k] = blob_ptr(p, p.lay.az_inv[k]);
+    }
     auto xform = [&](bool inverse) {
         return fx ? launch_xfold_f64(js, p, inverse, s)
                   : launch_xgemm_f64(js, p.nz, p.nx, p.nx, inverse ? xb_i : xb_f, s);
@@ -244,7 +248,7 @@ static ibs_status run_refined(Plan &p, SplitSet ss, float *const *W1, float *con
     for (int q = 0; q < ss.n; ++q) cells += (double)p.nz * ss.j[q].rows * p.nx;
     // algorithmic flops per cell: 2n for the plain transform, n folded
     const double xfl = (x_folds_split(p) ? 1.0 : 2.0) * p.nx * cells;
-    const double zfl = (can_fold_split(p.nz) ? 1.0 : 2.0) * p.nz * cells;
+    const double zfl = (z_folds_split(p) ? 1.0 : 2.0) * p.nz * cells;
     JobSet js{};
     js.n = ss.n;
     void *info[4];
@@ -255,6 +259,7 @@ static ibs_status run_refined(Plan &p, SplitSet ss, float *const *W1, float *con
         js.j[q].rows = ss.j[q].rows;
         js.j[q].kind = ss.j[q].kind;
         js.j[q].xk = ss.j[q].xk;
+        js.j[q].zk = ss.j[q].zk;
         js.j[q].c = ss.j[q].c;
     }
     // With a second pass to come, the first iterate is only FP32-accurate
@@ -407,6 +412,7 @@ ibs_status solve_poisson(ibs_plan plan, const double *b, double *phi, void *work
         ss.j[0].rows = p.ny;
         ss.j[0].kind = KIND_P;
         ss.j[0].xk = XK_P;
+        ss.j[0].zk = XK_P;
         ss.j[0].op = IBS_OP_POISSON;
         ss.j[0].c = 0.0;
         ss.j[0].info = info;
@@ -452,6 +458,7 @@ ibs_status solve_helmholtz_batch(ibs_plan plan, int32_t ncomp, const int32_t *co
         js.j[q].rows = comp_rows(p, comp[q]);
         js.j[q].kind = comp_kind(p, comp[q]);
         js.j[q].xk = comp_xkind(p, comp[q]);
+        js.j[q].zk = comp_zkind(p, comp[q]);
         js.j[q].c = c[q];
         js.j[q].info = info ? info + q : nullptr;
     }
@@ -468,6 +475,7 @@ ibs_status solve_helmholtz_batch(ibs_plan plan, int32_t ncomp, const int32_t *co
             ss.j[q].rows = js.j[q].rows;
             ss.j[q].kind = js.j[q].kind;
             ss.j[q].xk = js.j[q].xk;
+            ss.j[q].zk = js.j[q].zk;
             ss.j[q].op = comp[q] + 1;
             ss.j[q].c = c[q];
             ss.j[q].info = js.j[q].info;
@@ -596,8 +604,8 @@ ibs_status ibs_rk_stage(ibs_plan plan, const ibs_rk_coef *coef, const ibs_stage_
         set_error("coefficients must be finite with dt > 0, re > 0, beta >= 0 and alpha + beta > 0");
         return IBS_ERR_INVALID_ARG;
     }
-    if (p.wx) {
-        set_error("the Runge-Kutta stage is built for a periodic x (walls in x are served by the solves)");
+    if (p.wx || p.wz) {
+        set_error("the Runge-Kutta stage is built for periodic x and z (walls there are served by the solves)");
         return IBS_ERR_UNSUPPORTED;
     }
     const void *ptrs[] = {f->u, f->v, f->w, f->p, f->nu, f->nv, f->nw};
@@ -723,7 +731,7 @@ ibs_status ibs_autotune(ibs_plan plan, void *scratch, size_t scratch_bytes, int3
     }
     struct Knob { int id; bool applies; hipError_t (*launch)(const JobSet &, const Plan &, bool, hipStream_t); };
     const Knob knobs[NUM_TUNE] = {{TUNE_XFOLD, x_folds(p), launch_xfold_f64},
-                                  {TUNE_ZFOLD, can_fold(p.nz), launch_zfold_f64}};
+                                  {TUNE_ZFOLD, z_folds(p), launch_zfold_f64}};
     ibs_status st = IBS_OK;
     // candidates timed in interleaved rounds, each keeping its fastest
     // round, so that a transient slowdown of one measurement (clock ramp,
@@ -788,18 +796,20 @@ ibs_status ibs_plan_export(ibs_plan plan, int32_t table, double *out, size_t *n)
     switch (table) {
     case 0: v = &p.yf; break;
     case 1: v = &p.qx[XK_P]; break;
-    case 2: v = &p.qz; break;
+    case 2: v = &p.qz[XK_P]; break;
     case 3: v = &p.lam_x[XK_P]; break;
-    case 4: v = &p.lam_z; break;
+    case 4: v = &p.lam_z[XK_P]; break;
     default:
         if (table >= 5 && table < 5 + 3 * NUM_KINDS) {
             const int kd = (table - 5) / 3, which = (table - 5) % 3;
             v = which == 0 ? &p.lo[kd] : (which == 1 ? &p.di[kd] : &p.up[kd]);
-        } else if (table >= 5 + 3 * NUM_KINDS && table < 5 + 3 * NUM_KINDS + 4) {
-            // the x bases and eigenvalues of v/w (XK_C) and u (XK_F)
-            const int t = table - 5 - 3 * NUM_KINDS;
-            const int xk = (t % 2 == 0) ? XK_C : XK_F;
-            v = t < 2 ? &p.qx[xk] : &p.lam_x[xk];
+        } else if (table >= 5 + 3 * NUM_KINDS && table < 5 + 3 * NUM_KINDS + 8) {
+            // the x bases and eigenvalues of v/w (XK_C) and u (XK_F), then
+            // the z ones of u/v (XK_C) and w (XK_F)
+            const int t = (table - 5 - 3 * NUM_KINDS) % 4;
+            const bool zax = table - 5 - 3 * NUM_KINDS >= 4;
+            const int k = (t % 2 == 0) ? XK_C : XK_F;
+            v = t < 2 ? (zax ? &p.qz[k] : &p.qx[k]) : (zax ? &p.lam_z[k] : &p.lam_x[k]);
         }
     }
     if (!v) { set_error("unknown table"); return IBS_ERR_INVALID_ARG; }

@@ -28,23 +28,27 @@ enum { KIND_P = 0, KIND_C = 1, KIND_F = 2, KIND_PF = 3, NUM_KINDS = 4 };
 //   XK_F: u, x faces; slot 0 is the wall face x = 0 and face nx is not
 //         stored; the basis has a zero column 0 (and zero row 0), so the
 //         wall slot transforms to zero both ways (sine series on 1..nx-1)
+// Walls in z (bc_z = IBS_DIRICHLET) take the same three kinds along z, w
+// being the face-normal component (plane 0 the wall face z = 0).
 enum { XK_P = 0, XK_C = 1, XK_F = 2, NUM_XK = 3 };
 
 // Byte offsets of the tables inside the device constant blob.
 struct BlobLayout {
     size_t bx_fwd[NUM_XK], bx_inv[NUM_XK];   // x transform per x kind, B operand of C = A B,
                                              // swizzled (unfolded x: nx % 32 != 0 or walls)
-    size_t az_fwd, az_inv;   // z transform as A operand of C = A B, swizzled (nz % 32 != 0)
+    size_t az_fwd[NUM_XK], az_inv[NUM_XK];   // z transform per z kind, A operand of C = A B,
+                                             // swizzled (unfolded z: nz % 32 != 0 or walls)
     // folded transforms (n % 32 == 0): the two H x H factors (H = n/2)
     size_t fx_fwd_c, fx_fwd_s, fx_inv_c, fx_inv_s;   // B-operand swizzle
     size_t fz_fwd_c, fz_fwd_s, fz_inv_c, fz_inv_s;   // A-operand swizzle
-    size_t lam_x[NUM_XK], lam_z;   // eigenvalues (double), x per x kind
+    size_t lam_x[NUM_XK], lam_z[NUM_XK];   // eigenvalues (double) per x / z kind
     size_t lo[NUM_KINDS], di[NUM_KINDS], up[NUM_KINDS];  // y operator rows
     size_t wy;               // Delta_j (pressure weights), ny doubles
     size_t dyc, dyf;         // cell heights [ny], centre distances [ny+1]
     size_t sx_fwd[NUM_XK], sx_inv[NUM_XK];   // x transform per x kind, bf16x3 split, B-operand
                                              // swizzle (unfolded x: nx % 64 != 0 or walls)
-    size_t sz_fwd, sz_inv;   // z transform, bf16x3 split, A-operand swizzle (nz % 64 != 0)
+    size_t sz_fwd[NUM_XK], sz_inv[NUM_XK];   // z transform per z kind, bf16x3 split, A-operand
+                                             // swizzle (unfolded z: nz % 64 != 0 or walls)
     size_t sxf_fwd, sxf_inv; // folded x transform factors, bf16x3 split (nx % 64 == 0)
     size_t szf_fwd, szf_inv; // folded z transform factors, bf16x3 split (nz % 64 == 0)
     size_t lane_mask;        // refined: per z-mode bit mask of FP64-lane x-tiles (uint32 [nz])
@@ -111,12 +115,13 @@ struct Plan {
     ibs_grid_desc desc;
     bool py = false;                               // y periodic (no walls)
     bool wx = false;                               // walls at x = 0 and x = lx
+    bool wz = false;                               // walls at z = 0 and z = lz
     int tune[NUM_TUNE] = {-1, -1};   // candidate index per knob; -1 = default
     int nx, ny, nz;
     double hx, hz;
     std::vector<double> yf, yc, dyc, dyf;          // grid
-    std::vector<double> qx[NUM_XK], qz;            // Q[i][a], row-major n x n (x: per x kind)
-    std::vector<double> lam_x[NUM_XK], lam_z;
+    std::vector<double> qx[NUM_XK], qz[NUM_XK];    // Q[i][a], row-major n x n, per x / z kind
+    std::vector<double> lam_x[NUM_XK], lam_z[NUM_XK];
     std::vector<double> lo[NUM_KINDS], di[NUM_KINDS], up[NUM_KINDS];
     int rows[NUM_KINDS];
     BlobLayout lay;
@@ -148,6 +153,8 @@ struct FieldJob {
     int kind;           // KIND_*
     int xk;             // XK_* (x operator)
     const void *xq;     // x transform matrix of this job (set by the x launchers)
+    int zk;             // XK_* kind of the z operator
+    const void *zq;     // z transform matrix of this job (set by the z launchers)
     double c;           // Helmholtz coefficient (Poisson: unused)
     void *info;         // ibs_solve_info* or null
 };
@@ -173,6 +180,11 @@ inline int comp_xkind(const Plan &p, int comp)
 {
     return !p.wx ? XK_P : (comp == 0 ? XK_F : XK_C);
 }
+// z kind of a component: w is the face-normal one.
+inline int comp_zkind(const Plan &p, int comp)
+{
+    return !p.wz ? XK_P : (comp == 2 ? XK_F : XK_C);
+}
 
 // Workspace of one solve call: the work fields and the state after them.
 size_t field_bytes_for(const Plan &p, int op, int ncomp);
@@ -192,14 +204,16 @@ bool can_fold(int n);
 int fold_candidates();
 // Folded split transforms: the half length must hold whole 32-deep chunks.
 inline bool can_fold_split(int n) { return n % 64 == 0; }
-// The folds use the Fourier basis's mirror symmetry: x folds only when x is
-// periodic (z always is).
+// The folds use the Fourier basis's mirror symmetry: a direction folds only
+// when it is periodic.
 inline bool x_folds(const Plan &p) { return !p.wx && can_fold(p.nx); }
 inline bool x_folds_split(const Plan &p) { return !p.wx && can_fold_split(p.nx); }
+inline bool z_folds(const Plan &p) { return !p.wz && can_fold(p.nz); }
+inline bool z_folds_split(const Plan &p) { return !p.wz && can_fold_split(p.nz); }
 hipError_t launch_xfold_f64(const JobSet &js, const Plan &p, bool inverse, hipStream_t s);
 hipError_t launch_zfold_f64(const JobSet &js, const Plan &p, bool inverse, hipStream_t s);
 hipError_t launch_zgemm_f64(const JobSet &js, int M, int K, int nx,
-                            const double *as, hipStream_t s);
+                            const double *const as[NUM_XK], hipStream_t s);
 // Tridiagonal pencils along y, in place on js.j[q].out ([nz][rows][nx]).
 // poisson: pressure operator (pin + weighted-mean handling of pencil 0,0).
 hipError_t launch_tridiag_f64(const JobSet &js, const Plan &p, const State &st, bool poisson,
@@ -251,6 +265,8 @@ struct SplitJob {
     int kind;
     int xk;             // XK_* (x operator)
     const void *xq;     // x transform matrix of this job (set by the x launchers)
+    int zk;             // XK_* kind of the z operator
+    const void *zq;     // z transform matrix of this job (set by the z launchers)
     int op;             // IBS_OP_* of the job (residual stencil)
     double c;
     void *info;

@@ -321,6 +321,8 @@ __global__ __launch_bounds__(512) void split_zgemm_kernel(SplitSet ss, int M, in
     __shared__ b8 sq[(DB ? 2 : 1) * QCNT];
     if (skip && skip[blockIdx.z]) return;
     const SplitJob &jb = ss.j[blockIdx.z];
+    // the job's own matrix when the jobs' z operators differ (walls in z)
+    const b8 *__restrict__ qj = jb.zq ? static_cast<const b8 *>(jb.zq) : qs;
     const int rskip = skip_first_row(jb.kind);
     const int Ncol = (jb.rows - rskip) * nx;
     const size_t ldp = (size_t)jb.rows * nx;   // plane stride
@@ -349,7 +351,7 @@ __global__ __launch_bounds__(512) void split_zgemm_kernel(SplitSet ss, int M, in
             for (int e = 0; e < 8; ++e) d[j][e] = (j < ncb) ? brow[(size_t)e * ldp + 16 * j] : 0.f;
     };
     b8 qreg[QPER];
-    q_load<QPER>(qs, qcnt, qreg);
+    q_load<QPER>(qj, qcnt, qreg);
     q_store<QPER>(sq, qcnt, qreg);
     load_data(0, dcur);
     for (int kc = 0; kc < KC; ++kc) {
@@ -357,7 +359,7 @@ __global__ __launch_bounds__(512) void split_zgemm_kernel(SplitSet ss, int M, in
         const b8 *cur = sq + (DB ? (kc & 1) * QCNT : 0);
         const bool more = kc + 1 < KC;
         if (more) {
-            q_load<QPER>(qs + (size_t)(kc + 1) * qcnt, qcnt, qreg);
+            q_load<QPER>(qj + (size_t)(kc + 1) * qcnt, qcnt, qreg);
             load_data(kc + 1, dnext);
         }
         b8 b[WN][3];
@@ -1018,7 +1020,7 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
                                                            const double *__restrict__ bmean,
                                                            double *__restrict__ xsum,
                                                            const int *__restrict__ skip, int rb_rows,
-                                                           int tiles_y, int rz, int py, int wxw)
+                                                           int tiles_y, int rz, int py, int wxw, int wzw)
 {
     typedef Tx tx4 __attribute__((ext_vector_type(4)));
     typedef double dv4_ __attribute__((ext_vector_type(4)));
@@ -1090,6 +1092,9 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
         // west neighbour of slot 1 that wall (0)
         const bool xw_u = wxw && op == IBS_OP_HELMHOLTZ_U;
         const double gx = pois ? 1.0 : (op == IBS_OP_HELMHOLTZ_U ? 0.0 : -1.0);
+        // walls in z: the same along z, w the face-normal component
+        const bool zw_w = wzw && op == IBS_OP_HELMHOLTZ_W;
+        const double gz = pois ? 1.0 : (op == IBS_OP_HELMHOLTZ_W ? 0.0 : -1.0);
         auto ld4 = [&](size_t at) { return *reinterpret_cast<const tx4 *>(x + at); };
         tx4 xm = ld4((size_t)(k0 == 0 ? nz - 1 : k0 - 1) * plane + o + i0);
         tx4 xc = ld4((size_t)k0 * plane + o + i0);
@@ -1114,8 +1119,14 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
                     if (xw_u && i == 1) xw = 0.0;
                     xwall = xw_u && i == 0;
                 }
-                double lap = ((xe - xcc) - (xcc - xw)) * ihx2 +
-                             (((double)xp[e] - xcc) - (xcc - (double)xm[e])) * ihz2;
+                double zp = (double)xp[e], zm = (double)xm[e];
+                if (wzw) {
+                    if (k == 0) zm = gz * xcc;
+                    if (k + 1 == nz) zp = gz * xcc;
+                    if (zw_w && k == 1) zm = 0.0;
+                    xwall = xwall || (zw_w && k == 0);
+                }
+                double lap = ((xe - xcc) - (xcc - xw)) * ihx2 + ((zp - xcc) - (xcc - zm)) * ihz2;
                 lap += cu * (wu * (double)xu[e] - xcc) - cl * (xcc - wl * (double)xl[e]);
                 const double ax = pois ? lap : xcc - cj * lap;
                 rv[e] = (wall || xwall) ? 0.f : (float)((bv[e] - bm) - ax);
@@ -1371,7 +1382,7 @@ hipError_t launch_split_zgemm(const SplitSet &ss, const Plan &p, const State &st
                               hipStream_t s)
 {
     const int *skip = pass >= 2 ? st.done : nullptr;
-    if (can_fold_split(p.nz)) {
+    if (z_folds_split(p)) {
         // folded: HBT 16-blocks per factor (HB = nz/32), WN column blocks per wave
         const b8 *qs = reinterpret_cast<const b8 *>(blob_ptr(p, inverse ? p.lay.szf_inv : p.lay.szf_fwd));
         const int hb = p.nz / 32;
@@ -1385,16 +1396,19 @@ hipError_t launch_split_zgemm(const SplitSet &ss, const Plan &p, const State &st
     }
     const int M = p.nz;
     const int Ncol = max_rows(ss) * p.nx;
-    const b8 *qs = reinterpret_cast<const b8 *>(blob_ptr(p, inverse ? p.lay.sz_inv : p.lay.sz_fwd));
+    const size_t *tab = inverse ? p.lay.sz_inv : p.lay.sz_fwd;
+    const b8 *qs = reinterpret_cast<const b8 *>(blob_ptr(p, tab[XK_P]));
+    SplitSet sj = ss;   // each job's matrix for its z operator
+    for (int q = 0; q < sj.n; ++q) sj.j[q].zq = blob_ptr(p, tab[sj.j[q].zk]);
     const int mbt = M <= 64 ? 4 : (M <= 128 ? 8 : (M <= 256 ? 16 : (M <= 384 ? 24 : 32)));
     const int wn = mbt == 4 ? 4 : (mbt <= 16 ? 2 : 1);
     dim3 grid((Ncol + 8 * 16 * wn - 1) / (8 * 16 * wn), 1, ss.n);
     switch (mbt) {
-    case 4: hipLaunchKernelGGL((split_zgemm_kernel<4, 4>), grid, dim3(512), 0, s, ss, M, M, p.nx, qs, skip); break;
-    case 8: hipLaunchKernelGGL((split_zgemm_kernel<8, 2>), grid, dim3(512), 0, s, ss, M, M, p.nx, qs, skip); break;
-    case 16: hipLaunchKernelGGL((split_zgemm_kernel<16, 2>), grid, dim3(512), 0, s, ss, M, M, p.nx, qs, skip); break;
-    case 24: hipLaunchKernelGGL((split_zgemm_kernel<24, 1>), grid, dim3(512), 0, s, ss, M, M, p.nx, qs, skip); break;
-    default: hipLaunchKernelGGL((split_zgemm_kernel<32, 1>), grid, dim3(512), 0, s, ss, M, M, p.nx, qs, skip); break;
+    case 4: hipLaunchKernelGGL((split_zgemm_kernel<4, 4>), grid, dim3(512), 0, s, sj, M, M, p.nx, qs, skip); break;
+    case 8: hipLaunchKernelGGL((split_zgemm_kernel<8, 2>), grid, dim3(512), 0, s, sj, M, M, p.nx, qs, skip); break;
+    case 16: hipLaunchKernelGGL((split_zgemm_kernel<16, 2>), grid, dim3(512), 0, s, sj, M, M, p.nx, qs, skip); break;
+    case 24: hipLaunchKernelGGL((split_zgemm_kernel<24, 1>), grid, dim3(512), 0, s, sj, M, M, p.nx, qs, skip); break;
+    default: hipLaunchKernelGGL((split_zgemm_kernel<32, 1>), grid, dim3(512), 0, s, sj, M, M, p.nx, qs, skip); break;
     }
     return hipGetLastError();
 }
@@ -1431,7 +1445,8 @@ hipError_t launch_residual_f32(const SplitSet &ss, const Plan &p, const State &s
     auto go = [&](auto kernel) {
         hipLaunchKernelGGL(kernel, grid, dim3(256), 0, s, ss, p.nx, p.ny, p.nz, 1.0 / (p.hx * p.hx),
                            1.0 / (p.hz * p.hz), blob_ptr(p, p.lay.dyc), blob_ptr(p, p.lay.dyf),
-                           st.bmean, st.xsum, skip, rb_rows, tiles_y, rz, p.py ? 1 : 0, p.wx ? 1 : 0);
+                           st.bmean, st.xsum, skip, rb_rows, tiles_y, rz, p.py ? 1 : 0, p.wx ? 1 : 0,
+                           p.wz ? 1 : 0);
     };
     if (x32) go(residual_f32_kernel<float>);
     else go(residual_f32_kernel<double>);

@@ -16,6 +16,7 @@ struct Geo {
     int py;                   // periodic y: no walls, v has ny faces
     int wx;                   // walls in x: u slot 0 is the wall face x = 0
                               // (zero), face nx is not stored (zero)
+    int wz;                   // walls in z: the same for w's plane 0
 };
 
 static Geo geo_of(const Plan &p)
@@ -24,6 +25,7 @@ static Geo geo_of(const Plan &p)
     g.nx = p.nx; g.ny = p.ny; g.nz = p.nz;
     g.py = p.py ? 1 : 0;
     g.wx = p.wx ? 1 : 0;
+    g.wz = p.wz ? 1 : 0;
     g.ihx = 1.0 / p.hx; g.ihz = 1.0 / p.hz;
     g.dyc = blob_ptr(p, p.lay.dyc);
     g.dyf = blob_ptr(p, p.lay.dyf);
@@ -72,7 +74,9 @@ __global__ __launch_bounds__(256) void divergence_kernel(Geo g, const double *__
     const double uw = (g.wx && i == 0) ? 0.0 : u[c];
     const double du = (ue - uw) * g.ihx;
     const double dv = (v[vn] - v[vc]) / g.dyc[j];
-    const double dw = (w[kp * plane + (size_t)j * g.nx + i] - w[c]) * g.ihz;
+    const double wt = (g.wz && kp == 0) ? 0.0 : w[kp * plane + (size_t)j * g.nx + i];
+    const double wb = (g.wz && k == 0) ? 0.0 : w[c];
+    const double dw = (wt - wb) * g.ihz;
     b[c] = scale * (du + dv + dw);
 }
 
@@ -97,7 +101,8 @@ __global__ __launch_bounds__(256) void correct_kernel(Geo g, const double *__res
         const double ph = phi[c];
         if (g.wx && i == 0) u[c] = 0.0;   // the wall face x = 0
         else u[c] -= gs * (ph - phi[c - i + im]) * g.ihx;
-        w[c] -= gs * (ph - phi[km * plane + (size_t)j * g.nx + i]) * g.ihz;
+        if (g.wz && k == 0) w[c] = 0.0;   // the wall face z = 0
+        else w[c] -= gs * (ph - phi[km * plane + (size_t)j * g.nx + i]) * g.ihz;
         if (pr) pr[c] += ph - (cp != 0.0 ? cp * lap[c] : 0.0);
         if (j > 0) v[vc] -= gs * (ph - phi[c - g.nx]) / g.dyf[j];
         else if (g.py) v[vc] -= gs * (ph - phi[c + (size_t)(g.ny - 1) * g.nx]) / g.dyf[0];   // across the wrap
@@ -158,8 +163,16 @@ __global__ __launch_bounds__(256) void residual_kernel(Geo g, int op, double cc,
                 if (i + 1 == g.nx) xe = gx;
                 if (op == IBS_OP_HELMHOLTZ_U && i == 0) unknown = false;
             }
-            const double xt = x[kp * plane + (size_t)j * g.nx + i];
-            const double xb = x[km * plane + (size_t)j * g.nx + i];
+            double xt = x[kp * plane + (size_t)j * g.nx + i];
+            double xb = x[km * plane + (size_t)j * g.nx + i];
+            if (g.wz) {
+                // walls in z: as in x, with w the face-normal component
+                const double gz = op == IBS_OP_POISSON ? xc : (op == IBS_OP_HELMHOLTZ_W ? 0.0 : -xc);
+                if (op == IBS_OP_HELMHOLTZ_W && k == 1) xb = 0.0;
+                if (k == 0) xb = gz;
+                if (k + 1 == g.nz) xt = gz;
+                if (op == IBS_OP_HELMHOLTZ_W && k == 0) unknown = false;
+            }
             double lap = ((xe - xc) - (xc - xw)) * (g.ihx * g.ihx) +
                          ((xt - xc) - (xc - xb)) * (g.ihz * g.ihz);
             if (g.py) {

@@ -35,7 +35,8 @@ static double helmholtz_kappa(const JobSet &js, const Plan &p)
     for (int xk = 0; xk < NUM_XK; ++xk)
         for (double v : p.lam_x[xk]) smax = std::max(smax, -v);
     double szmax = 0.0;
-    for (double v : p.lam_z) szmax = std::max(szmax, -v);
+    for (int zk = 0; zk < NUM_XK; ++zk)
+        for (double v : p.lam_z[zk]) szmax = std::max(szmax, -v);
     double kap = 1.0;
     for (int q = 0; q < js.n; ++q) {
         const int kd = js.j[q].kind;
@@ -66,7 +67,7 @@ static hipError_t launch_tridiag(const JobSet &js, const Plan &p, const State &s
 {
     TriParams tp;
     for (int xk = 0; xk < NUM_XK; ++xk) tp.lam_x[xk] = blob_ptr(p, p.lay.lam_x[xk]);
-    tp.lam_z = blob_ptr(p, p.lay.lam_z);
+    for (int zk = 0; zk < NUM_XK; ++zk) tp.lam_z[zk] = blob_ptr(p, p.lay.lam_z[zk]);
     for (int kd = 0; kd < NUM_KINDS; ++kd) {
         tp.lo[kd] = blob_ptr(p, p.lay.lo[kd]);
         tp.di[kd] = blob_ptr(p, p.lay.di[kd]);

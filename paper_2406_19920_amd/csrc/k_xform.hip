@@ -92,10 +92,10 @@ __global__ __launch_bounds__(256) void xgemm_f64_kernel(JobSet js, int nz, int K
 // (M = K = nz), B = in viewed as K x Ncol (Ncol = transform rows * nx, at
 // plane stride rows * nx), C = out (M x Ncol).
 template <int WM, int WN>
-__global__ __launch_bounds__(256) void zgemm_f64_kernel(JobSet js, int M, int K, int nx,
-                                                        const double *__restrict__ as, int wgn)
+__global__ __launch_bounds__(256) void zgemm_f64_kernel(JobSet js, int M, int K, int nx, int wgn)
 {
     const FieldJob &jb = js.j[blockIdx.z];
+    const double *__restrict__ as = static_cast<const double *>(jb.zq);
     const int skip = skip_first_row(jb.kind);
     const int Ncol = (jb.rows - skip) * nx;
     const size_t ldp = (size_t)jb.rows * nx;   // plane stride
@@ -180,16 +180,18 @@ hipError_t launch_xgemm_f64(const JobSet &js_in, int nz, int K, int N, const dou
     return hipGetLastError();
 }
 
-hipError_t launch_zgemm_f64(const JobSet &js, int M, int K, int nx, const double *as,
+hipError_t launch_zgemm_f64(const JobSet &js_in, int M, int K, int nx, const double *const as[NUM_XK],
                             hipStream_t s)
 {
+    JobSet js = js_in;
+    for (int q = 0; q < js.n; ++q) js.j[q].zq = as[js.j[q].zk];
     constexpr int WM = 4, WN = 4;
     const int Ncol = max_rows(js) * nx;
     int wgm = M >= 256 ? 4 : (M >= 128 ? 2 : 1);
     int wgn = 4 / wgm;
     dim3 grid((Ncol + 16 * WN * wgn - 1) / (16 * WN * wgn), (M + 16 * WM * wgm - 1) / (16 * WM * wgm),
               js.n);
-    hipLaunchKernelGGL((zgemm_f64_kernel<WM, WN>), grid, dim3(256), 0, s, js, M, K, nx, as, wgn);
+    hipLaunchKernelGGL((zgemm_f64_kernel<WM, WN>), grid, dim3(256), 0, s, js, M, K, nx, wgn);
     return hipGetLastError();
 }
 

@@ -390,10 +390,10 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     }
     const bool walls_y = d.bc_y_vel == IBS_DIRICHLET && d.bc_y_p == IBS_NEUMANN;
     const bool periodic_y = d.bc_y_vel == IBS_PERIODIC && d.bc_y_p == IBS_PERIODIC;
-    if ((d.bc_x != IBS_PERIODIC && d.bc_x != IBS_DIRICHLET) || d.bc_z != IBS_PERIODIC ||
-        !(walls_y || periodic_y)) {
-        set_error("supported: x periodic or walls (bc_x = IBS_DIRICHLET: Dirichlet velocity, Neumann "
-                  "pressure), periodic z, and in y either Dirichlet velocity / Neumann pressure walls "
+    if ((d.bc_x != IBS_PERIODIC && d.bc_x != IBS_DIRICHLET) ||
+        (d.bc_z != IBS_PERIODIC && d.bc_z != IBS_DIRICHLET) || !(walls_y || periodic_y)) {
+        set_error("supported: x and z each periodic or walls (IBS_DIRICHLET: Dirichlet velocity, "
+                  "Neumann pressure), and in y either Dirichlet velocity / Neumann pressure walls "
                   "or periodic (triply periodic)");
         return IBS_ERR_UNSUPPORTED;
     }
@@ -432,6 +432,7 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     p->desc.y_faces = nullptr;
     p->py = periodic_y;
     p->wx = d.bc_x == IBS_DIRICHLET;
+    p->wz = d.bc_z == IBS_DIRICHLET;
     const double lx = d.lx > 0 ? d.lx : 1.0, ly = d.ly > 0 ? d.ly : 1.0, lz = d.lz > 0 ? d.lz : 1.0;
     p->desc.lx = lx; p->desc.ly = ly; p->desc.lz = lz;
     if (p->desc.tol <= 0) p->desc.tol = 1e-10;
@@ -526,27 +527,32 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     std::shared_ptr<const AxisTables> ax[NUM_XK];
     for (int k = 0; k < NUM_XK; ++k)
         ax[k] = (p->wx || k == 0) ? axis_tables(nx, p->hx, false, split, p->wx ? k : -1) : ax[0];
-    const std::shared_ptr<const AxisTables> az = axis_tables(nz, p->hz, true, split);
+    std::shared_ptr<const AxisTables> az[NUM_XK];
+    for (int k = 0; k < NUM_XK; ++k)
+        az[k] = (p->wz || k == 0) ? axis_tables(nz, p->hz, true, split, p->wz ? k : -1) : az[0];
     for (int k = 0; k < NUM_XK; ++k) {
         p->qx[k] = ax[k]->Q;
         p->lam_x[k] = ax[k]->lam;
+        p->qz[k] = az[k]->Q;
+        p->lam_z[k] = az[k]->lam;
     }
-    p->qz = az->Q;
-    p->lam_z = az->lam;
     const int nxk = p->wx ? NUM_XK : 1;   // distinct x tables
+    const int nzk = p->wz ? NUM_XK : 1;   // distinct z tables
 
     // blob layout
     BlobLayout &L = p->lay;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
-    const bool fold_x = x_folds(*p), fold_z = can_fold(nz);
+    const bool fold_x = x_folds(*p), fold_z = z_folds(*p);
     const size_t hx2 = size_t(nx / 2) * (nx / 2), hz2 = size_t(nz / 2) * (nz / 2);
     for (int k = 0; k < NUM_XK; ++k) {
         L.bx_fwd[k] = k < nxk ? take(fold_x ? 0 : sizeof(double) * nx * nx) : L.bx_fwd[0];
         L.bx_inv[k] = k < nxk ? take(fold_x ? 0 : sizeof(double) * nx * nx) : L.bx_inv[0];
     }
-    L.az_fwd = take(fold_z ? 0 : sizeof(double) * nz * nz);
-    L.az_inv = take(fold_z ? 0 : sizeof(double) * nz * nz);
+    for (int k = 0; k < NUM_XK; ++k) {
+        L.az_fwd[k] = k < nzk ? take(fold_z ? 0 : sizeof(double) * nz * nz) : L.az_fwd[0];
+        L.az_inv[k] = k < nzk ? take(fold_z ? 0 : sizeof(double) * nz * nz) : L.az_inv[0];
+    }
     L.fx_fwd_c = take(fold_x ? sizeof(double) * hx2 : 0);
     L.fx_fwd_s = take(fold_x ? sizeof(double) * hx2 : 0);
     L.fx_inv_c = take(fold_x ? sizeof(double) * hx2 : 0);
@@ -556,7 +562,7 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     L.fz_inv_c = take(fold_z ? sizeof(double) * hz2 : 0);
     L.fz_inv_s = take(fold_z ? sizeof(double) * hz2 : 0);
     for (int k = 0; k < NUM_XK; ++k) L.lam_x[k] = k < nxk ? take(sizeof(double) * nx) : L.lam_x[0];
-    L.lam_z = take(sizeof(double) * nz);
+    for (int k = 0; k < NUM_XK; ++k) L.lam_z[k] = k < nzk ? take(sizeof(double) * nz) : L.lam_z[0];
     for (int kd = 0; kd < NUM_KINDS; ++kd) {
         L.lo[kd] = take(sizeof(double) * (ny + 1));
         L.di[kd] = take(sizeof(double) * (ny + 1));
@@ -565,13 +571,15 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     L.wy = take(sizeof(double) * ny);
     L.dyc = take(sizeof(double) * ny);
     L.dyf = take(sizeof(double) * (ny + 1));
-    const bool sfold_x = split && x_folds_split(*p), sfold_z = split && can_fold_split(nz);
+    const bool sfold_x = split && x_folds_split(*p), sfold_z = split && z_folds_split(*p);
     for (int k = 0; k < NUM_XK; ++k) {
         L.sx_fwd[k] = k < nxk ? take(split && !sfold_x ? sizeof(uint16_t) * 3 * nx * nx : 0) : L.sx_fwd[0];
         L.sx_inv[k] = k < nxk ? take(split && !sfold_x ? sizeof(uint16_t) * 3 * nx * nx : 0) : L.sx_inv[0];
     }
-    L.sz_fwd = take(split && !sfold_z ? sizeof(uint16_t) * 3 * nz * nz : 0);
-    L.sz_inv = take(split && !sfold_z ? sizeof(uint16_t) * 3 * nz * nz : 0);
+    for (int k = 0; k < NUM_XK; ++k) {
+        L.sz_fwd[k] = k < nzk ? take(split && !sfold_z ? sizeof(uint16_t) * 3 * nz * nz : 0) : L.sz_fwd[0];
+        L.sz_inv[k] = k < nzk ? take(split && !sfold_z ? sizeof(uint16_t) * 3 * nz * nz : 0) : L.sz_inv[0];
+    }
     L.sxf_fwd = take(sfold_x ? sizeof(uint16_t) * 3 * 2 * hx2 : 0);
     L.sxf_inv = take(sfold_x ? sizeof(uint16_t) * 3 * 2 * hx2 : 0);
     L.szf_fwd = take(sfold_z ? sizeof(uint16_t) * 3 * 2 * hz2 : 0);
@@ -590,7 +598,7 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
             for (int t = 0; t < nx / 32; ++t) {
                 bool need = false;
                 for (int a = 32 * t; a < 32 * t + 32 && !need; ++a) {
-                    const double sabs = std::fabs(p->lam_x[XK_P][a] + p->lam_z[c]);
+                    const double sabs = std::fabs(p->lam_x[XK_P][a] + p->lam_z[XK_P][c]);
                     need = sabs == 0.0 || 1.0 + g / sabs > (p->py ? LANE64_KAPPA_CYCLIC : LANE64_KAPPA);
                 }
                 if (need) {
@@ -622,13 +630,15 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
         }
     }
     if (fold_z) {
-        put(L.fz_fwd_c, az->f64[0].data(), hz2);
-        put(L.fz_fwd_s, az->f64[1].data(), hz2);
-        put(L.fz_inv_c, az->f64[2].data(), hz2);
-        put(L.fz_inv_s, az->f64[3].data(), hz2);
+        put(L.fz_fwd_c, az[0]->f64[0].data(), hz2);
+        put(L.fz_fwd_s, az[0]->f64[1].data(), hz2);
+        put(L.fz_inv_c, az[0]->f64[2].data(), hz2);
+        put(L.fz_inv_s, az[0]->f64[3].data(), hz2);
     } else {
-        put(L.az_fwd, az->f64[0].data(), size_t(nz) * nz);
-        put(L.az_inv, az->f64[1].data(), size_t(nz) * nz);
+        for (int k = 0; k < nzk; ++k) {
+            put(L.az_fwd[k], az[k]->f64[0].data(), size_t(nz) * nz);
+            put(L.az_inv[k], az[k]->f64[1].data(), size_t(nz) * nz);
+        }
     }
     if (split) {
         if (sfold_x) {
@@ -640,13 +650,20 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
                 put16(L.sx_inv[k], ax[k]->split[1]);
             }
         }
-        put16(sfold_z ? L.szf_fwd : L.sz_fwd, az->split[0]);
-        put16(sfold_z ? L.szf_inv : L.sz_inv, az->split[1]);
+        if (sfold_z) {
+            put16(L.szf_fwd, az[0]->split[0]);
+            put16(L.szf_inv, az[0]->split[1]);
+        } else {
+            for (int k = 0; k < nzk; ++k) {
+                put16(L.sz_fwd[k], az[k]->split[0]);
+                put16(L.sz_inv[k], az[k]->split[1]);
+            }
+        }
     }
     if (!lane_mask.empty()) std::memcpy(p->blob.data() + L.lane_mask, lane_mask.data(), 4 * lane_mask.size());
     if (!lane_list.empty()) std::memcpy(p->blob.data() + L.lane_list, lane_list.data(), 4 * lane_list.size());
     for (int k = 0; k < nxk; ++k) put(L.lam_x[k], p->lam_x[k].data(), nx);
-    put(L.lam_z, p->lam_z.data(), nz);
+    for (int k = 0; k < nzk; ++k) put(L.lam_z[k], p->lam_z[k].data(), nz);
     for (int kd = 0; kd < NUM_KINDS; ++kd) {
         put(L.lo[kd], p->lo[kd].data(), ny + 1);
         put(L.di[kd], p->di[kd].data(), ny + 1);

@@ -87,7 +87,7 @@ static __device__ __forceinline__ float rcpr(float d)
 constexpr double FP32_KAPPA = 16.0;
 
 struct TriParams {
-    const double *lam_x[NUM_XK], *lam_z;   // x: per x kind of the job
+    const double *lam_x[NUM_XK], *lam_z[NUM_XK];   // per x / z kind of the job
     const double *lo[NUM_KINDS], *di[NUM_KINDS], *up[NUM_KINDS];
     const double *wy;   // Delta_j: weights of the pressure unknowns
     double *bmean;      // per job: weighted mean removed from the rhs (Poisson)
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
         decode(tile < ntiles ? tile : ntiles - 1, job, c, a0);
         const bool live = tile < ntiles && !((skipmask >> job) & 1) && !lane_skipped(c, a0);
         plx = tp.lam_x[js.j[job].xk][a0 + p];
-        plz = tp.lam_z[c];
+        plz = tp.lam_z[js.j[job].zk][c];
         const auto rs = plane_rsrc(job, c, live);
         const uint32_t sys0 = skip_first_row(js.j[job].kind);   // first row of the system
         const uint32_t voff = (uint32_t)(a0 + lcol) * sizeof(T) + (lrow + sys0) * row_bytes;

@@ -169,10 +169,12 @@ def test_plan_bytes_and_errors():
         assert e.value.status == ibs.IBS_ERR_INVALID_ARG
     finally:
         ibs.solver_plan_destroy(p)
-    # x walls are served; Neumann x (no meaning for the velocity) and
-    # non-periodic z are not
+    # walls in x and z are served; Neumann x or z (no meaning for the
+    # velocity) is not
     ibs.solver_plan_destroy(_plan(32, 16, 32, bc_x=ibs.IBS_DIRICHLET))
-    for kw in (dict(bc_x=ibs.IBS_NEUMANN), dict(bc_z=ibs.IBS_DIRICHLET)):
+    ibs.solver_plan_destroy(_plan(32, 16, 32, bc_z=ibs.IBS_DIRICHLET))
+    ibs.solver_plan_destroy(_plan(32, 16, 32, bc_x=ibs.IBS_DIRICHLET, bc_z=ibs.IBS_DIRICHLET))
+    for kw in (dict(bc_x=ibs.IBS_NEUMANN), dict(bc_z=ibs.IBS_NEUMANN)):
         with pytest.raises(ibs.IbsError) as e:
             _plan(32, 16, 32, **kw)
         assert e.value.status == ibs.IBS_ERR_UNSUPPORTED
@@ -468,5 +470,99 @@ def test_host_emulation_xwalls_matches_oracle(op, beta):
         assert err < 1e-13, err
         if op == OP_U:
             assert np.abs(xe[:, :, 0]).max() == 0.0
+    finally:
+        ibs.solver_plan_destroy(p)
+
+
+# ------------------------------------------------------------------------
+# walls in z (and ducts): the plan's z bases and a host emulation
+# ------------------------------------------------------------------------
+def _z_tables(p, nz, zk):
+    """(Q, lambda) of z kind zk (0 pressure, 1 u/v, 2 w) from the exports."""
+    if zk == 0:
+        return ibs.ibs_plan_export(p, 2).reshape(nz, nz), ibs.ibs_plan_export(p, 4)
+    base = 5 + 3 * 4 + 4
+    q = ibs.ibs_plan_export(p, base + (0 if zk == 1 else 1)).reshape(nz, nz)
+    lam = ibs.ibs_plan_export(p, base + (2 if zk == 1 else 3))
+    return q, lam
+
+
+@pytest.mark.parametrize("nz", [16, 48, 64])
+def test_z_wall_bases_diagonalise_the_z_operators(nz):
+    p = _plan(32, 8, nz, lz=0.6, bc_z=ibs.IBS_DIRICHLET)
+    h = 0.6 / nz
+    try:
+        for zk in range(3):
+            Q, lam = _z_tables(p, nz, zk)
+            T = _x_operator(nz, h, zk)
+            np.testing.assert_allclose(T @ Q, Q * lam[None, :], rtol=0, atol=1e-11 / h ** 2)
+            keep = np.arange(1, nz) if zk == 2 else np.arange(nz)
+            Qk = Q[np.ix_(keep, keep)]
+            np.testing.assert_allclose(Qk.T @ Qk, np.eye(len(keep)), atol=1e-14)
+        # the x tables of a periodic x stay the Fourier basis
+        Qx = ibs.ibs_plan_export(p, 1).reshape(32, 32)
+        np.testing.assert_allclose(Qx.T @ Qx, np.eye(32), atol=1e-14)
+    finally:
+        ibs.solver_plan_destroy(p)
+
+
+def _emulate_walls(p, nx, ny, nz, op, rhs, c=0.0, wx=False, wz=False):
+    xk = 0 if (op == OP_P or not wx) else (2 if op == OP_U else 1)
+    zk = 0 if (op == OP_P or not wz) else (2 if op == OP_W else 1)
+    Qx, lx = _x_tables(p, nx, xk)
+    Qz, lz = _z_tables(p, nz, zk)
+    kind = {OP_P: 0, OP_U: 1, OP_W: 1, OP_V: 2}[op]
+    lo, di, up = _tables(p, kind)
+    n = ny + 1 if op == OP_V else ny
+    lo, di, up = lo[:n], di[:n], up[:n]
+    f = rhs.copy()
+    if op == OP_V:
+        f[:, 0, :] = 0
+        f[:, ny, :] = 0
+    h = np.einsum("kc,kja->cja", Qz, f @ Qx)
+    dyc = np.diff(ibs.ibs_plan_export(p, 0))
+    out = np.zeros_like(h)
+    for cz in range(nz):
+        for a in range(nx):
+            s = lx[a] + lz[cz]
+            if op == OP_P:
+                A = np.diag(di + s) + np.diag(lo[1:], -1) + np.diag(up[:-1], 1)
+            else:
+                A = np.eye(n) * (1 - c * s) - c * (np.diag(di) + np.diag(lo[1:], -1) + np.diag(up[:-1], 1))
+            rr = h[cz, :, a].copy()
+            if op == OP_P and a == 0 and cz == 0:
+                rr -= (dyc @ rr) / dyc.sum()
+                A[0, :] = 0
+                A[0, 0] = 1
+                rr[0] = 0
+                x = np.linalg.solve(A, rr)
+                x -= (dyc @ x) / dyc.sum()
+            elif op == OP_V:
+                x = np.zeros(n)
+                x[1:n - 1] = np.linalg.solve(A[1:n - 1, 1:n - 1], rr[1:n - 1])
+            else:
+                x = np.linalg.solve(A, rr)
+            out[cz, :, a] = x
+    return np.einsum("kc,cja->kja", Qz, out) @ Qx.T
+
+
+@pytest.mark.parametrize("wx", [False, True])
+@pytest.mark.parametrize("op", [OP_P, OP_U, OP_V, OP_W])
+def test_host_emulation_zwalls_matches_oracle(op, wx):
+    nx, ny, nz = 16, 12, 16
+    kw = dict(bc_z=ibs.IBS_DIRICHLET)
+    if wx:
+        kw["bc_x"] = ibs.IBS_DIRICHLET
+    p = _plan(nx, ny, nz, beta=1.5, **kw)
+    try:
+        g = oracle.Grid(nx, ny, nz, beta=1.5, periodic_z=False, periodic_x=not wx)
+        rhs = synth.scalar(nx, ny, nz, 24, rows=ny + 1 if op == OP_V else None)
+        c = 0.0 if op == OP_P else 2e-3
+        xo, _ = oracle.solve(g, op, rhs, c=c)
+        xe = _emulate_walls(p, nx, ny, nz, op, rhs, c=c, wx=wx, wz=True)
+        err = np.linalg.norm(xe - xo) / np.linalg.norm(xo)
+        assert err < 1e-13, err
+        if op == OP_W:
+            assert np.abs(xe[0]).max() == 0.0
     finally:
         ibs.solver_plan_destroy(p)
