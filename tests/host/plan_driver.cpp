@@ -1,6 +1,7 @@
 // Host-only driver of the plan builder for the sanitizer build (address and
 // undefined-behaviour checks): builds plans for valid and invalid grids of
-// both precisions and both y conditions and walks every table.
+// both precisions, both y conditions and periodic or wall-bounded x and z,
+// and walks every table.
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -16,19 +17,22 @@ using namespace ibs;
 
 int main()
 {
-    struct Case { int nx, ny, nz; double beta; int prec, py, expect_ok; };
+    struct Case { int nx, ny, nz; double beta; int prec, py, expect_ok, wx = 0, wz = 0; };
     const std::vector<Case> cases = {
         {32, 24, 16, 2.0, IBS_FP64, 0, 1},  {64, 64, 64, 0.0, IBS_REFINED_BF16X3, 0, 1},
         {96, 33, 32, 3.0, IBS_REFINED_BF16X3, 0, 1}, {48, 2, 80, 1.0, IBS_FP64, 0, 1},
         {64, 48, 32, 0.0, IBS_REFINED_BF16X3, 1, 1}, {32, 160, 64, 2.0, IBS_FP64, 1, 1},
         {512, 5, 64, 2.0, IBS_REFINED_BF16X3, 0, 1}, {16, 2, 16, 0.0, IBS_FP64, 0, 1},
         {24, 16, 32, 0.0, IBS_FP64, 0, 0},  {32, 100, 32, 0.0, IBS_FP64, 1, 0},
-        {48, 16, 64, 0.0, IBS_REFINED_BF16X3, 0, 0}, {32, 1, 32, 0.0, IBS_FP64, 0, 0}};
+        {48, 16, 64, 0.0, IBS_REFINED_BF16X3, 0, 0}, {32, 1, 32, 0.0, IBS_FP64, 0, 0},
+        {64, 40, 32, 1.5, IBS_FP64, 0, 1, 1, 0}, {96, 24, 64, 2.0, IBS_REFINED_BF16X3, 0, 1, 0, 1},
+        {64, 48, 64, 0.0, IBS_REFINED_BF16X3, 1, 1, 1, 1}, {48, 17, 80, 1.0, IBS_FP64, 0, 1, 1, 1}};
     int bad = 0;
     for (const Case &c : cases) {
         ibs_grid_desc d{};
         d.nx = c.nx; d.ny = c.ny; d.nz = c.nz; d.beta = c.beta;
-        d.bc_x = d.bc_z = IBS_PERIODIC;
+        d.bc_x = c.wx ? IBS_DIRICHLET : IBS_PERIODIC;
+        d.bc_z = c.wz ? IBS_DIRICHLET : IBS_PERIODIC;
         d.bc_y_vel = c.py ? IBS_PERIODIC : IBS_DIRICHLET;
         d.bc_y_p = c.py ? IBS_PERIODIC : IBS_NEUMANN;
         d.precision = c.prec;
