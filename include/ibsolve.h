@@ -346,14 +346,32 @@ typedef struct {
     ibs_solve_info *info;   /* NULL or ncomp (Poisson: 1) device records */
 } ibs_batch_job;
 
+/* Schedule policies of a batch: how the jobs' workspaces are dealt to the
+ * graph's lanes (jobs sharing a workspace always share a lane). */
+#define IBS_SCHED_BALANCED 0   /* largest work first, each to the least loaded lane */
+#define IBS_SCHED_IN_ORDER 1   /* workspaces in submission order, round-robin */
+
 /* Record njobs solves (the batching of the multi-grid configuration) into
  * one HIP graph by stream capture.  Jobs are spread over up to nlanes
- * independent graph branches (jobs of one plan stay on one branch, lanes
- * balanced by work) so that small grids overlap on the device.  Nothing is
- * executed.  Errors: IBS_ERR_INVALID_ARG (bad job; ibs_last_error() names
+ * independent graph branches by IBS_SCHED_BALANCED so that small grids
+ * overlap on the device.  Nothing is executed.  The schedule never changes
+ * a result: each job's launches run in the same order on its own
+ * workspace.  Errors: IBS_ERR_INVALID_ARG (bad job; ibs_last_error() names
  * it), IBS_ERR_HIP, and any error a job's solve call would return. */
 ibs_status ibs_batch_build(const ibs_batch_job *jobs, int32_t njobs, int32_t nlanes,
                            ibs_batch *out);
+/* As ibs_batch_build() with the schedule policy given (IBS_SCHED_*). */
+ibs_status ibs_batch_build_sched(const ibs_batch_job *jobs, int32_t njobs, int32_t nlanes, int32_t policy,
+                                 ibs_batch *out);
+/* Schedule autotuner: builds the batch for each candidate (lane counts 1,
+ * 2, 4, ... up to the number of distinct workspaces, both policies),
+ * replays each once untimed and then `reps` times in each of three
+ * interleaved rounds on stream (synchronising), keeps each candidate's
+ * fastest round and returns the fastest candidate's lane count, policy
+ * and ms per replay (ms may be NULL).  The jobs run; their outputs are
+ * those of any schedule.  Errors as ibs_batch_build(), IBS_ERR_HIP. */
+ibs_status ibs_batch_autotune(const ibs_batch_job *jobs, int32_t njobs, int32_t reps, int32_t *nlanes,
+                              int32_t *policy, float *ms, void *stream);
 /* Replay the whole batch on stream with one graph launch (asynchronous). */
 ibs_status ibs_batch_launch(ibs_batch batch, void *stream);
 ibs_status ibs_batch_destroy(ibs_batch batch);

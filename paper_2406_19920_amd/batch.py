@@ -69,9 +69,13 @@ class Job:
 
 
 class Batch:
-    """All jobs of a batch, captured once; launch() replays the graph."""
+    """All jobs of a batch, captured once; launch() replays the graph.
+    nlanes="auto": the schedule (lane count and policy) is chosen by the
+    library's schedule autotuner, timed on the device at set-up (the jobs
+    run during tuning); self.schedule records (nlanes, policy, ms)."""
 
-    def __init__(self, specs, precision=ibs.IBS_REFINED_BF16X3, nlanes=8, device="cuda"):
+    def __init__(self, specs, precision=ibs.IBS_REFINED_BF16X3, nlanes=8, device="cuda",
+                 policy=ibs.IBS_SCHED_BALANCED, tune_reps=3):
         import torch
         self.torch = torch
         self.jobs = [Job(s, precision, device) for s in specs]
@@ -79,7 +83,12 @@ class Batch:
         recs = []
         for j in self.jobs:
             recs.extend(j.records())
-        self.handle = ibs.ibs_batch_build(recs, nlanes)
+        self.schedule = None
+        if nlanes == "auto":
+            stream = torch.cuda.current_stream().cuda_stream
+            nlanes, policy, ms = ibs.ibs_batch_autotune(recs, tune_reps, stream)
+            self.schedule = (nlanes, policy, ms)
+        self.handle = ibs.ibs_batch_build(recs, nlanes, policy)
 
     @property
     def cell_solves(self) -> int:

@@ -5,9 +5,13 @@
 // side; ibs_batch_launch() replays the whole batch with one hipGraphLaunch.
 // All solves that use the same workspace are placed on the same lane (the
 // workspace holds a call's fields and mutable state, so calls sharing it
-// must not overlap), and lanes are balanced greedily by the work of their
-// jobs.  The plans' device constants are only read, so jobs of one plan
-// with distinct workspaces may run side by side.
+// must not overlap); the workspaces are dealt to the lanes by a schedule
+// policy (balanced by work, or in submission order), and ibs_batch_autotune()
+// times the candidate lane counts and policies on the device and returns
+// the fastest.  The plans' device constants are only read, so jobs of one
+// plan with distinct workspaces may run side by side.  Every schedule runs
+// each job's launches in the same order on its own workspace, so the
+// results do not depend on the schedule.
 #include <algorithm>
 #include <map>
 #include <string>
@@ -35,41 +39,73 @@ static ibs_status fail_hip(hipError_t e, const char *where)
     return IBS_ERR_HIP;
 }
 
-extern "C" {
-
-ibs_status ibs_batch_build(const ibs_batch_job *jobs, int32_t njobs, int32_t nlanes, ibs_batch *out)
+// Lane of every workspace under a schedule policy (IBS_SCHED_*).
+static std::map<void *, int> assign_lanes(const ibs_batch_job *jobs, int njobs, int nlanes, int policy,
+                                          int &L)
 {
-    if (!jobs || njobs < 1 || !out || nlanes < 1 || nlanes > 64) {
-        set_error("jobs, out must be non-NULL, njobs >= 1, nlanes in [1, 64]");
-        return IBS_ERR_INVALID_ARG;
+    std::map<void *, double> cost;
+    std::vector<void *> first_seen;
+    for (int q = 0; q < njobs; ++q) {
+        Plan *p = reinterpret_cast<Plan *>(jobs[q].plan);
+        const double cells = (double)p->nx * p->ny * p->nz;
+        if (!cost.count(jobs[q].work)) first_seen.push_back(jobs[q].work);
+        cost[jobs[q].work] += cells * (jobs[q].op == IBS_OP_POISSON ? 1 : jobs[q].ncomp);
     }
-    *out = nullptr;
+    L = std::min<int>(nlanes, (int)first_seen.size());
+    std::map<void *, int> lane_of;
+    if (policy == IBS_SCHED_IN_ORDER) {
+        for (size_t w = 0; w < first_seen.size(); ++w) lane_of[first_seen[w]] = (int)(w % L);
+        return lane_of;
+    }
+    // balanced: largest workspace first, each to the least loaded lane
+    std::vector<std::pair<double, void *>> order;
+    for (void *w : first_seen) order.push_back({cost[w], w});
+    std::stable_sort(order.begin(), order.end(), [](auto &a, auto &b) { return a.first > b.first; });
+    std::vector<double> load(L, 0.0);
+    for (auto &o : order) {
+        int best = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        lane_of[o.second] = best;
+        load[best] += o.first;
+    }
+    return lane_of;
+}
+
+static ibs_status check_jobs(const ibs_batch_job *jobs, int32_t njobs)
+{
     for (int q = 0; q < njobs; ++q) {
         const ibs_batch_job &j = jobs[q];
         if (!j.plan) { set_error("job without a plan"); return IBS_ERR_INVALID_ARG; }
         if (j.op != IBS_OP_POISSON && j.op != IBS_OP_HELMHOLTZ_U) { set_error("job op must be IBS_OP_POISSON or IBS_OP_HELMHOLTZ_U"); return IBS_ERR_INVALID_ARG; }
         if (j.op == IBS_OP_HELMHOLTZ_U && (j.ncomp < 1 || j.ncomp > 3)) { set_error("Helmholtz job ncomp must be 1..3"); return IBS_ERR_INVALID_ARG; }
     }
-    // lane per workspace, greedy by work (cells x solve count)
-    std::map<void *, double> cost;
+    return IBS_OK;
+}
+
+extern "C" {
+
+ibs_status ibs_batch_build(const ibs_batch_job *jobs, int32_t njobs, int32_t nlanes, ibs_batch *out)
+{
+    return ibs_batch_build_sched(jobs, njobs, nlanes, IBS_SCHED_BALANCED, out);
+}
+
+ibs_status ibs_batch_build_sched(const ibs_batch_job *jobs, int32_t njobs, int32_t nlanes, int32_t policy,
+                                 ibs_batch *out)
+{
+    if (!jobs || njobs < 1 || !out || nlanes < 1 || nlanes > 64) {
+        set_error("jobs, out must be non-NULL, njobs >= 1, nlanes in [1, 64]");
+        return IBS_ERR_INVALID_ARG;
+    }
+    if (policy != IBS_SCHED_BALANCED && policy != IBS_SCHED_IN_ORDER) {
+        set_error("unknown schedule policy");
+        return IBS_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    ibs_status chk = check_jobs(jobs, njobs);
+    if (chk != IBS_OK) return chk;
     std::map<ibs_plan, int> plans;
-    for (int q = 0; q < njobs; ++q) {
-        Plan *p = reinterpret_cast<Plan *>(jobs[q].plan);
-        const double cells = (double)p->nx * p->ny * p->nz;
-        cost[jobs[q].work] += cells * (jobs[q].op == IBS_OP_POISSON ? 1 : jobs[q].ncomp);
-        plans[jobs[q].plan] = 1;
-    }
-    std::vector<std::pair<double, void *>> order;
-    for (auto &kv : cost) order.push_back({kv.second, kv.first});
-    std::stable_sort(order.begin(), order.end(), [](auto &a, auto &b) { return a.first > b.first; });
-    const int L = std::min<int>(nlanes, (int)order.size());
-    std::vector<double> load(L, 0.0);
-    std::map<void *, int> lane_of;
-    for (auto &o : order) {
-        int best = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        lane_of[o.second] = best;
-        load[best] += o.first;
-    }
+    for (int q = 0; q < njobs; ++q) plans[jobs[q].plan] = 1;
+    int L = 0;
+    std::map<void *, int> lane_of = assign_lanes(jobs, njobs, nlanes, policy, L);
 
     hipStream_t cap = nullptr;
     std::vector<hipStream_t> lanes(L, nullptr);
@@ -151,6 +187,66 @@ ibs_status ibs_batch_destroy(ibs_batch batch)
     if (batch->exec) hipGraphExecDestroy(batch->exec);
     if (batch->graph) hipGraphDestroy(batch->graph);
     delete batch;
+    return IBS_OK;
+}
+
+ibs_status ibs_batch_autotune(const ibs_batch_job *jobs, int32_t njobs, int32_t reps, int32_t *nlanes,
+                              int32_t *policy, float *ms, void *stream)
+{
+    if (!jobs || njobs < 1 || reps < 1 || reps > 100 || !nlanes || !policy) {
+        set_error("jobs, nlanes, policy must be non-NULL, njobs >= 1, reps in [1, 100]");
+        return IBS_ERR_INVALID_ARG;
+    }
+    ibs_status chk = check_jobs(jobs, njobs);
+    if (chk != IBS_OK) return chk;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // candidates: lane counts up to the number of workspaces, both policies
+    int nws = 0;
+    assign_lanes(jobs, njobs, 64, IBS_SCHED_BALANCED, nws);
+    struct Cand { int lanes, policy; float best; };
+    std::vector<int> counts;
+    for (int l : {1, 2, 4, 8, 12, 16, 24, 32, 48, 64}) {
+        const int ll = std::min(l, nws);
+        if (counts.empty() || counts.back() != ll) counts.push_back(ll);
+    }
+    std::vector<Cand> cands;
+    for (int ll : counts) {
+        cands.push_back({ll, IBS_SCHED_BALANCED, 1e30f});
+        if (ll > 1) cands.push_back({ll, IBS_SCHED_IN_ORDER, 1e30f});
+    }
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e;
+    if ((e = hipEventCreate(&ev[0])) != hipSuccess) return fail_hip(e, "autotune event");
+    if ((e = hipEventCreate(&ev[1])) != hipSuccess) { hipEventDestroy(ev[0]); return fail_hip(e, "autotune event"); }
+    ibs_status st = IBS_OK;
+    std::vector<ibs_batch> built(cands.size(), nullptr);
+    for (size_t c = 0; c < cands.size() && st == IBS_OK; ++c)
+        st = ibs_batch_build_sched(jobs, njobs, cands[c].lanes, cands[c].policy, &built[c]);
+    // one warm replay each, then three interleaved timed rounds; each
+    // candidate keeps its fastest round
+    constexpr int ROUNDS = 3;
+    for (int round = -1; round < ROUNDS && st == IBS_OK; ++round)
+        for (size_t c = 0; c < cands.size() && st == IBS_OK; ++c) {
+            const int n = round < 0 ? 1 : reps;
+            hipEventRecord(ev[0], s);
+            for (int r = 0; r < n && st == IBS_OK; ++r) st = ibs_batch_launch(built[c], s);
+            hipEventRecord(ev[1], s);
+            if (st != IBS_OK) break;
+            if ((e = hipEventSynchronize(ev[1])) != hipSuccess) { st = fail_hip(e, "autotune sync"); break; }
+            float t = 0.f;
+            hipEventElapsedTime(&t, ev[0], ev[1]);
+            if (round >= 0) cands[c].best = std::min(cands[c].best, t / n);
+        }
+    for (ibs_batch b : built) ibs_batch_destroy(b);
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+    if (st != IBS_OK) return st;
+    size_t pick = 0;
+    for (size_t c = 1; c < cands.size(); ++c)
+        if (cands[c].best < cands[pick].best) pick = c;
+    *nlanes = cands[pick].lanes;
+    *policy = cands[pick].policy;
+    if (ms) *ms = cands[pick].best;
     return IBS_OK;
 }
 

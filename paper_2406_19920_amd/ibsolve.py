@@ -34,7 +34,8 @@ EXPORTS = ("solver_plan", "solver_plan_bytes", "solver_plan_upload", "solver_pla
            "solve_poisson", "solve_poisson_noalloc", "solve_helmholtz_batch", "residual",
            "ibs_divergence", "ibs_wall_data", "ibs_stage_bytes", "ibs_rk_stage",
            "ibs_correct", "ibs_plan_export", "ibs_profile", "ibs_profile_read",
-           "ibs_batch_build", "ibs_batch_launch", "ibs_batch_destroy",
+           "ibs_batch_build", "ibs_batch_build_sched", "ibs_batch_autotune",
+           "ibs_batch_launch", "ibs_batch_destroy",
            "ibs_autotune_bytes", "ibs_autotune", "ibs_plan_set_tiles",
            "ibs_last_error", "ibs_version")
 
@@ -115,6 +116,9 @@ def _load():
     L.ibs_autotune.argtypes = [vp, vp, sz, ctypes.POINTER(i32), vp]
     L.ibs_plan_set_tiles.argtypes = [vp, ctypes.POINTER(i32), i32]
     L.ibs_batch_build.argtypes = [ctypes.POINTER(ibs_batch_job), i32, i32, ctypes.POINTER(vp)]
+    L.ibs_batch_build_sched.argtypes = [ctypes.POINTER(ibs_batch_job), i32, i32, i32, ctypes.POINTER(vp)]
+    L.ibs_batch_autotune.argtypes = [ctypes.POINTER(ibs_batch_job), i32, i32, ctypes.POINTER(i32),
+                                     ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float), vp]
     L.ibs_batch_launch.argtypes = [vp, vp]
     L.ibs_batch_destroy.argtypes = [vp]
     L.ibs_profile_read.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64),
@@ -270,11 +274,23 @@ def ibs_plan_set_tiles(plan, choices):
     _check(lib.ibs_plan_set_tiles(plan, arr, len(choices)), "ibs_plan_set_tiles")
 
 
-def ibs_batch_build(jobs, nlanes: int) -> int:
+IBS_SCHED_BALANCED, IBS_SCHED_IN_ORDER = 0, 1
+
+
+def ibs_batch_build(jobs, nlanes: int, policy: int = IBS_SCHED_BALANCED) -> int:
     arr = (ibs_batch_job * len(jobs))(*jobs)
     h = ctypes.c_void_p()
-    _check(lib.ibs_batch_build(arr, len(jobs), nlanes, ctypes.byref(h)), "ibs_batch_build")
+    _check(lib.ibs_batch_build_sched(arr, len(jobs), nlanes, policy, ctypes.byref(h)), "ibs_batch_build_sched")
     return h.value
+
+
+def ibs_batch_autotune(jobs, reps: int, stream: int):
+    """Returns (nlanes, policy, ms per replay) of the fastest schedule."""
+    arr = (ibs_batch_job * len(jobs))(*jobs)
+    nl, pol, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+    _check(lib.ibs_batch_autotune(arr, len(jobs), reps, ctypes.byref(nl), ctypes.byref(pol), ctypes.byref(ms),
+                                  stream), "ibs_batch_autotune")
+    return nl.value, pol.value, ms.value
 
 
 def ibs_batch_launch(batch: int, stream: int):

@@ -175,3 +175,38 @@ def test_batch_boundary_kinds(mods, refined):
         for k in range(4):
             assert j.solver.read_info(k).status == 0
     B.close()
+
+
+def test_schedule_autotuner(mods):
+    """The schedule autotuner returns a valid (lanes, policy) and a batch
+    built with it reproduces every job bitwise (each job's launches run in
+    the same order on its own workspace, whatever the schedule)."""
+    batch, ibs = mods
+    print("case batch schedule autotuner", flush=True)
+    B0 = batch.Batch(SPECS, precision=ibs.IBS_REFINED_BF16X3, nlanes=1)
+    B0.launch()
+    torch.cuda.synchronize()
+    ref = [[o.cpu().numpy().copy() for o in j.outputs()] for j in B0.jobs]
+    B0.close()
+    B = batch.Batch(SPECS, precision=ibs.IBS_REFINED_BF16X3, nlanes="auto")
+    nl, pol, ms = B.schedule
+    print("schedule", B.schedule, flush=True)
+    assert 1 <= nl <= len(SPECS) and pol in (ibs.IBS_SCHED_BALANCED, ibs.IBS_SCHED_IN_ORDER) and ms > 0
+    for j in B.jobs:
+        for o in j.outputs():
+            o.fill_(float("nan"))
+    B.launch()
+    torch.cuda.synchronize()
+    for q, j in enumerate(B.jobs):
+        for a, o in zip(ref[q], j.outputs()):
+            np.testing.assert_array_equal(o.cpu().numpy(), a)
+    # both policies at the largest lane count give the same results too
+    for policy in (ibs.IBS_SCHED_BALANCED, ibs.IBS_SCHED_IN_ORDER):
+        B2 = batch.Batch(SPECS, precision=ibs.IBS_REFINED_BF16X3, nlanes=len(SPECS), policy=policy)
+        B2.launch()
+        torch.cuda.synchronize()
+        for q, j in enumerate(B2.jobs):
+            for a, o in zip(ref[q], j.outputs()):
+                np.testing.assert_array_equal(o.cpu().numpy(), a)
+        B2.close()
+    B.close()
