@@ -95,7 +95,11 @@ class _CGeom(ctypes.Structure):
                 ("hx", ctypes.c_double), ("hz", ctypes.c_double),
                 ("dyc", ctypes.POINTER(ctypes.c_double)),
                 ("dyf", ctypes.POINTER(ctypes.c_double)),
-                ("py", ctypes.c_int), ("wx", ctypes.c_int), ("wz", ctypes.c_int)]
+                ("py", ctypes.c_int), ("wx", ctypes.c_int), ("wz", ctypes.c_int),
+                ("dxc", ctypes.POINTER(ctypes.c_double)),
+                ("dxf", ctypes.POINTER(ctypes.c_double)),
+                ("dzc", ctypes.POINTER(ctypes.c_double)),
+                ("dzf", ctypes.POINTER(ctypes.c_double))]
 
 
 class _CInfo(ctypes.Structure):
@@ -116,7 +120,10 @@ class Grid:
     u Dirichlet (zero on the wall faces; slot 0 of u is the wall face x = 0,
     the face x = lx is not stored), v and w Dirichlet through a mirror ghost,
     the pressure homogeneous Neumann.  periodic_z=False: the same walls at
-    z = 0 and z = lz (w's plane 0 is the wall face z = 0)."""
+    z = 0 and z = lz (w's plane 0 is the wall face z = 0).  A wall-bounded x
+    or z may be stretched like y (beta_x / xf_in, beta_z / zf_in; this
+    library's extension): its operators are the flux forms over the local
+    widths, dxc (cell widths) and dxf (centre distances)."""
     nx: int
     ny: int
     nz: int
@@ -128,6 +135,10 @@ class Grid:
     periodic_y: bool = False
     periodic_x: bool = True
     periodic_z: bool = True
+    beta_x: float = 0.0
+    xf_in: np.ndarray | None = None
+    beta_z: float = 0.0
+    zf_in: np.ndarray | None = None
     yf: np.ndarray = field(init=False)
     yc: np.ndarray = field(init=False)
     dyc: np.ndarray = field(init=False)
@@ -152,13 +163,42 @@ class Grid:
             if ny < 3:
                 raise ValueError("periodic y needs ny >= 3")
             self.dyf[0] = self.dyf[ny] = 0.5 * (self.dyc[0] + self.dyc[ny - 1])
-        self._c = _CGeom(self.nx, self.ny, self.nz, self.hx, self.hz,
-                         _dp(self.dyc), _dp(self.dyf), 1 if self.periodic_y else 0,
-                         0 if self.periodic_x else 1, 0 if self.periodic_z else 1)
         if not self.periodic_x and self.nx < 3:
             raise ValueError("walls in x need nx >= 3")
         if not self.periodic_z and self.nz < 3:
             raise ValueError("walls in z need nz >= 3")
+        self.stretched_x = self.beta_x != 0.0 or self.xf_in is not None
+        self.stretched_z = self.beta_z != 0.0 or self.zf_in is not None
+        if self.stretched_x and self.periodic_x:
+            raise ValueError("a stretched x needs walls in x")
+        if self.stretched_z and self.periodic_z:
+            raise ValueError("a stretched z needs walls in z")
+        self.xf, self.xc, self.dxc, self.dxf = self._axis(self.nx, self.lx, self.beta_x, self.xf_in)
+        self.zf, self.zc, self.dzc, self.dzf = self._axis(self.nz, self.lz, self.beta_z, self.zf_in)
+        self._c = _CGeom(self.nx, self.ny, self.nz, self.hx, self.hz,
+                         _dp(self.dyc), _dp(self.dyf), 1 if self.periodic_y else 0,
+                         0 if self.periodic_x else 1, 0 if self.periodic_z else 1,
+                         _dp(self.dxc) if self.stretched_x else None,
+                         _dp(self.dxf) if self.stretched_x else None,
+                         _dp(self.dzc) if self.stretched_z else None,
+                         _dp(self.dzf) if self.stretched_z else None)
+
+    @staticmethod
+    def _axis(n, length, beta, faces):
+        """Faces, centres, cell widths and centre distances of a wall-bounded
+        axis (the y construction); uniform: the widths are exactly h."""
+        f, c, dc, df = np.zeros(n + 1), np.zeros(n), np.zeros(n), np.zeros(n + 1)
+        fin = None if faces is None else np.ascontiguousarray(faces, dtype=np.float64)
+        if fin is not None:
+            assert fin.shape == (n + 1,)
+        rc = lib().orc_grid(n, length, beta, _dp(fin) if fin is not None else None,
+                            _dp(f), _dp(c), _dp(dc), _dp(df))
+        if rc != 0:
+            raise ValueError(f"orc_grid failed ({rc})")
+        if beta == 0.0 and fin is None:
+            dc[:] = length / n
+            df[:] = length / n
+        return f, c, dc, df
 
     @property
     def hx(self) -> float:

@@ -106,43 +106,48 @@ def gy_cells_to_faces_periodic(g: Grid) -> np.ndarray:
     return m
 
 
-def dx_faces_to_cells_walls(n: int, h: float) -> np.ndarray:
-    """(n x n), x walls: (F_{i+1} - F_i)/h with the face slots 0..n-1, slot
-    0 the wall face (its column is zero: u = 0 there) and face n absent."""
+def dx_faces_to_cells_walls(dc: np.ndarray) -> np.ndarray:
+    """(n x n), walls: (F_{i+1} - F_i)/Delta_i with the face slots 0..n-1,
+    slot 0 the wall face (its column is zero: u = 0 there) and face n
+    absent; dc[i] = Delta_i the cell widths (uniform: h)."""
+    n = len(dc)
     m = np.zeros((n, n))
     for i in range(n):
         if i + 1 < n:
-            m[i, i + 1] = 1.0 / h
+            m[i, i + 1] = 1.0 / dc[i]
         if i >= 1:
-            m[i, i] = -1.0 / h
+            m[i, i] = -1.0 / dc[i]
     return m
 
 
-def gx_cells_to_faces_walls(n: int, h: float) -> np.ndarray:
-    """(n x n), x walls: (f_i - f_{i-1})/h on the face slots 1..n-1, zero on
-    the wall slot 0 (homogeneous Neumann)."""
+def gx_cells_to_faces_walls(df: np.ndarray) -> np.ndarray:
+    """(n x n), walls: (f_i - f_{i-1})/delta_i on the face slots 1..n-1,
+    zero on the wall slot 0 (homogeneous Neumann); df[i] = delta_i the
+    centre distances (n+1 entries, 1..n-1 used)."""
+    n = len(df) - 1
     m = np.zeros((n, n))
     for i in range(1, n):
-        m[i, i] = 1.0 / h
-        m[i, i - 1] = -1.0 / h
+        m[i, i] = 1.0 / df[i]
+        m[i, i - 1] = -1.0 / df[i]
     return m
 
 
-def lx_mirror_walls(n: int, h: float) -> np.ndarray:
-    """(n x n) x part of the Laplacian of a cell-centred (in x) velocity with
-    Dirichlet walls: D over the n+1 faces of the gradient whose wall faces
-    take the mirror ghost (opposite sign, one cell away): 2 f_0/h and
-    -2 f_{n-1}/h."""
+def lx_mirror_walls(dc: np.ndarray, df: np.ndarray) -> np.ndarray:
+    """(n x n) part of the Laplacian of a velocity cell-centred along a
+    wall-bounded axis: D over the n+1 faces of the gradient whose wall faces
+    take the mirror ghost (opposite sign, one cell away, at distance
+    Delta/2): 2 f_0/Delta_0 and -2 f_{n-1}/Delta_{n-1}."""
+    n = len(dc)
     G = np.zeros((n + 1, n))
     for i in range(1, n):
-        G[i, i] = 1.0 / h
-        G[i, i - 1] = -1.0 / h
-    G[0, 0] = 2.0 / h
-    G[n, n - 1] = -2.0 / h
+        G[i, i] = 1.0 / df[i]
+        G[i, i - 1] = -1.0 / df[i]
+    G[0, 0] = 2.0 / dc[0]
+    G[n, n - 1] = -2.0 / dc[n - 1]
     D = np.zeros((n, n + 1))
     for i in range(n):
-        D[i, i + 1] = 1.0 / h
-        D[i, i] = -1.0 / h
+        D[i, i + 1] = 1.0 / dc[i]
+        D[i, i] = -1.0 / dc[i]
     return D @ G
 
 
@@ -153,10 +158,10 @@ def _k3(az, ay, ax):
 def divergence_matrix(g: Grid) -> np.ndarray:
     """D: cells <- (u faces, v faces incl. walls, w faces)."""
     Ix, Iy, Iz = np.eye(g.nx), np.eye(g.ny), np.eye(g.nz)
-    Dx = _circ_diff_fwd(g.nx, g.hx) if g.periodic_x else dx_faces_to_cells_walls(g.nx, g.hx)
+    Dx = _circ_diff_fwd(g.nx, g.hx) if g.periodic_x else dx_faces_to_cells_walls(g.dxc)
     Du = _k3(Iz, Iy, Dx)
     Dv = _k3(Iz, dy_faces_to_cells_periodic(g) if g.periodic_y else dy_faces_to_cells(g), Ix)
-    Dz = _circ_diff_fwd(g.nz, g.hz) if g.periodic_z else dx_faces_to_cells_walls(g.nz, g.hz)
+    Dz = _circ_diff_fwd(g.nz, g.hz) if g.periodic_z else dx_faces_to_cells_walls(g.dzc)
     Dw = _k3(Dz, Iy, Ix)
     return np.hstack([Du, Dv, Dw])
 
@@ -164,10 +169,10 @@ def divergence_matrix(g: Grid) -> np.ndarray:
 def gradient_matrix(g: Grid) -> np.ndarray:
     """G: (u faces, v faces incl. walls, w faces) <- cells."""
     Ix, Iy, Iz = np.eye(g.nx), np.eye(g.ny), np.eye(g.nz)
-    Gx = _circ_diff_bwd(g.nx, g.hx) if g.periodic_x else gx_cells_to_faces_walls(g.nx, g.hx)
+    Gx = _circ_diff_bwd(g.nx, g.hx) if g.periodic_x else gx_cells_to_faces_walls(g.dxf)
     Gu = _k3(Iz, Iy, Gx)
     Gv = _k3(Iz, gy_cells_to_faces_periodic(g) if g.periodic_y else gy_cells_to_faces_neumann(g), Ix)
-    Gz = _circ_diff_bwd(g.nz, g.hz) if g.periodic_z else gx_cells_to_faces_walls(g.nz, g.hz)
+    Gz = _circ_diff_bwd(g.nz, g.hz) if g.periodic_z else gx_cells_to_faces_walls(g.dzf)
     Gw = _k3(Gz, Iy, Ix)
     return np.vstack([Gu, Gv, Gw])
 
@@ -180,19 +185,19 @@ def laplacian(g: Grid, op: int) -> np.ndarray:
     if g.periodic_x:
         Lx = _circ_diff_bwd(g.nx, g.hx) @ _circ_diff_fwd(g.nx, g.hx)
     elif op == OP_U:
-        full = gx_cells_to_faces_walls(g.nx, g.hx) @ dx_faces_to_cells_walls(g.nx, g.hx)
+        full = gx_cells_to_faces_walls(g.dxf) @ dx_faces_to_cells_walls(g.dxc)
         Lx = full[1:, 1:]
         Ix = np.eye(g.nx - 1)
     else:
-        Lx = lx_mirror_walls(g.nx, g.hx)
+        Lx = lx_mirror_walls(g.dxc, g.dxf)
     if g.periodic_z:
         Lz = _circ_diff_bwd(g.nz, g.hz) @ _circ_diff_fwd(g.nz, g.hz)
     elif op == OP_W:
-        full = gx_cells_to_faces_walls(g.nz, g.hz) @ dx_faces_to_cells_walls(g.nz, g.hz)
+        full = gx_cells_to_faces_walls(g.dzf) @ dx_faces_to_cells_walls(g.dzc)
         Lz = full[1:, 1:]
         Iz = np.eye(g.nz - 1)
     else:
-        Lz = lx_mirror_walls(g.nz, g.hz)
+        Lz = lx_mirror_walls(g.dzc, g.dzf)
     if g.periodic_y:
         Iy = np.eye(g.ny)
         if op in (OP_U, OP_W):
@@ -225,7 +230,10 @@ def weights(g: Grid, op: int) -> np.ndarray:
     else:
         wy = g.dyc
         nyu = g.ny
-    return np.broadcast_to((g.hx * g.hz * wy)[None, :, None], (nzu, nyu, nxu)).reshape(-1).copy()
+    # control-cell widths in x and z: cells Delta, faces delta (slots 1..n-1)
+    wx = g.dxf[1:g.nx] if (op == OP_U and not g.periodic_x) else g.dxc
+    wz = g.dzf[1:g.nz] if (op == OP_W and not g.periodic_z) else g.dzc
+    return (wz[:, None, None] * wy[None, :, None] * wx[None, None, :]).reshape(-1).copy()
 
 
 def operator(g: Grid, op: int, c: float = 0.0) -> np.ndarray:

@@ -53,6 +53,9 @@
  * Walls in z (flag wz) are the same construction along z: w's plane k holds
  * the face z = k hz, plane 0 being the wall face (unknowns: planes
  * 1..nz-1); u and v take the mirror-ghost row, the pressure zero flux.
+ * A wall-bounded x or z may be stretched (dxc/dxf, dzc/dzf): its rows are
+ * then the flux forms with the local widths, as the y rows are, and the
+ * weights W carry the local widths too.
  *
  * Operator codes: 0 = pressure Poisson (A = L_p), 1 = u Helmholtz,
  * 2 = v Helmholtz, 3 = w Helmholtz (A = I - c L).
@@ -80,6 +83,12 @@ typedef struct {
                        /*    periodic x (see the header comment)        */
     int wz;            /* 1: walls at z = 0 and z = lz, the same way    */
                        /*    (w's plane 0 is the wall face z = 0)       */
+    const double *dxc; /* NULL, or with walls in x the cell widths      */
+                       /*    Delta^x_i [nx] of a stretched x            */
+    const double *dxf; /*    and the centre distances delta^x_i [nx+1]  */
+                       /*    (valid for i = 1..nx-1)                    */
+    const double *dzc; /* the same for a stretched z with walls         */
+    const double *dzf;
 } orc_geom;
 
 typedef struct {
@@ -135,6 +144,11 @@ static inline int64_t vidx(const orc_geom *g, int i, int j, int k)
     return ((int64_t)k * vrows(g) + j) * g->nx + i;
 }
 static inline int wrap(int i, int n) { return (i % n + n) % n; }
+/* local widths: cell width and centre distance in x and z (uniform: h) */
+static inline double DX(const orc_geom *g, int i) { return g->dxc ? g->dxc[i] : g->hx; }
+static inline double DXF(const orc_geom *g, int i) { return g->dxf ? g->dxf[i] : g->hx; }
+static inline double DZ(const orc_geom *g, int k) { return g->dzc ? g->dzc[k] : g->hz; }
+static inline double DZF(const orc_geom *g, int k) { return g->dzf ? g->dzf[k] : g->hz; }
 
 /* ------------------------------------------------------------------ */
 /* Divergence and gradient (Section 2.1; kernels E2 and E3).           */
@@ -152,13 +166,13 @@ void orc_divergence(const orc_geom *g, const double *u, const double *v,
                 /* x walls: u = 0 on the wall faces 0 and nx */
                 double ue = (g->wx && i + 1 == g->nx) ? 0.0 : u[cidx(g, wrap(i + 1, g->nx), j, k)];
                 double uw = (g->wx && i == 0) ? 0.0 : u[cidx(g, i, j, k)];
-                double du = (ue - uw) / g->hx;
+                double du = (ue - uw) / DX(g, i);
                 /* z walls: w = 0 on the wall faces 0 and nz */
                 double wt = (g->wz && k + 1 == g->nz) ? 0.0 : w[cidx(g, i, j, wrap(k + 1, g->nz))];
                 double wb = (g->wz && k == 0) ? 0.0 : w[cidx(g, i, j, k)];
                 int jt = (g->py && j + 1 == g->ny) ? 0 : j + 1;   /* face ny = face 0 */
                 double dv = (v[vidx(g, i, jt, k)] - v[vidx(g, i, j, k)]) / g->dyc[j];
-                double dw = (wt - wb) / g->hz;
+                double dw = (wt - wb) / DZ(g, k);
                 b[cidx(g, i, j, k)] = scale * (du + dv + dw);
             }
 }
@@ -178,18 +192,18 @@ void orc_gradient(const orc_geom *g, const double *phi, double *gu, double *gv,
                     /* every face is interior; face 0 lies between cells
                      * ny-1 and 0, dyf[0] apart */
                     gu[cidx(g, i, j, k)] = (g->wx && i == 0) ? 0.0 :
-                        (phi[cidx(g, i, j, k)] - phi[cidx(g, wrap(i - 1, g->nx), j, k)]) / g->hx;
+                        (phi[cidx(g, i, j, k)] - phi[cidx(g, wrap(i - 1, g->nx), j, k)]) / DXF(g, i);
                     gw[cidx(g, i, j, k)] = (g->wz && k == 0) ? 0.0 :
-                        (phi[cidx(g, i, j, k)] - phi[cidx(g, i, j, wrap(k - 1, g->nz))]) / g->hz;
+                        (phi[cidx(g, i, j, k)] - phi[cidx(g, i, j, wrap(k - 1, g->nz))]) / DZF(g, k);
                     gv[vidx(g, i, j, k)] =
                         (phi[cidx(g, i, j, k)] - phi[cidx(g, i, wrap(j - 1, g->ny), k)]) / g->dyf[j];
                     continue;
                 }
                 if (j < g->ny) {
                     gu[cidx(g, i, j, k)] = (g->wx && i == 0) ? 0.0 :
-                        (phi[cidx(g, i, j, k)] - phi[cidx(g, wrap(i - 1, g->nx), j, k)]) / g->hx;
+                        (phi[cidx(g, i, j, k)] - phi[cidx(g, wrap(i - 1, g->nx), j, k)]) / DXF(g, i);
                     gw[cidx(g, i, j, k)] = (g->wz && k == 0) ? 0.0 :
-                        (phi[cidx(g, i, j, k)] - phi[cidx(g, i, j, wrap(k - 1, g->nz))]) / g->hz;
+                        (phi[cidx(g, i, j, k)] - phi[cidx(g, i, j, wrap(k - 1, g->nz))]) / DZF(g, k);
                 }
                 if (j == 0 || j == g->ny)
                     gv[vidx(g, i, j, k)] = 0.0;
@@ -250,13 +264,16 @@ static int64_t unknown_to_array(const orc_geom *g, int op, int64_t r)
     unknown_ijk(g, op, r, &i, &j, &k);
     return (op == 2) ? vidx(g, i, j, k) : cidx(g, i, j, k);
 }
-/* weight W of unknown r: hx hz Delta_j (cells and cell-height faces),
- * hx hz delta_j (y faces) */
+/* weight W of unknown r: the volume of its control cell, Delta^x Delta_j
+ * Delta^z for cells, with delta_j for y faces, delta^x for x faces and
+ * delta^z for z faces (uniform x, z: hx, hz) */
 static double unknown_weight(const orc_geom *g, int op, int64_t r)
 {
     int i, j, k;
     unknown_ijk(g, op, r, &i, &j, &k);
-    return g->hx * g->hz * ((op == 2) ? g->dyf[j] : g->dyc[j]);
+    const double wxi = (op == 1) ? DXF(g, i) : DX(g, i);
+    const double wzk = (op == 3) ? DZF(g, k) : DZ(g, k);
+    return wxi * wzk * ((op == 2) ? g->dyf[j] : g->dyc[j]);
 }
 
 /* ------------------------------------------------------------------ */
@@ -282,45 +299,56 @@ static int laplacian_row(const orc_geom *g, int op, int i, int j, int k,
         n = add_entry(cols, vals, n, me, -2.0 * az);
         n = add_entry(cols, vals, n, unknown_id(g, op, i, j, wrap(k - 1, g->nz)), az);
         n = add_entry(cols, vals, n, unknown_id(g, op, i, j, wrap(k + 1, g->nz)), az);
-    } else if (op == 3) { /* z faces 1..nz-1, wall values w_0 = w_nz = 0 */
-        n = add_entry(cols, vals, n, me, -2.0 * az);
-        if (k + 1 <= g->nz - 1) n = add_entry(cols, vals, n, unknown_id(g, op, i, j, k + 1), az);
-        if (k - 1 >= 1) n = add_entry(cols, vals, n, unknown_id(g, op, i, j, k - 1), az);
+    } else if (op == 3) { /* z faces 1..nz-1, wall values w_0 = w_nz = 0:
+                           * ((w_{k+1}-w_k)/Dz_k - (w_k-w_{k-1})/Dz_{k-1}) / dz_k */
+        const double at = 1.0 / (DZ(g, k) * DZF(g, k)), ab = 1.0 / (DZ(g, k - 1) * DZF(g, k));
+        n = add_entry(cols, vals, n, me, -at - ab);
+        if (k + 1 <= g->nz - 1) n = add_entry(cols, vals, n, unknown_id(g, op, i, j, k + 1), at);
+        if (k - 1 >= 1) n = add_entry(cols, vals, n, unknown_id(g, op, i, j, k - 1), ab);
     } else { /* cell centres in z: Neumann (pressure) or mirror ghost (u, v) */
+        const double D = DZ(g, k);
         if (k + 1 < g->nz) {
-            n = add_entry(cols, vals, n, me, -az);
-            n = add_entry(cols, vals, n, unknown_id(g, op, i, j, k + 1), az);
+            const double a = 1.0 / (DZF(g, k + 1) * D);
+            n = add_entry(cols, vals, n, me, -a);
+            n = add_entry(cols, vals, n, unknown_id(g, op, i, j, k + 1), a);
         } else if (op != 0) {
-            n = add_entry(cols, vals, n, me, -2.0 * az);
+            n = add_entry(cols, vals, n, me, -2.0 / (D * D));
         }
         if (k > 0) {
-            n = add_entry(cols, vals, n, me, -az);
-            n = add_entry(cols, vals, n, unknown_id(g, op, i, j, k - 1), az);
+            const double a = 1.0 / (DZF(g, k) * D);
+            n = add_entry(cols, vals, n, me, -a);
+            n = add_entry(cols, vals, n, unknown_id(g, op, i, j, k - 1), a);
         } else if (op != 0) {
-            n = add_entry(cols, vals, n, me, -2.0 * az);
+            n = add_entry(cols, vals, n, me, -2.0 / (D * D));
         }
     }
     if (!g->wx) { /* periodic x: the same */
         n = add_entry(cols, vals, n, me, -2.0 * ax);
         n = add_entry(cols, vals, n, unknown_id(g, op, wrap(i - 1, g->nx), j, k), ax);
         n = add_entry(cols, vals, n, unknown_id(g, op, wrap(i + 1, g->nx), j, k), ax);
-    } else if (op == 1) { /* x faces 1..nx-1, wall values u_0 = u_nx = 0 */
-        n = add_entry(cols, vals, n, me, -2.0 * ax);
-        if (i + 1 <= g->nx - 1) n = add_entry(cols, vals, n, unknown_id(g, op, i + 1, j, k), ax);
-        if (i - 1 >= 1) n = add_entry(cols, vals, n, unknown_id(g, op, i - 1, j, k), ax);
-    } else { /* cell centres in x: interior flux, or at a wall zero flux
-              * (pressure, Neumann) or the mirror-ghost flux -2 f/hx (v, w) */
+    } else if (op == 1) { /* x faces 1..nx-1, wall values u_0 = u_nx = 0:
+                           * ((u_{i+1}-u_i)/Dx_i - (u_i-u_{i-1})/Dx_{i-1}) / dx_i */
+        const double ae = 1.0 / (DX(g, i) * DXF(g, i)), aw = 1.0 / (DX(g, i - 1) * DXF(g, i));
+        n = add_entry(cols, vals, n, me, -ae - aw);
+        if (i + 1 <= g->nx - 1) n = add_entry(cols, vals, n, unknown_id(g, op, i + 1, j, k), ae);
+        if (i - 1 >= 1) n = add_entry(cols, vals, n, unknown_id(g, op, i - 1, j, k), aw);
+    } else { /* cell centres in x: interior flux over delta^x, or at a wall
+              * zero flux (pressure, Neumann) or the mirror-ghost flux
+              * -2 f/Dx (v, w); divided by Dx_i */
+        const double D = DX(g, i);
         if (i + 1 < g->nx) {
-            n = add_entry(cols, vals, n, me, -ax);
-            n = add_entry(cols, vals, n, unknown_id(g, op, i + 1, j, k), ax);
+            const double a = 1.0 / (DXF(g, i + 1) * D);
+            n = add_entry(cols, vals, n, me, -a);
+            n = add_entry(cols, vals, n, unknown_id(g, op, i + 1, j, k), a);
         } else if (op != 0) {
-            n = add_entry(cols, vals, n, me, -2.0 * ax);
+            n = add_entry(cols, vals, n, me, -2.0 / (D * D));
         }
         if (i > 0) {
-            n = add_entry(cols, vals, n, me, -ax);
-            n = add_entry(cols, vals, n, unknown_id(g, op, i - 1, j, k), ax);
+            const double a = 1.0 / (DXF(g, i) * D);
+            n = add_entry(cols, vals, n, me, -a);
+            n = add_entry(cols, vals, n, unknown_id(g, op, i - 1, j, k), a);
         } else if (op != 0) {
-            n = add_entry(cols, vals, n, me, -2.0 * ax);
+            n = add_entry(cols, vals, n, me, -2.0 / (D * D));
         }
     }
     const int ny = g->ny;
@@ -451,13 +479,16 @@ static long double flux_apply_bc_ld(const orc_geom *g, int op, int i, int j, int
     } else if (op == 3) { /* faces: wall values w_0 = w_nz = 0 */
         long double xt = (k + 1 <= nz - 1) ? (long double)x[at(g, i, j, k + 1)] : 0.0L;
         long double xb = (k - 1 >= 1) ? (long double)x[at(g, i, j, k - 1)] : 0.0L;
-        ft = (xt - xc) / hz;
-        fb = (xc - xb) / hz;
+        ft = (xt - xc) / (long double)DZ(g, k);
+        fb = (xc - xb) / (long double)DZ(g, k - 1);
+        hz = DZF(g, k);
     } else { /* cells: Neumann (pressure) or mirror ghost (u, v) at a wall */
-        ft = (k + 1 < nz) ? ((long double)x[at(g, i, j, k + 1)] - xc) / hz
-                          : (op == 0 ? 0.0L : -xc / (hz / 2.0L));
-        fb = (k > 0) ? (xc - (long double)x[at(g, i, j, k - 1)]) / hz
-                     : (op == 0 ? 0.0L : xc / (hz / 2.0L));
+        const long double D = DZ(g, k);
+        ft = (k + 1 < nz) ? ((long double)x[at(g, i, j, k + 1)] - xc) / (long double)DZF(g, k + 1)
+                          : (op == 0 ? 0.0L : -xc / (D / 2.0L));
+        fb = (k > 0) ? (xc - (long double)x[at(g, i, j, k - 1)]) / (long double)DZF(g, k)
+                     : (op == 0 ? 0.0L : xc / (D / 2.0L));
+        hz = D;
     }
     long double fe, fw;   /* x fluxes through the east and west sides */
     if (!g->wx) {
@@ -466,13 +497,16 @@ static long double flux_apply_bc_ld(const orc_geom *g, int op, int i, int j, int
     } else if (op == 1) { /* faces: wall values u_0 = u_nx = 0 */
         long double xe = (i + 1 <= nx - 1) ? (long double)x[at(g, i + 1, j, k)] : 0.0L;
         long double xw = (i - 1 >= 1) ? (long double)x[at(g, i - 1, j, k)] : 0.0L;
-        fe = (xe - xc) / hx;
-        fw = (xc - xw) / hx;
+        fe = (xe - xc) / (long double)DX(g, i);
+        fw = (xc - xw) / (long double)DX(g, i - 1);
+        hx = DXF(g, i);
     } else { /* cells: Neumann (pressure) or mirror ghost (v, w) at a wall */
-        fe = (i + 1 < nx) ? ((long double)x[at(g, i + 1, j, k)] - xc) / hx
-                          : (op == 0 ? 0.0L : -xc / (hx / 2.0L));
-        fw = (i > 0) ? (xc - (long double)x[at(g, i - 1, j, k)]) / hx
-                     : (op == 0 ? 0.0L : xc / (hx / 2.0L));
+        const long double D = DX(g, i);
+        fe = (i + 1 < nx) ? ((long double)x[at(g, i + 1, j, k)] - xc) / (long double)DXF(g, i + 1)
+                          : (op == 0 ? 0.0L : -xc / (D / 2.0L));
+        fw = (i > 0) ? (xc - (long double)x[at(g, i - 1, j, k)]) / (long double)DXF(g, i)
+                     : (op == 0 ? 0.0L : xc / (D / 2.0L));
+        hx = D;
     }
     long double lap = (fe - fw) / hx + (ft - fb) / hz;
     if (g->py) {

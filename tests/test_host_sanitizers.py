@@ -40,4 +40,4 @@ def test_oracle_sanitized(tmp_path):
           os.path.join(ROOT, "oracle", "orc.c"), "-o", str(exe), "-lm"])
     r = _run([str(exe)], env=ENV)
     assert "runtime error" not in r.stderr
-    assert r.stdout.count("rel") == 32
+    assert r.stdout.count("rel") == 48
