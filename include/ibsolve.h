@@ -104,7 +104,15 @@ typedef enum { IBS_PERIODIC = 0, IBS_DIRICHLET = 1, IBS_NEUMANN = 2 } ibs_bc;
  * Walls in z (bc_z = IBS_DIRICHLET) are the same along z, w being the
  * face-normal component: w's plane 0 is the wall face z = 0 (ignored on
  * input, zero on output), the face z = lz is not stored; u and v take the
- * mirror-ghost row.  Walls in x and z together make a duct. */
+ * mirror-ghost row.  Walls in x and z together make a duct.
+ * A wall-bounded x or z may be stretched (x_faces / z_faces: this
+ * library's extension of the uniform grid of Section 2.1, as y's): every
+ * operator along it is then the flux form over the local cell widths
+ * Delta_i = f[i+1] - f[i] and centre distances delta_i (as in y), the
+ * pressure's volume weights take Delta_x Delta_y Delta_z, and the
+ * transforms along it are the generalised eigenbases of S q = lambda W q
+ * (S the symmetric flux form, W the control widths), computed when the
+ * plan is built (implicit QL in long double; O(n^3) host time). */
 typedef struct {
     int32_t nx, ny, nz;
     double lx, ly, lz;        /* <= 0 means 1                                */
@@ -127,6 +135,12 @@ typedef struct {
                                  (checked in FP64 on b itself) reports
                                  IBS_ERR_INCOMPATIBLE_RHS in info (the solve
                                  still runs, with the mean removed)          */
+    const double *x_faces;    /* optional host array [nx+1], finite and
+                                 strictly increasing, the x faces of a
+                                 stretched x (bc_x = IBS_DIRICHLET only);
+                                 overrides lx (= x_faces[nx] - x_faces[0]);
+                                 copied.  NULL: uniform                      */
+    const double *z_faces;    /* the same for z ([nz+1], bc_z walls)         */
 } ibs_grid_desc;
 
 /* Per-solve report, written by the device at the end of the solve.  Must
@@ -387,7 +401,11 @@ ibs_status ibs_batch_destroy(ibs_batch batch);
  * the pressure's x basis; with walls in x, 17 and 18 are Q_x of v/w and of
  * u, 19 and 20 their lambda_x (periodic x: the same as 1 and 3); with walls
  * in z, 21 and 22 are Q_z of u/v and of w, 23 and 24 their lambda_z
- * (periodic z: the same as 2 and 4).
+ * (periodic z: the same as 2 and 4).  The Q tables are the forward
+ * transforms, xhat_a = sum_i Q[i*n+a] x_i; 25 + k (x) and 28 + k (z) are
+ * the inverse transforms G of kind k (0 pressure, 1 mirror-ghost velocity
+ * components, 2 the face-normal one), x_i = sum_a G[i*n+a] xhat_a, equal
+ * to Q except on a stretched axis; 31 and 32 the x and z faces [n+1].
  * out: host array of n doubles; n must equal the table length (queried by
  * passing out = NULL, which returns the length through *n). */
 ibs_status ibs_plan_export(ibs_plan plan, int32_t table, double *out, size_t *n);

@@ -810,6 +810,14 @@ ibs_status ibs_plan_export(ibs_plan plan, int32_t table, double *out, size_t *n)
             const bool zax = table - 5 - 3 * NUM_KINDS >= 4;
             const int k = (t % 2 == 0) ? XK_C : XK_F;
             v = t < 2 ? (zax ? &p.qz[k] : &p.qx[k]) : (zax ? &p.lam_z[k] : &p.lam_x[k]);
+        } else if (table >= 25 && table < 25 + 2 * NUM_XK) {
+            // the inverse bases of kind XK_P, XK_C, XK_F: x, then z
+            const int k = (table - 25) % NUM_XK;
+            v = table - 25 < NUM_XK ? &p.gx[k] : &p.gz[k];
+        } else if (table == 31) {
+            v = &p.xf;
+        } else if (table == 32) {
+            v = &p.zf;
         }
     }
     if (!v) { set_error("unknown table"); return IBS_ERR_INVALID_ARG; }

@@ -53,6 +53,8 @@ struct BlobLayout {
     size_t szf_fwd, szf_inv; // folded z transform factors, bf16x3 split (nz % 64 == 0)
     size_t lane_mask;        // refined: per z-mode bit mask of FP64-lane x-tiles (uint32 [nz])
     size_t lane_list;        // refined: FP64-lane tiles, (c << 8) | t (int [lane_len])
+    size_t sgx, sgz;         // stretched wall-bounded x / z: SG_SLOTS arrays of n doubles
+                             // each (StretchSlot), else empty
     size_t total;
 };
 
@@ -111,16 +113,36 @@ struct Profile {
 enum { TUNE_XFOLD = 0, TUNE_ZFOLD, NUM_TUNE };
 static_assert(NUM_TUNE == IBS_NUM_TUNE, "tuning knobs and the ABI disagree");
 
+// Per-index geometry of a stretched wall-bounded axis (n cells, widths
+// Delta_i, centre distances delta_i), SG_SLOTS consecutive arrays of n
+// doubles.  The 3-point rows along the axis are ae[i] (x_{i+1} - x_i) -
+// aw[i] (x_i - x_{i-1}), a missing neighbour being the wall ghost (x_i for
+// the pressure, -x_i for the mirror kind, 0 for the face kind), per kind:
+//   XK_P cells: ae = 1/(delta_{i+1} Delta_i), aw = 1/(delta_i Delta_i)
+//   XK_C cells: the same, the wall ones 1/Delta^2 (mirror ghost)
+//   XK_F faces 1..n-1: ae = 1/(Delta_i delta_i), aw = 1/(Delta_{i-1} delta_i)
+// (slots not used by a row hold 0).  rc = 1/Delta_i (divergence), rf =
+// 1/delta_i (gradient; rf[0] = 0), wn = Delta_i / hbar (the cell's share
+// of the volume weight, hbar the mean width).
+enum StretchSlot { SG_RC = 0, SG_RF = 1, SG_WN = 2, SG_AE = 3, SG_AW = 4, SG_SLOTS = 3 + 2 * NUM_XK };
+__host__ __device__ inline int sg_ae(int xk) { return SG_AE + 2 * xk; }
+__host__ __device__ inline int sg_aw(int xk) { return SG_AW + 2 * xk; }
+
 struct Plan {
     ibs_grid_desc desc;
     bool py = false;                               // y periodic (no walls)
     bool wx = false;                               // walls at x = 0 and x = lx
     bool wz = false;                               // walls at z = 0 and z = lz
+    bool sx = false, sz = false;                   // stretched (wall-bounded) x / z
     int tune[NUM_TUNE] = {-1, -1};   // candidate index per knob; -1 = default
     int nx, ny, nz;
     double hx, hz;
     std::vector<double> yf, yc, dyc, dyf;          // grid
+    std::vector<double> xf, zf;                    // x / z faces [n+1] (uniform: i h)
     std::vector<double> qx[NUM_XK], qz[NUM_XK];    // Q[i][a], row-major n x n, per x / z kind
+                                                   // (forward: xhat_a = sum_i Q[i][a] x_i)
+    std::vector<double> gx[NUM_XK], gz[NUM_XK];    // inverse bases: x_i = sum_a G[i][a] xhat_a
+                                                   // (G = Q unless stretched)
     std::vector<double> lam_x[NUM_XK], lam_z[NUM_XK];
     std::vector<double> lo[NUM_KINDS], di[NUM_KINDS], up[NUM_KINDS];
     int rows[NUM_KINDS];

@@ -1012,7 +1012,11 @@ __global__ __launch_bounds__(512) void split_zfold_kernel(SplitSet ss, int N, in
 // registers (each x value is read from HBM about once; y neighbours come
 // from the same or adjacent blocks' rows).  grid: (tiles per job, jobs),
 // the same tile count for all jobs.
-template <typename Tx>
+// ST: a stretched wall-bounded x and/or z (sgx / sgz the per-index
+// geometry, StretchSlot layout, null for a uniform axis): the x and z rows
+// take their per-index coefficients, and the weighted sums Delta_j x
+// become W x with the cells' x and z shares of the volume weight.
+template <typename Tx, bool ST>
 __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, int ny, int nz,
                                                            double ihx2, double ihz2,
                                                            const double *__restrict__ dyc,
@@ -1020,7 +1024,9 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
                                                            const double *__restrict__ bmean,
                                                            double *__restrict__ xsum,
                                                            const int *__restrict__ skip, int rb_rows,
-                                                           int tiles_y, int rz, int py, int wxw, int wzw)
+                                                           int tiles_y, int rz, int py, int wxw, int wzw,
+                                                           const double *__restrict__ sgx,
+                                                           const double *__restrict__ sgz)
 {
     typedef Tx tx4 __attribute__((ext_vector_type(4)));
     typedef double dv4_ __attribute__((ext_vector_type(4)));
@@ -1096,6 +1102,22 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
         const bool zw_w = wzw && op == IBS_OP_HELMHOLTZ_W;
         const double gz = pois ? 1.0 : (op == IBS_OP_HELMHOLTZ_W ? 0.0 : -1.0);
         auto ld4 = [&](size_t at) { return *reinterpret_cast<const tx4 *>(x + at); };
+        // stretched: this thread's x coefficients and volume shares
+        const int xkd = pois ? XK_P : (op == IBS_OP_HELMHOLTZ_U ? XK_F : XK_C);
+        const int zkd = pois ? XK_P : (op == IBS_OP_HELMHOLTZ_W ? XK_F : XK_C);
+        double aex[4], awx[4], wnx[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            aex[e] = awx[e] = ihx2;
+            wnx[e] = 1.0;
+            if constexpr (ST) {
+                if (sgx) {
+                    aex[e] = sgx[(size_t)sg_ae(xkd) * nx + i0 + e];
+                    awx[e] = sgx[(size_t)sg_aw(xkd) * nx + i0 + e];
+                    wnx[e] = sgx[(size_t)SG_WN * nx + i0 + e];
+                }
+            }
+        }
         tx4 xm = ld4((size_t)(k0 == 0 ? nz - 1 : k0 - 1) * plane + o + i0);
         tx4 xc = ld4((size_t)k0 * plane + o + i0);
 #pragma unroll 2
@@ -1105,6 +1127,14 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
             const tx4 xu = ld4((size_t)((ptrdiff_t)c + du + i0)), xl = ld4((size_t)((ptrdiff_t)c - dl + i0));
             const double xwe = (double)x[c + iw], xee = (double)x[c + ie];
             const dv4_ bv = *reinterpret_cast<const dv4_ *>(bb + c + i0);
+            double aez = ihz2, awz = ihz2, wnz = 1.0;
+            if constexpr (ST) {
+                if (sgz) {
+                    aez = sgz[(size_t)sg_ae(zkd) * nz + k];
+                    awz = sgz[(size_t)sg_aw(zkd) * nz + k];
+                    wnz = sgz[(size_t)SG_WN * nz + k];
+                }
+            }
             fv4 rv;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -1126,11 +1156,16 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
                     if (zw_w && k == 1) zm = 0.0;
                     xwall = xwall || (zw_w && k == 0);
                 }
-                double lap = ((xe - xcc) - (xcc - xw)) * ihx2 + ((zp - xcc) - (xcc - zm)) * ihz2;
+                double lap;
+                if constexpr (ST)
+                    lap = (xe - xcc) * aex[e] - (xcc - xw) * awx[e] + (zp - xcc) * aez - (xcc - zm) * awz;
+                else
+                    lap = ((xe - xcc) - (xcc - xw)) * ihx2 + ((zp - xcc) - (xcc - zm)) * ihz2;
                 lap += cu * (wu * (double)xu[e] - xcc) - cl * (xcc - wl * (double)xl[e]);
                 const double ax = pois ? lap : xcc - cj * lap;
                 rv[e] = (wall || xwall) ? 0.f : (float)((bv[e] - bm) - ax);
-                wx += wD * xcc;
+                if constexpr (ST) wx += wD * wnx[e] * wnz * xcc;
+                else wx += wD * xcc;
             }
             *reinterpret_cast<fv4 *>(rr + c + i0) = rv;
             xm = xc;
@@ -1446,10 +1481,12 @@ hipError_t launch_residual_f32(const SplitSet &ss, const Plan &p, const State &s
         hipLaunchKernelGGL(kernel, grid, dim3(256), 0, s, ss, p.nx, p.ny, p.nz, 1.0 / (p.hx * p.hx),
                            1.0 / (p.hz * p.hz), blob_ptr(p, p.lay.dyc), blob_ptr(p, p.lay.dyf),
                            st.bmean, st.xsum, skip, rb_rows, tiles_y, rz, p.py ? 1 : 0, p.wx ? 1 : 0,
-                           p.wz ? 1 : 0);
+                           p.wz ? 1 : 0, p.sx ? blob_ptr(p, p.lay.sgx) : nullptr,
+                           p.sz ? blob_ptr(p, p.lay.sgz) : nullptr);
     };
-    if (x32) go(residual_f32_kernel<float>);
-    else go(residual_f32_kernel<double>);
+    const bool st_ = p.sx || p.sz;
+    if (x32) st_ ? go(residual_f32_kernel<float, true>) : go(residual_f32_kernel<float, false>);
+    else st_ ? go(residual_f32_kernel<double, true>) : go(residual_f32_kernel<double, false>);
     return hipGetLastError();
 }
 

@@ -17,7 +17,20 @@ struct Geo {
     int wx;                   // walls in x: u slot 0 is the wall face x = 0
                               // (zero), face nx is not stored (zero)
     int wz;                   // walls in z: the same for w's plane 0
+    const double *sgx, *sgz;  // stretched wall-bounded x / z: per-index geometry
+                              // (StretchSlot arrays of nx / nz), else null
 };
+
+// x / z kind of the 3-point rows of operator op (the pressure's, the
+// mirror-ghost velocity components', the face-normal component's)
+static __device__ __forceinline__ int x_kind(int op)
+{
+    return op == IBS_OP_POISSON ? XK_P : (op == IBS_OP_HELMHOLTZ_U ? XK_F : XK_C);
+}
+static __device__ __forceinline__ int z_kind(int op)
+{
+    return op == IBS_OP_POISSON ? XK_P : (op == IBS_OP_HELMHOLTZ_W ? XK_F : XK_C);
+}
 
 static Geo geo_of(const Plan &p)
 {
@@ -29,6 +42,8 @@ static Geo geo_of(const Plan &p)
     g.ihx = 1.0 / p.hx; g.ihz = 1.0 / p.hz;
     g.dyc = blob_ptr(p, p.lay.dyc);
     g.dyf = blob_ptr(p, p.lay.dyf);
+    g.sgx = p.sx ? blob_ptr(p, p.lay.sgx) : nullptr;
+    g.sgz = p.sz ? blob_ptr(p, p.lay.sgz) : nullptr;
     return g;
 }
 
@@ -54,6 +69,7 @@ static __device__ __forceinline__ bool xcd_tile(int gx, int rows, int nz, int &b
 }
 
 // b = scale * ((u_{i+1}-u_i)/hx + (v_{j+1}-v_j)/Delta_j + (w_{k+1}-w_k)/hz)
+// (a stretched x or z: over the cell's own width Delta_i, Delta_k)
 __global__ __launch_bounds__(256) void divergence_kernel(Geo g, const double *__restrict__ u,
                                                          const double *__restrict__ v,
                                                          const double *__restrict__ w,
@@ -72,15 +88,16 @@ __global__ __launch_bounds__(256) void divergence_kernel(Geo g, const double *__
     // with walls in x the wall faces x = 0 and x = lx carry u = 0
     const double ue = (g.wx && ip == 0) ? 0.0 : u[c - i + ip];
     const double uw = (g.wx && i == 0) ? 0.0 : u[c];
-    const double du = (ue - uw) * g.ihx;
+    const double du = (ue - uw) * (g.sgx ? g.sgx[SG_RC * g.nx + i] : g.ihx);
     const double dv = (v[vn] - v[vc]) / g.dyc[j];
     const double wt = (g.wz && kp == 0) ? 0.0 : w[kp * plane + (size_t)j * g.nx + i];
     const double wb = (g.wz && k == 0) ? 0.0 : w[c];
-    const double dw = (wt - wb) * g.ihz;
+    const double dw = (wt - wb) * (g.sgz ? g.sgz[(size_t)SG_RC * g.nz + k] : g.ihz);
     b[c] = scale * (du + dv + dw);
 }
 
-// u -= g dphi/dx, v -= g dphi/dy (walls: 0), w -= g dphi/dz;
+// u -= g dphi/dx, v -= g dphi/dy (walls: 0), w -= g dphi/dz (differences
+// over the centre distances: hx, hz, or delta_i, delta_k when stretched);
 // p += phi - cp * lap (optional).  Grid rows j = 0..ny (v has ny+1 rows).
 __global__ __launch_bounds__(256) void correct_kernel(Geo g, const double *__restrict__ phi,
                                                       double *__restrict__ u, double *__restrict__ v,
@@ -100,9 +117,10 @@ __global__ __launch_bounds__(256) void correct_kernel(Geo g, const double *__res
         const size_t km = (k == 0) ? (size_t)(g.nz - 1) : (size_t)(k - 1);
         const double ph = phi[c];
         if (g.wx && i == 0) u[c] = 0.0;   // the wall face x = 0
-        else u[c] -= gs * (ph - phi[c - i + im]) * g.ihx;
+        else u[c] -= gs * (ph - phi[c - i + im]) * (g.sgx ? g.sgx[SG_RF * g.nx + i] : g.ihx);
         if (g.wz && k == 0) w[c] = 0.0;   // the wall face z = 0
-        else w[c] -= gs * (ph - phi[km * plane + (size_t)j * g.nx + i]) * g.ihz;
+        else w[c] -= gs * (ph - phi[km * plane + (size_t)j * g.nx + i]) *
+                     (g.sgz ? g.sgz[(size_t)SG_RF * g.nz + k] : g.ihz);
         if (pr) pr[c] += ph - (cp != 0.0 ? cp * lap[c] : 0.0);
         if (j > 0) v[vc] -= gs * (ph - phi[c - g.nx]) / g.dyf[j];
         else if (g.py) v[vc] -= gs * (ph - phi[c + (size_t)(g.ny - 1) * g.nx]) / g.dyf[0];   // across the wrap
@@ -173,8 +191,19 @@ __global__ __launch_bounds__(256) void residual_kernel(Geo g, int op, double cc,
                 if (k + 1 == g.nz) xt = gz;
                 if (op == IBS_OP_HELMHOLTZ_W && k == 0) unknown = false;
             }
-            double lap = ((xe - xc) - (xc - xw)) * (g.ihx * g.ihx) +
-                         ((xt - xc) - (xc - xb)) * (g.ihz * g.ihz);
+            double lap;
+            if (!g.sgx && !g.sgz) {
+                lap = ((xe - xc) - (xc - xw)) * (g.ihx * g.ihx) + ((xt - xc) - (xc - xb)) * (g.ihz * g.ihz);
+            } else {
+                // a stretched x or z: the flux form over the local widths
+                const double lx = g.sgx ? (xe - xc) * g.sgx[(size_t)sg_ae(x_kind(op)) * g.nx + i] -
+                                              (xc - xw) * g.sgx[(size_t)sg_aw(x_kind(op)) * g.nx + i]
+                                        : ((xe - xc) - (xc - xw)) * (g.ihx * g.ihx);
+                const double lz = g.sgz ? (xt - xc) * g.sgz[(size_t)sg_ae(z_kind(op)) * g.nz + k] -
+                                              (xc - xb) * g.sgz[(size_t)sg_aw(z_kind(op)) * g.nz + k]
+                                        : ((xt - xc) - (xc - xb)) * (g.ihz * g.ihz);
+                lap = lx + lz;
+            }
             if (g.py) {
                 // periodic y: interior formulas everywhere, neighbours wrapping
                 const int jn = (j + 1 == g.ny) ? 0 : j + 1, js = (j == 0) ? g.ny - 1 : j - 1;
@@ -333,7 +362,9 @@ hipError_t launch_residual(const Plan &p, int op, double c, const double *x, con
 
 // Strict compatibility, first stage: block q of job j walks the cell rows
 // (j, k) = q, q + G, ... (fixed order) and writes its partial sums of
-// Delta_j b and Delta_j b^2 to part[2 (j * G + q) ..].
+// W b and W b^2 to part[2 (j * G + q) ..], W = Delta_j (times Delta_i /
+// hbar_x and Delta_k / hbar_z on a stretched x or z, whose shares sum to
+// nx and nz as the uniform ones do).
 __global__ __launch_bounds__(256) void compat_partials_kernel(Geo g, const double *__restrict__ b0,
                                                               const double *__restrict__ b1,
                                                               const double *__restrict__ b2,
@@ -346,13 +377,15 @@ __global__ __launch_bounds__(256) void compat_partials_kernel(Geo g, const doubl
     const int nrow = g.ny * g.nz;
     double s1 = 0.0, s2 = 0.0;
     for (int rw = blockIdx.x; rw < nrow; rw += gridDim.x) {
-        const int j = rw % g.ny;
-        const double w = g.dyc[j];
+        const int j = rw % g.ny, k = rw / g.ny;
+        double w = g.dyc[j];
+        if (g.sgz) w *= g.sgz[(size_t)SG_WN * g.nz + k];
         const double *row = b + (size_t)rw * g.nx;
         for (int i = threadIdx.x; i < g.nx; i += blockDim.x) {
             const double v = row[i];
-            s1 += w * v;
-            s2 += w * v * v;
+            const double wi = g.sgx ? w * g.sgx[SG_WN * g.nx + i] : w;
+            s1 += wi * v;
+            s2 += wi * v * v;
         }
     }
     const double t1 = block_sum(s1, sm);

@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -110,6 +111,154 @@ static void wall_basis(int n, double h, int xk, std::vector<double> &Q, std::vec
             Q[size_t(i) * n + col] = (double)v;
         }
     }
+}
+
+// Eigenpairs of a real symmetric tridiagonal matrix (diagonal d[0..m-1],
+// off-diagonal e[i] coupling rows i and i+1), by the implicit QL iteration
+// with Wilkinson's shift (Bowdler, Martin, Reinsch and Wilkinson, 1968):
+// each sweep chases the shifted QL bulge up from the first negligible
+// off-diagonal with plane rotations, which are accumulated into V (m x m,
+// row-major, V[i*m + a] = component i of eigenvector a).  Runs in long
+// double, so the eigenvalues carry absolute errors near 1e-19 ||T||: the
+// smallest ones (the modes that matter most to a solve) stay accurate to
+// about 1e-15 relative at the grid sizes served.  On return d holds the
+// eigenvalues (unsorted).  Returns false if some eigenvalue needs more
+// than 60 sweeps.
+static bool tridiag_eigen(int m, std::vector<long double> &d, std::vector<long double> e,
+                          std::vector<long double> &V)
+{
+    V.assign(size_t(m) * m, 0.0L);
+    for (int i = 0; i < m; ++i) V[size_t(i) * m + i] = 1.0L;
+    e.resize(m, 0.0L);
+    e[m - 1] = 0.0L;
+    const long double eps = std::numeric_limits<long double>::epsilon();
+    for (int l = 0; l < m; ++l) {
+        for (int sweep = 0;; ++sweep) {
+            int k = l;   // first negligible coupling at or after l
+            while (k + 1 < m && std::fabs(e[k]) > eps * (std::fabs(d[k]) + std::fabs(d[k + 1]))) ++k;
+            if (k == l) break;
+            if (sweep == 60) return false;
+            // Wilkinson shift from the leading 2 x 2 block of rows l, l+1
+            long double g = (d[l + 1] - d[l]) / (2.0L * e[l]);
+            long double r = std::hypot(g, 1.0L);
+            g = d[k] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+            long double sn = 1.0L, cs = 1.0L, shift = 0.0L;
+            bool deflated = false;
+            for (int i = k - 1; i >= l; --i) {
+                const long double f = sn * e[i], b = cs * e[i];
+                r = std::hypot(f, g);
+                e[i + 1] = r;
+                if (r == 0.0L) {   // underflow: the block splits here
+                    d[i + 1] -= shift;
+                    e[k] = 0.0L;
+                    deflated = true;
+                    break;
+                }
+                sn = f / r;
+                cs = g / r;
+                g = d[i + 1] - shift;
+                r = (d[i] - g) * sn + 2.0L * cs * b;
+                shift = sn * r;
+                d[i + 1] = g + shift;
+                g = cs * r - b;
+                for (int q = 0; q < m; ++q) {   // accumulate the rotation of columns i, i+1
+                    long double &vi = V[size_t(q) * m + i], &vn = V[size_t(q) * m + i + 1];
+                    const long double t = vn;
+                    vn = sn * vi + cs * t;
+                    vi = cs * vi - sn * t;
+                }
+            }
+            if (deflated) continue;
+            d[l] -= shift;
+            e[l] = g;
+            e[k] = 0.0L;
+        }
+    }
+    return true;
+}
+
+// Eigenbases of the wall-bounded 3-point operators on a stretched axis:
+// faces f[0..n] (strictly increasing), cell widths Delta_i = f[i+1] - f[i],
+// centres c_i = (f[i] + f[i+1]) / 2, centre distances delta_i = c_i -
+// c_{i-1}.  The operator L (flux form: the x rows of the staggered
+// Laplacian over the local widths, with the same wall rows as the uniform
+// kinds) is W^{-1} S with S symmetric and W the control widths (Delta_i for
+// cell unknowns, delta_i for face unknowns), so it is diagonalised by the
+// generalised eigenproblem S q = lambda W q.  Here through the symmetric
+// T = W^{1/2} L W^{-1/2} = V Lambda V^T:
+//   forward  xhat_a = sum_i F[i][a] x_i,  F = Wn^{1/2} V
+//   inverse  x_i    = sum_a G[i][a] xhat_a, G = Wn^{-1/2} V
+// with Wn = W / hbar (hbar = mean cell width), so that uniform faces give
+// back the orthonormal bases above (F = G = Q) and a constant field of cell
+// values maps onto mode 0 exactly as there: xhat_0 = sum_i Wn_i x_i /
+// sqrt(n), and mode 0 inverts to the constant xhat_0 / sqrt(n).  Modes are
+// ordered by increasing |lambda| (the pressure's mode 0 is its constant,
+// lambda exactly 0), each with the sign that makes its largest component
+// positive; XK_F keeps the wall slot as row and column 0 (zero, lambda 0).
+// F and G are row-major n x n.  Returns false if the eigensolver fails.
+static bool stretched_basis(int n, const std::vector<double> &f, int xk, std::vector<double> &F,
+                            std::vector<double> &G, std::vector<double> &lam)
+{
+    F.assign(size_t(n) * n, 0.0);
+    G.assign(size_t(n) * n, 0.0);
+    lam.assign(n, 0.0);
+    std::vector<long double> D(n), c(n), dl(n + 1, 0.0L);
+    for (int i = 0; i < n; ++i) {
+        D[i] = (long double)f[i + 1] - (long double)f[i];
+        c[i] = 0.5L * ((long double)f[i] + (long double)f[i + 1]);
+    }
+    for (int i = 1; i < n; ++i) dl[i] = c[i] - c[i - 1];
+    const long double hbar = ((long double)f[n] - (long double)f[0]) / n;
+    const int first = (xk == XK_F) ? 1 : 0, m = n - first;   // unknowns first..n-1
+    std::vector<long double> W(m), sd(m), so(m, 0.0L);      // S: diagonal, off-diagonal
+    for (int r = 0; r < m; ++r) {
+        const int i = r + first;
+        if (xk == XK_F) {
+            W[r] = dl[i];
+            sd[r] = -(1.0L / D[i] + 1.0L / D[i - 1]);
+            if (i + 1 <= n - 1) so[r] = 1.0L / D[i];
+        } else {
+            W[r] = D[i];
+            long double diag = 0.0L;
+            if (i + 1 < n) { diag -= 1.0L / dl[i + 1]; so[r] = 1.0L / dl[i + 1]; }
+            if (i > 0) diag -= 1.0L / dl[i];
+            if (xk == XK_C && i == 0) diag -= 2.0L / D[0];
+            if (xk == XK_C && i == n - 1) diag -= 2.0L / D[n - 1];
+            sd[r] = diag;
+        }
+    }
+    std::vector<long double> td(m), te(m, 0.0L), V;
+    for (int r = 0; r < m; ++r) {
+        td[r] = sd[r] / W[r];
+        if (r + 1 < m) te[r] = so[r] / std::sqrt(W[r] * W[r + 1]);
+    }
+    if (!tridiag_eigen(m, td, te, V)) return false;
+    std::vector<int> ord(m);
+    for (int a = 0; a < m; ++a) ord[a] = a;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return td[a] > td[b]; });
+    long double wsum = 0.0L;
+    for (int r = 0; r < m; ++r) wsum += W[r];
+    for (int a = 0; a < m; ++a) {
+        const int src = ord[a], col = a + first;
+        // sign: the mode's largest component (the first of equal ones)
+        // positive.  Not the first component: on a grid graded towards
+        // both walls the high modes come in pairs localised at either wall,
+        // degenerate to rounding, and a mode may vanish at the first wall.
+        int rmax = 0;
+        for (int r = 1; r < m; ++r)
+            if (std::fabs(V[size_t(r) * m + src]) > std::fabs(V[size_t(rmax) * m + src])) rmax = r;
+        const long double sg = V[size_t(rmax) * m + src] < 0 ? -1.0L : 1.0L;
+        lam[col] = (double)td[src];
+        for (int r = 0; r < m; ++r) {
+            long double v = sg * V[size_t(r) * m + src];
+            if (xk == XK_P && a == 0) v = std::sqrt(W[r] / wsum);   // the exact null vector
+            const long double wn = std::sqrt(W[r] / hbar);
+            F[size_t(r + first) * n + col] = (double)(wn * v);
+            G[size_t(r + first) * n + col] = (double)(v / wn);
+        }
+    }
+    if (xk == XK_P) lam[0] = 0.0;
+    return true;
 }
 
 // Swizzle a K x N row-major matrix B into the per-lane fragment order of
@@ -265,11 +414,12 @@ static void swizzle_split_pair(const std::vector<double> &F0, const std::vector<
 // from request to request) take these from a small process-wide cache.
 struct AxisTables {
     std::vector<double> Q, lam;
+    std::vector<double> Qi;            // stretched axis: the inverse basis G (else empty: G = Q)
     std::vector<double> f64[4];        // folded: fwd_c, fwd_s, inv_c, inv_s; plain: fwd, inv
     std::vector<uint16_t> split[2];    // fwd, inv (folded pairs or plain); empty without split
     size_t bytes() const
     {
-        size_t b = (Q.size() + lam.size()) * sizeof(double);
+        size_t b = (Q.size() + Qi.size() + lam.size()) * sizeof(double);
         for (const auto &v : f64) b += v.size() * sizeof(double);
         for (const auto &v : split) b += v.size() * sizeof(uint16_t);
         return b;
@@ -277,13 +427,18 @@ struct AxisTables {
 };
 
 // basis: -1 the periodic Fourier basis; XK_* a wall-bounded x basis (never
-// folded: the folds rest on the Fourier basis's mirror symmetry).
-static std::shared_ptr<const AxisTables> build_axis(int n, double h, bool z_axis, bool split, int basis)
+// folded: the folds rest on the Fourier basis's mirror symmetry), on the
+// given faces when `faces` is not empty (stretched: forward F = Q and
+// inverse G = Qi differ).  Returns null if the eigensolver fails.
+static std::shared_ptr<const AxisTables> build_axis(int n, double h, bool z_axis, bool split, int basis,
+                                                    const std::vector<double> &faces)
 {
     auto t = std::make_shared<AxisTables>();
     if (basis < 0) fourier_basis(n, h, t->Q, t->lam);
-    else wall_basis(n, h, basis, t->Q, t->lam);
+    else if (faces.empty()) wall_basis(n, h, basis, t->Q, t->lam);
+    else if (!stretched_basis(n, faces, basis, t->Q, t->Qi, t->lam)) return nullptr;
     const std::vector<double> &Q = t->Q;
+    const std::vector<double> &Gi = t->Qi.empty() ? t->Q : t->Qi;   // inverse basis
     const int hn = n / 2;
     const size_t h2 = size_t(hn) * hn;
     const bool fourier = basis < 0;
@@ -302,17 +457,21 @@ static std::shared_ptr<const AxisTables> build_axis(int n, double h, bool z_axis
             swizzle_a(f.s_inv.data(), hn, hn, t->f64[3].data());               // inverse: Qs Xs
         }
     } else {
-        std::vector<double> tr(size_t(n) * n);
+        // tq = Q^T (forward, z), tg = G^T (inverse, x); G = Q unless stretched
+        std::vector<double> tq(size_t(n) * n), tg(size_t(n) * n);
         for (int i = 0; i < n; ++i)
-            for (int a = 0; a < n; ++a) tr[size_t(a) * n + i] = Q[size_t(i) * n + a];
+            for (int a = 0; a < n; ++a) {
+                tq[size_t(a) * n + i] = Q[size_t(i) * n + a];
+                tg[size_t(a) * n + i] = Gi[size_t(i) * n + a];
+            }
         t->f64[0].resize(size_t(n) * n);
         t->f64[1].resize(size_t(n) * n);
         if (!z_axis) {
             swizzle_b(Q.data(), n, n, t->f64[0].data());    // x forward: C = X Q
-            swizzle_b(tr.data(), n, n, t->f64[1].data());   // x inverse: C = Xhat Q^T
+            swizzle_b(tg.data(), n, n, t->f64[1].data());   // x inverse: C = Xhat G^T
         } else {
-            swizzle_a(tr.data(), n, n, t->f64[0].data());   // z forward: A = Q^T
-            swizzle_a(Q.data(), n, n, t->f64[1].data());    // z inverse: A = Q
+            swizzle_a(tq.data(), n, n, t->f64[0].data());   // z forward: A = Q^T
+            swizzle_a(Gi.data(), n, n, t->f64[1].data());   // z inverse: A = G
         }
     }
     if (split) {
@@ -328,17 +487,20 @@ static std::shared_ptr<const AxisTables> build_axis(int n, double h, bool z_axis
                 swizzle_split_pair(f.c, f.s_inv, hn, true, t->split[1].data());
             }
         } else {
-            std::vector<double> tr(size_t(n) * n);
+            std::vector<double> tq(size_t(n) * n), tg(size_t(n) * n);
             for (int i = 0; i < n; ++i)
-                for (int a = 0; a < n; ++a) tr[size_t(a) * n + i] = Q[size_t(i) * n + a];
+                for (int a = 0; a < n; ++a) {
+                    tq[size_t(a) * n + i] = Q[size_t(i) * n + a];
+                    tg[size_t(a) * n + i] = Gi[size_t(i) * n + a];
+                }
             t->split[0].resize(size_t(3) * n * n);
             t->split[1].resize(size_t(3) * n * n);
             if (!z_axis) {
                 swizzle_b_split(Q.data(), n, n, t->split[0].data());
-                swizzle_b_split(tr.data(), n, n, t->split[1].data());
+                swizzle_b_split(tg.data(), n, n, t->split[1].data());
             } else {
-                swizzle_a_split(tr.data(), n, n, t->split[0].data());
-                swizzle_a_split(Q.data(), n, n, t->split[1].data());
+                swizzle_a_split(tq.data(), n, n, t->split[0].data());
+                swizzle_a_split(Gi.data(), n, n, t->split[1].data());
             }
         }
     }
@@ -350,13 +512,15 @@ static std::shared_ptr<const AxisTables> build_axis(int n, double h, bool z_axis
 // never affects an existing plan.
 constexpr size_t AXIS_CACHE_BYTES = size_t(256) << 20;
 static std::shared_ptr<const AxisTables> axis_tables(int n, double h, bool z_axis, bool split,
-                                                     int basis = -1)
+                                                     int basis = -1,
+                                                     const std::vector<double> &faces = {})
 {
     struct Entry {
         int n;
         double h;
         bool z, split;
         int basis;
+        std::vector<double> faces;
         std::shared_ptr<const AxisTables> t;
     };
     static std::mutex mu;
@@ -364,9 +528,12 @@ static std::shared_ptr<const AxisTables> axis_tables(int n, double h, bool z_axi
     {
         std::lock_guard<std::mutex> lock(mu);
         for (const Entry &e : cache)
-            if (e.n == n && e.h == h && e.z == z_axis && e.split == split && e.basis == basis) return e.t;
+            if (e.n == n && e.h == h && e.z == z_axis && e.split == split && e.basis == basis &&
+                e.faces == faces)
+                return e.t;
     }
-    std::shared_ptr<const AxisTables> t = build_axis(n, h, z_axis, split, basis);
+    std::shared_ptr<const AxisTables> t = build_axis(n, h, z_axis, split, basis, faces);
+    if (!t) return t;
     std::lock_guard<std::mutex> lock(mu);
     size_t total = t->bytes();
     for (const Entry &e : cache) total += e.t->bytes();
@@ -374,8 +541,36 @@ static std::shared_ptr<const AxisTables> axis_tables(int n, double h, bool z_axi
         total -= cache.front().t->bytes();
         cache.erase(cache.begin());
     }
-    if (t->bytes() <= AXIS_CACHE_BYTES) cache.push_back(Entry{n, h, z_axis, split, basis, t});
+    if (t->bytes() <= AXIS_CACHE_BYTES) cache.push_back(Entry{n, h, z_axis, split, basis, faces, t});
     return t;
+}
+
+// The per-index geometry of a stretched wall-bounded axis on faces f[0..n]
+// (StretchSlot layout): SG_SLOTS arrays of n doubles, from long-double
+// widths.
+static std::vector<double> stretch_geometry(const std::vector<double> &f)
+{
+    const int n = (int)f.size() - 1;
+    std::vector<long double> D(n), dl(n + 1, 0.0L);
+    for (int i = 0; i < n; ++i) D[i] = (long double)f[i + 1] - (long double)f[i];
+    for (int i = 1; i < n; ++i) dl[i] = 0.5L * (D[i - 1] + D[i]);
+    const long double hbar = ((long double)f[n] - (long double)f[0]) / n;
+    std::vector<double> g(size_t(SG_SLOTS) * n, 0.0);
+    auto at = [&](int slot, int i) -> double & { return g[size_t(slot) * n + i]; };
+    for (int i = 0; i < n; ++i) {
+        at(SG_RC, i) = (double)(1.0L / D[i]);
+        at(SG_RF, i) = i > 0 ? (double)(1.0L / dl[i]) : 0.0;
+        at(SG_WN, i) = (double)(D[i] / hbar);
+        const long double e = i + 1 < n ? 1.0L / (dl[i + 1] * D[i]) : 0.0L;
+        const long double w = i > 0 ? 1.0L / (dl[i] * D[i]) : 0.0L;
+        at(sg_ae(XK_P), i) = (double)e;
+        at(sg_aw(XK_P), i) = (double)w;
+        at(sg_ae(XK_C), i) = (double)(i + 1 < n ? e : 1.0L / (D[i] * D[i]));
+        at(sg_aw(XK_C), i) = (double)(i > 0 ? w : 1.0L / (D[i] * D[i]));
+        at(sg_ae(XK_F), i) = i > 0 ? (double)(1.0L / (D[i] * dl[i])) : 0.0;
+        at(sg_aw(XK_F), i) = i > 0 ? (double)(1.0L / (D[i - 1] * dl[i])) : 0.0;
+    }
+    return g;
 }
 
 ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
@@ -426,20 +621,45 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
         set_error("beta must be in [0, 10]");
         return IBS_ERR_INVALID_ARG;
     }
+    if ((d.x_faces && d.bc_x != IBS_DIRICHLET) || (d.z_faces && d.bc_z != IBS_DIRICHLET)) {
+        set_error("x_faces / z_faces (a stretched x or z) need walls along that axis (IBS_DIRICHLET)");
+        return IBS_ERR_UNSUPPORTED;
+    }
+    // faces of a stretched x or z: finite and strictly increasing
+    auto faces_ok = [](const double *f, int n) {
+        for (int i = 0; i <= n; ++i)
+            if (!std::isfinite(f[i]) || (i > 0 && !(f[i] - f[i - 1] > 0.0))) return false;
+        return true;
+    };
+    if ((d.x_faces && !faces_ok(d.x_faces, d.nx)) || (d.z_faces && !faces_ok(d.z_faces, d.nz))) {
+        set_error("x_faces / z_faces must be finite and strictly increasing");
+        return IBS_ERR_INVALID_ARG;
+    }
     Plan *p = new (std::nothrow) Plan();
     if (!p) { set_error("out of host memory"); return IBS_ERR_INVALID_ARG; }
     p->desc = d;
     p->desc.y_faces = nullptr;
+    p->desc.x_faces = nullptr;
+    p->desc.z_faces = nullptr;
     p->py = periodic_y;
     p->wx = d.bc_x == IBS_DIRICHLET;
     p->wz = d.bc_z == IBS_DIRICHLET;
-    const double lx = d.lx > 0 ? d.lx : 1.0, ly = d.ly > 0 ? d.ly : 1.0, lz = d.lz > 0 ? d.lz : 1.0;
+    p->sx = d.x_faces != nullptr;
+    p->sz = d.z_faces != nullptr;
+    double lx = d.lx > 0 ? d.lx : 1.0, lz = d.lz > 0 ? d.lz : 1.0;
+    const double ly = d.ly > 0 ? d.ly : 1.0;
+    if (p->sx) lx = d.x_faces[d.nx] - d.x_faces[0];
+    if (p->sz) lz = d.z_faces[d.nz] - d.z_faces[0];
     p->desc.lx = lx; p->desc.ly = ly; p->desc.lz = lz;
     if (p->desc.tol <= 0) p->desc.tol = 1e-10;
     const int nx = d.nx, ny = d.ny, nz = d.nz;
     p->nx = nx; p->ny = ny; p->nz = nz;
-    p->hx = lx / nx;
+    p->hx = lx / nx;   // the mean width on a stretched axis
     p->hz = lz / nz;
+    p->xf.resize(nx + 1);
+    p->zf.resize(nz + 1);
+    for (int i = 0; i <= nx; ++i) p->xf[i] = p->sx ? d.x_faces[i] : p->hx * i;
+    for (int k = 0; k <= nz; ++k) p->zf[k] = p->sz ? d.z_faces[k] : p->hz * k;
 
     // y grid: tanh-stretched faces (uniform for beta = 0), centres midway
     p->yf.resize(ny + 1);
@@ -524,16 +744,29 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
 
     const bool split = d.precision != IBS_FP64;
     // x: one Fourier table set (periodic), or one per x kind (walls)
+    const std::vector<double> no_faces;
     std::shared_ptr<const AxisTables> ax[NUM_XK];
     for (int k = 0; k < NUM_XK; ++k)
-        ax[k] = (p->wx || k == 0) ? axis_tables(nx, p->hx, false, split, p->wx ? k : -1) : ax[0];
+        ax[k] = (p->wx || k == 0) ? axis_tables(nx, p->hx, false, split, p->wx ? k : -1,
+                                                p->sx ? p->xf : no_faces)
+                                  : ax[0];
     std::shared_ptr<const AxisTables> az[NUM_XK];
     for (int k = 0; k < NUM_XK; ++k)
-        az[k] = (p->wz || k == 0) ? axis_tables(nz, p->hz, true, split, p->wz ? k : -1) : az[0];
+        az[k] = (p->wz || k == 0) ? axis_tables(nz, p->hz, true, split, p->wz ? k : -1,
+                                                p->sz ? p->zf : no_faces)
+                                  : az[0];
+    for (int k = 0; k < NUM_XK; ++k)
+        if (!ax[k] || !az[k]) {
+            set_error("the eigensolver of a stretched axis did not converge");
+            delete p;
+            return IBS_ERR_INVALID_ARG;
+        }
     for (int k = 0; k < NUM_XK; ++k) {
         p->qx[k] = ax[k]->Q;
+        p->gx[k] = ax[k]->Qi.empty() ? ax[k]->Q : ax[k]->Qi;
         p->lam_x[k] = ax[k]->lam;
         p->qz[k] = az[k]->Q;
+        p->gz[k] = az[k]->Qi.empty() ? az[k]->Q : az[k]->Qi;
         p->lam_z[k] = az[k]->lam;
     }
     const int nxk = p->wx ? NUM_XK : 1;   // distinct x tables
@@ -610,6 +843,8 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     p->lane_len = (int)lane_list.size();
     L.lane_mask = take(sizeof(uint32_t) * lane_mask.size());
     L.lane_list = take(sizeof(int) * lane_list.size());
+    L.sgx = take(p->sx ? sizeof(double) * SG_SLOTS * nx : 0);
+    L.sgz = take(p->sz ? sizeof(double) * SG_SLOTS * nz : 0);
     L.total = o;
     p->blob.assign(L.total, 0);
     auto put = [&](size_t off, const double *src, size_t n) {
@@ -672,6 +907,14 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
     put(L.wy, p->dyc.data(), ny);
     put(L.dyc, p->dyc.data(), ny);
     put(L.dyf, p->dyf.data(), ny + 1);
+    if (p->sx) {
+        const std::vector<double> g = stretch_geometry(p->xf);
+        put(L.sgx, g.data(), g.size());
+    }
+    if (p->sz) {
+        const std::vector<double> g = stretch_geometry(p->zf);
+        put(L.sgz, g.data(), g.size());
+    }
     out = p;
     return IBS_OK;
 }

@@ -52,7 +52,9 @@ class ibs_grid_desc(ctypes.Structure):
                 ("bc_x", ctypes.c_int32), ("bc_z", ctypes.c_int32),
                 ("bc_y_vel", ctypes.c_int32), ("bc_y_p", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("max_iter", ctypes.c_int32), ("strict_compat", ctypes.c_int32)]
+                ("max_iter", ctypes.c_int32), ("strict_compat", ctypes.c_int32),
+                ("x_faces", ctypes.POINTER(ctypes.c_double)),
+                ("z_faces", ctypes.POINTER(ctypes.c_double))]
 
 
 class ibs_solve_info(ctypes.Structure):
@@ -150,16 +152,17 @@ def _check(st: int, where: str):
 def make_desc(nx, ny, nz, lx=1.0, ly=1.0, lz=1.0, beta=0.0, y_faces=None,
               precision=IBS_FP64, tol=1e-10, max_iter=0, strict_compat=0,
               bc_x=IBS_PERIODIC, bc_z=IBS_PERIODIC, bc_y_vel=IBS_DIRICHLET,
-              bc_y_p=IBS_NEUMANN):
+              bc_y_p=IBS_NEUMANN, x_faces=None, z_faces=None):
     d = ibs_grid_desc()
     d.nx, d.ny, d.nz = nx, ny, nz
     d.lx, d.ly, d.lz = lx, ly, lz
     d.beta = beta
-    d._yf_keep = None
-    if y_faces is not None:
-        arr = (ctypes.c_double * len(y_faces))(*[float(t) for t in y_faces])
-        d._yf_keep = arr
-        d.y_faces = ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))
+    d._keep = []
+    for name, faces in (("y_faces", y_faces), ("x_faces", x_faces), ("z_faces", z_faces)):
+        if faces is not None:
+            arr = (ctypes.c_double * len(faces))(*[float(t) for t in faces])
+            d._keep.append(arr)
+            setattr(d, name, ctypes.cast(arr, ctypes.POINTER(ctypes.c_double)))
     d.bc_x, d.bc_z, d.bc_y_vel, d.bc_y_p = bc_x, bc_z, bc_y_vel, bc_y_p
     d.precision, d.tol, d.max_iter, d.strict_compat = precision, tol, max_iter, strict_compat
     return d

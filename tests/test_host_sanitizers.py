@@ -31,7 +31,7 @@ def test_plan_builder_sanitized(tmp_path):
           os.path.join(ROOT, "paper_2406_19920_amd", "csrc", "plan.cpp"), "-o", str(exe)])
     r = _run([str(exe)], env=ENV)
     assert "ERROR: AddressSanitizer" not in r.stderr and "runtime error" not in r.stderr
-    assert r.stdout.count("plan ") == 12
+    assert r.stdout.count("plan ") == 14
 
 
 def test_oracle_sanitized(tmp_path):

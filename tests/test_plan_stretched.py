@@ -1,0 +1,236 @@
+"""A stretched wall-bounded x or z in the plan (host only): the generalised
+eigenbases of the flux-form operators (forward F, inverse G) diagonalise the
+1-D operators built by the oracle's dense module from the same faces, are
+biorthogonal, reduce to the closed-form bases on uniform faces, and a host
+emulation of the separable solve built from the exported tables matches the
+oracle.  Plan rules for x_faces / z_faces."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import OP_P, OP_U, OP_V, OP_W, dense
+from paper_2406_19920_amd import ibsolve as ibs, synth
+
+
+def _plan(nx, ny, nz, **kw):
+    return ibs.solver_plan(ibs.make_desc(nx, ny, nz, **kw))
+
+
+def _faces(n, length, seed):
+    w = np.random.default_rng(seed).uniform(0.5, 2.0, n)
+    f = np.concatenate([[0.0], np.cumsum(w)])
+    return f * (length / f[-1])
+
+
+def _tanh_faces(n, length, beta):
+    j = np.arange(n + 1)
+    return 0.5 * length * (1 + np.tanh(beta * (2 * j / n - 1)) / np.tanh(beta))
+
+
+def _tables(p, n, k, z):
+    """(F, G, lambda) of kind k (0 pressure, 1 mirror-ghost, 2 face-normal)."""
+    if k == 0:
+        F = ibs.ibs_plan_export(p, 2 if z else 1).reshape(n, n)
+        lam = ibs.ibs_plan_export(p, 4 if z else 3)
+    else:
+        base = 17 + (4 if z else 0)
+        F = ibs.ibs_plan_export(p, base + (0 if k == 1 else 1)).reshape(n, n)
+        lam = ibs.ibs_plan_export(p, base + (2 if k == 1 else 3))
+    G = ibs.ibs_plan_export(p, (28 if z else 25) + k).reshape(n, n)
+    return F, G, lam
+
+
+def _op1d(faces, k):
+    """The 1-D operator of kind k on these faces, from the oracle's dense
+    builders (n x n; the face kind's wall slot 0 decoupled, zero)."""
+    f = np.asarray(faces, dtype=np.float64)
+    n = len(f) - 1
+    dc = np.diff(f)
+    c = 0.5 * (f[:-1] + f[1:])
+    df = np.zeros(n + 1)
+    df[1:n] = np.diff(c)
+    if k == 0:
+        return dense.dx_faces_to_cells_walls(dc) @ dense.gx_cells_to_faces_walls(df)
+    if k == 1:
+        return dense.lx_mirror_walls(dc, df)
+    T = np.zeros((n, n))
+    T[1:, 1:] = (dense.gx_cells_to_faces_walls(df) @ dense.dx_faces_to_cells_walls(dc))[1:, 1:]
+    return T
+
+
+@pytest.mark.parametrize("z", [False, True])
+@pytest.mark.parametrize("n,kind", [(32, "random"), (64, "tanh"), (128, "tanh")])
+def test_stretched_bases_diagonalise_the_operators(n, kind, z):
+    length = 1.3
+    f = _faces(n, length, n) if kind == "random" else _tanh_faces(n, length, 1.6)
+    kw = dict(bc_z=ibs.IBS_DIRICHLET, z_faces=f) if z else dict(bc_x=ibs.IBS_DIRICHLET, x_faces=f)
+    p = _plan(32 if z else n, 8, n if z else 32, **kw)
+    try:
+        np.testing.assert_array_equal(ibs.ibs_plan_export(p, 32 if z else 31), f)
+        for k in range(3):
+            F, G, lam = _tables(p, n, k, z)
+            L = _op1d(f, k)
+            scale = np.abs(L).max()
+            keep = np.arange(1, n) if k == 2 else np.arange(n)
+            # L G = G Lambda, F^T L = Lambda F^T, F^T G = I on the unknowns
+            np.testing.assert_allclose(L @ G, G * lam[None, :], rtol=0, atol=2e-12 * scale)
+            np.testing.assert_allclose(F.T @ L, lam[:, None] * F.T, rtol=0, atol=2e-12 * scale)
+            Fk, Gk = F[np.ix_(keep, keep)], G[np.ix_(keep, keep)]
+            np.testing.assert_allclose(Fk.T @ Gk, np.eye(len(keep)), atol=1e-13)
+            # modes by increasing |lambda|, none positive; the pressure's mode
+            # 0 is the constant (exactly zero eigenvalue, G column constant)
+            assert np.all(np.diff(np.abs(lam[keep])) >= -1e-12 * scale) and lam.max() <= 0
+            if k == 0:
+                assert lam[0] == 0.0 and lam[1] < 0
+                np.testing.assert_allclose(G[:, 0], 1 / np.sqrt(n), rtol=1e-14)
+                dc = np.diff(f)
+                np.testing.assert_allclose(F[:, 0], dc / (length / n) / np.sqrt(n), rtol=1e-14)
+            if k == 2:
+                assert np.all(F[0] == 0) and np.all(F[:, 0] == 0) and lam[0] == 0
+        # the tables are a deterministic function of the faces
+        p2 = _plan(32 if z else n, 8, n if z else 32, **kw)
+        try:
+            for k in range(3):
+                for a, b in zip(_tables(p, n, k, z), _tables(p2, n, k, z)):
+                    np.testing.assert_array_equal(a, b)
+        finally:
+            ibs.solver_plan_destroy(p2)
+    finally:
+        ibs.solver_plan_destroy(p)
+
+
+@pytest.mark.parametrize("z", [False, True])
+def test_uniform_faces_give_the_closed_form_bases(z):
+    n, length = 48, 0.9
+    f = length * np.arange(n + 1) / n
+    if z:
+        pu = _plan(32, 8, n, lz=length, bc_z=ibs.IBS_DIRICHLET)
+        ps = _plan(32, 8, n, bc_z=ibs.IBS_DIRICHLET, z_faces=f)
+    else:
+        pu = _plan(n, 8, 32, lx=length, bc_x=ibs.IBS_DIRICHLET)
+        ps = _plan(n, 8, 32, bc_x=ibs.IBS_DIRICHLET, x_faces=f)
+    try:
+        for k in range(3):
+            Fu, Gu, lu = _tables(pu, n, k, z)
+            Fs, Gs, ls = _tables(ps, n, k, z)
+            np.testing.assert_array_equal(Fu, Gu)
+            np.testing.assert_allclose(ls, lu, rtol=1e-13, atol=1e-9)
+            # the same modes up to each one's sign (F and G flip together)
+            sg = np.sign(np.sum(Fs * Fu, axis=0))
+            sg[sg == 0] = 1
+            np.testing.assert_allclose(Fs * sg, Fu, atol=2e-13)
+            np.testing.assert_allclose(Gs * sg, Gu, atol=2e-13)
+    finally:
+        ibs.solver_plan_destroy(pu)
+        ibs.solver_plan_destroy(ps)
+
+
+def _emulate(p, nx, ny, nz, op, rhs, c, wx, wz):
+    xk = 0 if (op == OP_P or not wx) else (2 if op == OP_U else 1)
+    zk = 0 if (op == OP_P or not wz) else (2 if op == OP_W else 1)
+    Fx, Gx, lx = _tables(p, nx, xk, False)
+    Fz, Gz, lz = _tables(p, nz, zk, True)
+    kind = {OP_P: 0, OP_U: 1, OP_W: 1, OP_V: 2}[op]
+    lo = ibs.ibs_plan_export(p, 5 + 3 * kind)
+    di = ibs.ibs_plan_export(p, 6 + 3 * kind)
+    up = ibs.ibs_plan_export(p, 7 + 3 * kind)
+    n = ny + 1 if op == OP_V else ny
+    lo, di, up = lo[:n], di[:n], up[:n]
+    f = rhs.copy()
+    if op == OP_V:
+        f[:, 0, :] = 0
+        f[:, ny, :] = 0
+    h = np.einsum("kc,kja->cja", Fz, f @ Fx)
+    dyc = np.diff(ibs.ibs_plan_export(p, 0))
+    out = np.zeros_like(h)
+    for cz in range(nz):
+        for a in range(nx):
+            s = lx[a] + lz[cz]
+            if op == OP_P:
+                A = np.diag(di + s) + np.diag(lo[1:], -1) + np.diag(up[:-1], 1)
+            else:
+                A = np.eye(n) * (1 - c * s) - c * (np.diag(di) + np.diag(lo[1:], -1) + np.diag(up[:-1], 1))
+            rr = h[cz, :, a].copy()
+            if op == OP_P and a == 0 and cz == 0:
+                rr -= (dyc @ rr) / dyc.sum()
+                A[0, :] = 0
+                A[0, 0] = 1
+                rr[0] = 0
+                x = np.linalg.solve(A, rr)
+                x -= (dyc @ x) / dyc.sum()
+            elif op == OP_V:
+                x = np.zeros(n)
+                x[1:n - 1] = np.linalg.solve(A[1:n - 1, 1:n - 1], rr[1:n - 1])
+            else:
+                x = np.linalg.solve(A, rr)
+            out[cz, :, a] = x
+    return np.einsum("kc,cja->kja", Gz, out) @ Gx.T
+
+
+@pytest.mark.parametrize("case", ["x", "z", "duct", "duct_x_only"])
+@pytest.mark.parametrize("op", [OP_P, OP_U, OP_V, OP_W])
+def test_host_emulation_stretched_matches_oracle(op, case):
+    nx, ny, nz = 16, 10, 16
+    lx, lz = 1.2, 0.8
+    xf = _faces(nx, lx, 5) if case in ("x", "duct", "duct_x_only") else None
+    zf = _tanh_faces(nz, lz, 1.4) if case in ("z", "duct") else None
+    wx = case != "z"
+    wz = case != "x"
+    kw = dict(lx=lx, lz=lz, beta=1.5)
+    if wx:
+        kw["bc_x"] = ibs.IBS_DIRICHLET
+    if wz:
+        kw["bc_z"] = ibs.IBS_DIRICHLET
+    p = _plan(nx, ny, nz, x_faces=xf, z_faces=zf, **kw)
+    try:
+        g = oracle.Grid(nx, ny, nz, lx=lx, lz=lz, beta=1.5, periodic_x=not wx, periodic_z=not wz,
+                        xf_in=xf, zf_in=zf)
+        rhs = synth.scalar(nx, ny, nz, 31, rows=ny + 1 if op == OP_V else None)
+        c = 0.0 if op == OP_P else 3e-3
+        xo, _ = oracle.solve(g, op, rhs, c=c)
+        xe = _emulate(p, nx, ny, nz, op, rhs, c, wx, wz)
+        err = np.linalg.norm(xe - xo) / np.linalg.norm(xo)
+        assert err < 1e-12, err
+    finally:
+        ibs.solver_plan_destroy(p)
+
+
+def test_stretched_plan_rules():
+    f16 = _faces(16, 1.0, 1)
+    # faces along a periodic axis
+    for kw in (dict(x_faces=f16), dict(z_faces=f16)):
+        with pytest.raises(ibs.IbsError) as e:
+            _plan(16, 8, 16, **kw)
+        assert e.value.status == ibs.IBS_ERR_UNSUPPORTED
+    # not strictly increasing / not finite
+    bad = f16.copy()
+    bad[5] = bad[4]
+    with pytest.raises(ibs.IbsError) as e:
+        _plan(16, 8, 16, bc_x=ibs.IBS_DIRICHLET, x_faces=bad)
+    assert e.value.status == ibs.IBS_ERR_INVALID_ARG
+    bad = f16.copy()
+    bad[3] = np.nan
+    with pytest.raises(ibs.IbsError) as e:
+        _plan(16, 8, 16, bc_z=ibs.IBS_DIRICHLET, z_faces=bad)
+    assert e.value.status == ibs.IBS_ERR_INVALID_ARG
+    # the length follows the faces
+    p = _plan(16, 8, 16, lx=5.0, bc_x=ibs.IBS_DIRICHLET, x_faces=2.0 + 0.5 * f16)
+    try:
+        np.testing.assert_array_equal(ibs.ibs_plan_export(p, 31), 2.0 + 0.5 * f16)
+        F, G, lam = _tables(p, 16, 0, False)
+        np.testing.assert_allclose(G[:, 0], 0.25)
+    finally:
+        ibs.solver_plan_destroy(p)
+
+
+def test_stretched_plan_build_time():
+    """The O(n^3) long-double eigensolver stays a set-up cost of seconds at
+    the refined path's largest axis (three kinds at n = 512)."""
+    f = _tanh_faces(512, 1.0, 1.2)
+    t = time.perf_counter()
+    p = _plan(512, 8, 32, bc_x=ibs.IBS_DIRICHLET, x_faces=f)
+    dt = time.perf_counter() - t
+    ibs.solver_plan_destroy(p)
+    assert dt < 60, dt
