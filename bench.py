@@ -316,6 +316,9 @@ def main():
         log("config duct")
         rd, wd = run_xw(10, 2, walls_z=True)
         configs["duct"] = {"workload": wd, "steps": 10, "warmup": 2, "unit": "Mcell-solves/s", **rd}
+        log("config stretched duct")
+        rs, ws = run_xw(10, 2, walls_z=True, stretch_xz=1.5)
+        configs["stretched_duct"] = {"workload": ws, "steps": 10, "warmup": 2, "unit": "Mcell-solves/s", **rs}
         log("config rk3")
         rr, wr = run_rk3(5, 1)
         configs["rk3_step"] = {"workload": wr, "steps": 5, "warmup": 1,
@@ -567,11 +570,13 @@ def run_3p(steps, warmup, n=256):
     return res, f"{n}^3 uniform, periodic in x, y and z, N(0,1) filtered to k <= 16, c = {c:.4e}"
 
 
-def run_xw(steps, warmup, n=256, beta=2.0, walls_z=False):
+def run_xw(steps, warmup, n=256, beta=2.0, walls_z=False, stretch_xz=0.0):
     """Walls in x (Dirichlet velocity, Neumann pressure at x = 0 and x = lx;
     unfolded cosine/sine transforms in x), and in z too when walls_z (a
     duct), at n^3 with tanh-stretched walls in y, both paths: one step of 3
-    Helmholtz + divergence + Poisson + correction on N(0,1) velocities."""
+    Helmholtz + divergence + Poisson + correction on N(0,1) velocities.
+    stretch_xz > 0 (with walls_z): x and z tanh-stretched too, with that
+    beta (the generalised eigenbases)."""
     import torch
     from paper_2406_19920_amd import ibsolve as ibs
     dev = torch.device("cuda:0")
@@ -582,6 +587,11 @@ def run_xw(steps, warmup, n=256, beta=2.0, walls_z=False):
         w[0] = 0.0
     kwz = {"bc_z": ibs.IBS_DIRICHLET} if walls_z else {}
     c = 0.125 * h_min(n, beta) ** 2
+    if stretch_xz > 0:
+        j = np.arange(n + 1)
+        f = 0.5 * (1 + np.tanh(stretch_xz * (2 * j / n - 1)) / np.tanh(stretch_xz))
+        kwz.update(x_faces=f, z_faces=f)
+        c = 0.125 * min(h_min(n, beta), float(np.diff(f).min())) ** 2
     ru, rv, rw = (torch.from_numpy(a).to(dev) for a in (u, v, w))
     res = {}
     for path, prec in (("refined", ibs.IBS_REFINED_BF16X3), ("fp64", ibs.IBS_FP64)):
@@ -612,6 +622,8 @@ def run_xw(steps, warmup, n=256, beta=2.0, walls_z=False):
                      "tiles": tiles}
         S.close()
     walls = "walls in x and z (uniform) and y" if walls_z else "walls in x (uniform) and y"
+    if stretch_xz > 0:
+        walls = f"walls in x and z (tanh beta={stretch_xz}) and y"
     return res, (f"{n}^3, {walls} (tanh beta={beta})" + ("" if walls_z else ", periodic z")
                  + f", N(0,1) rhs, c = {c:.4e}")
 
