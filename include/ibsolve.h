@@ -386,6 +386,26 @@ ibs_status ibs_batch_build_sched(const ibs_batch_job *jobs, int32_t njobs, int32
  * those of any schedule.  Errors as ibs_batch_build(), IBS_ERR_HIP. */
 ibs_status ibs_batch_autotune(const ibs_batch_job *jobs, int32_t njobs, int32_t reps, int32_t *nlanes,
                               int32_t *policy, float *ms, void *stream);
+/* Multi-grid batch (the many-grid configuration through persistent
+ * work-queue kernels): every field of every job is listed in one device job
+ * table, and each stage of the separable solve (x transform, z transform,
+ * y tridiagonal, inverse z, inverse x; Section 2.3.3, items S2.1-S2.2) is
+ * ONE persistent launch whose waves walk a device work list of tiles drawn
+ * from all grids, so a batch of G grids of any sizes replays as 5 kernel
+ * launches in one graph.  FP64 arithmetic throughout (plain FP64
+ * matrix-core transforms against each grid's eigenbases, Thomas pencils):
+ * results agree with solve_poisson / solve_helmholtz_batch to rounding, not
+ * bitwise.  Jobs: plans uploaded, precision IBS_FP64, walls in y (not
+ * periodic y), strict_compat 0, any x / z conditions (uniform or
+ * stretched); workspaces as for the single solves (solver_plan_bytes),
+ * one of its own per job (jobs run side by side); rhs may alias x.  info
+ * reports as the FP64 solves do.  The builder allocates one device buffer
+ * (job table, work lists and transform tables; freed by
+ * ibs_batch_destroy()).  Errors: IBS_ERR_INVALID_ARG (bad job, shared
+ * workspace), IBS_ERR_UNSUPPORTED (refined or periodic-y plan, strict
+ * compatibility), IBS_ERR_NOT_UPLOADED, IBS_ERR_WORKSPACE_TOO_SMALL,
+ * IBS_ERR_HIP. */
+ibs_status ibs_batch_build_multigrid(const ibs_batch_job *jobs, int32_t njobs, ibs_batch *out);
 /* Replay the whole batch on stream with one graph launch (asynchronous). */
 ibs_status ibs_batch_launch(ibs_batch batch, void *stream);
 ibs_status ibs_batch_destroy(ibs_batch batch);

@@ -4,7 +4,9 @@ Each job is one fractional-step solve set on its own grid: the three
 Helmholtz components (one batched call) and one pressure Poisson solve.
 The library records all jobs into one graph (ibs_batch_build) whose
 independent branches let small grids overlap on the device; a replay is one
-hipGraphLaunch.  Buffers are torch allocations that live as long as the
+hipGraphLaunch.  mode="multigrid" (FP64 plans) builds the batch with
+ibs_batch_build_multigrid instead: each solve stage is one persistent
+launch over every grid, five launches per replay whatever the job count.  Buffers are torch allocations that live as long as the
 batch.
 """
 from __future__ import annotations
@@ -33,7 +35,7 @@ BC_KINDS = {
 
 
 class Job:
-    def __init__(self, spec, precision, device):
+    def __init__(self, spec, precision, device, own_poisson_work=False):
         nx, ny, nz = spec["nx"], spec["ny"], spec["nz"]
         self.spec = spec
         self.solver = ibs.Solver(nx, ny, nz, beta=spec["beta"], precision=precision, device=device,
@@ -48,6 +50,12 @@ class Job:
         self.b = synth.device_normal(S.shape(0), seed * 8 + 5, S.device)
         self.x = [S.empty(op) for op in (1, 2, 3)]
         self.phi = S.empty(0)
+        # multi-grid batches run every job side by side: the Poisson solve
+        # then needs a workspace of its own
+        self.work_p = None
+        if own_poisson_work:
+            import torch
+            self.work_p = torch.empty(S.work_p, dtype=torch.uint8, device=S.device)
 
     @property
     def cell_solves(self) -> int:
@@ -57,7 +65,7 @@ class Job:
     def records(self):
         S = self.solver
         return [S.helmholtz_job([0, 1, 2], [self.c] * 3, self.r, self.x, info_slot=0),
-                S.poisson_job(self.b, self.phi, info_slot=3)]
+                S.poisson_job(self.b, self.phi, info_slot=3, work=self.work_p)]
 
     def run_eager(self):
         S = self.solver
@@ -75,15 +83,21 @@ class Batch:
     run during tuning); self.schedule records (nlanes, policy, ms)."""
 
     def __init__(self, specs, precision=ibs.IBS_REFINED_BF16X3, nlanes=8, device="cuda",
-                 policy=ibs.IBS_SCHED_BALANCED, tune_reps=3):
+                 policy=ibs.IBS_SCHED_BALANCED, tune_reps=3, mode="graph"):
         import torch
         self.torch = torch
-        self.jobs = [Job(s, precision, device) for s in specs]
+        if mode not in ("graph", "multigrid"):
+            raise ValueError(mode)
+        self.mode = mode
+        self.jobs = [Job(s, precision, device, own_poisson_work=mode == "multigrid") for s in specs]
         torch.cuda.synchronize()
         recs = []
         for j in self.jobs:
             recs.extend(j.records())
         self.schedule = None
+        if mode == "multigrid":
+            self.handle = ibs.ibs_batch_build_multigrid(recs)
+            return
         if nlanes == "auto":
             stream = torch.cuda.current_stream().cuda_stream
             nlanes, policy, ms = ibs.ibs_batch_autotune(recs, tune_reps, stream)

@@ -16,7 +16,7 @@ OBJDIR = os.path.join(HERE, "_build")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SOURCES = ["api.cpp", "plan.cpp", "k_xform.hip", "k_fold.hip", "k_tridiag.hip", "k_tridiag_cyc.hip",
-           "k_stencil.hip", "k_split.hip", "k_fstep.hip", "batch.cpp", "noalloc.hip"]
+           "k_stencil.hip", "k_split.hip", "k_fstep.hip", "k_multigrid.hip", "batch.cpp", "noalloc.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE,
          # no packed FP32 instructions in device code

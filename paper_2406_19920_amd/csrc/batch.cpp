@@ -13,11 +13,15 @@
 // each job's launches in the same order on its own workspace, so the
 // results do not depend on the schedule.
 #include <algorithm>
+#include <cmath>
+#include <cstring>
 #include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "ibs_internal.h"
+#include "multigrid.h"
 
 namespace ibs {
 ibs_status profile_suspend(ibs_plan plan, bool *was_on);
@@ -31,6 +35,7 @@ struct ibs_batch_s {
     hipGraphExec_t exec = nullptr;
     int njobs = 0;
     int nlanes = 0;
+    void *dev = nullptr;   // multi-grid batches: job table, work lists, tables
 };
 
 static ibs_status fail_hip(hipError_t e, const char *where)
@@ -186,8 +191,176 @@ ibs_status ibs_batch_destroy(ibs_batch batch)
     if (!batch) return IBS_OK;
     if (batch->exec) hipGraphExecDestroy(batch->exec);
     if (batch->graph) hipGraphDestroy(batch->graph);
+    if (batch->dev) hipFree(batch->dev);
     delete batch;
     return IBS_OK;
+}
+
+// Multi-grid batch: the fields of every job in one device job table, one
+// work list per stage kind (x transforms: 64 x 64 tiles of rows x modes; z
+// transforms: 64 x 64 tiles of modes x columns; pencils: 64-pencil runs of
+// a plane), the plain transform tables of every (plan, axis, kind,
+// direction) used, and a graph of the five stage launches.
+ibs_status ibs_batch_build_multigrid(const ibs_batch_job *jobs, int32_t njobs, ibs_batch *out)
+{
+    if (!jobs || njobs < 1 || !out) {
+        set_error("jobs, out must be non-NULL, njobs >= 1");
+        return IBS_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    ibs_status chk = check_jobs(jobs, njobs);
+    if (chk != IBS_OK) return chk;
+    std::map<void *, int> works;
+    for (int q = 0; q < njobs; ++q) {
+        const ibs_batch_job &j = jobs[q];
+        const Plan &p = *reinterpret_cast<const Plan *>(j.plan);
+        const std::string who = "multi-grid job " + std::to_string(q) + ": ";
+        if (!p.dev_const) { set_error(who + "plan not uploaded"); return IBS_ERR_NOT_UPLOADED; }
+        if (p.desc.precision != IBS_FP64 || p.py || p.desc.strict_compat) {
+            set_error(who + "multi-grid batches take FP64 plans with walls in y and strict_compat 0");
+            return IBS_ERR_UNSUPPORTED;
+        }
+        const int nc = j.op == IBS_OP_POISSON ? 1 : j.ncomp;
+        if (!j.work || j.work_bytes < work_bytes_for(p, j.op, nc)) {
+            set_error(who + "workspace missing or too small");
+            return IBS_ERR_WORKSPACE_TOO_SMALL;
+        }
+        if (works.count(j.work)) {
+            set_error(who + "multi-grid jobs run side by side and need workspaces of their own");
+            return IBS_ERR_INVALID_ARG;
+        }
+        works[j.work] = q;
+        for (int k = 0; k < nc; ++k) {
+            if (!j.rhs[k] || !j.x[k]) { set_error(who + "rhs and x must be non-NULL"); return IBS_ERR_INVALID_ARG; }
+            if (j.op != IBS_OP_POISSON &&
+                (j.comp[k] < 0 || j.comp[k] > 2 || !(j.c[k] >= 0.0) || !std::isfinite(j.c[k]))) {
+                set_error(who + "comp must be 0..2 and c finite and >= 0");
+                return IBS_ERR_INVALID_ARG;
+            }
+        }
+    }
+
+    // host images: tables first (deduplicated), then fields and work lists
+    std::vector<double> tables;
+    std::map<std::tuple<const Plan *, int, int, int>, size_t> table_at;   // (plan, axis, kind, inv) -> doubles
+    auto table = [&](const Plan &p, bool z, int kind, bool inv) {
+        const auto key = std::make_tuple(&p, z ? 1 : 0, kind, inv ? 1 : 0);
+        auto it = table_at.find(key);
+        if (it != table_at.end()) return it->second;
+        std::vector<double> t;
+        plain_transform_table(p, z, kind, inv, t);
+        const size_t at = tables.size();
+        tables.insert(tables.end(), t.begin(), t.end());
+        tables.resize((tables.size() + 31) & ~size_t(31));   // 256-byte aligned tables
+        table_at[key] = at;
+        return at;
+    };
+    struct Pending { MgField f; size_t xf, xi, zf, zi; };
+    std::vector<Pending> fields;
+    for (int q = 0; q < njobs; ++q) {
+        const ibs_batch_job &j = jobs[q];
+        const Plan &p = *reinterpret_cast<const Plan *>(j.plan);
+        const bool pois = j.op == IBS_OP_POISSON;
+        const int nc = pois ? 1 : j.ncomp;
+        for (int k = 0; k < nc; ++k) {
+            const int comp = pois ? -1 : j.comp[k];
+            const int kind = pois ? KIND_P : comp_kind(p, comp);
+            const int xk = pois ? XK_P : comp_xkind(p, comp);
+            const int zk = pois ? XK_P : comp_zkind(p, comp);
+            Pending e{};
+            MgField &f = e.f;
+            f.in = j.rhs[k];
+            f.out = j.x[k];
+            f.work = static_cast<double *>(j.work) + (size_t)k * p.nz * (p.ny + 1) * p.nx;
+            f.lam_x = blob_ptr(p, p.lay.lam_x[xk]);
+            f.lam_z = blob_ptr(p, p.lay.lam_z[zk]);
+            f.lo = blob_ptr(p, p.lay.lo[kind]);
+            f.di = blob_ptr(p, p.lay.di[kind]);
+            f.up = blob_ptr(p, p.lay.up[kind]);
+            f.wy = blob_ptr(p, p.lay.wy);
+            f.info = j.info ? j.info + k : nullptr;
+            f.c = pois ? 0.0 : j.c[k];
+            f.inv_sqrt_nxnz = 1.0 / std::sqrt((double)p.nx * (double)p.nz);
+            f.nx = p.nx; f.ny = p.ny; f.nz = p.nz;
+            f.rows = p.rows[kind];
+            f.kind = kind;
+            f.poisson = pois ? 1 : 0;
+            e.xf = table(p, false, xk, false);
+            e.xi = table(p, false, xk, true);
+            e.zf = table(p, true, zk, false);
+            e.zi = table(p, true, zk, true);
+            fields.push_back(e);
+        }
+    }
+    std::vector<int4> xitems, zitems, titems;
+    for (size_t fi = 0; fi < fields.size(); ++fi) {
+        const MgField &f = fields[fi].f;
+        const int trows = f.rows - skip_first_row(f.kind);
+        for (int r = 0; r < f.nz * trows; r += 64)
+            for (int c = 0; c < f.nx; c += 64) xitems.push_back(make_int4((int)fi, r, c, 0));
+        for (int r = 0; r < f.nz; r += 64)
+            for (int c = 0; c < trows * f.nx; c += 64) zitems.push_back(make_int4((int)fi, r, c, 0));
+        for (int c = 0; c < f.nz; ++c)
+            for (int a = 0; a < f.nx; a += 64) titems.push_back(make_int4((int)fi, c, a, 0));
+    }
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t o_tab = 0;
+    const size_t o_fld = al(o_tab + tables.size() * sizeof(double));
+    const size_t o_x = al(o_fld + fields.size() * sizeof(MgField));
+    const size_t o_z = al(o_x + xitems.size() * sizeof(int4));
+    const size_t o_t = al(o_z + zitems.size() * sizeof(int4));
+    const size_t total = al(o_t + titems.size() * sizeof(int4));
+
+    ibs_batch_s *b = new ibs_batch_s();
+    hipStream_t cap = nullptr;
+    hipError_t e;
+    ibs_status st = IBS_OK;
+    std::vector<unsigned char> img(total, 0);
+    unsigned char *dev = nullptr;
+    if ((e = hipMalloc(&b->dev, total)) != hipSuccess) { st = fail_hip(e, "multi-grid buffer"); goto fail; }
+    dev = static_cast<unsigned char *>(b->dev);
+    std::memcpy(img.data() + o_tab, tables.data(), tables.size() * sizeof(double));
+    for (size_t fi = 0; fi < fields.size(); ++fi) {
+        MgField f = fields[fi].f;
+        f.xfwd = reinterpret_cast<const double *>(dev + o_tab) + fields[fi].xf;
+        f.xinv = reinterpret_cast<const double *>(dev + o_tab) + fields[fi].xi;
+        f.zfwd = reinterpret_cast<const double *>(dev + o_tab) + fields[fi].zf;
+        f.zinv = reinterpret_cast<const double *>(dev + o_tab) + fields[fi].zi;
+        std::memcpy(img.data() + o_fld + fi * sizeof(MgField), &f, sizeof(MgField));
+    }
+    std::memcpy(img.data() + o_x, xitems.data(), xitems.size() * sizeof(int4));
+    std::memcpy(img.data() + o_z, zitems.data(), zitems.size() * sizeof(int4));
+    std::memcpy(img.data() + o_t, titems.data(), titems.size() * sizeof(int4));
+    if ((e = hipMemcpy(b->dev, img.data(), total, hipMemcpyHostToDevice)) != hipSuccess) { st = fail_hip(e, "multi-grid upload"); goto fail; }
+    if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) { st = fail_hip(e, "capture stream"); goto fail; }
+    if ((e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) { st = fail_hip(e, "begin capture"); goto fail; }
+    {
+        const MgField *fl = reinterpret_cast<const MgField *>(dev + o_fld);
+        const int4 *xi = reinterpret_cast<const int4 *>(dev + o_x);
+        const int4 *zi = reinterpret_cast<const int4 *>(dev + o_z);
+        const int4 *ti = reinterpret_cast<const int4 *>(dev + o_t);
+        const int nx_ = (int)xitems.size(), nz_ = (int)zitems.size(), nt_ = (int)titems.size();
+        hipError_t le = launch_multigrid_stage(MG_X_FWD, fl, xi, nx_, cap);
+        if (le == hipSuccess) le = launch_multigrid_stage(MG_Z_FWD, fl, zi, nz_, cap);
+        if (le == hipSuccess) le = launch_multigrid_stage(MG_TRI, fl, ti, nt_, cap);
+        if (le == hipSuccess) le = launch_multigrid_stage(MG_Z_INV, fl, zi, nz_, cap);
+        if (le == hipSuccess) le = launch_multigrid_stage(MG_X_INV, fl, xi, nx_, cap);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cap, &g);
+        if (le != hipSuccess) { if (g) hipGraphDestroy(g); st = fail_hip(le, "multi-grid stage launch"); goto fail; }
+        if (e != hipSuccess) { st = fail_hip(e, "end capture"); goto fail; }
+        b->graph = g;
+    }
+    if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess) { st = fail_hip(e, "instantiate"); goto fail; }
+    hipStreamDestroy(cap);
+    b->njobs = njobs;
+    b->nlanes = 1;
+    *out = b;
+    return IBS_OK;
+fail:
+    if (cap) hipStreamDestroy(cap);
+    ibs_batch_destroy(b);
+    return st;
 }
 
 ibs_status ibs_batch_autotune(const ibs_batch_job *jobs, int32_t njobs, int32_t reps, int32_t *nlanes,

@@ -211,6 +211,7 @@ inline int comp_zkind(const Plan &p, int comp)
 // Workspace of one solve call: the work fields and the state after them.
 size_t field_bytes_for(const Plan &p, int op, int ncomp);
 size_t state_bytes_for(const Plan &p, int op, int ncomp);
+size_t work_bytes_for(const Plan &p, int op, int ncomp);
 State state_in(const Plan &p, void *work, int op, int ncomp);
 
 // ---- kernel launchers (return hipError_t of the launch) --------------------

@@ -8,6 +8,7 @@
 #include <new>
 
 #include "ibs_internal.h"
+#include "multigrid.h"
 
 namespace ibs {
 
@@ -505,6 +506,20 @@ static std::shared_ptr<const AxisTables> build_axis(int n, double h, bool z_axis
         }
     }
     return t;
+}
+
+void plain_transform_table(const Plan &p, bool z_axis, int kind, bool inverse, std::vector<double> &out)
+{
+    const int n = z_axis ? p.nz : p.nx;
+    const std::vector<double> &Q = z_axis ? p.qz[kind] : p.qx[kind];
+    const std::vector<double> &G = z_axis ? p.gz[kind] : p.gx[kind];
+    out.assign(size_t(n) * n, 0.0);
+    std::vector<double> t(size_t(n) * n);
+    const std::vector<double> &M = inverse ? G : Q;
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < n; ++a) t[size_t(a) * n + i] = M[size_t(i) * n + a];
+    if (!z_axis) swizzle_b(inverse ? t.data() : Q.data(), n, n, out.data());   // X Q, Xhat G^T
+    else swizzle_a(inverse ? G.data() : t.data(), n, n, out.data());           // Q^T X, G Xhat
 }
 
 // Cache of axis tables, at most AXIS_CACHE_BYTES of host memory (oldest

@@ -34,7 +34,7 @@ EXPORTS = ("solver_plan", "solver_plan_bytes", "solver_plan_upload", "solver_pla
            "solve_poisson", "solve_poisson_noalloc", "solve_helmholtz_batch", "residual",
            "ibs_divergence", "ibs_wall_data", "ibs_stage_bytes", "ibs_rk_stage",
            "ibs_correct", "ibs_plan_export", "ibs_profile", "ibs_profile_read",
-           "ibs_batch_build", "ibs_batch_build_sched", "ibs_batch_autotune",
+           "ibs_batch_build", "ibs_batch_build_sched", "ibs_batch_autotune", "ibs_batch_build_multigrid",
            "ibs_batch_launch", "ibs_batch_destroy",
            "ibs_autotune_bytes", "ibs_autotune", "ibs_plan_set_tiles",
            "ibs_last_error", "ibs_version")
@@ -119,6 +119,7 @@ def _load():
     L.ibs_plan_set_tiles.argtypes = [vp, ctypes.POINTER(i32), i32]
     L.ibs_batch_build.argtypes = [ctypes.POINTER(ibs_batch_job), i32, i32, ctypes.POINTER(vp)]
     L.ibs_batch_build_sched.argtypes = [ctypes.POINTER(ibs_batch_job), i32, i32, i32, ctypes.POINTER(vp)]
+    L.ibs_batch_build_multigrid.argtypes = [ctypes.POINTER(ibs_batch_job), i32, ctypes.POINTER(vp)]
     L.ibs_batch_autotune.argtypes = [ctypes.POINTER(ibs_batch_job), i32, i32, ctypes.POINTER(i32),
                                      ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float), vp]
     L.ibs_batch_launch.argtypes = [vp, vp]
@@ -284,6 +285,14 @@ def ibs_batch_build(jobs, nlanes: int, policy: int = IBS_SCHED_BALANCED) -> int:
     arr = (ibs_batch_job * len(jobs))(*jobs)
     h = ctypes.c_void_p()
     _check(lib.ibs_batch_build_sched(arr, len(jobs), nlanes, policy, ctypes.byref(h)), "ibs_batch_build_sched")
+    return h.value
+
+
+def ibs_batch_build_multigrid(jobs) -> int:
+    """Multi-grid batch: one persistent launch per solve stage over all jobs."""
+    arr = (ibs_batch_job * len(jobs))(*jobs)
+    h = ctypes.c_void_p()
+    _check(lib.ibs_batch_build_multigrid(arr, len(jobs), ctypes.byref(h)), "ibs_batch_build_multigrid")
     return h.value
 
 
@@ -455,14 +464,18 @@ class Solver:
                     p.data_ptr() if p is not None else None,
                     lap_phi.data_ptr() if lap_phi is not None else None, cp, self.stream())
 
-    def poisson_job(self, b, phi, info_slot=0):
-        """An ibs_batch_job record for a Poisson solve (buffers must outlive the batch)."""
+    def poisson_job(self, b, phi, info_slot=0, work=None):
+        """An ibs_batch_job record for a Poisson solve (buffers must outlive the
+        batch); work: a workspace tensor of its own instead of the solver's."""
         self._chk(b, IBS_OP_POISSON)
         self._chk(phi, IBS_OP_POISSON)
         j = ibs_batch_job()
         j.plan, j.op, j.ncomp = self.plan, IBS_OP_POISSON, 1
         j.rhs[0], j.x[0] = b.data_ptr(), phi.data_ptr()
-        j.work, j.work_bytes = self.work.data_ptr(), self.work_bytes
+        if work is None:
+            j.work, j.work_bytes = self.work.data_ptr(), self.work_bytes
+        else:
+            j.work, j.work_bytes = work.data_ptr(), work.numel() * work.element_size()
         j.info = self.info[info_slot].data_ptr()
         return j
 
