@@ -299,6 +299,7 @@ def main():
     # --config modes run them in full)
     configs = None
     if not args.no_extra_configs and n == 256 and beta == 2.0:
+        from paper_2406_19920_amd import synth
         configs = {}
         log("config c3")
         c3, c3w = run_c3(5, 1)
@@ -325,6 +326,13 @@ def main():
                                "unit": "Mcell-steps/s (cells x full RK3 steps per second)", **rr}
         log("config c4")
         configs["c4"] = run_batch(5, 1)
+        configs["c4_fp64_forms"] = run_batch_modes(
+            5, 1, synth.batch_specs(64, seed=4),
+            "the 64 mixed-size jobs (64^3 to 192x256x192), FP64: graph lanes vs multi-grid stage launches")
+        configs["small_grids"] = run_batch_modes(
+            10, 2, synth.batch_specs(128, seed=5, sizes=((32, 32, 32), (48, 32, 48), (64, 64, 64))),
+            "128 jobs of 32^3, 48x32x48 and 64^3 (beta ~ U[0,3]), Poisson + 3 Helmholtz each, FP64: "
+            "graph lanes vs multi-grid stage launches")
         log("config c5")
         rows, nwarm, w5 = run_serve([200.0, 1000.0, 5000.0], 300)
         configs["c5"] = {"workload": w5, "unit": "Mcell-solves/s", "sweep": rows}
@@ -403,6 +411,36 @@ def run_batch(steps, warmup, njobs=64):
            "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))},
            "all_status_ok": all(s == 0 for s in status)}
     B.close()
+    return out
+
+
+def run_batch_modes(steps, warmup, specs, label):
+    """The same FP64 jobs as a graph of per-grid launch sequences (schedule
+    autotuned) and as a multi-grid batch (one persistent launch per stage
+    over all grids): ms per replay and throughput of each, and the form the
+    batch's own chooser (mode="auto") keeps."""
+    import torch
+    from paper_2406_19920_amd import batch, ibsolve as ibs
+    out = {"workload": label, "unit": "Mcell-solves/s", "steps": steps, "warmup": warmup}
+    for mode in ("graph", "multigrid"):
+        log("batch", label, mode)
+        B = batch.Batch(specs, precision=ibs.IBS_FP64, nlanes="auto", mode=mode)
+        for _ in range(warmup):
+            B.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            B.launch()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        status = [j.solver.read_info(q).status for j in B.jobs for q in (0, 1, 2, 3)]
+        out[mode] = {"value": B.cell_solves / (ms * 1e-3) / 1e6, "ms_per_launch": ms,
+                     "kernel_launches_per_replay": 5 if mode == "multigrid" else None,
+                     "all_status_ok": all(st == 0 for st in status)}
+        if mode == "graph":
+            out[mode]["schedule"] = {"nlanes": B.schedule[0], "policy": ["balanced", "in_order"][B.schedule[1]]}
+        B.close()
+    out["faster"] = min(("graph", "multigrid"), key=lambda m: out[m]["ms_per_launch"])
     return out
 
 

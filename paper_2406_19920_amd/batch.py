@@ -80,23 +80,46 @@ class Batch:
     """All jobs of a batch, captured once; launch() replays the graph.
     nlanes="auto": the schedule (lane count and policy) is chosen by the
     library's schedule autotuner, timed on the device at set-up (the jobs
-    run during tuning); self.schedule records (nlanes, policy, ms)."""
+    run during tuning); self.schedule records (nlanes, policy, ms).
+    mode: "graph" (per-grid launch sequences on graph lanes), "multigrid"
+    (FP64: one persistent launch per stage over all grids) or "auto" (FP64:
+    both timed at set-up, the faster kept; self.mode names it and
+    self.timings holds both ms per replay)."""
 
     def __init__(self, specs, precision=ibs.IBS_REFINED_BF16X3, nlanes=8, device="cuda",
                  policy=ibs.IBS_SCHED_BALANCED, tune_reps=3, mode="graph"):
         import torch
         self.torch = torch
-        if mode not in ("graph", "multigrid"):
+        if mode not in ("graph", "multigrid", "auto"):
             raise ValueError(mode)
+        if mode == "auto" and precision != ibs.IBS_FP64:
+            mode = "graph"                 # multi-grid batches are FP64 only
         self.mode = mode
-        self.jobs = [Job(s, precision, device, own_poisson_work=mode == "multigrid") for s in specs]
+        self.jobs = [Job(s, precision, device, own_poisson_work=mode != "graph") for s in specs]
         torch.cuda.synchronize()
         recs = []
         for j in self.jobs:
             recs.extend(j.records())
         self.schedule = None
+        self.timings = None
         if mode == "multigrid":
             self.handle = ibs.ibs_batch_build_multigrid(recs)
+            return
+        if mode == "auto":
+            # both forms timed on the device (the jobs run), the faster kept:
+            # many small grids favour the multi-grid stage launches, large
+            # ones the per-grid folded transforms of the graph
+            stream = torch.cuda.current_stream().cuda_stream
+            nl, pol, ms_graph = ibs.ibs_batch_autotune(recs, tune_reps, stream)
+            mg = ibs.ibs_batch_build_multigrid(recs)
+            ms_mg = self._time(mg, tune_reps)
+            self.timings = {"graph": ms_graph, "multigrid": ms_mg}
+            if ms_mg < ms_graph:
+                self.mode, self.handle = "multigrid", mg
+                return
+            ibs.ibs_batch_destroy(mg)
+            self.mode, self.schedule = "graph", (nl, pol, ms_graph)
+            self.handle = ibs.ibs_batch_build(recs, nl, pol)
             return
         if nlanes == "auto":
             stream = torch.cuda.current_stream().cuda_stream
@@ -107,6 +130,23 @@ class Batch:
     @property
     def cell_solves(self) -> int:
         return sum(j.cell_solves for j in self.jobs)
+
+    def _time(self, handle, reps):
+        """Best of three rounds of reps replays (ms per replay), after one
+        untimed replay."""
+        torch = self.torch
+        s = torch.cuda.current_stream().cuda_stream
+        ibs.ibs_batch_launch(handle, s)
+        best = float("inf")
+        for _ in range(3):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                ibs.ibs_batch_launch(handle, s)
+            b.record()
+            b.synchronize()
+            best = min(best, a.elapsed_time(b) / reps)
+        return best
 
     def launch(self, stream=None):
         s = self.torch.cuda.current_stream().cuda_stream if stream is None else stream

@@ -235,3 +235,25 @@ def test_multigrid_refuses_bad_jobs(mods):
     assert e.value.status == ibs.IBS_ERR_INVALID_ARG
     for s in (S, P, F):
         s.close()
+
+
+def test_batch_auto_picks_a_form(mods):
+    """mode="auto" times both forms on the device and keeps the faster; the
+    kept batch's results match the single-grid FP64 solves."""
+    ibs, batch = mods
+    _say("case batch auto")
+    specs = synth.batch_specs(12, seed=9, sizes=((32, 32, 32), (64, 48, 64)))
+    B = batch.Batch(specs, precision=ibs.IBS_FP64, mode="auto", tune_reps=2)
+    try:
+        _say("auto kept", B.mode, "timings", B.timings)
+        assert B.mode in ("graph", "multigrid") and set(B.timings) == {"graph", "multigrid"}
+        assert B.timings[B.mode] == min(B.timings.values())
+        B.launch()
+        torch.cuda.synchronize()
+        for j in B.jobs:
+            got = [t.cpu().numpy() for t in j.outputs()]
+            S = j.solver
+            ref = [t.cpu().numpy() for t in S.helmholtz([0, 1, 2], [j.c] * 3, j.r)] + [S.poisson(j.b).cpu().numpy()]
+            assert max(_maxrel(a, b) for a, b in zip(got, ref)) < 1e-12
+    finally:
+        B.close()
