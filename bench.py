@@ -142,10 +142,11 @@ def main():
     ap.add_argument("--no-extra-configs", action="store_true",
                     help="skip the shortened 512x384x384, 64-job batch and serving runs that the "
                          "default run appends under 'configs'")
-    ap.add_argument("--config", choices=["c2", "c3", "batch", "serve", "rk3"], default="c2",
+    ap.add_argument("--config", choices=["c2", "c3", "batch", "serve", "rk3", "small_grids"], default="c2",
                     help="c2: 256^3 step (default); c3: 512x384x384 refined step with a forcing "
                          "shell; batch: 64 mixed-size jobs as one graph; serve: arrival-rate sweep; "
-                         "rk3: full Runge-Kutta step with immersed markers at --n^3")
+                         "rk3: full Runge-Kutta step with immersed markers at --n^3; small_grids: 128 "
+                         "FP64 jobs of 32^3-64^3 as graph lanes and as multi-grid stage launches")
     ap.add_argument("--count", type=int, default=2000, help="serve: requests per rate")
     ap.add_argument("--rates", type=str, default="100,200,500,1000,2000,5000")
     ap.add_argument("--geometries", type=int, default=0,
@@ -179,6 +180,19 @@ def main():
         return bench_c3(args)
     if args.config == "rk3":
         return bench_rk3(args)
+    if args.config == "small_grids":
+        from paper_2406_19920_amd import synth
+        r = run_batch_modes(args.steps, args.warmup,
+                            synth.batch_specs(128, seed=5, sizes=((32, 32, 32), (48, 32, 48), (64, 64, 64))),
+                            "128 jobs of 32^3, 48x32x48 and 64^3 (beta ~ U[0,3]), Poisson + 3 Helmholtz "
+                            "each, FP64")
+        best = r[r["faster"]]
+        print(json.dumps({"metric": "Mcell-solves/s, 128 small FP64 jobs (Poisson + 3 Helmholtz)",
+                          "value": best["value"], "unit": "Mcell-solves/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": best["ms_per_launch"],
+                          "higher_is_better": True, "vs_baseline": None, "dtype": "f64",
+                          "data": "synthetic", "config": {"workload": r["workload"]}, "forms": r}))
+        return
 
     n, beta = args.n, args.beta
     dev = torch.device("cuda:0")
