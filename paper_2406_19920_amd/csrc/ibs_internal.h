@@ -67,6 +67,7 @@ constexpr int XSUM_SLOTS = 4096;     // max residual blocks per job (fixed order
 constexpr int COMPAT_SLOTS = 2048;   // max blocks of the compatibility reduction
 constexpr int RESID_SLOTS = 4096;    // max blocks of the residual() norm reduction
 constexpr int MAX_PASSES = 8;        // most refinement passes a solve may take (max_iter)
+constexpr int MAX_PLANES = 1024;     // largest nz a plan accepts
 // Refined path: pressure pencils whose condition bound 1 + g/|s| (g the
 // Gershgorin bound of the y operator, s the pencil's transverse eigenvalue)
 // exceeds this are solved with FP64 arithmetic (the FP64 lane); the rest in

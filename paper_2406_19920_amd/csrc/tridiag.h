@@ -144,6 +144,11 @@ __global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
     __shared__ R sx[(DB ? 2 : 1) * NRS * LDR];
     __shared__ R slo[NRS], sdi[NRS], sup[NRS], sw[NRS];
     __shared__ double xs_sm[NT / 64];   // per-wave sums of the x-sum partials
+    // the FP64-lane mask (lane_mode 1), staged once per block: read per tile
+    // from LDS, its check waits on the LDS counter only, where a global
+    // load would make the wave wait for every load in flight (the next
+    // tiles' prefetch included)
+    __shared__ unsigned lm_sm[MAX_PLANES];
 
     const int tid = threadIdx.x;
     const int nx = tp.nx;
@@ -190,8 +195,11 @@ __global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
         }
     };
     // tiles left to the FP64 lane (lane_mode 1): block-uniform
+    if (tp.lane_mode == 1)
+        for (int q = tid; q < tp.nz; q += NT) lm_sm[q] = tp.lane_mask[q];
+    __syncthreads();
     auto lane_skipped = [&](int c, int a0) {
-        return tp.lane_mode == 1 && ((tp.lane_mask[c] >> (a0 >> 5)) & 1u);
+        return tp.lane_mode == 1 && ((lm_sm[c] >> (a0 >> 5)) & 1u);
     };
     // raw values only: conversion and wall rows are applied when the tile is
     // staged, so that nothing here waits for the loads
