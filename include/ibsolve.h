@@ -69,7 +69,10 @@ typedef enum {
                                solver_plan() returns IBS_ERR_UNSUPPORTED        */
     IBS_REFINED_BF16X3 = 2, /* split-BF16 (3 terms) transforms, FP32
                                accumulation, FP32 work arrays, refined against
-                               an FP64 residual                                 */
+                               an FP64 residual stored scaled by a power of
+                               two taken from the first pass (rhs magnitudes
+                               of about 1e-30 to 1e35 converge; beyond, a
+                               solve may report IBS_ERR_NOT_CONVERGED)          */
     IBS_REFINED_AUTO = 3    /* reserved: library-chosen split scheme; not
                                built, so IBS_ERR_UNSUPPORTED                    */
 } ibs_precision;

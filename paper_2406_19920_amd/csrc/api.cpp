@@ -125,7 +125,8 @@ static size_t red_doubles(const Plan &p, int op, int ncomp)
 }
 
 // State layout (after the fields, 256-byte aligned): bmean[4], done[4],
-// incompat[4], xsum[4][XSUM_SLOTS], compat[2 COMPAT_SLOTS], red[...].
+// incompat[4], xsum[4][XSUM_SLOTS], compat[2 COMPAT_SLOTS], red[...],
+// bmax[4][BMAX_SLOTS], scale[4].
 size_t state_bytes_for(const Plan &p, int op, int ncomp)
 {
     size_t o = align256(STATE_JOBS * sizeof(double));
@@ -133,6 +134,8 @@ size_t state_bytes_for(const Plan &p, int op, int ncomp)
     o += align256((size_t)STATE_JOBS * XSUM_SLOTS * sizeof(double));
     o += align256(2 * (size_t)COMPAT_SLOTS * sizeof(double));
     o += align256(red_doubles(p, op, ncomp) * sizeof(double));
+    o += align256((size_t)STATE_JOBS * BMAX_SLOTS * sizeof(double));
+    o += align256(STATE_JOBS * sizeof(double));
     return o;
 }
 
@@ -151,6 +154,10 @@ State state_in(const Plan &p, void *work, int op, int ncomp)
     b += align256(2 * (size_t)COMPAT_SLOTS * sizeof(double));
     st.red = reinterpret_cast<double *>(b);
     st.red_count = red_doubles(p, op, ncomp);
+    b += align256(st.red_count * sizeof(double));
+    st.bmax = reinterpret_cast<double *>(b);
+    b += align256((size_t)STATE_JOBS * BMAX_SLOTS * sizeof(double));
+    st.scale = reinterpret_cast<double *>(b);
     return st;
 }
 
@@ -270,6 +277,10 @@ static ibs_status run_refined(Plan &p, SplitSet ss, float *const *W1, float *con
         for (int q = 0; q < ss.n; ++q)
             ss.j[q].xs = xs32 ? static_cast<void *>(W3[q]) : static_cast<void *>(ss.j[q].x);
         if (pass > 0) {
+            if (pass == 1) {
+                e = launch_residual_scale(ss, st, s);
+                if (e != hipSuccess) return hip_fail(e, "residual scale");
+            }
             for (int q = 0; q < ss.n; ++q) ss.j[q].r = W2[q];
             e = timed(p, PK_RESIDUAL, 10.0 * cells, (xs32 ? 16.0 : 20.0) * cells, s,
                       [&] { return launch_residual_f32(ss, p, st, pass, xs32, s); });

@@ -68,6 +68,7 @@ constexpr int COMPAT_SLOTS = 2048;   // max blocks of the compatibility reductio
 constexpr int RESID_SLOTS = 4096;    // max blocks of the residual() norm reduction
 constexpr int MAX_PASSES = 8;        // most refinement passes a solve may take (max_iter)
 constexpr int MAX_PLANES = 1024;     // largest nz a plan accepts
+constexpr int BMAX_SLOTS = 2048;     // partial maxima per job (two halves of 1024 blocks)
 // Refined path: pressure pencils whose condition bound 1 + g/|s| (g the
 // Gershgorin bound of the y operator, s the pencil's transverse eigenvalue)
 // exceeds this are solved with FP64 arithmetic (the FP64 lane); the rest in
@@ -86,6 +87,10 @@ struct State {
     double *compat = nullptr;  // compatibility partials (2 per block)
     double *red = nullptr;     // refinement update partials, then residual() partials
     size_t red_count = 0;      // doubles in red
+    double *bmax = nullptr;    // per job: partial maxima of the first pass's pencil data
+                               // (BMAX_SLOTS each: the FP32 tiles' blocks, then the FP64 lane's)
+    double *scale = nullptr;   // per job: power of two sigma the refinement passes scale
+                               // their FP32 residuals by
 };
 
 // Kernel classes for the optional live profile (HIP events around launches).
@@ -321,6 +326,7 @@ int residual_tiles(const Plan &p);   // residual blocks (x-sum partials) per job
 // After pass >= 1: predict the error, write the report, set the stop flag.
 // pass 0 (a one-pass solve): no estimate exists; the report says so.
 hipError_t launch_refine_check(const SplitSet &ss, const Plan &p, const State &st, int pass, hipStream_t s);
+hipError_t launch_residual_scale(const SplitSet &ss, const State &st, hipStream_t s);
 
 inline const double *blob_ptr(const Plan &p, size_t off) {
     return reinterpret_cast<const double *>(static_cast<const unsigned char *>(p.dev_const) + off);

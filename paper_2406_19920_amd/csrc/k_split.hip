@@ -172,7 +172,8 @@ template <int NBT, int WM, typename Tin, int MODE>
 __global__ __launch_bounds__(512) void split_xgemm_kernel(SplitSet ss, int nz, int K, int N,
                                                           const b8 *__restrict__ qs,
                                                           double *__restrict__ red,
-                                                          const int *__restrict__ skip)
+                                                          const int *__restrict__ skip,
+                                                          const double *__restrict__ scale)
 {
     constexpr int QCNT = NBT * 3 * 64;                // fragments per chunk
     constexpr bool DB = 2 * QCNT * 16 <= 144 * 1024;  // double buffer if it fits
@@ -180,6 +181,9 @@ __global__ __launch_bounds__(512) void split_xgemm_kernel(SplitSet ss, int nz, i
     __shared__ b8 sq[(DB ? 2 : 1) * QCNT];
     if (skip && skip[blockIdx.z]) return;   // this job has already converged
     const SplitJob &jb = ss.j[blockIdx.z];
+    // update modes: the residual was stored scaled by sigma (a power of
+    // two), so the correction is scaled back exactly
+    const double isg = (XStore<MODE>::update && scale) ? 1.0 / scale[blockIdx.z] : 1.0;
     // the job's own matrix when the jobs' x operators differ (walls in x)
     const b8 *__restrict__ qj = jb.xq ? static_cast<const b8 *>(jb.xq) : qs;
     const int rskip = skip_first_row(jb.kind), trows = jb.rows - rskip;
@@ -285,7 +289,8 @@ __global__ __launch_bounds__(512) void split_xgemm_kernel(SplitSet ss, int nz, i
                         } else if constexpr (XStore<MODE>::store) {
                             xdest<MODE>(jb)[o] = acc[i][j][q];
                         } else {
-                            const double d = (double)acc[i][j][q];
+                            // the correction of the sigma-scaled residual, unscaled
+                            const double d = (double)acc[i][j][q] * isg;
                             const double xn = (double)stored_iterate<MODE>(jb)[o] + d;
                             jb.x[o] = xn;
                             sd += d * d;
@@ -430,7 +435,8 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                                                           const b8 *__restrict__ qs,
                                                           double *__restrict__ red,
                                                           const int *__restrict__ skip, double s0,
-                                                          double s1, int tiles_per_job)
+                                                          double s1, int tiles_per_job,
+                                                          const double *__restrict__ scale)
 {
     // FS = 1: a pipeline step is one 32-deep chunk of both factors; FS = 2
     // (large n): one factor at a time, so a double-buffered step fits LDS
@@ -641,6 +647,9 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
         if (last) {   // the tile is complete: store it
             const TileRef r = tile_ref(chunk / KC);
             const SplitJob &jb = *r.jb;
+            // update modes: the residual was stored scaled by sigma (a power
+            // of two), so the correction is scaled back exactly
+            const double isg = (XStore<MODE>::update && scale) ? 1.0 / scale[r.job] : 1.0;
             double sd = 0.0, sx = 0.0;
 #pragma unroll
             for (int i = 0; i < WM; ++i) {
@@ -692,9 +701,9 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                         if constexpr (XStore<MODE>::store) {
                             xd[rr + H] = xh;
                         } else {
-                            const double xn = (double)xhold[i] + xh;
+                            const double dh = xh * isg, xn = (double)xhold[i] + dh;
                             xd[rr + H] = xn;
-                            sd += xh * xh;
+                            sd += dh * dh;
                             sx += xn * xn;
                         }
                     }
@@ -743,12 +752,12 @@ __global__ __launch_bounds__(512) void split_xfold_kernel(SplitSet ss, int nz, i
                                         xd[o1] = u + v;
                                         if (ii != 0) xd[o2] = u - v;
                                     } else {
-                                        const double d1 = u + v, x1 = xo[qq][0][jj] + d1;
+                                        const double d1 = (u + v) * isg, x1 = xo[qq][0][jj] + d1;
                                         xd[o1] = x1;
                                         sd += d1 * d1;
                                         sx += x1 * x1;
                                         if (ii != 0) {
-                                            const double d2 = u - v, x2 = xo[qq][1][jj] + d2;
+                                            const double d2 = (u - v) * isg, x2 = xo[qq][1][jj] + d2;
                                             xd[o2] = x2;
                                             sd += d2 * d2;
                                             sx += x2 * x2;
@@ -1026,7 +1035,8 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
                                                            const int *__restrict__ skip, int rb_rows,
                                                            int tiles_y, int rz, int py, int wxw, int wzw,
                                                            const double *__restrict__ sgx,
-                                                           const double *__restrict__ sgz)
+                                                           const double *__restrict__ sgz,
+                                                           const double *__restrict__ scale)
 {
     typedef Tx tx4 __attribute__((ext_vector_type(4)));
     typedef double dv4_ __attribute__((ext_vector_type(4)));
@@ -1038,6 +1048,7 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
     const size_t plane = (size_t)rows * nx;
     const Tx *__restrict__ x = static_cast<const Tx *>(jb.xs);
     const double bm = (op == IBS_OP_POISSON) ? bmean[job] : 0.0;
+    const double sg = scale[job];   // power of two: the stored residual is r sigma
     const int kz = blockIdx.x / tiles_y, ty = blockIdx.x - kz * tiles_y;
     const int k0 = kz * rz, k1 = min(nz, k0 + rz);
     const int tr = nx >> 2;                       // threads per row
@@ -1163,7 +1174,7 @@ __global__ __launch_bounds__(256) void residual_f32_kernel(SplitSet ss, int nx, 
                     lap = ((xe - xcc) - (xcc - xw)) * ihx2 + ((zp - xcc) - (xcc - zm)) * ihz2;
                 lap += cu * (wu * (double)xu[e] - xcc) - cl * (xcc - wl * (double)xl[e]);
                 const double ax = pois ? lap : xcc - cj * lap;
-                rv[e] = (wall || xwall) ? 0.f : (float)((bv[e] - bm) - ax);
+                rv[e] = (wall || xwall) ? 0.f : (float)(sg * ((bv[e] - bm) - ax));
                 if constexpr (ST) wx += wD * wnx[e] * wnz * xcc;
                 else wx += wD * xcc;
             }
@@ -1303,6 +1314,7 @@ static int resident_blocks(K kernel)
 
 template <int HBT, typename Tin, int MODE, bool INV>
 static void launch_xf(const SplitSet &ss, const Plan &p, const b8 *qs, double *red, const int *skip,
+                      const double *scale,
                       dim3 grid, hipStream_t s)
 {
     static const int resident =
@@ -1312,40 +1324,43 @@ static void launch_xf(const SplitSet &ss, const Plan &p, const b8 *qs, double *r
     const int g = ntiles < resident ? ntiles : resident;
     const double s0 = 1.0 / std::sqrt((double)p.nx), s1 = std::sqrt(2.0 / (double)p.nx);
     hipLaunchKernelGGL((split_xfold_kernel<HBT, xf_wm(HBT), Tin, MODE, INV, f_steps(HBT)>), dim3(g), dim3(512), 0, s,
-                       ss, p.nz, p.nx, qs, red, skip, s0, s1, tiles_per_job);
+                       ss, p.nz, p.nx, qs, red, skip, s0, s1, tiles_per_job, scale);
 }
 
 template <typename Tin, int MODE, bool INV>
 static void launch_xf_hb(const SplitSet &ss, const Plan &p, const b8 *qs, double *red, const int *skip,
+                      const double *scale,
                          dim3 grid, hipStream_t s)
 {
     switch (xf_hbt(p.nx)) {
-    case 2: launch_xf<2, Tin, MODE, INV>(ss, p, qs, red, skip, grid, s); break;
-    case 4: launch_xf<4, Tin, MODE, INV>(ss, p, qs, red, skip, grid, s); break;
-    case 6: launch_xf<6, Tin, MODE, INV>(ss, p, qs, red, skip, grid, s); break;
-    case 8: launch_xf<8, Tin, MODE, INV>(ss, p, qs, red, skip, grid, s); break;
-    case 12: launch_xf<12, Tin, MODE, INV>(ss, p, qs, red, skip, grid, s); break;
-    default: launch_xf<16, Tin, MODE, INV>(ss, p, qs, red, skip, grid, s); break;
+    case 2: launch_xf<2, Tin, MODE, INV>(ss, p, qs, red, skip, scale, grid, s); break;
+    case 4: launch_xf<4, Tin, MODE, INV>(ss, p, qs, red, skip, scale, grid, s); break;
+    case 6: launch_xf<6, Tin, MODE, INV>(ss, p, qs, red, skip, scale, grid, s); break;
+    case 8: launch_xf<8, Tin, MODE, INV>(ss, p, qs, red, skip, scale, grid, s); break;
+    case 12: launch_xf<12, Tin, MODE, INV>(ss, p, qs, red, skip, scale, grid, s); break;
+    default: launch_xf<16, Tin, MODE, INV>(ss, p, qs, red, skip, scale, grid, s); break;
     }
 }
 
 template <int NBT, typename Tin, int MODE>
 static void launch_x(const SplitSet &ss, const Plan &p, const b8 *qs, double *red, const int *skip,
+                      const double *scale,
                      dim3 grid, hipStream_t s)
 {
     hipLaunchKernelGGL((split_xgemm_kernel<NBT, x_wm(NBT), Tin, MODE>), grid, dim3(512), 0, s, ss,
-                       p.nz, p.nx, p.nx, qs, red, skip);
+                       p.nz, p.nx, p.nx, qs, red, skip, scale);
 }
 
 template <typename Tin, int MODE>
 static void launch_x_nb(const SplitSet &ss, const Plan &p, const b8 *qs, double *red, const int *skip,
+                      const double *scale,
                         dim3 grid, hipStream_t s)
 {
     switch (x_nbt(p.nx)) {
-    case 4: launch_x<4, Tin, MODE>(ss, p, qs, red, skip, grid, s); break;
-    case 8: launch_x<8, Tin, MODE>(ss, p, qs, red, skip, grid, s); break;
-    case 16: launch_x<16, Tin, MODE>(ss, p, qs, red, skip, grid, s); break;
-    default: launch_x<32, Tin, MODE>(ss, p, qs, red, skip, grid, s); break;
+    case 4: launch_x<4, Tin, MODE>(ss, p, qs, red, skip, scale, grid, s); break;
+    case 8: launch_x<8, Tin, MODE>(ss, p, qs, red, skip, scale, grid, s); break;
+    case 16: launch_x<16, Tin, MODE>(ss, p, qs, red, skip, scale, grid, s); break;
+    default: launch_x<32, Tin, MODE>(ss, p, qs, red, skip, scale, grid, s); break;
     }
 }
 
@@ -1362,15 +1377,16 @@ hipError_t launch_split_xgemm(const SplitSet &ss, const Plan &p, const State &st
     const size_t region = update_region(p, ss.n);
     const bool upd = mode == 2 || mode == 4;
     double *red = st.red + (upd ? (size_t)(pass - 1) * region : 0);
+    const double *scale = upd ? st.scale : nullptr;   // the residuals' sigma
     if (x_folds_split(p)) {
         const b8 *qs = reinterpret_cast<const b8 *>(blob_ptr(p, inverse ? p.lay.sxf_inv : p.lay.sxf_fwd));
         switch (in64 ? -1 : mode) {
-        case -1: launch_xf_hb<double, 0, false>(ss, p, qs, red, skip, grid, s); break;
-        case 0: launch_xf_hb<float, 0, false>(ss, p, qs, red, skip, grid, s); break;
-        case 1: launch_xf_hb<float, 1, true>(ss, p, qs, red, skip, grid, s); break;
-        case 2: launch_xf_hb<float, 2, true>(ss, p, qs, red, skip, grid, s); break;
-        case 3: launch_xf_hb<float, 3, true>(ss, p, qs, red, skip, grid, s); break;
-        default: launch_xf_hb<float, 4, true>(ss, p, qs, red, skip, grid, s); break;
+        case -1: launch_xf_hb<double, 0, false>(ss, p, qs, red, skip, scale, grid, s); break;
+        case 0: launch_xf_hb<float, 0, false>(ss, p, qs, red, skip, scale, grid, s); break;
+        case 1: launch_xf_hb<float, 1, true>(ss, p, qs, red, skip, scale, grid, s); break;
+        case 2: launch_xf_hb<float, 2, true>(ss, p, qs, red, skip, scale, grid, s); break;
+        case 3: launch_xf_hb<float, 3, true>(ss, p, qs, red, skip, scale, grid, s); break;
+        default: launch_xf_hb<float, 4, true>(ss, p, qs, red, skip, scale, grid, s); break;
         }
         return hipGetLastError();
     }
@@ -1379,12 +1395,12 @@ hipError_t launch_split_xgemm(const SplitSet &ss, const Plan &p, const State &st
     SplitSet sj = ss;   // each job's matrix for its x operator
     for (int q = 0; q < sj.n; ++q) sj.j[q].xq = blob_ptr(p, tab[sj.j[q].xk]);
     switch (in64 ? -1 : mode) {
-    case -1: launch_x_nb<double, 0>(sj, p, qs, red, skip, grid, s); break;
-    case 0: launch_x_nb<float, 0>(sj, p, qs, red, skip, grid, s); break;
-    case 1: launch_x_nb<float, 1>(sj, p, qs, red, skip, grid, s); break;
-    case 2: launch_x_nb<float, 2>(sj, p, qs, red, skip, grid, s); break;
-    case 3: launch_x_nb<float, 3>(sj, p, qs, red, skip, grid, s); break;
-    default: launch_x_nb<float, 4>(sj, p, qs, red, skip, grid, s); break;
+    case -1: launch_x_nb<double, 0>(sj, p, qs, red, skip, scale, grid, s); break;
+    case 0: launch_x_nb<float, 0>(sj, p, qs, red, skip, scale, grid, s); break;
+    case 1: launch_x_nb<float, 1>(sj, p, qs, red, skip, scale, grid, s); break;
+    case 2: launch_x_nb<float, 2>(sj, p, qs, red, skip, scale, grid, s); break;
+    case 3: launch_x_nb<float, 3>(sj, p, qs, red, skip, scale, grid, s); break;
+    default: launch_x_nb<float, 4>(sj, p, qs, red, skip, scale, grid, s); break;
     }
     return hipGetLastError();
 }
@@ -1467,6 +1483,43 @@ int residual_tiles(const Plan &p)
     return t;
 }
 
+// Power-of-two scale sigma of each job's FP32 residuals (refinement
+// passes): from the largest magnitude of the first pass's pencil data (the
+// block maxima its tridiagonal launches recorded; an orthonormal transform
+// of the rhs, within a factor sqrt(n) of its largest entry), sigma =
+// 2^-e with 2^e <= that maximum < 2^(e+1), so the residuals, about the
+// first pass's relative error times the rhs, stay far inside the FP32 and
+// bfloat16 exponent range whatever the rhs's own magnitude.  Scaling by a
+// power of two is exact: it changes no rounding unless a value would
+// otherwise leave that range.  One block per job, a fixed reduction order.
+__global__ __launch_bounds__(256) void residual_scale_kernel(const double *__restrict__ bmax,
+                                                             double *__restrict__ scale)
+{
+    __shared__ double sm[4];
+    const int job = blockIdx.x;
+    double m = 0.0;
+    for (int q = threadIdx.x; q < BMAX_SLOTS; q += blockDim.x) m = fmax(m, bmax[(size_t)job * BMAX_SLOTS + q]);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) m = fmax(m, __shfl_xor(m, d, 64));
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = fmax(fmax(sm[0], sm[1]), fmax(sm[2], sm[3]));
+        double sg = 1.0;
+        if (m > 0.0 && m <= 1.7976931348623157e308) {
+            const int e = max(-120, min(120, ilogb(m)));
+            sg = ldexp(1.0, -e);
+        }
+        scale[job] = sg;
+    }
+}
+
+hipError_t launch_residual_scale(const SplitSet &ss, const State &st, hipStream_t s)
+{
+    hipLaunchKernelGGL(residual_scale_kernel, dim3(ss.n), dim3(256), 0, s, st.bmax, st.scale);
+    return hipGetLastError();
+}
+
 hipError_t launch_residual_f32(const SplitSet &ss, const Plan &p, const State &st, int pass, bool x32,
                                hipStream_t s)
 {
@@ -1482,7 +1535,7 @@ hipError_t launch_residual_f32(const SplitSet &ss, const Plan &p, const State &s
                            1.0 / (p.hz * p.hz), blob_ptr(p, p.lay.dyc), blob_ptr(p, p.lay.dyf),
                            st.bmean, st.xsum, skip, rb_rows, tiles_y, rz, p.py ? 1 : 0, p.wx ? 1 : 0,
                            p.wz ? 1 : 0, p.sx ? blob_ptr(p, p.lay.sgx) : nullptr,
-                           p.sz ? blob_ptr(p, p.lay.sgz) : nullptr);
+                           p.sz ? blob_ptr(p, p.lay.sgz) : nullptr, st.scale);
     };
     const bool st_ = p.sx || p.sz;
     if (x32) st_ ? go(residual_f32_kernel<float, true>) : go(residual_f32_kernel<float, false>);

@@ -94,6 +94,10 @@ static hipError_t launch_tridiag(const JobSet &js, const Plan &p, const State &s
     tp.lane_list = nullptr;
     tp.lane_len = 0;
     tp.lane_mode = 0;
+    // refined path (FP32 data): the first pass records the partial maxima
+    // the residual scale is taken from; later passes steer in its units
+    tp.bmax = (sizeof(T) == 4 && pass == 0) ? st.bmax : nullptr;
+    tp.scale = (sizeof(T) == 4 && pass > 0) ? st.scale : nullptr;
     int n = 0;
     for (int q = 0; q < js.n; ++q) {
         const int rows = js.j[q].rows - skip_first_row(js.j[q].kind);   // system rows

@@ -107,6 +107,13 @@ struct TriParams {
     const int *lane_list;        // FP64-lane tiles as (c << 8) | t
     int lane_len;
     int lane_mode;
+    // refined path: the first pass's launches record per-job partial maxima
+    // of their pencil data (BMAX_SLOTS per job, one per block: the FP32
+    // tiles' launch the first half, the FP64 lane's the second), from which
+    // the refinement passes take the power of two sigma that scales their
+    // FP32 residuals; those passes then steer the mean in sigma units
+    double *bmax;          // first pass: partial maxima, or null
+    const double *scale;   // later passes: per job sigma, or null (1)
 };
 
 // T: storage type of the field (double, or float on the refined path);
@@ -119,7 +126,10 @@ struct TriParams {
 // reduction takes the neighbours at distance d modulo P, and after the last
 // step (d = P/2, where both neighbours are the lane itself) each equation
 // reads (EA + EB + EC) z = ED.
-template <typename T, typename R, int P, int M, int TA, bool CYC = false>
+// BMX: this launch records the partial maxima (the refined path's first
+// pass); a separate instantiation, so that no other launch carries the
+// tracking.
+template <typename T, typename R, int P, int M, int TA, bool CYC = false, bool BMX = false>
 __global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tridiag_kernel(JobSet js, TriParams tp, int ntx,
                                                          int ntiles)
 {
@@ -144,11 +154,6 @@ __global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
     __shared__ R sx[(DB ? 2 : 1) * NRS * LDR];
     __shared__ R slo[NRS], sdi[NRS], sup[NRS], sw[NRS];
     __shared__ double xs_sm[NT / 64];   // per-wave sums of the x-sum partials
-    // the FP64-lane mask (lane_mode 1), staged once per block: read per tile
-    // from LDS, its check waits on the LDS counter only, where a global
-    // load would make the wave wait for every load in flight (the next
-    // tiles' prefetch included)
-    __shared__ unsigned lm_sm[MAX_PLANES];
 
     const int tid = threadIdx.x;
     const int nx = tp.nx;
@@ -194,12 +199,21 @@ __global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
             a0 = (rem - c * ntx) * TA;
         }
     };
+    // maxima of |staged value| per job (BMX): each thread keeps a running
+    // maximum for the job of its current tiles and folds it into the job's
+    // LDS slot when the job changes (rarely: tiles run job by job) and at
+    // the end, by an integer max on the bit patterns (non-negative floats
+    // order as their patterns do)
+    __shared__ unsigned bmx_sm[BMX ? STATE_JOBS : 1];
+    float tmax = 0.f;
+    int tjob = -1;
+    if constexpr (BMX) {
+        if (tid < STATE_JOBS) bmx_sm[tid] = 0u;
+        __syncthreads();
+    }
     // tiles left to the FP64 lane (lane_mode 1): block-uniform
-    if (tp.lane_mode == 1)
-        for (int q = tid; q < tp.nz; q += NT) lm_sm[q] = tp.lane_mask[q];
-    __syncthreads();
     auto lane_skipped = [&](int c, int a0) {
-        return tp.lane_mode == 1 && ((lm_sm[c] >> (a0 >> 5)) & 1u);
+        return tp.lane_mode == 1 && ((tp.lane_mask[c] >> (a0 >> 5)) & 1u);
     };
     // raw values only: conversion and wall rows are applied when the tile is
     // staged, so that nothing here waits for the loads
@@ -253,6 +267,20 @@ __global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
         for (int r = 0; r < M; ++r) {
             const int j = lrow + P * r;
             sx[lr(j) * LDR + lcol] = (walls && j == n - 1) ? R(0) : (R)pf[r];
+        }
+        if constexpr (BMX) {
+            if (live) {   // block-uniform
+                if (job != tjob) {
+                    if (tjob >= 0) atomicMax(&bmx_sm[tjob], __float_as_uint(tmax));
+                    tjob = job;
+                    tmax = 0.f;
+                }
+#pragma unroll
+                for (int r = 0; r < M; ++r) {
+                    const int j = lrow + P * r;
+                    if (!(walls && j == n - 1)) tmax = fmaxf(tmax, fabsf((float)pf[r]));
+                }
+            }
         }
         const R sh = (R)(plx + plz);
         if (live && tp.xsum && pois && a0 == 0 && c == 0) {
@@ -420,7 +448,8 @@ __global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
                     double part = 0.0;
 #pragma unroll
                     for (int w = 0; w < NT / 64; ++w) part += xs_sm[w];
-                    mx += part * tp.inv_sqrt_nxnz / tp.wsum_y;
+                    const double sgj = tp.scale ? tp.scale[job] : 1.0;
+                    mx += sgj * part * tp.inv_sqrt_nxnz / tp.wsum_y;
                 }
 #pragma unroll
                 for (int t = 0; t < M; ++t)
@@ -460,10 +489,29 @@ __global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tr
         process(tile, pfa, lxa, lza, sx);
         if (tile + 1 < ntiles) process(tile + 1, pfb, lxb, lzb, DB ? sx + NRS * LDR : sx);
     }
+    if constexpr (BMX) {
+        // block maxima per job, written to slot blockIdx.x of this launch's
+        // half (the FP64 lane's launch: the second); the block also zeroes
+        // its other slots of the half (blockIdx.x + k G), and a launch of
+        // the first half the same slots of the second, which the lane's
+        // launch, if any, then fills
+        if (tjob >= 0) atomicMax(&bmx_sm[tjob], __float_as_uint(tmax));
+        __syncthreads();
+        constexpr int HALF = BMAX_SLOTS / 2;
+        const int base = tp.lane_mode == 2 ? HALF : 0;
+        for (int q = 0; q < js.n; ++q) {
+            const double m = (double)__uint_as_float(bmx_sm[q]);
+            double *dst = tp.bmax + (size_t)q * BMAX_SLOTS;
+            for (int sl = (int)blockIdx.x + G * tid; sl < HALF; sl += G * NT) {
+                dst[base + sl] = sl == (int)blockIdx.x ? m : 0.0;
+                if (tp.lane_mode != 2) dst[HALF + sl] = 0.0;
+            }
+        }
+    }
 }
 
-template <typename T, typename R, int P, int M, bool CYC = false>
-static hipError_t launch_pm(const JobSet &js, const TriParams &tp, hipStream_t s)
+template <typename T, typename R, int P, int M, bool CYC, bool BMX>
+static hipError_t launch_pm_k(const JobSet &js, const TriParams &tp, hipStream_t s)
 {
     // pencils per tile: 16; 8 for FP32 data with FP64 arithmetic, whose
     // registers allow fewer waves per SIMD (blocks of 4 waves then still
@@ -477,7 +525,7 @@ static hipError_t launch_pm(const JobSet &js, const TriParams &tp, hipStream_t s
     // run back to back
     static const int resident = [] {
         int per_cu = 0, dev = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tridiag_kernel<T, R, P, M, TA, CYC>, TA * P, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tridiag_kernel<T, R, P, M, TA, CYC, BMX>, TA * P, 0) !=
                 hipSuccess ||
             hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -489,10 +537,19 @@ static hipError_t launch_pm(const JobSet &js, const TriParams &tp, hipStream_t s
     const int ntiles = tp.lane_mode == 2 ? js.n * tp.lane_len * (32 / TA) : ntx * tp.nz * js.n;
     if (ntiles == 0) return hipSuccess;
     const int pairs = (ntiles + 1) / 2;
-    const int grid = pairs < resident ? pairs : resident;
-    hipLaunchKernelGGL((tridiag_kernel<T, R, P, M, TA, CYC>), dim3(grid), dim3(TA * P), 0, s, js, tp, ntx,
+    int grid = pairs < resident ? pairs : resident;
+    if (BMX && grid > BMAX_SLOTS / 2) grid = BMAX_SLOTS / 2;   // one slot per block
+    hipLaunchKernelGGL((tridiag_kernel<T, R, P, M, TA, CYC, BMX>), dim3(grid), dim3(TA * P), 0, s, js, tp, ntx,
                        ntiles);
     return hipGetLastError();
+}
+
+template <typename T, typename R, int P, int M, bool CYC = false>
+static hipError_t launch_pm(const JobSet &js, const TriParams &tp, hipStream_t s)
+{
+    if constexpr (sizeof(T) == 4)
+        if (tp.bmax) return launch_pm_k<T, R, P, M, CYC, true>(js, tp, s);
+    return launch_pm_k<T, R, P, M, CYC, false>(js, tp, s);
 }
 
 }  // namespace ibs
