@@ -115,7 +115,11 @@ typedef enum { IBS_PERIODIC = 0, IBS_DIRICHLET = 1, IBS_NEUMANN = 2 } ibs_bc;
  * pressure's volume weights take Delta_x Delta_y Delta_z, and the
  * transforms along it are the generalised eigenbases of S q = lambda W q
  * (S the symmetric flux form, W the control widths), computed when the
- * plan is built (implicit QL in long double; O(n^3) host time). */
+ * plan is built (implicit QL in long double; O(n^3) host time).
+ * Conditioning: a grid with a cell narrower than 1e-7 of its axis's length
+ * (tanh stretching beyond beta = 8 at 64 cells, say) is refused with
+ * IBS_ERR_UNSUPPORTED: its operators' condition number is past what FP64
+ * residuals resolve, so neither path could solve it to a known accuracy. */
 typedef struct {
     int32_t nx, ny, nz;
     double lx, ly, lz;        /* <= 0 means 1                                */

@@ -69,6 +69,14 @@ constexpr int RESID_SLOTS = 4096;    // max blocks of the residual() norm reduct
 constexpr int MAX_PASSES = 8;        // most refinement passes a solve may take (max_iter)
 constexpr int MAX_PLANES = 1024;     // largest nz a plan accepts
 constexpr int BMAX_SLOTS = 2048;     // partial maxima per job (two halves of 1024 blocks)
+// Smallest cell width a plan accepts, as a fraction of the domain length
+// along that axis.  The operators' condition numbers grow as the inverse
+// square of it: below about 1e-7 (tanh stretching beyond beta = 8 at 64
+// cells) FP64 itself no longer resolves the solution (measured on
+// manufactured solutions at beta = 10: errors of 1e-8 on the FP64 path and
+// 1e-7 on the refined one, whose FP64 residuals then cannot tell it), so
+// such grids are refused instead of solved to an accuracy no report shows.
+constexpr double MIN_CELL_FRACTION = 1e-7;
 // Refined path: pressure pencils whose condition bound 1 + g/|s| (g the
 // Gershgorin bound of the y operator, s the pencil's transverse eigenvalue)
 // exceeds this are solved with FP64 arithmetic (the FP64 lane); the rest in

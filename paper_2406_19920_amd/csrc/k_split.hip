@@ -1247,10 +1247,14 @@ __global__ __launch_bounds__(256) void refine_check_kernel(SplitSet ss, const do
     double rprev = 1.0;
     if (red_prev) {
         const double2 prev = sum_pairs(red_prev + off, slots_per_job);
-        rprev = prev.y > 0.0 ? sqrt(prev.x / prev.y) : 0.0;
+        rprev = !(isfinite(prev.x) && isfinite(prev.y)) ? __builtin_nan("")
+                                                        : (prev.y > 0.0 ? sqrt(prev.x / prev.y) : 0.0);
     }
     if (threadIdx.x == 0) {
-        const double rc = last.y > 0.0 ? sqrt(last.x / last.y) : 0.0;
+        // a non-finite norm (a NaN or infinity in the data) predicts NaN,
+        // which never meets tol
+        const bool finite = isfinite(last.x) && isfinite(last.y) && isfinite(rprev);
+        const double rc = !finite ? __builtin_nan("") : (last.y > 0.0 ? sqrt(last.x / last.y) : 0.0);
         const double ratio = rprev > 0.0 ? fmin(1.0, rc / rprev) : 1.0;
         const double predicted = rc * ratio;
         const bool ok = predicted <= tol;

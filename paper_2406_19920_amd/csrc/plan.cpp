@@ -701,6 +701,21 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
         }
     }
     for (int j = 1; j < ny; ++j) p->dyf[j] = p->yc[j] - p->yc[j - 1];
+    // conditioning: no cell below MIN_CELL_FRACTION of its axis's length
+    {
+        auto min_fraction = [](const std::vector<double> &f) {
+            double m = f[1] - f[0];
+            for (size_t i = 1; i + 1 < f.size(); ++i) m = std::min(m, f[i + 1] - f[i]);
+            return m / (f.back() - f.front());
+        };
+        if (min_fraction(p->yf) < MIN_CELL_FRACTION || min_fraction(p->xf) < MIN_CELL_FRACTION ||
+            min_fraction(p->zf) < MIN_CELL_FRACTION) {
+            set_error("a cell narrower than 1e-7 of its axis's length (the stretching is too strong): "
+                      "the operators' condition number exceeds what FP64 residuals resolve");
+            delete p;
+            return IBS_ERR_UNSUPPORTED;
+        }
+    }
     // periodic y: the centres of cells ny-1 and 0 are (Delta_{ny-1} +
     // Delta_0)/2 apart across the wrap; that distance is delta_0 = delta_ny
     if (p->py) p->dyf[0] = p->dyf[ny] = 0.5 * (p->dyc[0] + p->dyc[ny - 1]);

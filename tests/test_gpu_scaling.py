@@ -70,3 +70,51 @@ def test_refined_rhs_magnitudes(ibs, bc):
             assert ir.status == 0 and all(s == 0 for s in st)
     R.close()
     F.close()
+
+
+@pytest.mark.parametrize("n,beta", [(64, 4.0), (64, 7.0), (128, 4.0), (128, 7.0)])
+def test_strong_stretching_manufactured(ibs, n, beta):
+    """Strongly stretched walls, up to cells of 2e-7 of the height: both
+    paths return the manufactured pressure (b = L_p x_true by the oracle's
+    long-double stencil) to tol (refined) and to 1e-10 (FP64: its rounding
+    grows with the condition number, 1e-10 of the solution at beta = 7),
+    and a refined solve that stops reports success only when it met tol."""
+    import oracle
+    from oracle import OP_P
+    print("case stretching", n, beta, flush=True)
+    g = oracle.Grid(n, n, n, beta=beta)
+    xt = synth.manufactured(n, n, n, seed=7)
+    xt = xt - oracle.weighted_mean(g, OP_P, xt)
+    r, _, _ = oracle.residual_ld(g, OP_P, 0.0, xt, np.zeros_like(xt))
+    b = torch.from_numpy(-r).cuda()
+    for prec, tol in ((ibs.IBS_REFINED_BF16X3, 1e-10), (ibs.IBS_FP64, 1e-10)):
+        S = ibs.Solver(n, n, n, beta=beta, precision=prec)
+        x = S.poisson(b).cpu().numpy()
+        inf = S.read_info()
+        d = x - xt
+        err = max(np.linalg.norm(d) / np.linalg.norm(xt), np.abs(d).max() / np.abs(xt).max())
+        print(f"  precision {prec}: err {err:.2e} status {inf.status} passes {inf.iters}", flush=True)
+        assert inf.status == 0 and err < tol
+        S.close()
+
+
+def test_too_strong_stretching_refused(ibs):
+    """Cells below 1e-7 of the height (beta = 10 at 64 cells: 1.8e-9) are
+    refused at plan time on both paths."""
+    for prec in (ibs.IBS_FP64, ibs.IBS_REFINED_BF16X3):
+        with pytest.raises(ibs.IbsError) as e:
+            ibs.solver_plan(ibs.make_desc(64, 64, 64, beta=10.0, precision=prec))
+        assert e.value.status == ibs.IBS_ERR_UNSUPPORTED
+
+
+def test_refined_nan_rhs_reports_failure(ibs):
+    """A NaN in the right-hand side never comes back as a converged solve."""
+    n = 32
+    R = ibs.Solver(n, n, n, beta=1.0, precision=ibs.IBS_REFINED_BF16X3)
+    print("case nan rhs", flush=True)
+    b = synth.device_normal((n, n, n), 6, "cuda")
+    b[3, 4, 5] = float("nan")
+    R.poisson(b)
+    torch.cuda.synchronize()
+    assert R.read_info().status != 0
+    R.close()

@@ -234,3 +234,21 @@ def test_stretched_plan_build_time():
     dt = time.perf_counter() - t
     ibs.solver_plan_destroy(p)
     assert dt < 60, dt
+
+
+def test_conditioning_guard():
+    """A cell narrower than 1e-7 of its axis is refused (UNSUPPORTED) in y,
+    and in a stretched x or z; beta = 7 at 128 cells (2e-7) is accepted."""
+    p = _plan(32, 128, 32, beta=7.0)
+    ibs.solver_plan_destroy(p)
+    with pytest.raises(ibs.IbsError) as e:
+        _plan(32, 64, 32, beta=10.0)
+    assert e.value.status == ibs.IBS_ERR_UNSUPPORTED
+    f = np.linspace(0.0, 1.0, 33)
+    f[1] = 1e-9
+    with pytest.raises(ibs.IbsError) as e:
+        _plan(32, 8, 32, bc_x=ibs.IBS_DIRICHLET, x_faces=f)
+    assert e.value.status == ibs.IBS_ERR_UNSUPPORTED
+    with pytest.raises(ibs.IbsError) as e:
+        _plan(32, 8, 32, bc_z=ibs.IBS_DIRICHLET, z_faces=f)
+    assert e.value.status == ibs.IBS_ERR_UNSUPPORTED
