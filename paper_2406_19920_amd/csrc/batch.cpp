@@ -296,9 +296,9 @@ ibs_status ibs_batch_build_multigrid(const ibs_batch_job *jobs, int32_t njobs, i
     for (size_t fi = 0; fi < fields.size(); ++fi) {
         const MgField &f = fields[fi].f;
         const int trows = f.rows - skip_first_row(f.kind);
-        for (int r = 0; r < f.nz * trows; r += 64)
+        for (int r = 0; r < f.nz * trows; r += 16 * MG_WM)
             for (int c = 0; c < f.nx; c += 64) xitems.push_back(make_int4((int)fi, r, c, 0));
-        for (int r = 0; r < f.nz; r += 64)
+        for (int r = 0; r < f.nz; r += 16 * MG_WM)
             for (int c = 0; c < trows * f.nx; c += 64) zitems.push_back(make_int4((int)fi, r, c, 0));
         for (int c = 0; c < f.nz; ++c)
             for (int a = 0; a < f.nx; a += 64) titems.push_back(make_int4((int)fi, c, a, 0));

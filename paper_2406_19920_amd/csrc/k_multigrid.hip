@@ -23,10 +23,11 @@ static __device__ __forceinline__ d4 mma(double a, double b, d4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// x transform of one 64 x 64 tile per wave: C = A B, A the field's
+// x transform of one (16 WM) x 64 tile per wave: C = A B, A the field's
 // transform rows (M = nz * trows rows of K = nx values), B the swizzled
 // nx x nx table (forward Q or inverse G^T), C rows of nx values.  The
 // operand order and chunking are those of the single-grid plain kernel.
+template <int WM>
 __global__ __launch_bounds__(256) void mg_xgemm_kernel(const MgField *__restrict__ fields,
                                                        const int4 *__restrict__ items, int nitems,
                                                        int inverse)
@@ -40,24 +41,24 @@ __global__ __launch_bounds__(256) void mg_xgemm_kernel(const MgField *__restrict
         const int K = f.nx, N = f.nx;
         const int skip = skip_first_row(f.kind), trows = f.rows - skip;
         const int M = f.nz * trows;
-        const int nrb = min(4, (M - row0) >> 4), ncb = min(4, (N - col0) >> 4);
+        const int nrb = min(WM, (M - row0) >> 4), ncb = min(4, (N - col0) >> 4);
         const double *__restrict__ A = inverse ? f.work : f.in;
         double *__restrict__ C = inverse ? f.out : f.work;
         const double *__restrict__ bs = inverse ? f.xinv : f.xfwd;
         const int nb = N >> 4;
-        d4 acc[4][4];
+        d4 acc[WM][4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < WM; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
-        const double *arow[4];
+        const double *arow[WM];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < WM; ++i)
             arow[i] = A + phys_row(row0 + 16 * i + (i < nrb ? li : 0), trows, skip) * K + 4 * lg;
         for (int kc = 0; kc < (K >> 4); ++kc) {
-            d4 a[4], b[4];
+            d4 a[WM], b[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < WM; ++i)
                 a[i] = (i < nrb) ? *reinterpret_cast<const d4 *>(arow[i] + 16 * kc) : (d4){0, 0, 0, 0};
 #pragma unroll
             for (int j = 0; j < 4; ++j)
@@ -67,12 +68,12 @@ __global__ __launch_bounds__(256) void mg_xgemm_kernel(const MgField *__restrict
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < WM; ++i)
 #pragma unroll
                     for (int j = 0; j < 4; ++j) acc[i][j] = mma(a[i][t], b[j][t], acc[i][j]);
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < WM; ++i) {
             if (i >= nrb) break;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -85,10 +86,11 @@ __global__ __launch_bounds__(256) void mg_xgemm_kernel(const MgField *__restrict
     }
 }
 
-// z transform of one 64 x 64 tile per wave: C = As B, As the swizzled
+// z transform of one (16 WM) x 64 tile per wave: C = As B, As the swizzled
 // nz x nz table (forward Q^T or inverse G), B the field viewed as nz rows
 // of Ncol = trows * nx values at plane stride rows * nx.  Forward reads
 // work and writes out; inverse reads out and writes work.
+template <int WM>
 __global__ __launch_bounds__(256) void mg_zgemm_kernel(const MgField *__restrict__ fields,
                                                        const int4 *__restrict__ items, int nitems,
                                                        int inverse)
@@ -103,20 +105,20 @@ __global__ __launch_bounds__(256) void mg_zgemm_kernel(const MgField *__restrict
         const int skip = skip_first_row(f.kind);
         const int Ncol = (f.rows - skip) * nx;
         const size_t ldp = (size_t)f.rows * nx;
-        const int nrb = min(4, (M - row0) >> 4), ncb = min(4, (Ncol - col0) >> 4);
+        const int nrb = min(WM, (M - row0) >> 4), ncb = min(4, (Ncol - col0) >> 4);
         const double *__restrict__ as = inverse ? f.zinv : f.zfwd;
         const double *__restrict__ B = (inverse ? f.out : f.work) + skip * nx;
         double *__restrict__ C = (inverse ? f.work : f.out) + skip * nx;
         const int mb = M >> 4;
-        d4 acc[4][4];
+        d4 acc[WM][4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < WM; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
         for (int kc = 0; kc < (K >> 4); ++kc) {
-            d4 a[4], b[4];
+            d4 a[WM], b[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < WM; ++i)
                 a[i] = (i < nrb) ? *reinterpret_cast<const d4 *>(
                                        as + (((size_t)kc * mb + (row0 >> 4) + i) * 64 + lane) * 4)
                                  : (d4){0, 0, 0, 0};
@@ -133,12 +135,12 @@ __global__ __launch_bounds__(256) void mg_zgemm_kernel(const MgField *__restrict
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < WM; ++i)
 #pragma unroll
                     for (int j = 0; j < 4; ++j) acc[i][j] = mma(a[i][t], b[j][t], acc[i][j]);
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < WM; ++i) {
             if (i >= nrb) break;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -252,16 +254,16 @@ hipError_t launch_multigrid_stage(int stage, const MgField *fields, const int4 *
                                   hipStream_t s)
 {
     if (nitems <= 0) return hipSuccess;
-    static const int rx = resident(mg_xgemm_kernel), rz = resident(mg_zgemm_kernel),
+    static const int rx = resident(mg_xgemm_kernel<MG_WM>), rz = resident(mg_zgemm_kernel<MG_WM>),
                      rt = resident(mg_tridiag_kernel);
     const int res = stage == MG_TRI ? rt : (stage == MG_Z_FWD || stage == MG_Z_INV ? rz : rx);
     const int blocks = std::min((nitems + 3) / 4, res);
     switch (stage) {
-    case MG_X_FWD: hipLaunchKernelGGL(mg_xgemm_kernel, dim3(blocks), dim3(256), 0, s, fields, items, nitems, 0); break;
-    case MG_Z_FWD: hipLaunchKernelGGL(mg_zgemm_kernel, dim3(blocks), dim3(256), 0, s, fields, items, nitems, 0); break;
+    case MG_X_FWD: hipLaunchKernelGGL(mg_xgemm_kernel<MG_WM>, dim3(blocks), dim3(256), 0, s, fields, items, nitems, 0); break;
+    case MG_Z_FWD: hipLaunchKernelGGL(mg_zgemm_kernel<MG_WM>, dim3(blocks), dim3(256), 0, s, fields, items, nitems, 0); break;
     case MG_TRI: hipLaunchKernelGGL(mg_tridiag_kernel, dim3(blocks), dim3(256), 0, s, fields, items, nitems); break;
-    case MG_Z_INV: hipLaunchKernelGGL(mg_zgemm_kernel, dim3(blocks), dim3(256), 0, s, fields, items, nitems, 1); break;
-    default: hipLaunchKernelGGL(mg_xgemm_kernel, dim3(blocks), dim3(256), 0, s, fields, items, nitems, 1); break;
+    case MG_Z_INV: hipLaunchKernelGGL(mg_zgemm_kernel<MG_WM>, dim3(blocks), dim3(256), 0, s, fields, items, nitems, 1); break;
+    default: hipLaunchKernelGGL(mg_xgemm_kernel<MG_WM>, dim3(blocks), dim3(256), 0, s, fields, items, nitems, 1); break;
     }
     return hipGetLastError();
 }

@@ -26,6 +26,7 @@ struct MgField {
 
 enum { MG_X_FWD = 0, MG_Z_FWD, MG_TRI, MG_Z_INV, MG_X_INV, MG_STAGES };
 constexpr int MG_MAX_BLOCKS = 2048;   // persistent grid: at most 8 blocks per CU
+constexpr int MG_WM = 2;              // transform tiles: 16 MG_WM rows x 64 columns per wave
 
 hipError_t launch_multigrid_stage(int stage, const MgField *fields, const int4 *items, int nitems,
                                   hipStream_t s);
