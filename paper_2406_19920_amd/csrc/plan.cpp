@@ -594,8 +594,8 @@ ibs_status build_plan(const ibs_grid_desc &d, Plan *&out)
         set_error("nx and nz must be multiples of 16 in [16, 1024]");
         return IBS_ERR_UNSUPPORTED;
     }
-    if (d.ny < 2 || d.ny > 1024) {
-        set_error("ny must be in [2, 1024]");
+    if (d.ny < 2 || d.ny > 768) {   // the tridiagonal shapes cover up to 800 system rows
+        set_error("ny must be in [2, 768]");
         return IBS_ERR_UNSUPPORTED;
     }
     const bool walls_y = d.bc_y_vel == IBS_DIRICHLET && d.bc_y_p == IBS_NEUMANN;

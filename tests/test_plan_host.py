@@ -566,3 +566,13 @@ def test_host_emulation_zwalls_matches_oracle(op, wx):
             assert np.abs(xe[0]).max() == 0.0
     finally:
         ibs.solver_plan_destroy(p)
+
+
+def test_ny_limit_matches_header():
+    """ny up to 768 (the largest tridiagonal shape holds 800 rows, v's
+    included) is accepted; 769 is refused on the host, not at solve time."""
+    p = _plan(16, 768, 16)
+    ibs.solver_plan_destroy(p)
+    with pytest.raises(ibs.IbsError) as e:
+        _plan(16, 769, 16)
+    assert e.value.status == ibs.IBS_ERR_UNSUPPORTED
