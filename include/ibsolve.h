@@ -405,7 +405,8 @@ ibs_status ibs_batch_autotune(const ibs_batch_job *jobs, int32_t njobs, int32_t 
  * bitwise.  Jobs: plans uploaded, precision IBS_FP64, walls in y (not
  * periodic y), strict_compat 0, any x / z conditions (uniform or
  * stretched); workspaces as for the single solves (solver_plan_bytes),
- * one of its own per job (jobs run side by side); rhs may alias x.  info
+ * one of its own per job (jobs run side by side); rhs, x and work 32-byte
+ * aligned, as for the single solves; rhs may alias x.  info
  * reports as the FP64 solves do.  The builder allocates one device buffer
  * (job table, work lists and transform tables; freed by
  * ibs_batch_destroy()).  Errors: IBS_ERR_INVALID_ARG (bad job, shared

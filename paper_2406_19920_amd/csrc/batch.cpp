@@ -230,8 +230,14 @@ ibs_status ibs_batch_build_multigrid(const ibs_batch_job *jobs, int32_t njobs, i
             return IBS_ERR_INVALID_ARG;
         }
         works[j.work] = q;
+        auto aligned = [](const void *ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 31u) == 0; };
+        if (!aligned(j.work)) { set_error(who + "work must be 32-byte aligned"); return IBS_ERR_INVALID_ARG; }
         for (int k = 0; k < nc; ++k) {
             if (!j.rhs[k] || !j.x[k]) { set_error(who + "rhs and x must be non-NULL"); return IBS_ERR_INVALID_ARG; }
+            if (!aligned(j.rhs[k]) || !aligned(j.x[k])) {
+                set_error(who + "rhs and x must be 32-byte aligned");
+                return IBS_ERR_INVALID_ARG;
+            }
             if (j.op != IBS_OP_POISSON &&
                 (j.comp[k] < 0 || j.comp[k] > 2 || !(j.c[k] >= 0.0) || !std::isfinite(j.c[k]))) {
                 set_error(who + "comp must be 0..2 and c finite and >= 0");
