@@ -166,8 +166,14 @@ __global__ __launch_bounds__(256) void mg_zgemm_kernel(const MgField *__restrict
 __global__ __launch_bounds__(256) void mg_tridiag_kernel(const MgField *__restrict__ fields,
                                                          const int4 *__restrict__ items, int nitems)
 {
+    // Rows are read in bursts of TR, every load of a burst issued before the
+    // first row of the burst is eliminated (a row's store may not be moved
+    // above a later row's load, so loads issued row by row would each wait
+    // for the memory in turn).
+    constexpr int TR = 8;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int it = blockIdx.x * 4 + wave; it < nitems; it += gridDim.x * 4) {
+    for (int it0 = blockIdx.x * 4 + wave; it0 < nitems; it0 += gridDim.x * 4) {
+        const int it = __builtin_amdgcn_readfirstlane(it0);   // wave-uniform item
         const int4 w = items[it];
         const MgField &f = fields[w.x];
         const int c = w.y, a = w.z + lane;
@@ -177,7 +183,10 @@ __global__ __launch_bounds__(256) void mg_tridiag_kernel(const MgField *__restri
         const int j0 = faces ? 1 : 0, j1 = f.ny - 1;   // unknown rows j0..j1
         double *__restrict__ x = f.out + (size_t)c * f.rows * nx + a;
         double *__restrict__ cp = f.work + (size_t)c * f.rows * nx + a;
-        const double *__restrict__ lo = f.lo, *__restrict__ di = f.di, *__restrict__ up = f.up;
+        // the y rows are read-only here and the same for every lane: read
+        // through the scalar cache
+        typedef const __attribute__((address_space(4))) double *crow;
+        const crow lo = (crow)f.lo, di = (crow)f.di, up = (crow)f.up;
         const double s = f.lam_x[a] + f.lam_z[c];
         const bool pois = f.poisson != 0;
         const double cc = f.c;
@@ -191,24 +200,54 @@ __global__ __launch_bounds__(256) void mg_tridiag_kernel(const MgField *__restri
             }
             mean = swd / sw;
         }
-        // forward sweep: cp_j = up_j / m_j, x_j <- (d_j - lo_j x_{j-1}) / m_j
+        // forward sweep: m_j = d_j - a_j cp_{j-1}, cp_j = c_j / m_j,
+        // x_j <- (b_j - a_j x_{j-1}) / m_j
         double cprev = 0.0, dprev = 0.0;
-        for (int j = j0; j <= j1; ++j) {
-            double lj = (j > j0) ? lo[j] : 0.0, dj = di[j], uj = (j < j1) ? up[j] : 0.0;
-            double bj = x[(size_t)j * nx] - mean;
+        auto fwd_row = [&](int j, double bj, double lj, double dj, double uj) {
+            if (j == j0) lj = 0.0;
+            if (j == j1) uj = 0.0;
+            bj -= mean;
             double aj, mj, cj;
             if (pois) { aj = lj; mj = dj + s; cj = uj; }
             else { aj = -cc * lj; mj = 1.0 - cc * (dj + s); cj = -cc * uj; }
             if (pinned && j == j0) { aj = 0.0; mj = 1.0; cj = 0.0; bj = 0.0; }
-            const double m = mj - aj * cprev;
-            cprev = cj / m;
-            dprev = (bj - aj * dprev) / m;
+            const double im = 1.0 / (mj - aj * cprev);
+            cprev = cj * im;
+            dprev = (bj - aj * dprev) * im;
             cp[(size_t)j * nx] = cprev;
             x[(size_t)j * nx] = dprev;
+        };
+        int j = j0;
+        for (; j + TR - 1 <= j1; j += TR) {   // whole bursts: no branch between the loads
+            double bv[TR], lv[TR], dv[TR], uv[TR];
+#pragma unroll
+            for (int r = 0; r < TR; ++r) {
+                bv[r] = x[(size_t)(j + r) * nx];
+                lv[r] = lo[j + r];
+                dv[r] = di[j + r];
+                uv[r] = up[j + r];
+            }
+#pragma unroll
+            for (int r = 0; r < TR; ++r) fwd_row(j + r, bv[r], lv[r], dv[r], uv[r]);
         }
-        // back substitution: x_j = d_j - cp_j x_{j+1}
-        double xn = x[(size_t)j1 * nx];
-        for (int j = j1 - 1; j >= j0; --j) {
+        for (; j <= j1; ++j) fwd_row(j, x[(size_t)j * nx], lo[j], di[j], up[j]);
+        // back substitution: x_j = x_j - cp_j x_{j+1}, in bursts going down
+        double xn = dprev;   // row j1 is final
+        j = j1 - 1;
+        for (; j - (TR - 1) >= j0; j -= TR) {
+            double dv[TR], cv[TR];
+#pragma unroll
+            for (int r = 0; r < TR; ++r) {
+                dv[r] = x[(size_t)(j - r) * nx];
+                cv[r] = cp[(size_t)(j - r) * nx];
+            }
+#pragma unroll
+            for (int r = 0; r < TR; ++r) {
+                xn = dv[r] - cv[r] * xn;
+                x[(size_t)(j - r) * nx] = xn;
+            }
+        }
+        for (; j >= j0; --j) {
             xn = x[(size_t)j * nx] - cp[(size_t)j * nx] * xn;
             x[(size_t)j * nx] = xn;
         }
