@@ -408,8 +408,11 @@ ibs_status ibs_batch_autotune(const ibs_batch_job *jobs, int32_t njobs, int32_t 
  * one of its own per job (jobs run side by side); rhs, x and work 32-byte
  * aligned, as for the single solves; rhs may alias x.  info
  * reports as the FP64 solves do.  The builder allocates one device buffer
- * (job table, work lists and transform tables; freed by
- * ibs_batch_destroy()).  Errors: IBS_ERR_INVALID_ARG (bad job, shared
+ * (job table, work lists, transform tables, and the tridiagonal pencils'
+ * forward factors, which depend on the systems only: one field's size per
+ * field, about as much device memory again as the fields themselves; freed
+ * by ibs_batch_destroy()) and computes those factors once on the device
+ * before capturing the graph (synchronously).  Errors: IBS_ERR_INVALID_ARG (bad job, shared
  * workspace), IBS_ERR_UNSUPPORTED (refined or periodic-y plan, strict
  * compatibility), IBS_ERR_NOT_UPLOADED, IBS_ERR_WORKSPACE_TOO_SMALL,
  * IBS_ERR_HIP. */

@@ -299,6 +299,13 @@ ibs_status ibs_batch_build_multigrid(const ibs_batch_job *jobs, int32_t njobs, i
         }
     }
     std::vector<int4> xitems, zitems, titems;
+    std::vector<size_t> cpt_at;   // doubles from the start of the factor region
+    size_t cpt_doubles = 0;
+    for (size_t fi = 0; fi < fields.size(); ++fi) {
+        const MgField &f = fields[fi].f;
+        cpt_at.push_back(cpt_doubles);
+        cpt_doubles += ((size_t)f.nz * f.rows * f.nx + 31) & ~size_t(31);
+    }
     for (size_t fi = 0; fi < fields.size(); ++fi) {
         const MgField &f = fields[fi].f;
         const int trows = f.rows - skip_first_row(f.kind);
@@ -315,13 +322,15 @@ ibs_status ibs_batch_build_multigrid(const ibs_batch_job *jobs, int32_t njobs, i
     const size_t o_x = al(o_fld + fields.size() * sizeof(MgField));
     const size_t o_z = al(o_x + xitems.size() * sizeof(int4));
     const size_t o_t = al(o_z + zitems.size() * sizeof(int4));
-    const size_t total = al(o_t + titems.size() * sizeof(int4));
+    const size_t o_cp = al(o_t + titems.size() * sizeof(int4));
+    const size_t total = al(o_cp + cpt_doubles * sizeof(double));
+    const size_t upload = o_cp;   // the factor region is filled on the device
 
     ibs_batch_s *b = new ibs_batch_s();
     hipStream_t cap = nullptr;
     hipError_t e;
     ibs_status st = IBS_OK;
-    std::vector<unsigned char> img(total, 0);
+    std::vector<unsigned char> img(upload, 0);
     unsigned char *dev = nullptr;
     if ((e = hipMalloc(&b->dev, total)) != hipSuccess) { st = fail_hip(e, "multi-grid buffer"); goto fail; }
     dev = static_cast<unsigned char *>(b->dev);
@@ -332,13 +341,21 @@ ibs_status ibs_batch_build_multigrid(const ibs_batch_job *jobs, int32_t njobs, i
         f.xinv = reinterpret_cast<const double *>(dev + o_tab) + fields[fi].xi;
         f.zfwd = reinterpret_cast<const double *>(dev + o_tab) + fields[fi].zf;
         f.zinv = reinterpret_cast<const double *>(dev + o_tab) + fields[fi].zi;
+        f.cpt = reinterpret_cast<double *>(dev + o_cp) + cpt_at[fi];
         std::memcpy(img.data() + o_fld + fi * sizeof(MgField), &f, sizeof(MgField));
     }
     std::memcpy(img.data() + o_x, xitems.data(), xitems.size() * sizeof(int4));
     std::memcpy(img.data() + o_z, zitems.data(), zitems.size() * sizeof(int4));
     std::memcpy(img.data() + o_t, titems.data(), titems.size() * sizeof(int4));
-    if ((e = hipMemcpy(b->dev, img.data(), total, hipMemcpyHostToDevice)) != hipSuccess) { st = fail_hip(e, "multi-grid upload"); goto fail; }
+    if ((e = hipMemcpy(b->dev, img.data(), upload, hipMemcpyHostToDevice)) != hipSuccess) { st = fail_hip(e, "multi-grid upload"); goto fail; }
     if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) { st = fail_hip(e, "capture stream"); goto fail; }
+    // the pencils' factors, once (they depend on the systems, not the data)
+    if ((e = launch_multigrid_stage(MG_FACTOR, reinterpret_cast<const MgField *>(dev + o_fld),
+                                    reinterpret_cast<const int4 *>(dev + o_t), (int)titems.size(), cap)) != hipSuccess ||
+        (e = hipStreamSynchronize(cap)) != hipSuccess) {
+        st = fail_hip(e, "multi-grid factors");
+        goto fail;
+    }
     if ((e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) { st = fail_hip(e, "begin capture"); goto fail; }
     {
         const MgField *fl = reinterpret_cast<const MgField *>(dev + o_fld);

@@ -13,6 +13,7 @@ struct MgField {
     const double *in;
     double *out;
     double *work;
+    double *cpt;                 // the pencils' forward factors [nz][rows][nx] (library-owned, built once)
     const double *xfwd, *xinv;   // swizzled nx x nx B operands: Q, G^T
     const double *zfwd, *zinv;   // swizzled nz x nz A operands: Q^T, G
     const double *lam_x, *lam_z; // eigenvalues of the field's x / z kinds
@@ -25,6 +26,7 @@ struct MgField {
 };
 
 enum { MG_X_FWD = 0, MG_Z_FWD, MG_TRI, MG_Z_INV, MG_X_INV, MG_STAGES };
+constexpr int MG_FACTOR = MG_STAGES;  // set-up launch: the pencils' factors into cpt (tridiagonal work list)
 constexpr int MG_MAX_BLOCKS = 2048;   // persistent grid: at most 8 blocks per CU
 constexpr int MG_WM = 2;              // transform tiles: 16 MG_WM rows x 64 columns per wave
 
