@@ -28,7 +28,7 @@ static __device__ __forceinline__ d4 mma(double a, double b, d4 c)
 // nx x nx table (forward Q or inverse G^T), C rows of nx values.  The
 // operand order and chunking are those of the single-grid plain kernel.
 template <int WM>
-__global__ __launch_bounds__(256) void mg_xgemm_kernel(const MgField *__restrict__ fields,
+__global__ __launch_bounds__(256, 3) void mg_xgemm_kernel(const MgField *__restrict__ fields,
                                                        const int4 *__restrict__ items, int nitems,
                                                        int inverse)
 {
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void mg_xgemm_kernel(const MgField *__restrict
 // of Ncol = trows * nx values at plane stride rows * nx.  Forward reads
 // work and writes out; inverse reads out and writes work.
 template <int WM>
-__global__ __launch_bounds__(256) void mg_zgemm_kernel(const MgField *__restrict__ fields,
+__global__ __launch_bounds__(256, 3) void mg_zgemm_kernel(const MgField *__restrict__ fields,
                                                        const int4 *__restrict__ items, int nitems,
                                                        int inverse)
 {
@@ -124,13 +124,10 @@ __global__ __launch_bounds__(256) void mg_zgemm_kernel(const MgField *__restrict
                                  : (d4){0, 0, 0, 0};
             const double *brow = B + (size_t)(16 * kc + 4 * lg) * ldp + col0 + li;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (j < ncb) {
+            for (int t = 0; t < 4; ++t) {
+                const double *bt = brow + (size_t)t * ldp;   // one address per row, the blocks at immediate offsets
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) b[j][t] = brow[(size_t)t * ldp + 16 * j];
-                } else {
-                    b[j] = (d4){0, 0, 0, 0};
-                }
+                for (int j = 0; j < 4; ++j) b[j][t] = (j < ncb) ? bt[16 * j] : 0.0;
             }
 #pragma unroll
             for (int t = 0; t < 4; ++t)
