@@ -40,8 +40,16 @@ static __device__ __forceinline__ d4 mfma(double a, double b, d4 c)
 // physical row -> spectral row; inverse: spectral -> physical.  bc, bs:
 // the two H x H factors, swizzled as B operands.  A wave owns WM row
 // blocks and WN column blocks of both factors.
+// Waves per SIMD the register allocation is held to: three for the tiles
+// that fit without spilling (the memory latency then has a third wave to
+// hide behind), else what the tile needs.
+template <int WM, int WN, bool PF>
+constexpr int xf_waves() { return (!PF && WM * WN <= 4 && WM <= 2) ? 3 : 1; }
+template <int WM, int WN, bool PF>
+constexpr int zf_waves() { return (!PF && WM * WN <= 4 && WN <= 2) ? 3 : 1; }
+
 template <int WM, int WN, bool INV, bool PF>
-__global__ __launch_bounds__(256) void xfold_f64_kernel(JobSet js, int nz, int N,
+__global__ __launch_bounds__(256, (xf_waves<WM, WN, PF>())) void xfold_f64_kernel(JobSet js, int nz, int N,
                                                         const double *__restrict__ bc,
                                                         const double *__restrict__ bs, int wgn,
                                                         double s0, double s1)
@@ -217,7 +225,7 @@ __global__ __launch_bounds__(256) void xfold_f64_kernel(JobSet js, int nz, int N
 // swizzled as A operands.  A wave owns WM row blocks (of both factors) and
 // WN column blocks.
 template <int WM, int WN, bool INV, bool PF>
-__global__ __launch_bounds__(256) void zfold_f64_kernel(JobSet js, int N, int nx,
+__global__ __launch_bounds__(256, (zf_waves<WM, WN, PF>())) void zfold_f64_kernel(JobSet js, int N, int nx,
                                                         const double *__restrict__ ac,
                                                         const double *__restrict__ as, int wgn,
                                                         double s0, double s1)
