@@ -91,8 +91,11 @@ __global__ __launch_bounds__(256) void xgemm_f64_kernel(JobSet js, int nz, int K
 // z transform: for job q, C = As * B with As the swizzled M x K matrix
 // (M = K = nz), B = in viewed as K x Ncol (Ncol = transform rows * nx, at
 // plane stride rows * nx), C = out (M x Ncol).
+// Registers held to two waves per SIMD (the 4 x 4 tile's accumulators
+// then sit in the vector registers; unbounded, the allocation came to one
+// wave per SIMD).
 template <int WM, int WN>
-__global__ __launch_bounds__(256) void zgemm_f64_kernel(JobSet js, int M, int K, int nx, int wgn)
+__global__ __launch_bounds__(256, 2) void zgemm_f64_kernel(JobSet js, int M, int K, int nx, int wgn)
 {
     const FieldJob &jb = js.j[blockIdx.z];
     const double *__restrict__ as = static_cast<const double *>(jb.zq);
