@@ -40,13 +40,14 @@ static __device__ __forceinline__ d4 mfma(double a, double b, d4 c)
 // physical row -> spectral row; inverse: spectral -> physical.  bc, bs:
 // the two H x H factors, swizzled as B operands.  A wave owns WM row
 // blocks and WN column blocks of both factors.
-// Waves per SIMD the register allocation is held to: three for the tiles
-// that fit without spilling (the memory latency then has a third wave to
-// hide behind), else what the tile needs.
+// Waves per SIMD the register allocation is held to, where the tile fits
+// without spilling: three for the small tiles (the memory latency then has
+// a third wave to hide behind), two for the tiles that load ahead (left
+// alone they took one), else what the tile needs.
 template <int WM, int WN, bool PF>
-constexpr int xf_waves() { return (!PF && WM * WN <= 4 && WM <= 2) ? 3 : 1; }
+constexpr int xf_waves() { return (!PF && WM * WN <= 4 && WM <= 2) ? 3 : (PF ? 2 : 1); }
 template <int WM, int WN, bool PF>
-constexpr int zf_waves() { return (!PF && WM * WN <= 4 && WN <= 2) ? 3 : 1; }
+constexpr int zf_waves() { return (!PF && WM * WN <= 4 && WN <= 2) ? 3 : ((PF && WN <= 2) ? 2 : 1); }
 
 template <int WM, int WN, bool INV, bool PF>
 __global__ __launch_bounds__(256, (xf_waves<WM, WN, PF>())) void xfold_f64_kernel(JobSet js, int nz, int N,
