@@ -129,8 +129,12 @@ struct TriParams {
 // BMX: this launch records the partial maxima (the refined path's first
 // pass); a separate instantiation, so that no other launch carries the
 // tracking.
+// Registers: FP32 arithmetic is held to four waves per SIMD up to 9 rows per
+// lane, and up to 13 for the non-cyclic systems (a few registers spill
+// there, but two 8-wave blocks per CU instead of one: the 384-row pencils
+// of 512x384x384 run 4 % faster); the rest is left to the compiler.
 template <typename T, typename R, int P, int M, int TA, bool CYC = false, bool BMX = false>
-__global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && M <= 9) ? 4 : 1) void tridiag_kernel(JobSet js, TriParams tp, int ntx,
+__global__ __launch_bounds__(TA * P, (sizeof(R) == 4 && (M <= 9 || (!CYC && M <= 13))) ? 4 : 1) void tridiag_kernel(JobSet js, TriParams tp, int ntx,
                                                          int ntiles)
 {
     // TA: pencils per tile
