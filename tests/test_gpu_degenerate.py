@@ -1,0 +1,72 @@
+"""The degenerate Helmholtz coefficient c = 0 (eq. e with no viscous term:
+the operator is the identity): every path returns the right-hand side
+itself, through the full transform / pencil / inverse-transform sequence
+(single-grid FP64 and refined solves, periodic and wall-bounded x and z,
+and the multi-grid batch form), with the wall slots written as zero."""
+import sys
+
+import pytest
+
+from paper_2406_19920_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ibs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_19920_amd import ibsolve
+    return ibsolve
+
+
+def _maxrel(a, b):
+    return float((a - b).abs().max() / b.abs().max())
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("refined", [False, True])
+@pytest.mark.parametrize("duct", [False, True])
+def test_identity_helmholtz(ibs, refined, duct):
+    nx, ny, nz = 64, 40, 96   # the refined path takes nx, nz multiples of 32
+    _say("case identity helmholtz", "refined" if refined else "fp64", "duct" if duct else "periodic x/z")
+    kw = dict(beta=1.5)
+    if duct:
+        kw.update(bc_x=ibs.IBS_DIRICHLET, bc_z=ibs.IBS_DIRICHLET)
+    S = ibs.Solver(nx, ny, nz, precision=ibs.IBS_REFINED_BF16X3 if refined else ibs.IBS_FP64, **kw)
+    rs = [synth.device_normal(S.shape(op), 20 + op, "cuda") for op in (1, 2, 3)]
+    rs[1][:, 0, :] = 0          # v's wall rows
+    rs[1][:, ny, :] = 0
+    if duct:
+        rs[0][:, :, 0] = 0      # the wall faces x = 0 and z = 0 (slot 0)
+        rs[2][0] = 0
+    xs = S.helmholtz([0, 1, 2], [0.0] * 3, rs)
+    torch.cuda.synchronize()
+    tol = 1e-10 if refined else 1e-12
+    for q in range(3):
+        err = _maxrel(xs[q], rs[q])
+        _say("comp", q, "err", err, "status", S.read_info(q).status)
+        assert err < tol and S.read_info(q).status == 0
+    S.close()
+
+
+def test_identity_helmholtz_multigrid(ibs):
+    from paper_2406_19920_amd import batch
+    _say("case identity helmholtz, multi-grid batch")
+    specs = [dict(nx=32, ny=24, nz=48, beta=1.0, seed=7, c=0.0),
+             dict(nx=64, ny=72, nz=32, beta=2.0, seed=8, c=0.0),
+             dict(nx=48, ny=8, nz=64, beta=0.5, seed=9, c=0.0)]
+    B = batch.Batch(specs, precision=ibs.IBS_FP64, mode="multigrid")
+    B.launch()
+    torch.cuda.synchronize()
+    for jb in B.jobs:
+        for q in range(3):
+            err = _maxrel(jb.x[q], jb.r[q])
+            _say("job", jb.spec["nx"], jb.spec["ny"], jb.spec["nz"], "comp", q, "err", err)
+            assert err < 1e-12
+    B.close()
